@@ -1,0 +1,1027 @@
+/*
+ * dpcs_oracle.c -- plain, slow FP64 CPU reference of the DPCS project-and-capture
+ * path tracer and of its vector-Jacobian product.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may call, link or load
+ * this file; only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark use it.  It shares no code with the GPU library.
+ *
+ * What it computes (paper Sec. 3):
+ *   Eq. 1   PRF       E_p = g_p * I_p^gamma_p (per channel; with an optional 3x3 mixing
+ *                     matrix M after the gamma, M = I reduces to Eq. 1)
+ *   Eq. 2   L_p = E_p / phi; phi is folded into g_p (the projector is a pinhole
+ *                     emitter whose radiant intensity along a direction through image
+ *                     point (u,v) is E_p(u,v) / cos^3(alpha))
+ *   Eq. 3   rendering equation, direct projector light + indirect interreflection
+ *   Eq. 4   pixel value = mean radiance over the pixel footprint (box filter)
+ *   Eq. 5   CRF       I_c = (g_c * w * E_c)^gamma_c
+ *   Eq. 6   projective geometry x_c = K_c x_s, x_p = K_p [R_p | t_p] x_s (with the
+ *                     perspective divide)
+ *   Eq. 10  Monte-Carlo estimator with importance-sampled directions
+ *   Eq. 12  radiance clipping min(L, k / min(w)) per camera sample
+ *   Eq. 9/13 gradients of the rendered image w.r.t. I_p, the BRDF maps, the PRF and
+ *            CRF parameters (the adjoint below), for scene fitting and compensation.
+ *
+ * Structure: every camera sample is traced by a scalar loop; every ray is tested
+ * against every triangle (no acceleration structure), the nearest hit wins, equal
+ * distances go to the lower triangle index.  Random numbers come from the
+ * counter-based Philox4x32-10 generator (Salmon, Moraes, Dror, Shaw, SC'11) keyed
+ * by the seed and indexed by (pixel, sample, block, 0).
+ *
+ * The adjoint stores each sample's whole path and differentiates it by a plain
+ * reverse sweep (suffix sums from the last vertex), sampling decisions held fixed.
+ *
+ * Each traced ray also records how far every discrete decision it took was from
+ * flipping (edge distances, distance gaps, frustum borders, cosine signs, clip
+ * threshold).  A sample whose smallest normalised margin is >= 1 is "clean": on it
+ * any correct FP32 implementation must take exactly the same discrete decisions.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------- */
+/* scene / parameter description (mirrored by the Python wrapper)            */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    /* mesh: float32 inputs, read exactly into doubles */
+    int32_t nv, nt;
+    const float* V;        /* nv*3 */
+    const int32_t* F;      /* nt*3 */
+    const float* UV;       /* nt*3*2 per-corner texture coordinates */
+    const float* Le;       /* nt*3 surface emission (test scenes) or NULL */
+    /* camera and projector: world -> device [R|t], intrinsics K (row-major) */
+    double Kc[9], Rc[9], tc[3];
+    int32_t Wc, Hc;
+    double Kp[9], Rp[9], tp[3];
+    int32_t Wp, Hp;
+    /* BRDF maps (H x W, row-major; albedo has 3 channels) */
+    int32_t brdf;          /* 0 Lambert, 1 GGX */
+    int32_t tw, th;
+    const double* albedo;
+    const double* rough;
+    const double* spec;
+    const double* rough_sample; /* roughness used to sample directions and pdfs (NULL: rough) */
+    /* projector input image Hp x Wp x 3 */
+    const double* Ip;
+    double prf_gamma[3], prf_gain, prf_mix[9];
+    double crf_gamma[3], crf_gain, wb[3];
+    double env[3];
+    int32_t clip;
+    double clip_k;
+    int32_t spp, max_depth;
+    uint64_t seed;
+    uint32_t sample_offset;
+    int32_t nthreads;
+    double tmin;           /* ray epsilon; <= 0 selects 1e-5 * scene diagonal */
+} orc_desc;
+
+/* margin scales (see header comment); all margins are divided by these */
+#define TAU_X   2e-6   /* x scene diagonal: distance of a hit point to a triangle edge */
+#define TAU_T   1e-5   /* relative gap between the two nearest hits */
+#define TAU_UV  1e-3   /* projector pixels to the frustum border */
+#define TAU_COS 1e-5   /* |cosine| of a sign decision */
+#define TAU_CLIP 1e-4  /* relative distance of a sample to the clip threshold */
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10                                                             */
+/* ------------------------------------------------------------------------- */
+void orc_philox(uint64_t seed, const uint32_t ctr_in[4], uint32_t out[4]) {
+    uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    memcpy(out, c, sizeof c);
+}
+
+void orc_philox_batch(uint64_t seed, int64_t n, const uint32_t* ctr, uint32_t* out) {
+    for (int64_t i = 0; i < n; ++i) orc_philox(seed, ctr + 4 * i, out + 4 * i);
+}
+
+/* four uniforms in [0,1): the top 24 bits of each word times 2^-24 */
+static void uniforms(const orc_desc* d, uint32_t pixel, uint32_t sample, uint32_t block, double u[4]) {
+    uint32_t c[4] = {pixel, sample + d->sample_offset, block, 0u}, x[4];
+    orc_philox(d->seed, c, x);
+    for (int i = 0; i < 4; ++i) u[i] = (double)(x[i] >> 8) * (1.0 / 16777216.0);
+}
+
+/* ------------------------------------------------------------------------- */
+/* small vector helpers                                                       */
+/* ------------------------------------------------------------------------- */
+typedef struct { double x, y, z; } v3;
+static v3 mk(double x, double y, double z) { v3 r = {x, y, z}; return r; }
+static v3 add(v3 a, v3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+static v3 sub(v3 a, v3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+static v3 scl(v3 a, double s) { return mk(a.x * s, a.y * s, a.z * s); }
+static double dot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static v3 cross(v3 a, v3 b) { return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x); }
+static double len(v3 a) { return sqrt(dot(a, a)); }
+static v3 nrm(v3 a) { return scl(a, 1.0 / len(a)); }
+static v3 matv(const double* M, v3 a) {   /* M a, row-major */
+    return mk(M[0] * a.x + M[1] * a.y + M[2] * a.z, M[3] * a.x + M[4] * a.y + M[5] * a.z,
+              M[6] * a.x + M[7] * a.y + M[8] * a.z);
+}
+static v3 mattv(const double* M, v3 a) {  /* M^T a */
+    return mk(M[0] * a.x + M[3] * a.y + M[6] * a.z, M[1] * a.x + M[4] * a.y + M[7] * a.z,
+              M[2] * a.x + M[5] * a.y + M[8] * a.z);
+}
+static v3 vtx(const orc_desc* d, int32_t i) {
+    return mk(d->V[3 * i], d->V[3 * i + 1], d->V[3 * i + 2]);
+}
+static double mind(double a, double b) { return a < b ? a : b; }
+static double absd(double a) { return a < 0 ? -a : a; }
+
+/* 3x3 inverse by cofactors */
+static void inv3(const double* m, double* o) {
+    double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5], g = m[6], h = m[7], i = m[8];
+    double A = e * i - f * h, B = -(d * i - f * g), C = d * h - e * g;
+    double det = a * A + b * B + c * C;
+    o[0] = A / det; o[1] = -(b * i - c * h) / det; o[2] = (b * f - c * e) / det;
+    o[3] = B / det; o[4] = (a * i - c * g) / det; o[5] = -(a * f - c * d) / det;
+    o[6] = C / det; o[7] = -(a * h - b * g) / det; o[8] = (a * e - b * d) / det;
+}
+
+/* ------------------------------------------------------------------------- */
+/* ray / triangle (Moller-Trumbore, i.e. Cramer's rule on o + t d = v0 + b1 e1 + b2 e2) */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int ok;          /* plane not parallel to the ray */
+    double t, b0, b1, b2;
+    double edge;     /* signed distance of the plane point to the nearest edge line, metres
+                        (>= 0 inside the triangle) */
+} tri_isect;
+
+static tri_isect intersect_tri(const orc_desc* d, int32_t prim, v3 o, v3 dir) {
+    tri_isect r;
+    memset(&r, 0, sizeof r);
+    v3 v0 = vtx(d, d->F[3 * prim]), v1 = vtx(d, d->F[3 * prim + 1]), v2 = vtx(d, d->F[3 * prim + 2]);
+    v3 e1 = sub(v1, v0), e2 = sub(v2, v0);
+    v3 p = cross(dir, e2);
+    double det = dot(e1, p);
+    if (det == 0.0) return r;
+    double inv = 1.0 / det;
+    v3 s = sub(o, v0);
+    r.b1 = dot(s, p) * inv;
+    v3 q = cross(s, e1);
+    r.b2 = dot(dir, q) * inv;
+    r.t = dot(e2, q) * inv;
+    r.b0 = 1.0 - r.b1 - r.b2;
+    r.ok = 1;
+    /* barycentric b_i times the height over the opposite edge = distance to that edge */
+    double area2 = len(cross(e1, e2));
+    double h0 = area2 / len(sub(v2, v1)), h1 = area2 / len(e2), h2 = area2 / len(e1);
+    r.edge = mind(mind(r.b0 * h0, r.b1 * h1), r.b2 * h2);
+    return r;
+}
+
+static int inside(const tri_isect* h) { return h->b0 >= 0.0 && h->b1 >= 0.0 && h->b2 >= 0.0; }
+
+typedef struct { double tmin, diag; } scene_scale;
+
+/* Robustness of one triangle's hit decision "inside and t in range": the decision
+ * flips only through a component that does not already settle it.  m_e and m_t are
+ * the normalised distances of the edge test and of the range test from flipping. */
+static double decision_margin(int in, int inr, double m_e, double m_t) {
+    if (in && inr) return mind(m_e, m_t);
+    if (in) return m_t;
+    if (inr) return m_e;
+    return m_e > m_t ? m_e : m_t;
+}
+
+/* closest hit over (tmin, tmax), skipping `skip`; ties -> lowest index.
+ * *margin receives the normalised distance from the nearest decision boundary. */
+static int closest_hit(const orc_desc* d, const scene_scale* sc, v3 o, v3 dir, double tmax, int skip,
+                       tri_isect* best, double* margin) {
+    int bp = -1;
+    double bt = tmax;
+    for (int32_t p = 0; p < d->nt; ++p) {
+        if (p == skip) continue;
+        tri_isect h = intersect_tri(d, p, o, dir);
+        if (!h.ok || !inside(&h) || !(h.t > sc->tmin) || !(h.t < tmax)) continue;
+        if (h.t < bt || (h.t == bt && p < bp)) { bt = h.t; bp = p; *best = h; }
+    }
+    if (margin) {
+        double m = 1e300;
+        double tx = TAU_X * sc->diag;
+        double tlim = bp >= 0 ? bt : tmax;
+        for (int32_t p = 0; p < d->nt; ++p) {
+            if (p == skip) continue;
+            tri_isect h = intersect_tri(d, p, o, dir);
+            if (!h.ok) continue;
+            double m_e = absd(h.edge) / tx;
+            double m_t = absd(h.t - sc->tmin) / (0.5 * sc->tmin);
+            int in = inside(&h), above = h.t > sc->tmin;
+            if (p == bp) {
+                m = mind(m, mind(m_e, m_t));
+            } else if (h.t <= tlim * (1.0 + TAU_T) + tx) {
+                /* at or before the nearest hit: could take its place */
+                if (in && above)
+                    m = mind(m, bp >= 0 ? absd(h.t - bt) / (bt * TAU_T + tx) : 1e300);
+                else
+                    m = mind(m, decision_margin(in, above, m_e, m_t));
+            }
+        }
+        *margin = m;
+    }
+    return bp;
+}
+
+/* any hit over (tmin, tmax) skipping `skip` */
+static int occluded(const orc_desc* d, const scene_scale* sc, v3 o, v3 dir, double tmax, int skip,
+                    double* margin) {
+    int occ = 0;
+    double tx = TAU_X * sc->diag;
+    double best_occ = 0.0, m_clear = 1e300;
+    for (int32_t p = 0; p < d->nt; ++p) {
+        if (p == skip) continue;
+        tri_isect h = intersect_tri(d, p, o, dir);
+        if (!h.ok) continue;
+        double m_e = absd(h.edge) / tx;
+        double m_t = mind(absd(h.t - sc->tmin), absd(h.t - tmax)) / (0.5 * sc->tmin);
+        int in = inside(&h), inr = h.t > sc->tmin && h.t < tmax;
+        double dm = decision_margin(in, inr, m_e, m_t);
+        if (in && inr) {
+            occ = 1;
+            if (dm > best_occ) best_occ = dm;
+        } else {
+            m_clear = mind(m_clear, dm);
+        }
+    }
+    /* occluded: robust when one occluder is far from all its boundaries;
+       clear: robust when every candidate is */
+    if (margin) *margin = occ ? best_occ : m_clear;
+    return occ;
+}
+
+/* ------------------------------------------------------------------------- */
+/* texture lookup: bilinear, clamp-to-edge, texel centres at (i + 0.5)       */
+/* ------------------------------------------------------------------------- */
+typedef struct { int idx[4]; double w[4]; } bilin;
+
+/* x, y in texel units where texel (i, j) has its centre at (i, j) */
+static bilin bilinear_at(double x, double y, int W, int H) {
+    bilin b;
+    double fx = floor(x), fy = floor(y);
+    double ax = x - fx, ay = y - fy;
+    int x0 = (int)fx, y0 = (int)fy;
+    int xs[2] = {x0, x0 + 1}, ys[2] = {y0, y0 + 1};
+    for (int k = 0; k < 2; ++k) {
+        if (xs[k] < 0) xs[k] = 0;
+        if (xs[k] > W - 1) xs[k] = W - 1;
+        if (ys[k] < 0) ys[k] = 0;
+        if (ys[k] > H - 1) ys[k] = H - 1;
+    }
+    b.idx[0] = ys[0] * W + xs[0]; b.w[0] = (1 - ax) * (1 - ay);
+    b.idx[1] = ys[0] * W + xs[1]; b.w[1] = ax * (1 - ay);
+    b.idx[2] = ys[1] * W + xs[0]; b.w[2] = (1 - ax) * ay;
+    b.idx[3] = ys[1] * W + xs[1]; b.w[3] = ax * ay;
+    return b;
+}
+
+static bilin tex_lookup(const orc_desc* d, double u, double v) {
+    return bilinear_at(u * d->tw - 0.5, v * d->th - 0.5, d->tw, d->th);
+}
+
+static double fetch1(const double* tex, const bilin* b) {
+    double s = 0;
+    for (int k = 0; k < 4; ++k) s += b->w[k] * tex[b->idx[k]];
+    return s;
+}
+static void fetch3(const double* tex, const bilin* b, double out[3]) {
+    for (int c = 0; c < 3; ++c) {
+        out[c] = 0;
+        for (int k = 0; k < 4; ++k) out[c] += b->w[k] * tex[3 * b->idx[k] + c];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* BRDF: Lambert, or Lambert + GGX microfacet specular (reduced principled)  */
+/* ------------------------------------------------------------------------- */
+#define P_SPEC 0.25
+#define ALPHA_MIN 1e-3
+
+typedef struct {
+    double f[3];     /* BRDF value per channel */
+    double ds_dr;    /* d(specular term)/d(roughness) */
+    double ds_dsp;   /* d(specular term)/d(specular) */
+} brdf_val;
+
+static double ggx_alpha(double r) { double a = r * r; return a > ALPHA_MIN ? a : ALPHA_MIN; }
+static double ggx_dalpha(double r) { return r * r > ALPHA_MIN ? 2.0 * r : 0.0; }
+
+static double ggx_D(double nh, double a) {
+    double k = nh * nh * (a * a - 1.0) + 1.0;
+    return a * a / (PI * k * k);
+}
+static double ggx_dD(double nh, double a) {
+    double k = nh * nh * (a * a - 1.0) + 1.0;
+    return 2.0 * a / (PI * k * k) - a * a * 2.0 * (2.0 * a * nh * nh) / (PI * k * k * k);
+}
+static double ggx_G1(double c, double a) {
+    return 2.0 * c / (c + sqrt(a * a + (1.0 - a * a) * c * c));
+}
+static double ggx_dG1(double c, double a) {
+    double q = sqrt(a * a + (1.0 - a * a) * c * c);
+    double dq = a * (1.0 - c * c) / q;
+    return -2.0 * c * dq / ((c + q) * (c + q));
+}
+
+/* f(wo, wi) at a surface with normal n (two-sided: n already faces wo) */
+static brdf_val brdf_eval(int kind, v3 n, v3 wo, v3 wi, const double a[3], double r, double sp) {
+    brdf_val b;
+    memset(&b, 0, sizeof b);
+    double ci = dot(n, wi), co = dot(n, wo);
+    if (ci <= 0.0 || co <= 0.0) return b;
+    for (int c = 0; c < 3; ++c) b.f[c] = a[c] / PI;
+    if (kind == 0) return b;
+    v3 h = nrm(add(wi, wo));
+    double nh = dot(n, h), ih = dot(wi, h);
+    double al = ggx_alpha(r), dal = ggx_dalpha(r);
+    double D = ggx_D(nh, al), G1i = ggx_G1(ci, al), G1o = ggx_G1(co, al), G = G1i * G1o;
+    double F0 = 0.08 * sp;
+    double m5 = pow(1.0 - ih, 5.0);
+    double F = F0 + (1.0 - F0) * m5;
+    double den = 4.0 * ci * co;
+    double s = F * D * G / den;
+    for (int c = 0; c < 3; ++c) b.f[c] += s;
+    double dG = ggx_dG1(ci, al) * G1o + G1i * ggx_dG1(co, al);
+    b.ds_dr = F * (ggx_dD(nh, al) * G + D * dG) / den * dal;
+    b.ds_dsp = 0.08 * (1.0 - m5) * D * G / den;
+    return b;
+}
+
+/* mixture pdf of the bounce sampler (solid-angle measure) */
+static double bounce_pdf(int kind, v3 n, v3 wo, v3 wi, double r) {
+    double ci = dot(n, wi);
+    if (kind == 0) return ci > 0 ? ci / PI : 0.0;
+    double pd = ci > 0 ? ci / PI : 0.0;
+    /* the sampled microfacet normal is +-normalize(wi + wo), whichever faces n */
+    v3 h = nrm(add(wi, wo));
+    double nh = absd(dot(n, h)), oh = absd(dot(wo, h));
+    double ps = (nh > 0 && oh > 0) ? ggx_D(nh, ggx_alpha(r)) * nh / (4.0 * oh) : 0.0;
+    return (1.0 - P_SPEC) * pd + P_SPEC * ps;
+}
+
+/* orthonormal basis around n (Duff et al., JCGT 2017) */
+static void onb(v3 n, v3* b1, v3* b2) {
+    double s = n.z >= 0.0 ? 1.0 : -1.0;
+    double a = -1.0 / (s + n.z);
+    double b = n.x * n.y * a;
+    *b1 = mk(1.0 + s * n.x * n.x * a, s * b, -s * n.x);
+    *b2 = mk(b, s + n.y * n.y * a, -n.y);
+}
+
+static v3 to_world(v3 n, double x, double y, double z) {
+    v3 b1, b2;
+    onb(n, &b1, &b2);
+    return add(add(scl(b1, x), scl(b2, y)), scl(n, z));
+}
+
+/* cosine-weighted hemisphere about n (Malley's method on the unit disk, polar map) */
+static v3 sample_cosine(v3 n, double u1, double u2) {
+    double rr = sqrt(u1), phi = 2.0 * PI * u2;
+    return to_world(n, rr * cos(phi), rr * sin(phi), sqrt(1.0 - u1));
+}
+
+/* GGX normal distribution sampling (Walter et al. 2007): tan^2 theta_h = a^2 u1/(1-u1) */
+static v3 sample_ggx_h(v3 n, double r, double u1, double u2) {
+    double a = ggx_alpha(r);
+    double t2 = a * a * u1 / (1.0 - u1);
+    double ct = 1.0 / sqrt(1.0 + t2), st = sqrt(t2) * ct, phi = 2.0 * PI * u2;
+    return to_world(n, st * cos(phi), st * sin(phi), ct);
+}
+
+static v3 sample_bounce(int kind, v3 n, v3 wo, double r, double ulobe, double u1, double u2) {
+    if (kind == 1 && ulobe < P_SPEC) {
+        v3 h = sample_ggx_h(n, r, u1, u2);
+        return sub(scl(h, 2.0 * dot(wo, h)), wo);
+    }
+    return sample_cosine(n, u1, u2);
+}
+
+/* ------------------------------------------------------------------------- */
+/* path record (one entry per surface vertex of a camera sample)             */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int prim;
+    double beta[3];
+    double Le[3];
+    bilin tex;                  /* texture footprint of the vertex */
+    double alb[3], r, sp;
+    /* projector next-event estimation */
+    int proj;                   /* unoccluded and inside the frustum */
+    bilin ptex;                 /* projector image footprint */
+    double pf[3], pgeom, pE[3]; /* f(wo, wp), (1/cos^3) cos/d^2, bilinear E_p */
+    double pds_dr, pds_dsp;
+    /* environment next-event estimation */
+    int env;
+    double ef[3], eds_dr, eds_dsp;
+    /* bounce to the next vertex */
+    int bounced;
+    double bf[3], bw, bds_dr, bds_dsp; /* f(wo, wi), cos/pdf (pdf held fixed) */
+} vrec;
+
+typedef struct {
+    double L[3];       /* unclipped sample radiance */
+    int nv;            /* vertices recorded */
+    double margin;     /* forward decisions */
+    int reason;        /* which decision set the margin: 10*depth + check id */
+} sample_out;
+
+/* check ids: 1 closest hit, 2 facing sign, 3 projector depth, 4 frustum border,
+ * 5 projector cosine sign, 6 projector shadow ray, 7 environment shadow ray, 8 bounce sign */
+static void UPD(sample_out* so, int depth, double m, int check) {
+    if (m < so->margin) { so->margin = m; so->reason = 10 * depth + check; }
+}
+
+typedef struct {
+    const orc_desc* d;
+    scene_scale sc;
+    double Kc_inv[9];
+    v3 cam_o, proj_o;
+    double* Ep;        /* Hp*Wp*3 projector irradiance after the PRF */
+} ctx_t;
+
+/* Eq. 1 (with mixing M): E_p = max(0, g_p * M * max(I_p,0)^gamma_p) per texel */
+static void prf_forward(const orc_desc* d, double* Ep) {
+    int64_t n = (int64_t)d->Wp * d->Hp;
+    for (int64_t t = 0; t < n; ++t) {
+        double y[3];
+        for (int c = 0; c < 3; ++c) {
+            double x = d->Ip[3 * t + c];
+            y[c] = x > 0 ? pow(x, d->prf_gamma[c]) : 0.0;
+        }
+        for (int c = 0; c < 3; ++c) {
+            double z = d->prf_gain * (d->prf_mix[3 * c] * y[0] + d->prf_mix[3 * c + 1] * y[1] +
+                                      d->prf_mix[3 * c + 2] * y[2]);
+            Ep[3 * t + c] = z > 0 ? z : 0.0;
+        }
+    }
+}
+
+static void ctx_init(ctx_t* cx, const orc_desc* d) {
+    cx->d = d;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int32_t i = 0; i < d->nv; ++i)
+        for (int k = 0; k < 3; ++k) {
+            double v = d->V[3 * i + k];
+            if (v < lo[k]) lo[k] = v;
+            if (v > hi[k]) hi[k] = v;
+        }
+    cx->sc.diag = sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                       (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    cx->sc.tmin = d->tmin > 0 ? d->tmin : 1e-5 * cx->sc.diag;
+    inv3(d->Kc, cx->Kc_inv);
+    cx->cam_o = scl(mattv(d->Rc, mk(d->tc[0], d->tc[1], d->tc[2])), -1.0);
+    cx->proj_o = scl(mattv(d->Rp, mk(d->tp[0], d->tp[1], d->tp[2])), -1.0);
+    cx->Ep = (double*)malloc(sizeof(double) * 3 * (size_t)d->Wp * d->Hp);
+    prf_forward(d, cx->Ep);
+}
+
+static void ctx_free(ctx_t* cx) { free(cx->Ep); }
+
+/* Trace one camera sample (Eq. 3, 6, 10).  rec (may be NULL) receives max_depth vertices;
+ * hits (may be NULL) receives the hit triangle per vertex (-1 miss, -2 not reached). */
+static sample_out trace_sample(const ctx_t* cx, int32_t pixel, int32_t s, vrec* rec, int32_t* hits) {
+    const orc_desc* d = cx->d;
+    sample_out so;
+    memset(&so, 0, sizeof so);
+    so.margin = 1e300;
+    const double tx = TAU_X * cx->sc.diag;
+    if (hits)
+        for (int k = 0; k < d->max_depth; ++k) hits[k] = -2;
+
+    /* camera ray through the jittered pixel position (Eq. 6 inverted) */
+    int32_t i = pixel % d->Wc, j = pixel / d->Wc;
+    double u[4];
+    uniforms(d, (uint32_t)pixel, (uint32_t)s, 0u, u);
+    v3 pix = mk(i + u[0], j + u[1], 1.0);
+    v3 dir = nrm(mattv(d->Rc, matv(cx->Kc_inv, pix)));
+    v3 o = cx->cam_o;
+    int skip = -1;
+    double beta[3] = {1, 1, 1};
+    double* L = so.L;
+
+    for (int depth = 0; depth < d->max_depth; ++depth) {
+        tri_isect h;
+        double m;
+        int prim = closest_hit(d, &cx->sc, o, dir, 1e300, skip, &h, &m);
+        UPD(&so, depth, m, 1);
+        if (hits) hits[depth] = prim;
+        if (prim < 0) {
+            /* only a camera ray that escapes sees the environment directly */
+            if (depth == 0)
+                for (int c = 0; c < 3; ++c) L[c] += beta[c] * d->env[c];
+            break;
+        }
+        vrec* vr = rec ? &rec[depth] : NULL;
+        if (vr) {
+            memset(vr, 0, sizeof *vr);
+            vr->prim = prim;
+            for (int c = 0; c < 3; ++c) vr->beta[c] = beta[c];
+            so.nv = depth + 1;
+        }
+        /* hit attributes from barycentrics; flat, two-sided geometric normal */
+        int32_t i0 = d->F[3 * prim], i1 = d->F[3 * prim + 1], i2 = d->F[3 * prim + 2];
+        v3 v0 = vtx(d, i0), v1 = vtx(d, i1), v2 = vtx(d, i2);
+        v3 x = add(add(scl(v0, h.b0), scl(v1, h.b1)), scl(v2, h.b2));
+        v3 n = nrm(cross(sub(v1, v0), sub(v2, v0)));
+        v3 wo = scl(dir, -1.0);
+        double ndo = dot(n, wo);
+        UPD(&so, depth, absd(ndo) / TAU_COS, 2);
+        if (ndo < 0) { n = scl(n, -1.0); ndo = -ndo; }
+        const float* uvp = d->UV + 6 * (size_t)prim;
+        double tu = h.b0 * uvp[0] + h.b1 * uvp[2] + h.b2 * uvp[4];
+        double tv = h.b0 * uvp[1] + h.b1 * uvp[3] + h.b2 * uvp[5];
+        bilin tb = tex_lookup(d, tu, tv);
+        double alb[3], r = 0, sp = 0, rs = 0;
+        fetch3(d->albedo, &tb, alb);
+        if (d->brdf == 1) {
+            r = fetch1(d->rough, &tb);
+            sp = fetch1(d->spec, &tb);
+            rs = d->rough_sample ? fetch1(d->rough_sample, &tb) : r;
+        }
+        if (vr) {
+            vr->tex = tb;
+            for (int c = 0; c < 3; ++c) vr->alb[c] = alb[c];
+            vr->r = r;
+            vr->sp = sp;
+        }
+
+        /* surface emission (white-furnace test scenes only) */
+        if (d->Le) {
+            for (int c = 0; c < 3; ++c) {
+                double e = d->Le[3 * prim + c];
+                L[c] += beta[c] * e;
+                if (vr) vr->Le[c] = e;
+            }
+        }
+
+        /* next-event estimation toward the projector (Eq. 2, 3, 6) */
+        {
+            v3 xp = add(matv(d->Rp, x), mk(d->tp[0], d->tp[1], d->tp[2]));
+            UPD(&so, depth, absd(xp.z) / tx, 3);
+            if (xp.z > 0) {
+                double pu = (d->Kp[0] * xp.x + d->Kp[1] * xp.y + d->Kp[2] * xp.z) / xp.z;
+                double pv = (d->Kp[3] * xp.x + d->Kp[4] * xp.y + d->Kp[5] * xp.z) / xp.z;
+                double bu = mind(mind(absd(pu), absd(d->Wp - pu)), mind(absd(pv), absd(d->Hp - pv)));
+                UPD(&so, depth, bu / TAU_UV, 4);
+                if (pu >= 0 && pu < d->Wp && pv >= 0 && pv < d->Hp) {
+                    v3 tow = sub(cx->proj_o, x);
+                    double dist = len(tow);
+                    v3 wp = scl(tow, 1.0 / dist);
+                    double cp = dot(n, wp);
+                    UPD(&so, depth, absd(cp) / TAU_COS, 5);
+                    if (cp > 0) {
+                        double mo;
+                        int occ = occluded(d, &cx->sc, x, wp, dist - cx->sc.tmin, prim, &mo);
+                        UPD(&so, depth, mo, 6);
+                        if (!occ) {
+                            bilin pb = bilinear_at(pu - 0.5, pv - 0.5, d->Wp, d->Hp);
+                            double E[3];
+                            fetch3(cx->Ep, &pb, E);
+                            double ca = xp.z / len(xp);              /* cos alpha off the axis */
+                            double geom = cp / (ca * ca * ca * dist * dist);
+                            brdf_val fb = brdf_eval(d->brdf, n, wo, wp, alb, r, sp);
+                            for (int c = 0; c < 3; ++c) L[c] += beta[c] * fb.f[c] * E[c] * geom;
+                            if (vr) {
+                                vr->proj = 1;
+                                vr->ptex = pb;
+                                vr->pgeom = geom;
+                                for (int c = 0; c < 3; ++c) { vr->pf[c] = fb.f[c]; vr->pE[c] = E[c]; }
+                                vr->pds_dr = fb.ds_dr;
+                                vr->pds_dsp = fb.ds_dsp;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+
+        /* next-event estimation toward a constant environment (only if it is non-zero) */
+        if (d->env[0] != 0 || d->env[1] != 0 || d->env[2] != 0) {
+            double ue[4];
+            uniforms(d, (uint32_t)pixel, (uint32_t)s, 2u + 2u * depth, ue);
+            v3 we = sample_cosine(n, ue[0], ue[1]);
+            double mo;
+            int occ = occluded(d, &cx->sc, x, we, 1e300, prim, &mo);
+            UPD(&so, depth, mo, 7);
+            if (!occ) {
+                brdf_val fb = brdf_eval(d->brdf, n, wo, we, alb, r, sp);
+                /* f * L_env * cos / (cos / pi) */
+                for (int c = 0; c < 3; ++c) L[c] += beta[c] * fb.f[c] * d->env[c] * PI;
+                if (vr) {
+                    vr->env = 1;
+                    for (int c = 0; c < 3; ++c) vr->ef[c] = fb.f[c];
+                    vr->eds_dr = fb.ds_dr;
+                    vr->eds_dsp = fb.ds_dsp;
+                }
+            }
+        }
+
+        if (depth == d->max_depth - 1) break;
+
+        /* bounce: sample a direction, pdf and lobe choice held fixed (detached) */
+        double ub[4];
+        uniforms(d, (uint32_t)pixel, (uint32_t)s, 1u + 2u * depth, ub);
+        v3 wi = sample_bounce(d->brdf, n, wo, rs, ub[0], ub[1], ub[2]);
+        double ci = dot(n, wi);
+        UPD(&so, depth, absd(ci) / TAU_COS, 8);
+        double pdf = bounce_pdf(d->brdf, n, wo, wi, rs);
+        if (ci <= 0 || pdf <= 0) break;
+        brdf_val fb = brdf_eval(d->brdf, n, wo, wi, alb, r, sp);
+        double w = ci / pdf;
+        for (int c = 0; c < 3; ++c) beta[c] *= fb.f[c] * w;
+        if (vr) {
+            vr->bounced = 1;
+            vr->bw = w;
+            for (int c = 0; c < 3; ++c) vr->bf[c] = fb.f[c];
+            vr->bds_dr = fb.ds_dr;
+            vr->bds_dsp = fb.ds_dsp;
+        }
+        o = x;
+        dir = wi;
+        skip = prim;
+    }
+    return so;
+}
+
+static double clip_threshold(const orc_desc* d, int* argmin) {
+    int a = 0;
+    for (int c = 1; c < 3; ++c)
+        if (d->wb[c] < d->wb[a]) a = c;
+    if (argmin) *argmin = a;
+    return d->clip_k / d->wb[a];
+}
+
+/* Eq. 5 */
+static double crf(const orc_desc* d, int c, double Ec) {
+    double y = d->crf_gain * d->wb[c] * Ec;
+    return y > 0 ? pow(y, d->crf_gamma[c]) : 0.0;
+}
+
+static int nthreads_of(const orc_desc* d) {
+#ifdef _OPENMP
+    return d->nthreads > 0 ? d->nthreads : omp_get_max_threads();
+#else
+    (void)d;
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* forward render of a set of pixels                                           */
+/*   pixels: npix pixel indices (j*Wc + i), or NULL for all Wc*Hc in order     */
+/*   out_Ec/out_Ic: npix*3; out_L: npix*spp*3 unclipped sample radiance;       */
+/*   out_hits: npix*spp*max_depth; out_margin: npix*spp; out_margin_clip:      */
+/*   npix*spp (forward margin combined with the clip-threshold margin);        */
+/*   out_reason: npix*spp, which decision set the forward margin               */
+/* ------------------------------------------------------------------------- */
+int orc_render(const orc_desc* d, int32_t npix, const int32_t* pixels, double* out_Ec, double* out_Ic,
+               double* out_L, int32_t* out_hits, double* out_margin, double* out_margin_clip,
+               int32_t* out_reason) {
+    ctx_t cx;
+    ctx_init(&cx, d);
+    int thr_arg;
+    double thr = clip_threshold(d, &thr_arg);
+    int nth = nthreads_of(d);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
+    for (int32_t q = 0; q < npix; ++q) {
+        int32_t pixel = pixels ? pixels[q] : q;
+        double acc[3] = {0, 0, 0};
+        for (int32_t s = 0; s < d->spp; ++s) {
+            int64_t sid = (int64_t)q * d->spp + s;
+            sample_out so = trace_sample(&cx, pixel, s, NULL,
+                                         out_hits ? out_hits + sid * d->max_depth : NULL);
+            double mclip = so.margin;
+            for (int c = 0; c < 3; ++c) {
+                double v = so.L[c];
+                if (out_L) out_L[3 * sid + c] = v;
+                if (d->clip) {
+                    mclip = mind(mclip, absd(v - thr) / (thr * TAU_CLIP));
+                    if (v > thr) v = thr;   /* Eq. 12 */
+                }
+                acc[c] += v;
+            }
+            if (out_margin) out_margin[sid] = so.margin;
+            if (out_reason) out_reason[sid] = so.reason;
+            if (out_margin_clip) out_margin_clip[sid] = mclip;
+        }
+        for (int c = 0; c < 3; ++c) {
+            double Ec = acc[c] / d->spp;   /* Eq. 4 as a box-filtered mean */
+            if (out_Ec) out_Ec[3 * q + c] = Ec;
+            if (out_Ic) out_Ic[3 * q + c] = crf(d, c, Ec);
+        }
+    }
+    ctx_free(&cx);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* vector-Jacobian product                                                    */
+/*   G: Hc*Wc*3 cotangent of I_c.  Only the listed pixels (NULL: all) are     */
+/*   differentiated, i.e. G is taken as zero elsewhere.                       */
+/*   Outputs are overwritten (any may be NULL):                                */
+/*     d_Ip Hp*Wp*3, d_albedo th*tw*3, d_rough th*tw, d_spec th*tw,            */
+/*     d_scalars[18] = gamma_p(3), M(9 row-major), gamma_c(3), w(3)            */
+/*   d_Ep (optional, Hp*Wp*3) receives the cotangent of E_p before the PRF.    */
+/* ------------------------------------------------------------------------- */
+int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32_t* pixels,
+                   double* d_Ip, double* d_albedo, double* d_rough, double* d_spec, double* d_scalars,
+                   double* d_Ep_out) {
+    ctx_t cx;
+    ctx_init(&cx, d);
+    int thr_arg;
+    double thr = clip_threshold(d, &thr_arg);
+    int nth = nthreads_of(d);
+    size_t nEp = 3 * (size_t)d->Wp * d->Hp, nT = (size_t)d->tw * d->th;
+    /* per-thread accumulators: dEp, dalb (3), drough, dspec, 6 CRF scalars, 1 threshold */
+    size_t per = nEp + 3 * nT + nT + nT + 7;
+    double* acc = (double*)calloc((size_t)nth * per, sizeof(double));
+    int npix_all = d->Wc * d->Hc;
+    if (!pixels) npix = npix_all;
+
+#pragma omp parallel num_threads(nth)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double* a = acc + (size_t)tid * per;
+        double* gEp = a;
+        double* galb = gEp + nEp;
+        double* grough = galb + 3 * nT;
+        double* gspec = grough + nT;
+        double* gsc = gspec + nT;  /* gamma_c(3), w(3), threshold(1) */
+        vrec* rec = (vrec*)malloc(sizeof(vrec) * (size_t)d->spp * d->max_depth);
+        sample_out* so = (sample_out*)malloc(sizeof(sample_out) * (size_t)d->spp);
+#pragma omp for schedule(dynamic, 1)
+        for (int32_t q = 0; q < npix; ++q) {
+            int32_t pixel = pixels ? pixels[q] : q;
+            /* forward for this pixel */
+            double Ec[3] = {0, 0, 0};
+            for (int32_t s = 0; s < d->spp; ++s) {
+                so[s] = trace_sample(&cx, pixel, s, rec + (size_t)s * d->max_depth, NULL);
+                for (int c = 0; c < 3; ++c) {
+                    double v = so[s].L[c];
+                    if (d->clip && v > thr) v = thr;
+                    Ec[c] += v;
+                }
+            }
+            for (int c = 0; c < 3; ++c) Ec[c] /= d->spp;
+            /* CRF backward (Eq. 5): y = g_c w E_c, I_c = y^gamma_c */
+            double dEc[3];
+            for (int c = 0; c < 3; ++c) {
+                double g = G[3 * (size_t)pixel + c];
+                double y = d->crf_gain * d->wb[c] * Ec[c];
+                dEc[c] = 0;
+                if (y > 0 && g != 0) {
+                    double gc = d->crf_gamma[c];
+                    double dy = g * gc * pow(y, gc - 1.0);
+                    dEc[c] = dy * d->crf_gain * d->wb[c];
+                    gsc[c] += g * pow(y, gc) * log(y);
+                    gsc[3 + c] += dy * d->crf_gain * Ec[c];
+                }
+            }
+            /* per sample: clip (Eq. 12) then the path's own reverse sweep */
+            for (int32_t s = 0; s < d->spp; ++s) {
+                double delta[3];
+                for (int c = 0; c < 3; ++c) {
+                    double g = dEc[c] / d->spp;
+                    if (d->clip && so[s].L[c] > thr) {
+                        gsc[6] += g;        /* flows into the threshold k / min(w) */
+                        delta[c] = 0;
+                    } else {
+                        delta[c] = g;
+                    }
+                }
+                if (delta[0] == 0 && delta[1] == 0 && delta[2] == 0) continue;
+                vrec* pr = rec + (size_t)s * d->max_depth;
+                int nv = so[s].nv;
+                /* R[k]: radiance leaving vertex k toward the previous vertex, unit throughput */
+                double Rn[3] = {0, 0, 0};   /* R of vertex k+1 */
+                for (int k = nv - 1; k >= 0; --k) {
+                    vrec* v = &pr[k];
+                    double Rk[3];
+                    double ga[3] = {0, 0, 0}, gr = 0, gs = 0;
+                    for (int c = 0; c < 3; ++c) {
+                        double own = v->Le[c];
+                        double bd = delta[c] * v->beta[c];  /* dL/d(term of vertex k) */
+                        if (v->proj) {
+                            double Ex = v->pE[c] * v->pgeom;
+                            own += v->pf[c] * Ex;
+                            /* d/dE_p through the bilinear weights */
+                            double gE = bd * v->pf[c] * v->pgeom;
+                            for (int t = 0; t < 4; ++t) gEp[3 * (size_t)v->ptex.idx[t] + c] += gE * v->ptex.w[t];
+                            ga[c] += bd * Ex / PI;
+                            gr += bd * Ex * v->pds_dr;
+                            gs += bd * Ex * v->pds_dsp;
+                        }
+                        if (v->env) {
+                            double Ee = d->env[c] * PI;
+                            own += v->ef[c] * Ee;
+                            ga[c] += bd * Ee / PI;
+                            gr += bd * Ee * v->eds_dr;
+                            gs += bd * Ee * v->eds_dsp;
+                        }
+                        if (v->bounced) {
+                            double Ei = v->bw * Rn[c];
+                            own += v->bf[c] * Ei;
+                            ga[c] += bd * Ei / PI;
+                            gr += bd * Ei * v->bds_dr;
+                            gs += bd * Ei * v->bds_dsp;
+                        }
+                        Rk[c] = own;
+                    }
+                    for (int t = 0; t < 4; ++t) {
+                        size_t ti = (size_t)v->tex.idx[t];
+                        double w = v->tex.w[t];
+                        for (int c = 0; c < 3; ++c) galb[3 * ti + c] += ga[c] * w;
+                        if (d->brdf == 1) {
+                            grough[ti] += gr * w;
+                            gspec[ti] += gs * w;
+                        }
+                    }
+                    for (int c = 0; c < 3; ++c) Rn[c] = Rk[c];
+                }
+            }
+        }
+        free(rec);
+        free(so);
+    }
+    /* reduce the per-thread accumulators in thread order */
+    double* tot = (double*)calloc(per, sizeof(double));
+    for (int t = 0; t < nth; ++t)
+        for (size_t k = 0; k < per; ++k) tot[k] += acc[(size_t)t * per + k];
+    double* gEp = tot;
+    double* galb = gEp + nEp;
+    double* grough = galb + 3 * nT;
+    double* gspec = grough + nT;
+    double* gsc = gspec + nT;
+    double sc[18];
+    memset(sc, 0, sizeof sc);
+    for (int c = 0; c < 3; ++c) { sc[12 + c] = gsc[c]; sc[15 + c] = gsc[3 + c]; }
+    if (d->clip) sc[15 + thr_arg] += -gsc[6] * d->clip_k / (d->wb[thr_arg] * d->wb[thr_arg]);
+
+    /* PRF backward (Eq. 1 with mixing): z = g_p M y, y = I_p^gamma_p, E_p = max(0, z) */
+    if (d_Ip) memset(d_Ip, 0, sizeof(double) * nEp);
+    for (size_t t = 0; t < (size_t)d->Wp * d->Hp; ++t) {
+        double y[3], z[3], dz[3], dy[3];
+        for (int c = 0; c < 3; ++c) {
+            double x = d->Ip[3 * t + c];
+            y[c] = x > 0 ? pow(x, d->prf_gamma[c]) : 0.0;
+        }
+        for (int c = 0; c < 3; ++c) {
+            z[c] = d->prf_gain * (d->prf_mix[3 * c] * y[0] + d->prf_mix[3 * c + 1] * y[1] +
+                                  d->prf_mix[3 * c + 2] * y[2]);
+            dz[c] = z[c] > 0 ? gEp[3 * t + c] : 0.0;
+        }
+        for (int c = 0; c < 3; ++c)
+            dy[c] = d->prf_gain * (d->prf_mix[c] * dz[0] + d->prf_mix[3 + c] * dz[1] + d->prf_mix[6 + c] * dz[2]);
+        for (int c = 0; c < 3; ++c) {
+            double x = d->Ip[3 * t + c];
+            if (x > 0) {
+                if (d_Ip) d_Ip[3 * t + c] = dy[c] * d->prf_gamma[c] * pow(x, d->prf_gamma[c] - 1.0);
+                sc[c] += dy[c] * y[c] * log(x);
+            }
+            for (int k = 0; k < 3; ++k) sc[3 + 3 * c + k] += d->prf_gain * dz[c] * y[k];
+        }
+    }
+    if (d_Ep_out) memcpy(d_Ep_out, gEp, sizeof(double) * nEp);
+    if (d_albedo) memcpy(d_albedo, galb, sizeof(double) * 3 * nT);
+    if (d_rough) memcpy(d_rough, grough, sizeof(double) * nT);
+    if (d_spec) memcpy(d_spec, gspec, sizeof(double) * nT);
+    if (d_scalars) memcpy(d_scalars, sc, sizeof sc);
+    free(tot);
+    free(acc);
+    ctx_free(&cx);
+    (void)npix_all;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* test hooks                                                                 */
+/* ------------------------------------------------------------------------- */
+
+/* brute-force closest hit for n rays: rays = n*8 (o.xyz, d.xyz, tmax, skip) */
+void orc_intersect(const orc_desc* d, int64_t n, const double* rays, int32_t* prim, double* t,
+                   double* b1, double* b2, double* margin) {
+    ctx_t cx;
+    ctx_init(&cx, d);
+    for (int64_t k = 0; k < n; ++k) {
+        const double* r = rays + 8 * k;
+        tri_isect h;
+        memset(&h, 0, sizeof h);
+        double m = 0;
+        int p = closest_hit(d, &cx.sc, mk(r[0], r[1], r[2]), mk(r[3], r[4], r[5]), r[6], (int)r[7], &h,
+                            margin ? &m : NULL);
+        prim[k] = p;
+        if (t) t[k] = p >= 0 ? h.t : INFINITY;
+        if (b1) b1[k] = p >= 0 ? h.b1 : 0;
+        if (b2) b2[k] = p >= 0 ? h.b2 : 0;
+        if (margin) margin[k] = m;
+    }
+    ctx_free(&cx);
+}
+
+/* BRDF value and its derivatives: out[0..2] f, out[3] ds/dr, out[4] ds/dsp */
+void orc_brdf(int32_t kind, const double* n, const double* wo, const double* wi, const double* a, double r,
+              double sp, double* out) {
+    brdf_val b = brdf_eval(kind, mk(n[0], n[1], n[2]), mk(wo[0], wo[1], wo[2]), mk(wi[0], wi[1], wi[2]), a, r, sp);
+    out[0] = b.f[0]; out[1] = b.f[1]; out[2] = b.f[2]; out[3] = b.ds_dr; out[4] = b.ds_dsp;
+}
+
+/* bounce sampler: u[3] = (lobe, u1, u2) -> wi, pdf */
+void orc_sample(int32_t kind, const double* n, const double* wo, double r, int64_t count, const double* u,
+                double* wi, double* pdf) {
+    v3 N = mk(n[0], n[1], n[2]), WO = mk(wo[0], wo[1], wo[2]);
+    for (int64_t k = 0; k < count; ++k) {
+        v3 w = sample_bounce(kind, N, WO, r, u[3 * k], u[3 * k + 1], u[3 * k + 2]);
+        wi[3 * k] = w.x; wi[3 * k + 1] = w.y; wi[3 * k + 2] = w.z;
+        pdf[k] = bounce_pdf(kind, N, WO, w, r);
+    }
+}
+
+double orc_pdf(int32_t kind, const double* n, const double* wo, const double* wi, double r) {
+    return bounce_pdf(kind, mk(n[0], n[1], n[2]), mk(wo[0], wo[1], wo[2]), mk(wi[0], wi[1], wi[2]), r);
+}
+
+double orc_ggx_D(double nh, double r) { return ggx_D(nh, ggx_alpha(r)); }
+double orc_ggx_G1(double c, double r) { return ggx_G1(c, ggx_alpha(r)); }
+
+/* per-texel PRF (Eq. 1 with mixing) for tests */
+void orc_prf(const orc_desc* d, double* Ep) { prf_forward(d, Ep); }
+
+/* bilinear lookup of an arbitrary Hx W x C image at texel-centred coordinates */
+void orc_bilinear(const double* img, int32_t W, int32_t H, int32_t C, int64_t n, const double* xy, double* out) {
+    for (int64_t k = 0; k < n; ++k) {
+        bilin b = bilinear_at(xy[2 * k], xy[2 * k + 1], W, H);
+        for (int c = 0; c < C; ++c) {
+            double s = 0;
+            for (int t = 0; t < 4; ++t) s += b.w[t] * img[(size_t)C * b.idx[t] + c];
+            out[(size_t)C * k + c] = s;
+        }
+    }
+}
+
+int orc_threads(const orc_desc* d) { return nthreads_of(d); }
+
+/* camera ray and first-hit attributes of sample (pixel, s):
+ * out[0..2] ray origin, [3..5] direction, [6] t (inf on miss), [7] prim, [8..10] x,
+ * [11..13] two-sided normal, [14..15] texture uv, [16..17] projector (u,v) of x (nan if behind) */
+void orc_first_hit(const orc_desc* d, int32_t pixel, int32_t s, double* out) {
+    ctx_t cx;
+    ctx_init(&cx, d);
+    int32_t i = pixel % d->Wc, j = pixel / d->Wc;
+    double u[4];
+    uniforms(d, (uint32_t)pixel, (uint32_t)s, 0u, u);
+    v3 dir = nrm(mattv(d->Rc, matv(cx.Kc_inv, mk(i + u[0], j + u[1], 1.0))));
+    v3 o = cx.cam_o;
+    tri_isect h;
+    int prim = closest_hit(d, &cx.sc, o, dir, 1e300, -1, &h, NULL);
+    for (int k = 0; k < 18; ++k) out[k] = NAN;
+    out[0] = o.x; out[1] = o.y; out[2] = o.z; out[3] = dir.x; out[4] = dir.y; out[5] = dir.z;
+    out[6] = INFINITY;
+    out[7] = prim;
+    if (prim >= 0) {
+        v3 v0 = vtx(d, d->F[3 * prim]), v1 = vtx(d, d->F[3 * prim + 1]), v2 = vtx(d, d->F[3 * prim + 2]);
+        v3 x = add(add(scl(v0, h.b0), scl(v1, h.b1)), scl(v2, h.b2));
+        v3 n = nrm(cross(sub(v1, v0), sub(v2, v0)));
+        if (dot(n, dir) > 0) n = scl(n, -1.0);
+        const float* uvp = d->UV + 6 * (size_t)prim;
+        out[6] = h.t;
+        out[8] = x.x; out[9] = x.y; out[10] = x.z;
+        out[11] = n.x; out[12] = n.y; out[13] = n.z;
+        out[14] = h.b0 * uvp[0] + h.b1 * uvp[2] + h.b2 * uvp[4];
+        out[15] = h.b0 * uvp[1] + h.b1 * uvp[3] + h.b2 * uvp[5];
+        v3 xp = add(matv(d->Rp, x), mk(d->tp[0], d->tp[1], d->tp[2]));
+        if (xp.z > 0) {
+            out[16] = (d->Kp[0] * xp.x + d->Kp[1] * xp.y + d->Kp[2] * xp.z) / xp.z;
+            out[17] = (d->Kp[3] * xp.x + d->Kp[4] * xp.y + d->Kp[5] * xp.z) / xp.z;
+        }
+    }
+    ctx_free(&cx);
+}
+
+/* mixture pdf for many directions */
+void orc_pdf_batch(int32_t kind, const double* n, const double* wo, double r, int64_t count, const double* wi,
+                   double* out) {
+    v3 N = mk(n[0], n[1], n[2]), WO = mk(wo[0], wo[1], wo[2]);
+    for (int64_t k = 0; k < count; ++k)
+        out[k] = bounce_pdf(kind, N, WO, mk(wi[3 * k], wi[3 * k + 1], wi[3 * k + 2]), r);
+}

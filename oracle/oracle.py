@@ -1,0 +1,272 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle/dpcs_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: used by the test-suite, the smoke check and the CPU
+baseline of the benchmark.  Nothing on the product path imports this module.
+It takes the plain arrays the seeded generators produce and shares no code
+with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "dpcs_oracle.c")
+LIB = os.path.join(HERE, "libdpcs_oracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C99, FP64, OpenMP over pixels)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fopenmp", "-ffp-contract=off",
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Desc(C.Structure):
+    _fields_ = [
+        ("nv", C.c_int32), ("nt", C.c_int32),
+        ("V", C.c_void_p), ("F", C.c_void_p), ("UV", C.c_void_p), ("Le", C.c_void_p),
+        ("Kc", C.c_double * 9), ("Rc", C.c_double * 9), ("tc", C.c_double * 3),
+        ("Wc", C.c_int32), ("Hc", C.c_int32),
+        ("Kp", C.c_double * 9), ("Rp", C.c_double * 9), ("tp", C.c_double * 3),
+        ("Wp", C.c_int32), ("Hp", C.c_int32),
+        ("brdf", C.c_int32), ("tw", C.c_int32), ("th", C.c_int32),
+        ("albedo", C.c_void_p), ("rough", C.c_void_p), ("spec", C.c_void_p), ("rough_sample", C.c_void_p),
+        ("Ip", C.c_void_p),
+        ("prf_gamma", C.c_double * 3), ("prf_gain", C.c_double), ("prf_mix", C.c_double * 9),
+        ("crf_gamma", C.c_double * 3), ("crf_gain", C.c_double), ("wb", C.c_double * 3),
+        ("env", C.c_double * 3),
+        ("clip", C.c_int32), ("clip_k", C.c_double),
+        ("spp", C.c_int32), ("max_depth", C.c_int32),
+        ("seed", C.c_uint64), ("sample_offset", C.c_uint32),
+        ("nthreads", C.c_int32),
+        ("tmin", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        P = C.c_void_p
+        L.orc_render.argtypes = [C.POINTER(Desc), C.c_int32, P, P, P, P, P, P, P, P]
+        L.orc_render_vjp.argtypes = [C.POINTER(Desc), P, C.c_int32, P, P, P, P, P, P, P]
+        L.orc_philox_batch.argtypes = [C.c_uint64, C.c_int64, P, P]
+        L.orc_intersect.argtypes = [C.POINTER(Desc), C.c_int64, P, P, P, P, P, P]
+        L.orc_brdf.argtypes = [C.c_int32, P, P, P, P, C.c_double, C.c_double, P]
+        L.orc_sample.argtypes = [C.c_int32, P, P, C.c_double, C.c_int64, P, P, P]
+        L.orc_pdf.argtypes = [C.c_int32, P, P, P, C.c_double]
+        L.orc_pdf.restype = C.c_double
+        L.orc_ggx_D.argtypes = [C.c_double, C.c_double]
+        L.orc_ggx_D.restype = C.c_double
+        L.orc_ggx_G1.argtypes = [C.c_double, C.c_double]
+        L.orc_ggx_G1.restype = C.c_double
+        L.orc_prf.argtypes = [C.POINTER(Desc), P]
+        L.orc_bilinear.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int64, P, P]
+        L.orc_threads.argtypes = [C.POINTER(Desc)]
+        L.orc_first_hit.argtypes = [C.POINTER(Desc), C.c_int32, C.c_int32, P]
+        L.orc_pdf_batch.argtypes = [C.c_int32, P, P, C.c_double, C.c_int64, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Scene:
+    """Everything the oracle needs, as contiguous arrays kept alive for the C side.
+
+    `w` is a `synth.Workload`-like object; keyword overrides replace its fields.
+    Textures and the projector image are held in float64 so that finite
+    differences can perturb them.
+    """
+
+    def __init__(self, w, **over):
+        g = lambda k: over[k] if k in over else getattr(w, k)
+        mesh = g("mesh")
+        self.V = np.ascontiguousarray(mesh.vertices, np.float32)
+        self.F = np.ascontiguousarray(mesh.triangles, np.int32)
+        self.UV = np.ascontiguousarray(mesh.corner_uvs, np.float32)
+        self.Le = None if mesh.emission is None else np.ascontiguousarray(mesh.emission, np.float32)
+        self.camera = g("camera")
+        self.projector = g("projector")
+        self.brdf = int(g("brdf"))
+        self.albedo = np.ascontiguousarray(g("albedo"), np.float64)
+        self.rough = np.ascontiguousarray(g("roughness"), np.float64)
+        self.spec = np.ascontiguousarray(g("specular"), np.float64)
+        self.rough_sample = None if over.get("rough_sample") is None else \
+            np.ascontiguousarray(over["rough_sample"], np.float64)
+        self.Ip = np.ascontiguousarray(g("proj_image"), np.float64)
+        self.prf_gamma = np.asarray(g("prf_gamma"), np.float64)
+        self.prf_gain = float(g("prf_gain"))
+        self.prf_mix = np.asarray(g("prf_mix"), np.float64)
+        self.crf_gamma = np.asarray(g("crf_gamma"), np.float64)
+        self.crf_gain = float(g("crf_gain"))
+        self.wb = np.asarray(g("white_balance"), np.float64)
+        self.env = np.asarray(g("env"), np.float64)
+        self.clip = bool(g("clip"))
+        self.clip_k = float(g("clip_k"))
+        self.spp = int(g("spp"))
+        self.max_depth = int(g("max_depth"))
+        self.seed = int(g("seed"))
+        self.sample_offset = int(g("sample_offset"))
+        self.nthreads = int(over.get("nthreads", 0))
+        self.tmin = float(over.get("tmin", 0.0))
+
+    def desc(self) -> Desc:
+        d = Desc()
+        d.nv, d.nt = self.V.shape[0], self.F.shape[0]
+        d.V, d.F, d.UV, d.Le = _p(self.V), _p(self.F), _p(self.UV), _p(self.Le)
+        cam, prj = self.camera, self.projector
+        d.Kc[:] = list(np.ravel(cam.K)); d.Rc[:] = list(np.ravel(cam.R)); d.tc[:] = list(cam.t)
+        d.Wc, d.Hc = cam.width, cam.height
+        d.Kp[:] = list(np.ravel(prj.K)); d.Rp[:] = list(np.ravel(prj.R)); d.tp[:] = list(prj.t)
+        d.Wp, d.Hp = prj.width, prj.height
+        d.brdf = self.brdf
+        d.th, d.tw = self.albedo.shape[0], self.albedo.shape[1]
+        d.albedo, d.rough, d.spec = _p(self.albedo), _p(self.rough), _p(self.spec)
+        d.rough_sample = _p(self.rough_sample)
+        d.Ip = _p(self.Ip)
+        d.prf_gamma[:] = list(self.prf_gamma); d.prf_gain = self.prf_gain
+        d.prf_mix[:] = list(np.ravel(self.prf_mix))
+        d.crf_gamma[:] = list(self.crf_gamma); d.crf_gain = self.crf_gain; d.wb[:] = list(self.wb)
+        d.env[:] = list(self.env)
+        d.clip = int(self.clip); d.clip_k = self.clip_k
+        d.spp, d.max_depth = self.spp, self.max_depth
+        d.seed, d.sample_offset = self.seed, self.sample_offset
+        d.nthreads = self.nthreads
+        d.tmin = self.tmin
+        self._d = d
+        return d
+
+
+def render(sc: Scene, pixels=None, want=("Ec", "Ic", "L", "hits", "margin", "margin_clip")):
+    """Forward render of all pixels (pixels=None) or of the listed pixel indices j*W+i."""
+    d = sc.desc()
+    n = sc.camera.width * sc.camera.height if pixels is None else len(pixels)
+    px = None if pixels is None else np.ascontiguousarray(pixels, np.int32)
+    out = {}
+    out["Ec"] = np.zeros((n, 3)) if "Ec" in want else None
+    out["Ic"] = np.zeros((n, 3)) if "Ic" in want else None
+    out["L"] = np.zeros((n, sc.spp, 3)) if "L" in want else None
+    out["hits"] = np.zeros((n, sc.spp, sc.max_depth), np.int32) if "hits" in want else None
+    out["margin"] = np.zeros((n, sc.spp)) if "margin" in want else None
+    out["margin_clip"] = np.zeros((n, sc.spp)) if "margin_clip" in want else None
+    out["reason"] = np.zeros((n, sc.spp), np.int32) if "reason" in want else None
+    lib().orc_render(C.byref(d), n, _p(px), _p(out["Ec"]), _p(out["Ic"]), _p(out["L"]), _p(out["hits"]),
+                     _p(out["margin"]), _p(out["margin_clip"]), _p(out["reason"]))
+    return {k: v for k, v in out.items() if v is not None}
+
+
+def render_vjp(sc: Scene, G, pixels=None):
+    """VJP of the rendered image I_c with cotangent G (Hc x Wc x 3)."""
+    d = sc.desc()
+    G = np.ascontiguousarray(G, np.float64)
+    px = None if pixels is None else np.ascontiguousarray(pixels, np.int32)
+    n = 0 if pixels is None else len(pixels)
+    th, tw = sc.albedo.shape[:2]
+    out = dict(Ip=np.zeros(sc.Ip.shape), albedo=np.zeros((th, tw, 3)), roughness=np.zeros((th, tw)),
+               specular=np.zeros((th, tw)), scalars=np.zeros(18), Ep=np.zeros(sc.Ip.shape))
+    lib().orc_render_vjp(C.byref(d), _p(G), n, _p(px), _p(out["Ip"]), _p(out["albedo"]), _p(out["roughness"]),
+                         _p(out["specular"]), _p(out["scalars"]), _p(out["Ep"]))
+    s = out.pop("scalars")
+    out.update(prf_gamma=s[0:3], prf_mix=s[3:12].reshape(3, 3), crf_gamma=s[12:15], white_balance=s[15:18])
+    return out
+
+
+def philox(seed: int, counters: np.ndarray) -> np.ndarray:
+    c = np.ascontiguousarray(counters, np.uint32).reshape(-1, 4)
+    out = np.zeros_like(c)
+    lib().orc_philox_batch(seed, c.shape[0], _p(c), _p(out))
+    return out
+
+
+def intersect(sc: Scene, rays: np.ndarray, with_margin=False):
+    """rays: n x 8 (o, d, tmax, skip) -> prim, t, b1, b2 (brute force, FP64)."""
+    d = sc.desc()
+    r = np.ascontiguousarray(rays, np.float64)
+    n = r.shape[0]
+    prim = np.zeros(n, np.int32)
+    t, b1, b2 = np.zeros(n), np.zeros(n), np.zeros(n)
+    m = np.zeros(n) if with_margin else None
+    lib().orc_intersect(C.byref(d), n, _p(r), _p(prim), _p(t), _p(b1), _p(b2), _p(m))
+    return (prim, t, b1, b2, m) if with_margin else (prim, t, b1, b2)
+
+
+def brdf(kind, n, wo, wi, a, r, sp):
+    out = np.zeros(5)
+    f = lambda v: np.ascontiguousarray(v, np.float64)
+    lib().orc_brdf(kind, _p(f(n)), _p(f(wo)), _p(f(wi)), _p(f(a)), float(r), float(sp), _p(out))
+    return out
+
+
+def sample(kind, n, wo, r, u):
+    u = np.ascontiguousarray(u, np.float64).reshape(-1, 3)
+    wi = np.zeros((u.shape[0], 3))
+    pdf = np.zeros(u.shape[0])
+    f = lambda v: np.ascontiguousarray(v, np.float64)
+    lib().orc_sample(kind, _p(f(n)), _p(f(wo)), float(r), u.shape[0], _p(u), _p(wi), _p(pdf))
+    return wi, pdf
+
+
+def pdf(kind, n, wo, wi, r):
+    f = lambda v: np.ascontiguousarray(v, np.float64)
+    return lib().orc_pdf(kind, _p(f(n)), _p(f(wo)), _p(f(wi)), float(r))
+
+
+def ggx_D(nh, r):
+    return lib().orc_ggx_D(float(nh), float(r))
+
+
+def ggx_G1(c, r):
+    return lib().orc_ggx_G1(float(c), float(r))
+
+
+def prf(sc: Scene):
+    d = sc.desc()
+    out = np.zeros(sc.Ip.shape)
+    lib().orc_prf(C.byref(d), _p(out))
+    return out
+
+
+def bilinear(img, xy):
+    img = np.ascontiguousarray(img, np.float64)
+    H, W = img.shape[:2]
+    Cc = 1 if img.ndim == 2 else img.shape[2]
+    xy = np.ascontiguousarray(xy, np.float64).reshape(-1, 2)
+    out = np.zeros((xy.shape[0], Cc))
+    lib().orc_bilinear(_p(img), W, H, Cc, xy.shape[0], _p(xy), _p(out))
+    return out
+
+
+def threads(sc: Scene) -> int:
+    return lib().orc_threads(C.byref(sc.desc()))
+
+
+def first_hit(sc: Scene, pixel: int, s: int):
+    """Camera ray and first-hit attributes of one camera sample."""
+    d = sc.desc()
+    out = np.zeros(18)
+    lib().orc_first_hit(C.byref(d), int(pixel), int(s), _p(out))
+    return dict(o=out[0:3], d=out[3:6], t=out[6], prim=int(out[7]), x=out[8:11], n=out[11:14],
+                uv=out[14:16], puv=out[16:18])
+
+
+def pdf_batch(kind, n, wo, r, wi):
+    f = lambda v: np.ascontiguousarray(v, np.float64)
+    wi = f(wi).reshape(-1, 3)
+    out = np.zeros(wi.shape[0])
+    lib().orc_pdf_batch(kind, _p(f(n)), _p(f(wo)), float(r), wi.shape[0], _p(wi), _p(out))
+    return out
