@@ -1,0 +1,227 @@
+/*
+ * dpcs.h -- C ABI of the MI355X (gfx950) DPCS project-and-capture renderer.
+ *
+ * The library renders the camera image a projector-camera system captures when a
+ * projector input image is projected onto a textured triangle-mesh surface, and the
+ * vector-Jacobian product of that map (paper Sec. 3):
+ *
+ *   forward rendering   I_c = R(I_p, theta)                       (Eq. 7)
+ *   inverse rendering   {I_p, theta} = R^-1(I_c) by gradients      (Eq. 8, 9, 13)
+ *
+ * with the projector response E_p = g_p M I_p^gamma_p (Eq. 1; M = I gives Eq. 1
+ * exactly), a pinhole projector emitter (Eq. 2, 6), multi-bounce Monte-Carlo light
+ * transport with importance sampling (Eq. 3, 10), per-sample radiance clipping
+ * min(L, k / min(w)) (Eq. 12), a box-filtered pixel mean (Eq. 4) and the camera
+ * response I_c = (g_c w E_c)^gamma_c (Eq. 5).
+ *
+ * Conventions (every entry point):
+ *  - Images and maps are float32, contiguous, row-major HWC (H rows, W columns,
+ *    C channels); albedo H x W x 3, roughness and specular H x W.
+ *  - Unless stated otherwise, pointers passed to render / VJP / server calls are
+ *    DEVICE pointers on the context's device; the caller owns them and keeps them
+ *    valid until the context's stream has passed the call.  Mesh inputs of
+ *    dpcs_scene_create are HOST pointers and are copied.
+ *  - Every render call is asynchronous on the context's HIP stream; nothing syncs
+ *    the host except dpcs_scene_create, dpcs_context_synchronize and the server.
+ *  - Argument checks happen before any launch and return DPCS_E_INVALID with a
+ *    message for dpcs_last_error().  Device faults are sticky: the next call on the
+ *    context returns DPCS_E_DEVICE.
+ *  - Pinhole devices map a world point x to device coordinates R x + t (OpenCV axes,
+ *    +z forward) and to pixel coordinates (K (R x + t)).xy / z; pixel (i, j) covers
+ *    [i, i+1) x [j, j+1).
+ */
+#ifndef DPCS_H
+#define DPCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define DPCS_API __attribute__((visibility("default")))
+#else
+#define DPCS_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DPCS_OK = 0,
+    DPCS_E_INVALID = -1,      /* bad argument; nothing was launched */
+    DPCS_E_OOM = -2,          /* scratch limit or device memory exhausted; outputs undefined */
+    DPCS_E_DEVICE = -3,       /* a HIP call or kernel failed (sticky on the context) */
+    DPCS_E_UNSUPPORTED = -4,  /* valid request this build cannot serve (e.g. BVH too deep) */
+    DPCS_E_BUSY = -5,         /* object still referenced by queued work */
+    DPCS_E_REJECTED = -6      /* server: the request can never fit the memory budget */
+} dpcs_status;
+
+enum { DPCS_BRDF_LAMBERT = 0, DPCS_BRDF_GGX = 1 };
+
+typedef struct dpcs_context_s* dpcs_context;
+typedef struct dpcs_scene_s* dpcs_scene;
+typedef struct dpcs_server_s* dpcs_server;
+
+/* ---------------------------------------------------------------- context */
+
+/* One device, one HIP stream (hip_stream may be NULL: the null stream) and a scratch
+ * pool that grows up to scratch_limit_bytes (0: no limit). */
+DPCS_API dpcs_status dpcs_context_create(int32_t device, void* hip_stream, size_t scratch_limit_bytes,
+                                dpcs_context* out);
+DPCS_API void dpcs_context_destroy(dpcs_context ctx);
+/* Text of the last error on ctx (valid until the next call on ctx); "" if none. */
+DPCS_API const char* dpcs_last_error(dpcs_context ctx);
+/* Waits for the context's stream; reports DPCS_E_DEVICE if queued work failed. */
+DPCS_API dpcs_status dpcs_context_synchronize(dpcs_context ctx);
+/* Samples per launch wave (in-flight path capacity, >= 1).  Results do not depend on it. */
+DPCS_API dpcs_status dpcs_context_set_capacity(dpcs_context ctx, int64_t paths);
+
+/* ------------------------------------------------------------------ scene */
+
+/* Triangle mesh of the projection surface (paper Sec. 3.1: the surface x_s the
+ * projector lights and the camera sees).  HOST pointers, copied. */
+typedef struct {
+    const float* positions;     /* num_vertices x 3 */
+    int32_t num_vertices;
+    const int32_t* triangles;   /* num_triangles x 3 vertex indices */
+    int32_t num_triangles;
+    const float* corner_uvs;    /* num_triangles x 3 x 2 texture coordinates */
+    const float* emission;      /* NULL, or num_triangles x 3 surface radiance (test scenes) */
+} dpcs_mesh_desc;
+
+typedef struct {
+    int32_t num_triangles;
+    int32_t num_nodes;          /* binary BVH internal nodes */
+    int32_t max_depth;          /* deepest leaf */
+    int32_t reserved;
+    int64_t device_bytes;       /* resident bytes (BVH + triangle records + attributes) */
+    double build_ms;            /* GPU time of the BVH build */
+    float bbox_lo[3], bbox_hi[3];
+    float tmin;                 /* ray epsilon: 1e-5 x bounding-box diagonal */
+} dpcs_scene_info;
+
+/* Uploads the mesh and builds its BVH on the device (Morton codes, radix sort,
+ * binary radix tree, bottom-up bounds).  Synchronises the context's stream. */
+DPCS_API dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc* mesh, dpcs_scene* out);
+DPCS_API dpcs_status dpcs_scene_get_info(dpcs_scene s, dpcs_scene_info* out);
+/* Frees the scene after the context's stream has drained; DPCS_E_BUSY while a server
+ * still holds requests on it. */
+DPCS_API dpcs_status dpcs_scene_destroy(dpcs_scene s);
+
+/* ----------------------------------------------------------------- render */
+
+typedef struct {
+    double K[9];                /* intrinsics, row-major */
+    double R[9];                /* world -> device rotation, row-major */
+    double t[3];                /* world -> device translation */
+    int32_t width, height;
+} dpcs_pinhole;
+
+/* Scalar parameters of theta that the VJP differentiates, in this order. */
+enum { DPCS_NUM_SCALARS = 18 };  /* gamma_p[3], M[9] row-major, gamma_c[3], w[3] */
+
+typedef struct {
+    dpcs_pinhole camera, projector;       /* Eq. 6 */
+    int32_t brdf;                         /* DPCS_BRDF_LAMBERT or DPCS_BRDF_GGX */
+    const float* albedo;                  /* tex_h x tex_w x 3 (device) */
+    const float* roughness;               /* tex_h x tex_w (device; GGX only, else may be NULL) */
+    const float* specular;                /* tex_h x tex_w (device; GGX only, else may be NULL) */
+    int32_t tex_w, tex_h;
+    float prf_gamma[3];                   /* gamma_p (Eq. 1) */
+    float prf_gain;                       /* g_p (Eq. 1; folds phi of Eq. 2) */
+    float prf_mix[9];                     /* M, row-major; identity for Eq. 1 */
+    float crf_gamma[3];                   /* gamma_c (Eq. 5) */
+    float crf_gain;                       /* g_c (Eq. 5) */
+    float white_balance[3];               /* w (Eq. 5, Eq. 12) */
+    const float* device_scalars;          /* NULL, or device[18] overriding the five fields
+                                             gamma_p, M, gamma_c, w above (same order) */
+    float env_radiance[3];                /* constant environment radiance (0: dark room) */
+    int32_t clip_enable;                  /* Eq. 12 on/off */
+    float clip_k;                         /* k of Eq. 12 */
+    int32_t spp;                          /* camera samples per pixel, >= 1 */
+    int32_t max_depth;                    /* surface vertices per path, 1..64 (1: direct only) */
+    uint64_t seed;                        /* Philox key */
+    uint32_t sample_offset;               /* added to the sample index of every counter */
+} dpcs_render_params;
+
+/* Optional per-call outputs of dpcs_render (any field may be NULL). */
+typedef struct {
+    float* linear;              /* Hc x Wc x 3: E_c before the CRF */
+    float* sample_radiance;     /* Hc x Wc x spp x 3: unclipped radiance of every camera sample */
+    int32_t* hit_prims;         /* Hc x Wc x spp x max_depth: triangle hit per vertex,
+                                   -1 escaped, -2 path ended earlier */
+} dpcs_render_aux;
+
+/* I_c = R(I_p, theta) (Eq. 7).  proj_image: Hp x Wp x 3, out_image: Hc x Wc x 3. */
+DPCS_API dpcs_status dpcs_render(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
+                        const float* proj_image, float* out_image, const dpcs_render_aux* aux);
+
+/* Gradient buffers of dpcs_render_vjp (device pointers, OVERWRITTEN, any may be NULL). */
+typedef struct {
+    float* d_proj_image;        /* Hp x Wp x 3 */
+    float* d_albedo;            /* tex_h x tex_w x 3 */
+    float* d_roughness;         /* tex_h x tex_w */
+    float* d_specular;          /* tex_h x tex_w */
+    float* d_scalars;           /* DPCS_NUM_SCALARS, layout of device_scalars */
+} dpcs_grads;
+
+/* Vector-Jacobian product of dpcs_render at the same params (same seed: the same
+ * sample paths are replayed): given grad_image = dLoss/dI_c (Hc x Wc x 3), writes
+ * dLoss/d{I_p, albedo, roughness, specular, gamma_p, M, gamma_c, w} (Eq. 9, 13).
+ * sample_radiance (optional) is the aux output of the forward call with the same
+ * params; when NULL the forward samples are recomputed. */
+DPCS_API dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
+                            const float* proj_image, const float* grad_image,
+                            const float* sample_radiance, const dpcs_grads* grads);
+
+/* ------------------------------------------------------------ debug/test */
+
+/* Closest hits of n rays (device: rays n x 8 = o.xyz, d.xyz, tmax, skip prim as float),
+ * through the BVH (use_bvh = 1) or by brute force over all triangles (0).
+ * Output device arrays: prim (n), t/b1/b2 (n each; may be NULL). */
+DPCS_API dpcs_status dpcs_debug_intersect(dpcs_context ctx, dpcs_scene scene, const float* rays, int64_t n,
+                                 int32_t use_bvh, int32_t* prim, float* t, float* b1, float* b2);
+/* Philox4x32-10 of n counters (device: ctr n x 4, out n x 4). */
+DPCS_API dpcs_status dpcs_debug_philox(dpcs_context ctx, uint64_t seed, const uint32_t* ctr, int64_t n,
+                              uint32_t* out);
+
+/* ----------------------------------------------------------------- server */
+
+/* Continuous-batching request loop on ctx's device: requests are admitted while the
+ * device-memory estimate of all admitted requests stays within memory_budget_bytes and
+ * fewer than max_slots are active; every launch wave mixes camera samples of all active
+ * requests in shared path queues. */
+DPCS_API dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget_bytes, int32_t max_slots,
+                               dpcs_server* out);
+
+typedef struct {
+    dpcs_scene scene;
+    dpcs_render_params params;  /* copied at submit; device pointers must stay valid */
+    const float* proj_image;    /* Hp x Wp x 3 */
+    float* out_image;           /* Hc x Wc x 3 */
+    /* compensation step (fwd + VJP), when grads != NULL: the cotangent is grad_image, or,
+       if grad_image is NULL and target is not, the gradient of the L2 loss
+       sum((I_c - target)^2) / (Hc Wc 3) */
+    const float* grad_image;
+    const float* target;
+    const dpcs_grads* grads;
+    uint64_t request_id;
+} dpcs_request;
+
+/* Non-blocking.  DPCS_E_REJECTED if the request alone exceeds the budget. */
+DPCS_API dpcs_status dpcs_server_submit(dpcs_server srv, const dpcs_request* req);
+/* Non-blocking: up to max finished requests (ids, statuses, latency in ms from submit
+ * to completion on the device; latency_ms may be NULL).  Returns the count. */
+DPCS_API int32_t dpcs_server_poll(dpcs_server srv, uint64_t* done_ids, int32_t* done_status, double* latency_ms,
+                         int32_t max);
+/* Counters: [0] submitted, [1] completed, [2] rejected, [3] active, [4] queued,
+ * [5] launch waves, [6] samples traced, [7] peak admitted bytes. */
+DPCS_API dpcs_status dpcs_server_stats(dpcs_server srv, int64_t* out8);
+/* Waits for every admitted request, then stops the loop. */
+DPCS_API dpcs_status dpcs_server_destroy(dpcs_server srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPCS_H */

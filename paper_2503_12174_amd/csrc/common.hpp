@@ -1,0 +1,307 @@
+// common.hpp -- device-side building blocks shared by the gfx950 kernels:
+// small vector math, the Philox4x32-10 counter-based generator, the BRDF (Lambert,
+// Lambert + GGX microfacet specular) with its derivatives, the bounce sampler, and
+// the per-request descriptor every kernel reads.
+//
+// Precision plan: BVH traversal runs in FP32 on rounded copies of the rays (it only
+// decides which triangle is hit).  Everything that turns a hit into a number --
+// hit point, texture and projector coordinates, directions, BRDF -- runs in FP64:
+// FP32 texel coordinates of 512^2 maps carry ~3e-5 texel of rounding, which steep
+// roughness maps turn into ~1e-3 relative error of a glossy GGX lobe.  CDNA4 runs
+// FP64 vector math at half the FP32 rate, and shading is not the bottleneck.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpcs {
+
+constexpr int BLOCK = 256;          // threads per workgroup (4 wave64)
+constexpr double PI = 3.14159265358979323846;
+constexpr double P_SPEC = 0.25;     // probability of sampling the GGX lobe
+constexpr double ALPHA_MIN = 1e-3;  // GGX alpha floor
+
+// ---------------------------------------------------------------------------
+// vectors
+// ---------------------------------------------------------------------------
+template <class T>
+struct Vec3 {
+    T x, y, z;
+};
+using V3 = Vec3<float>;
+using D3 = Vec3<double>;
+
+template <class T> __device__ __forceinline__ Vec3<T> mk3(T x, T y, T z) { return Vec3<T>{x, y, z}; }
+__device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ D3 d3(double x, double y, double z) { return D3{x, y, z}; }
+template <class T> __device__ __forceinline__ Vec3<T> operator+(Vec3<T> a, Vec3<T> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class T> __device__ __forceinline__ Vec3<T> operator-(Vec3<T> a, Vec3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class T> __device__ __forceinline__ Vec3<T> operator-(Vec3<T> a) { return {-a.x, -a.y, -a.z}; }
+template <class T> __device__ __forceinline__ Vec3<T> operator*(Vec3<T> a, T s) { return {a.x * s, a.y * s, a.z * s}; }
+template <class T> __device__ __forceinline__ Vec3<T> operator*(Vec3<T> a, Vec3<T> b) { return {a.x * b.x, a.y * b.y, a.z * b.z}; }
+template <class T> __device__ __forceinline__ T dot(Vec3<T> a, Vec3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class T> __device__ __forceinline__ Vec3<T> cross(Vec3<T> a, Vec3<T> b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ V3 normalize(V3 a) { return a * (1.0f / sqrtf(dot(a, a))); }
+__device__ __forceinline__ D3 normalize(D3 a) { return a * (1.0 / sqrt(dot(a, a))); }
+__device__ __forceinline__ V3 xyz(float4 a) { return v3(a.x, a.y, a.z); }
+__device__ __forceinline__ float4 f4(V3 a, float w) { return make_float4(a.x, a.y, a.z, w); }
+__device__ __forceinline__ V3 to_f(D3 a) { return v3((float)a.x, (float)a.y, (float)a.z); }
+__device__ __forceinline__ D3 to_d(V3 a) { return d3(a.x, a.y, a.z); }
+__device__ __forceinline__ float comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
+// 3x3 row-major times vector
+__device__ __forceinline__ D3 mat3(const double* m, D3 a) {
+    return d3(m[0] * a.x + m[1] * a.y + m[2] * a.z, m[3] * a.x + m[4] * a.y + m[5] * a.z,
+              m[6] * a.x + m[7] * a.y + m[8] * a.z);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): counter (c0..c3), 64-bit key
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                            uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+// top 24 bits -> [0, 1), exact in float and double
+__device__ __forceinline__ double u24(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
+
+// ---------------------------------------------------------------------------
+// path state in HBM: 80 bytes per path
+// ---------------------------------------------------------------------------
+struct alignas(16) PathO {   // ray origin, request slot, triangle the ray leaves (-1: none)
+    double x, y, z;
+    int32_t slot, skip;
+};
+struct alignas(16) PathD {   // unit direction, global sample index
+    double x, y, z;
+    uint32_t g, pad;
+};
+
+// ---------------------------------------------------------------------------
+// per-request descriptor (one per active request; kernels read it by slot)
+// ---------------------------------------------------------------------------
+struct ReqDesc {
+    // camera: world direction of pixel position (px, py) is cam_M (px, py, 1)
+    double cam_o[3];
+    double cam_M[9];
+    // projector: device coords R x + t, pixel (K (R x + t)).xy / z
+    double prj_R[9];
+    double prj_t[3];
+    double prj_o[3];
+    double prj_K[6];
+    int32_t Wc, Hc, Wp, Hp;
+    // scene (BVH + leaf-ordered triangle records)
+    const float4* nodes;
+    const float4* tris;      // 3 float4 per leaf: v0 (w = prim id bits), v1, v2
+    const float4* tri_uv;    // 2 float4 per leaf: (u0 v0 u1 v1), (u2 v2 - -)
+    const float4* emission;  // per leaf (rgb, -) or null
+    float tmin;
+    int32_t stack_hint;
+    // material
+    int32_t brdf;
+    int32_t tw, th;
+    const float4* tex4;      // packed (albedo rgb, roughness) per texel
+    const float* spec;       // specular per texel
+    // lights
+    const float4* Ep;        // projector irradiance after the PRF, per texel (rgb, -)
+    float env[3];
+    int32_t env_on;
+    // sampling
+    int32_t spp, max_depth;
+    uint32_t seed_lo, seed_hi, sample_offset;
+    // responses
+    float prf_gain, crf_gain;
+    int32_t clip;
+    float clip_k;
+    float scal[18];          // gamma_p[3], M[9], gamma_c[3], w[3]
+    const float* dscal;      // device override of scal (or null)
+    // mapping of this wave's samples: batch index sid = g - g_base + sid_base
+    uint32_t g_base, sid_base;
+    // outputs
+    const float* proj_image;
+    float* out_image;
+    float* out_linear;
+    float* out_L;
+    int32_t* out_hits;
+    // adjoint
+    const float* grad_image;   // dLoss/dI_c, or null with target set
+    const float* target;       // L2 target (server compensation step)
+    float* dEp;                // cotangent of E_p, 4 floats per texel
+    float* d_tex;              // cotangent of (albedo rgb, roughness, specular), 5 floats per texel
+    float* d_acc;              // 8 floats: d gamma_c[3], d w[3], d threshold, pad
+};
+
+__device__ __forceinline__ float scalar(const ReqDesc& r, int k) { return r.dscal ? r.dscal[k] : r.scal[k]; }
+__device__ __forceinline__ float clip_threshold(const ReqDesc& r) {
+    float w0 = scalar(r, 15), w1 = scalar(r, 16), w2 = scalar(r, 17);
+    return r.clip_k / fminf(w0, fminf(w1, w2));
+}
+
+// ---------------------------------------------------------------------------
+// BRDF: f = albedo / pi  [+ F D G / (4 cos_i cos_o)]  (GGX, Smith G, Schlick F)
+// evaluated in FP64; the microfacet term uses sin^2 theta_h from |n x h|^2 so the
+// GGX denominator has no cancellation near the lobe peak.
+// ---------------------------------------------------------------------------
+struct Brdf {
+    D3 f;           // value per channel
+    double ds_dr;   // d(specular term)/d roughness
+    double ds_dsp;  // d(specular term)/d specular
+};
+
+__device__ __forceinline__ double ggx_alpha(double r) { return fmax(r * r, ALPHA_MIN); }
+// D(h) from cos^2 and sin^2 of the half-vector angle
+__device__ __forceinline__ double ggx_D(double c2, double s2, double a) {
+    const double a2 = a * a;
+    const double k = a2 * c2 + s2;
+    return a2 / (PI * k * k);
+}
+
+template <bool GRAD>
+__device__ __forceinline__ Brdf brdf_eval(int kind, D3 n, D3 wo, D3 wi, D3 alb, double r, double sp) {
+    Brdf b{d3(0., 0., 0.), 0., 0.};
+    const double ci = dot(n, wi), co = dot(n, wo);
+    if (ci <= 0.0 || co <= 0.0) return b;
+    b.f = alb * (1.0 / PI);
+    if (kind == 0) return b;
+    const D3 h = normalize(wi + wo);
+    const double nh = dot(n, h), ih = dot(wi, h);
+    const D3 nxh = cross(n, h);
+    const double c2 = nh * nh, s2 = dot(nxh, nxh);
+    const double a = ggx_alpha(r);
+    const double a2 = a * a;
+    const double k = a2 * c2 + s2;
+    const double D = a2 / (PI * k * k);
+    const double qi = sqrt(a2 + (1.0 - a2) * ci * ci), qo = sqrt(a2 + (1.0 - a2) * co * co);
+    const double G1i = 2.0 * ci / (ci + qi), G1o = 2.0 * co / (co + qo);
+    const double G = G1i * G1o;
+    const double F0 = 0.08 * sp;
+    const double m = 1.0 - ih;
+    const double m5 = m * m * m * m * m;
+    const double F = F0 + (1.0 - F0) * m5;
+    const double inv_den = 1.0 / (4.0 * ci * co);
+    const double s = F * D * G * inv_den;
+    b.f = b.f + d3(s, s, s);
+    if (GRAD) {
+        // dD/da = 2a/(pi k^2) (1 - 2 a^2 cos^2 / k);  dG1/da = -2c (a (1 - c^2)/q) / (c + q)^2
+        const double dD = 2.0 * a / (PI * k * k) * (1.0 - 2.0 * a2 * c2 / k);
+        const double dG1i = -2.0 * ci * (a * (1.0 - ci * ci) / qi) / ((ci + qi) * (ci + qi));
+        const double dG1o = -2.0 * co * (a * (1.0 - co * co) / qo) / ((co + qo) * (co + qo));
+        const double dG = dG1i * G1o + G1i * dG1o;
+        const double da_dr = (r * r > ALPHA_MIN) ? 2.0 * r : 0.0;
+        b.ds_dr = F * (dD * G + D * dG) * inv_den * da_dr;
+        b.ds_dsp = 0.08 * (1.0 - m5) * D * G * inv_den;
+    }
+    return b;
+}
+
+// branchless orthonormal basis (Duff et al., JCGT 2017)
+__device__ __forceinline__ D3 local_to_world(D3 n, double x, double y, double z) {
+    const double s = copysign(1.0, n.z);
+    const double a = -1.0 / (s + n.z);
+    const double b = n.x * n.y * a;
+    const D3 t1 = d3(1.0 + s * n.x * n.x * a, s * b, -s * n.x);
+    const D3 t2 = d3(b, s + n.y * n.y * a, -n.y);
+    return t1 * x + t2 * y + n * z;
+}
+
+__device__ __forceinline__ D3 sample_cosine(D3 n, double u1, double u2) {
+    const double rr = sqrt(u1);
+    double sn, cs;
+    sincos(2.0 * PI * u2, &sn, &cs);
+    return local_to_world(n, rr * cs, rr * sn, sqrt(1.0 - u1));
+}
+
+// GGX normal-distribution sampling (Walter et al. 2007): tan^2 theta_h = a^2 u1 / (1 - u1)
+__device__ __forceinline__ D3 sample_ggx_h(D3 n, double r, double u1, double u2) {
+    const double a = ggx_alpha(r);
+    const double t2 = a * a * u1 / (1.0 - u1);
+    const double ct = 1.0 / sqrt(1.0 + t2);
+    const double st = sqrt(t2) * ct;
+    double sn, cs;
+    sincos(2.0 * PI * u2, &sn, &cs);
+    return local_to_world(n, st * cs, st * sn, ct);
+}
+
+__device__ __forceinline__ D3 sample_bounce(int kind, D3 n, D3 wo, double r, double ulobe, double u1, double u2) {
+    if (kind == 1 && ulobe < P_SPEC) {
+        const D3 h = sample_ggx_h(n, r, u1, u2);
+        return h * (2.0 * dot(wo, h)) - wo;
+    }
+    return sample_cosine(n, u1, u2);
+}
+
+// density of sample_bounce (solid angle); the microfacet normal that produced wi is
+// the one of +-(wi + wo) on n's side
+__device__ __forceinline__ double bounce_pdf(int kind, D3 n, D3 wo, D3 wi, double r) {
+    const double ci = dot(n, wi);
+    const double pd = ci > 0.0 ? ci * (1.0 / PI) : 0.0;
+    if (kind == 0) return pd;
+    const D3 h = normalize(wi + wo);
+    const double nh = fabs(dot(n, h)), oh = fabs(dot(wo, h));
+    const D3 nxh = cross(n, h);
+    const double ps = (nh > 0.0 && oh > 0.0) ? ggx_D(nh * nh, dot(nxh, nxh), ggx_alpha(r)) * nh / (4.0 * oh) : 0.0;
+    return (1.0 - P_SPEC) * pd + P_SPEC * ps;
+}
+
+// ---------------------------------------------------------------------------
+// bilinear footprint, clamp-to-edge, texel centres at integer + 0.5; coordinates,
+// weights and the interpolation in FP64 (map values are FP32 inputs)
+// ---------------------------------------------------------------------------
+struct Bilin {
+    int i00, i10, i01, i11;
+    double w00, w10, w01, w11;
+};
+// x, y in texel units with texel (i, j) centred at (i, j)
+__device__ __forceinline__ Bilin bilinear(double x, double y, int W, int H) {
+    const double fx = floor(x), fy = floor(y);
+    const double ax = x - fx, ay = y - fy;
+    const double cx = fmin(fmax(fx, -2.0), (double)W + 1.0), cy = fmin(fmax(fy, -2.0), (double)H + 1.0);
+    int x0 = (int)cx, y0 = (int)cy;
+    int x1 = x0 + 1, y1 = y0 + 1;
+    x0 = min(max(x0, 0), W - 1);
+    x1 = min(max(x1, 0), W - 1);
+    y0 = min(max(y0, 0), H - 1);
+    y1 = min(max(y1, 0), H - 1);
+    Bilin b;
+    b.i00 = y0 * W + x0;
+    b.i10 = y0 * W + x1;
+    b.i01 = y1 * W + x0;
+    b.i11 = y1 * W + x1;
+    b.w00 = (1.0 - ax) * (1.0 - ay);
+    b.w10 = ax * (1.0 - ay);
+    b.w01 = (1.0 - ax) * ay;
+    b.w11 = ax * ay;
+    return b;
+}
+
+struct D4 {
+    double x, y, z, w;
+};
+__device__ __forceinline__ D4 fetch4(const float4* __restrict__ t, const Bilin& b) {
+    const float4 p = t[b.i00], q = t[b.i10], s = t[b.i01], u = t[b.i11];
+    return D4{b.w00 * p.x + b.w10 * q.x + b.w01 * s.x + b.w11 * u.x,
+              b.w00 * p.y + b.w10 * q.y + b.w01 * s.y + b.w11 * u.y,
+              b.w00 * p.z + b.w10 * q.z + b.w01 * s.z + b.w11 * u.z,
+              b.w00 * p.w + b.w10 * q.w + b.w01 * s.w + b.w11 * u.w};
+}
+__device__ __forceinline__ double fetch1(const float* __restrict__ t, const Bilin& b) {
+    return b.w00 * t[b.i00] + b.w10 * t[b.i10] + b.w01 * t[b.i01] + b.w11 * t[b.i11];
+}
+
+}  // namespace dpcs

@@ -1,0 +1,107 @@
+// kernels.hpp -- host-side entry points of the device kernels (one process, one device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace dpcs {
+
+// ------------------------------------------------------------------ BVH build
+struct BvhInputs {
+    const float* V;          // device vertices
+    const int* F;            // device triangles
+    const float* UV;         // device corner uvs
+    const float* Le;         // device emission or null
+    int nt;
+    float lo[3], scale[3];   // centroid box origin and 1023 / extent
+    uint32_t* keys[2];
+    uint32_t* vals[2];
+    uint32_t* hist;          // 256 * ntiles
+    int* child;              // 2 * (nt - 1)
+    int* parent_int;         // nt - 1
+    int* parent_leaf;        // nt
+    int* flags;              // nt - 1, zeroed
+    float* node_box;         // 6 * (nt - 1)
+};
+struct BvhOutputs {
+    float4* nodes;           // 4 * max(nt - 1, 1)
+    float4* tris;            // 3 * nt
+    float4* tri_uv;          // 2 * nt
+    float4* emission;        // nt or null
+    int* leaf_of_prim;       // nt
+    const uint32_t* order;   // leaf -> original triangle (points into keys/vals scratch)
+};
+hipError_t build_bvh(hipStream_t st, const BvhInputs& in, BvhOutputs& out);
+
+// ------------------------------------------------------------------ path queues
+// Structure-of-arrays queues in HBM.  Path state is FP64 position/direction (PathO,
+// PathD, 32 B each) plus FP32 throughput; shadow rays only need a visibility
+// decision and are FP32 (16-byte float4 fields: a wave64 touches 1 KiB per field).
+struct Queues {
+    PathO* po[2];      // path ray origin, slot, triangle left
+    PathD* pd[2];      // path ray direction, global sample index g
+    float4* pb[2];     // path throughput beta (rgb, -)
+    int* hit;          // leaf-order triangle hit by the current queue (-1: escaped)
+    float4* so[2];     // shadow ray origin (w: slot); [0] projector, [1] environment
+    float4* sd[2];     // shadow direction (w: triangle the ray leaves)
+    float4* sc[2];     // shadow contribution (w: batch sample index)
+    float* st[2];      // shadow tmax
+    float4* L;         // per batch sample radiance (rgb, -)
+    uint32_t* cnt;     // [0], [1] path queue sizes, [2], [3] shadow queue sizes
+    int64_t cap;       // path capacity
+};
+
+// adjoint additions (see adjoint.hip)
+struct AdjQueues {
+    float4* rl[2];     // remaining radiance L_r of the path (rgb, -), follows the path queue
+    float4* delta;     // per batch sample cotangent of its radiance (rgb, -)
+    float4* sx[2];     // shadow: projector (u, v) and texture (u, v) of the vertex
+    float4* sg[2];     // shadow: E_p cotangent weight per channel (w: -)
+    float4* sa[2];     // shadow: albedo cotangent rgb (w: roughness cotangent)
+    float* ss[2];      // shadow: specular cotangent
+    float4* pend[2];   // pending bounce: (u, v, dr, dsp) cotangent scale of the previous vertex
+    float4* penda[2];  // pending bounce: albedo cotangent scale rgb
+};
+
+struct Launch {
+    hipStream_t st;
+    int grid_cap;      // upper bound on workgroups of grid-stride kernels
+};
+
+// forward kernels; `uni` is the request descriptor when every path of the launch
+// belongs to one request (table == null), else descriptors are read from `table`.
+void launch_prf(const Launch& l, const ReqDesc& r, float4* Ep);
+void launch_pack_tex(const Launch& l, const ReqDesc& r, const float* albedo, const float* rough, float4* tex4);
+void launch_set_count(const Launch& l, uint32_t* cnt, int idx, uint32_t value, int zero_from, int zero_to);
+void launch_raygen(const Launch& l, const Queues& q, const ReqDesc& r, const ReqDesc* table, int slot,
+                   uint32_t g0, uint32_t n, bool adjoint, const AdjQueues* aq);
+void launch_trace(const Launch& l, const Queues& q, int cur, const ReqDesc& uni, const ReqDesc* table, int64_t n_upper,
+                  int stack);
+void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const ReqDesc& uni, const ReqDesc* table,
+                  int64_t n_upper);
+void launch_shadow(const Launch& l, const Queues& q, int which, const ReqDesc& uni, const ReqDesc* table,
+                   int64_t n_upper, int stack);
+void launch_finalize(const Launch& l, const Queues& q, const ReqDesc& r, const ReqDesc* table, int slot,
+                     uint32_t p0, uint32_t p1);
+void launch_set_desc(const Launch& l, ReqDesc* table, int slot, const ReqDesc& r);
+
+// adjoint kernels
+void launch_adj_pixel(const Launch& l, const Queues& q, const AdjQueues& aq, const ReqDesc& r, const ReqDesc* table,
+                      int slot, uint32_t p0, uint32_t p1);
+void launch_adj_shade(const Launch& l, const Queues& q, const AdjQueues& aq, int cur, int depth, const ReqDesc& uni,
+                      const ReqDesc* table, int64_t n_upper);
+void launch_adj_shadow(const Launch& l, const Queues& q, const AdjQueues& aq, int which, const ReqDesc& uni,
+                       const ReqDesc* table, int64_t n_upper, int stack);
+void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* d_albedo, float* d_rough,
+                       float* d_spec, float* d_scalars, float* scal_partials, int nblocks_partials);
+void launch_zero(const Launch& l, float* p, int64_t n);
+
+// debug
+void launch_debug_intersect(const Launch& l, const float4* nodes, const float4* tris, const int* leaf_of_prim, int nt,
+                            float tmin, const float* rays, int64_t n, int use_bvh, int stack, int32_t* prim,
+                            float* t, float* b1, float* b2);
+void launch_debug_philox(const Launch& l, uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out);
+
+}  // namespace dpcs

@@ -1,0 +1,361 @@
+// render.hip -- forward wavefront path tracer of the project-and-capture process.
+//
+// One launch wave traces a batch of camera samples through structure-of-arrays
+// queues in HBM:
+//   raygen   camera ray of every sample (Philox jitter, Eq. 6 inverted)
+//   trace    closest hit of every queued path (BVH)
+//   shade    hit point, BRDF maps, projector next-event estimation (Eq. 1-3, 6),
+//            environment next-event estimation, bounce sampling (Eq. 10); emits
+//            shadow rays and the surviving paths, compacted with wave64 ballots
+//   shadow   any-hit visibility of each shadow ray; visible contributions are added
+//            to the sample's radiance slot (one writer per slot per launch)
+//   finalize clip per sample (Eq. 12), ordered mean over the pixel's samples (Eq. 4),
+//            camera response and white balance (Eq. 5)
+#include "kernels.hpp"
+#include "shade.hpp"
+
+namespace dpcs {
+
+constexpr int TB = 128;   // threads per workgroup of the traversal kernels
+
+// ---------------------------------------------------------------- per texel
+// Eq. 1 with colour mixing: E_p = max(0, g_p M max(I_p, 0)^gamma_p)
+__global__ void k_prf(ReqDesc r, float4* __restrict__ Ep) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= r.Wp * r.Hp) return;
+    float y[3];
+    for (int c = 0; c < 3; ++c) {
+        const float x = r.proj_image[3 * t + c];
+        y[c] = x > 0.0f ? powf(x, scalar(r, c)) : 0.0f;
+    }
+    float e[3];
+    for (int c = 0; c < 3; ++c) {
+        const float z = r.prf_gain * (scalar(r, 3 + 3 * c) * y[0] + scalar(r, 4 + 3 * c) * y[1] +
+                                      scalar(r, 5 + 3 * c) * y[2]);
+        e[c] = fmaxf(z, 0.0f);
+    }
+    Ep[t] = make_float4(e[0], e[1], e[2], 0.0f);
+}
+
+__global__ void k_pack_tex(int n, const float* __restrict__ albedo, const float* __restrict__ rough,
+                           float4* __restrict__ tex4) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    tex4[t] = make_float4(albedo[3 * t], albedo[3 * t + 1], albedo[3 * t + 2], rough ? rough[t] : 0.0f);
+}
+
+__global__ void k_set_count(uint32_t* cnt, int idx, uint32_t value, int zero_from, int zero_to) {
+    if (threadIdx.x == 0) {
+        if (idx >= 0) cnt[idx] = value;
+        for (int k = zero_from; k < zero_to; ++k) cnt[k] = 0u;
+    }
+}
+
+__global__ void k_zero(float* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+__global__ void k_set_desc(ReqDesc r, ReqDesc* table, int slot) {
+    if (threadIdx.x == 0) table[slot] = r;
+}
+
+// ---------------------------------------------------------------- raygen
+__global__ void k_raygen(Queues q, ReqDesc r, int slot, uint32_t g0, uint32_t n) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t g = g0 + k;
+    const uint32_t sid = g - r.g_base + r.sid_base;
+    const D3 d = camera_dir(r, g);
+    q.po[0][sid] = PathO{r.cam_o[0], r.cam_o[1], r.cam_o[2], slot, -1};
+    q.pd[0][sid] = PathD{d.x, d.y, d.z, g, 0u};
+    q.pb[0][sid] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
+    q.L[sid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (r.out_hits)
+        for (int dd = 0; dd < r.max_depth; ++dd) r.out_hits[(size_t)g * r.max_depth + dd] = -2;
+}
+
+// ---------------------------------------------------------------- closest hit
+template <bool UNI, int STACK>
+__global__ void __launch_bounds__(TB) k_trace(Queues q, int cur, ReqDesc uni, const ReqDesc* __restrict__ table) {
+    __shared__ int stack[STACK * TB];
+    const uint32_t n = q.cnt[cur];
+    for (uint32_t i = blockIdx.x * TB + threadIdx.x; i < n; i += gridDim.x * TB) {
+        const PathO o = q.po[cur][i];
+        const PathD d = q.pd[cur][i];
+        const ReqDesc& r = sel<UNI>(uni, table, o.slot);
+        Hit h;
+        traverse<false, STACK, TB>(r.nodes, r.tris, v3((float)o.x, (float)o.y, (float)o.z),
+                                   v3((float)d.x, (float)d.y, (float)d.z), r.tmin, __builtin_inff(), o.skip, h,
+                                   stack + threadIdx.x);
+        q.hit[i] = h.leaf;
+    }
+}
+
+// ---------------------------------------------------------------- shading
+template <bool UNI>
+__global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, ReqDesc uni,
+                                                 const ReqDesc* __restrict__ table) {
+    const int nxt = cur ^ 1;
+    const uint32_t n = q.cnt[cur];
+    for (uint32_t base = blockIdx.x * BLOCK; base < n; base += gridDim.x * BLOCK) {
+        const uint32_t i = base + threadIdx.x;
+        bool cont = false, shp = false, she = false;
+        PathO no{};
+        PathD nd{};
+        float4 nb = {}, po = {}, pd = {}, pc = {}, eo = {}, ed = {}, ec = {};
+        float ptmax = 0.0f;
+        if (i < n) {
+            const PathO o = q.po[cur][i];
+            const PathD dd = q.pd[cur][i];
+            const float4 b = q.pb[cur][i];
+            const int leaf = q.hit[i];
+            const ReqDesc& r = sel<UNI>(uni, table, o.slot);
+            const uint32_t g = dd.g;
+            const uint32_t sid = g - r.g_base + r.sid_base;
+            const D3 beta = d3(b.x, b.y, b.z);
+            if (leaf < 0) {
+                if (r.out_hits) r.out_hits[(size_t)g * r.max_depth + depth] = -1;
+                if (depth == 0 && r.env_on) {   // a camera ray that escapes sees the environment
+                    float4 L = q.L[sid];
+                    L.x += (float)(beta.x * r.env[0]);
+                    L.y += (float)(beta.y * r.env[1]);
+                    L.z += (float)(beta.z * r.env[2]);
+                    q.L[sid] = L;
+                }
+            } else {
+                const Surf s = surface(r, leaf, d3(o.x, o.y, o.z), d3(dd.x, dd.y, dd.z));
+                if (r.out_hits) r.out_hits[(size_t)g * r.max_depth + depth] = s.prim;
+                if (r.emission) {   // test scenes: surface emission
+                    const float4 e = r.emission[leaf];
+                    float4 L = q.L[sid];
+                    L.x += (float)(beta.x * e.x);
+                    L.y += (float)(beta.y * e.y);
+                    L.z += (float)(beta.z * e.z);
+                    q.L[sid] = L;
+                }
+                ProjNee p;
+                if (projector_nee(r, s, p)) {
+                    const D4 E = fetch4(r.Ep, p.pb);
+                    const Brdf f = brdf_eval<false>(r.brdf, s.n, s.wo, p.wp, s.alb, s.rough, s.spec);
+                    const D3 C = beta * f.f * d3(E.x, E.y, E.z) * p.geom;
+                    if (C.x > 0.0 || C.y > 0.0 || C.z > 0.0) {
+                        shp = true;
+                        po = f4(to_f(s.x), __int_as_float(o.slot));
+                        pd = f4(to_f(p.wp), __int_as_float(s.prim));
+                        pc = f4(to_f(C), __uint_as_float(sid));
+                        ptmax = (float)(p.dist - r.tmin);
+                    }
+                }
+                if (r.env_on) {
+                    const U4 x = vertex_rng(r, g, 2u + 2u * depth);
+                    const D3 we = sample_cosine(s.n, u24(x.x), u24(x.y));
+                    const Brdf f = brdf_eval<false>(r.brdf, s.n, s.wo, we, s.alb, s.rough, s.spec);
+                    const D3 C = beta * f.f * d3(r.env[0], r.env[1], r.env[2]) * PI;
+                    if (C.x > 0.0 || C.y > 0.0 || C.z > 0.0) {
+                        she = true;
+                        eo = f4(to_f(s.x), __int_as_float(o.slot));
+                        ed = f4(to_f(we), __int_as_float(s.prim));
+                        ec = f4(to_f(C), __uint_as_float(sid));
+                    }
+                }
+                if (depth < r.max_depth - 1) {
+                    const U4 x = vertex_rng(r, g, 1u + 2u * depth);
+                    const D3 wi = sample_bounce(r.brdf, s.n, s.wo, s.rough, u24(x.x), u24(x.y), u24(x.z));
+                    const double ci = dot(s.n, wi);
+                    const double pdf = bounce_pdf(r.brdf, s.n, s.wo, wi, s.rough);
+                    if (ci > 0.0 && pdf > 0.0) {
+                        const Brdf f = brdf_eval<false>(r.brdf, s.n, s.wo, wi, s.alb, s.rough, s.spec);
+                        const D3 nbeta = beta * (f.f * (ci / pdf));
+                        cont = true;
+                        no = PathO{s.x.x, s.x.y, s.x.z, o.slot, s.prim};
+                        nd = PathD{wi.x, wi.y, wi.z, g, 0u};
+                        nb = make_float4((float)nbeta.x, (float)nbeta.y, (float)nbeta.z, 0.0f);
+                    }
+                }
+            }
+        }
+        const uint32_t jn = wave_append(cont, &q.cnt[nxt]);
+        if (cont) {
+            q.po[nxt][jn] = no;
+            q.pd[nxt][jn] = nd;
+            q.pb[nxt][jn] = nb;
+        }
+        const uint32_t jp = wave_append(shp, &q.cnt[2]);
+        if (shp) {
+            q.so[0][jp] = po;
+            q.sd[0][jp] = pd;
+            q.sc[0][jp] = pc;
+            q.st[0][jp] = ptmax;
+        }
+        const uint32_t je = wave_append(she, &q.cnt[3]);
+        if (she) {
+            q.so[1][je] = eo;
+            q.sd[1][je] = ed;
+            q.sc[1][je] = ec;
+            q.st[1][je] = __builtin_inff();
+        }
+    }
+}
+
+// ---------------------------------------------------------------- shadows
+template <bool UNI, int STACK>
+__global__ void __launch_bounds__(TB) k_shadow(Queues q, int which, ReqDesc uni, const ReqDesc* __restrict__ table) {
+    __shared__ int stack[STACK * TB];
+    const uint32_t n = q.cnt[2 + which];
+    for (uint32_t i = blockIdx.x * TB + threadIdx.x; i < n; i += gridDim.x * TB) {
+        const float4 o = q.so[which][i], d = q.sd[which][i];
+        const ReqDesc& r = sel<UNI>(uni, table, __float_as_int(o.w));
+        Hit h;
+        const bool occ = traverse<true, STACK, TB>(r.nodes, r.tris, xyz(o), xyz(d), r.tmin, q.st[which][i],
+                                                   __float_as_int(d.w), h, stack + threadIdx.x);
+        if (!occ) {
+            const float4 c = q.sc[which][i];
+            const uint32_t sid = __float_as_uint(c.w);
+            float4 L = q.L[sid];
+            L.x += c.x;
+            L.y += c.y;
+            L.z += c.z;
+            q.L[sid] = L;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- finalize
+__device__ __forceinline__ float crf(const ReqDesc& r, int c, float Ec) {
+    const float y = r.crf_gain * scalar(r, 15 + c) * Ec;
+    return y > 0.0f ? powf(y, scalar(r, 12 + c)) : 0.0f;
+}
+
+__global__ void k_finalize(Queues q, ReqDesc r, uint32_t p0, uint32_t p1) {
+    const uint32_t p = p0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= p1) return;
+    const float thr = clip_threshold(r);
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    for (int s = 0; s < r.spp; ++s) {
+        const uint32_t g = p * (uint32_t)r.spp + (uint32_t)s;
+        const float4 L = q.L[g - r.g_base + r.sid_base];
+        const float l[3] = {L.x, L.y, L.z};
+        for (int c = 0; c < 3; ++c) {
+            if (r.out_L) r.out_L[3 * (size_t)g + c] = l[c];
+            acc[c] += r.clip ? fminf(l[c], thr) : l[c];
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        const float Ec = acc[c] / (float)r.spp;
+        if (r.out_linear) r.out_linear[3 * (size_t)p + c] = Ec;
+        if (r.out_image) r.out_image[3 * (size_t)p + c] = crf(r, c, Ec);
+    }
+}
+
+// ---------------------------------------------------------------- debug
+template <int STACK>
+__global__ void __launch_bounds__(TB) k_debug_intersect(const float4* __restrict__ nodes,
+                                                        const float4* __restrict__ tris,
+                                                        const int* __restrict__ leaf_of_prim, int nt, float tmin,
+                                                        const float* __restrict__ rays, int64_t n, int use_bvh,
+                                                        int32_t* prim, float* t, float* b1, float* b2) {
+    __shared__ int stack[STACK * TB];
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    const float* ry = rays + 8 * i;
+    const V3 o = v3(ry[0], ry[1], ry[2]), d = v3(ry[3], ry[4], ry[5]);
+    Hit h;
+    if (use_bvh)
+        traverse<false, STACK, TB>(nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, stack + threadIdx.x);
+    else
+        brute_force<false>(tris, leaf_of_prim, nt, o, d, tmin, ry[6], (int)ry[7], h);
+    prim[i] = h.prim;
+    if (t) t[i] = h.t;
+    if (b1) b1[i] = h.b1;
+    if (b2) b2[i] = h.b2;
+}
+
+__global__ void k_debug_philox(uint32_t klo, uint32_t khi, const uint32_t* __restrict__ ctr, int64_t n,
+                               uint32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const U4 x = philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], klo, khi);
+    out[4 * i] = x.x;
+    out[4 * i + 1] = x.y;
+    out[4 * i + 2] = x.z;
+    out[4 * i + 3] = x.w;
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned grid_of(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+static inline unsigned grid_cap(const Launch& l, int64_t n, int b) {
+    const int64_t g = (n + b - 1) / b;
+    return (unsigned)(g < 1 ? 1 : (g > l.grid_cap ? l.grid_cap : g));
+}
+
+void launch_prf(const Launch& l, const ReqDesc& r, float4* Ep) {
+    hipLaunchKernelGGL(k_prf, dim3(grid_of((int64_t)r.Wp * r.Hp, 256)), dim3(256), 0, l.st, r, Ep);
+}
+void launch_pack_tex(const Launch& l, const ReqDesc& r, const float* albedo, const float* rough, float4* tex4) {
+    const int n = r.tw * r.th;
+    hipLaunchKernelGGL(k_pack_tex, dim3(grid_of(n, 256)), dim3(256), 0, l.st, n, albedo, rough, tex4);
+}
+void launch_set_count(const Launch& l, uint32_t* cnt, int idx, uint32_t value, int zero_from, int zero_to) {
+    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(64), 0, l.st, cnt, idx, value, zero_from, zero_to);
+}
+void launch_zero(const Launch& l, float* p, int64_t n) {
+    if (n > 0) hipLaunchKernelGGL(k_zero, dim3(grid_of(n, 256)), dim3(256), 0, l.st, p, n);
+}
+void launch_set_desc(const Launch& l, ReqDesc* table, int slot, const ReqDesc& r) {
+    hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, l.st, r, table, slot);
+}
+void launch_raygen(const Launch& l, const Queues& q, const ReqDesc& r, const ReqDesc*, int slot, uint32_t g0,
+                   uint32_t n, bool, const AdjQueues*) {
+    if (n) hipLaunchKernelGGL(k_raygen, dim3(grid_of(n, 256)), dim3(256), 0, l.st, q, r, slot, g0, n);
+}
+void launch_trace(const Launch& l, const Queues& q, int cur, const ReqDesc& uni, const ReqDesc* table,
+                  int64_t n_upper, int stack) {
+    const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
+    if (table) {
+        if (stack <= 32) hipLaunchKernelGGL((k_trace<false, 32>), g, b, 0, l.st, q, cur, uni, table);
+        else hipLaunchKernelGGL((k_trace<false, 64>), g, b, 0, l.st, q, cur, uni, table);
+    } else {
+        if (stack <= 32) hipLaunchKernelGGL((k_trace<true, 32>), g, b, 0, l.st, q, cur, uni, table);
+        else hipLaunchKernelGGL((k_trace<true, 64>), g, b, 0, l.st, q, cur, uni, table);
+    }
+}
+void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const ReqDesc& uni, const ReqDesc* table,
+                  int64_t n_upper) {
+    const dim3 g(grid_cap(l, n_upper, BLOCK)), b(BLOCK);
+    if (table) hipLaunchKernelGGL((k_shade<false>), g, b, 0, l.st, q, cur, depth, uni, table);
+    else hipLaunchKernelGGL((k_shade<true>), g, b, 0, l.st, q, cur, depth, uni, table);
+}
+void launch_shadow(const Launch& l, const Queues& q, int which, const ReqDesc& uni, const ReqDesc* table,
+                   int64_t n_upper, int stack) {
+    const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
+    if (table) {
+        if (stack <= 32) hipLaunchKernelGGL((k_shadow<false, 32>), g, b, 0, l.st, q, which, uni, table);
+        else hipLaunchKernelGGL((k_shadow<false, 64>), g, b, 0, l.st, q, which, uni, table);
+    } else {
+        if (stack <= 32) hipLaunchKernelGGL((k_shadow<true, 32>), g, b, 0, l.st, q, which, uni, table);
+        else hipLaunchKernelGGL((k_shadow<true, 64>), g, b, 0, l.st, q, which, uni, table);
+    }
+}
+void launch_finalize(const Launch& l, const Queues& q, const ReqDesc& r, const ReqDesc*, int, uint32_t p0,
+                     uint32_t p1) {
+    if (p1 > p0) hipLaunchKernelGGL(k_finalize, dim3(grid_of(p1 - p0, 256)), dim3(256), 0, l.st, q, r, p0, p1);
+}
+void launch_debug_intersect(const Launch& l, const float4* nodes, const float4* tris, const int* leaf_of_prim, int nt,
+                            float tmin, const float* rays, int64_t n, int use_bvh, int stack, int32_t* prim,
+                            float* t, float* b1, float* b2) {
+    if (n <= 0) return;
+    if (stack <= 32)
+        hipLaunchKernelGGL(k_debug_intersect<32>, dim3(grid_of(n, TB)), dim3(TB), 0, l.st, nodes, tris, leaf_of_prim,
+                           nt, tmin, rays, n, use_bvh, prim, t, b1, b2);
+    else
+        hipLaunchKernelGGL(k_debug_intersect<64>, dim3(grid_of(n, TB)), dim3(TB), 0, l.st, nodes, tris, leaf_of_prim,
+                           nt, tmin, rays, n, use_bvh, prim, t, b1, b2);
+}
+void launch_debug_philox(const Launch& l, uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_debug_philox, dim3(grid_of(n, 256)), dim3(256), 0, l.st, (uint32_t)seed,
+                           (uint32_t)(seed >> 32), ctr, n, out);
+}
+
+}  // namespace dpcs

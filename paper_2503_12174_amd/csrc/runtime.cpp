@@ -1,0 +1,611 @@
+// runtime.cpp -- C ABI implementation: context, scratch pool, scene residency and BVH
+// build, forward render orchestration, debug entry points.
+#include "runtime.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+using namespace dpcs;
+
+namespace dpcs {
+
+dpcs_status fail(dpcs_context ctx, dpcs_status s, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return s;
+}
+
+bool hip_ok(dpcs_context ctx, hipError_t e, const char* what) {
+    if (e == hipSuccess) return true;
+    if (ctx) {
+        ctx->sticky = true;
+        ctx->err = std::string(what) + ": " + hipGetErrorString(e);
+    }
+    return false;
+}
+
+void* scratch(dpcs_context ctx, const char* name, size_t bytes, dpcs_status* st) {
+    bytes = (bytes + 255) & ~size_t(255);
+    auto it = ctx->pool.find(name);
+    if (it != ctx->pool.end() && it->second.second >= bytes) return it->second.first;
+    size_t old = it != ctx->pool.end() ? it->second.second : 0;
+    if (ctx->scratch_limit && ctx->scratch_bytes - old + bytes > ctx->scratch_limit) {
+        *st = fail(ctx, DPCS_E_OOM, std::string("scratch limit exceeded by buffer ") + name);
+        return nullptr;
+    }
+    if (it != ctx->pool.end()) {
+        // the old buffer may still be read by queued work
+        if (!hip_ok(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize")) {
+            *st = DPCS_E_DEVICE;
+            return nullptr;
+        }
+        hipFree(it->second.first);
+        ctx->scratch_bytes -= old;
+        ctx->pool.erase(it);
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        hipGetLastError();
+        *st = fail(ctx, DPCS_E_OOM, std::string("hipMalloc failed for buffer ") + name);
+        return nullptr;
+    }
+    ctx->pool[name] = {p, bytes};
+    ctx->scratch_bytes += bytes;
+    return p;
+}
+
+bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpcs_status* st) {
+    const size_t c = (size_t)cap;
+    // per path: 2 x (PathO 32 + PathD 32 + beta 16) + hit 4 + 2 x shadow (48 + 4) + L 16
+    const size_t bytes = c * (2 * 80 + 4 + 2 * 52 + 16) + 4096;
+    char* b = (char*)scratch(ctx, name, bytes, st);
+    if (!b) return false;
+    auto take = [&](size_t n) {   // 256-byte aligned parts
+        char* p = b;
+        b += (n + 255) & ~size_t(255);
+        return (void*)p;
+    };
+    for (int k = 0; k < 2; ++k) {
+        q.po[k] = (PathO*)take(32 * c);
+        q.pd[k] = (PathD*)take(32 * c);
+        q.pb[k] = (float4*)take(16 * c);
+        q.so[k] = (float4*)take(16 * c);
+        q.sd[k] = (float4*)take(16 * c);
+        q.sc[k] = (float4*)take(16 * c);
+        q.st[k] = (float*)take(4 * c);
+    }
+    q.hit = (int*)take(4 * c);
+    q.L = (float4*)take(16 * c);
+    q.cnt = (uint32_t*)take(16);
+    q.cap = cap;
+    return true;
+}
+
+static void inv3(const double* m, double* o) {
+    const double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5], g = m[6], h = m[7], i = m[8];
+    const double A = e * i - f * h, B = -(d * i - f * g), C = d * h - e * g;
+    const double det = a * A + b * B + c * C;
+    o[0] = A / det;
+    o[1] = -(b * i - c * h) / det;
+    o[2] = (b * f - c * e) / det;
+    o[3] = B / det;
+    o[4] = (a * i - c * g) / det;
+    o[5] = -(a * f - c * d) / det;
+    o[6] = C / det;
+    o[7] = -(a * h - b * g) / det;
+    o[8] = (a * e - b * d) / det;
+}
+
+static double det3(const double* m) {
+    return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+           m[2] * (m[3] * m[7] - m[4] * m[6]);
+}
+
+static bool pinhole_ok(const dpcs_pinhole& p, const char* what, std::string* why) {
+    if (p.width <= 0 || p.height <= 0 || p.width > 16384 || p.height > 16384) {
+        *why = std::string(what) + ": width/height must be in 1..16384";
+        return false;
+    }
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(p.K[k]) || !std::isfinite(p.R[k])) {
+            *why = std::string(what) + ": K and R must be finite";
+            return false;
+        }
+    if (!(std::fabs(det3(p.K)) > 1e-12)) {
+        *why = std::string(what) + ": K is not invertible";
+        return false;
+    }
+    return true;
+}
+
+bool fill_desc(dpcs_context, ReqDesc& r, const dpcs_render_params* p, dpcs_scene sc, const float* proj_image,
+               std::string* why) {
+    std::memset(&r, 0, sizeof r);
+    if (!p) return *why = "params is NULL", false;
+    if (!pinhole_ok(p->camera, "camera", why) || !pinhole_ok(p->projector, "projector", why)) return false;
+    if (p->brdf != DPCS_BRDF_LAMBERT && p->brdf != DPCS_BRDF_GGX) return *why = "brdf must be LAMBERT or GGX", false;
+    if (!p->albedo) return *why = "albedo is NULL", false;
+    if (p->brdf == DPCS_BRDF_GGX && (!p->roughness || !p->specular))
+        return *why = "GGX needs roughness and specular maps", false;
+    if (p->tex_w <= 0 || p->tex_h <= 0 || p->tex_w > 16384 || p->tex_h > 16384)
+        return *why = "tex_w/tex_h must be in 1..16384", false;
+    if (p->spp < 1 || p->spp > 65536) return *why = "spp must be in 1..65536", false;
+    if (p->max_depth < 1 || p->max_depth > 64) return *why = "max_depth must be in 1..64", false;
+    if (!proj_image) return *why = "proj_image is NULL", false;
+    if (!p->device_scalars) {
+        for (int c = 0; c < 3; ++c) {
+            if (!(p->prf_gamma[c] > 0.f) || !(p->crf_gamma[c] > 0.f)) return *why = "gammas must be > 0", false;
+            if (!(p->white_balance[c] > 0.f)) return *why = "white balance must be > 0", false;
+        }
+    }
+    if (!(p->prf_gain >= 0.f) || !(p->crf_gain >= 0.f)) return *why = "gains must be >= 0", false;
+    if (p->clip_enable && !(p->clip_k > 0.f)) return *why = "clip_k must be > 0", false;
+    const int64_t pix = (int64_t)p->camera.width * p->camera.height;
+    if (pix * p->spp >= (int64_t(1) << 32)) return *why = "pixels x spp must be < 2^32", false;
+
+    double Ki[9];
+    inv3(p->camera.K, Ki);
+    const double* R = p->camera.R;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) r.cam_M[3 * i + j] = R[i] * Ki[j] + R[3 + i] * Ki[3 + j] + R[6 + i] * Ki[6 + j];
+    for (int i = 0; i < 3; ++i)
+        r.cam_o[i] = -(R[i] * p->camera.t[0] + R[3 + i] * p->camera.t[1] + R[6 + i] * p->camera.t[2]);
+    r.Wc = p->camera.width;
+    r.Hc = p->camera.height;
+    const double* Rp = p->projector.R;
+    for (int k = 0; k < 9; ++k) r.prj_R[k] = Rp[k];
+    for (int i = 0; i < 3; ++i) {
+        r.prj_t[i] = p->projector.t[i];
+        r.prj_o[i] = -(Rp[i] * p->projector.t[0] + Rp[3 + i] * p->projector.t[1] + Rp[6 + i] * p->projector.t[2]);
+    }
+    for (int k = 0; k < 6; ++k) r.prj_K[k] = p->projector.K[k];
+    r.Wp = p->projector.width;
+    r.Hp = p->projector.height;
+    r.nodes = sc->nodes;
+    r.tris = sc->tris;
+    r.tri_uv = sc->tri_uv;
+    r.emission = sc->emission;
+    r.tmin = sc->tmin;
+    r.stack_hint = stack_for(sc);
+    r.brdf = p->brdf;
+    r.tw = p->tex_w;
+    r.th = p->tex_h;
+    r.spec = p->brdf == DPCS_BRDF_GGX ? p->specular : nullptr;
+    r.env_on = 0;
+    for (int c = 0; c < 3; ++c) {
+        r.env[c] = p->env_radiance[c];
+        if (p->env_radiance[c] != 0.f) r.env_on = 1;
+    }
+    r.spp = p->spp;
+    r.max_depth = p->max_depth;
+    r.seed_lo = (uint32_t)p->seed;
+    r.seed_hi = (uint32_t)(p->seed >> 32);
+    r.sample_offset = p->sample_offset;
+    r.prf_gain = p->prf_gain;
+    r.crf_gain = p->crf_gain;
+    r.clip = p->clip_enable ? 1 : 0;
+    r.clip_k = p->clip_k;
+    for (int c = 0; c < 3; ++c) {
+        r.scal[c] = p->prf_gamma[c];
+        r.scal[12 + c] = p->crf_gamma[c];
+        r.scal[15 + c] = p->white_balance[c];
+    }
+    for (int k = 0; k < 9; ++k) r.scal[3 + k] = p->prf_mix[k];
+    r.dscal = p->device_scalars;
+    r.proj_image = proj_image;
+    return true;
+}
+
+int stack_for(dpcs_scene sc) { return sc->depth <= 32 ? 32 : 64; }
+
+}  // namespace dpcs
+
+// ====================================================================== context
+extern "C" dpcs_status dpcs_context_create(int32_t device, void* hip_stream, size_t scratch_limit_bytes,
+                                           dpcs_context* out) {
+    if (!out) return DPCS_E_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        hipGetLastError();
+        return DPCS_E_INVALID;
+    }
+    if (hipSetDevice(device) != hipSuccess) return DPCS_E_DEVICE;
+    auto* c = new dpcs_context_s();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->scratch_limit = scratch_limit_bytes;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->grid_cap = std::max(1024, prop.multiProcessorCount * 16);
+    *out = c;
+    return DPCS_OK;
+}
+
+extern "C" void dpcs_context_destroy(dpcs_context ctx) {
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->pool) hipFree(kv.second.first);
+    delete ctx;
+}
+
+extern "C" const char* dpcs_last_error(dpcs_context ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" dpcs_status dpcs_context_synchronize(dpcs_context ctx) {
+    if (!ctx) return DPCS_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    hipSetDevice(ctx->device);
+    if (!hip_ok(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize")) return DPCS_E_DEVICE;
+    return ctx->sticky ? DPCS_E_DEVICE : DPCS_OK;
+}
+
+extern "C" dpcs_status dpcs_context_set_capacity(dpcs_context ctx, int64_t paths) {
+    if (!ctx || paths < 1 || paths > (int64_t(1) << 30)) return DPCS_E_INVALID;
+    ctx->capacity = paths;
+    return DPCS_OK;
+}
+
+// ====================================================================== scene
+extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc* m, dpcs_scene* out) {
+    if (!ctx || !m || !out) return DPCS_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    *out = nullptr;
+    if (ctx->sticky) return DPCS_E_DEVICE;
+    (void)hipGetLastError();   // drop errors left by other libraries on this thread
+    if (!m->positions || !m->triangles || !m->corner_uvs || m->num_vertices <= 0 || m->num_triangles <= 0)
+        return fail(ctx, DPCS_E_INVALID, "mesh needs positions, triangles, corner_uvs and positive counts");
+    if (m->num_triangles > (1 << 29)) return fail(ctx, DPCS_E_UNSUPPORTED, "too many triangles");
+    const int nt = m->num_triangles, nv = m->num_vertices;
+    for (int64_t i = 0; i < 3 * (int64_t)nt; ++i)
+        if (m->triangles[i] < 0 || m->triangles[i] >= nv)
+            return fail(ctx, DPCS_E_INVALID, "triangle index out of range");
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < nv; ++i)
+        for (int k = 0; k < 3; ++k) {
+            const double v = m->positions[3 * i + k];
+            if (!std::isfinite(v)) return fail(ctx, DPCS_E_INVALID, "non-finite vertex");
+            lo[k] = std::min(lo[k], v);
+            hi[k] = std::max(hi[k], v);
+        }
+    double clo[3] = {1e300, 1e300, 1e300}, chi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t p = 0; p < nt; ++p)
+        for (int k = 0; k < 3; ++k) {
+            const float c = (m->positions[3 * m->triangles[3 * p] + k] + m->positions[3 * m->triangles[3 * p + 1] + k] +
+                             m->positions[3 * m->triangles[3 * p + 2] + k]) *
+                            (1.0f / 3.0f);
+            clo[k] = std::min(clo[k], (double)c);
+            chi[k] = std::max(chi[k], (double)c);
+        }
+    hipSetDevice(ctx->device);
+    auto* sc = new dpcs_scene_s();
+    sc->ctx = ctx;
+    sc->nt = nt;
+    const double diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                  (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    sc->tmin = (float)(1e-5 * diag);
+    for (int k = 0; k < 3; ++k) {
+        sc->lo[k] = (float)lo[k];
+        sc->hi[k] = (float)hi[k];
+    }
+    const int ni = std::max(nt - 1, 1);
+    const int ntiles = (nt + 1023) / 1024;
+    // resident arrays
+    bool ok = true;
+    auto dmalloc = [&](void** p, size_t b) {
+        if (!ok) return;
+        if (hipMalloc(p, std::max<size_t>(b, 16)) != hipSuccess) {
+            hipGetLastError();
+            ok = false;
+        }
+    };
+    dmalloc((void**)&sc->nodes, sizeof(float4) * 4 * ni);
+    dmalloc((void**)&sc->tris, sizeof(float4) * 3 * nt);
+    dmalloc((void**)&sc->tri_uv, sizeof(float4) * 2 * nt);
+    if (m->emission) dmalloc((void**)&sc->emission, sizeof(float4) * nt);
+    dmalloc((void**)&sc->leaf_of_prim, sizeof(int) * nt);
+    sc->nnodes = ni;
+    sc->bytes = (int64_t)sizeof(float4) * (4 * ni + 3 * nt + 2 * nt + (m->emission ? nt : 0)) + 4 * nt;
+    // build temporaries
+    void *dV = nullptr, *dF = nullptr, *dUV = nullptr, *dLe = nullptr, *tmp = nullptr;
+    dmalloc(&dV, sizeof(float) * 3 * nv);
+    dmalloc(&dF, sizeof(int) * 3 * nt);
+    dmalloc(&dUV, sizeof(float) * 6 * nt);
+    if (m->emission) dmalloc(&dLe, sizeof(float) * 3 * nt);
+    // build temporaries are carved from one buffer, each part rounded up to 256 bytes
+    auto r256 = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t tmp_parts[] = {4 * (size_t)nt, 4 * (size_t)nt, 4 * (size_t)nt, 4 * (size_t)nt,
+                                4 * 256 * (size_t)ntiles, 8 * (size_t)ni, 4 * (size_t)ni, 4 * (size_t)nt,
+                                4 * (size_t)ni, 24 * (size_t)ni};
+    size_t tmp_bytes = 0;
+    for (size_t b : tmp_parts) tmp_bytes += r256(b);
+    dmalloc(&tmp, tmp_bytes);
+    auto cleanup_tmp = [&]() {
+        hipFree(dV);
+        hipFree(dF);
+        hipFree(dUV);
+        if (dLe) hipFree(dLe);
+        hipFree(tmp);
+    };
+    auto destroy_scene = [&]() {
+        hipFree(sc->nodes);
+        hipFree(sc->tris);
+        hipFree(sc->tri_uv);
+        if (sc->emission) hipFree(sc->emission);
+        hipFree(sc->leaf_of_prim);
+        delete sc;
+    };
+    if (!ok) {
+        cleanup_tmp();
+        destroy_scene();
+        return fail(ctx, DPCS_E_OOM, "device allocation failed while creating the scene");
+    }
+    BvhInputs in{};
+    BvhOutputs bo{};
+    char* t = (char*)tmp;
+    int part = 0;
+    auto take = [&]() {   // next part, in the order of tmp_parts
+        char* p = t;
+        t += r256(tmp_parts[part++]);
+        return (void*)p;
+    };
+    in.keys[0] = (uint32_t*)take();
+    in.keys[1] = (uint32_t*)take();
+    in.vals[0] = (uint32_t*)take();
+    in.vals[1] = (uint32_t*)take();
+    in.hist = (uint32_t*)take();
+    in.child = (int*)take();
+    in.parent_int = (int*)take();
+    in.parent_leaf = (int*)take();
+    in.flags = (int*)take();
+    in.node_box = (float*)take();
+    in.V = (const float*)dV;
+    in.F = (const int*)dF;
+    in.UV = (const float*)dUV;
+    in.Le = (const float*)dLe;
+    in.nt = nt;
+    for (int k = 0; k < 3; ++k) {
+        in.lo[k] = (float)clo[k];
+        const double ext = chi[k] - clo[k];
+        in.scale[k] = ext > 0 ? (float)(1023.0 / ext) : 0.0f;
+    }
+    bo.nodes = sc->nodes;
+    bo.tris = sc->tris;
+    bo.tri_uv = sc->tri_uv;
+    bo.emission = sc->emission;
+    bo.leaf_of_prim = sc->leaf_of_prim;
+    hipStream_t st = ctx->stream;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    const char* step = "upload";
+    hipError_t e = hipMemcpyAsync(dV, m->positions, sizeof(float) * 3 * nv, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dF, m->triangles, sizeof(int) * 3 * nt, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dUV, m->corner_uvs, sizeof(float) * 6 * nt, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && m->emission)
+        e = hipMemcpyAsync(dLe, m->emission, sizeof(float) * 3 * nt, hipMemcpyHostToDevice, st);
+    Launch l{st, ctx->grid_cap};
+    if (e == hipSuccess) {
+        step = "init";
+        launch_zero(l, (float*)in.flags, ni);
+        e = hipMemsetAsync(in.parent_int, 0xff, sizeof(int) * ni, st);   // -1: no parent (root)
+        if (e == hipSuccess) e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        step = "build kernels";
+        hipEventRecord(e0, st);
+        e = build_bvh(st, in, bo);
+        hipEventRecord(e1, st);
+    }
+    if (e == hipSuccess) {
+        step = "synchronize";
+        e = hipStreamSynchronize(st);
+    }
+    // depth of the tree (the traversal stack bound)
+    std::vector<int> child(2 * (size_t)ni);
+    std::vector<uint32_t> order(nt);
+    if (e == hipSuccess && nt > 1) e = hipMemcpy(child.data(), in.child, sizeof(int) * 2 * ni, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(order.data(), bo.order, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost);
+    float ms = 0.f;
+    if (e == hipSuccess) hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    cleanup_tmp();
+    if (e != hipSuccess) {
+        hip_ok(ctx, e, (std::string("scene build (") + step + ")").c_str());
+        destroy_scene();
+        return DPCS_E_DEVICE;
+    }
+    // validate the tree before any traversal runs on it: the leaf order is a permutation,
+    // every internal node and every leaf is reached exactly once from the root
+    {
+        std::vector<char> seen(nt, 0);
+        bool perm = true;
+        for (int k = 0; k < nt && perm; ++k) {
+            if (order[k] >= (uint32_t)nt || seen[order[k]]) perm = false;
+            else seen[order[k]] = 1;
+        }
+        if (!perm) {
+            destroy_scene();
+            return fail(ctx, DPCS_E_DEVICE, "BVH build: sorted order is not a permutation");
+        }
+    }
+    int maxd = 1;
+    if (nt > 1) {
+        std::vector<char> seen_node(ni, 0), seen_leaf(nt, 0);
+        std::vector<std::pair<int, int>> stk{{0, 0}};
+        seen_node[0] = 1;
+        bool valid = true;
+        int64_t steps = 0;
+        while (!stk.empty() && valid) {
+            auto [nd, dd] = stk.back();
+            stk.pop_back();
+            if (++steps > 2 * (int64_t)nt) valid = false;
+            for (int k = 0; k < 2 && valid; ++k) {
+                const int c = child[2 * nd + k];
+                if (c < 0) {
+                    const int lf = ~c;
+                    if (lf >= nt || seen_leaf[lf]) valid = false;
+                    else seen_leaf[lf] = 1;
+                    maxd = std::max(maxd, dd + 1);
+                } else {
+                    if (c >= ni || seen_node[c]) valid = false;
+                    else {
+                        seen_node[c] = 1;
+                        stk.push_back({c, dd + 1});
+                    }
+                }
+            }
+        }
+        for (int k = 0; k < ni && valid; ++k) valid = seen_node[k];
+        for (int k = 0; k < nt && valid; ++k) valid = seen_leaf[k];
+        if (!valid) {
+            destroy_scene();
+            return fail(ctx, DPCS_E_DEVICE, "BVH build produced an invalid tree");
+        }
+    }
+    sc->depth = maxd;
+    sc->build_ms = ms;
+    if (maxd > 64) {
+        destroy_scene();
+        return fail(ctx, DPCS_E_UNSUPPORTED, "BVH deeper than 64 levels");
+    }
+    *out = sc;
+    return DPCS_OK;
+}
+
+extern "C" dpcs_status dpcs_scene_get_info(dpcs_scene s, dpcs_scene_info* out) {
+    if (!s || !out) return DPCS_E_INVALID;
+    std::memset(out, 0, sizeof *out);
+    out->num_triangles = s->nt;
+    out->num_nodes = s->nnodes;
+    out->max_depth = s->depth;
+    out->device_bytes = s->bytes;
+    out->build_ms = s->build_ms;
+    for (int k = 0; k < 3; ++k) {
+        out->bbox_lo[k] = s->lo[k];
+        out->bbox_hi[k] = s->hi[k];
+    }
+    out->tmin = s->tmin;
+    return DPCS_OK;
+}
+
+extern "C" dpcs_status dpcs_scene_destroy(dpcs_scene s) {
+    if (!s) return DPCS_E_INVALID;
+    if (s->refs.load() > 0) return fail(s->ctx, DPCS_E_BUSY, "scene still used by queued server requests");
+    dpcs_context ctx = s->ctx;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    hipFree(s->nodes);
+    hipFree(s->tris);
+    hipFree(s->tri_uv);
+    if (s->emission) hipFree(s->emission);
+    hipFree(s->leaf_of_prim);
+    delete s;
+    return DPCS_OK;
+}
+
+// ====================================================================== render
+namespace dpcs {
+
+// Per-request resident inputs of a render: E_p after the PRF and the packed maps.
+bool prepare_request(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, const char* tag, dpcs_status* st) {
+    Launch l{ctx->stream, ctx->grid_cap};
+    std::string a = std::string(tag) + ".Ep", b = std::string(tag) + ".tex";
+    float4* Ep = (float4*)scratch(ctx, a.c_str(), sizeof(float4) * (size_t)r.Wp * r.Hp, st);
+    if (!Ep) return false;
+    float4* tex = (float4*)scratch(ctx, b.c_str(), sizeof(float4) * (size_t)r.tw * r.th, st);
+    if (!tex) return false;
+    launch_prf(l, r, Ep);
+    launch_pack_tex(l, r, p->albedo, p->brdf == DPCS_BRDF_GGX ? p->roughness : nullptr, tex);
+    r.Ep = Ep;
+    r.tex4 = tex;
+    return true;
+}
+
+// Forward waves over pixels [p0, p1) of one request, whole pixels per wave.
+bool forward_waves(dpcs_context ctx, const Queues& q, ReqDesc r, uint32_t p0, uint32_t p1) {
+    Launch l{ctx->stream, ctx->grid_cap};
+    const int64_t ppw = std::max<int64_t>(1, q.cap / r.spp);   // pixels per wave
+    const int stack = r.stack_hint;
+    for (int64_t a = p0; a < p1; a += ppw) {
+        const uint32_t b = (uint32_t)std::min<int64_t>(p1, a + ppw);
+        const uint32_t n = (b - (uint32_t)a) * (uint32_t)r.spp;
+        r.g_base = (uint32_t)a * (uint32_t)r.spp;
+        r.sid_base = 0;
+        launch_set_count(l, q.cnt, 0, n, 1, 4);
+        launch_raygen(l, q, r, nullptr, 0, r.g_base, n, false, nullptr);
+        int cur = 0;
+        for (int d = 0; d < r.max_depth; ++d) {
+            launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);   // next path queue and shadow queues empty
+            launch_trace(l, q, cur, r, nullptr, n, stack);
+            launch_shade(l, q, cur, d, r, nullptr, n);
+            launch_shadow(l, q, 0, r, nullptr, n, stack);
+            if (r.env_on) launch_shadow(l, q, 1, r, nullptr, n, stack);
+            cur ^= 1;
+        }
+        launch_finalize(l, q, r, nullptr, 0, (uint32_t)a, b);
+    }
+    return hip_ok(ctx, hipGetLastError(), "kernel launch");
+}
+
+}  // namespace dpcs
+
+extern "C" dpcs_status dpcs_render(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
+                                   const float* proj_image, float* out_image, const dpcs_render_aux* aux) {
+    if (!ctx) return DPCS_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (ctx->sticky) return DPCS_E_DEVICE;
+    if (!scene || scene->ctx != ctx) return fail(ctx, DPCS_E_INVALID, "scene is NULL or from another context");
+    if (!out_image) return fail(ctx, DPCS_E_INVALID, "out_image is NULL");
+    (void)hipGetLastError();
+    ReqDesc r;
+    std::string why;
+    if (!fill_desc(ctx, r, params, scene, proj_image, &why)) return fail(ctx, DPCS_E_INVALID, why);
+    hipSetDevice(ctx->device);
+    r.out_image = out_image;
+    if (aux) {
+        r.out_linear = aux->linear;
+        r.out_L = aux->sample_radiance;
+        r.out_hits = aux->hit_prims;
+    }
+    dpcs_status st = DPCS_OK;
+    if (!prepare_request(ctx, r, params, "fwd", &st)) return st;
+    const int64_t npix = (int64_t)r.Wc * r.Hc;
+    const int64_t cap = std::min<int64_t>(std::max<int64_t>(ctx->capacity, r.spp), npix * r.spp);
+    Queues q;
+    if (!make_queues(ctx, "fwd.queues", (cap / r.spp) * r.spp, q, &st)) return st;
+    if (!forward_waves(ctx, q, r, 0, (uint32_t)npix)) return DPCS_E_DEVICE;
+    ctx->err.clear();
+    return DPCS_OK;
+}
+
+// ====================================================================== debug
+extern "C" dpcs_status dpcs_debug_intersect(dpcs_context ctx, dpcs_scene scene, const float* rays, int64_t n,
+                                            int32_t use_bvh, int32_t* prim, float* t, float* b1, float* b2) {
+    if (!ctx) return DPCS_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (ctx->sticky) return DPCS_E_DEVICE;
+    if (!scene || !rays || !prim || n < 0) return fail(ctx, DPCS_E_INVALID, "bad debug_intersect arguments");
+    hipSetDevice(ctx->device);
+    (void)hipGetLastError();
+    Launch l{ctx->stream, ctx->grid_cap};
+    launch_debug_intersect(l, scene->nodes, scene->tris, scene->leaf_of_prim, scene->nt, scene->tmin, rays, n, use_bvh,
+                           stack_for(scene), prim, t, b1, b2);
+    return hip_ok(ctx, hipGetLastError(), "debug_intersect") ? DPCS_OK : DPCS_E_DEVICE;
+}
+
+extern "C" dpcs_status dpcs_debug_philox(dpcs_context ctx, uint64_t seed, const uint32_t* ctr, int64_t n,
+                                         uint32_t* out) {
+    if (!ctx) return DPCS_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (!ctr || !out || n < 0) return fail(ctx, DPCS_E_INVALID, "bad debug_philox arguments");
+    hipSetDevice(ctx->device);
+    (void)hipGetLastError();
+    Launch l{ctx->stream, ctx->grid_cap};
+    launch_debug_philox(l, seed, ctr, n, out);
+    return hip_ok(ctx, hipGetLastError(), "debug_philox") ? DPCS_OK : DPCS_E_DEVICE;
+}

@@ -1,0 +1,59 @@
+// runtime.hpp -- host-side state behind the C ABI (context, scratch pool, scenes).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "../../include/dpcs.h"
+#include "kernels.hpp"
+
+struct dpcs_context_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t scratch_limit = 0;
+    size_t scratch_bytes = 0;
+    int64_t capacity = int64_t(1) << 22;   // paths per launch wave
+    std::string err;
+    bool sticky = false;
+    std::map<std::string, std::pair<void*, size_t>> pool;
+    std::recursive_mutex mu;               // serialises calls from several host threads
+    int grid_cap = 4096;
+};
+
+struct dpcs_scene_s {
+    dpcs_context ctx = nullptr;
+    float4* nodes = nullptr;
+    float4* tris = nullptr;
+    float4* tri_uv = nullptr;
+    float4* emission = nullptr;
+    int* leaf_of_prim = nullptr;
+    int nt = 0, nnodes = 0, depth = 0;
+    float tmin = 0.0f;
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    int64_t bytes = 0;
+    double build_ms = 0.0;
+    std::atomic<int> refs{0};              // requests of a server that still use the scene
+};
+
+namespace dpcs {
+
+// sets ctx->err and returns s
+dpcs_status fail(dpcs_context ctx, dpcs_status s, const std::string& msg);
+// checks a HIP status; on error marks the context sticky-failed
+bool hip_ok(dpcs_context ctx, hipError_t e, const char* what);
+// named scratch buffer of at least `bytes` (grows; never shrinks)
+void* scratch(dpcs_context ctx, const char* name, size_t bytes, dpcs_status* st);
+// fills a request descriptor from validated params; false + message on invalid input
+bool fill_desc(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, dpcs_scene sc, const float* proj_image,
+               std::string* why);
+int stack_for(dpcs_scene sc);
+
+// path queues for `cap` paths carved from one scratch buffer (prefix selects the buffer)
+bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpcs_status* st);
+bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues& aq, dpcs_status* st);
+
+}  // namespace dpcs

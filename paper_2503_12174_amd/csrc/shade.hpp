@@ -1,0 +1,112 @@
+// shade.hpp -- per-vertex shading steps shared by the forward kernels and the
+// path-replay adjoint (the replay must reproduce the forward path exactly, so both
+// call these same routines).
+#pragma once
+
+#include "common.hpp"
+#include "trace.hpp"
+
+namespace dpcs {
+
+template <bool UNI>
+__device__ __forceinline__ const ReqDesc& sel(const ReqDesc& uni, const ReqDesc* __restrict__ table, int slot) {
+    return UNI ? uni : table[slot];
+}
+
+// wave-aggregated append: one atomic per wave64, lane order preserved
+__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0ull) return 0u;
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, leader);
+    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+// camera ray of global sample g (pixel = g / spp, sample = g % spp), Eq. 6 inverted
+__device__ __forceinline__ D3 camera_dir(const ReqDesc& r, uint32_t g) {
+    const uint32_t pixel = g / (uint32_t)r.spp, s = g - pixel * (uint32_t)r.spp;
+    const U4 x = philox4x32_10(pixel, s + r.sample_offset, 0u, 0u, r.seed_lo, r.seed_hi);
+    const double px = (double)(pixel % (uint32_t)r.Wc) + u24(x.x);
+    const double py = (double)(pixel / (uint32_t)r.Wc) + u24(x.y);
+    return normalize(mat3(r.cam_M, d3(px, py, 1.0)));
+}
+
+struct Surf {
+    D3 x, n, wo;
+    double u, v;     // texture coordinates
+    int prim;
+    Bilin tb;
+    D3 alb;
+    double rough, spec;
+};
+
+// Hit attributes of the ray (o, d) on the leaf the FP32 traversal found: barycentrics
+// re-solved in FP64 (Cramer's rule on o + t d = v0 + b1 e1 + b2 e2), flat two-sided
+// normal facing the incoming ray, bilinear BRDF maps at the interpolated UV.
+__device__ __forceinline__ Surf surface(const ReqDesc& r, int leaf, D3 o, D3 d) {
+    Surf s;
+    V3 f0, f1, f2;
+    load_tri(r.tris, leaf, f0, f1, f2, s.prim);
+    const D3 v0 = to_d(f0), v1 = to_d(f1), v2 = to_d(f2);
+    const D3 e1 = v1 - v0, e2 = v2 - v0;
+    const D3 p = cross(d, e2);
+    const double det = dot(e1, p);
+    double b1 = 1.0 / 3.0, b2 = 1.0 / 3.0;
+    if (det != 0.0) {
+        const double inv = 1.0 / det;
+        const D3 tv = o - v0;
+        b1 = dot(tv, p) * inv;
+        b2 = dot(d, cross(tv, e1)) * inv;
+    }
+    const double b0 = 1.0 - b1 - b2;
+    s.x = v0 * b0 + v1 * b1 + v2 * b2;
+    D3 n = normalize(cross(e1, e2));
+    s.wo = -d;
+    if (dot(n, s.wo) < 0.0) n = -n;
+    s.n = n;
+    const float4 ua = r.tri_uv[2 * leaf], ub = r.tri_uv[2 * leaf + 1];
+    s.u = b0 * ua.x + b1 * ua.z + b2 * ub.x;
+    s.v = b0 * ua.y + b1 * ua.w + b2 * ub.y;
+    s.tb = bilinear(s.u * r.tw - 0.5, s.v * r.th - 0.5, r.tw, r.th);
+    const D4 t4 = fetch4(r.tex4, s.tb);
+    s.alb = d3(t4.x, t4.y, t4.z);
+    s.rough = t4.w;
+    s.spec = r.brdf ? fetch1(r.spec, s.tb) : 0.0;
+    return s;
+}
+
+// projector next-event estimation geometry (Eq. 2, 6); false outside the frustum or
+// when the projector is behind the surface
+struct ProjNee {
+    D3 wp;
+    double dist, geom;   // (1/cos^3 alpha) cos theta / d^2
+    double pu, pv;
+    Bilin pb;
+};
+__device__ __forceinline__ bool projector_nee(const ReqDesc& r, const Surf& s, ProjNee& p) {
+    const D3 xp = mat3(r.prj_R, s.x) + d3(r.prj_t[0], r.prj_t[1], r.prj_t[2]);
+    if (!(xp.z > 0.0)) return false;
+    const double iz = 1.0 / xp.z;
+    p.pu = (r.prj_K[0] * xp.x + r.prj_K[1] * xp.y + r.prj_K[2] * xp.z) * iz;
+    p.pv = (r.prj_K[3] * xp.x + r.prj_K[4] * xp.y + r.prj_K[5] * xp.z) * iz;
+    if (!(p.pu >= 0.0 && p.pu < (double)r.Wp && p.pv >= 0.0 && p.pv < (double)r.Hp)) return false;
+    const D3 tow = d3(r.prj_o[0], r.prj_o[1], r.prj_o[2]) - s.x;
+    p.dist = sqrt(dot(tow, tow));
+    p.wp = tow * (1.0 / p.dist);
+    const double cp = dot(s.n, p.wp);
+    if (!(cp > 0.0)) return false;
+    const double ca = xp.z / sqrt(dot(xp, xp));
+    p.geom = cp / (ca * ca * ca * p.dist * p.dist);
+    p.pb = bilinear(p.pu - 0.5, p.pv - 0.5, r.Wp, r.Hp);
+    return true;
+}
+
+__device__ __forceinline__ U4 vertex_rng(const ReqDesc& r, uint32_t g, uint32_t block) {
+    const uint32_t pixel = g / (uint32_t)r.spp, s = g - pixel * (uint32_t)r.spp;
+    return philox4x32_10(pixel, s + r.sample_offset, block, 0u, r.seed_lo, r.seed_hi);
+}
+
+}  // namespace dpcs

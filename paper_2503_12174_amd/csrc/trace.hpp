@@ -1,0 +1,217 @@
+// trace.hpp -- ray queries on the device BVH.
+//
+// BVH2 node (64 B, 4 x float4): both children's boxes inline so one node fetch
+// tests two boxes.
+//   n0 = (lo0.x, lo0.y, lo0.z, hi0.x)  n1 = (hi0.y, hi0.z, lo1.x, lo1.y)
+//   n2 = (lo1.z, hi1.x, hi1.y, hi1.z)  n3 = (child0, child1, -, -) as int bits
+// child >= 0: internal node index; child < 0: leaf ~child (one triangle, leaf order).
+// Triangle record (48 B): v0 (w = original triangle index bits), v1, v2.
+//
+// Closest hit: smallest t in (tmin, tmax); equal t -> smaller original triangle
+// index, so the result equals a brute-force scan in the same arithmetic.  Box tests
+// are widened by a few ulps so no triangle a brute-force scan would accept is culled.
+#pragma once
+
+#include "common.hpp"
+
+namespace dpcs {
+
+// watertight ray / triangle test (Woop, Benthin, Wald, JCGT 2013)
+struct WtRay {
+    V3 o;
+    int kx, ky, kz;
+    float Sx, Sy, Sz;
+};
+
+__device__ __forceinline__ WtRay wt_setup(V3 o, V3 d) {
+    WtRay r;
+    r.o = o;
+    const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    const float dz = comp(d, kz);
+    if (dz < 0.0f) {
+        const int tmp = kx;
+        kx = ky;
+        ky = tmp;
+    }
+    r.kx = kx;
+    r.ky = ky;
+    r.kz = kz;
+    r.Sx = comp(d, kx) / dz;
+    r.Sy = comp(d, ky) / dz;
+    r.Sz = 1.0f / dz;
+    return r;
+}
+
+// returns false on a miss; on a hit t and the barycentrics (b1 of v1, b2 of v2)
+__device__ __forceinline__ bool wt_intersect(const WtRay& r, V3 v0, V3 v1, V3 v2, float& t, float& b1, float& b2) {
+    const V3 A = v0 - r.o, B = v1 - r.o, C = v2 - r.o;
+    const float Akz = comp(A, r.kz), Bkz = comp(B, r.kz), Ckz = comp(C, r.kz);
+    const float Ax = comp(A, r.kx) - r.Sx * Akz, Ay = comp(A, r.ky) - r.Sy * Akz;
+    const float Bx = comp(B, r.kx) - r.Sx * Bkz, By = comp(B, r.ky) - r.Sy * Bkz;
+    const float Cx = comp(C, r.kx) - r.Sx * Ckz, Cy = comp(C, r.ky) - r.Sy * Ckz;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {  // edge case: decide in double
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    const float det = U + V + W;
+    if (det == 0.0f) return false;
+    const float T = U * (r.Sz * Akz) + V * (r.Sz * Bkz) + W * (r.Sz * Ckz);
+    const float inv = 1.0f / det;
+    t = T * inv;
+    b1 = V * inv;
+    b2 = W * inv;
+    return true;
+}
+
+struct Hit {
+    float t;
+    int leaf;   // leaf-order triangle index, -1 on a miss
+    int prim;   // original triangle index
+    float b1, b2;
+};
+
+struct BoxRay {
+    V3 o, inv;
+};
+__device__ __forceinline__ BoxRay box_setup(V3 o, V3 d) { return BoxRay{o, v3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z)}; }
+
+// conservative entry distance of the ray into [lo, hi]; returns +inf when missed
+__device__ __forceinline__ float box_enter(const BoxRay& r, float lx, float ly, float lz, float hx, float hy, float hz,
+                                           float tmin, float tmax) {
+    const float tx0 = (lx - r.o.x) * r.inv.x, tx1 = (hx - r.o.x) * r.inv.x;
+    const float ty0 = (ly - r.o.y) * r.inv.y, ty1 = (hy - r.o.y) * r.inv.y;
+    const float tz0 = (lz - r.o.z) * r.inv.z, tz1 = (hz - r.o.z) * r.inv.z;
+    float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fminf(tz0, tz1));
+    float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
+    // widen by 4e-6 relative (a few ulps of every operation above)
+    tn = tn - fabsf(tn) * 4e-6f;
+    tf = tf + fabsf(tf) * 4e-6f;
+    tn = fmaxf(tn, tmin);
+    tf = fminf(tf, tmax);
+    return tn <= tf ? tn : __builtin_inff();
+}
+
+__device__ __forceinline__ void load_tri(const float4* __restrict__ tris, int leaf, V3& v0, V3& v1, V3& v2, int& prim) {
+    const float4 a = tris[3 * leaf], b = tris[3 * leaf + 1], c = tris[3 * leaf + 2];
+    v0 = xyz(a);
+    v1 = xyz(b);
+    v2 = xyz(c);
+    prim = __float_as_int(a.w);
+}
+
+// Stack of internal node indices lives in LDS: entry k of thread tid at stack[k * TBK + tid],
+// TBK = threads per workgroup (consecutive lanes hit consecutive banks).
+template <bool ANY, int STACK, int TBK>
+__device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const float4* __restrict__ tris, V3 o, V3 d,
+                                         float tmin, float tmax, int skip, Hit& h, int* stack) {
+    const BoxRay br = box_setup(o, d);
+    const WtRay wr = wt_setup(o, d);
+    float best_t = tmax;
+    int best_prim = 0x7fffffff, best_leaf = -1;
+    float bb1 = 0.f, bb2 = 0.f;
+    int sp = 0;
+    int node = 0;
+    while (true) {
+        const float4 n0 = nodes[4 * node], n1 = nodes[4 * node + 1], n2 = nodes[4 * node + 2];
+        const int4 n3 = *reinterpret_cast<const int4*>(&nodes[4 * node + 3]);
+        float t0 = box_enter(br, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tmin, best_t);
+        float t1 = box_enter(br, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tmin, best_t);
+        const int c0 = n3.x, c1 = n3.y;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int c = k == 0 ? c0 : c1;
+            const float tc = k == 0 ? t0 : t1;
+            if (c < 0 && tc < __builtin_inff()) {
+                const int leaf = ~c;
+                V3 v0, v1, v2;
+                int prim;
+                load_tri(tris, leaf, v0, v1, v2, prim);
+                float t, b1, b2;
+                if (prim != skip && wt_intersect(wr, v0, v1, v2, t, b1, b2) && t > tmin &&
+                    (t < best_t || (t == best_t && best_leaf >= 0 && prim < best_prim))) {
+                    best_t = t;
+                    best_prim = prim;
+                    best_leaf = leaf;
+                    bb1 = b1;
+                    bb2 = b2;
+                    if (ANY) {
+                        h.t = t;
+                        h.leaf = leaf;
+                        h.prim = prim;
+                        h.b1 = b1;
+                        h.b2 = b2;
+                        return true;
+                    }
+                }
+            }
+        }
+        const bool h0 = c0 >= 0 && t0 <= best_t;
+        const bool h1 = c1 >= 0 && t1 <= best_t;
+        if (h0 && h1) {
+            const bool first0 = t0 <= t1;
+            // the host only launches on trees with depth < STACK, so this never drops
+            if (sp < STACK) {
+                stack[sp * TBK] = first0 ? c1 : c0;
+                ++sp;
+            }
+            node = first0 ? c0 : c1;
+        } else if (h0) {
+            node = c0;
+        } else if (h1) {
+            node = c1;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = stack[sp * TBK];
+        }
+    }
+    h.t = best_t;
+    h.leaf = best_leaf;
+    h.prim = best_leaf >= 0 ? best_prim : -1;
+    h.b1 = bb1;
+    h.b2 = bb2;
+    return best_leaf >= 0;
+}
+
+// reference: every triangle in original order, same arithmetic and tie rule
+template <bool ANY>
+__device__ __forceinline__ bool brute_force(const float4* __restrict__ tris, const int* __restrict__ leaf_of_prim,
+                                            int ntri, V3 o, V3 d, float tmin, float tmax, int skip, Hit& h) {
+    const WtRay wr = wt_setup(o, d);
+    float best_t = tmax;
+    int best = -1, best_leaf = -1;
+    float bb1 = 0.f, bb2 = 0.f;
+    for (int p = 0; p < ntri; ++p) {
+        if (p == skip) continue;
+        const int leaf = leaf_of_prim[p];
+        V3 v0, v1, v2;
+        int prim;
+        load_tri(tris, leaf, v0, v1, v2, prim);
+        float t, b1, b2;
+        // triangles are visited in increasing original index, so on equal t the first wins
+        if (wt_intersect(wr, v0, v1, v2, t, b1, b2) && t > tmin && t < best_t) {
+            best_t = t;
+            best = prim;
+            best_leaf = leaf;
+            bb1 = b1;
+            bb2 = b2;
+            if (ANY) break;
+        }
+    }
+    h.t = best_t;
+    h.leaf = best_leaf;
+    h.prim = best;
+    h.b1 = bb1;
+    h.b2 = bb2;
+    return best >= 0;
+}
+
+}  // namespace dpcs

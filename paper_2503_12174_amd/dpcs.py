@@ -1,0 +1,254 @@
+"""ctypes binding of libdpcs.so (include/dpcs.h): argument marshalling only.
+
+Every computation happens in the HIP library; this module converts torch tensors
+to device pointers, mirrors the C structs and raises on non-OK statuses.  Loading
+fails loudly when the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpcs.so")
+
+OK, E_INVALID, E_OOM, E_DEVICE, E_UNSUPPORTED, E_BUSY, E_REJECTED = 0, -1, -2, -3, -4, -5, -6
+STATUS = {0: "OK", -1: "INVALID", -2: "OOM", -3: "DEVICE", -4: "UNSUPPORTED", -5: "BUSY", -6: "REJECTED"}
+LAMBERT, GGX = 0, 1
+NUM_SCALARS = 18
+
+
+class DpcsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"dpcs status {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("positions", C.c_void_p), ("num_vertices", C.c_int32), ("triangles", C.c_void_p),
+                ("num_triangles", C.c_int32), ("corner_uvs", C.c_void_p), ("emission", C.c_void_p)]
+
+
+class SceneInfo(C.Structure):
+    _fields_ = [("num_triangles", C.c_int32), ("num_nodes", C.c_int32), ("max_depth", C.c_int32),
+                ("reserved", C.c_int32), ("device_bytes", C.c_int64), ("build_ms", C.c_double),
+                ("bbox_lo", C.c_float * 3), ("bbox_hi", C.c_float * 3), ("tmin", C.c_float)]
+
+
+class Pinhole(C.Structure):
+    _fields_ = [("K", C.c_double * 9), ("R", C.c_double * 9), ("t", C.c_double * 3),
+                ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class RenderParams(C.Structure):
+    _fields_ = [("camera", Pinhole), ("projector", Pinhole), ("brdf", C.c_int32),
+                ("albedo", C.c_void_p), ("roughness", C.c_void_p), ("specular", C.c_void_p),
+                ("tex_w", C.c_int32), ("tex_h", C.c_int32),
+                ("prf_gamma", C.c_float * 3), ("prf_gain", C.c_float), ("prf_mix", C.c_float * 9),
+                ("crf_gamma", C.c_float * 3), ("crf_gain", C.c_float), ("white_balance", C.c_float * 3),
+                ("device_scalars", C.c_void_p), ("env_radiance", C.c_float * 3),
+                ("clip_enable", C.c_int32), ("clip_k", C.c_float), ("spp", C.c_int32), ("max_depth", C.c_int32),
+                ("seed", C.c_uint64), ("sample_offset", C.c_uint32)]
+
+
+class RenderAux(C.Structure):
+    _fields_ = [("linear", C.c_void_p), ("sample_radiance", C.c_void_p), ("hit_prims", C.c_void_p)]
+
+
+class Grads(C.Structure):
+    _fields_ = [("d_proj_image", C.c_void_p), ("d_albedo", C.c_void_p), ("d_roughness", C.c_void_p),
+                ("d_specular", C.c_void_p), ("d_scalars", C.c_void_p)]
+
+
+class Request(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("params", RenderParams), ("proj_image", C.c_void_p),
+                ("out_image", C.c_void_p), ("grad_image", C.c_void_p), ("target", C.c_void_p),
+                ("grads", C.POINTER(Grads)), ("request_id", C.c_uint64)]
+
+
+# every symbol the header declares (a test checks the library exports all of them)
+SYMBOLS = ["dpcs_context_create", "dpcs_context_destroy", "dpcs_last_error", "dpcs_context_synchronize",
+           "dpcs_context_set_capacity", "dpcs_scene_create", "dpcs_scene_get_info", "dpcs_scene_destroy",
+           "dpcs_render", "dpcs_render_vjp", "dpcs_debug_intersect", "dpcs_debug_philox", "dpcs_server_create",
+           "dpcs_server_submit", "dpcs_server_poll", "dpcs_server_stats", "dpcs_server_destroy"]
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2503_12174_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P, S, I32, I64 = C.c_void_p, C.c_int32, C.c_int32, C.c_int64
+        sig = {
+            "dpcs_context_create": ([I32, P, C.c_size_t, C.POINTER(P)], S),
+            "dpcs_context_destroy": ([P], None),
+            "dpcs_last_error": ([P], C.c_char_p),
+            "dpcs_context_synchronize": ([P], S),
+            "dpcs_context_set_capacity": ([P, I64], S),
+            "dpcs_scene_create": ([P, C.POINTER(MeshDesc), C.POINTER(P)], S),
+            "dpcs_scene_get_info": ([P, C.POINTER(SceneInfo)], S),
+            "dpcs_scene_destroy": ([P], S),
+            "dpcs_render": ([P, P, C.POINTER(RenderParams), P, P, C.POINTER(RenderAux)], S),
+            "dpcs_render_vjp": ([P, P, C.POINTER(RenderParams), P, P, P, C.POINTER(Grads)], S),
+            "dpcs_debug_intersect": ([P, P, P, I64, I32, P, P, P, P], S),
+            "dpcs_debug_philox": ([P, C.c_uint64, P, I64, P], S),
+            "dpcs_server_create": ([P, C.c_size_t, I32, C.POINTER(P)], S),
+            "dpcs_server_submit": ([P, C.POINTER(Request)], S),
+            "dpcs_server_poll": ([P, P, P, P, I32], I32),
+            "dpcs_server_stats": ([P, P], S),
+            "dpcs_server_destroy": ([P], S),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    """Device (or host) pointer of a contiguous tensor / array; None stays NULL."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        if not t.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return t.data_ptr()
+    return t.ctypes.data
+
+
+class Context:
+    """dpcs_context on one device and the torch stream current at creation."""
+
+    def __init__(self, device: int = 0, stream=None, scratch_limit: int = 0, capacity: int | None = None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        st = lib().dpcs_context_create(device, C.c_void_p(stream.cuda_stream), scratch_limit, C.byref(h))
+        if st != OK:
+            raise DpcsError(st, "dpcs_context_create")
+        self.h = h
+        if capacity is not None:
+            self.check(lib().dpcs_context_set_capacity(self.h, int(capacity)))
+
+    def check(self, st):
+        if st != OK:
+            raise DpcsError(st, lib().dpcs_last_error(self.h).decode())
+        return st
+
+    def synchronize(self):
+        return self.check(lib().dpcs_context_synchronize(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dpcs_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Scene:
+    """Resident mesh + BVH (dpcs_scene) built from a synth.Mesh-like object."""
+
+    def __init__(self, ctx: Context, mesh):
+        self.ctx = ctx
+        V = np.ascontiguousarray(mesh.vertices, np.float32)
+        F = np.ascontiguousarray(mesh.triangles, np.int32)
+        UV = np.ascontiguousarray(mesh.corner_uvs, np.float32)
+        E = None if mesh.emission is None else np.ascontiguousarray(mesh.emission, np.float32)
+        d = MeshDesc(V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], UV.ctypes.data,
+                     None if E is None else E.ctypes.data)
+        h = C.c_void_p()
+        ctx.check(lib().dpcs_scene_create(ctx.h, C.byref(d), C.byref(h)))
+        self.h = h
+
+    def info(self) -> SceneInfo:
+        i = SceneInfo()
+        self.ctx.check(lib().dpcs_scene_get_info(self.h, C.byref(i)))
+        return i
+
+    def close(self):
+        if getattr(self, "h", None):
+            st = lib().dpcs_scene_destroy(self.h)
+            if st == OK:
+                self.h = None
+            return st
+        return OK
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pinhole(p) -> Pinhole:
+    ph = Pinhole()
+    ph.K[:] = [float(x) for x in np.ravel(p.K)]
+    ph.R[:] = [float(x) for x in np.ravel(p.R)]
+    ph.t[:] = [float(x) for x in np.ravel(p.t)]
+    ph.width, ph.height = int(p.width), int(p.height)
+    return ph
+
+
+def params_from(w, albedo, roughness=None, specular=None, device_scalars=None, **over) -> RenderParams:
+    """RenderParams from a synth.Workload-like object and device tensors for the maps."""
+    g = lambda k: over[k] if k in over else getattr(w, k)
+    p = RenderParams()
+    p.camera = pinhole(g("camera"))
+    p.projector = pinhole(g("projector"))
+    p.brdf = int(g("brdf"))
+    p.albedo, p.roughness, p.specular = _ptr(albedo), _ptr(roughness), _ptr(specular)
+    p.tex_h, p.tex_w = int(albedo.shape[0]), int(albedo.shape[1])
+    p.prf_gamma[:] = [float(x) for x in g("prf_gamma")]
+    p.prf_gain = float(g("prf_gain"))
+    p.prf_mix[:] = [float(x) for x in np.ravel(g("prf_mix"))]
+    p.crf_gamma[:] = [float(x) for x in g("crf_gamma")]
+    p.crf_gain = float(g("crf_gain"))
+    p.white_balance[:] = [float(x) for x in g("white_balance")]
+    p.device_scalars = _ptr(device_scalars)
+    p.env_radiance[:] = [float(x) for x in g("env")]
+    p.clip_enable = int(bool(g("clip")))
+    p.clip_k = float(g("clip_k"))
+    p.spp = int(g("spp"))
+    p.max_depth = int(g("max_depth"))
+    p.seed = int(g("seed"))
+    p.sample_offset = int(g("sample_offset"))
+    return p
+
+
+# ------------------------------------------------------------------ entry points
+
+def dpcs_render(ctx: Context, scene: Scene, params: RenderParams, proj_image, out_image, linear=None,
+                sample_radiance=None, hit_prims=None):
+    aux = RenderAux(_ptr(linear), _ptr(sample_radiance), _ptr(hit_prims))
+    return ctx.check(lib().dpcs_render(ctx.h, scene.h, C.byref(params), _ptr(proj_image), _ptr(out_image),
+                                       C.byref(aux)))
+
+
+def dpcs_render_vjp(ctx: Context, scene: Scene, params: RenderParams, proj_image, grad_image, sample_radiance=None,
+                    d_proj_image=None, d_albedo=None, d_roughness=None, d_specular=None, d_scalars=None):
+    g = Grads(_ptr(d_proj_image), _ptr(d_albedo), _ptr(d_roughness), _ptr(d_specular), _ptr(d_scalars))
+    return ctx.check(lib().dpcs_render_vjp(ctx.h, scene.h, C.byref(params), _ptr(proj_image), _ptr(grad_image),
+                                           _ptr(sample_radiance), C.byref(g)))
+
+
+def dpcs_debug_intersect(ctx: Context, scene: Scene, rays, use_bvh: bool, prim, t=None, b1=None, b2=None):
+    return ctx.check(lib().dpcs_debug_intersect(ctx.h, scene.h, _ptr(rays), int(rays.shape[0]), int(bool(use_bvh)),
+                                                _ptr(prim), _ptr(t), _ptr(b1), _ptr(b2)))
+
+
+def dpcs_debug_philox(ctx: Context, seed: int, ctr, out):
+    return ctx.check(lib().dpcs_debug_philox(ctx.h, int(seed), _ptr(ctr), int(ctr.shape[0]), _ptr(out)))

@@ -1,0 +1,189 @@
+"""GPU forward path vs the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2503_12174_amd import synth
+
+from . import scenes
+from .gpu_util import GpuRun, compare_forward, ctx, dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle_built():
+    O.build(force=False)
+
+
+def test_philox_bit_exact_against_oracle():
+    import torch
+    from paper_2503_12174_amd import dpcs
+    rng = np.random.default_rng(0)
+    c = rng.integers(0, 2**32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    c[:3] = [[0, 0, 0, 0], [0xFFFFFFFF] * 4, [7, 1, 2, 0]]
+    for seed in (0, 0xFFFFFFFFFFFFFFFF, 0x0123456789ABCDEF):
+        out = torch.zeros((4096, 4), dtype=torch.int32, device="cuda")
+        dpcs.dpcs_debug_philox(ctx(), seed, dev(c.view(np.int32)), out)
+        ctx().synchronize()
+        got = out.cpu().numpy().view(np.uint32)
+        np.testing.assert_array_equal(got, O.philox(seed, c))
+
+
+def _rays_for(mesh, n, rng):
+    V = mesh.vertices.astype(np.float64)
+    lo, hi = V.min(0), V.max(0)
+    c = (lo + hi) / 2
+    ext = np.linalg.norm(hi - lo)
+    o = c + rng.normal(size=(n, 3)) * ext
+    tgt = V[mesh.triangles[rng.integers(0, mesh.num_triangles, n)]].mean(1) + rng.normal(size=(n, 3)) * 0.01 * ext
+    d = tgt - o
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rays = np.zeros((n, 8), np.float32)
+    rays[:, :3], rays[:, 3:6], rays[:, 6] = o, d, np.inf
+    rays[:, 7] = -1
+    # some rays leave a triangle (skip it) with a finite tmax
+    k = n // 4
+    rays[:k, 7] = rng.integers(0, mesh.num_triangles, k)
+    rays[:k, 6] = rng.uniform(0.1, 2.0, k) * ext
+    return rays
+
+
+MESHES = {
+    "quad+cube": lambda: synth.quad_and_cube(),
+    "single": lambda: synth.quad_mesh([(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0)]),
+    "sphere": lambda: synth.icosphere(2, 0.5),
+    "corner": lambda: synth.folded_corner(12, 1, 2),
+    "closed box": lambda: synth.closed_box(0.5),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_bvh_traversal_equals_brute_force(name):
+    """Closest hit through the BVH == brute force over all triangles, same FP32 arithmetic."""
+    import torch
+    from paper_2503_12174_amd import dpcs
+    mesh = MESHES[name]()
+    if name == "single":
+        mesh = synth.Mesh(mesh.vertices, mesh.triangles[:1], mesh.corner_uvs[:1])
+    sc = dpcs.Scene(ctx(), mesh)
+    rng = np.random.default_rng(1)
+    rays = _rays_for(mesh, 20000, rng)
+    r = dev(rays)
+    outs = []
+    for use_bvh in (True, False):
+        prim = torch.zeros(len(rays), dtype=torch.int32, device="cuda")
+        t = torch.zeros(len(rays), dtype=torch.float32, device="cuda")
+        b1 = torch.zeros_like(t)
+        b2 = torch.zeros_like(t)
+        dpcs.dpcs_debug_intersect(ctx(), sc, r, use_bvh, prim, t, b1, b2)
+        ctx().synchronize()
+        outs.append([x.cpu().numpy() for x in (prim, t, b1, b2)])
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
+    assert (outs[0][0] >= 0).mean() > 0.3
+    # and the brute force agrees with the FP64 oracle on rays far from every decision boundary
+    w = synth.config1()
+    osc = O.Scene(w, mesh=mesh, tmin=float(sc.info().tmin))
+    prim_o, t_o, _, _, m = O.intersect(osc, rays.astype(np.float64), with_margin=True)
+    clean = m >= 1
+    # the cube's bottom face is coplanar with the floor: rays from below tie there
+    assert clean.mean() > (0.8 if name == "quad+cube" else 0.97)
+    np.testing.assert_array_equal(outs[1][0][clean], prim_o[clean])
+    hit = clean & (prim_o >= 0)
+    # FP32 t carries ~1 ulp of the ray origin's magnitude: relative and absolute parts
+    diag = float(np.linalg.norm(mesh.vertices.max(0) - mesh.vertices.min(0)))
+    np.testing.assert_allclose(outs[1][1][hit], t_o[hit], rtol=1e-5, atol=1e-6 * diag)
+
+
+def test_forward_parity_config1_full_image():
+    w = synth.config1()
+    g = GpuRun(w).render()
+    ref = O.render(O.Scene(w))
+    frac, rel, relp = compare_forward(g, ref)
+    print(f"clean {frac:.5f} max rel sample {rel:.2e} pixel {relp:.2e}")
+
+
+def test_forward_parity_ggx_env_mix_clip():
+    """GGX maps, non-identity colour mixing, environment light on, clipping active."""
+    w = scenes.c3_ggx(spp=8, seed=9, max_depth=4)
+    w.env = np.array([0.05, 0.08, 0.03])
+    w.clip = True
+    w.clip_k = 0.6
+    g = GpuRun(w).render()
+    ref = O.render(O.Scene(w))
+    frac, rel, relp = compare_forward(g, ref)
+    assert ((ref["L"] > 0.6 / w.white_balance.min()).any())
+    print(f"clean {frac:.5f} max rel sample {rel:.2e} pixel {relp:.2e}")
+
+
+@pytest.mark.parametrize("depth", [1, 3, 6])
+def test_white_furnace_on_gpu(depth):
+    rho = 0.7
+    w = scenes.furnace_workload(rho=rho, max_depth=depth, res=32, spp=8)
+    g = GpuRun(w).render()
+    r = float(np.float32(rho))
+    want = sum(r ** k for k in range(depth))
+    np.testing.assert_allclose(g["L"], want, rtol=2e-6)
+
+
+def test_chunked_waves_are_bit_identical():
+    """Capacity (paths per launch wave) changes the launch schedule, never the result."""
+    w = scenes.c3_ggx(spp=4, seed=3, max_depth=3)
+    w.env = np.full(3, 0.02)
+    full = GpuRun(w).render()
+    small = GpuRun(w, capacity=4 * 37).render()    # 37 pixels per wave, ragged last wave
+    GpuRun(w, capacity=1 << 22)
+    for k in ("Ic", "Ec", "L", "hits"):
+        np.testing.assert_array_equal(full[k], small[k])
+
+
+def test_ragged_and_tiny_images():
+    for W, H, spp in [(1, 1, 1), (37, 23, 3), (5, 129, 2)]:
+        w = synth.config1(spp=spp)
+        cam = synth.pinhole((0, 0, 0.8), (0, 0, 0), 60.0, W, H, up=(0, 1, 0))
+        w.camera = cam
+        g = GpuRun(w).render()
+        ref = O.render(O.Scene(w))
+        compare_forward(g, ref, min_clean=0.9)
+
+
+def test_single_triangle_scene_and_direct_only():
+    w = scenes.plane_workload(max_depth=1)
+    w.mesh = synth.Mesh(w.mesh.vertices, w.mesh.triangles[:1], w.mesh.corner_uvs[:1])
+    g = GpuRun(w).render()
+    ref = O.render(O.Scene(w))
+    compare_forward(g, ref, min_clean=0.9)
+
+
+def test_forward_config2_sampled_pixels():
+    """Full paper-scale render (50k triangles, 256^2, 64 spp, depth 4) on the GPU,
+    checked on 48 random pixels the oracle computes one by one."""
+    w = synth.config2()
+    g = GpuRun(w).render()
+    rng = np.random.default_rng(77)
+    px = rng.choice(256 * 256, 48, replace=False)
+    ref = O.render(O.Scene(w), pixels=px)
+    frac, rel, relp = compare_forward(g, ref, pixels=px, min_clean=0.97)
+    print(f"clean {frac:.5f} max rel sample {rel:.2e} pixel {relp:.2e}")
+    assert np.isfinite(g["Ic"]).all() and g["Ic"].max() > 0
+
+
+def test_invalid_arguments_are_rejected_before_launch():
+    from paper_2503_12174_amd import dpcs
+    w = synth.config1()
+    run = GpuRun(w)
+    run.params.spp = 0
+    with pytest.raises(dpcs.DpcsError) as e:
+        run.render()
+    assert e.value.status == dpcs.E_INVALID
+    run.params.spp = 4
+    run.params.max_depth = 65
+    with pytest.raises(dpcs.DpcsError):
+        run.render()
+    run.params.max_depth = 3
+    run.params.white_balance[1] = 0.0
+    with pytest.raises(dpcs.DpcsError):
+        run.render()
+    run.params.white_balance[1] = 1.0
+    run.render()   # the context is still usable
