@@ -185,6 +185,29 @@ DPCS_API dpcs_status dpcs_debug_intersect(dpcs_context ctx, dpcs_scene scene, co
 DPCS_API dpcs_status dpcs_debug_philox(dpcs_context ctx, uint64_t seed, const uint32_t* ctr, int64_t n,
                               uint32_t* out);
 
+/* -------------------------------------------------------------- profiling */
+
+/* Per-stage kernel timing for benchmarks.  mode 0: off.  mode 1: every launch of a
+ * stage is bracketed by HIP events on the context's stream and its work-item count
+ * (queue size) is copied to pinned host memory.  mode 2: as 1, and the traversal
+ * kernels also count visited BVH nodes and tested triangles (slower; use it to measure
+ * the traversal byte model, not to time).  Enabling or disabling clears the record. */
+enum {
+    DPCS_STAGE_RAYGEN = 0, DPCS_STAGE_TRACE = 1, DPCS_STAGE_SHADE = 2, DPCS_STAGE_SHADOW = 3,
+    DPCS_STAGE_FINALIZE = 4, DPCS_STAGE_ADJ_PIXEL = 5, DPCS_STAGE_ADJ_SHADE = 6, DPCS_STAGE_ADJ_SHADOW = 7,
+    DPCS_STAGE_OTHER = 8, DPCS_NUM_STAGES = 9
+};
+typedef struct {
+    int64_t launches[DPCS_NUM_STAGES];
+    double ms[DPCS_NUM_STAGES];        /* sum of event-measured launch durations */
+    int64_t items[DPCS_NUM_STAGES];    /* rays / paths / pixels processed */
+    int64_t nodes[DPCS_NUM_STAGES];    /* mode 2: BVH nodes visited (TRACE, SHADOW, ADJ_SHADOW) */
+    int64_t tris[DPCS_NUM_STAGES];     /* mode 2: triangles tested */
+} dpcs_profile;
+DPCS_API dpcs_status dpcs_context_set_profiling(dpcs_context ctx, int32_t mode);
+/* Synchronises the stream, returns the totals since profiling was enabled and clears them. */
+DPCS_API dpcs_status dpcs_context_get_profile(dpcs_context ctx, dpcs_profile* out);
+
 /* ----------------------------------------------------------------- server */
 
 /* Continuous-batching request loop on ctx's device: requests are admitted while the

@@ -51,6 +51,7 @@ struct Queues {
     float4* L;         // per batch sample radiance (rgb, -)
     uint32_t* cnt;     // [0], [1] path queue sizes, [2], [3] shadow queue sizes
     int64_t cap;       // path capacity
+    unsigned long long* stats;   // null, or [0] nodes visited, [1] triangles tested (profiling)
 };
 
 // adjoint additions (see adjoint.hip)

@@ -85,10 +85,15 @@ __global__ void __launch_bounds__(TB) k_trace(Queues q, int cur, ReqDesc uni, co
         const PathD d = q.pd[cur][i];
         const ReqDesc& r = sel<UNI>(uni, table, o.slot);
         Hit h;
+        Visits vis;
         traverse<false, STACK, TB>(r.nodes, r.tris, v3((float)o.x, (float)o.y, (float)o.z),
                                    v3((float)d.x, (float)d.y, (float)d.z), r.tmin, __builtin_inff(), o.skip, h,
-                                   stack + threadIdx.x);
+                                   stack + threadIdx.x, vis);
         q.hit[i] = h.leaf;
+        if (q.stats) {
+            atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
+            atomicAdd(&q.stats[1], (unsigned long long)vis.tris);
+        }
     }
 }
 
@@ -207,8 +212,13 @@ __global__ void __launch_bounds__(TB) k_shadow(Queues q, int which, ReqDesc uni,
         const float4 o = q.so[which][i], d = q.sd[which][i];
         const ReqDesc& r = sel<UNI>(uni, table, __float_as_int(o.w));
         Hit h;
+        Visits vis;
         const bool occ = traverse<true, STACK, TB>(r.nodes, r.tris, xyz(o), xyz(d), r.tmin, q.st[which][i],
-                                                   __float_as_int(d.w), h, stack + threadIdx.x);
+                                                   __float_as_int(d.w), h, stack + threadIdx.x, vis);
+        if (q.stats) {
+            atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
+            atomicAdd(&q.stats[1], (unsigned long long)vis.tris);
+        }
         if (!occ) {
             const float4 c = q.sc[which][i];
             const uint32_t sid = __float_as_uint(c.w);
@@ -261,8 +271,9 @@ __global__ void __launch_bounds__(TB) k_debug_intersect(const float4* __restrict
     const float* ry = rays + 8 * i;
     const V3 o = v3(ry[0], ry[1], ry[2]), d = v3(ry[3], ry[4], ry[5]);
     Hit h;
+    Visits vis;
     if (use_bvh)
-        traverse<false, STACK, TB>(nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, stack + threadIdx.x);
+        traverse<false, STACK, TB>(nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, stack + threadIdx.x, vis);
     else
         brute_force<false>(tris, leaf_of_prim, nt, o, d, tmin, ry[6], (int)ry[7], h);
     prim[i] = h.prim;

@@ -81,6 +81,7 @@ bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpc
     q.L = (float4*)take(16 * c);
     q.cnt = (uint32_t*)take(16);
     q.cap = cap;
+    q.stats = nullptr;
     return true;
 }
 
@@ -201,6 +202,39 @@ bool fill_desc(dpcs_context, ReqDesc& r, const dpcs_render_params* p, dpcs_scene
 
 int stack_for(dpcs_scene sc) { return sc->depth <= 32 ? 32 : 64; }
 
+static hipEvent_t prof_event(dpcs_context ctx) {
+    if (ctx->ev_used == ctx->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ctx->ev_pool.push_back(e);
+    }
+    return ctx->ev_pool[ctx->ev_used++];
+}
+
+int prof_begin(dpcs_context ctx, int stage) {
+    if (!ctx->prof_mode) return -1;
+    hipEvent_t a = prof_event(ctx), b = prof_event(ctx);
+    if (!a || !b) return -1;
+    hipEventRecord(a, ctx->stream);
+    ctx->prof.push_back({stage, a, b, -1, 0});
+    return (int)ctx->prof.size() - 1;
+}
+
+void prof_end(dpcs_context ctx, int rec, const uint32_t* dev_count, int64_t host_count) {
+    if (rec < 0) return;
+    auto& r = ctx->prof[rec];
+    hipEventRecord(r.b, ctx->stream);
+    r.host_count = host_count;
+    if (dev_count && ctx->pinned && ctx->pinned_used < ctx->pinned_cap) {
+        r.slot = ctx->pinned_used++;
+        hipMemcpyAsync(ctx->pinned + r.slot, dev_count, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream);
+    }
+}
+
+unsigned long long* prof_stats(dpcs_context ctx, int stage) {
+    return ctx->prof_mode >= 2 && ctx->dstats ? ctx->dstats + 2 * stage : nullptr;
+}
+
 }  // namespace dpcs
 
 // ====================================================================== context
@@ -229,6 +263,9 @@ extern "C" void dpcs_context_destroy(dpcs_context ctx) {
     hipSetDevice(ctx->device);
     hipStreamSynchronize(ctx->stream);
     for (auto& kv : ctx->pool) hipFree(kv.second.first);
+    for (auto e : ctx->ev_pool) hipEventDestroy(e);
+    if (ctx->pinned) hipHostFree(ctx->pinned);
+    if (ctx->dstats) hipFree(ctx->dstats);
     delete ctx;
 }
 
@@ -527,27 +564,42 @@ bool prepare_request(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, 
 }
 
 // Forward waves over pixels [p0, p1) of one request, whole pixels per wave.
-bool forward_waves(dpcs_context ctx, const Queues& q, ReqDesc r, uint32_t p0, uint32_t p1) {
+bool forward_waves(dpcs_context ctx, const Queues& q0, ReqDesc r, uint32_t p0, uint32_t p1) {
     Launch l{ctx->stream, ctx->grid_cap};
-    const int64_t ppw = std::max<int64_t>(1, q.cap / r.spp);   // pixels per wave
+    const int64_t ppw = std::max<int64_t>(1, q0.cap / r.spp);   // pixels per wave
     const int stack = r.stack_hint;
+    Queues q = q0;
     for (int64_t a = p0; a < p1; a += ppw) {
         const uint32_t b = (uint32_t)std::min<int64_t>(p1, a + ppw);
         const uint32_t n = (b - (uint32_t)a) * (uint32_t)r.spp;
         r.g_base = (uint32_t)a * (uint32_t)r.spp;
         r.sid_base = 0;
         launch_set_count(l, q.cnt, 0, n, 1, 4);
+        int pr = prof_begin(ctx, DPCS_STAGE_RAYGEN);
         launch_raygen(l, q, r, nullptr, 0, r.g_base, n, false, nullptr);
+        prof_end(ctx, pr, nullptr, n);
         int cur = 0;
         for (int d = 0; d < r.max_depth; ++d) {
             launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);   // next path queue and shadow queues empty
+            q.stats = prof_stats(ctx, DPCS_STAGE_TRACE);
+            pr = prof_begin(ctx, DPCS_STAGE_TRACE);
             launch_trace(l, q, cur, r, nullptr, n, stack);
+            prof_end(ctx, pr, q.cnt + cur, 0);
+            pr = prof_begin(ctx, DPCS_STAGE_SHADE);
             launch_shade(l, q, cur, d, r, nullptr, n);
-            launch_shadow(l, q, 0, r, nullptr, n, stack);
-            if (r.env_on) launch_shadow(l, q, 1, r, nullptr, n, stack);
+            prof_end(ctx, pr, q.cnt + cur, 0);
+            q.stats = prof_stats(ctx, DPCS_STAGE_SHADOW);
+            for (int w = 0; w < (r.env_on ? 2 : 1); ++w) {
+                pr = prof_begin(ctx, DPCS_STAGE_SHADOW);
+                launch_shadow(l, q, w, r, nullptr, n, stack);
+                prof_end(ctx, pr, q.cnt + 2 + w, 0);
+            }
+            q.stats = nullptr;
             cur ^= 1;
         }
+        pr = prof_begin(ctx, DPCS_STAGE_FINALIZE);
         launch_finalize(l, q, r, nullptr, 0, (uint32_t)a, b);
+        prof_end(ctx, pr, nullptr, b - (uint32_t)a);
     }
     return hip_ok(ctx, hipGetLastError(), "kernel launch");
 }
@@ -608,4 +660,60 @@ extern "C" dpcs_status dpcs_debug_philox(dpcs_context ctx, uint64_t seed, const 
     Launch l{ctx->stream, ctx->grid_cap};
     launch_debug_philox(l, seed, ctr, n, out);
     return hip_ok(ctx, hipGetLastError(), "debug_philox") ? DPCS_OK : DPCS_E_DEVICE;
+}
+
+// ====================================================================== profiling
+extern "C" dpcs_status dpcs_context_set_profiling(dpcs_context ctx, int32_t mode) {
+    if (!ctx || mode < 0 || mode > 2) return DPCS_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    ctx->prof.clear();
+    ctx->ev_used = 0;
+    ctx->pinned_used = 0;
+    if (mode && !ctx->pinned) {
+        ctx->pinned_cap = 1 << 16;
+        if (hipHostMalloc((void**)&ctx->pinned, sizeof(uint32_t) * ctx->pinned_cap) != hipSuccess) {
+            hipGetLastError();
+            ctx->pinned = nullptr;
+            ctx->pinned_cap = 0;
+        }
+    }
+    if (mode >= 2 && !ctx->dstats) {
+        if (hipMalloc((void**)&ctx->dstats, sizeof(unsigned long long) * 2 * DPCS_NUM_STAGES) != hipSuccess) {
+            hipGetLastError();
+            return fail(ctx, DPCS_E_OOM, "profiling counters");
+        }
+    }
+    if (ctx->dstats) hipMemset(ctx->dstats, 0, sizeof(unsigned long long) * 2 * DPCS_NUM_STAGES);
+    ctx->prof_mode = mode;
+    return DPCS_OK;
+}
+
+extern "C" dpcs_status dpcs_context_get_profile(dpcs_context ctx, dpcs_profile* out) {
+    if (!ctx || !out) return DPCS_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    hipSetDevice(ctx->device);
+    if (!hip_ok(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize")) return DPCS_E_DEVICE;
+    std::memset(out, 0, sizeof *out);
+    for (const auto& r : ctx->prof) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, r.a, r.b);
+        out->launches[r.stage] += 1;
+        out->ms[r.stage] += ms;
+        out->items[r.stage] += r.slot >= 0 ? (int64_t)ctx->pinned[r.slot] : r.host_count;
+    }
+    if (ctx->dstats) {
+        unsigned long long h[2 * DPCS_NUM_STAGES];
+        hipMemcpy(h, ctx->dstats, sizeof h, hipMemcpyDeviceToHost);
+        for (int k = 0; k < DPCS_NUM_STAGES; ++k) {
+            out->nodes[k] = (int64_t)h[2 * k];
+            out->tris[k] = (int64_t)h[2 * k + 1];
+        }
+        hipMemset(ctx->dstats, 0, sizeof h);
+    }
+    ctx->prof.clear();
+    ctx->ev_used = 0;
+    ctx->pinned_used = 0;
+    return DPCS_OK;
 }

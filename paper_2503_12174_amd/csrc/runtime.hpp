@@ -7,6 +7,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/dpcs.h"
 #include "kernels.hpp"
@@ -22,6 +23,20 @@ struct dpcs_context_s {
     std::map<std::string, std::pair<void*, size_t>> pool;
     std::recursive_mutex mu;               // serialises calls from several host threads
     int grid_cap = 4096;
+    // profiling (dpcs_context_set_profiling)
+    struct ProfRec {
+        int stage;
+        hipEvent_t a, b;
+        int slot;            // pinned count slot, -1: host count below
+        int64_t host_count;
+    };
+    int prof_mode = 0;
+    std::vector<ProfRec> prof;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    uint32_t* pinned = nullptr;            // queue-size snapshots
+    int pinned_cap = 0, pinned_used = 0;
+    unsigned long long* dstats = nullptr;  // device [DPCS_NUM_STAGES][2]
 };
 
 struct dpcs_scene_s {
@@ -51,6 +66,11 @@ void* scratch(dpcs_context ctx, const char* name, size_t bytes, dpcs_status* st)
 bool fill_desc(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, dpcs_scene sc, const float* proj_image,
                std::string* why);
 int stack_for(dpcs_scene sc);
+
+// profiling hooks around one stage launch (no-ops when profiling is off)
+int prof_begin(dpcs_context ctx, int stage);
+void prof_end(dpcs_context ctx, int rec, const uint32_t* dev_count, int64_t host_count);
+unsigned long long* prof_stats(dpcs_context ctx, int stage);
 
 // path queues for `cap` paths carved from one scratch buffer (prefix selects the buffer)
 bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpcs_status* st);

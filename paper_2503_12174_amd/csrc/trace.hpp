@@ -109,9 +109,13 @@ __device__ __forceinline__ void load_tri(const float4* __restrict__ tris, int le
 
 // Stack of internal node indices lives in LDS: entry k of thread tid at stack[k * TBK + tid],
 // TBK = threads per workgroup (consecutive lanes hit consecutive banks).
+struct Visits {
+    uint32_t nodes = 0, tris = 0;
+};
+
 template <bool ANY, int STACK, int TBK>
 __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const float4* __restrict__ tris, V3 o, V3 d,
-                                         float tmin, float tmax, int skip, Hit& h, int* stack) {
+                                         float tmin, float tmax, int skip, Hit& h, int* stack, Visits& vis) {
     const BoxRay br = box_setup(o, d);
     const WtRay wr = wt_setup(o, d);
     float best_t = tmax;
@@ -120,6 +124,7 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
     int sp = 0;
     int node = 0;
     while (true) {
+        ++vis.nodes;
         const float4 n0 = nodes[4 * node], n1 = nodes[4 * node + 1], n2 = nodes[4 * node + 2];
         const int4 n3 = *reinterpret_cast<const int4*>(&nodes[4 * node + 3]);
         float t0 = box_enter(br, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tmin, best_t);
@@ -133,6 +138,7 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
                 const int leaf = ~c;
                 V3 v0, v1, v2;
                 int prim;
+                ++vis.tris;
                 load_tri(tris, leaf, v0, v1, v2, prim);
                 float t, b1, b2;
                 if (prim != skip && wt_intersect(wr, v0, v1, v2, t, b1, b2) && t > tmin &&
@@ -153,8 +159,9 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
                 }
             }
         }
-        const bool h0 = c0 >= 0 && t0 <= best_t;
-        const bool h1 = c1 >= 0 && t1 <= best_t;
+        // a missed box reports +inf, which must not pass while best_t is still +inf
+        const bool h0 = c0 >= 0 && t0 < __builtin_inff() && t0 <= best_t;
+        const bool h1 = c1 >= 0 && t1 < __builtin_inff() && t1 <= best_t;
         if (h0 && h1) {
             const bool first0 = t0 <= t1;
             // the host only launches on trees with depth < STACK, so this never drops

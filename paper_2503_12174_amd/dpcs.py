@@ -62,6 +62,20 @@ class Grads(C.Structure):
                 ("d_specular", C.c_void_p), ("d_scalars", C.c_void_p)]
 
 
+NUM_STAGES = 9
+STAGES = ["raygen", "trace", "shade", "shadow", "finalize", "adj_pixel", "adj_shade", "adj_shadow", "other"]
+
+
+class Profile(C.Structure):
+    _fields_ = [("launches", C.c_int64 * NUM_STAGES), ("ms", C.c_double * NUM_STAGES),
+                ("items", C.c_int64 * NUM_STAGES), ("nodes", C.c_int64 * NUM_STAGES),
+                ("tris", C.c_int64 * NUM_STAGES)]
+
+    def as_dict(self):
+        return {name: dict(launches=self.launches[k], ms=self.ms[k], items=self.items[k], nodes=self.nodes[k],
+                           tris=self.tris[k]) for k, name in enumerate(STAGES)}
+
+
 class Request(C.Structure):
     _fields_ = [("scene", C.c_void_p), ("params", RenderParams), ("proj_image", C.c_void_p),
                 ("out_image", C.c_void_p), ("grad_image", C.c_void_p), ("target", C.c_void_p),
@@ -71,7 +85,8 @@ class Request(C.Structure):
 # every symbol the header declares (a test checks the library exports all of them)
 SYMBOLS = ["dpcs_context_create", "dpcs_context_destroy", "dpcs_last_error", "dpcs_context_synchronize",
            "dpcs_context_set_capacity", "dpcs_scene_create", "dpcs_scene_get_info", "dpcs_scene_destroy",
-           "dpcs_render", "dpcs_render_vjp", "dpcs_debug_intersect", "dpcs_debug_philox", "dpcs_server_create",
+           "dpcs_render", "dpcs_render_vjp", "dpcs_debug_intersect", "dpcs_debug_philox",
+           "dpcs_context_set_profiling", "dpcs_context_get_profile", "dpcs_server_create",
            "dpcs_server_submit", "dpcs_server_poll", "dpcs_server_stats", "dpcs_server_destroy"]
 
 _lib = None
@@ -98,6 +113,8 @@ def lib():
             "dpcs_render_vjp": ([P, P, C.POINTER(RenderParams), P, P, P, C.POINTER(Grads)], S),
             "dpcs_debug_intersect": ([P, P, P, I64, I32, P, P, P, P], S),
             "dpcs_debug_philox": ([P, C.c_uint64, P, I64, P], S),
+            "dpcs_context_set_profiling": ([P, I32], S),
+            "dpcs_context_get_profile": ([P, C.POINTER(Profile)], S),
             "dpcs_server_create": ([P, C.c_size_t, I32, C.POINTER(P)], S),
             "dpcs_server_submit": ([P, C.POINTER(Request)], S),
             "dpcs_server_poll": ([P, P, P, P, I32], I32),
@@ -146,6 +163,14 @@ class Context:
 
     def synchronize(self):
         return self.check(lib().dpcs_context_synchronize(self.h))
+
+    def set_profiling(self, mode: int):
+        return self.check(lib().dpcs_context_set_profiling(self.h, int(mode)))
+
+    def profile(self) -> dict:
+        p = Profile()
+        self.check(lib().dpcs_context_get_profile(self.h, C.byref(p)))
+        return p.as_dict()
 
     def close(self):
         if getattr(self, "h", None):
