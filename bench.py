@@ -2,11 +2,11 @@
 
 One step = one pass of the whole path over one batch: forward render of the
 paper-scale scene (50k-triangle displaced folded corner + 3 box occluders, GGX
-512^2 maps, 256x256 camera, 256x256 projector, 64 spp, depth 4) and, once the
-adjoint is available, its vector-Jacobian product with the same samples.
+512^2 maps, 256x256 camera, 256x256 projector, 64 spp, depth 4) and its
+vector-Jacobian product by path replay of the same samples.
 
 Prints ONE JSON line.  Inputs are synthetic and resident in HBM before timing.
-  value          path samples/s of the timed steps
+  value          path samples/s of the timed fwd+VJP steps (fwd_samples_per_s: forward alone)
   roofline       live HIP-event timing of the dominant kernel (closest-hit
                  traversal) against its algorithmic bytes (HBM bound)
   cpu_baseline   the FP64 CPU oracle timed on a bounded pixel sample
@@ -78,24 +78,38 @@ def main():
     params = dpcs.params_from(w, alb, rough, spec)
     H, W = w.camera.height, w.camera.width
     out = torch.zeros((H, W, 3), device="cuda")
+    Ls = torch.zeros((H, W, w.spp, 3), device="cuda")
+    G = torch.as_tensor(np.random.default_rng(7).normal(size=(H, W, 3)).astype(np.float32)).cuda()
+    grads = dict(d_proj_image=torch.zeros_like(proj), d_albedo=torch.zeros_like(alb),
+                 d_roughness=torch.zeros_like(rough), d_specular=torch.zeros_like(spec),
+                 d_scalars=torch.zeros(18, device="cuda"))
     samples = H * W * w.spp
 
-    def step():
+    def fwd():
         dpcs.dpcs_render(ctx, scene, params, proj, out)
 
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        step()
-    ctx.synchronize()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / a.steps
-    fwd_sps = samples / (ms_step * 1e-3)
-    print(f"[bench] forward {ms_step:.3f} ms/step, {fwd_sps:.4e} samples/s", file=sys.stderr, flush=True)
+    def step():   # the whole path: forward (keeping per-sample radiance) + VJP by path replay
+        dpcs.dpcs_render(ctx, scene, params, proj, out, sample_radiance=Ls)
+        dpcs.dpcs_render_vjp(ctx, scene, params, proj, G, sample_radiance=Ls, **grads)
+
+    def timed(fn, k):
+        for _ in range(a.warmup):
+            fn()
+        ctx.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        ctx.synchronize()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / k
+
+    ms_fwd = timed(fwd, a.steps)
+    fwd_sps = samples / (ms_fwd * 1e-3)
+    ms_step = timed(step, a.steps)
+    step_sps = samples / (ms_step * 1e-3)
+    print(f"[bench] forward {ms_fwd:.3f} ms, {fwd_sps:.4e} samples/s; fwd+vjp {ms_step:.3f} ms, "
+          f"{step_sps:.4e} samples/s", file=sys.stderr, flush=True)
 
     roof = None
     stages = None
@@ -164,13 +178,15 @@ def main():
         print(f"[bench] oracle {cpu['value']:.1f} samples/s on {cpu['cores']} threads", file=sys.stderr, flush=True)
 
     line = {
-        "metric": METRIC, "value": round(fwd_sps, 1), "unit": "samples/s", "n_gpus": 1, "steps": a.steps,
+        "metric": METRIC, "value": round(step_sps, 1), "unit": "samples/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 traversal + f64 shading", "data": "synthetic",
         "config": {"workload": w.name, "camera": [W, H], "projector": [w.projector.width, w.projector.height],
                    "spp": w.spp, "max_depth": w.max_depth, "triangles": info.num_triangles,
-                   "bvh_build_ms": round(info.build_ms, 3), "step": "forward render"},
-        "fwd_samples_per_s": round(fwd_sps, 1),
+                   "bvh_build_ms": round(info.build_ms, 3),
+                   "step": "forward render + VJP (path replay) of the same samples"},
+        "fwd_samples_per_s": round(fwd_sps, 1), "fwd_ms": round(ms_fwd, 4),
+        "fwd_adj_samples_per_s": round(step_sps, 1),
         "roofline": roof, "cpu_baseline": cpu, "stages": stages,
     }
     print(json.dumps(line))

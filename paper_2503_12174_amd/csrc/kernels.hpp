@@ -89,14 +89,17 @@ void launch_finalize(const Launch& l, const Queues& q, const ReqDesc& r, const R
 void launch_set_desc(const Launch& l, ReqDesc* table, int slot, const ReqDesc& r);
 
 // adjoint kernels
-void launch_adj_pixel(const Launch& l, const Queues& q, const AdjQueues& aq, const ReqDesc& r, const ReqDesc* table,
-                      int slot, uint32_t p0, uint32_t p1);
+void launch_adj_pixel(const Launch& l, const Queues& q, const AdjQueues& aq, const ReqDesc& r, uint32_t p0,
+                      uint32_t p1, const float* sample_L);
+void launch_adj_raygen(const Launch& l, const Queues& q, const AdjQueues& aq, const ReqDesc& r, int slot, uint32_t g0,
+                       uint32_t n);
 void launch_adj_shade(const Launch& l, const Queues& q, const AdjQueues& aq, int cur, int depth, const ReqDesc& uni,
                       const ReqDesc* table, int64_t n_upper);
-void launch_adj_shadow(const Launch& l, const Queues& q, const AdjQueues& aq, int which, const ReqDesc& uni,
+void launch_adj_shadow(const Launch& l, const Queues& q, const AdjQueues& aq, int which, int nxt, const ReqDesc& uni,
                        const ReqDesc* table, int64_t n_upper, int stack);
+// PRF backward, map de-interleave and scalar gradients; acc: 20 floats (see adjoint.hip)
 void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* d_albedo, float* d_rough,
-                       float* d_spec, float* d_scalars, float* scal_partials, int nblocks_partials);
+                       float* d_spec, float* d_scalars, float* acc);
 void launch_zero(const Launch& l, float* p, int64_t n);
 
 // debug

@@ -85,6 +85,29 @@ bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpc
     return true;
 }
 
+bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues& aq, dpcs_status* st) {
+    const size_t c = (size_t)cap;
+    const size_t bytes = c * (2 * 48 + 16 + 2 * 52) + 4096;
+    char* b = (char*)scratch(ctx, name, bytes, st);
+    if (!b) return false;
+    auto take = [&](size_t n) {
+        char* p = b;
+        b += (n + 255) & ~size_t(255);
+        return (void*)p;
+    };
+    for (int k = 0; k < 2; ++k) {
+        aq.rl[k] = (float4*)take(16 * c);
+        aq.pend[k] = (float4*)take(16 * c);
+        aq.penda[k] = (float4*)take(16 * c);
+        aq.sx[k] = (float4*)take(16 * c);
+        aq.sg[k] = (float4*)take(16 * c);
+        aq.sa[k] = (float4*)take(16 * c);
+        aq.ss[k] = (float*)take(4 * c);
+    }
+    aq.delta = (float4*)take(16 * c);
+    return true;
+}
+
 static void inv3(const double* m, double* o) {
     const double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5], g = m[6], h = m[7], i = m[8];
     const double A = e * i - f * h, B = -(d * i - f * g), C = d * h - e * g;
@@ -563,45 +586,73 @@ bool prepare_request(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, 
     return true;
 }
 
-// Forward waves over pixels [p0, p1) of one request, whole pixels per wave.
-bool forward_waves(dpcs_context ctx, const Queues& q0, ReqDesc r, uint32_t p0, uint32_t p1) {
+void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t b, bool finalize) {
     Launch l{ctx->stream, ctx->grid_cap};
-    const int64_t ppw = std::max<int64_t>(1, q0.cap / r.spp);   // pixels per wave
     const int stack = r.stack_hint;
-    Queues q = q0;
-    for (int64_t a = p0; a < p1; a += ppw) {
-        const uint32_t b = (uint32_t)std::min<int64_t>(p1, a + ppw);
-        const uint32_t n = (b - (uint32_t)a) * (uint32_t)r.spp;
-        r.g_base = (uint32_t)a * (uint32_t)r.spp;
-        r.sid_base = 0;
-        launch_set_count(l, q.cnt, 0, n, 1, 4);
-        int pr = prof_begin(ctx, DPCS_STAGE_RAYGEN);
-        launch_raygen(l, q, r, nullptr, 0, r.g_base, n, false, nullptr);
-        prof_end(ctx, pr, nullptr, n);
-        int cur = 0;
-        for (int d = 0; d < r.max_depth; ++d) {
-            launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);   // next path queue and shadow queues empty
-            q.stats = prof_stats(ctx, DPCS_STAGE_TRACE);
-            pr = prof_begin(ctx, DPCS_STAGE_TRACE);
-            launch_trace(l, q, cur, r, nullptr, n, stack);
-            prof_end(ctx, pr, q.cnt + cur, 0);
-            pr = prof_begin(ctx, DPCS_STAGE_SHADE);
-            launch_shade(l, q, cur, d, r, nullptr, n);
-            prof_end(ctx, pr, q.cnt + cur, 0);
-            q.stats = prof_stats(ctx, DPCS_STAGE_SHADOW);
-            for (int w = 0; w < (r.env_on ? 2 : 1); ++w) {
-                pr = prof_begin(ctx, DPCS_STAGE_SHADOW);
-                launch_shadow(l, q, w, r, nullptr, n, stack);
-                prof_end(ctx, pr, q.cnt + 2 + w, 0);
-            }
-            q.stats = nullptr;
-            cur ^= 1;
+    const uint32_t n = (b - a) * (uint32_t)r.spp;
+    r.g_base = a * (uint32_t)r.spp;
+    r.sid_base = 0;
+    launch_set_count(l, q.cnt, 0, n, 1, 4);
+    int pr = prof_begin(ctx, DPCS_STAGE_RAYGEN);
+    launch_raygen(l, q, r, nullptr, 0, r.g_base, n, false, nullptr);
+    prof_end(ctx, pr, nullptr, n);
+    int cur = 0;
+    for (int d = 0; d < r.max_depth; ++d) {
+        launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);   // next path queue and shadow queues empty
+        q.stats = prof_stats(ctx, DPCS_STAGE_TRACE);
+        pr = prof_begin(ctx, DPCS_STAGE_TRACE);
+        launch_trace(l, q, cur, r, nullptr, n, stack);
+        prof_end(ctx, pr, q.cnt + cur, 0);
+        pr = prof_begin(ctx, DPCS_STAGE_SHADE);
+        launch_shade(l, q, cur, d, r, nullptr, n);
+        prof_end(ctx, pr, q.cnt + cur, 0);
+        q.stats = prof_stats(ctx, DPCS_STAGE_SHADOW);
+        for (int w = 0; w < (r.env_on ? 2 : 1); ++w) {
+            pr = prof_begin(ctx, DPCS_STAGE_SHADOW);
+            launch_shadow(l, q, w, r, nullptr, n, stack);
+            prof_end(ctx, pr, q.cnt + 2 + w, 0);
         }
-        pr = prof_begin(ctx, DPCS_STAGE_FINALIZE);
-        launch_finalize(l, q, r, nullptr, 0, (uint32_t)a, b);
-        prof_end(ctx, pr, nullptr, b - (uint32_t)a);
+        q.stats = nullptr;
+        cur ^= 1;
     }
-    return hip_ok(ctx, hipGetLastError(), "kernel launch");
+    if (finalize) {
+        pr = prof_begin(ctx, DPCS_STAGE_FINALIZE);
+        launch_finalize(l, q, r, nullptr, 0, a, b);
+        prof_end(ctx, pr, nullptr, b - a);
+    }
+}
+
+void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, uint32_t a, uint32_t b,
+                  const float* sample_L) {
+    Launch l{ctx->stream, ctx->grid_cap};
+    const int stack = r.stack_hint;
+    const uint32_t n = (b - a) * (uint32_t)r.spp;
+    r.g_base = a * (uint32_t)r.spp;
+    r.sid_base = 0;
+    int pr = prof_begin(ctx, DPCS_STAGE_ADJ_PIXEL);
+    launch_adj_pixel(l, q, aq, r, a, b, sample_L);
+    prof_end(ctx, pr, nullptr, b - a);
+    launch_set_count(l, q.cnt, 0, n, 1, 4);
+    launch_adj_raygen(l, q, aq, r, 0, r.g_base, n);
+    int cur = 0;
+    for (int d = 0; d < r.max_depth; ++d) {
+        launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
+        q.stats = prof_stats(ctx, DPCS_STAGE_TRACE);
+        pr = prof_begin(ctx, DPCS_STAGE_TRACE);
+        launch_trace(l, q, cur, r, nullptr, n, stack);
+        prof_end(ctx, pr, q.cnt + cur, 0);
+        pr = prof_begin(ctx, DPCS_STAGE_ADJ_SHADE);
+        launch_adj_shade(l, q, aq, cur, d, r, nullptr, n);
+        prof_end(ctx, pr, q.cnt + cur, 0);
+        q.stats = prof_stats(ctx, DPCS_STAGE_ADJ_SHADOW);
+        for (int w = 0; w < (r.env_on ? 2 : 1); ++w) {
+            pr = prof_begin(ctx, DPCS_STAGE_ADJ_SHADOW);
+            launch_adj_shadow(l, q, aq, w, cur ^ 1, r, nullptr, n, stack);
+            prof_end(ctx, pr, q.cnt + 2 + w, 0);
+        }
+        q.stats = nullptr;
+        cur ^= 1;
+    }
 }
 
 }  // namespace dpcs
@@ -628,9 +679,11 @@ extern "C" dpcs_status dpcs_render(dpcs_context ctx, dpcs_scene scene, const dpc
     if (!prepare_request(ctx, r, params, "fwd", &st)) return st;
     const int64_t npix = (int64_t)r.Wc * r.Hc;
     const int64_t cap = std::min<int64_t>(std::max<int64_t>(ctx->capacity, r.spp), npix * r.spp);
+    const int64_t ppw = std::max<int64_t>(1, cap / r.spp);   // whole pixels per wave
     Queues q;
-    if (!make_queues(ctx, "fwd.queues", (cap / r.spp) * r.spp, q, &st)) return st;
-    if (!forward_waves(ctx, q, r, 0, (uint32_t)npix)) return DPCS_E_DEVICE;
+    if (!make_queues(ctx, "fwd.queues", ppw * r.spp, q, &st)) return st;
+    for (int64_t a = 0; a < npix; a += ppw) forward_wave(ctx, q, r, (uint32_t)a, (uint32_t)std::min(npix, a + ppw), true);
+    if (!hip_ok(ctx, hipGetLastError(), "kernel launch")) return DPCS_E_DEVICE;
     ctx->err.clear();
     return DPCS_OK;
 }

@@ -76,4 +76,14 @@ unsigned long long* prof_stats(dpcs_context ctx, int stage);
 bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpcs_status* st);
 bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues& aq, dpcs_status* st);
 
+// PRF'd projector irradiance and packed maps of one request in scratch (tag selects the buffers)
+bool prepare_request(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, const char* tag, dpcs_status* st);
+// one launch wave of the forward path over pixels [a, b) (whole pixels); per-sample
+// radiance lands in q.L; finalize writes the request's outputs
+void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t b, bool finalize);
+// one launch wave of the path-replay adjoint over pixels [a, b) (q.L holds the samples
+// unless sample_L is given)
+void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, uint32_t a, uint32_t b,
+                  const float* sample_L);
+
 }  // namespace dpcs

@@ -1,7 +1,58 @@
-// vjp.cpp -- dpcs_render_vjp orchestration (entry point; adjoint kernels follow).
+// vjp.cpp -- dpcs_render_vjp: per launch wave of whole pixels, forward samples (unless
+// the caller hands in the forward call's per-sample radiance), CRF/clip backward,
+// path replay with gradient scatter; finally the PRF backward and scalar reductions.
+#include <algorithm>
+
 #include "runtime.hpp"
 
-extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene, const dpcs_render_params*, const float*,
-                                       const float*, const float*, const dpcs_grads*) {
-    return dpcs::fail(ctx, DPCS_E_UNSUPPORTED, "VJP not available in this build");
+using namespace dpcs;
+
+extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
+                                       const float* proj_image, const float* grad_image, const float* sample_radiance,
+                                       const dpcs_grads* grads) {
+    if (!ctx) return DPCS_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (ctx->sticky) return DPCS_E_DEVICE;
+    if (!scene || scene->ctx != ctx) return fail(ctx, DPCS_E_INVALID, "scene is NULL or from another context");
+    if (!grad_image) return fail(ctx, DPCS_E_INVALID, "grad_image is NULL");
+    if (!grads) return fail(ctx, DPCS_E_INVALID, "grads is NULL");
+    (void)hipGetLastError();
+    ReqDesc r;
+    std::string why;
+    if (!fill_desc(ctx, r, params, scene, proj_image, &why)) return fail(ctx, DPCS_E_INVALID, why);
+    hipSetDevice(ctx->device);
+    r.grad_image = grad_image;
+    dpcs_status st = DPCS_OK;
+    if (!prepare_request(ctx, r, params, "vjp", &st)) return st;
+    const size_t nEp = (size_t)r.Wp * r.Hp, nT = (size_t)r.tw * r.th;
+    float* dEp = (float*)scratch(ctx, "vjp.dEp", sizeof(float) * 4 * nEp, &st);
+    if (!dEp) return st;
+    float* dtex = (float*)scratch(ctx, "vjp.dtex", sizeof(float) * 5 * nT, &st);
+    if (!dtex) return st;
+    float* acc = (float*)scratch(ctx, "vjp.acc", sizeof(float) * 32, &st);
+    if (!acc) return st;
+    Launch l{ctx->stream, ctx->grid_cap};
+    launch_zero(l, dEp, 4 * (int64_t)nEp);
+    launch_zero(l, dtex, 5 * (int64_t)nT);
+    launch_zero(l, acc, 32);
+    r.dEp = dEp;
+    r.d_tex = dtex;
+    r.d_acc = acc;
+    const int64_t npix = (int64_t)r.Wc * r.Hc;
+    const int64_t cap = std::min<int64_t>(std::max<int64_t>(ctx->capacity, r.spp), npix * r.spp);
+    const int64_t ppw = std::max<int64_t>(1, cap / r.spp);
+    Queues q;
+    AdjQueues aq;
+    if (!make_queues(ctx, "fwd.queues", ppw * r.spp, q, &st)) return st;
+    if (!make_adj_queues(ctx, "vjp.queues", ppw * r.spp, aq, &st)) return st;
+    for (int64_t a = 0; a < npix; a += ppw) {
+        const uint32_t b = (uint32_t)std::min(npix, a + ppw);
+        if (!sample_radiance) forward_wave(ctx, q, r, (uint32_t)a, b, false);
+        adjoint_wave(ctx, q, aq, r, (uint32_t)a, b, sample_radiance);
+    }
+    launch_adj_finish(l, r, grads->d_proj_image, grads->d_albedo, grads->d_roughness, grads->d_specular,
+                      grads->d_scalars, acc);
+    if (!hip_ok(ctx, hipGetLastError(), "kernel launch")) return DPCS_E_DEVICE;
+    ctx->err.clear();
+    return DPCS_OK;
 }

@@ -1,0 +1,79 @@
+"""Thin optimisation drivers over the differentiable renderer (paper Sec. 3.2).
+
+compensate()  projector compensation, Eq. 13: find I_p whose rendering matches a
+              target camera image, by Adam on an L2 loss, I_p clamped to [0, 1]
+fit()         scene-parameter fit, Eq. 9: BRDF maps and PRF/CRF scalars from image
+              pairs, L2 loss, with the paper's constraints on gamma_p, gamma_c, w
+              (Sec. 3.2: gamma_p in [2, 3], gamma_c in [1/3, 1], w in (0.2, 2.5))
+Each optimisation step uses its own Philox seed (base seed + step), so a run is
+reproducible and resumable from any step.
+"""
+from __future__ import annotations
+
+import copy
+
+import torch
+
+from .autograd import render, scalars_from
+
+
+def compensate(ctx, scene, cfg, target, albedo, roughness, specular, steps=100, lr=0.01, init=0.5,
+               base_seed=0, callback=None):
+    scal = scalars_from(cfg)
+    H, W = cfg.projector.height, cfg.projector.width
+    ip = torch.full((H, W, 3), init, device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([ip], lr=lr)
+    losses = []
+    for k in range(steps):
+        c = copy.copy(cfg)
+        c.seed = base_seed + k
+        out = render(ctx, scene, c, ip, albedo, roughness, specular, scal)
+        loss = ((out - target) ** 2).mean()
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            ip.clamp_(0.0, 1.0)
+        losses.append(float(loss))
+        if callback:
+            callback(k, losses[-1], ip)
+    return ip.detach(), losses
+
+
+def project_constraints(scal: torch.Tensor, clamp_gamma_p=True):
+    with torch.no_grad():
+        if clamp_gamma_p:
+            scal[0:3].clamp_(2.0, 3.0)
+        scal[12:15].clamp_(1.0 / 3.0, 1.0)
+        scal[15:18].clamp_(0.2 + 1e-4, 2.5 - 1e-4)
+
+
+def fit(ctx, scene, cfg, images, targets, steps=50, lr=0.02, base_seed=0, clamp_gamma_p=True, init=None):
+    """Fit albedo/roughness/specular maps and the 18 response scalars to (image, target) pairs."""
+    th, tw = cfg.albedo.shape[:2]
+    dev = lambda x: torch.as_tensor(x, dtype=torch.float32, device="cuda").clone().requires_grad_(True)
+    init = init or {}
+    alb = dev(init.get("albedo", torch.full((th, tw, 3), 0.5)))
+    rough = dev(init.get("roughness", torch.full((th, tw), 0.5)))
+    spec = dev(init.get("specular", torch.full((th, tw), 0.5)))
+    scal = scalars_from(cfg).clone().requires_grad_(True)
+    opt = torch.optim.Adam([alb, rough, spec, scal], lr=lr)
+    losses = []
+    for k in range(steps):
+        c = copy.copy(cfg)
+        c.seed = base_seed + k
+        loss = 0.0
+        for ip, tgt in zip(images, targets):
+            out = render(ctx, scene, c, ip, alb, rough, spec, scal)
+            loss = loss + ((out - tgt) ** 2).mean()
+        loss = loss / len(images)
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            alb.clamp_(0.0, 1.0)
+            rough.clamp_(0.05, 1.0)
+            spec.clamp_(0.0, 1.0)
+        project_constraints(scal, clamp_gamma_p)
+        losses.append(float(loss))
+    return dict(albedo=alb.detach(), roughness=rough.detach(), specular=spec.detach(), scalars=scal.detach()), losses
