@@ -1,11 +1,497 @@
-// server.cpp -- continuous-batching request loop (entry points; loop implementation follows).
+// server.cpp -- continuous-batching request loop.
+//
+// One scheduler thread per server owns a HIP stream (default priority) on the
+// context's device.  Requests are admitted while the device-memory estimate of all
+// admitted requests fits the budget and a descriptor slot is free.  Every launch
+// wave packs whole-pixel segments of all active requests into shared path queues:
+// raygen / finalize / adj_pixel run per segment, trace / shade / shadow (and their
+// adjoint forms) run once over the shared queues and read each path's request
+// descriptor from a device table by slot.  Compensation-step requests (forward +
+// VJP) put their segments first so their replay fills a dense queue prefix.  A
+// request completes when its last wave (and its gradient reduction) has passed on
+// the device; its latency is measured from submit to that point on the host clock.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <thread>
+
 #include "runtime.hpp"
 
-extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t, int32_t, dpcs_server* out) {
-    if (out) *out = nullptr;
-    return dpcs::fail(ctx, DPCS_E_UNSUPPORTED, "server not available in this build");
+using namespace dpcs;
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+// first-fit allocator of offsets inside one device arena
+class Arena {
+  public:
+    void reset(size_t size) {
+        size_ = size;
+        free_.clear();
+        if (size) free_.push_back({0, size});
+    }
+    bool alloc(size_t bytes, size_t* off) {
+        bytes = (bytes + 255) & ~size_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                it->first += bytes;
+                it->second -= bytes;
+                if (it->second == 0) free_.erase(it);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = (bytes + 255) & ~size_t(255);
+        auto it = free_.begin();
+        while (it != free_.end() && it->first < off) ++it;
+        it = free_.insert(it, {off, bytes});
+        auto nx = std::next(it);   // coalesce with neighbours
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    size_t size_ = 0;
+    std::list<std::pair<size_t, size_t>> free_;
+};
+
+struct Req {
+    uint64_t id = 0;
+    dpcs_scene scene = nullptr;
+    dpcs_render_params params{};
+    ReqDesc r{};
+    const float* proj = nullptr;
+    float* out = nullptr;
+    const float* grad = nullptr;
+    const float* target = nullptr;
+    dpcs_grads grads{};
+    bool adjoint = false;
+    int64_t npix = 0, next_pixel = 0;
+    size_t bytes = 0, off = 0;
+    int slot = -1;
+    clk::time_point t_submit;
+    hipEvent_t done = nullptr;
+    int32_t status = DPCS_OK;
+    bool scheduled_all = false;
+};
+
+struct Seg {
+    Req* q;
+    uint32_t a, b;   // pixels
+};
+
+size_t request_bytes(const ReqDesc& r, bool adjoint) {
+    const size_t nEp = (size_t)r.Wp * r.Hp, nT = (size_t)r.tw * r.th;
+    size_t b = 16 * nEp + 256 + 16 * nT + 256;          // E_p, packed maps
+    if (adjoint) b += 16 * nEp + 256 + 20 * nT + 256 + 256;   // dE_p, map cotangents, scalars
+    return b;
 }
-extern "C" dpcs_status dpcs_server_submit(dpcs_server, const dpcs_request*) { return DPCS_E_UNSUPPORTED; }
-extern "C" int32_t dpcs_server_poll(dpcs_server, uint64_t*, int32_t*, double*, int32_t) { return 0; }
-extern "C" dpcs_status dpcs_server_stats(dpcs_server, int64_t*) { return DPCS_E_UNSUPPORTED; }
-extern "C" dpcs_status dpcs_server_destroy(dpcs_server) { return DPCS_E_UNSUPPORTED; }
+
+}  // namespace
+
+struct dpcs_server_s {
+    dpcs_context ctx = nullptr;
+    hipStream_t st = nullptr;
+    size_t budget = 0, shared_bytes = 0, admitted_bytes = 0;
+    int max_slots = 0;
+    int64_t cap = 0;
+    ReqDesc* table = nullptr;
+    char* arena_base = nullptr;
+    Arena arena;
+    void* qbuf = nullptr;
+    Queues q{};
+    AdjQueues aq{};
+    std::vector<int> free_slots;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req*> queued;
+    std::vector<Req*> active, finishing;
+    std::deque<std::tuple<uint64_t, int32_t, double>> completed;
+    bool stop = false;
+    int64_t st_submitted = 0, st_completed = 0, st_rejected = 0, st_waves = 0, st_samples = 0, st_peak = 0;
+    std::thread worker;
+    std::string err;
+    void run();
+    void admit_locked(Launch& l);
+    void wave(Launch& l);
+};
+
+void dpcs_server_s::admit_locked(Launch& l) {
+    while (!queued.empty() && !free_slots.empty()) {
+        Req* q = queued.front();
+        if (admitted_bytes + q->bytes + shared_bytes > budget) break;   // FIFO: wait for memory
+        size_t off = 0;
+        if (!arena.alloc(q->bytes, &off)) break;
+        queued.pop_front();
+        q->off = off;
+        q->slot = free_slots.back();
+        free_slots.pop_back();
+        admitted_bytes += q->bytes;
+        st_peak = std::max<int64_t>(st_peak, (int64_t)(admitted_bytes + shared_bytes));
+        // carve the request's device state from its arena region
+        char* base = arena_base + off;
+        auto take = [&](size_t n) {
+            char* p = base;
+            base += (n + 255) & ~size_t(255);
+            return (void*)p;
+        };
+        ReqDesc& r = q->r;
+        const size_t nEp = (size_t)r.Wp * r.Hp, nT = (size_t)r.tw * r.th;
+        float4* Ep = (float4*)take(16 * nEp);
+        float4* tex = (float4*)take(16 * nT);
+        launch_prf(l, r, Ep);
+        launch_pack_tex(l, r, q->params.albedo, q->params.brdf == DPCS_BRDF_GGX ? q->params.roughness : nullptr, tex);
+        r.Ep = Ep;
+        r.tex4 = tex;
+        if (q->adjoint) {
+            r.dEp = (float*)take(16 * nEp);
+            r.d_tex = (float*)take(20 * nT);
+            r.d_acc = (float*)take(128);
+            launch_zero(l, r.dEp, 4 * (int64_t)nEp);
+            launch_zero(l, r.d_tex, 5 * (int64_t)nT);
+            launch_zero(l, r.d_acc, 32);
+        }
+        active.push_back(q);
+    }
+}
+
+void dpcs_server_s::wave(Launch& l) {
+    // share the wave's capacity among active requests, whole pixels each, adjoint first
+    std::vector<Req*> order;
+    for (Req* q : active)
+        if (q->adjoint && !q->scheduled_all) order.push_back(q);
+    for (Req* q : active)
+        if (!q->adjoint && !q->scheduled_all) order.push_back(q);
+    if (order.empty()) return;
+    std::vector<Seg> segs;
+    int64_t used = 0, n_adj = 0;
+    int max_depth = 1, stack = 32;
+    bool env = false, any_adj = false;
+    const int64_t share = std::max<int64_t>(1, cap / (int64_t)order.size());
+    for (Req* q : order) {
+        const int spp = q->r.spp;
+        int64_t px = std::min<int64_t>(q->npix - q->next_pixel, std::max<int64_t>(1, share / spp));
+        px = std::min<int64_t>(px, (cap - used) / spp);
+        if (px <= 0) continue;
+        Seg s{q, (uint32_t)q->next_pixel, (uint32_t)(q->next_pixel + px)};
+        q->r.g_base = s.a * (uint32_t)spp;
+        q->r.sid_base = (uint32_t)used;
+        launch_set_desc(l, table, q->slot, q->r);
+        segs.push_back(s);
+        used += px * spp;
+        if (q->adjoint) n_adj = used, any_adj = true;
+        q->next_pixel += px;
+        max_depth = std::max(max_depth, q->r.max_depth);
+        stack = std::max(stack, q->r.stack_hint);
+        env = env || q->r.env_on;
+    }
+    if (segs.empty()) return;
+    const ReqDesc& any = segs[0].q->r;
+    // forward over the shared queues
+    launch_set_count(l, q.cnt, 0, (uint32_t)used, 1, 4);
+    for (const Seg& s : segs) launch_raygen(l, q, s.q->r, table, s.q->slot, s.q->r.g_base, (s.b - s.a) * s.q->r.spp,
+                                            false, nullptr);
+    int cur = 0;
+    for (int d = 0; d < max_depth; ++d) {
+        launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
+        launch_trace(l, q, cur, any, table, used, stack);
+        launch_shade(l, q, cur, d, any, table, used);
+        launch_shadow(l, q, 0, any, table, used, stack);
+        if (env) launch_shadow(l, q, 1, any, table, used, stack);
+        cur ^= 1;
+    }
+    for (const Seg& s : segs) launch_finalize(l, q, s.q->r, table, s.q->slot, s.a, s.b);
+    // adjoint replay of the compensation-step segments (a dense prefix of the wave)
+    if (any_adj) {
+        for (const Seg& s : segs)
+            if (s.q->adjoint) launch_adj_pixel(l, q, aq, s.q->r, s.a, s.b, nullptr);
+        launch_set_count(l, q.cnt, 0, (uint32_t)n_adj, 1, 4);
+        for (const Seg& s : segs)
+            if (s.q->adjoint) launch_adj_raygen(l, q, aq, s.q->r, s.q->slot, s.q->r.g_base, (s.b - s.a) * s.q->r.spp);
+        cur = 0;
+        for (int d = 0; d < max_depth; ++d) {
+            launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
+            launch_trace(l, q, cur, any, table, n_adj, stack);
+            launch_adj_shade(l, q, aq, cur, d, any, table, n_adj);
+            launch_adj_shadow(l, q, aq, 0, cur ^ 1, any, table, n_adj, stack);
+            if (env) launch_adj_shadow(l, q, aq, 1, cur ^ 1, any, table, n_adj, stack);
+            cur ^= 1;
+        }
+    }
+    ++st_waves;
+    st_samples += used + n_adj;
+    for (const Seg& s : segs) {
+        Req* q = s.q;
+        if (q->next_pixel >= q->npix) {
+            q->scheduled_all = true;
+            if (q->adjoint)
+                launch_adj_finish(l, q->r, q->grads.d_proj_image, q->grads.d_albedo, q->grads.d_roughness,
+                                  q->grads.d_specular, q->grads.d_scalars, q->r.d_acc);
+            hipEventRecord(q->done, st);
+        }
+    }
+    if (hipGetLastError() != hipSuccess) err = "kernel launch failed in the server loop";
+}
+
+void dpcs_server_s::run() {
+    hipSetDevice(ctx->device);
+    Launch l{st, ctx->grid_cap};
+    std::deque<hipEvent_t> inflight;
+    std::vector<hipEvent_t> ev_pool;
+    for (int k = 0; k < 4; ++k) {
+        hipEvent_t e;
+        hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        ev_pool.push_back(e);
+    }
+    size_t ev_next = 0;
+    while (true) {
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            admit_locked(l);
+            if (stop && queued.empty() && active.empty() && finishing.empty()) break;
+            if (active.empty() && finishing.empty())
+                cv.wait_for(lk, std::chrono::milliseconds(2));
+        }
+        // one wave over everything active (the lists only change on this thread)
+        bool launched = false;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            const bool have = std::any_of(active.begin(), active.end(), [](Req* q) { return !q->scheduled_all; });
+            if (have) {
+                wave(l);
+                launched = true;
+            }
+            for (auto it = active.begin(); it != active.end();) {
+                if ((*it)->scheduled_all) {
+                    finishing.push_back(*it);
+                    it = active.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+        }
+        if (launched) {
+            hipEvent_t e = ev_pool[ev_next++ % ev_pool.size()];
+            hipEventRecord(e, st);
+            inflight.push_back(e);
+            while (inflight.size() > 2) {   // keep at most two waves queued on the device
+                hipEventSynchronize(inflight.front());
+                inflight.pop_front();
+            }
+        } else if (!finishing.empty()) {
+            std::this_thread::sleep_for(std::chrono::microseconds(50));
+        }
+        // retire requests whose work has passed on the device
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto it = finishing.begin(); it != finishing.end();) {
+            Req* q = *it;
+            const hipError_t e = hipEventQuery(q->done);
+            if (e == hipErrorNotReady) {
+                ++it;
+                continue;
+            }
+            const double ms = std::chrono::duration<double, std::milli>(clk::now() - q->t_submit).count();
+            const int32_t status = e == hipSuccess && err.empty() ? DPCS_OK : DPCS_E_DEVICE;
+            completed.emplace_back(q->id, status, ms);
+            ++st_completed;
+            arena.release(q->off, q->bytes);
+            admitted_bytes -= q->bytes;
+            free_slots.push_back(q->slot);
+            q->scene->refs.fetch_sub(1);
+            hipEventDestroy(q->done);
+            delete q;
+            it = finishing.erase(it);
+        }
+    }
+    hipStreamSynchronize(st);
+    for (auto e : ev_pool) hipEventDestroy(e);
+}
+
+extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget_bytes, int32_t max_slots,
+                                          dpcs_server* out) {
+    if (!ctx || !out || max_slots < 1 || max_slots > 4096) return DPCS_E_INVALID;
+    *out = nullptr;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (ctx->sticky) return DPCS_E_DEVICE;
+    hipSetDevice(ctx->device);
+    (void)hipGetLastError();
+    auto* s = new dpcs_server_s();
+    s->ctx = ctx;
+    s->budget = memory_budget_bytes;
+    s->max_slots = max_slots;
+    // shared wave queues take at most a quarter of the budget
+    const size_t per_path = (2 * 80 + 4 + 2 * 52 + 16) + (2 * 48 + 16 + 2 * 52);
+    const int64_t fit = (int64_t)(memory_budget_bytes / 4 / per_path);
+    s->cap = std::max<int64_t>(1024, std::min<int64_t>({ctx->capacity, int64_t(1) << 22, fit}));
+    const size_t c = (size_t)s->cap;
+    const size_t qbytes = c * per_path + 2 * 4096 + 64 * 256;
+    s->shared_bytes = qbytes + sizeof(ReqDesc) * (size_t)max_slots;
+    if (s->shared_bytes >= s->budget) {
+        delete s;
+        return fail(ctx, DPCS_E_INVALID, "memory budget smaller than the shared queues of one wave");
+    }
+    const size_t arena_bytes = s->budget - s->shared_bytes;
+    bool ok = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipMalloc((void**)&s->table, sizeof(ReqDesc) * max_slots) == hipSuccess;
+    ok = ok && hipMalloc(&s->qbuf, qbytes) == hipSuccess;
+    ok = ok && hipMalloc((void**)&s->arena_base, arena_bytes) == hipSuccess;
+    if (!ok) {
+        hipGetLastError();
+        if (s->table) hipFree(s->table);
+        if (s->qbuf) hipFree(s->qbuf);
+        if (s->st) hipStreamDestroy(s->st);
+        delete s;
+        return fail(ctx, DPCS_E_OOM, "server allocation failed");
+    }
+    s->arena.reset(arena_bytes);
+    // carve the shared queues
+    char* b = (char*)s->qbuf;
+    auto take = [&](size_t n) {
+        char* p = b;
+        b += (n + 255) & ~size_t(255);
+        return (void*)p;
+    };
+    for (int k = 0; k < 2; ++k) {
+        s->q.po[k] = (PathO*)take(32 * c);
+        s->q.pd[k] = (PathD*)take(32 * c);
+        s->q.pb[k] = (float4*)take(16 * c);
+        s->q.so[k] = (float4*)take(16 * c);
+        s->q.sd[k] = (float4*)take(16 * c);
+        s->q.sc[k] = (float4*)take(16 * c);
+        s->q.st[k] = (float*)take(4 * c);
+        s->aq.rl[k] = (float4*)take(16 * c);
+        s->aq.pend[k] = (float4*)take(16 * c);
+        s->aq.penda[k] = (float4*)take(16 * c);
+        s->aq.sx[k] = (float4*)take(16 * c);
+        s->aq.sg[k] = (float4*)take(16 * c);
+        s->aq.sa[k] = (float4*)take(16 * c);
+        s->aq.ss[k] = (float*)take(4 * c);
+    }
+    s->q.hit = (int*)take(4 * c);
+    s->q.L = (float4*)take(16 * c);
+    s->aq.delta = (float4*)take(16 * c);
+    s->q.cnt = (uint32_t*)take(16);
+    s->q.cap = s->cap;
+    s->q.stats = nullptr;
+    for (int k = max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
+    s->worker = std::thread([s] { s->run(); });
+    *out = s;
+    return DPCS_OK;
+}
+
+extern "C" dpcs_status dpcs_server_submit(dpcs_server s, const dpcs_request* rq) {
+    if (!s || !rq) return DPCS_E_INVALID;
+    dpcs_context ctx = s->ctx;
+    if (!rq->scene || rq->scene->ctx != ctx || !rq->out_image) return DPCS_E_INVALID;
+    hipSetDevice(ctx->device);
+    auto* q = new Req();
+    std::string why;
+    if (!fill_desc(ctx, q->r, &rq->params, rq->scene, rq->proj_image, &why)) {
+        delete q;
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->err = why;
+        return DPCS_E_INVALID;
+    }
+    q->adjoint = rq->grads != nullptr;
+    if (q->adjoint && !rq->grad_image && !rq->target) {
+        delete q;
+        return DPCS_E_INVALID;
+    }
+    q->id = rq->request_id;
+    q->scene = rq->scene;
+    q->params = rq->params;
+    q->proj = rq->proj_image;
+    q->out = rq->out_image;
+    q->grad = rq->grad_image;
+    q->target = rq->target;
+    if (q->adjoint) q->grads = *rq->grads;
+    q->r.out_image = rq->out_image;
+    q->r.grad_image = rq->grad_image;
+    q->r.target = rq->grad_image ? nullptr : rq->target;
+    q->npix = (int64_t)q->r.Wc * q->r.Hc;
+    q->bytes = request_bytes(q->r, q->adjoint);
+    q->t_submit = clk::now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    ++s->st_submitted;
+    if (q->bytes + s->shared_bytes > s->budget || q->r.spp > s->cap) {
+        ++s->st_rejected;
+        delete q;
+        return DPCS_E_REJECTED;
+    }
+    if (s->stop) {
+        delete q;
+        return DPCS_E_INVALID;
+    }
+    if (hipEventCreateWithFlags(&q->done, hipEventDisableTiming) != hipSuccess) {
+        delete q;
+        return DPCS_E_DEVICE;
+    }
+    q->scene->refs.fetch_add(1);
+    s->queued.push_back(q);
+    s->cv.notify_one();
+    return DPCS_OK;
+}
+
+extern "C" int32_t dpcs_server_poll(dpcs_server s, uint64_t* ids, int32_t* status, double* latency_ms, int32_t max) {
+    if (!s || max <= 0) return 0;
+    std::lock_guard<std::mutex> lk(s->mu);
+    int32_t n = 0;
+    while (n < max && !s->completed.empty()) {
+        auto [id, stt, ms] = s->completed.front();
+        s->completed.pop_front();
+        if (ids) ids[n] = id;
+        if (status) status[n] = stt;
+        if (latency_ms) latency_ms[n] = ms;
+        ++n;
+    }
+    return n;
+}
+
+extern "C" dpcs_status dpcs_server_stats(dpcs_server s, int64_t* o) {
+    if (!s || !o) return DPCS_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    o[0] = s->st_submitted;
+    o[1] = s->st_completed;
+    o[2] = s->st_rejected;
+    o[3] = (int64_t)s->active.size() + (int64_t)s->finishing.size();
+    o[4] = (int64_t)s->queued.size();
+    o[5] = s->st_waves;
+    o[6] = s->st_samples;
+    o[7] = s->st_peak;
+    return DPCS_OK;
+}
+
+extern "C" dpcs_status dpcs_server_destroy(dpcs_server s) {
+    if (!s) return DPCS_E_INVALID;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv.notify_all();
+    }
+    s->worker.join();
+    hipSetDevice(s->ctx->device);
+    hipStreamSynchronize(s->st);
+    hipFree(s->arena_base);
+    hipFree(s->qbuf);
+    hipFree(s->table);
+    hipStreamDestroy(s->st);
+    const bool failed = !s->err.empty();
+    delete s;
+    return failed ? DPCS_E_DEVICE : DPCS_OK;
+}

@@ -277,3 +277,58 @@ def dpcs_debug_intersect(ctx: Context, scene: Scene, rays, use_bvh: bool, prim, 
 
 def dpcs_debug_philox(ctx: Context, seed: int, ctr, out):
     return ctx.check(lib().dpcs_debug_philox(ctx.h, int(seed), _ptr(ctr), int(ctr.shape[0]), _ptr(out)))
+
+
+class Server:
+    """dpcs_server: continuous-batching request loop on a context's device."""
+
+    def __init__(self, ctx: Context, budget_bytes: int, max_slots: int = 64):
+        self.ctx = ctx
+        h = C.c_void_p()
+        ctx.check(lib().dpcs_server_create(ctx.h, int(budget_bytes), int(max_slots), C.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, request_id: int, scene: Scene, params: RenderParams, proj_image, out_image, grad_image=None,
+               target=None, grads: dict | None = None, keep=None) -> int:
+        g = None
+        if grads is not None:
+            g = Grads(_ptr(grads.get("d_proj_image")), _ptr(grads.get("d_albedo")), _ptr(grads.get("d_roughness")),
+                      _ptr(grads.get("d_specular")), _ptr(grads.get("d_scalars")))
+        rq = Request(scene.h, params, _ptr(proj_image), _ptr(out_image), _ptr(grad_image), _ptr(target),
+                     C.pointer(g) if g is not None else None, int(request_id))
+        st = lib().dpcs_server_submit(self.h, C.byref(rq))
+        if st == OK:
+            self._keep[int(request_id)] = (params, proj_image, out_image, grad_image, target, grads, g, keep)
+        return st
+
+    def poll(self, max_items: int = 256):
+        ids = (C.c_uint64 * max_items)()
+        sts = (C.c_int32 * max_items)()
+        lat = (C.c_double * max_items)()
+        n = lib().dpcs_server_poll(self.h, ids, sts, lat, max_items)
+        out = []
+        for k in range(n):
+            out.append((int(ids[k]), int(sts[k]), float(lat[k])))
+            self._keep.pop(int(ids[k]), None)
+        return out
+
+    def stats(self) -> dict:
+        v = (C.c_int64 * 8)()
+        self.ctx.check(lib().dpcs_server_stats(self.h, v))
+        keys = ["submitted", "completed", "rejected", "active", "queued", "waves", "samples", "peak_bytes"]
+        return dict(zip(keys, [int(x) for x in v]))
+
+    def close(self):
+        if getattr(self, "h", None):
+            st = lib().dpcs_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+            return st
+        return OK
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
