@@ -54,7 +54,108 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--quick", action="store_true", help="skip the profiled passes")
+    ap.add_argument("--serving-requests", type=int, default=300, help="0 disables the serving run")
+    ap.add_argument("--serving-alone", type=int, default=60, help="requests also timed alone")
     return ap.parse_args()
+
+
+def serving_bench(ctx, n_req, n_alone, warmup=20, rate=50.0):
+    """Config-5 shaped serving: 4 resident corners (10k/50k/200k/500k triangles),
+    Poisson arrivals, resolution in {128, 256, 512}^2, spp in {16, 64, 256}, depth 4,
+    half relighting and half compensation steps (fwd + VJP of an L2 loss)."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2503_12174_amd import dpcs, synth
+
+    t = time.perf_counter()
+    meshes = synth.serving_scenes()
+    scenes = [dpcs.Scene(ctx, m) for m in meshes]
+    infos = [sc.info() for sc in scenes]
+    alb, rough, spec = (torch.as_tensor(x).cuda() for x in synth.ggx_textures(503, 512))
+    reqs = synth.serving_requests(warmup + n_req, seed=501, rate=rate)
+    prep = []
+    for k, rq in enumerate(reqs):
+        res = rq["res"]
+        w = synth.config2(spp=rq["spp"], max_depth=rq["depth"], res=res)
+        w.mesh = meshes[rq["scene"]]
+        w.projector = synth.pinhole((0.85, 0.15, 0.85), (0.3, 0.0, 0.3), 45.0, res, res)
+        w.seed = k
+        p = dpcs.params_from(w, alb, rough, spec)
+        ip = torch.as_tensor(np.random.default_rng(rq["image_seed"]).uniform(0, 1, (res, res, 3)).astype(np.float32)).cuda()
+        out = torch.zeros((res, res, 3), device="cuda")
+        grads = target = None
+        if rq["compensation"]:
+            target = torch.as_tensor(synth.blob_image(res, res, rq["image_seed"] % 1000, lo=0.1, hi=0.9)).cuda()
+            grads = dict(d_proj_image=torch.zeros_like(ip), d_albedo=torch.zeros_like(alb),
+                         d_roughness=torch.zeros_like(rough), d_specular=torch.zeros_like(spec),
+                         d_scalars=torch.zeros(18, device="cuda"))
+        prep.append((k, rq, p, ip, out, target, grads, res * res * rq["spp"]))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+
+    srv = dpcs.Server(ctx, budget_bytes=64 << 30, max_slots=64)
+    lat = {}
+    t0 = time.perf_counter()
+
+    def client():
+        for k, rq, p, ip, out, target, grads, _ in prep:
+            dt = rq["arrival"] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            st = srv.submit(k, scenes[rq["scene"]], p, ip, out, target=target, grads=grads)
+            if st != dpcs.OK:
+                lat[k] = None
+
+    th = threading.Thread(target=client)
+    th.start()
+    last_print = time.perf_counter()
+    while len(lat) < len(prep):
+        for k, st, ms in srv.poll():
+            lat[k] = ms if st == dpcs.OK else None
+        if time.perf_counter() - last_print > 20:
+            print(f"[bench] serving: {len(lat)}/{len(prep)} done", file=sys.stderr, flush=True)
+            last_print = time.perf_counter()
+        time.sleep(0.001)
+    th.join()
+    wall = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    measured = [k for k, *_ in prep[warmup:]]
+    ok = [lat[k] for k in measured if lat[k] is not None]
+    span = wall - reqs[warmup]["arrival"]
+    samples = sum(x[-1] * (2 if x[1]["compensation"] else 1) for x in prep[warmup:])
+
+    # the same requests alone through the plain entry points (a subset, back to back)
+    alone = []
+    for k, rq, p, ip, out, target, grads, _ in prep[warmup:warmup + n_alone]:
+        sc = scenes[rq["scene"]]
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        if grads is None:
+            dpcs.dpcs_render(ctx, sc, p, ip, out)
+        else:
+            L = torch.empty((rq["res"], rq["res"], rq["spp"], 3), device="cuda")
+            dpcs.dpcs_render(ctx, sc, p, ip, out, sample_radiance=L)
+            G = (2.0 * (out - target) / out.numel()).contiguous()
+            dpcs.dpcs_render_vjp(ctx, sc, p, ip, G, sample_radiance=L, **grads)
+        ctx.synchronize()
+        alone.append((time.perf_counter() - ta) * 1e3)
+    offered = sum(x[-1] * (2 if x[1]["compensation"] else 1) for x in prep) / reqs[-1]["arrival"]
+    return {
+        "requests": len(measured), "warmup_requests": warmup, "rate_req_s": rate, "completed_ok": len(ok),
+        "p50_ms": round(float(np.percentile(ok, 50)), 2), "p99_ms": round(float(np.percentile(ok, 99)), 2),
+        "mean_ms": round(float(np.mean(ok)), 2), "achieved_req_s": round(len(ok) / span, 2),
+        "samples_per_s": round(samples / span, 1), "offered_samples_per_s": round(offered, 1),
+        "alone_p50_ms": round(float(np.percentile(alone, 50)), 2),
+        "alone_p99_ms": round(float(np.percentile(alone, 99)), 2), "alone_requests": len(alone),
+        "waves": stats["waves"], "peak_admitted_bytes": stats["peak_bytes"],
+        "scenes_tris": [int(i.num_triangles) for i in infos],
+        "bvh_build_ms": [round(i.build_ms, 2) for i in infos], "setup_s": round(setup_s, 1),
+        "note": "samples count fwd + replay for compensation steps; latency = submit to device completion",
+    }
 
 
 def main():
@@ -159,6 +260,11 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
 
+    serving = None
+    if a.serving_requests > 0:
+        serving = serving_bench(ctx, a.serving_requests, a.serving_alone)
+        print(f"[bench] serving p50 {serving['p50_ms']} ms p99 {serving['p99_ms']} ms", file=sys.stderr, flush=True)
+
     cpu = None
     if not a.no_cpu_baseline:
         from oracle import oracle as O
@@ -187,7 +293,7 @@ def main():
                    "step": "forward render + VJP (path replay) of the same samples"},
         "fwd_samples_per_s": round(fwd_sps, 1), "fwd_ms": round(ms_fwd, 4),
         "fwd_adj_samples_per_s": round(step_sps, 1),
-        "roofline": roof, "cpu_baseline": cpu, "stages": stages,
+        "roofline": roof, "cpu_baseline": cpu, "serving": serving, "stages": stages,
     }
     print(json.dumps(line))
 
