@@ -22,14 +22,54 @@
 
 namespace dpcs {
 
-constexpr int TB = 128;
+constexpr int TB = TRACE_TB;
 
-__device__ __forceinline__ void scatter_tex(const ReqDesc& r, double u, double v, D3 ga, double gr, double gs) {
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Adds v[0..N) to base[stride * idx + j] for every active lane.  Must be called by all
+// lanes of the wave.  Lanes that share an index (common: neighbouring samples of one
+// pixel) are summed across the wave first and written by one atomic per distinct index;
+// once a group has a single lane the remaining lanes add directly.
+template <int N>
+__device__ __forceinline__ void wave_scatter_add(bool active, int idx, float* base, int stride, const float* v) {
+    unsigned long long todo = __ballot(active);
+    const int lane = __lane_id();
+    while (todo) {
+        const int leader = __ffsll(todo) - 1;
+        const int lidx = __shfl(idx, leader);
+        const bool mine = active && idx == lidx;
+        const unsigned long long m = __ballot(mine);
+        if (__popcll(m) < 2) break;
+        float sum[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) sum[j] = wave_sum(mine ? v[j] : 0.0f);
+        if (lane == leader) {
+            float* t = base + (size_t)stride * lidx;
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                if (sum[j] != 0.0f) atomicAdd(t + j, sum[j]);
+        }
+        if (mine) active = false;
+        todo &= ~m;
+    }
+    if (active) {
+        float* t = base + (size_t)stride * idx;
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if (v[j] != 0.0f) atomicAdd(t + j, v[j]);
+    }
+}
+
+// per-lane form (no wave-level cooperation)
+__device__ __forceinline__ void scatter_tex_lane(const ReqDesc& r, double u, double v, D3 ga, double gr, double gs) {
     if (!r.d_tex) return;
     const Bilin b = bilinear(u * r.tw - 0.5, v * r.th - 0.5, r.tw, r.th);
     const int idx[4] = {b.i00, b.i10, b.i01, b.i11};
     const double wt[4] = {b.w00, b.w10, b.w01, b.w11};
-#pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (wt[k] == 0.0) continue;
         float* t = r.d_tex + 5 * (size_t)idx[k];
@@ -40,6 +80,24 @@ __device__ __forceinline__ void scatter_tex(const ReqDesc& r, double u, double v
             atomicAdd(t + 3, (float)(gr * wt[k]));
             atomicAdd(t + 4, (float)(gs * wt[k]));
         }
+    }
+}
+
+// BRDF-map cotangents at texture coordinate (u, v) through the bilinear weights;
+// wave-uniform call (inactive lanes pass active = false)
+__device__ __forceinline__ void scatter_tex(const ReqDesc& r, bool active, double u, double v, D3 ga, double gr,
+                                            double gs) {
+    if (!r.d_tex) return;
+    Bilin b = bilinear(active ? u * r.tw - 0.5 : 0.0, active ? v * r.th - 0.5 : 0.0, r.tw, r.th);
+    const int idx[4] = {b.i00, b.i10, b.i01, b.i11};
+    const double wt[4] = {b.w00, b.w10, b.w01, b.w11};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float val[5] = {(float)(ga.x * wt[k]), (float)(ga.y * wt[k]), (float)(ga.z * wt[k]),
+                              (float)(gr * wt[k]), (float)(gs * wt[k])};
+        const bool on = active && wt[k] != 0.0;
+        if (r.brdf) wave_scatter_add<5>(on, idx[k], r.d_tex, 5, val);
+        else wave_scatter_add<3>(on, idx[k], r.d_tex, 5, val);
     }
 }
 
@@ -148,12 +206,17 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
         float4 po = {}, pd = {}, pc = {}, px = {}, pg = {}, pa = {};
         float4 eo = {}, ed = {}, ec = {}, ex = {}, ea = {};
         float ptmax = 0.f, ps = 0.f, es = 0.f;
+        bool pend_on = false;
+        double pend_u = 0.0, pend_v = 0.0, pend_gr = 0.0, pend_gs = 0.0;
+        D3 pend_ga = d3(0., 0., 0.);
+        const ReqDesc* rp = &sel<UNI>(uni, table, 0);
         if (i < n) {
             const PathO o = q.po[cur][i];
             const PathD dd = q.pd[cur][i];
             const float4 b = q.pb[cur][i];
             const int leaf = q.hit[i];
             const ReqDesc& r = sel<UNI>(uni, table, o.slot);
+            rp = &r;
             const uint32_t g = dd.g;
             const uint32_t sid = g - r.g_base + r.sid_base;
             const float4 dl = aq.delta[sid];
@@ -167,7 +230,12 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
                 if (penda.w >= 0.f) {
                     const D3 t = delta * d3(rl.x, rl.y, rl.z) * d3(penda.x, penda.y, penda.z);
                     const double sum = t.x + t.y + t.z;
-                    scatter_tex(r, pend.x, pend.y, t * (1.0 / PI), sum * pend.z, sum * pend.w);
+                    pend_on = true;
+                    pend_u = pend.x;
+                    pend_v = pend.y;
+                    pend_ga = t * (1.0 / PI);
+                    pend_gr = sum * pend.z;
+                    pend_gs = sum * pend.w;
                 }
                 if (r.emission) {
                     const float4 e = r.emission[leaf];
@@ -232,6 +300,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
                 }
             }
         }
+        if (UNI) scatter_tex(*rp, pend_on, pend_u, pend_v, pend_ga, pend_gr, pend_gs);
+        else if (pend_on) scatter_tex_lane(*rp, pend_u, pend_v, pend_ga, pend_gr, pend_gs);
         const uint32_t jn = wave_append(cont, &q.cnt[nxt]);
         if (cont) {
             q.po[nxt][jn] = no;
@@ -270,47 +340,74 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
 }
 
 // ---------------------------------------------------------------- shadows
-template <bool UNI, int STACK>
+template <bool UNI>
 __global__ void __launch_bounds__(TB) k_adj_shadow(Queues q, AdjQueues aq, int which, int nxt, ReqDesc uni,
                                                    const ReqDesc* __restrict__ table) {
-    __shared__ int stack[STACK * TB];
+    __shared__ int stack[SHORT_STACK * TB];
+    int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL + threadIdx.x;
     const uint32_t n = q.cnt[2 + which];
-    for (uint32_t i = blockIdx.x * TB + threadIdx.x; i < n; i += gridDim.x * TB) {
-        const float4 o = q.so[which][i], d = q.sd[which][i];
+    // the loop bound is uniform per workgroup so every lane reaches the wave-level scatter
+    for (uint32_t base = blockIdx.x * TB; base < n; base += gridDim.x * TB) {
+        const uint32_t i = base + threadIdx.x;
+        const bool live = i < n;
+        const uint32_t ii = live ? i : base;
+        const float4 o = q.so[which][ii], d = q.sd[which][ii];
         const ReqDesc& r = sel<UNI>(uni, table, __float_as_int(o.w));
-        Hit h;
-        Visits vis;
-        const bool occ = traverse<true, STACK, TB>(r.nodes, r.tris, xyz(o), xyz(d), r.tmin, q.st[which][i],
-                                                   __float_as_int(d.w), h, stack + threadIdx.x, vis);
-        if (q.stats) {
-            atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
-            atomicAdd(&q.stats[1], (unsigned long long)vis.tris);
+        bool occ = true;
+        if (live) {
+            Hit h;
+            Visits vis;
+            occ = traverse<true, SHORT_STACK, TB>(r.nodes, r.tris, xyz(o), xyz(d), r.tmin, q.st[which][i],
+                                                  __float_as_int(d.w), h, stack + threadIdx.x, spill, vis);
+            if (q.stats) {
+                atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
+                atomicAdd(&q.stats[1], (unsigned long long)vis.tris);
+            }
         }
-        if (occ) continue;
-        const float4 c = q.sc[which][i], x = aq.sx[which][i], a = aq.sa[which][i];
+        const float4 c = q.sc[which][ii], x = aq.sx[which][ii], a = aq.sa[which][ii];
+        const float sv = aq.ss[which][ii];
+        if (!occ) {
+            const int j = __float_as_int(c.w);
+            if (j >= 0) {
+                float4 rl = aq.rl[nxt][j];
+                rl.x -= c.x;
+                rl.y -= c.y;
+                rl.z -= c.z;
+                aq.rl[nxt][j] = rl;
+            }
+        }
+        if (!UNI) {   // paths of several requests: per-lane atomics
+            if (!occ) {
+                if (which == 0 && r.dEp) {
+                    const float4 gE = aq.sg[which][i];
+                    const Bilin b = bilinear((double)x.x - 0.5, (double)x.y - 0.5, r.Wp, r.Hp);
+                    const int idx[4] = {b.i00, b.i10, b.i01, b.i11};
+                    const double wt[4] = {b.w00, b.w10, b.w01, b.w11};
+                    for (int k = 0; k < 4; ++k) {
+                        if (wt[k] == 0.0) continue;
+                        float* t = r.dEp + 4 * (size_t)idx[k];
+                        atomicAdd(t + 0, (float)(gE.x * wt[k]));
+                        atomicAdd(t + 1, (float)(gE.y * wt[k]));
+                        atomicAdd(t + 2, (float)(gE.z * wt[k]));
+                    }
+                }
+                scatter_tex_lane(r, x.z, x.w, d3(a.x, a.y, a.z), a.w, sv);
+            }
+            continue;
+        }
+        // one request: lanes of one wave sum shared texels before the atomics
         if (which == 0 && r.dEp) {   // d/dE_p at the four projector texels
-            const float4 gE = aq.sg[which][i];
-            const Bilin b = bilinear((double)x.x - 0.5, (double)x.y - 0.5, r.Wp, r.Hp);
+            const float4 gE = aq.sg[which][ii];
+            const Bilin b = bilinear(occ ? 0.0 : (double)x.x - 0.5, occ ? 0.0 : (double)x.y - 0.5, r.Wp, r.Hp);
             const int idx[4] = {b.i00, b.i10, b.i01, b.i11};
             const double wt[4] = {b.w00, b.w10, b.w01, b.w11};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (wt[k] == 0.0) continue;
-                float* t = r.dEp + 4 * (size_t)idx[k];
-                atomicAdd(t + 0, (float)(gE.x * wt[k]));
-                atomicAdd(t + 1, (float)(gE.y * wt[k]));
-                atomicAdd(t + 2, (float)(gE.z * wt[k]));
+                const float val[3] = {(float)(gE.x * wt[k]), (float)(gE.y * wt[k]), (float)(gE.z * wt[k])};
+                wave_scatter_add<3>(!occ && wt[k] != 0.0, idx[k], r.dEp, 4, val);
             }
         }
-        scatter_tex(r, x.z, x.w, d3(a.x, a.y, a.z), a.w, aq.ss[which][i]);
-        const int j = __float_as_int(c.w);
-        if (j >= 0) {
-            float4 rl = aq.rl[nxt][j];
-            rl.x -= c.x;
-            rl.y -= c.y;
-            rl.z -= c.z;
-            aq.rl[nxt][j] = rl;
-        }
+        scatter_tex(r, !occ, x.z, x.w, d3(a.x, a.y, a.z), a.w, sv);
     }
 }
 
@@ -410,15 +507,10 @@ void launch_adj_shade(const Launch& l, const Queues& q, const AdjQueues& aq, int
     else hipLaunchKernelGGL((k_adj_shade<true>), g, b, 0, l.st, q, aq, cur, depth, uni, table);
 }
 void launch_adj_shadow(const Launch& l, const Queues& q, const AdjQueues& aq, int which, int nxt, const ReqDesc& uni,
-                       const ReqDesc* table, int64_t n_upper, int stack) {
+                       const ReqDesc* table, int64_t n_upper, int) {
     const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
-    if (table) {
-        if (stack <= 32) hipLaunchKernelGGL((k_adj_shadow<false, 32>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
-        else hipLaunchKernelGGL((k_adj_shadow<false, 64>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
-    } else {
-        if (stack <= 32) hipLaunchKernelGGL((k_adj_shadow<true, 32>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
-        else hipLaunchKernelGGL((k_adj_shadow<true, 64>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
-    }
+    if (table) hipLaunchKernelGGL((k_adj_shadow<false>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
+    else hipLaunchKernelGGL((k_adj_shadow<true>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
 }
 void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* d_albedo, float* d_rough,
                        float* d_spec, float* d_scalars, float* acc) {

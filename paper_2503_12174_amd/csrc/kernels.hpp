@@ -52,7 +52,13 @@ struct Queues {
     uint32_t* cnt;     // [0], [1] path queue sizes, [2], [3] shadow queue sizes
     int64_t cap;       // path capacity
     unsigned long long* stats;   // null, or [0] nodes visited, [1] triangles tested (profiling)
+    int* spill;        // traversal stack overflow: SPILL ints per thread of a capped grid
 };
+
+constexpr int SHORT_STACK = 8;                 // LDS stack entries per thread
+constexpr int SPILL = 64 - SHORT_STACK;        // overflow entries per thread
+constexpr int TRACE_TB = 128;                  // threads per workgroup of the traversal kernels
+inline size_t spill_ints(int grid_cap) { return (size_t)grid_cap * TRACE_TB * SPILL; }
 
 // adjoint additions (see adjoint.hip)
 struct AdjQueues {

@@ -16,7 +16,7 @@
 
 namespace dpcs {
 
-constexpr int TB = 128;   // threads per workgroup of the traversal kernels
+constexpr int TB = TRACE_TB;
 
 // ---------------------------------------------------------------- per texel
 // Eq. 1 with colour mixing: E_p = max(0, g_p M max(I_p, 0)^gamma_p)
@@ -76,9 +76,10 @@ __global__ void k_raygen(Queues q, ReqDesc r, int slot, uint32_t g0, uint32_t n)
 }
 
 // ---------------------------------------------------------------- closest hit
-template <bool UNI, int STACK>
+template <bool UNI>
 __global__ void __launch_bounds__(TB) k_trace(Queues q, int cur, ReqDesc uni, const ReqDesc* __restrict__ table) {
-    __shared__ int stack[STACK * TB];
+    __shared__ int stack[SHORT_STACK * TB];
+    int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL + threadIdx.x;
     const uint32_t n = q.cnt[cur];
     for (uint32_t i = blockIdx.x * TB + threadIdx.x; i < n; i += gridDim.x * TB) {
         const PathO o = q.po[cur][i];
@@ -86,9 +87,9 @@ __global__ void __launch_bounds__(TB) k_trace(Queues q, int cur, ReqDesc uni, co
         const ReqDesc& r = sel<UNI>(uni, table, o.slot);
         Hit h;
         Visits vis;
-        traverse<false, STACK, TB>(r.nodes, r.tris, v3((float)o.x, (float)o.y, (float)o.z),
-                                   v3((float)d.x, (float)d.y, (float)d.z), r.tmin, __builtin_inff(), o.skip, h,
-                                   stack + threadIdx.x, vis);
+        traverse<false, SHORT_STACK, TB>(r.nodes, r.tris, v3((float)o.x, (float)o.y, (float)o.z),
+                                         v3((float)d.x, (float)d.y, (float)d.z), r.tmin, __builtin_inff(), o.skip,
+                                         h, stack + threadIdx.x, spill, vis);
         q.hit[i] = h.leaf;
         if (q.stats) {
             atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
@@ -204,17 +205,18 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
 }
 
 // ---------------------------------------------------------------- shadows
-template <bool UNI, int STACK>
+template <bool UNI>
 __global__ void __launch_bounds__(TB) k_shadow(Queues q, int which, ReqDesc uni, const ReqDesc* __restrict__ table) {
-    __shared__ int stack[STACK * TB];
+    __shared__ int stack[SHORT_STACK * TB];
+    int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL + threadIdx.x;
     const uint32_t n = q.cnt[2 + which];
     for (uint32_t i = blockIdx.x * TB + threadIdx.x; i < n; i += gridDim.x * TB) {
         const float4 o = q.so[which][i], d = q.sd[which][i];
         const ReqDesc& r = sel<UNI>(uni, table, __float_as_int(o.w));
         Hit h;
         Visits vis;
-        const bool occ = traverse<true, STACK, TB>(r.nodes, r.tris, xyz(o), xyz(d), r.tmin, q.st[which][i],
-                                                   __float_as_int(d.w), h, stack + threadIdx.x, vis);
+        const bool occ = traverse<true, SHORT_STACK, TB>(r.nodes, r.tris, xyz(o), xyz(d), r.tmin, q.st[which][i],
+                                                         __float_as_int(d.w), h, stack + threadIdx.x, spill, vis);
         if (q.stats) {
             atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
             atomicAdd(&q.stats[1], (unsigned long long)vis.tris);
@@ -259,13 +261,13 @@ __global__ void k_finalize(Queues q, ReqDesc r, uint32_t p0, uint32_t p1) {
 }
 
 // ---------------------------------------------------------------- debug
-template <int STACK>
+// full 64-entry LDS stack (no spill region needed: depth <= 64 is checked on the host)
 __global__ void __launch_bounds__(TB) k_debug_intersect(const float4* __restrict__ nodes,
                                                         const float4* __restrict__ tris,
                                                         const int* __restrict__ leaf_of_prim, int nt, float tmin,
                                                         const float* __restrict__ rays, int64_t n, int use_bvh,
                                                         int32_t* prim, float* t, float* b1, float* b2) {
-    __shared__ int stack[STACK * TB];
+    __shared__ int stack[MAX_STACK * TB];
     const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (i >= n) return;
     const float* ry = rays + 8 * i;
@@ -273,7 +275,8 @@ __global__ void __launch_bounds__(TB) k_debug_intersect(const float4* __restrict
     Hit h;
     Visits vis;
     if (use_bvh)
-        traverse<false, STACK, TB>(nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, stack + threadIdx.x, vis);
+        traverse<false, MAX_STACK, TB>(nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, stack + threadIdx.x, nullptr,
+                                       vis);
     else
         brute_force<false>(tris, leaf_of_prim, nt, o, d, tmin, ry[6], (int)ry[7], h);
     prim[i] = h.prim;
@@ -321,15 +324,10 @@ void launch_raygen(const Launch& l, const Queues& q, const ReqDesc& r, const Req
     if (n) hipLaunchKernelGGL(k_raygen, dim3(grid_of(n, 256)), dim3(256), 0, l.st, q, r, slot, g0, n);
 }
 void launch_trace(const Launch& l, const Queues& q, int cur, const ReqDesc& uni, const ReqDesc* table,
-                  int64_t n_upper, int stack) {
+                  int64_t n_upper, int) {
     const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
-    if (table) {
-        if (stack <= 32) hipLaunchKernelGGL((k_trace<false, 32>), g, b, 0, l.st, q, cur, uni, table);
-        else hipLaunchKernelGGL((k_trace<false, 64>), g, b, 0, l.st, q, cur, uni, table);
-    } else {
-        if (stack <= 32) hipLaunchKernelGGL((k_trace<true, 32>), g, b, 0, l.st, q, cur, uni, table);
-        else hipLaunchKernelGGL((k_trace<true, 64>), g, b, 0, l.st, q, cur, uni, table);
-    }
+    if (table) hipLaunchKernelGGL((k_trace<false>), g, b, 0, l.st, q, cur, uni, table);
+    else hipLaunchKernelGGL((k_trace<true>), g, b, 0, l.st, q, cur, uni, table);
 }
 void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const ReqDesc& uni, const ReqDesc* table,
                   int64_t n_upper) {
@@ -338,15 +336,10 @@ void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const Re
     else hipLaunchKernelGGL((k_shade<true>), g, b, 0, l.st, q, cur, depth, uni, table);
 }
 void launch_shadow(const Launch& l, const Queues& q, int which, const ReqDesc& uni, const ReqDesc* table,
-                   int64_t n_upper, int stack) {
+                   int64_t n_upper, int) {
     const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
-    if (table) {
-        if (stack <= 32) hipLaunchKernelGGL((k_shadow<false, 32>), g, b, 0, l.st, q, which, uni, table);
-        else hipLaunchKernelGGL((k_shadow<false, 64>), g, b, 0, l.st, q, which, uni, table);
-    } else {
-        if (stack <= 32) hipLaunchKernelGGL((k_shadow<true, 32>), g, b, 0, l.st, q, which, uni, table);
-        else hipLaunchKernelGGL((k_shadow<true, 64>), g, b, 0, l.st, q, which, uni, table);
-    }
+    if (table) hipLaunchKernelGGL((k_shadow<false>), g, b, 0, l.st, q, which, uni, table);
+    else hipLaunchKernelGGL((k_shadow<true>), g, b, 0, l.st, q, which, uni, table);
 }
 void launch_finalize(const Launch& l, const Queues& q, const ReqDesc& r, const ReqDesc*, int, uint32_t p0,
                      uint32_t p1) {
@@ -356,12 +349,8 @@ void launch_debug_intersect(const Launch& l, const float4* nodes, const float4* 
                             float tmin, const float* rays, int64_t n, int use_bvh, int stack, int32_t* prim,
                             float* t, float* b1, float* b2) {
     if (n <= 0) return;
-    if (stack <= 32)
-        hipLaunchKernelGGL(k_debug_intersect<32>, dim3(grid_of(n, TB)), dim3(TB), 0, l.st, nodes, tris, leaf_of_prim,
-                           nt, tmin, rays, n, use_bvh, prim, t, b1, b2);
-    else
-        hipLaunchKernelGGL(k_debug_intersect<64>, dim3(grid_of(n, TB)), dim3(TB), 0, l.st, nodes, tris, leaf_of_prim,
-                           nt, tmin, rays, n, use_bvh, prim, t, b1, b2);
+    hipLaunchKernelGGL(k_debug_intersect, dim3(grid_of(n, TB)), dim3(TB), 0, l.st, nodes, tris, leaf_of_prim, nt, tmin,
+                       rays, n, use_bvh, prim, t, b1, b2);
 }
 void launch_debug_philox(const Launch& l, uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out) {
     if (n > 0)

@@ -340,7 +340,7 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     const int64_t fit = (int64_t)(memory_budget_bytes / 4 / per_path);
     s->cap = std::max<int64_t>(1024, std::min<int64_t>({ctx->capacity, int64_t(1) << 22, fit}));
     const size_t c = (size_t)s->cap;
-    const size_t qbytes = c * per_path + 2 * 4096 + 64 * 256;
+    const size_t qbytes = c * per_path + 2 * 4096 + 64 * 256 + 4 * spill_ints(ctx->grid_cap);
     s->shared_bytes = qbytes + sizeof(ReqDesc) * (size_t)max_slots;
     if (s->shared_bytes >= s->budget) {
         delete s;
@@ -387,6 +387,7 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     s->q.L = (float4*)take(16 * c);
     s->aq.delta = (float4*)take(16 * c);
     s->q.cnt = (uint32_t*)take(16);
+    s->q.spill = (int*)take(4 * spill_ints(ctx->grid_cap));
     s->q.cap = s->cap;
     s->q.stats = nullptr;
     for (int k = max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);

@@ -107,15 +107,20 @@ __device__ __forceinline__ void load_tri(const float4* __restrict__ tris, int le
     prim = __float_as_int(a.w);
 }
 
-// Stack of internal node indices lives in LDS: entry k of thread tid at stack[k * TBK + tid],
-// TBK = threads per workgroup (consecutive lanes hit consecutive banks).
+// Traversal stack of internal node indices: the first SHORT entries live in LDS
+// (entry k of thread tid at lds[k * TBK + tid], consecutive lanes on consecutive banks);
+// deeper entries -- rare with near-child-first order -- go to the workgroup's region of
+// global memory with the same interleaving (spill[k * TBK + tid]).  The host only
+// launches on trees of depth <= 64, so at most 64 entries are ever live.
+constexpr int MAX_STACK = 64;
 struct Visits {
     uint32_t nodes = 0, tris = 0;
 };
 
-template <bool ANY, int STACK, int TBK>
+template <bool ANY, int SHORT, int TBK>
 __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const float4* __restrict__ tris, V3 o, V3 d,
-                                         float tmin, float tmax, int skip, Hit& h, int* stack, Visits& vis) {
+                                         float tmin, float tmax, int skip, Hit& h, int* stack, int* spill,
+                                         Visits& vis) {
     const BoxRay br = box_setup(o, d);
     const WtRay wr = wt_setup(o, d);
     float best_t = tmax;
@@ -164,11 +169,12 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
         const bool h1 = c1 >= 0 && t1 < __builtin_inff() && t1 <= best_t;
         if (h0 && h1) {
             const bool first0 = t0 <= t1;
-            // the host only launches on trees with depth < STACK, so this never drops
-            if (sp < STACK) {
-                stack[sp * TBK] = first0 ? c1 : c0;
-                ++sp;
+            const int far = first0 ? c1 : c0;
+            if (sp < SHORT) stack[sp * TBK] = far;
+            else if constexpr (SHORT < MAX_STACK) {
+                if (sp < MAX_STACK) spill[(sp - SHORT) * TBK] = far;
             }
+            sp = sp < MAX_STACK ? sp + 1 : sp;   // depth <= 64 is checked on the host
             node = first0 ? c0 : c1;
         } else if (h0) {
             node = c0;
@@ -177,7 +183,8 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
         } else {
             if (sp == 0) break;
             --sp;
-            node = stack[sp * TBK];
+            if constexpr (SHORT < MAX_STACK) node = sp < SHORT ? stack[sp * TBK] : spill[(sp - SHORT) * TBK];
+            else node = stack[sp * TBK];
         }
     }
     h.t = best_t;
