@@ -138,9 +138,10 @@ def serving_bench(ctx, n_req, n_alone, warmup=20, rate=50.0):
             dpcs.dpcs_render(ctx, sc, p, ip, out)
         else:
             L = torch.empty((rq["res"], rq["res"], rq["spp"], 3), device="cuda")
-            dpcs.dpcs_render(ctx, sc, p, ip, out, sample_radiance=L)
+            rc = torch.empty((rq["res"], rq["res"], rq["spp"], p.max_depth), dtype=torch.int32, device="cuda")
+            dpcs.dpcs_render(ctx, sc, p, ip, out, sample_radiance=L, path_records=rc)
             G = (2.0 * (out - target) / out.numel()).contiguous()
-            dpcs.dpcs_render_vjp(ctx, sc, p, ip, G, sample_radiance=L, **grads)
+            dpcs.dpcs_render_vjp(ctx, sc, p, ip, G, sample_radiance=L, path_records=rc, **grads)
         ctx.synchronize()
         alone.append((time.perf_counter() - ta) * 1e3)
     offered = sum(x[-1] * (2 if x[1]["compensation"] else 1) for x in prep) / reqs[-1]["arrival"]
@@ -180,6 +181,7 @@ def main():
     H, W = w.camera.height, w.camera.width
     out = torch.zeros((H, W, 3), device="cuda")
     Ls = torch.zeros((H, W, w.spp, 3), device="cuda")
+    rec = torch.zeros((H, W, w.spp, w.max_depth), dtype=torch.int32, device="cuda")
     G = torch.as_tensor(np.random.default_rng(7).normal(size=(H, W, 3)).astype(np.float32)).cuda()
     grads = dict(d_proj_image=torch.zeros_like(proj), d_albedo=torch.zeros_like(alb),
                  d_roughness=torch.zeros_like(rough), d_specular=torch.zeros_like(spec),
@@ -189,9 +191,9 @@ def main():
     def fwd():
         dpcs.dpcs_render(ctx, scene, params, proj, out)
 
-    def step():   # the whole path: forward (keeping per-sample radiance) + VJP by path replay
-        dpcs.dpcs_render(ctx, scene, params, proj, out, sample_radiance=Ls)
-        dpcs.dpcs_render_vjp(ctx, scene, params, proj, G, sample_radiance=Ls, **grads)
+    def step():   # the whole path: forward (keeping per-sample radiance and path records) + VJP by replay
+        dpcs.dpcs_render(ctx, scene, params, proj, out, sample_radiance=Ls, path_records=rec)
+        dpcs.dpcs_render_vjp(ctx, scene, params, proj, G, sample_radiance=Ls, path_records=rec, **grads)
 
     def timed(fn, k):
         for _ in range(a.warmup):

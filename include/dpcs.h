@@ -150,6 +150,12 @@ typedef struct {
     float* sample_radiance;     /* Hc x Wc x spp x 3: unclipped radiance of every camera sample */
     int32_t* hit_prims;         /* Hc x Wc x spp x max_depth: triangle hit per vertex,
                                    -1 escaped, -2 path ended earlier */
+    uint32_t* path_records;     /* Hc x Wc x spp x max_depth: opaque replay records for
+                                   dpcs_render_vjp (which leaf each vertex hit, which of its
+                                   shadow rays were unoccluded); words past a path's end are
+                                   left as they were.  4 bytes per (sample, depth).  Setting
+                                   it makes the forward trace shadow rays whose contribution
+                                   is zero too (their visibility carries gradient). */
 } dpcs_render_aux;
 
 /* I_c = R(I_p, theta) (Eq. 7).  proj_image: Hp x Wp x 3, out_image: Hc x Wc x 3. */
@@ -168,11 +174,19 @@ typedef struct {
 /* Vector-Jacobian product of dpcs_render at the same params (same seed: the same
  * sample paths are replayed): given grad_image = dLoss/dI_c (Hc x Wc x 3), writes
  * dLoss/d{I_p, albedo, roughness, specular, gamma_p, M, gamma_c, w} (Eq. 9, 13).
- * sample_radiance (optional) is the aux output of the forward call with the same
- * params; when NULL the forward samples are recomputed. */
+ * sample_radiance and path_records (optional) are aux outputs of a forward call with
+ * the same scene, params and proj_image:
+ *   both NULL           the forward samples and their path records are recomputed
+ *                       here, wave by wave (scratch: 4 B x spp x max_depth per pixel
+ *                       of a wave), then replayed without tracing;
+ *   both given          replay from the caller's records, no tracing;
+ *   sample_radiance     replay that traces every bounce and shadow ray again.
+ *   only
+ * path_records without sample_radiance is DPCS_E_INVALID. */
 DPCS_API dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
                             const float* proj_image, const float* grad_image,
-                            const float* sample_radiance, const dpcs_grads* grads);
+                            const float* sample_radiance, const uint32_t* path_records,
+                            const dpcs_grads* grads);
 
 /* ------------------------------------------------------------ debug/test */
 

@@ -1,7 +1,8 @@
 """torch.autograd.Function over dpcs_render / dpcs_render_vjp (argument marshalling only).
 
-Forward keeps each camera sample's radiance so backward replays the same Philox
-paths without recomputing the forward samples.  Differentiable inputs: projector
+Forward keeps each camera sample's radiance and the path records (hit leaf and
+shadow visibility per vertex, 4 B) so backward replays the same Philox paths
+without recomputing the forward samples or tracing.  Differentiable inputs: projector
 image, albedo, roughness, specular maps and the 18 response scalars
 (gamma_p[3], M[9], gamma_c[3], w[3]) as one device tensor.
 """
@@ -28,21 +29,22 @@ class DPCSRender(torch.autograd.Function):
         H, W = p.camera.height, p.camera.width
         out = torch.empty((H, W, 3), dtype=torch.float32, device=proj_image.device)
         L = torch.empty((H, W, p.spp, 3), dtype=torch.float32, device=proj_image.device)
-        dpcs.dpcs_render(ctx, scene, p, proj_image, out, sample_radiance=L)
-        fctx.save_for_backward(proj_image, albedo, roughness, specular, scalars, L)
+        rec = torch.empty((H, W, p.spp, p.max_depth), dtype=torch.int32, device=proj_image.device)
+        dpcs.dpcs_render(ctx, scene, p, proj_image, out, sample_radiance=L, path_records=rec)
+        fctx.save_for_backward(proj_image, albedo, roughness, specular, scalars, L, rec)
         fctx.ctx, fctx.scene, fctx.cfg = ctx, scene, cfg
         return out
 
     @staticmethod
     def backward(fctx, grad_out):
-        proj_image, albedo, roughness, specular, scalars, L = fctx.saved_tensors
+        proj_image, albedo, roughness, specular, scalars, L, rec = fctx.saved_tensors
         p = dpcs.params_from(fctx.cfg, albedo, roughness, specular, device_scalars=scalars)
         need = fctx.needs_input_grad
         z = lambda t, k: torch.empty_like(t) if need[k] else None
         d_proj, d_alb, d_rough, d_spec = z(proj_image, 0), z(albedo, 1), z(roughness, 2), z(specular, 3)
         d_scal = torch.empty_like(scalars) if need[4] else None
         dpcs.dpcs_render_vjp(fctx.ctx, fctx.scene, p, proj_image, grad_out.contiguous(), sample_radiance=L,
-                             d_proj_image=d_proj, d_albedo=d_alb, d_roughness=d_rough, d_specular=d_spec,
+                             path_records=rec, d_proj_image=d_proj, d_albedo=d_alb, d_roughness=d_rough, d_specular=d_spec,
                              d_scalars=d_scal)
         return d_proj, d_alb, d_rough, d_spec, d_scal, None, None, None
 

@@ -16,6 +16,8 @@
 //               emits next-event shadow rays with their gradient payloads, bounces
 //   adj_shadow  visible: scatter dE_p and BRDF-map cotangents, subtract the
 //               contribution from the path's remaining radiance
+//   adj_replay  with the forward's path records: adj_shade and adj_shadow in one pass,
+//               visibility and hit leaf read from the records instead of traced
 //   adj_finish  PRF backward (Eq. 1) per texel and the scalar reductions
 #include "kernels.hpp"
 #include "shade.hpp"
@@ -64,40 +66,60 @@ __device__ __forceinline__ void wave_scatter_add(bool active, int idx, float* ba
     }
 }
 
-// per-lane form (no wave-level cooperation)
-__device__ __forceinline__ void scatter_tex_lane(const ReqDesc& r, double u, double v, D3 ga, double gr, double gs) {
+// BRDF-map cotangents g = (albedo rgb, roughness, specular) at texture coordinate
+// (u, v), spread over the four texels of the bilinear lookup.  Per-lane form:
+__device__ __forceinline__ void scatter_tex_lane(const ReqDesc& r, double u, double v, const float* gv) {
     if (!r.d_tex) return;
     const Bilin b = bilinear(u * r.tw - 0.5, v * r.th - 0.5, r.tw, r.th);
     const int idx[4] = {b.i00, b.i10, b.i01, b.i11};
     const double wt[4] = {b.w00, b.w10, b.w01, b.w11};
+    const int nc = r.brdf ? 5 : 3;
     for (int k = 0; k < 4; ++k) {
         if (wt[k] == 0.0) continue;
         float* t = r.d_tex + 5 * (size_t)idx[k];
-        atomicAdd(t + 0, (float)(ga.x * wt[k]));
-        atomicAdd(t + 1, (float)(ga.y * wt[k]));
-        atomicAdd(t + 2, (float)(ga.z * wt[k]));
-        if (r.brdf) {
-            atomicAdd(t + 3, (float)(gr * wt[k]));
-            atomicAdd(t + 4, (float)(gs * wt[k]));
+        for (int j = 0; j < nc; ++j) {
+            const float val = (float)(gv[j] * wt[k]);
+            if (val != 0.0f) atomicAdd(t + j, val);
         }
     }
 }
 
-// BRDF-map cotangents at texture coordinate (u, v) through the bilinear weights;
-// wave-uniform call (inactive lanes pass active = false)
-__device__ __forceinline__ void scatter_tex(const ReqDesc& r, bool active, double u, double v, D3 ga, double gr,
-                                            double gs) {
+// wave-uniform form (inactive lanes pass active = false)
+__device__ __forceinline__ void scatter_tex(const ReqDesc& r, bool active, double u, double v, const float* gv) {
     if (!r.d_tex) return;
     Bilin b = bilinear(active ? u * r.tw - 0.5 : 0.0, active ? v * r.th - 0.5 : 0.0, r.tw, r.th);
     const int idx[4] = {b.i00, b.i10, b.i01, b.i11};
     const double wt[4] = {b.w00, b.w10, b.w01, b.w11};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const float val[5] = {(float)(ga.x * wt[k]), (float)(ga.y * wt[k]), (float)(ga.z * wt[k]),
-                              (float)(gr * wt[k]), (float)(gs * wt[k])};
+        const float val[5] = {(float)(gv[0] * wt[k]), (float)(gv[1] * wt[k]), (float)(gv[2] * wt[k]),
+                              (float)(gv[3] * wt[k]), (float)(gv[4] * wt[k])};
         const bool on = active && wt[k] != 0.0;
         if (r.brdf) wave_scatter_add<5>(on, idx[k], r.d_tex, 5, val);
         else wave_scatter_add<3>(on, idx[k], r.d_tex, 5, val);
+    }
+}
+
+// cotangent of E_p (rgb per texel, stride 4) at projector pixel position (pu, pv)
+__device__ __forceinline__ void scatter_ep_lane(const ReqDesc& r, double pu, double pv, const float* gE) {
+    const Bilin b = bilinear(pu - 0.5, pv - 0.5, r.Wp, r.Hp);
+    const int idx[4] = {b.i00, b.i10, b.i01, b.i11};
+    const double wt[4] = {b.w00, b.w10, b.w01, b.w11};
+    for (int k = 0; k < 4; ++k) {
+        if (wt[k] == 0.0) continue;
+        float* t = r.dEp + 4 * (size_t)idx[k];
+        for (int j = 0; j < 3; ++j) atomicAdd(t + j, (float)(gE[j] * wt[k]));
+    }
+}
+
+__device__ __forceinline__ void scatter_ep(const ReqDesc& r, bool active, double pu, double pv, const float* gE) {
+    const Bilin b = bilinear(active ? pu - 0.5 : 0.0, active ? pv - 0.5 : 0.0, r.Wp, r.Hp);
+    const int idx[4] = {b.i00, b.i10, b.i01, b.i11};
+    const double wt[4] = {b.w00, b.w10, b.w01, b.w11};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float val[3] = {(float)(gE[0] * wt[k]), (float)(gE[1] * wt[k]), (float)(gE[2] * wt[k])};
+        wave_scatter_add<3>(active && wt[k] != 0.0, idx[k], r.dEp, 4, val);
     }
 }
 
@@ -189,6 +211,8 @@ __global__ void k_adj_raygen(Queues q, AdjQueues aq, ReqDesc r, int slot, uint32
     aq.rl[0][sid] = q.L[sid];
     aq.pend[0][sid] = make_float4(0.f, 0.f, 0.f, 0.f);
     aq.penda[0][sid] = make_float4(0.f, 0.f, 0.f, -1.f);   // w < 0: no pending bounce
+    aq.pn[0][sid] = make_float4(0.f, 0.f, 0.f, 0.f);
+    aq.pns[0][sid] = 0.f;
 }
 
 // ---------------------------------------------------------------- shading
@@ -207,8 +231,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
         float4 eo = {}, ed = {}, ec = {}, ex = {}, ea = {};
         float ptmax = 0.f, ps = 0.f, es = 0.f;
         bool pend_on = false;
-        double pend_u = 0.0, pend_v = 0.0, pend_gr = 0.0, pend_gs = 0.0;
-        D3 pend_ga = d3(0., 0., 0.);
+        double pend_u = 0.0, pend_v = 0.0;
+        float pend_g[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
         const ReqDesc* rp = &sel<UNI>(uni, table, 0);
         if (i < n) {
             const PathO o = q.po[cur][i];
@@ -233,9 +257,11 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
                     pend_on = true;
                     pend_u = pend.x;
                     pend_v = pend.y;
-                    pend_ga = t * (1.0 / PI);
-                    pend_gr = sum * pend.z;
-                    pend_gs = sum * pend.w;
+                    pend_g[0] = (float)(t.x * (1.0 / PI));
+                    pend_g[1] = (float)(t.y * (1.0 / PI));
+                    pend_g[2] = (float)(t.z * (1.0 / PI));
+                    pend_g[3] = (float)(sum * pend.z);
+                    pend_g[4] = (float)(sum * pend.w);
                 }
                 if (r.emission) {
                     const float4 e = r.emission[leaf];
@@ -300,8 +326,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
                 }
             }
         }
-        if (UNI) scatter_tex(*rp, pend_on, pend_u, pend_v, pend_ga, pend_gr, pend_gs);
-        else if (pend_on) scatter_tex_lane(*rp, pend_u, pend_v, pend_ga, pend_gr, pend_gs);
+        if (UNI) scatter_tex(*rp, pend_on, pend_u, pend_v, pend_g);
+        else if (pend_on) scatter_tex_lane(*rp, pend_u, pend_v, pend_g);
         const uint32_t jn = wave_append(cont, &q.cnt[nxt]);
         if (cont) {
             q.po[nxt][jn] = no;
@@ -376,38 +402,193 @@ __global__ void __launch_bounds__(TB) k_adj_shadow(Queues q, AdjQueues aq, int w
                 aq.rl[nxt][j] = rl;
             }
         }
+        const float gt[5] = {a.x, a.y, a.z, a.w, sv};
         if (!UNI) {   // paths of several requests: per-lane atomics
             if (!occ) {
                 if (which == 0 && r.dEp) {
                     const float4 gE = aq.sg[which][i];
-                    const Bilin b = bilinear((double)x.x - 0.5, (double)x.y - 0.5, r.Wp, r.Hp);
-                    const int idx[4] = {b.i00, b.i10, b.i01, b.i11};
-                    const double wt[4] = {b.w00, b.w10, b.w01, b.w11};
-                    for (int k = 0; k < 4; ++k) {
-                        if (wt[k] == 0.0) continue;
-                        float* t = r.dEp + 4 * (size_t)idx[k];
-                        atomicAdd(t + 0, (float)(gE.x * wt[k]));
-                        atomicAdd(t + 1, (float)(gE.y * wt[k]));
-                        atomicAdd(t + 2, (float)(gE.z * wt[k]));
-                    }
+                    const float ge[3] = {gE.x, gE.y, gE.z};
+                    scatter_ep_lane(r, x.x, x.y, ge);
                 }
-                scatter_tex_lane(r, x.z, x.w, d3(a.x, a.y, a.z), a.w, sv);
+                scatter_tex_lane(r, x.z, x.w, gt);
             }
             continue;
         }
         // one request: lanes of one wave sum shared texels before the atomics
         if (which == 0 && r.dEp) {   // d/dE_p at the four projector texels
             const float4 gE = aq.sg[which][ii];
-            const Bilin b = bilinear(occ ? 0.0 : (double)x.x - 0.5, occ ? 0.0 : (double)x.y - 0.5, r.Wp, r.Hp);
-            const int idx[4] = {b.i00, b.i10, b.i01, b.i11};
-            const double wt[4] = {b.w00, b.w10, b.w01, b.w11};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float val[3] = {(float)(gE.x * wt[k]), (float)(gE.y * wt[k]), (float)(gE.z * wt[k])};
-                wave_scatter_add<3>(!occ && wt[k] != 0.0, idx[k], r.dEp, 4, val);
+            const float ge[3] = {gE.x, gE.y, gE.z};
+            scatter_ep(r, !occ, x.x, x.y, ge);
+        }
+        scatter_tex(r, !occ, x.z, x.w, gt);
+    }
+}
+
+// ---------------------------------------------------------------- replay from records
+// One bounce of the replay when the forward kept its path records: the vertex's leaf and
+// the visibility of its shadow rays are read instead of traced.  Shading, the
+// next-event terms and the bounce are re-evaluated with the forward's Philox counters.
+// The next-event cotangents on the BRDF maps at this vertex travel with the path and
+// are added to its bounce derivative when that is settled at the next vertex, so each
+// vertex scatters into the maps once (twice where the path ends).
+template <bool UNI>
+__global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, int cur, int depth, ReqDesc uni,
+                                                      const ReqDesc* __restrict__ table) {
+    const int nxt = cur ^ 1;
+    const uint32_t n = q.cnt[cur];
+    for (uint32_t base = blockIdx.x * BLOCK; base < n; base += gridDim.x * BLOCK) {
+        const uint32_t i = base + threadIdx.x;
+        bool cont = false;
+        PathO no{};
+        PathD nd{};
+        float4 nb = {}, nrl = {}, npend = {}, npenda = {}, npn = {};
+        float npns = 0.f;
+        // map cotangents of the previous vertex (a) and of this one when the path ends here (b)
+        bool a_on = false, b_on = false, e_on = false;
+        float a_u = 0.f, a_v = 0.f, b_u = 0.f, b_v = 0.f;
+        float ag[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, bg[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        // E_p cotangent of this vertex's projector term
+        double e_pu = 0.0, e_pv = 0.0;
+        float eg[3] = {0.f, 0.f, 0.f};
+        const ReqDesc* rp = &sel<UNI>(uni, table, 0);
+        if (i < n) {
+            const PathO o = q.po[cur][i];
+            const PathD dd = q.pd[cur][i];
+            const float4 b = q.pb[cur][i];
+            const ReqDesc& r = sel<UNI>(uni, table, o.slot);
+            rp = &r;
+            const uint32_t g = dd.g;
+            const uint32_t sid = g - r.g_base + r.sid_base;
+            const uint32_t rec = r.rec[(size_t)(g - r.rec_g0) * r.max_depth + depth];
+            const int leaf = (int)(rec & REC_LEAF) - 1;
+            const float4 dl = aq.delta[sid];
+            const D3 delta = d3(dl.x, dl.y, dl.z);
+            const D3 beta = d3(b.x, b.y, b.z);
+            float4 rl = aq.rl[cur][i];
+            const float4 penda = aq.penda[cur][i];
+            if (penda.w >= 0.f) {
+                // previous vertex: its next-event cotangents plus d/df of its bounce,
+                // beta_k f cos/pdf R_{k+1} -> R_{k+1} / f (zero when this ray escaped)
+                const float4 pend = aq.pend[cur][i], pn = aq.pn[cur][i];
+                const float pns = aq.pns[cur][i];
+                a_on = true;
+                a_u = pend.x;
+                a_v = pend.y;
+                double ga0 = pn.x, ga1 = pn.y, ga2 = pn.z, gr = pn.w, gs = pns;
+                if (leaf >= 0) {
+                    const D3 t = delta * d3(rl.x, rl.y, rl.z) * d3(penda.x, penda.y, penda.z);
+                    const double sum = t.x + t.y + t.z;
+                    ga0 += t.x * (1.0 / PI);
+                    ga1 += t.y * (1.0 / PI);
+                    ga2 += t.z * (1.0 / PI);
+                    gr += sum * pend.z;
+                    gs += sum * pend.w;
+                }
+                ag[0] = (float)ga0;
+                ag[1] = (float)ga1;
+                ag[2] = (float)ga2;
+                ag[3] = (float)gr;
+                ag[4] = (float)gs;
+            }
+            if (leaf >= 0) {
+                const Surf s = surface(r, leaf, d3(o.x, o.y, o.z), d3(dd.x, dd.y, dd.z));
+                if (r.emission) {
+                    const float4 e = r.emission[leaf];
+                    rl.x -= (float)(beta.x * e.x);
+                    rl.y -= (float)(beta.y * e.y);
+                    rl.z -= (float)(beta.z * e.z);
+                }
+                const D3 db = delta * beta;
+                D3 nga = d3(0., 0., 0.);
+                double ngr = 0.0, ngs = 0.0;
+                ProjNee p;
+                if ((rec & REC_PRJ) && projector_nee(r, s, p)) {
+                    const D4 E = fetch4(r.Ep, p.pb);
+                    const Brdf f = brdf_eval<true>(r.brdf, s.n, s.wo, p.wp, s.alb, s.rough, s.spec);
+                    const D3 Ex = d3(E.x, E.y, E.z) * p.geom;
+                    const D3 C = beta * f.f * Ex;
+                    const D3 gE = db * f.f * p.geom;   // d/dE_p before the bilinear weights
+                    const double sx = db.x * Ex.x + db.y * Ex.y + db.z * Ex.z;
+                    e_on = r.dEp != nullptr;
+                    e_pu = p.pu;
+                    e_pv = p.pv;
+                    eg[0] = (float)gE.x;
+                    eg[1] = (float)gE.y;
+                    eg[2] = (float)gE.z;
+                    nga = nga + db * Ex * (1.0 / PI);
+                    ngr += sx * f.ds_dr;
+                    ngs += sx * f.ds_dsp;
+                    rl.x -= (float)C.x;
+                    rl.y -= (float)C.y;
+                    rl.z -= (float)C.z;
+                }
+                if (r.env_on && (rec & REC_ENV)) {
+                    const U4 x = vertex_rng(r, g, 2u + 2u * depth);
+                    const D3 we = sample_cosine(s.n, u24(x.x), u24(x.y));
+                    const Brdf f = brdf_eval<true>(r.brdf, s.n, s.wo, we, s.alb, s.rough, s.spec);
+                    const D3 Ee = d3(r.env[0], r.env[1], r.env[2]) * PI;
+                    const D3 C = beta * f.f * Ee;
+                    const double sx = db.x * Ee.x + db.y * Ee.y + db.z * Ee.z;
+                    nga = nga + db * Ee * (1.0 / PI);
+                    ngr += sx * f.ds_dr;
+                    ngs += sx * f.ds_dsp;
+                    rl.x -= (float)C.x;
+                    rl.y -= (float)C.y;
+                    rl.z -= (float)C.z;
+                }
+                if (depth < r.max_depth - 1) {
+                    const U4 x = vertex_rng(r, g, 1u + 2u * depth);
+                    const D3 wi = sample_bounce(r.brdf, s.n, s.wo, s.rough, u24(x.x), u24(x.y), u24(x.z));
+                    const double ci = dot(s.n, wi);
+                    const double pdf = bounce_pdf(r.brdf, s.n, s.wo, wi, s.rough);
+                    if (ci > 0.0 && pdf > 0.0) {
+                        const Brdf f = brdf_eval<true>(r.brdf, s.n, s.wo, wi, s.alb, s.rough, s.spec);
+                        const D3 nbeta = beta * (f.f * (ci / pdf));
+                        cont = true;
+                        no = PathO{s.x.x, s.x.y, s.x.z, o.slot, s.prim};
+                        nd = PathD{wi.x, wi.y, wi.z, g, 0u};
+                        nb = make_float4((float)nbeta.x, (float)nbeta.y, (float)nbeta.z, 0.0f);
+                        nrl = rl;
+                        npend = make_float4((float)s.u, (float)s.v, (float)f.ds_dr, (float)f.ds_dsp);
+                        npenda = make_float4(f.f.x > 0.0 ? (float)(1.0 / f.f.x) : 0.f,
+                                             f.f.y > 0.0 ? (float)(1.0 / f.f.y) : 0.f,
+                                             f.f.z > 0.0 ? (float)(1.0 / f.f.z) : 0.f, 1.f);
+                        npn = make_float4((float)nga.x, (float)nga.y, (float)nga.z, (float)ngr);
+                        npns = (float)ngs;
+                    }
+                }
+                if (!cont) {   // the path ends here: its next-event cotangents go out now
+                    b_on = true;
+                    b_u = (float)s.u;
+                    b_v = (float)s.v;
+                    bg[0] = (float)nga.x;
+                    bg[1] = (float)nga.y;
+                    bg[2] = (float)nga.z;
+                    bg[3] = (float)ngr;
+                    bg[4] = (float)ngs;
+                }
             }
         }
-        scatter_tex(r, !occ, x.z, x.w, d3(a.x, a.y, a.z), a.w, sv);
+        if (UNI) {
+            scatter_tex(*rp, a_on, a_u, a_v, ag);
+            scatter_tex(*rp, b_on, b_u, b_v, bg);
+            if (rp->dEp) scatter_ep(*rp, e_on, e_pu, e_pv, eg);
+        } else {
+            if (a_on) scatter_tex_lane(*rp, a_u, a_v, ag);
+            if (b_on) scatter_tex_lane(*rp, b_u, b_v, bg);
+            if (e_on) scatter_ep_lane(*rp, e_pu, e_pv, eg);
+        }
+        const uint32_t jn = wave_append(cont, &q.cnt[nxt]);
+        if (cont) {
+            q.po[nxt][jn] = no;
+            q.pd[nxt][jn] = nd;
+            q.pb[nxt][jn] = nb;
+            aq.rl[nxt][jn] = nrl;
+            aq.pend[nxt][jn] = npend;
+            aq.penda[nxt][jn] = npenda;
+            aq.pn[nxt][jn] = npn;
+            aq.pns[nxt][jn] = npns;
+        }
     }
 }
 
@@ -511,6 +692,12 @@ void launch_adj_shadow(const Launch& l, const Queues& q, const AdjQueues& aq, in
     const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
     if (table) hipLaunchKernelGGL((k_adj_shadow<false>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
     else hipLaunchKernelGGL((k_adj_shadow<true>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
+}
+void launch_adj_replay(const Launch& l, const Queues& q, const AdjQueues& aq, int cur, int depth, const ReqDesc& uni,
+                       const ReqDesc* table, int64_t n_upper) {
+    const dim3 g(grid_cap(l, n_upper, BLOCK)), b(BLOCK);
+    if (table) hipLaunchKernelGGL((k_adj_replay<false>), g, b, 0, l.st, q, aq, cur, depth, uni, table);
+    else hipLaunchKernelGGL((k_adj_replay<true>), g, b, 0, l.st, q, aq, cur, depth, uni, table);
 }
 void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* d_albedo, float* d_rough,
                        float* d_spec, float* d_scalars, float* acc) {

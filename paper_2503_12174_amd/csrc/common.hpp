@@ -145,7 +145,17 @@ struct ReqDesc {
     float* dEp;                // cotangent of E_p, 4 floats per texel
     float* d_tex;              // cotangent of (albedo rgb, roughness, specular), 5 floats per texel
     float* d_acc;              // 8 floats: d gamma_c[3], d w[3], d threshold, pad
+    // path records: one word per (sample, depth) at rec[(g - rec_g0) * max_depth + depth];
+    // the forward writes them when rec is set, the replay adjoint reads them
+    uint32_t* rec;
+    uint32_t rec_g0;
 };
+
+// path record word: bits 0..29 leaf + 1 of the vertex hit at that depth (0: the ray
+// escaped), bit 30 environment shadow ray unoccluded, bit 31 projector shadow ray unoccluded
+constexpr uint32_t REC_LEAF = 0x3fffffffu;
+constexpr uint32_t REC_ENV = 1u << 30;
+constexpr uint32_t REC_PRJ = 1u << 31;
 
 __device__ __forceinline__ float scalar(const ReqDesc& r, int k) { return r.dscal ? r.dscal[k] : r.scal[k]; }
 __device__ __forceinline__ float clip_threshold(const ReqDesc& r) {

@@ -68,6 +68,8 @@ struct AdjQueues {
     float4* sg[2];     // shadow: E_p cotangent weight per channel (w: -)
     float4* sa[2];     // shadow: albedo cotangent rgb (w: roughness cotangent)
     float* ss[2];      // shadow: specular cotangent
+    float4* pn[2];     // replay: pending next-event cotangents of the previous vertex (albedo rgb, roughness)
+    float* pns[2];     // replay: pending next-event specular cotangent
     float4* pend[2];   // pending bounce: (u, v, dr, dsp) cotangent scale of the previous vertex
     float4* penda[2];  // pending bounce: albedo cotangent scale rgb
 };
@@ -88,8 +90,9 @@ void launch_trace(const Launch& l, const Queues& q, int cur, const ReqDesc& uni,
                   int stack);
 void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const ReqDesc& uni, const ReqDesc* table,
                   int64_t n_upper);
+// depth: the bounce the shadow rays leave from (for the path records)
 void launch_shadow(const Launch& l, const Queues& q, int which, const ReqDesc& uni, const ReqDesc* table,
-                   int64_t n_upper, int stack);
+                   int64_t n_upper, int depth);
 void launch_finalize(const Launch& l, const Queues& q, const ReqDesc& r, const ReqDesc* table, int slot,
                      uint32_t p0, uint32_t p1);
 void launch_set_desc(const Launch& l, ReqDesc* table, int slot, const ReqDesc& r);
@@ -103,6 +106,10 @@ void launch_adj_shade(const Launch& l, const Queues& q, const AdjQueues& aq, int
                       const ReqDesc* table, int64_t n_upper);
 void launch_adj_shadow(const Launch& l, const Queues& q, const AdjQueues& aq, int which, int nxt, const ReqDesc& uni,
                        const ReqDesc* table, int64_t n_upper, int stack);
+// replay of one bounce from the path records (no tracing): shade, next-event gradients
+// for the recorded visibilities, bounce
+void launch_adj_replay(const Launch& l, const Queues& q, const AdjQueues& aq, int cur, int depth, const ReqDesc& uni,
+                       const ReqDesc* table, int64_t n_upper);
 // PRF backward, map de-interleave and scalar gradients; acc: 20 floats (see adjoint.hip)
 void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* d_albedo, float* d_rough,
                        float* d_spec, float* d_scalars, float* acc);

@@ -120,6 +120,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
             const uint32_t g = dd.g;
             const uint32_t sid = g - r.g_base + r.sid_base;
             const D3 beta = d3(b.x, b.y, b.z);
+            if (r.rec) r.rec[(size_t)(g - r.rec_g0) * r.max_depth + depth] = (uint32_t)(leaf + 1);
             if (leaf < 0) {
                 if (r.out_hits) r.out_hits[(size_t)g * r.max_depth + depth] = -1;
                 if (depth == 0 && r.env_on) {   // a camera ray that escapes sees the environment
@@ -145,7 +146,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
                     const D4 E = fetch4(r.Ep, p.pb);
                     const Brdf f = brdf_eval<false>(r.brdf, s.n, s.wo, p.wp, s.alb, s.rough, s.spec);
                     const D3 C = beta * f.f * d3(E.x, E.y, E.z) * p.geom;
-                    if (C.x > 0.0 || C.y > 0.0 || C.z > 0.0) {
+                    if (r.rec || C.x > 0.0 || C.y > 0.0 || C.z > 0.0) {
                         shp = true;
                         po = f4(to_f(s.x), __int_as_float(o.slot));
                         pd = f4(to_f(p.wp), __int_as_float(s.prim));
@@ -158,7 +159,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
                     const D3 we = sample_cosine(s.n, u24(x.x), u24(x.y));
                     const Brdf f = brdf_eval<false>(r.brdf, s.n, s.wo, we, s.alb, s.rough, s.spec);
                     const D3 C = beta * f.f * d3(r.env[0], r.env[1], r.env[2]) * PI;
-                    if (C.x > 0.0 || C.y > 0.0 || C.z > 0.0) {
+                    if (r.rec || C.x > 0.0 || C.y > 0.0 || C.z > 0.0) {
                         she = true;
                         eo = f4(to_f(s.x), __int_as_float(o.slot));
                         ed = f4(to_f(we), __int_as_float(s.prim));
@@ -206,7 +207,8 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
 
 // ---------------------------------------------------------------- shadows
 template <bool UNI>
-__global__ void __launch_bounds__(TB) k_shadow(Queues q, int which, ReqDesc uni, const ReqDesc* __restrict__ table) {
+__global__ void __launch_bounds__(TB) k_shadow(Queues q, int which, int depth, ReqDesc uni,
+                                               const ReqDesc* __restrict__ table) {
     __shared__ int stack[SHORT_STACK * TB];
     int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL + threadIdx.x;
     const uint32_t n = q.cnt[2 + which];
@@ -229,6 +231,10 @@ __global__ void __launch_bounds__(TB) k_shadow(Queues q, int which, ReqDesc uni,
             L.y += c.y;
             L.z += c.z;
             q.L[sid] = L;
+            if (r.rec) {
+                const uint32_t g = sid - r.sid_base + r.g_base;
+                atomicOr(&r.rec[(size_t)(g - r.rec_g0) * r.max_depth + depth], which == 0 ? REC_PRJ : REC_ENV);
+            }
         }
     }
 }
@@ -336,10 +342,10 @@ void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const Re
     else hipLaunchKernelGGL((k_shade<true>), g, b, 0, l.st, q, cur, depth, uni, table);
 }
 void launch_shadow(const Launch& l, const Queues& q, int which, const ReqDesc& uni, const ReqDesc* table,
-                   int64_t n_upper, int) {
+                   int64_t n_upper, int depth) {
     const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
-    if (table) hipLaunchKernelGGL((k_shadow<false>), g, b, 0, l.st, q, which, uni, table);
-    else hipLaunchKernelGGL((k_shadow<true>), g, b, 0, l.st, q, which, uni, table);
+    if (table) hipLaunchKernelGGL((k_shadow<false>), g, b, 0, l.st, q, which, depth, uni, table);
+    else hipLaunchKernelGGL((k_shadow<true>), g, b, 0, l.st, q, which, depth, uni, table);
 }
 void launch_finalize(const Launch& l, const Queues& q, const ReqDesc& r, const ReqDesc*, int, uint32_t p0,
                      uint32_t p1) {

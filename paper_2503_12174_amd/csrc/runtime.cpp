@@ -60,7 +60,8 @@ void* scratch(dpcs_context ctx, const char* name, size_t bytes, dpcs_status* st)
 bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpcs_status* st) {
     const size_t c = (size_t)cap;
     // per path: 2 x (PathO 32 + PathD 32 + beta 16) + hit 4 + 2 x shadow (48 + 4) + L 16
-    const size_t bytes = c * (2 * 80 + 4 + 2 * 52 + 16) + 4096 + 4 * spill_ints(ctx->grid_cap) + 256;
+    // + 256 bytes of alignment slack per part (18 parts)
+    const size_t bytes = c * (2 * 80 + 4 + 2 * 52 + 16) + 4 * spill_ints(ctx->grid_cap) + 32 * 256;
     char* b = (char*)scratch(ctx, name, bytes, st);
     if (!b) return false;
     auto take = [&](size_t n) {   // 256-byte aligned parts
@@ -88,7 +89,8 @@ bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpc
 
 bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues& aq, dpcs_status* st) {
     const size_t c = (size_t)cap;
-    const size_t bytes = c * (2 * 48 + 16 + 2 * 52) + 4096;
+    // + 256 bytes of alignment slack per part (19 parts)
+    const size_t bytes = c * (2 * 48 + 16 + 2 * 52 + 2 * 20) + 32 * 256;
     char* b = (char*)scratch(ctx, name, bytes, st);
     if (!b) return false;
     auto take = [&](size_t n) {
@@ -104,6 +106,8 @@ bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues&
         aq.sg[k] = (float4*)take(16 * c);
         aq.sa[k] = (float4*)take(16 * c);
         aq.ss[k] = (float*)take(4 * c);
+        aq.pn[k] = (float4*)take(16 * c);
+        aq.pns[k] = (float*)take(4 * c);
     }
     aq.delta = (float4*)take(16 * c);
     return true;
@@ -610,7 +614,7 @@ void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t 
         q.stats = prof_stats(ctx, DPCS_STAGE_SHADOW);
         for (int w = 0; w < (r.env_on ? 2 : 1); ++w) {
             pr = prof_begin(ctx, DPCS_STAGE_SHADOW);
-            launch_shadow(l, q, w, r, nullptr, n, stack);
+            launch_shadow(l, q, w, r, nullptr, n, d);
             prof_end(ctx, pr, q.cnt + 2 + w, 0);
         }
         q.stats = nullptr;
@@ -636,6 +640,16 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
     launch_set_count(l, q.cnt, 0, n, 1, 4);
     launch_adj_raygen(l, q, aq, r, 0, r.g_base, n);
     int cur = 0;
+    if (r.rec) {   // the forward's path records stand in for tracing
+        for (int d = 0; d < r.max_depth; ++d) {
+            launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
+            pr = prof_begin(ctx, DPCS_STAGE_ADJ_SHADE);
+            launch_adj_replay(l, q, aq, cur, d, r, nullptr, n);
+            prof_end(ctx, pr, q.cnt + cur, 0);
+            cur ^= 1;
+        }
+        return;
+    }
     for (int d = 0; d < r.max_depth; ++d) {
         launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
         q.stats = prof_stats(ctx, DPCS_STAGE_TRACE);
@@ -675,7 +689,10 @@ extern "C" dpcs_status dpcs_render(dpcs_context ctx, dpcs_scene scene, const dpc
         r.out_linear = aux->linear;
         r.out_L = aux->sample_radiance;
         r.out_hits = aux->hit_prims;
+        r.rec = aux->path_records;
+        r.rec_g0 = 0;
     }
+    if (r.rec && scene->nt >= (int)REC_LEAF) return fail(ctx, DPCS_E_UNSUPPORTED, "path records need < 2^30 triangles");
     dpcs_status st = DPCS_OK;
     if (!prepare_request(ctx, r, params, "fwd", &st)) return st;
     const int64_t npix = (int64_t)r.Wc * r.Hc;

@@ -212,8 +212,8 @@ void dpcs_server_s::wave(Launch& l) {
         launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
         launch_trace(l, q, cur, any, table, used, stack);
         launch_shade(l, q, cur, d, any, table, used);
-        launch_shadow(l, q, 0, any, table, used, stack);
-        if (env) launch_shadow(l, q, 1, any, table, used, stack);
+        launch_shadow(l, q, 0, any, table, used, d);
+        if (env) launch_shadow(l, q, 1, any, table, used, d);
         cur ^= 1;
     }
     for (const Seg& s : segs) launch_finalize(l, q, s.q->r, table, s.q->slot, s.a, s.b);
@@ -336,11 +336,12 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     s->budget = memory_budget_bytes;
     s->max_slots = max_slots;
     // shared wave queues take at most a quarter of the budget
-    const size_t per_path = (2 * 80 + 4 + 2 * 52 + 16) + (2 * 48 + 16 + 2 * 52);
+    const size_t per_path = (2 * 80 + 4 + 2 * 52 + 16) + (2 * 48 + 16 + 2 * 52 + 2 * 20);
     const int64_t fit = (int64_t)(memory_budget_bytes / 4 / per_path);
     s->cap = std::max<int64_t>(1024, std::min<int64_t>({ctx->capacity, int64_t(1) << 22, fit}));
     const size_t c = (size_t)s->cap;
-    const size_t qbytes = c * per_path + 2 * 4096 + 64 * 256 + 4 * spill_ints(ctx->grid_cap);
+    // + 256 bytes of alignment slack per part (38 parts)
+    const size_t qbytes = c * per_path + 64 * 256 + 4 * spill_ints(ctx->grid_cap);
     s->shared_bytes = qbytes + sizeof(ReqDesc) * (size_t)max_slots;
     if (s->shared_bytes >= s->budget) {
         delete s;
@@ -382,6 +383,8 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
         s->aq.sg[k] = (float4*)take(16 * c);
         s->aq.sa[k] = (float4*)take(16 * c);
         s->aq.ss[k] = (float*)take(4 * c);
+        s->aq.pn[k] = (float4*)take(16 * c);
+        s->aq.pns[k] = (float*)take(4 * c);
     }
     s->q.hit = (int*)take(4 * c);
     s->q.L = (float4*)take(16 * c);

@@ -1,6 +1,7 @@
-// vjp.cpp -- dpcs_render_vjp: per launch wave of whole pixels, forward samples (unless
-// the caller hands in the forward call's per-sample radiance), CRF/clip backward,
-// path replay with gradient scatter; finally the PRF backward and scalar reductions.
+// vjp.cpp -- dpcs_render_vjp: per launch wave of whole pixels, forward samples with path
+// records (unless the caller hands in the forward call's per-sample radiance), CRF/clip
+// backward, path replay with gradient scatter; finally the PRF backward and scalar
+// reductions.
 #include <algorithm>
 
 #include "runtime.hpp"
@@ -9,13 +10,15 @@ using namespace dpcs;
 
 extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
                                        const float* proj_image, const float* grad_image, const float* sample_radiance,
-                                       const dpcs_grads* grads) {
+                                       const uint32_t* path_records, const dpcs_grads* grads) {
     if (!ctx) return DPCS_E_INVALID;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (ctx->sticky) return DPCS_E_DEVICE;
     if (!scene || scene->ctx != ctx) return fail(ctx, DPCS_E_INVALID, "scene is NULL or from another context");
     if (!grad_image) return fail(ctx, DPCS_E_INVALID, "grad_image is NULL");
     if (!grads) return fail(ctx, DPCS_E_INVALID, "grads is NULL");
+    if (path_records && !sample_radiance)
+        return fail(ctx, DPCS_E_INVALID, "path_records need the sample_radiance of the same forward call");
     (void)hipGetLastError();
     ReqDesc r;
     std::string why;
@@ -45,9 +48,27 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     AdjQueues aq;
     if (!make_queues(ctx, "fwd.queues", ppw * r.spp, q, &st)) return st;
     if (!make_adj_queues(ctx, "vjp.queues", ppw * r.spp, aq, &st)) return st;
+    // Path records: the caller's (whole image, from the forward call that produced
+    // sample_radiance), or this call's own per wave when it runs the forward itself.
+    // With sample_radiance alone the replay traces again.
+    uint32_t* wave_rec = nullptr;
+    const bool own_rec = !sample_radiance;
+    if ((own_rec || path_records) && scene->nt >= (int)REC_LEAF)
+        return fail(ctx, DPCS_E_UNSUPPORTED, "path records need < 2^30 triangles");
+    if (own_rec) {
+        wave_rec = (uint32_t*)scratch(ctx, "vjp.records", sizeof(uint32_t) * (size_t)(ppw * r.spp) * r.max_depth, &st);
+        if (!wave_rec) return st;
+    }
     for (int64_t a = 0; a < npix; a += ppw) {
         const uint32_t b = (uint32_t)std::min(npix, a + ppw);
-        if (!sample_radiance) forward_wave(ctx, q, r, (uint32_t)a, b, false);
+        if (own_rec) {
+            r.rec = wave_rec;
+            r.rec_g0 = (uint32_t)a * (uint32_t)r.spp;
+            forward_wave(ctx, q, r, (uint32_t)a, b, false);
+        } else {
+            r.rec = const_cast<uint32_t*>(path_records);   // read only in the adjoint
+            r.rec_g0 = 0;
+        }
         adjoint_wave(ctx, q, aq, r, (uint32_t)a, b, sample_radiance);
     }
     launch_adj_finish(l, r, grads->d_proj_image, grads->d_albedo, grads->d_roughness, grads->d_specular,

@@ -54,7 +54,8 @@ class RenderParams(C.Structure):
 
 
 class RenderAux(C.Structure):
-    _fields_ = [("linear", C.c_void_p), ("sample_radiance", C.c_void_p), ("hit_prims", C.c_void_p)]
+    _fields_ = [("linear", C.c_void_p), ("sample_radiance", C.c_void_p), ("hit_prims", C.c_void_p),
+                ("path_records", C.c_void_p)]
 
 
 class Grads(C.Structure):
@@ -110,7 +111,7 @@ def lib():
             "dpcs_scene_get_info": ([P, C.POINTER(SceneInfo)], S),
             "dpcs_scene_destroy": ([P], S),
             "dpcs_render": ([P, P, C.POINTER(RenderParams), P, P, C.POINTER(RenderAux)], S),
-            "dpcs_render_vjp": ([P, P, C.POINTER(RenderParams), P, P, P, C.POINTER(Grads)], S),
+            "dpcs_render_vjp": ([P, P, C.POINTER(RenderParams), P, P, P, P, C.POINTER(Grads)], S),
             "dpcs_debug_intersect": ([P, P, P, I64, I32, P, P, P, P], S),
             "dpcs_debug_philox": ([P, C.c_uint64, P, I64, P], S),
             "dpcs_context_set_profiling": ([P, I32], S),
@@ -257,17 +258,18 @@ def params_from(w, albedo, roughness=None, specular=None, device_scalars=None, *
 # ------------------------------------------------------------------ entry points
 
 def dpcs_render(ctx: Context, scene: Scene, params: RenderParams, proj_image, out_image, linear=None,
-                sample_radiance=None, hit_prims=None):
-    aux = RenderAux(_ptr(linear), _ptr(sample_radiance), _ptr(hit_prims))
+                sample_radiance=None, hit_prims=None, path_records=None):
+    aux = RenderAux(_ptr(linear), _ptr(sample_radiance), _ptr(hit_prims), _ptr(path_records))
     return ctx.check(lib().dpcs_render(ctx.h, scene.h, C.byref(params), _ptr(proj_image), _ptr(out_image),
                                        C.byref(aux)))
 
 
 def dpcs_render_vjp(ctx: Context, scene: Scene, params: RenderParams, proj_image, grad_image, sample_radiance=None,
-                    d_proj_image=None, d_albedo=None, d_roughness=None, d_specular=None, d_scalars=None):
+                    d_proj_image=None, d_albedo=None, d_roughness=None, d_specular=None, d_scalars=None,
+                    path_records=None):
     g = Grads(_ptr(d_proj_image), _ptr(d_albedo), _ptr(d_roughness), _ptr(d_specular), _ptr(d_scalars))
     return ctx.check(lib().dpcs_render_vjp(ctx.h, scene.h, C.byref(params), _ptr(proj_image), _ptr(grad_image),
-                                           _ptr(sample_radiance), C.byref(g)))
+                                           _ptr(sample_radiance), _ptr(path_records), C.byref(g)))
 
 
 def dpcs_debug_intersect(ctx: Context, scene: Scene, rays, use_bvh: bool, prim, t=None, b1=None, b2=None):

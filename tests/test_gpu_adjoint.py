@@ -6,7 +6,7 @@ from oracle import oracle as O
 from paper_2503_12174_amd import synth
 
 from . import scenes
-from .gpu_util import GpuRun, compare_grads, dev, run_vjp
+from .gpu_util import VJP_MODES, GpuRun, compare_grads, dev, run_vjp
 
 pytestmark = pytest.mark.gpu
 
@@ -37,9 +37,11 @@ def test_vjp_matches_oracle_ggx(clip, env):
     sc = O.Scene(w)
     G = _clean_cotangent(w, 5, sc)
     ref = O.render_vjp(sc, G)
-    gpu = run_vjp(GpuRun(w), G)
-    worst = compare_grads(gpu, ref)
-    print(f"worst global relative gradient error {worst:.2e}")
+    run = GpuRun(w)
+    for mode in VJP_MODES:   # own records, caller's records, re-tracing replay
+        gpu = run_vjp(run, G, mode=mode)
+        worst = compare_grads(gpu, ref)
+        print(f"{mode}: worst global relative gradient error {worst:.2e}")
 
 
 def test_vjp_lambert_config1():
@@ -96,14 +98,46 @@ def test_vjp_config4_sampled_pixels():
     G[px] = rng.normal(size=(len(px), 3))
     G = G.reshape(512, 512, 3)
     ref = O.render_vjp(sc, G, pixels=px)
-    gpu = run_vjp(GpuRun(w), G)
-    compare_grads(gpu, ref, keys=("Ip", "albedo", "roughness", "specular", "crf_gamma", "white_balance"))
+    run = GpuRun(w)
+    for mode in ("own", "retrace"):
+        gpu = run_vjp(run, G, mode=mode)
+        compare_grads(gpu, ref, keys=("Ip", "albedo", "roughness", "specular", "crf_gamma", "white_balance"))
 
 
 def test_vjp_rejects_bad_arguments():
+    import torch
     from paper_2503_12174_amd import dpcs
     w = synth.config1()
     run = GpuRun(w)
     with pytest.raises(dpcs.DpcsError):
         dpcs.dpcs_render_vjp(run.c, run.scene, run.params, run.proj, None)
+    rec = torch.zeros((64, 64, w.spp, w.max_depth), dtype=torch.int32, device="cuda")
+    G = torch.zeros((64, 64, 3), device="cuda")
+    with pytest.raises(dpcs.DpcsError, match="sample_radiance"):   # records without their radiance
+        dpcs.dpcs_render_vjp(run.c, run.scene, run.params, run.proj, G, path_records=rec,
+                             d_albedo=torch.zeros_like(run.albedo))
     run_vjp(run, np.zeros((64, 64, 3)))   # still usable
+
+
+def test_path_records_match_hits():
+    """Record words name the leaf hit at each vertex: escaped vertices (hit -1) are 0,
+    vertices on a surface are nonzero, and the forward image is unchanged by keeping them."""
+    import torch
+    from paper_2503_12174_amd import dpcs
+    w = scenes.c3_ggx(spp=4, seed=5, max_depth=3)
+    run = GpuRun(w)
+    H, W = w.camera.height, w.camera.width
+    hp = torch.full((H, W, w.spp, w.max_depth), -2, dtype=torch.int32, device="cuda")
+    rec = torch.zeros((H, W, w.spp, w.max_depth), dtype=torch.int32, device="cuda")
+    a = torch.zeros((H, W, 3), device="cuda")
+    b = torch.zeros((H, W, 3), device="cuda")
+    dpcs.dpcs_render(run.c, run.scene, run.params, run.proj, a, hit_prims=hp)
+    dpcs.dpcs_render(run.c, run.scene, run.params, run.proj, b, path_records=rec)
+    run.c.synchronize()
+    hp, rec = hp.cpu().numpy(), rec.cpu().numpy().view(np.uint32)
+    leaf = rec & np.uint32(0x3FFFFFFF)
+    assert (leaf[hp == -1] == 0).all()
+    assert (leaf[hp >= 0] > 0).all()
+    assert ((rec[hp == -1] >> np.uint32(30)) == 0).all()   # no shadow rays from an escaped vertex
+    assert (rec[hp >= 0] >> np.uint32(31)).any()           # some projector shadow rays are unoccluded
+    np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
