@@ -578,7 +578,10 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
             if (b_on) scatter_tex_lane(*rp, b_u, b_v, bg);
             if (e_on) scatter_ep_lane(*rp, e_pu, e_pv, eg);
         }
-        const uint32_t jn = wave_append(cont, &q.cnt[nxt]);
+        const bool pred[1] = {cont};
+        uint32_t* const ctr[1] = {&q.cnt[nxt]};
+        uint32_t jn;
+        block_append<1>(pred, ctr, &jn);
         if (cont) {
             q.po[nxt][jn] = no;
             q.pd[nxt][jn] = nd;

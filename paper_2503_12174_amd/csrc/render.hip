@@ -182,20 +182,22 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
                 }
             }
         }
-        const uint32_t jn = wave_append(cont, &q.cnt[nxt]);
+        const bool pred[3] = {cont, shp, she};
+        uint32_t* const ctr[3] = {&q.cnt[nxt], &q.cnt[2], &q.cnt[3]};
+        uint32_t at[3];
+        block_append<3>(pred, ctr, at);
+        const uint32_t jn = at[0], jp = at[1], je = at[2];
         if (cont) {
             q.po[nxt][jn] = no;
             q.pd[nxt][jn] = nd;
             q.pb[nxt][jn] = nb;
         }
-        const uint32_t jp = wave_append(shp, &q.cnt[2]);
         if (shp) {
             q.so[0][jp] = po;
             q.sd[0][jp] = pd;
             q.sc[0][jp] = pc;
             q.st[0][jp] = ptmax;
         }
-        const uint32_t je = wave_append(she, &q.cnt[3]);
         if (she) {
             q.so[1][je] = eo;
             q.sd[1][je] = ed;

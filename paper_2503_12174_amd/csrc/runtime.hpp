@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dpcs.h"
+#include "dpcs.h"
 #include "kernels.hpp"
 
 struct dpcs_context_s {

@@ -25,6 +25,39 @@ __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
     return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
 }
 
+// workgroup-aggregated append to NQ queues: one atomic per queue per workgroup
+// (instead of one per wave), lane order preserved within each wave.  Every thread of
+// the workgroup (BLOCK threads) must call it, with its predicates; idx[q] is the slot
+// of a thread whose pred[q] holds.
+template <int NQ>
+__device__ __forceinline__ void block_append(const bool* pred, uint32_t* const* counter, uint32_t* idx) {
+    constexpr int NW = BLOCK / 64;
+    __shared__ uint32_t wcount[NQ][NW];
+    __shared__ uint32_t wbase[NQ][NW];
+    const int lane = __lane_id(), wv = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long m[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        m[q] = __ballot(pred[q]);
+        if (lane == 0) wcount[q][wv] = (uint32_t)__popcll(m[q]);
+    }
+    __syncthreads();
+    if (threadIdx.x < NQ) {
+        const int q = threadIdx.x;
+        uint32_t total = 0;
+        for (int w = 0; w < NW; ++w) total += wcount[q][w];
+        uint32_t run = total ? atomicAdd(counter[q], total) : 0u;
+        for (int w = 0; w < NW; ++w) {
+            wbase[q][w] = run;
+            run += wcount[q][w];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) idx[q] = wbase[q][wv] + (uint32_t)__popcll(m[q] & below);
+}
+
 // camera ray of global sample g (pixel = g / spp, sample = g % spp), Eq. 6 inverted
 __device__ __forceinline__ D3 camera_dir(const ReqDesc& r, uint32_t g) {
     const uint32_t pixel = g / (uint32_t)r.spp, s = g - pixel * (uint32_t)r.spp;
