@@ -424,6 +424,273 @@ __global__ void __launch_bounds__(TB) k_adj_shadow(Queues q, AdjQueues aq, int w
     }
 }
 
+// ---------------------------------------------------------------- binned map cotangents
+// A record starts with one header word: base texel y0 * W + x0 of the bilinear corners
+// (bits 0..27), x1 - x0 (bit 28) and y1 - y0 (bit 29), then the offsets ax, ay and the
+// C cotangent values.
+constexpr int TEX_RS = 8, EP_RS = 6;   // floats per record (C = 5, C = 3)
+constexpr int BIN_CHUNK = 16384;       // records per workgroup in the counting passes
+
+__device__ __forceinline__ uint32_t map_head(const Corners& c, int W) {
+    return (uint32_t)(c.y0 * W + c.x0) | ((uint32_t)(c.x1 - c.x0) << 28) | ((uint32_t)(c.y1 - c.y0) << 29);
+}
+__device__ __forceinline__ int map_bin(const MapBins& mb, uint32_t head) {
+    const uint32_t base = head & 0x0fffffffu;
+    const int y0 = (int)(base / (uint32_t)mb.W), x0 = (int)(base - (uint32_t)y0 * (uint32_t)mb.W);
+    return (y0 / mb.T) * mb.nbx + x0 / mb.T;
+}
+// BRDF-map record at texture coordinate (u, v); false when the buffer is full
+__device__ __forceinline__ bool put_tex_rec(const MapBins& mb, uint32_t slot, double u, double v, const float* g) {
+    if ((int64_t)slot >= mb.cap) return false;
+    const Corners c = bilinear_corners(u * mb.W - 0.5, v * mb.H - 0.5, mb.W, mb.H);
+    float4* p = (float4*)(mb.rec + (size_t)slot * TEX_RS);
+    p[0] = make_float4(__uint_as_float(map_head(c, mb.W)), (float)c.ax, (float)c.ay, g[0]);
+    p[1] = make_float4(g[1], g[2], g[3], g[4]);
+    return true;
+}
+// E_p record at projector pixel position (pu, pv); false when the buffer is full
+__device__ __forceinline__ bool put_ep_rec(const MapBins& mb, uint32_t slot, double pu, double pv, const float* g) {
+    if ((int64_t)slot >= mb.cap) return false;
+    const Corners c = bilinear_corners(pu - 0.5, pv - 0.5, mb.W, mb.H);
+    float2* p = (float2*)(mb.rec + (size_t)slot * EP_RS);
+    p[0] = make_float2(__uint_as_float(map_head(c, mb.W)), (float)c.ax);
+    p[1] = make_float2((float)c.ay, g[0]);
+    p[2] = make_float2(g[1], g[2]);
+    return true;
+}
+
+// lanes of the wave whose (12-bit) bin equals this lane's, among the valid lanes
+__device__ __forceinline__ unsigned long long bin_peers(bool valid, uint32_t bin) {
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 12; ++bit) {
+        const bool set = (bin >> bit) & 1u;
+        const unsigned long long m = __ballot(set);
+        peers &= set ? m : ~m;
+    }
+    return peers;
+}
+// LDS counter add aggregated over the lanes of a wave with the same bin; returns the
+// counter's old value plus the lane's rank among those lanes.  Whole wave must call.
+__device__ __forceinline__ uint32_t lds_bin_add(uint32_t* cnt, bool valid, uint32_t bin) {
+    const unsigned long long peers = bin_peers(valid, bin);
+    const int lane = __lane_id();
+    const int leader = valid ? __ffsll(peers) - 1 : lane;
+    uint32_t base = 0u;
+    if (valid && lane == leader) base = atomicAdd(&cnt[bin], (uint32_t)__popcll(peers));
+    base = (uint32_t)__shfl((int)base, leader);
+    return base + (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+}
+
+__device__ __forceinline__ uint32_t map_records(const MapBins& mb) {
+    const uint32_t n = *mb.count;
+    return (int64_t)n < mb.cap ? n : (uint32_t)mb.cap;
+}
+
+// records per tile: workgroup histogram in LDS, one atomic per touched tile; also the
+// largest |cotangent| of any record (for the fixed-point accumulation)
+template <int C, int RS>
+__global__ void __launch_bounds__(256) k_bin_hist(MapBins mb) {
+    __shared__ uint32_t h[MAP_MAX_BINS];
+    __shared__ uint32_t hmax;
+    const uint32_t n = map_records(mb);
+    const uint32_t b0 = blockIdx.x * BIN_CHUNK;
+    if (b0 >= n) return;   // uniform per workgroup
+    for (int k = threadIdx.x; k < mb.nb; k += 256) h[k] = 0u;
+    if (threadIdx.x == 0) hmax = 0u;
+    __syncthreads();
+    const uint32_t e = min(n, b0 + BIN_CHUNK);
+    float m = 0.f;
+    for (uint32_t base = b0; base < e; base += 256) {
+        const uint32_t i = base + threadIdx.x;
+        const bool valid = i < e;
+        const float* p = mb.rec + (size_t)(valid ? i : b0) * RS;
+        const uint32_t bin = valid ? (uint32_t)map_bin(mb, __float_as_uint(p[0])) : 0u;
+        lds_bin_add(h, valid, bin);
+        if (valid)
+#pragma unroll
+            for (int c = 0; c < C; ++c) m = fmaxf(m, fabsf(p[3 + c]));   // NaN is dropped here; see accum
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if (__lane_id() == 0) atomicMax(&hmax, __float_as_uint(m));   // non-negative floats order as integers
+    __syncthreads();
+    for (int k = threadIdx.x; k < mb.nb; k += 256)
+        if (h[k]) atomicAdd(&mb.bins[k], h[k]);
+    if (threadIdx.x == 0 && hmax) atomicMax(&mb.bins[3 * mb.nb + 1], hmax);
+}
+
+// tile offsets (exclusive scan of the counts, nb <= 4096); clears counts and fill
+__global__ void __launch_bounds__(1024) k_bin_scan(MapBins mb) {
+    __shared__ uint32_t part[1024];
+    uint32_t* off = mb.bins + mb.nb;
+    uint32_t* fill = off + mb.nb + 1;
+    const int per = (mb.nb + 1023) / 1024;
+    const int b = threadIdx.x * per, e = min(b + per, mb.nb);
+    uint32_t s = 0;
+    for (int i = b; i < e; ++i) s += mb.bins[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint32_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    for (int i = b; i < e; ++i) {
+        const uint32_t v = mb.bins[i];
+        off[i] = run;
+        run += v;
+        mb.bins[i] = 0u;
+        fill[i] = 0u;
+    }
+    if (threadIdx.x == 1023) off[mb.nb] = part[1023];
+}
+
+// copy every record to its tile's range: the workgroup's base inside each touched tile
+// from one global atomic, ranks inside the workgroup from LDS atomics
+template <int RS>
+__global__ void __launch_bounds__(256) k_bin_place(MapBins mb) {
+    __shared__ uint32_t cnt[MAP_MAX_BINS];
+    const uint32_t n = map_records(mb);
+    const uint32_t b0 = blockIdx.x * BIN_CHUNK;
+    if (b0 >= n) return;   // uniform per workgroup
+    const uint32_t e = min(n, b0 + BIN_CHUNK);
+    for (int k = threadIdx.x; k < mb.nb; k += 256) cnt[k] = 0u;
+    __syncthreads();
+    for (uint32_t base = b0; base < e; base += 256) {
+        const uint32_t i = base + threadIdx.x;
+        const bool valid = i < e;
+        const uint32_t bin = valid ? (uint32_t)map_bin(mb, __float_as_uint(mb.rec[(size_t)i * RS])) : 0u;
+        lds_bin_add(cnt, valid, bin);
+    }
+    __syncthreads();
+    const uint32_t* off = mb.bins + mb.nb;
+    uint32_t* fill = mb.bins + 2 * mb.nb + 1;
+    for (int k = threadIdx.x; k < mb.nb; k += 256) {
+        const uint32_t c = cnt[k];
+        if (c) cnt[k] = off[k] + atomicAdd(&fill[k], c);
+    }
+    __syncthreads();
+    for (uint32_t base = b0; base < e; base += 256) {
+        const uint32_t i = base + threadIdx.x;
+        const bool valid = i < e;
+        const float2* src = (const float2*)(mb.rec + (size_t)(valid ? i : b0) * RS);
+        const float2 h = src[0];
+        const uint32_t bin = valid ? (uint32_t)map_bin(mb, __float_as_uint(h.x)) : 0u;
+        const uint32_t pos = lds_bin_add(cnt, valid, bin);
+        if (!valid || (int64_t)pos >= mb.cap) continue;   // pos < cap always for consistent counts
+        float2* dst = (float2*)(mb.sorted + (size_t)pos * RS);
+        dst[0] = h;
+#pragma unroll
+        for (int k = 1; k < RS / 2; ++k) dst[k] = src[k];
+    }
+}
+
+// Accumulation over fixed chunks of the tile-sorted records (balanced whatever the
+// tile sizes): a workgroup walks the tiles its chunk covers and, per tile, sums the
+// records in LDS over the tile plus one halo row/column and stores the (T + 1)^2 x C
+// block at pair index chunk + tile (unique: both grow along the sorted records).
+template <int C, int RS>
+__global__ void __launch_bounds__(256) k_bin_accum(MapBins mb) {
+    // Sums in 64-bit fixed point (integer LDS atomics are exact and much faster than
+    // FP32 ones): values scaled by 2^E with |chunk sum| < 2^62 for every texel, i.e.
+    // 2^-50 of the largest record value as resolution.
+    __shared__ long long t[(MAP_MAX_T + 1) * (MAP_MAX_T + 1) * C];
+    const uint32_t* off = mb.bins + mb.nb;
+    const uint32_t total = off[mb.nb];
+    const uint32_t c = blockIdx.x;
+    const uint32_t i0 = c * ACC_CHUNK;
+    if (c == 0 && threadIdx.x == 0) *mb.count = 0u;   // the counting passes are done
+    if (i0 >= total) return;   // uniform per workgroup
+    const uint32_t i1 = min(total, i0 + ACC_CHUNK);
+    const float gmax = __uint_as_float(mb.bins[3 * mb.nb + 1]);
+    int ge = 0;
+    frexpf(gmax, &ge);                              // gmax < 2^ge
+    const int E = 62 - 12 - ge;                     // ACC_CHUNK = 2^12 contributions at most
+    const double up = ldexp(1.0, E), down = ldexp(1.0, -E);
+    int lo = 0, hi = mb.nb;   // the tile holding record i0: last b with off[b] <= i0
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= i0) lo = mid;
+        else hi = mid;
+    }
+    int b = lo;
+    const int S = mb.T + 1, SS = S * S * C;
+    for (;;) {
+        const uint32_t s0 = max(off[b], i0), s1 = min(off[b + 1], i1);
+        for (int k = threadIdx.x; k < SS; k += 256) t[k] = 0;
+        __syncthreads();
+        const int tx0 = (b % mb.nbx) * mb.T, ty0 = (b / mb.nbx) * mb.T;
+        bool bad = false;
+        for (uint32_t i = s0 + threadIdx.x; i < s1; i += 256) {
+            const float* p = mb.sorted + (size_t)i * RS;
+            const uint32_t head = __float_as_uint(p[0]);
+            const uint32_t base = head & 0x0fffffffu;
+            const int y0 = (int)(base / (uint32_t)mb.W), x0 = (int)(base - (uint32_t)y0 * (uint32_t)mb.W);
+            const int lx = x0 - tx0, ly = y0 - ty0;
+            const int dx = (int)((head >> 28) & 1u), dy = (int)((head >> 29) & 1u);
+            const double ax = p[1], ay = p[2];
+            const double w[4] = {(1.0 - ax) * (1.0 - ay), ax * (1.0 - ay), (1.0 - ax) * ay, ax * ay};
+            const int idx[4] = {ly * S + lx, ly * S + lx + dx, (ly + dy) * S + lx, (ly + dy) * S + lx + dx};
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch) {
+                const double g = (double)p[3 + ch] * up;
+                bad = bad || !(fabs(g) <= 0x1p62);       // non-finite cotangent
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const long long q = bad ? 0ll : __double2ll_rn(g * w[k]);
+                    if (q != 0ll) atomicAdd((unsigned long long*)&t[idx[k] * C + ch], (unsigned long long)q);
+                }
+            }
+        }
+        const bool any_bad = __syncthreads_or(bad);
+        float* st = mb.stage + (size_t)(c + b) * SS;
+        for (int k = threadIdx.x; k < SS; k += 256)
+            st[k] = any_bad ? __builtin_nanf("") : (float)((double)t[k] * down);
+        __syncthreads();
+        if (off[b + 1] >= i1) break;
+        ++b;
+        while (off[b + 1] == off[b]) ++b;   // skip empty tiles (a later tile holds record i1 - 1)
+    }
+}
+
+// one thread per texel: the blocks of every (chunk, tile) pair of its own tile plus
+// the halos of the tiles to the left, above and above-left, added into the map (each
+// texel written by one thread)
+template <int C>
+__global__ void k_bin_gather(MapBins mb, float* __restrict__ out, int stride) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t == 0) mb.bins[3 * mb.nb + 1] = 0u;   // largest |value|: read by the accumulation only
+    if (t >= (int64_t)mb.W * mb.H) return;
+    const int y = (int)(t / mb.W), x = (int)(t - (int64_t)y * mb.W);
+    const int T = mb.T, S = T + 1, SS = S * S * C;
+    const int tx = x / T, ty = y / T, lx = x - tx * T, ly = y - ty * T;
+    const uint32_t* off = mb.bins + mb.nb;
+    float v[C];
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) v[ch] = 0.f;
+    auto add = [&](int bx, int by, int ix, int iy) {
+        const int b = by * mb.nbx + bx;
+        const uint32_t a = off[b], e = off[b + 1];
+        if (a == e) return;
+        for (uint32_t c = a / ACC_CHUNK; c <= (e - 1) / ACC_CHUNK; ++c) {
+            const float* p = mb.stage + (size_t)(c + b) * SS + ((size_t)iy * S + ix) * C;
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch) v[ch] += p[ch];
+        }
+    };
+    add(tx, ty, lx, ly);
+    if (lx == 0 && tx > 0) add(tx - 1, ty, T, ly);
+    if (ly == 0 && ty > 0) add(tx, ty - 1, lx, T);
+    if (lx == 0 && ly == 0 && tx > 0 && ty > 0) add(tx - 1, ty - 1, T, T);
+    float* o = out + (size_t)t * stride;
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch)
+        if (v[ch] != 0.f) o[ch] += v[ch];
+}
+
 // ---------------------------------------------------------------- replay from records
 // One bounce of the replay when the forward kept its path records: the vertex's leaf and
 // the visibility of its shadow rays are read instead of traced.  Shading, the
@@ -569,7 +836,16 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
                 }
             }
         }
-        if (UNI) {
+        if (UNI && aq.tb.rec) {   // records for the binned flush (direct atomics if full)
+            const bool to_e = e_on && aq.eb.rec;
+            const bool pred[3] = {a_on, b_on, to_e};
+            uint32_t* const ctr[3] = {aq.tb.count, aq.tb.count, aq.eb.count};
+            uint32_t at[3];
+            block_append<3>(pred, ctr, at);
+            if (a_on && !put_tex_rec(aq.tb, at[0], a_u, a_v, ag)) scatter_tex_lane(*rp, a_u, a_v, ag);
+            if (b_on && !put_tex_rec(aq.tb, at[1], b_u, b_v, bg)) scatter_tex_lane(*rp, b_u, b_v, bg);
+            if (e_on && !(to_e && put_ep_rec(aq.eb, at[2], e_pu, e_pv, eg))) scatter_ep_lane(*rp, e_pu, e_pv, eg);
+        } else if (UNI) {
             scatter_tex(*rp, a_on, a_u, a_v, ag);
             scatter_tex(*rp, b_on, b_u, b_v, bg);
             if (rp->dEp) scatter_ep(*rp, e_on, e_pu, e_pv, eg);
@@ -701,6 +977,30 @@ void launch_adj_replay(const Launch& l, const Queues& q, const AdjQueues& aq, in
     const dim3 g(grid_cap(l, n_upper, BLOCK)), b(BLOCK);
     if (table) hipLaunchKernelGGL((k_adj_replay<false>), g, b, 0, l.st, q, aq, cur, depth, uni, table);
     else hipLaunchKernelGGL((k_adj_replay<true>), g, b, 0, l.st, q, aq, cur, depth, uni, table);
+}
+bool map_tiling(int W, int H, int& T, int& nbx, int& nby) {
+    for (int t = 8; t <= MAP_MAX_T; t *= 2) {
+        T = t;
+        nbx = (W + t - 1) / t;
+        nby = (H + t - 1) / t;
+        if ((int64_t)nbx * nby <= 1024) return true;
+    }
+    return (int64_t)nbx * nby <= MAP_MAX_BINS;
+}
+template <int C, int RS>
+static void flush_one(const Launch& l, const MapBins& mb, float* out, int stride) {
+    const unsigned g = (unsigned)((mb.cap + BIN_CHUNK - 1) / BIN_CHUNK);
+    hipLaunchKernelGGL((k_bin_hist<C, RS>), dim3(g), dim3(256), 0, l.st, mb);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, l.st, mb);
+    hipLaunchKernelGGL(k_bin_place<RS>, dim3(g), dim3(256), 0, l.st, mb);
+    hipLaunchKernelGGL((k_bin_accum<C, RS>), dim3((unsigned)((mb.cap + ACC_CHUNK - 1) / ACC_CHUNK)), dim3(256), 0,
+                       l.st, mb);
+    hipLaunchKernelGGL(k_bin_gather<C>, dim3(grid_of((int64_t)mb.W * mb.H, 256)), dim3(256), 0, l.st, mb, out,
+                       stride);
+}
+void launch_map_flush(const Launch& l, const AdjQueues& aq, const ReqDesc& r) {
+    if (aq.tb.rec && r.d_tex) flush_one<5, TEX_RS>(l, aq.tb, r.d_tex, 5);
+    if (aq.eb.rec && r.dEp) flush_one<3, EP_RS>(l, aq.eb, r.dEp, 4);
 }
 void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* d_albedo, float* d_rough,
                        float* d_spec, float* d_scalars, float* acc) {

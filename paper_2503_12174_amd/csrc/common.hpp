@@ -277,17 +277,29 @@ struct Bilin {
     int i00, i10, i01, i11;
     double w00, w10, w01, w11;
 };
+// Corner texels (clamped to the map) and fractional offsets of a bilinear lookup at
 // x, y in texel units with texel (i, j) centred at (i, j)
-__device__ __forceinline__ Bilin bilinear(double x, double y, int W, int H) {
+struct Corners {
+    int x0, x1, y0, y1;
+    double ax, ay;
+};
+__device__ __forceinline__ Corners bilinear_corners(double x, double y, int W, int H) {
     const double fx = floor(x), fy = floor(y);
-    const double ax = x - fx, ay = y - fy;
+    Corners c;
+    c.ax = x - fx;
+    c.ay = y - fy;
     const double cx = fmin(fmax(fx, -2.0), (double)W + 1.0), cy = fmin(fmax(fy, -2.0), (double)H + 1.0);
-    int x0 = (int)cx, y0 = (int)cy;
-    int x1 = x0 + 1, y1 = y0 + 1;
-    x0 = min(max(x0, 0), W - 1);
-    x1 = min(max(x1, 0), W - 1);
-    y0 = min(max(y0, 0), H - 1);
-    y1 = min(max(y1, 0), H - 1);
+    const int x0 = (int)cx, y0 = (int)cy;
+    c.x0 = min(max(x0, 0), W - 1);
+    c.x1 = min(max(x0 + 1, 0), W - 1);
+    c.y0 = min(max(y0, 0), H - 1);
+    c.y1 = min(max(y0 + 1, 0), H - 1);
+    return c;
+}
+__device__ __forceinline__ Bilin bilinear(double x, double y, int W, int H) {
+    const Corners c = bilinear_corners(x, y, W, H);
+    const int x0 = c.x0, x1 = c.x1, y0 = c.y0, y1 = c.y1;
+    const double ax = c.ax, ay = c.ay;
     Bilin b;
     b.i00 = y0 * W + x0;
     b.i10 = y0 * W + x1;

@@ -60,6 +60,26 @@ constexpr int SPILL = 64 - SHORT_STACK;        // overflow entries per thread
 constexpr int TRACE_TB = 128;                  // threads per workgroup of the traversal kernels
 inline size_t spill_ints(int grid_cap) { return (size_t)grid_cap * TRACE_TB * SPILL; }
 
+// Binned accumulation of the cotangent of one texel map (BRDF maps or E_p): the replay
+// writes one record per (vertex, map) -- bilinear base texel and offsets plus the C
+// cotangent values -- instead of 4 x C global atomics; a flush groups the records by
+// T x T texel tile (counting sort), accumulates every tile in LDS and adds the tiles
+// into the map with plain stores.
+constexpr int MAP_MAX_BINS = 4096;
+constexpr int MAP_MAX_T = 16;   // tile side 8 or 16: maps up to 1024 x 1024 are binned
+constexpr int BIN_DEPTHS = 4;   // replay depths between flushes (record capacity follows)
+constexpr int ACC_CHUNK = 4096; // records per workgroup of the accumulation; the stage holds
+                                // ceil(cap / ACC_CHUNK) + nb blocks of (T + 1)^2 x C floats
+struct MapBins {
+    float* rec;          // records of rs floats (null: binning off, the replay scatters directly)
+    float* sorted;       // the same records grouped by tile
+    float* stage;        // per (chunk, tile) pair (T + 1)^2 x C sums (tile plus one halo row/column)
+    uint32_t* count;     // records appended since the last flush (may exceed cap)
+    uint32_t* bins;      // counts[nb], offsets[nb + 1], fill[nb], largest |value| (float bits)
+    int64_t cap;         // record capacity
+    int W, H, T, nbx, nby, nb;
+};
+
 // adjoint additions (see adjoint.hip)
 struct AdjQueues {
     float4* rl[2];     // remaining radiance L_r of the path (rgb, -), follows the path queue
@@ -72,6 +92,8 @@ struct AdjQueues {
     float* pns[2];     // replay: pending next-event specular cotangent
     float4* pend[2];   // pending bounce: (u, v, dr, dsp) cotangent scale of the previous vertex
     float4* penda[2];  // pending bounce: albedo cotangent scale rgb
+    MapBins tb;        // BRDF-map cotangent records (C = 5, 8 floats per record)
+    MapBins eb;        // E_p cotangent records (C = 3, 6 floats per record)
 };
 
 struct Launch {
@@ -110,6 +132,10 @@ void launch_adj_shadow(const Launch& l, const Queues& q, const AdjQueues& aq, in
 // for the recorded visibilities, bounce
 void launch_adj_replay(const Launch& l, const Queues& q, const AdjQueues& aq, int cur, int depth, const ReqDesc& uni,
                        const ReqDesc* table, int64_t n_upper);
+// adds the binned records of tb / eb into r.d_tex / r.dEp and empties the bins
+void launch_map_flush(const Launch& l, const AdjQueues& aq, const ReqDesc& r);
+// tile side and bin count for a W x H map (false: too many tiles, bin nothing)
+bool map_tiling(int W, int H, int& T, int& nbx, int& nby);
 // PRF backward, map de-interleave and scalar gradients; acc: 20 floats (see adjoint.hip)
 void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* d_albedo, float* d_rough,
                        float* d_spec, float* d_scalars, float* acc);

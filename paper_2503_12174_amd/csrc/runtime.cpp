@@ -110,7 +110,48 @@ bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues&
         aq.pns[k] = (float*)take(4 * c);
     }
     aq.delta = (float4*)take(16 * c);
+    aq.tb = MapBins{};
+    aq.eb = MapBins{};
     return true;
+}
+
+// Record buffers of the binned map-cotangent flush for a W x H map with C values per
+// texel; leaves mb empty (direct atomics) when the map has too many tiles or the
+// scratch allocation fails.
+void make_map_bins(dpcs_context ctx, const Launch& l, MapBins& mb, const char* name, int W, int H, int C, int RS,
+                   int64_t cap) {
+    mb = MapBins{};
+    int T = 0, nbx = 0, nby = 0;
+    if (!map_tiling(W, H, T, nbx, nby)) return;
+    cap = std::min<int64_t>(cap, int64_t(1) << 31);
+    const int nb = nbx * nby;
+    const size_t rec = 4 * (size_t)RS * cap, stage = 4 * (size_t)((cap + ACC_CHUNK - 1) / ACC_CHUNK + nb) * (T + 1) * (T + 1) * C;
+    const size_t bytes = 2 * rec + stage + 4 * (3 * (size_t)nb + 2) + 8 * 256;
+    dpcs_status st = DPCS_OK;
+    char* b = (char*)scratch(ctx, name, bytes, &st);
+    if (!b) {   // run without binning
+        ctx->err.clear();
+        return;
+    }
+    auto take = [&](size_t n) {
+        char* p = b;
+        b += (n + 255) & ~size_t(255);
+        return (void*)p;
+    };
+    mb.rec = (float*)take(rec);
+    mb.sorted = (float*)take(rec);
+    mb.stage = (float*)take(stage);
+    mb.count = (uint32_t*)take(4);
+    mb.bins = (uint32_t*)take(4 * (3 * (size_t)nb + 2));
+    mb.cap = cap;
+    mb.W = W;
+    mb.H = H;
+    mb.T = T;
+    mb.nbx = nbx;
+    mb.nby = nby;
+    mb.nb = nb;
+    launch_zero(l, (float*)mb.count, 1);
+    launch_zero(l, (float*)mb.bins, 3 * (int64_t)nb + 2);
 }
 
 static void inv3(const double* m, double* o) {
@@ -646,6 +687,11 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
             pr = prof_begin(ctx, DPCS_STAGE_ADJ_SHADE);
             launch_adj_replay(l, q, aq, cur, d, r, nullptr, n);
             prof_end(ctx, pr, q.cnt + cur, 0);
+            if ((aq.tb.rec || aq.eb.rec) && ((d + 1) % BIN_DEPTHS == 0 || d == r.max_depth - 1)) {
+                pr = prof_begin(ctx, DPCS_STAGE_OTHER);
+                launch_map_flush(l, aq, r);
+                prof_end(ctx, pr, nullptr, 0);
+            }
             cur ^= 1;
         }
         return;

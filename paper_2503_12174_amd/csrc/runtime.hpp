@@ -75,6 +75,8 @@ unsigned long long* prof_stats(dpcs_context ctx, int stage);
 // path queues for `cap` paths carved from one scratch buffer (prefix selects the buffer)
 bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpcs_status* st);
 bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues& aq, dpcs_status* st);
+void make_map_bins(dpcs_context ctx, const Launch& l, MapBins& mb, const char* name, int W, int H, int C, int RS,
+                   int64_t cap);
 
 // PRF'd projector irradiance and packed maps of one request in scratch (tag selects the buffers)
 bool prepare_request(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, const char* tag, dpcs_status* st);

@@ -389,6 +389,8 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     s->q.hit = (int*)take(4 * c);
     s->q.L = (float4*)take(16 * c);
     s->aq.delta = (float4*)take(16 * c);
+    s->aq.tb = MapBins{};   // the request loop replays by tracing and scatters directly
+    s->aq.eb = MapBins{};
     s->q.cnt = (uint32_t*)take(16);
     s->q.spill = (int*)take(4 * spill_ints(ctx->grid_cap));
     s->q.cap = s->cap;

@@ -44,8 +44,8 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     const int64_t npix = (int64_t)r.Wc * r.Hc;
     const int64_t cap = std::min<int64_t>(std::max<int64_t>(ctx->capacity, r.spp), npix * r.spp);
     const int64_t ppw = std::max<int64_t>(1, cap / r.spp);
-    Queues q;
-    AdjQueues aq;
+    Queues q{};
+    AdjQueues aq{};
     if (!make_queues(ctx, "fwd.queues", ppw * r.spp, q, &st)) return st;
     if (!make_adj_queues(ctx, "vjp.queues", ppw * r.spp, aq, &st)) return st;
     // Path records: the caller's (whole image, from the forward call that produced
@@ -58,6 +58,11 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     if (own_rec) {
         wave_rec = (uint32_t*)scratch(ctx, "vjp.records", sizeof(uint32_t) * (size_t)(ppw * r.spp) * r.max_depth, &st);
         if (!wave_rec) return st;
+    }
+    if (own_rec || path_records) {   // the replay bins its map cotangents
+        const int64_t k = std::min(r.max_depth, BIN_DEPTHS);
+        make_map_bins(ctx, l, aq.tb, "vjp.tex_bins", r.tw, r.th, 5, 8, ppw * r.spp * (k + 1));
+        make_map_bins(ctx, l, aq.eb, "vjp.ep_bins", r.Wp, r.Hp, 3, 6, ppw * r.spp * k);
     }
     for (int64_t a = 0; a < npix; a += ppw) {
         const uint32_t b = (uint32_t)std::min(npix, a + ppw);
