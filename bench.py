@@ -38,10 +38,11 @@ def kernel_hash() -> str:
 
 
 # algorithmic bytes of one closest-hit query in this layout: path origin and
-# direction read (PathO + PathD = 64 B), each visited BVH2 node (64 B), each tested
-# triangle record (48 B), the hit index written (4 B)
+# direction read (PathO + PathD = 64 B), each visited BVH node (64 B binary, 128 B
+# 4-wide), each tested triangle record (48 B), the hit index written (4 B)
 RAY_IO_BYTES = 64 + 4
-NODE_BYTES = 64
+NODE_BYTES = 64       # binary BVH node: two child boxes + two child references
+NODE4_BYTES = 128     # 4-wide BVH node: four child boxes (SoA) + four references + pad
 TRI_BYTES = 48
 
 
@@ -230,7 +231,8 @@ def main():
         tr = prof["trace"]
         nodes_per_ray = vis["trace"]["nodes"] / max(vis["trace"]["items"], 1)
         tris_per_ray = vis["trace"]["tris"] / max(vis["trace"]["items"], 1)
-        per_ray = RAY_IO_BYTES + NODE_BYTES * nodes_per_ray + TRI_BYTES * tris_per_ray
+        node_bytes = NODE4_BYTES if info.wide_nodes else NODE_BYTES
+        per_ray = RAY_IO_BYTES + node_bytes * nodes_per_ray + TRI_BYTES * tris_per_ray
         rays_per_launch = tr["items"] / max(tr["launches"], 1)
         avg_ms = tr["ms"] / max(tr["launches"], 1)
         achieved = per_ray * rays_per_launch / (avg_ms * 1e-3) / 1e9
@@ -244,7 +246,7 @@ def main():
                 traffic = tf.get("bytes_per_launch")
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_trace (closest-hit BVH2 traversal)",
+                "kernel": "k_trace (closest-hit traversal, %s BVH)" % ("4-wide" if info.wide_nodes else "binary"),
                 "bytes_per_ray": round(per_ray, 1), "nodes_per_ray": round(nodes_per_ray, 2),
                 "tris_per_ray": round(tris_per_ray, 2), "rays_per_launch": round(rays_per_launch),
                 "avg_launch_ms": round(avg_ms, 4)}

@@ -93,7 +93,7 @@ typedef struct {
     int32_t num_triangles;
     int32_t num_nodes;          /* binary BVH internal nodes */
     int32_t max_depth;          /* deepest leaf */
-    int32_t reserved;
+    int32_t wide_nodes;         /* nodes of the 4-wide BVH the renderer traverses (0: binary) */
     int64_t device_bytes;       /* resident bytes (BVH + triangle records + attributes) */
     double build_ms;            /* GPU time of the BVH build */
     float bbox_lo[3], bbox_hi[3];
@@ -190,9 +190,11 @@ DPCS_API dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const d
 
 /* ------------------------------------------------------------ debug/test */
 
-/* Closest hits of n rays (device: rays n x 8 = o.xyz, d.xyz, tmax, skip prim as float),
- * through the BVH (use_bvh = 1) or by brute force over all triangles (0).
- * Output device arrays: prim (n), t/b1/b2 (n each; may be NULL). */
+/* Hits of n rays (device: rays n x 8 = o.xyz, d.xyz, tmax, skip prim as float).
+ * use_bvh: 0 closest hit by brute force over all triangles, 1 closest hit through the
+ * BVH the renderer traverses (4-wide when built), 2 closest hit through the binary
+ * BVH, 3 any hit (shadow query) through the renderer's BVH, 4 any hit by brute force.
+ * Output device arrays: prim (n, -1 on a miss), t/b1/b2 (n each; may be NULL). */
 DPCS_API dpcs_status dpcs_debug_intersect(dpcs_context ctx, dpcs_scene scene, const float* rays, int64_t n,
                                  int32_t use_bvh, int32_t* prim, float* t, float* b1, float* b2);
 /* Philox4x32-10 of n counters (device: ctr n x 4, out n x 4). */

@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(TB) k_adj_shadow(Queues q, AdjQueues aq, int w
         if (live) {
             Hit h;
             Visits vis;
-            occ = traverse<true, SHORT_STACK, TB>(r.nodes, r.tris, xyz(o), xyz(d), r.tmin, q.st[which][i],
+            occ = trace_ray<true, SHORT_STACK, TB>(r.nodes4, r.nodes, r.tris, xyz(o), xyz(d), r.tmin, q.st[which][i],
                                                   __float_as_int(d.w), h, stack + threadIdx.x, spill, vis);
             if (q.stats) {
                 atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);

@@ -142,9 +142,9 @@ void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* 
 void launch_zero(const Launch& l, float* p, int64_t n);
 
 // debug
-void launch_debug_intersect(const Launch& l, const float4* nodes, const float4* tris, const int* leaf_of_prim, int nt,
-                            float tmin, const float* rays, int64_t n, int use_bvh, int stack, int32_t* prim,
-                            float* t, float* b1, float* b2);
+void launch_debug_intersect(const Launch& l, const float4* nodes4, const float4* nodes, const float4* tris,
+                            const int* leaf_of_prim, int nt, float tmin, const float* rays, int64_t n, int mode,
+                            int32_t* prim, float* t, float* b1, float* b2);
 void launch_debug_philox(const Launch& l, uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out);
 
 }  // namespace dpcs

@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(TB) k_trace(Queues q, int cur, ReqDesc uni, co
         const ReqDesc& r = sel<UNI>(uni, table, o.slot);
         Hit h;
         Visits vis;
-        traverse<false, SHORT_STACK, TB>(r.nodes, r.tris, v3((float)o.x, (float)o.y, (float)o.z),
+        trace_ray<false, SHORT_STACK, TB>(r.nodes4, r.nodes, r.tris, v3((float)o.x, (float)o.y, (float)o.z),
                                          v3((float)d.x, (float)d.y, (float)d.z), r.tmin, __builtin_inff(), o.skip,
                                          h, stack + threadIdx.x, spill, vis);
         q.hit[i] = h.leaf;
@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(TB) k_shadow(Queues q, int which, int depth, R
         const ReqDesc& r = sel<UNI>(uni, table, __float_as_int(o.w));
         Hit h;
         Visits vis;
-        const bool occ = traverse<true, SHORT_STACK, TB>(r.nodes, r.tris, xyz(o), xyz(d), r.tmin, q.st[which][i],
+        const bool occ = trace_ray<true, SHORT_STACK, TB>(r.nodes4, r.nodes, r.tris, xyz(o), xyz(d), r.tmin, q.st[which][i],
                                                          __float_as_int(d.w), h, stack + threadIdx.x, spill, vis);
         if (q.stats) {
             atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
@@ -269,11 +269,14 @@ __global__ void k_finalize(Queues q, ReqDesc r, uint32_t p0, uint32_t p1) {
 }
 
 // ---------------------------------------------------------------- debug
-// full 64-entry LDS stack (no spill region needed: depth <= 64 is checked on the host)
-__global__ void __launch_bounds__(TB) k_debug_intersect(const float4* __restrict__ nodes,
+// full 64-entry LDS stack (no spill region needed: the host checks the stack bound).
+// mode: 0 brute force, 1 the BVH the renderer uses (4-wide when built), 2 the binary
+// BVH, 3 any hit on the renderer's BVH, 4 any hit by brute force
+__global__ void __launch_bounds__(TB) k_debug_intersect(const float4* __restrict__ nodes4,
+                                                        const float4* __restrict__ nodes,
                                                         const float4* __restrict__ tris,
                                                         const int* __restrict__ leaf_of_prim, int nt, float tmin,
-                                                        const float* __restrict__ rays, int64_t n, int use_bvh,
+                                                        const float* __restrict__ rays, int64_t n, int mode,
                                                         int32_t* prim, float* t, float* b1, float* b2) {
     __shared__ int stack[MAX_STACK * TB];
     const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
@@ -282,9 +285,15 @@ __global__ void __launch_bounds__(TB) k_debug_intersect(const float4* __restrict
     const V3 o = v3(ry[0], ry[1], ry[2]), d = v3(ry[3], ry[4], ry[5]);
     Hit h;
     Visits vis;
-    if (use_bvh)
-        traverse<false, MAX_STACK, TB>(nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, stack + threadIdx.x, nullptr,
-                                       vis);
+    int* st = stack + threadIdx.x;
+    if (mode == 1)
+        trace_ray<false, MAX_STACK, TB>(nodes4, nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, st, nullptr, vis);
+    else if (mode == 2)
+        traverse<false, MAX_STACK, TB>(nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, st, nullptr, vis);
+    else if (mode == 3)
+        trace_ray<true, MAX_STACK, TB>(nodes4, nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, st, nullptr, vis);
+    else if (mode == 4)
+        brute_force<true>(tris, leaf_of_prim, nt, o, d, tmin, ry[6], (int)ry[7], h);
     else
         brute_force<false>(tris, leaf_of_prim, nt, o, d, tmin, ry[6], (int)ry[7], h);
     prim[i] = h.prim;
@@ -353,12 +362,12 @@ void launch_finalize(const Launch& l, const Queues& q, const ReqDesc& r, const R
                      uint32_t p1) {
     if (p1 > p0) hipLaunchKernelGGL(k_finalize, dim3(grid_of(p1 - p0, 256)), dim3(256), 0, l.st, q, r, p0, p1);
 }
-void launch_debug_intersect(const Launch& l, const float4* nodes, const float4* tris, const int* leaf_of_prim, int nt,
-                            float tmin, const float* rays, int64_t n, int use_bvh, int stack, int32_t* prim,
-                            float* t, float* b1, float* b2) {
+void launch_debug_intersect(const Launch& l, const float4* nodes4, const float4* nodes, const float4* tris,
+                            const int* leaf_of_prim, int nt, float tmin, const float* rays, int64_t n, int mode,
+                            int32_t* prim, float* t, float* b1, float* b2) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_debug_intersect, dim3(grid_of(n, TB)), dim3(TB), 0, l.st, nodes, tris, leaf_of_prim, nt, tmin,
-                       rays, n, use_bvh, prim, t, b1, b2);
+    hipLaunchKernelGGL(k_debug_intersect, dim3(grid_of(n, TB)), dim3(TB), 0, l.st, nodes4, nodes, tris, leaf_of_prim,
+                       nt, tmin, rays, n, mode, prim, t, b1, b2);
 }
 void launch_debug_philox(const Launch& l, uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out) {
     if (n > 0)

@@ -235,6 +235,7 @@ bool fill_desc(dpcs_context, ReqDesc& r, const dpcs_render_params* p, dpcs_scene
     r.Wp = p->projector.width;
     r.Hp = p->projector.height;
     r.nodes = sc->nodes;
+    r.nodes4 = sc->nodes4;
     r.tris = sc->tris;
     r.tri_uv = sc->tri_uv;
     r.emission = sc->emission;
@@ -355,6 +356,90 @@ extern "C" dpcs_status dpcs_context_set_capacity(dpcs_context ctx, int64_t paths
 }
 
 // ====================================================================== scene
+// 4-wide BVH from the binary one (host, after the device build): each node starts from
+// a binary node's two children and keeps opening the internal child with the largest
+// surface area until it holds four.  Leaves stay single triangles.  stack_bound is the
+// most traversal stack entries any ray can hold: along a root-to-node path, each node
+// pushes at most (its internal children - 1).
+static std::vector<float4> collapse4(const std::vector<float4>& bn, int& stack_bound, int& depth4) {
+    struct Kid {
+        int ref;
+        float b[6];   // lo.xyz, hi.xyz
+    };
+    auto kid = [&](int node, int k) {
+        const float4* n = &bn[4 * (size_t)node];
+        const float v[12] = {n[0].x, n[0].y, n[0].z, n[0].w, n[1].x, n[1].y, n[1].z, n[1].w,
+                             n[2].x, n[2].y, n[2].z, n[2].w};
+        Kid c;
+        for (int j = 0; j < 6; ++j) c.b[j] = v[6 * k + j];
+        float r;
+        std::memcpy(&r, k == 0 ? &n[3].x : &n[3].y, 4);
+        std::memcpy(&c.ref, &r, 4);
+        return c;
+    };
+    auto area = [](const Kid& c) {
+        const double dx = c.b[3] - c.b[0], dy = c.b[4] - c.b[1], dz = c.b[5] - c.b[2];
+        return dx * dy + dy * dz + dz * dx;
+    };
+    std::vector<float4> out;
+    auto alloc = [&]() {
+        out.resize(out.size() + 8, make_float4(0.f, 0.f, 0.f, 0.f));
+        return (int)(out.size() / 8 - 1);
+    };
+    struct Work {
+        int bin, node, acc, depth;
+    };
+    std::vector<Work> work{{0, alloc(), 0, 1}};
+    stack_bound = 0;
+    depth4 = 0;
+    while (!work.empty()) {
+        const Work w = work.back();
+        work.pop_back();
+        std::vector<Kid> kids{kid(w.bin, 0), kid(w.bin, 1)};
+        while (kids.size() < 4) {
+            int best = -1;
+            double ba = -1.0;
+            for (size_t j = 0; j < kids.size(); ++j)
+                if (kids[j].ref >= 0 && area(kids[j]) > ba) {
+                    ba = area(kids[j]);
+                    best = (int)j;
+                }
+            if (best < 0) break;
+            const int c = kids[best].ref;
+            kids.erase(kids.begin() + best);
+            kids.push_back(kid(c, 0));
+            kids.push_back(kid(c, 1));
+        }
+        int internal = 0;
+        for (const Kid& k : kids) internal += k.ref >= 0;
+        const int acc = w.acc + std::max(internal - 1, 0);
+        stack_bound = std::max(stack_bound, acc);
+        depth4 = std::max(depth4, w.depth);
+        int refs[4];
+        float box[6][4];
+        for (int j = 0; j < 4; ++j) {
+            if (j < (int)kids.size()) {
+                for (int a = 0; a < 6; ++a) box[a][j] = kids[j].b[a];
+                if (kids[j].ref >= 0) {
+                    refs[j] = alloc();
+                    work.push_back({kids[j].ref, refs[j], acc, w.depth + 1});
+                } else {
+                    refs[j] = kids[j].ref;
+                }
+            } else {
+                for (int a = 0; a < 6; ++a) box[a][j] = 0.f;
+                refs[j] = (int)0x80000000;   // empty slot
+            }
+        }
+        float4* o = &out[8 * (size_t)w.node];
+        for (int a = 0; a < 6; ++a) o[a] = make_float4(box[a][0], box[a][1], box[a][2], box[a][3]);
+        float rf[4];
+        std::memcpy(rf, refs, 16);
+        o[6] = make_float4(rf[0], rf[1], rf[2], rf[3]);
+    }
+    return out;
+}
+
 extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc* m, dpcs_scene* out) {
     if (!ctx || !m || !out) return DPCS_E_INVALID;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
@@ -437,6 +522,7 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
     };
     auto destroy_scene = [&]() {
         hipFree(sc->nodes);
+        if (sc->nodes4) hipFree(sc->nodes4);
         hipFree(sc->tris);
         hipFree(sc->tri_uv);
         if (sc->emission) hipFree(sc->emission);
@@ -578,6 +664,33 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
         destroy_scene();
         return fail(ctx, DPCS_E_UNSUPPORTED, "BVH deeper than 64 levels");
     }
+    // 4-wide BVH for the traversal kernels, when its worst-case stack fits
+    if (nt > 1) {
+        std::vector<float4> bn(4 * (size_t)ni);
+        hipError_t e4 = hipMemcpy(bn.data(), sc->nodes, sizeof(float4) * bn.size(), hipMemcpyDeviceToHost);
+        if (e4 == hipSuccess) {
+            int bound = 0, depth4 = 0;
+            const std::vector<float4> n4 = collapse4(bn, bound, depth4);
+            if (bound <= MAX_STACK) {
+                e4 = hipMalloc((void**)&sc->nodes4, sizeof(float4) * n4.size());
+                if (e4 == hipSuccess)
+                    e4 = hipMemcpy(sc->nodes4, n4.data(), sizeof(float4) * n4.size(), hipMemcpyHostToDevice);
+                if (e4 == hipSuccess) {
+                    sc->nnodes4 = (int)(n4.size() / 8);
+                    sc->bytes += (int64_t)sizeof(float4) * n4.size();
+                } else {
+                    hipGetLastError();
+                    if (sc->nodes4) hipFree(sc->nodes4);
+                    sc->nodes4 = nullptr;   // the binary BVH serves
+                }
+            }
+        }
+        if (e4 != hipSuccess) {
+            hip_ok(ctx, e4, "scene build (4-wide BVH)");
+            destroy_scene();
+            return DPCS_E_DEVICE;
+        }
+    }
     *out = sc;
     return DPCS_OK;
 }
@@ -587,6 +700,7 @@ extern "C" dpcs_status dpcs_scene_get_info(dpcs_scene s, dpcs_scene_info* out) {
     std::memset(out, 0, sizeof *out);
     out->num_triangles = s->nt;
     out->num_nodes = s->nnodes;
+    out->wide_nodes = s->nnodes4;
     out->max_depth = s->depth;
     out->device_bytes = s->bytes;
     out->build_ms = s->build_ms;
@@ -606,6 +720,7 @@ extern "C" dpcs_status dpcs_scene_destroy(dpcs_scene s) {
     hipSetDevice(ctx->device);
     hipStreamSynchronize(ctx->stream);
     hipFree(s->nodes);
+    if (s->nodes4) hipFree(s->nodes4);
     hipFree(s->tris);
     hipFree(s->tri_uv);
     if (s->emission) hipFree(s->emission);
@@ -762,8 +877,9 @@ extern "C" dpcs_status dpcs_debug_intersect(dpcs_context ctx, dpcs_scene scene, 
     hipSetDevice(ctx->device);
     (void)hipGetLastError();
     Launch l{ctx->stream, ctx->grid_cap};
-    launch_debug_intersect(l, scene->nodes, scene->tris, scene->leaf_of_prim, scene->nt, scene->tmin, rays, n, use_bvh,
-                           stack_for(scene), prim, t, b1, b2);
+    if (use_bvh < 0 || use_bvh > 4) return fail(ctx, DPCS_E_INVALID, "debug_intersect mode must be in 0..4");
+    launch_debug_intersect(l, scene->nodes4, scene->nodes, scene->tris, scene->leaf_of_prim, scene->nt, scene->tmin,
+                           rays, n, use_bvh, prim, t, b1, b2);
     return hip_ok(ctx, hipGetLastError(), "debug_intersect") ? DPCS_OK : DPCS_E_DEVICE;
 }
 

@@ -42,11 +42,12 @@ struct dpcs_context_s {
 struct dpcs_scene_s {
     dpcs_context ctx = nullptr;
     float4* nodes = nullptr;
+    float4* nodes4 = nullptr;              // 4-wide BVH, or null
     float4* tris = nullptr;
     float4* tri_uv = nullptr;
     float4* emission = nullptr;
     int* leaf_of_prim = nullptr;
-    int nt = 0, nnodes = 0, depth = 0;
+    int nt = 0, nnodes = 0, nnodes4 = 0, depth = 0;
     float tmin = 0.0f;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     int64_t bytes = 0;

@@ -4,7 +4,11 @@
 // tests two boxes.
 //   n0 = (lo0.x, lo0.y, lo0.z, hi0.x)  n1 = (hi0.y, hi0.z, lo1.x, lo1.y)
 //   n2 = (lo1.z, hi1.x, hi1.y, hi1.z)  n3 = (child0, child1, -, -) as int bits
-// child >= 0: internal node index; child < 0: leaf ~child (one triangle, leaf order).
+// BVH4 node (128 B, one cache line, 8 x float4): the four children's boxes as
+// structure of arrays, lo.x[4], lo.y[4], lo.z[4], hi.x[4], hi.y[4], hi.z[4], then the
+// four child references and 16 unused bytes.
+// child >= 0: internal node index; child < 0: leaf ~child (one triangle, leaf order);
+// WIDE_EMPTY: unused slot of a BVH4 node.
 // Triangle record (48 B): v0 (w = original triangle index bits), v1, v2.
 //
 // Closest hit: smallest t in (tmin, tmax); equal t -> smaller original triangle
@@ -112,7 +116,6 @@ __device__ __forceinline__ void load_tri(const float4* __restrict__ tris, int le
 // deeper entries -- rare with near-child-first order -- go to the workgroup's region of
 // global memory with the same interleaving (spill[k * TBK + tid]).  The host only
 // launches on trees of depth <= 64, so at most 64 entries are ever live.
-constexpr int MAX_STACK = 64;
 struct Visits {
     uint32_t nodes = 0, tris = 0;
 };
@@ -193,6 +196,122 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
     h.b1 = bb1;
     h.b2 = bb2;
     return best_leaf >= 0;
+}
+
+constexpr int WIDE_EMPTY = (int)0x80000000;
+
+// compare-exchange on (key, ref) pairs, smaller key first
+__device__ __forceinline__ void cmpx(float& ka, int& ra, float& kb, int& rb) {
+    if (kb < ka) {
+        const float k = ka;
+        ka = kb;
+        kb = k;
+        const int r = ra;
+        ra = rb;
+        rb = r;
+    }
+}
+
+// Same query on the 4-wide BVH: per node, four box tests; leaf children are tested at
+// once, internal children still in range are visited nearest first (the others pushed,
+// farthest first).  The host only builds a BVH4 whose worst-case stack fits MAX_STACK.
+template <bool ANY, int SHORT, int TBK>
+__device__ __forceinline__ bool traverse4(const float4* __restrict__ nodes, const float4* __restrict__ tris, V3 o,
+                                          V3 d, float tmin, float tmax, int skip, Hit& h, int* stack, int* spill,
+                                          Visits& vis) {
+    const BoxRay br = box_setup(o, d);
+    const WtRay wr = wt_setup(o, d);
+    float best_t = tmax;
+    int best_prim = 0x7fffffff, best_leaf = -1;
+    float bb1 = 0.f, bb2 = 0.f;
+    int sp = 0;
+    int node = 0;
+    while (true) {
+        ++vis.nodes;
+        const float4* nd = nodes + 8 * (size_t)node;
+        const float4 lx = nd[0], ly = nd[1], lz = nd[2], hx = nd[3], hy = nd[4], hz = nd[5];
+        const int4 cr = *reinterpret_cast<const int4*>(nd + 6);
+        const int cc[4] = {cr.x, cr.y, cr.z, cr.w};
+        float tc[4];
+        tc[0] = box_enter(br, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, tmin, best_t);
+        tc[1] = box_enter(br, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, tmin, best_t);
+        tc[2] = box_enter(br, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, tmin, best_t);
+        tc[3] = box_enter(br, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, tmin, best_t);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (cc[k] == WIDE_EMPTY) tc[k] = __builtin_inff();
+            if (cc[k] < 0 && tc[k] < __builtin_inff()) {
+                const int leaf = ~cc[k];
+                V3 v0, v1, v2;
+                int prim;
+                ++vis.tris;
+                load_tri(tris, leaf, v0, v1, v2, prim);
+                float t, b1, b2;
+                if (prim != skip && wt_intersect(wr, v0, v1, v2, t, b1, b2) && t > tmin &&
+                    (t < best_t || (t == best_t && best_leaf >= 0 && prim < best_prim))) {
+                    best_t = t;
+                    best_prim = prim;
+                    best_leaf = leaf;
+                    bb1 = b1;
+                    bb2 = b2;
+                    if (ANY) {
+                        h.t = t;
+                        h.leaf = leaf;
+                        h.prim = prim;
+                        h.b1 = b1;
+                        h.b2 = b2;
+                        return true;
+                    }
+                }
+            }
+        }
+        // internal children still in range (a missed box reports +inf)
+        float key[4];
+        int ref[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool in = cc[k] >= 0 && tc[k] < __builtin_inff() && tc[k] <= best_t;
+            key[k] = in ? tc[k] : __builtin_inff();
+            ref[k] = cc[k];
+        }
+        cmpx(key[0], ref[0], key[1], ref[1]);
+        cmpx(key[2], ref[2], key[3], ref[3]);
+        cmpx(key[0], ref[0], key[2], ref[2]);
+        cmpx(key[1], ref[1], key[3], ref[3]);
+        cmpx(key[1], ref[1], key[2], ref[2]);
+        if (key[0] < __builtin_inff()) {
+            node = ref[0];
+#pragma unroll
+            for (int k = 3; k >= 1; --k) {
+                if (!(key[k] < __builtin_inff())) continue;
+                if (sp < SHORT) stack[sp * TBK] = ref[k];
+                else if constexpr (SHORT < MAX_STACK) {
+                    if (sp < MAX_STACK) spill[(sp - SHORT) * TBK] = ref[k];
+                }
+                sp = sp < MAX_STACK ? sp + 1 : sp;
+            }
+        } else {
+            if (sp == 0) break;
+            --sp;
+            if constexpr (SHORT < MAX_STACK) node = sp < SHORT ? stack[sp * TBK] : spill[(sp - SHORT) * TBK];
+            else node = stack[sp * TBK];
+        }
+    }
+    h.t = best_t;
+    h.leaf = best_leaf;
+    h.prim = best_leaf >= 0 ? best_prim : -1;
+    h.b1 = bb1;
+    h.b2 = bb2;
+    return best_leaf >= 0;
+}
+
+// closest or any hit on the request's BVH (4-wide when built)
+template <bool ANY, int SHORT, int TBK>
+__device__ __forceinline__ bool trace_ray(const float4* __restrict__ nodes4, const float4* __restrict__ nodes,
+                                          const float4* __restrict__ tris, V3 o, V3 d, float tmin, float tmax,
+                                          int skip, Hit& h, int* stack, int* spill, Visits& vis) {
+    if (nodes4) return traverse4<ANY, SHORT, TBK>(nodes4, tris, o, d, tmin, tmax, skip, h, stack, spill, vis);
+    return traverse<ANY, SHORT, TBK>(nodes, tris, o, d, tmin, tmax, skip, h, stack, spill, vis);
 }
 
 // reference: every triangle in original order, same arithmetic and tie rule

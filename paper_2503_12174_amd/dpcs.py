@@ -33,7 +33,7 @@ class MeshDesc(C.Structure):
 
 class SceneInfo(C.Structure):
     _fields_ = [("num_triangles", C.c_int32), ("num_nodes", C.c_int32), ("max_depth", C.c_int32),
-                ("reserved", C.c_int32), ("device_bytes", C.c_int64), ("build_ms", C.c_double),
+                ("wide_nodes", C.c_int32), ("device_bytes", C.c_int64), ("build_ms", C.c_double),
                 ("bbox_lo", C.c_float * 3), ("bbox_hi", C.c_float * 3), ("tmin", C.c_float)]
 
 
@@ -272,8 +272,10 @@ def dpcs_render_vjp(ctx: Context, scene: Scene, params: RenderParams, proj_image
                                            _ptr(sample_radiance), _ptr(path_records), C.byref(g)))
 
 
-def dpcs_debug_intersect(ctx: Context, scene: Scene, rays, use_bvh: bool, prim, t=None, b1=None, b2=None):
-    return ctx.check(lib().dpcs_debug_intersect(ctx.h, scene.h, _ptr(rays), int(rays.shape[0]), int(bool(use_bvh)),
+def dpcs_debug_intersect(ctx: Context, scene: Scene, rays, use_bvh, prim, t=None, b1=None, b2=None):
+    """use_bvh: 0 / False brute force, 1 / True the renderer's BVH, 2 the binary BVH,
+    3 any hit through the renderer's BVH, 4 any hit by brute force."""
+    return ctx.check(lib().dpcs_debug_intersect(ctx.h, scene.h, _ptr(rays), int(rays.shape[0]), int(use_bvh),
                                                 _ptr(prim), _ptr(t), _ptr(b1), _ptr(b2)))
 
 

@@ -70,17 +70,24 @@ def test_bvh_traversal_equals_brute_force(name):
     rng = np.random.default_rng(1)
     rays = _rays_for(mesh, 20000, rng)
     r = dev(rays)
-    outs = []
-    for use_bvh in (True, False):
+    if name != "single":
+        assert sc.info().wide_nodes > 0   # the renderer traverses the 4-wide BVH
+    res = {}
+    for mode in (0, 1, 2, 3, 4):   # brute force, renderer's BVH, binary BVH, any hit (BVH, brute force)
         prim = torch.zeros(len(rays), dtype=torch.int32, device="cuda")
         t = torch.zeros(len(rays), dtype=torch.float32, device="cuda")
         b1 = torch.zeros_like(t)
         b2 = torch.zeros_like(t)
-        dpcs.dpcs_debug_intersect(ctx(), sc, r, use_bvh, prim, t, b1, b2)
+        dpcs.dpcs_debug_intersect(ctx(), sc, r, mode, prim, t, b1, b2)
         ctx().synchronize()
-        outs.append([x.cpu().numpy() for x in (prim, t, b1, b2)])
-    for a, b in zip(outs[0], outs[1]):
-        np.testing.assert_array_equal(a, b)
+        res[mode] = [x.cpu().numpy() for x in (prim, t, b1, b2)]
+    for mode in (1, 2):   # closest hit: bit-exact with brute force
+        for a, b in zip(res[mode], res[0]):
+            np.testing.assert_array_equal(a, b)
+    # any hit: the same occlusion decision (which triangle is reported may differ)
+    np.testing.assert_array_equal(res[3][0] >= 0, res[4][0] >= 0)
+    np.testing.assert_array_equal(res[3][0] >= 0, res[0][0] >= 0)
+    outs = [res[1], res[0]]
     assert (outs[0][0] >= 0).mean() > 0.3
     # and the brute force agrees with the FP64 oracle on rays far from every decision boundary
     w = synth.config1()
