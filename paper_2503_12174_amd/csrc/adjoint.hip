@@ -221,7 +221,11 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
                                                      const ReqDesc* __restrict__ table) {
     const int nxt = cur ^ 1;
     const uint32_t n = q.cnt[cur];
-    for (uint32_t base = blockIdx.x * BLOCK; base < n; base += gridDim.x * BLOCK) {
+    // one path per thread (the grid covers the queue): with no grid-stride loop no
+    // descriptor field is held across iterations, which saves ~60 VGPRs
+    const uint32_t base = blockIdx.x * BLOCK;
+    if (base >= n) return;   // uniform per workgroup
+    {
         const uint32_t i = base + threadIdx.x;
         bool cont = false, shp = false, she = false;
         PathO no{};
@@ -703,7 +707,11 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
                                                       const ReqDesc* __restrict__ table) {
     const int nxt = cur ^ 1;
     const uint32_t n = q.cnt[cur];
-    for (uint32_t base = blockIdx.x * BLOCK; base < n; base += gridDim.x * BLOCK) {
+    // one path per thread (the grid covers the queue): with no grid-stride loop no
+    // descriptor field is held across iterations, which saves ~60 VGPRs
+    const uint32_t base = blockIdx.x * BLOCK;
+    if (base >= n) return;   // uniform per workgroup
+    {
         const uint32_t i = base + threadIdx.x;
         bool cont = false;
         PathO no{};
@@ -962,7 +970,7 @@ void launch_adj_raygen(const Launch& l, const Queues& q, const AdjQueues& aq, co
 }
 void launch_adj_shade(const Launch& l, const Queues& q, const AdjQueues& aq, int cur, int depth, const ReqDesc& uni,
                       const ReqDesc* table, int64_t n_upper) {
-    const dim3 g(grid_cap(l, n_upper, BLOCK)), b(BLOCK);
+    const dim3 g(grid_of(n_upper, BLOCK)), b(BLOCK);
     if (table) hipLaunchKernelGGL((k_adj_shade<false>), g, b, 0, l.st, q, aq, cur, depth, uni, table);
     else hipLaunchKernelGGL((k_adj_shade<true>), g, b, 0, l.st, q, aq, cur, depth, uni, table);
 }
@@ -974,7 +982,7 @@ void launch_adj_shadow(const Launch& l, const Queues& q, const AdjQueues& aq, in
 }
 void launch_adj_replay(const Launch& l, const Queues& q, const AdjQueues& aq, int cur, int depth, const ReqDesc& uni,
                        const ReqDesc* table, int64_t n_upper) {
-    const dim3 g(grid_cap(l, n_upper, BLOCK)), b(BLOCK);
+    const dim3 g(grid_of(n_upper, BLOCK)), b(BLOCK);
     if (table) hipLaunchKernelGGL((k_adj_replay<false>), g, b, 0, l.st, q, aq, cur, depth, uni, table);
     else hipLaunchKernelGGL((k_adj_replay<true>), g, b, 0, l.st, q, aq, cur, depth, uni, table);
 }

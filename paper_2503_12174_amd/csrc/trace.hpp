@@ -237,33 +237,49 @@ __device__ __forceinline__ bool traverse4(const float4* __restrict__ nodes, cons
         tc[1] = box_enter(br, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, tmin, best_t);
         tc[2] = box_enter(br, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, tmin, best_t);
         tc[3] = box_enter(br, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, tmin, best_t);
+        // Leaf children whose box is hit.  Closest hit: every slot unrolled, so the
+        // triangle fetches of all four are in flight together.  Any hit: one test per
+        // pass of a loop, the wave runs it as often as its busiest lane needs.
+        uint32_t lm = 0u;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (cc[k] == WIDE_EMPTY) tc[k] = __builtin_inff();
-            if (cc[k] < 0 && tc[k] < __builtin_inff()) {
-                const int leaf = ~cc[k];
-                V3 v0, v1, v2;
-                int prim;
-                ++vis.tris;
-                load_tri(tris, leaf, v0, v1, v2, prim);
-                float t, b1, b2;
-                if (prim != skip && wt_intersect(wr, v0, v1, v2, t, b1, b2) && t > tmin &&
-                    (t < best_t || (t == best_t && best_leaf >= 0 && prim < best_prim))) {
-                    best_t = t;
-                    best_prim = prim;
-                    best_leaf = leaf;
-                    bb1 = b1;
-                    bb2 = b2;
-                    if (ANY) {
-                        h.t = t;
-                        h.leaf = leaf;
-                        h.prim = prim;
-                        h.b1 = b1;
-                        h.b2 = b2;
-                        return true;
-                    }
+            if (cc[k] < 0 && tc[k] < __builtin_inff()) lm |= 1u << k;
+        }
+        auto test_leaf = [&](int leaf) {
+            V3 v0, v1, v2;
+            int prim;
+            ++vis.tris;
+            load_tri(tris, leaf, v0, v1, v2, prim);
+            float t, b1, b2;
+            if (prim != skip && wt_intersect(wr, v0, v1, v2, t, b1, b2) && t > tmin &&
+                (t < best_t || (t == best_t && best_leaf >= 0 && prim < best_prim))) {
+                best_t = t;
+                best_prim = prim;
+                best_leaf = leaf;
+                bb1 = b1;
+                bb2 = b2;
+                return true;
+            }
+            return false;
+        };
+        if constexpr (ANY) {
+            while (lm) {
+                const int k = __builtin_ctz(lm);
+                lm &= lm - 1u;
+                if (test_leaf(~(k == 0 ? cc[0] : (k == 1 ? cc[1] : (k == 2 ? cc[2] : cc[3]))))) {
+                    h.t = best_t;
+                    h.leaf = best_leaf;
+                    h.prim = best_prim;
+                    h.b1 = bb1;
+                    h.b2 = bb2;
+                    return true;
                 }
             }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (lm & (1u << k)) test_leaf(~cc[k]);
         }
         // internal children still in range (a missed box reports +inf)
         float key[4];
