@@ -123,6 +123,41 @@ __device__ __forceinline__ void scatter_ep(const ReqDesc& r, bool active, double
     }
 }
 
+// ---------------------------------------------------------------- binned map cotangents
+// A record starts with one header word: base texel y0 * W + x0 of the bilinear corners
+// (bits 0..27), x1 - x0 (bit 28) and y1 - y0 (bit 29), then the offsets ax, ay and the
+// C cotangent values.
+constexpr int TEX_RS = 8, EP_RS = 6;   // floats per record (C = 5, C = 3)
+constexpr int BIN_CHUNK = 16384;       // records per workgroup in the counting passes
+
+__device__ __forceinline__ uint32_t map_head(const Corners& c, int W) {
+    return (uint32_t)(c.y0 * W + c.x0) | ((uint32_t)(c.x1 - c.x0) << 28) | ((uint32_t)(c.y1 - c.y0) << 29);
+}
+__device__ __forceinline__ int map_bin(const MapBins& mb, uint32_t head) {
+    const uint32_t base = head & 0x0fffffffu;
+    const int y0 = (int)(base / (uint32_t)mb.W), x0 = (int)(base - (uint32_t)y0 * (uint32_t)mb.W);
+    return (y0 / mb.T) * mb.nbx + x0 / mb.T;
+}
+// BRDF-map record at texture coordinate (u, v); false when the buffer is full
+__device__ __forceinline__ bool put_tex_rec(const MapBins& mb, uint32_t slot, double u, double v, const float* g) {
+    if ((int64_t)slot >= mb.cap) return false;
+    const Corners c = bilinear_corners(u * mb.W - 0.5, v * mb.H - 0.5, mb.W, mb.H);
+    float4* p = (float4*)(mb.rec + (size_t)slot * TEX_RS);
+    p[0] = make_float4(__uint_as_float(map_head(c, mb.W)), (float)c.ax, (float)c.ay, g[0]);
+    p[1] = make_float4(g[1], g[2], g[3], g[4]);
+    return true;
+}
+// E_p record at projector pixel position (pu, pv); false when the buffer is full
+__device__ __forceinline__ bool put_ep_rec(const MapBins& mb, uint32_t slot, double pu, double pv, const float* g) {
+    if ((int64_t)slot >= mb.cap) return false;
+    const Corners c = bilinear_corners(pu - 0.5, pv - 0.5, mb.W, mb.H);
+    float2* p = (float2*)(mb.rec + (size_t)slot * EP_RS);
+    p[0] = make_float2(__uint_as_float(map_head(c, mb.W)), (float)c.ax);
+    p[1] = make_float2((float)c.ay, g[0]);
+    p[2] = make_float2(g[1], g[2]);
+    return true;
+}
+
 // ---------------------------------------------------------------- per pixel
 // Eq. 5 backward: y = g_c w E_c, I_c = y^gamma_c;  Eq. 12 backward per sample
 __global__ void k_adj_pixel(Queues q, AdjQueues aq, ReqDesc r, uint32_t p0, uint32_t p1, const float* sample_L) {
@@ -330,9 +365,19 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
                 }
             }
         }
-        if (UNI) scatter_tex(*rp, pend_on, pend_u, pend_v, pend_g);
-        else if (pend_on) scatter_tex_lane(*rp, pend_u, pend_v, pend_g);
-        const uint32_t jn = wave_append(cont, &q.cnt[nxt]);
+        const bool to_rec = UNI && aq.tb.rec && pend_on;
+        const bool pred[4] = {cont, shp, she, to_rec};
+        uint32_t* const ctr[4] = {&q.cnt[nxt], &q.cnt[2], &q.cnt[3], aq.tb.count};
+        uint32_t at[4];
+        block_append<4>(pred, ctr, at);
+        const uint32_t jn = at[0], jp = at[1], je = at[2];
+        if (UNI && aq.tb.rec) {
+            if (pend_on && !put_tex_rec(aq.tb, at[3], pend_u, pend_v, pend_g)) scatter_tex_lane(*rp, pend_u, pend_v, pend_g);
+        } else if (UNI) {
+            scatter_tex(*rp, pend_on, pend_u, pend_v, pend_g);
+        } else if (pend_on) {
+            scatter_tex_lane(*rp, pend_u, pend_v, pend_g);
+        }
         if (cont) {
             q.po[nxt][jn] = no;
             q.pd[nxt][jn] = nd;
@@ -342,7 +387,6 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
             aq.penda[nxt][jn] = npenda;
         }
         const int next_idx = cont ? (int)jn : -1;
-        const uint32_t jp = wave_append(shp, &q.cnt[2]);
         if (shp) {
             pc.w = __int_as_float(next_idx);
             q.so[0][jp] = po;
@@ -354,7 +398,6 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
             aq.sa[0][jp] = pa;
             aq.ss[0][jp] = ps;
         }
-        const uint32_t je = wave_append(she, &q.cnt[3]);
         if (she) {
             ec.w = __int_as_float(next_idx);
             q.so[1][je] = eo;
@@ -418,6 +461,21 @@ __global__ void __launch_bounds__(TB) k_adj_shadow(Queues q, AdjQueues aq, int w
             }
             continue;
         }
+        if (aq.tb.rec) {   // one request, binned flush: records (direct atomics if full)
+            const bool vis = !occ;
+            const bool to_e = vis && which == 0 && r.dEp && aq.eb.rec;
+            const bool pred[2] = {vis, to_e};
+            uint32_t* const ctr[2] = {aq.tb.count, aq.eb.count};
+            uint32_t at[2];
+            block_append<2, TB>(pred, ctr, at);
+            if (vis && !put_tex_rec(aq.tb, at[0], x.z, x.w, gt)) scatter_tex_lane(r, x.z, x.w, gt);
+            if (vis && which == 0 && r.dEp) {
+                const float4 gE = aq.sg[which][i];
+                const float ge[3] = {gE.x, gE.y, gE.z};
+                if (!(to_e && put_ep_rec(aq.eb, at[1], x.x, x.y, ge))) scatter_ep_lane(r, x.x, x.y, ge);
+            }
+            continue;
+        }
         // one request: lanes of one wave sum shared texels before the atomics
         if (which == 0 && r.dEp) {   // d/dE_p at the four projector texels
             const float4 gE = aq.sg[which][ii];
@@ -426,41 +484,6 @@ __global__ void __launch_bounds__(TB) k_adj_shadow(Queues q, AdjQueues aq, int w
         }
         scatter_tex(r, !occ, x.z, x.w, gt);
     }
-}
-
-// ---------------------------------------------------------------- binned map cotangents
-// A record starts with one header word: base texel y0 * W + x0 of the bilinear corners
-// (bits 0..27), x1 - x0 (bit 28) and y1 - y0 (bit 29), then the offsets ax, ay and the
-// C cotangent values.
-constexpr int TEX_RS = 8, EP_RS = 6;   // floats per record (C = 5, C = 3)
-constexpr int BIN_CHUNK = 16384;       // records per workgroup in the counting passes
-
-__device__ __forceinline__ uint32_t map_head(const Corners& c, int W) {
-    return (uint32_t)(c.y0 * W + c.x0) | ((uint32_t)(c.x1 - c.x0) << 28) | ((uint32_t)(c.y1 - c.y0) << 29);
-}
-__device__ __forceinline__ int map_bin(const MapBins& mb, uint32_t head) {
-    const uint32_t base = head & 0x0fffffffu;
-    const int y0 = (int)(base / (uint32_t)mb.W), x0 = (int)(base - (uint32_t)y0 * (uint32_t)mb.W);
-    return (y0 / mb.T) * mb.nbx + x0 / mb.T;
-}
-// BRDF-map record at texture coordinate (u, v); false when the buffer is full
-__device__ __forceinline__ bool put_tex_rec(const MapBins& mb, uint32_t slot, double u, double v, const float* g) {
-    if ((int64_t)slot >= mb.cap) return false;
-    const Corners c = bilinear_corners(u * mb.W - 0.5, v * mb.H - 0.5, mb.W, mb.H);
-    float4* p = (float4*)(mb.rec + (size_t)slot * TEX_RS);
-    p[0] = make_float4(__uint_as_float(map_head(c, mb.W)), (float)c.ax, (float)c.ay, g[0]);
-    p[1] = make_float4(g[1], g[2], g[3], g[4]);
-    return true;
-}
-// E_p record at projector pixel position (pu, pv); false when the buffer is full
-__device__ __forceinline__ bool put_ep_rec(const MapBins& mb, uint32_t slot, double pu, double pv, const float* g) {
-    if ((int64_t)slot >= mb.cap) return false;
-    const Corners c = bilinear_corners(pu - 0.5, pv - 0.5, mb.W, mb.H);
-    float2* p = (float2*)(mb.rec + (size_t)slot * EP_RS);
-    p[0] = make_float2(__uint_as_float(map_head(c, mb.W)), (float)c.ax);
-    p[1] = make_float2((float)c.ay, g[0]);
-    p[2] = make_float2(g[1], g[2]);
-    return true;
 }
 
 // lanes of the wave whose (12-bit) bin equals this lane's, among the valid lanes

@@ -827,6 +827,11 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
             prof_end(ctx, pr, q.cnt + 2 + w, 0);
         }
         q.stats = nullptr;
+        if ((aq.tb.rec || aq.eb.rec) && ((d + 1) % BIN_DEPTHS == 0 || d == r.max_depth - 1)) {
+            pr = prof_begin(ctx, DPCS_STAGE_OTHER);
+            launch_map_flush(l, aq, r);
+            prof_end(ctx, pr, nullptr, 0);
+        }
         cur ^= 1;
     }
 }

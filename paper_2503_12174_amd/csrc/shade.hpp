@@ -27,11 +27,11 @@ __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
 
 // workgroup-aggregated append to NQ queues: one atomic per queue per workgroup
 // (instead of one per wave), lane order preserved within each wave.  Every thread of
-// the workgroup (BLOCK threads) must call it, with its predicates; idx[q] is the slot
-// of a thread whose pred[q] holds.
-template <int NQ>
+// the workgroup (NT threads) must call it, with its predicates; idx[q] is the slot of
+// a thread whose pred[q] holds.
+template <int NQ, int NT = BLOCK>
 __device__ __forceinline__ void block_append(const bool* pred, uint32_t* const* counter, uint32_t* idx) {
-    constexpr int NW = BLOCK / 64;
+    constexpr int NW = NT / 64;
     __shared__ uint32_t wcount[NQ][NW];
     __shared__ uint32_t wbase[NQ][NW];
     const int lane = __lane_id(), wv = threadIdx.x >> 6;

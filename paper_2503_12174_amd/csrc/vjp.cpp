@@ -59,9 +59,13 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
         wave_rec = (uint32_t*)scratch(ctx, "vjp.records", sizeof(uint32_t) * (size_t)(ppw * r.spp) * r.max_depth, &st);
         if (!wave_rec) return st;
     }
-    if (own_rec || path_records) {   // the replay bins its map cotangents
+    {   // the replay bins its map cotangents: per group of k depths at most k + 1 texture
+        // records per path (one per vertex, one more where a path ends) -- the re-tracing
+        // replay writes one per vertex and one per unoccluded shadow ray, at most 3 per
+        // vertex -- and one E_p record per vertex
         const int64_t k = std::min(r.max_depth, BIN_DEPTHS);
-        make_map_bins(ctx, l, aq.tb, "vjp.tex_bins", r.tw, r.th, 5, 8, ppw * r.spp * (k + 1));
+        const int64_t per = (own_rec || path_records) ? k + 1 : 3 * k;
+        make_map_bins(ctx, l, aq.tb, "vjp.tex_bins", r.tw, r.th, 5, 8, ppw * r.spp * per);
         make_map_bins(ctx, l, aq.eb, "vjp.ep_bins", r.Wp, r.Hp, 3, 6, ppw * r.spp * k);
     }
     for (int64_t a = 0; a < npix; a += ppw) {
