@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "path samples/s fwd and fwd+adjoint (1 GPU, ≤1e-4 rel err); p50/p99 relight latency"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_traffic_config2.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_traffic_corner50k_256px.md")
 KERNEL_SOURCES = ["render.hip", "trace.hpp", "shade.hpp", "common.hpp"]
 
 
@@ -61,7 +61,7 @@ def parse():
 
 
 def serving_bench(ctx, n_req, n_alone, warmup=20, rate=50.0):
-    """Config-5 shaped serving: 4 resident corners (10k/50k/200k/500k triangles),
+    """Serving run: 4 resident corners (10k/50k/200k/500k triangles),
     Poisson arrivals, resolution in {128, 256, 512}^2, spp in {16, 64, 256}, depth 4,
     half relighting and half compensation steps (fwd + VJP of an L2 loss)."""
     import threading
@@ -80,7 +80,7 @@ def serving_bench(ctx, n_req, n_alone, warmup=20, rate=50.0):
     prep = []
     for k, rq in enumerate(reqs):
         res = rq["res"]
-        w = synth.config2(spp=rq["spp"], max_depth=rq["depth"], res=res)
+        w = synth.corner_50k(spp=rq["spp"], max_depth=rq["depth"], res=res)
         w.mesh = meshes[rq["scene"]]
         w.projector = synth.pinhole((0.85, 0.15, 0.85), (0.3, 0.0, 0.3), 45.0, res, res)
         w.seed = k
@@ -172,7 +172,7 @@ def main():
 
     from paper_2503_12174_amd import dpcs, synth
 
-    w = synth.config2()
+    w = synth.corner_50k()
     ctx = dpcs.Context(0)
     scene = dpcs.Scene(ctx, w.mesh)
     info = scene.info()
@@ -196,6 +196,10 @@ def main():
         dpcs.dpcs_render(ctx, scene, params, proj, out, sample_radiance=Ls, path_records=rec)
         dpcs.dpcs_render_vjp(ctx, scene, params, proj, G, sample_radiance=Ls, path_records=rec, **grads)
 
+    def step_retrace():   # the same step when the forward keeps only per-sample radiance: the VJP re-traces
+        dpcs.dpcs_render(ctx, scene, params, proj, out, sample_radiance=Ls)
+        dpcs.dpcs_render_vjp(ctx, scene, params, proj, G, sample_radiance=Ls, **grads)
+
     def timed(fn, k):
         for _ in range(a.warmup):
             fn()
@@ -212,8 +216,10 @@ def main():
     fwd_sps = samples / (ms_fwd * 1e-3)
     ms_step = timed(step, a.steps)
     step_sps = samples / (ms_step * 1e-3)
+    ms_rt = timed(step_retrace, a.steps)
+    rt_sps = samples / (ms_rt * 1e-3)
     print(f"[bench] forward {ms_fwd:.3f} ms, {fwd_sps:.4e} samples/s; fwd+vjp {ms_step:.3f} ms, "
-          f"{step_sps:.4e} samples/s", file=sys.stderr, flush=True)
+          f"{step_sps:.4e} samples/s; fwd+vjp re-tracing {ms_rt:.3f} ms", file=sys.stderr, flush=True)
 
     roof = None
     stages = None
@@ -276,15 +282,22 @@ def main():
         sc = O.Scene(w)
         rng = np.random.default_rng(12345)
         order = rng.permutation(H * W)
+        Gc = G.cpu().numpy().astype(np.float64)
+
+        def oracle_step(px):   # the same step as the GPU's: forward render + VJP of the same samples
+            O.render(sc, pixels=px, want=("Ec",))
+            O.render_vjp(sc, Gc, pixels=px)
+
         t = time.perf_counter()
-        O.render(sc, pixels=order[:8], want=("Ec",))
+        oracle_step(order[:8])
         dt = time.perf_counter() - t
         n = int(max(8, min(H * W, 8 * a.cpu_seconds / max(dt, 1e-6))))
         t = time.perf_counter()
-        O.render(sc, pixels=order[8:8 + n], want=("Ec",))
+        oracle_step(order[8:8 + n])
         dt = time.perf_counter() - t
         cpu = {"value": round(n * w.spp / dt, 2), "unit": "samples/s", "cores": O.threads(sc), "kind": "oracle",
-               "sample": f"{n} random pixels x {w.spp} spp of the same scene ({n * w.spp} samples, {dt:.1f} s)"}
+               "sample": f"forward + VJP of {n} random pixels x {w.spp} spp of the same scene "
+                         f"({n * w.spp} samples, {dt:.1f} s)"}
         print(f"[bench] oracle {cpu['value']:.1f} samples/s on {cpu['cores']} threads", file=sys.stderr, flush=True)
 
     line = {
@@ -294,9 +307,11 @@ def main():
         "config": {"workload": w.name, "camera": [W, H], "projector": [w.projector.width, w.projector.height],
                    "spp": w.spp, "max_depth": w.max_depth, "triangles": info.num_triangles,
                    "bvh_build_ms": round(info.build_ms, 3),
-                   "step": "forward render + VJP (path replay) of the same samples"},
+                   "step": "forward render keeping per-sample radiance and 4-byte path records + VJP "
+                           "replaying the same samples"},
         "fwd_samples_per_s": round(fwd_sps, 1), "fwd_ms": round(ms_fwd, 4),
         "fwd_adj_samples_per_s": round(step_sps, 1),
+        "fwd_adj_retrace_samples_per_s": round(rt_sps, 1), "fwd_adj_retrace_ms": round(ms_rt, 4),
         "roofline": roof, "cpu_baseline": cpu, "serving": serving, "stages": stages,
     }
     print(json.dumps(line))

@@ -413,7 +413,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
 }
 
 // ---------------------------------------------------------------- shadows
-template <bool UNI>
+// PROF only names a separate instantiation for the counting pass (q.stats set); same code
+template <bool UNI, bool PROF>
 __global__ void __launch_bounds__(TB) k_adj_shadow(Queues q, AdjQueues aq, int which, int nxt, ReqDesc uni,
                                                    const ReqDesc* __restrict__ table) {
     __shared__ int stack[SHORT_STACK * TB];
@@ -1000,8 +1001,13 @@ void launch_adj_shade(const Launch& l, const Queues& q, const AdjQueues& aq, int
 void launch_adj_shadow(const Launch& l, const Queues& q, const AdjQueues& aq, int which, int nxt, const ReqDesc& uni,
                        const ReqDesc* table, int64_t n_upper, int) {
     const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
-    if (table) hipLaunchKernelGGL((k_adj_shadow<false>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
-    else hipLaunchKernelGGL((k_adj_shadow<true>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
+    if (q.stats) {
+        if (table) hipLaunchKernelGGL((k_adj_shadow<false, true>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
+        else hipLaunchKernelGGL((k_adj_shadow<true, true>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
+    } else {
+        if (table) hipLaunchKernelGGL((k_adj_shadow<false, false>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
+        else hipLaunchKernelGGL((k_adj_shadow<true, false>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
+    }
 }
 void launch_adj_replay(const Launch& l, const Queues& q, const AdjQueues& aq, int cur, int depth, const ReqDesc& uni,
                        const ReqDesc* table, int64_t n_upper) {

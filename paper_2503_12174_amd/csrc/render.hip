@@ -76,7 +76,10 @@ __global__ void k_raygen(Queues q, ReqDesc r, int slot, uint32_t g0, uint32_t n)
 }
 
 // ---------------------------------------------------------------- closest hit
-template <bool UNI>
+// PROF only names a separate instantiation for the counting pass (q.stats set), so a
+// profiler reports those launches apart from the timed ones; the code is the same
+// (the runtime test of q.stats is kept: folding it away made this loop slower)
+template <bool UNI, bool PROF>
 __global__ void __launch_bounds__(TB) k_trace(Queues q, int cur, ReqDesc uni, const ReqDesc* __restrict__ table) {
     __shared__ int stack[SHORT_STACK * TB];
     int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL + threadIdx.x;
@@ -212,7 +215,10 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
 }
 
 // ---------------------------------------------------------------- shadows
-template <bool UNI>
+// PROF only names a separate instantiation for the counting pass (q.stats set), so a
+// profiler reports those launches apart from the timed ones; the code is the same
+// (the runtime test of q.stats is kept: folding it away made this loop slower)
+template <bool UNI, bool PROF>
 __global__ void __launch_bounds__(TB) k_shadow(Queues q, int which, int depth, ReqDesc uni,
                                                const ReqDesc* __restrict__ table) {
     __shared__ int stack[SHORT_STACK * TB];
@@ -347,8 +353,13 @@ void launch_raygen(const Launch& l, const Queues& q, const ReqDesc& r, const Req
 void launch_trace(const Launch& l, const Queues& q, int cur, const ReqDesc& uni, const ReqDesc* table,
                   int64_t n_upper, int) {
     const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
-    if (table) hipLaunchKernelGGL((k_trace<false>), g, b, 0, l.st, q, cur, uni, table);
-    else hipLaunchKernelGGL((k_trace<true>), g, b, 0, l.st, q, cur, uni, table);
+    if (q.stats) {
+        if (table) hipLaunchKernelGGL((k_trace<false, true>), g, b, 0, l.st, q, cur, uni, table);
+        else hipLaunchKernelGGL((k_trace<true, true>), g, b, 0, l.st, q, cur, uni, table);
+    } else {
+        if (table) hipLaunchKernelGGL((k_trace<false, false>), g, b, 0, l.st, q, cur, uni, table);
+        else hipLaunchKernelGGL((k_trace<true, false>), g, b, 0, l.st, q, cur, uni, table);
+    }
 }
 void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const ReqDesc& uni, const ReqDesc* table,
                   int64_t n_upper) {
@@ -359,8 +370,13 @@ void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const Re
 void launch_shadow(const Launch& l, const Queues& q, int which, const ReqDesc& uni, const ReqDesc* table,
                    int64_t n_upper, int depth) {
     const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
-    if (table) hipLaunchKernelGGL((k_shadow<false>), g, b, 0, l.st, q, which, depth, uni, table);
-    else hipLaunchKernelGGL((k_shadow<true>), g, b, 0, l.st, q, which, depth, uni, table);
+    if (q.stats) {
+        if (table) hipLaunchKernelGGL((k_shadow<false, true>), g, b, 0, l.st, q, which, depth, uni, table);
+        else hipLaunchKernelGGL((k_shadow<true, true>), g, b, 0, l.st, q, which, depth, uni, table);
+    } else {
+        if (table) hipLaunchKernelGGL((k_shadow<false, false>), g, b, 0, l.st, q, which, depth, uni, table);
+        else hipLaunchKernelGGL((k_shadow<true, false>), g, b, 0, l.st, q, which, depth, uni, table);
+    }
 }
 void launch_finalize(const Launch& l, const Queues& q, const ReqDesc& r, const ReqDesc*, int, uint32_t p0,
                      uint32_t p1) {

@@ -370,7 +370,7 @@ def _f32(a):
     return np.asarray(a, np.float64).astype(F32).astype(np.float64)
 
 
-def config1(spp: int = 4, max_depth: int = 3, seed: int = 0) -> Workload:
+def quad_cube(spp: int = 4, max_depth: int = 3, seed: int = 0) -> Workload:
     """Plain forward render at oracle scale: quad + cube, Lambert, 64x64 camera/projector."""
     mesh = quad_and_cube()
     albedo = uniform_texture(np.random.default_rng(101), 64, 64, 3, 0.2, 0.8)
@@ -393,7 +393,7 @@ def ggx_textures(seed: int, size: int):
     return albedo, rough, spec
 
 
-def config2(spp: int = 64, max_depth: int = 4, seed: int = 0, env: float = 0.0,
+def corner_50k(spp: int = 64, max_depth: int = 4, seed: int = 0, env: float = 0.0,
             res: int = 256, n_quads: int = 112) -> Workload:
     """Forward at the paper's scale: 50k-triangle displaced folded corner + 3 boxes, GGX."""
     mesh = folded_corner(n_quads, 201, 202)
@@ -407,7 +407,7 @@ def config2(spp: int = 64, max_depth: int = 4, seed: int = 0, env: float = 0.0,
                     env=np.full(3, env), spp=spp, max_depth=max_depth, seed=seed)
 
 
-def config3_truth(seed: int = 301):
+def fit_truth(seed: int = 301):
     """Hidden ground truth for the scene-parameter fit (textures 64^2, PRF/CRF, mixing, WB)."""
     rng = np.random.default_rng(seed)
     albedo = uniform_texture(rng, 64, 64, 3, 0.2, 0.8)
@@ -421,9 +421,9 @@ def config3_truth(seed: int = 301):
                 crf_gamma=crf_gamma, prf_mix=mix, white_balance=wb)
 
 
-def config3(spp: int = 32, seed: int = 0) -> Workload:
-    """Scene of config 1 with GGX maps at the fit's initial guess."""
-    w = config1(spp=spp, seed=seed)
+def fit_scene(spp: int = 32, seed: int = 0) -> Workload:
+    """The quad-and-cube scene with GGX maps at the fit's initial guess."""
+    w = quad_cube(spp=spp, seed=seed)
     w.name = "quad+cube 14 tris, GGX 64^2 maps, fit step (8 images, 32 spp fwd+VJP)"
     w.brdf = GGX
     w.albedo = np.full((64, 64, 3), 0.5, F32)
@@ -433,12 +433,12 @@ def config3(spp: int = 32, seed: int = 0) -> Workload:
     return w
 
 
-def config3_images(step: int, count: int = 8):
+def fit_images(step: int, count: int = 8):
     rng = np.random.default_rng(3000 + step)
     return rng.uniform(0, 1, size=(count, 64, 64, 3)).astype(F32)
 
 
-def config4(spp: int = 16, max_depth: int = 4, seed: int = 0, n_quads: int = 224,
+def corner_200k(spp: int = 16, max_depth: int = 4, seed: int = 0, n_quads: int = 224,
             res: int = 512) -> Workload:
     """Compensation scale: 200k-triangle folded corner, 512^2 GGX maps, 512^2 camera/projector."""
     mesh = folded_corner(n_quads, 401, 402)
@@ -452,7 +452,7 @@ def config4(spp: int = 16, max_depth: int = 4, seed: int = 0, n_quads: int = 224
                     spp=spp, max_depth=max_depth, seed=seed)
 
 
-def config4_target(res: int = 512):
+def compensation_target(res: int = 512):
     return blob_image(res, res, 402, lo=0.1, hi=0.9)
 
 

@@ -29,8 +29,8 @@ def plane_workload(proj_eye=(0.0, 0.0, 1.0), cam_eye=(0.3, 0.2, 1.2), half=2.0, 
 
 
 def c1_direct(spp=4, seed=3, const_image=0.8, albedo=0.6):
-    """Config-1 geometry, direct light only, constant albedo and projector image."""
-    w = synth.config1(spp=spp, max_depth=1, seed=seed)
+    """Quad-and-cube geometry, direct light only, constant albedo and projector image."""
+    w = synth.quad_cube(spp=spp, max_depth=1, seed=seed)
     w.albedo = np.full_like(w.albedo, albedo)
     w.proj_image = np.full_like(w.proj_image, const_image)
     w.clip = False
@@ -65,9 +65,9 @@ def linear_params(w):
 
 
 def c3_ggx(spp=4, seed=5, max_depth=3):
-    """Config-1 geometry with random GGX maps (64^2) and non-trivial PRF/CRF parameters."""
-    w = synth.config1(spp=spp, max_depth=max_depth, seed=seed)
-    t = synth.config3_truth(301)
+    """Quad-and-cube geometry with random GGX maps (64^2) and non-trivial PRF/CRF parameters."""
+    w = synth.quad_cube(spp=spp, max_depth=max_depth, seed=seed)
+    t = synth.fit_truth(301)
     w.brdf = synth.GGX
     w.albedo, w.roughness, w.specular = t["albedo"], t["roughness"], t["specular"]
     w.prf_gamma, w.crf_gamma, w.prf_mix, w.white_balance = t["prf_gamma"], t["crf_gamma"], t["prf_mix"], t["white_balance"]

@@ -44,7 +44,7 @@ def test_compensation_reduces_the_loss():
     """Eq. 13 by Adam: a 128^2 compensation on a 10k-triangle corner."""
     import torch
     from paper_2503_12174_amd import drivers, dpcs
-    w = synth.config4(spp=4, n_quads=50, res=128)
+    w = synth.corner_200k(spp=4, n_quads=50, res=128)
     scene = dpcs.Scene(ctx(), w.mesh)
     f = torch.float32
     target = dev(synth.blob_image(128, 128, 402, lo=0.1, hi=0.9), f)
@@ -57,16 +57,16 @@ def test_compensation_reduces_the_loss():
 
 
 def test_scene_fit_reduces_the_loss_on_oracle_targets():
-    """Eq. 9 shape of config 3: targets rendered by the FP64 oracle from hidden maps and
+    """Eq. 9 scene-parameter fit: targets rendered by the FP64 oracle from hidden maps and
     responses, fitted from the initial guess with fwd + VJP steps."""
     import torch
     from paper_2503_12174_amd import drivers, dpcs
-    truth = synth.config3_truth(301)
-    w = synth.config3(spp=8)
-    imgs = synth.config3_images(0, count=2)
+    truth = synth.fit_truth(301)
+    w = synth.fit_scene(spp=8)
+    imgs = synth.fit_images(0, count=2)
     targets = []
     for im in imgs:
-        tw = synth.config3(spp=64)
+        tw = synth.fit_scene(spp=64)
         for k, v in truth.items():
             setattr(tw, {"roughness": "roughness", "specular": "specular"}.get(k, k), v)
         targets.append(O.render(O.Scene(tw, proj_image=im), want=("Ic",))["Ic"].reshape(64, 64, 3))

@@ -21,7 +21,7 @@ def _setup(n_scenes=2):
 
 def _request(k, rng, albedo, rough, spec):
     res = int(rng.choice([16, 24, 40]))
-    w = synth.config2(spp=int(rng.choice([2, 4, 8])), max_depth=int(rng.integers(1, 5)), res=res, n_quads=8)
+    w = synth.corner_50k(spp=int(rng.choice([2, 4, 8])), max_depth=int(rng.integers(1, 5)), res=res, n_quads=8)
     w.projector = synth.pinhole((0.85, 0.15, 0.85), (0.3, 0.0, 0.3), 45.0, res, res)
     w.seed = k
     if k % 3 == 0:
@@ -109,7 +109,7 @@ def test_admission_by_memory_budget():
     # a compensation step with 4096^2 maps and projector needs > 1 GiB of request state:
     # rejected up front (every buffer it names exists, so nothing could be read out of bounds)
     n = 4096
-    big = synth.config2(spp=1, max_depth=1, res=16, n_quads=8)
+    big = synth.corner_50k(spp=1, max_depth=1, res=16, n_quads=8)
     big.projector = synth.pinhole((0.85, 0.15, 0.85), (0.3, 0.0, 0.3), 45.0, n, n)
     alb_b = torch.full((n, n, 3), 0.5, device="cuda")
     r_b = torch.full((n, n), 0.5, device="cuda")
@@ -132,7 +132,7 @@ def test_scene_in_use_cannot_be_destroyed():
     import torch
     from paper_2503_12174_amd import dpcs
     scenes, albedo, rough, spec = _setup(1)
-    w = synth.config2(spp=256, max_depth=4, res=64, n_quads=8)
+    w = synth.corner_50k(spp=256, max_depth=4, res=64, n_quads=8)
     p = dpcs.params_from(w, albedo, rough, spec)
     ip = dev(synth.blob_image(256, 256, 3), torch.float32)
     srv = dpcs.Server(ctx(), budget_bytes=4 << 30, max_slots=4)

@@ -61,7 +61,7 @@ def test_philox_uniformity_chi2():
 # ---------------------------------------------------------------------------
 
 def test_camera_ray_round_trip():
-    w = synth.config1()
+    w = synth.quad_cube()
     sc = O.Scene(w)
     rng = np.random.default_rng(0)
     for _ in range(200):
@@ -190,7 +190,7 @@ def test_projector_image_bilinear_against_library():
 
 
 def test_hard_shadow_of_the_cube():
-    """Config-1 geometry, direct only: samples on the floor inside the cube's shadow polygon
+    """Quad-and-cube geometry, direct only: samples on the floor inside the cube's shadow polygon
     (convex hull of the cube's corners projected from the projector centre) receive nothing;
     the others follow the flux-conservation closed form."""
     w = scenes.c1_direct()
@@ -269,7 +269,7 @@ def test_convex_scene_is_depth_invariant():
 
 @pytest.mark.parametrize("ggx", [False, True])
 def test_linearity_in_projector_image(ggx):
-    w = scenes.linear_params(scenes.c3_ggx(spp=2) if ggx else synth.config1(spp=2))
+    w = scenes.linear_params(scenes.c3_ggx(spp=2) if ggx else synth.quad_cube(spp=2))
     rng = np.random.default_rng(1)
     I1 = rng.uniform(0, 1, w.proj_image.shape)
     I2 = rng.uniform(0, 1, w.proj_image.shape)
@@ -300,7 +300,7 @@ def test_clip_forces_bright_samples_to_threshold():
 
 
 def test_prf_special_cases():
-    w = synth.config1()
+    w = synth.quad_cube()
     rng = np.random.default_rng(2)
     I = rng.uniform(0, 1, w.proj_image.shape)
     sc = O.Scene(w, proj_image=I, prf_gamma=np.ones(3), prf_gain=1.0, prf_mix=np.eye(3))
@@ -315,7 +315,7 @@ def test_prf_special_cases():
 
 
 def test_crf_special_cases():
-    w = synth.config1()
+    w = synth.quad_cube()
     w.clip = False   # the clip threshold k / min(w) would differ between the two renders
     a = O.render(O.Scene(w, crf_gamma=np.ones(3), crf_gain=1.0, white_balance=np.ones(3)))
     np.testing.assert_array_equal(a["Ic"], a["Ec"])
@@ -439,7 +439,7 @@ def test_bounce_sampler_matches_its_pdf(kind, r):
 def _tri_scene(V, F):
     mesh = synth.Mesh(np.asarray(V, np.float32), np.asarray(F, np.int32),
                       np.zeros((len(F), 3, 2), np.float32))
-    w = synth.config1()
+    w = synth.quad_cube()
     w.mesh = mesh
     return O.Scene(w, tmin=1e-6)
 
@@ -478,7 +478,7 @@ def test_margin_flags_near_edge_rays():
 def test_clean_samples_survive_fp32_level_perturbation():
     """The margin protocol: shifting the camera and projector poses by float32-rounding
     amounts (1e-7 relative) changes no hit on samples the unperturbed oracle marks clean."""
-    w = synth.config2(spp=2, n_quads=16, res=24)
+    w = synth.corner_50k(spp=2, n_quads=16, res=24)
     base = O.render(O.Scene(w), want=("hits", "margin"))
     rng = np.random.default_rng(5)
     cam, prj = w.camera, w.projector
