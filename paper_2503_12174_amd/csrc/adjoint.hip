@@ -751,9 +751,26 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
         float eg[3] = {0.f, 0.f, 0.f};
         const ReqDesc* rp = &sel<UNI>(uni, table, 0);
         if (i < n) {
-            const PathO o = q.po[cur][i];
-            const PathD dd = q.pd[cur][i];
-            const float4 b = q.pb[cur][i];
+            PathO o;
+            PathD dd;
+            float4 b, rl, penda;
+            if (UNI && depth == 0) {
+                // the dense camera wave (queue index = batch sample index): the ray is
+                // regenerated as the forward's raygen made it instead of read back
+                const uint32_t g = i - uni.sid_base + uni.g_base;
+                const D3 cd = camera_dir(uni, g);
+                o = PathO{uni.cam_o[0], uni.cam_o[1], uni.cam_o[2], 0, -1};
+                dd = PathD{cd.x, cd.y, cd.z, g, 0u};
+                b = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
+                rl = q.L[i];                                  // remaining radiance = the sample's total
+                penda = make_float4(0.f, 0.f, 0.f, -1.f);     // no pending bounce
+            } else {
+                o = q.po[cur][i];
+                dd = q.pd[cur][i];
+                b = q.pb[cur][i];
+                rl = aq.rl[cur][i];
+                penda = aq.penda[cur][i];
+            }
             const ReqDesc& r = sel<UNI>(uni, table, o.slot);
             rp = &r;
             const uint32_t g = dd.g;
@@ -763,8 +780,6 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
             const float4 dl = aq.delta[sid];
             const D3 delta = d3(dl.x, dl.y, dl.z);
             const D3 beta = d3(b.x, b.y, b.z);
-            float4 rl = aq.rl[cur][i];
-            const float4 penda = aq.penda[cur][i];
             if (penda.w >= 0.f) {
                 // previous vertex: its next-event cotangents plus d/df of its bounce,
                 // beta_k f cos/pdf R_{k+1} -> R_{k+1} / f (zero when this ray escaped)

@@ -794,9 +794,8 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
     launch_adj_pixel(l, q, aq, r, a, b, sample_L);
     prof_end(ctx, pr, nullptr, b - a);
     launch_set_count(l, q.cnt, 0, n, 1, 4);
-    launch_adj_raygen(l, q, aq, r, 0, r.g_base, n);
     int cur = 0;
-    if (r.rec) {   // the forward's path records stand in for tracing
+    if (r.rec) {   // the forward's path records stand in for tracing (camera rays regenerated in depth 0)
         for (int d = 0; d < r.max_depth; ++d) {
             launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
             pr = prof_begin(ctx, DPCS_STAGE_ADJ_SHADE);
@@ -811,6 +810,7 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
         }
         return;
     }
+    launch_adj_raygen(l, q, aq, r, 0, r.g_base, n);
     for (int d = 0; d < r.max_depth; ++d) {
         launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
         q.stats = prof_stats(ctx, DPCS_STAGE_TRACE);
