@@ -1014,7 +1014,7 @@ void launch_adj_shade(const Launch& l, const Queues& q, const AdjQueues& aq, int
     else hipLaunchKernelGGL((k_adj_shade<true>), g, b, 0, l.st, q, aq, cur, depth, uni, table);
 }
 void launch_adj_shadow(const Launch& l, const Queues& q, const AdjQueues& aq, int which, int nxt, const ReqDesc& uni,
-                       const ReqDesc* table, int64_t n_upper, int) {
+                       const ReqDesc* table, int64_t n_upper) {
     const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
     if (q.stats) {
         if (table) hipLaunchKernelGGL((k_adj_shadow<false, true>), g, b, 0, l.st, q, aq, which, nxt, uni, table);

@@ -114,7 +114,6 @@ struct ReqDesc {
     const float4* tri_uv;    // 2 float4 per leaf: (u0 v0 u1 v1), (u2 v2 - -)
     const float4* emission;  // per leaf (rgb, -) or null
     float tmin;
-    int32_t stack_hint;
     // material
     int32_t brdf;
     int32_t tw, th;

@@ -108,8 +108,8 @@ void launch_pack_tex(const Launch& l, const ReqDesc& r, const float* albedo, con
 void launch_set_count(const Launch& l, uint32_t* cnt, int idx, uint32_t value, int zero_from, int zero_to);
 void launch_raygen(const Launch& l, const Queues& q, const ReqDesc& r, const ReqDesc* table, int slot,
                    uint32_t g0, uint32_t n, bool adjoint, const AdjQueues* aq);
-void launch_trace(const Launch& l, const Queues& q, int cur, const ReqDesc& uni, const ReqDesc* table, int64_t n_upper,
-                  int stack);
+void launch_trace(const Launch& l, const Queues& q, int cur, const ReqDesc& uni, const ReqDesc* table,
+                  int64_t n_upper);
 void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const ReqDesc& uni, const ReqDesc* table,
                   int64_t n_upper);
 // depth: the bounce the shadow rays leave from (for the path records)
@@ -127,7 +127,7 @@ void launch_adj_raygen(const Launch& l, const Queues& q, const AdjQueues& aq, co
 void launch_adj_shade(const Launch& l, const Queues& q, const AdjQueues& aq, int cur, int depth, const ReqDesc& uni,
                       const ReqDesc* table, int64_t n_upper);
 void launch_adj_shadow(const Launch& l, const Queues& q, const AdjQueues& aq, int which, int nxt, const ReqDesc& uni,
-                       const ReqDesc* table, int64_t n_upper, int stack);
+                       const ReqDesc* table, int64_t n_upper);
 // replay of one bounce from the path records (no tracing): shade, next-event gradients
 // for the recorded visibilities, bounce
 void launch_adj_replay(const Launch& l, const Queues& q, const AdjQueues& aq, int cur, int depth, const ReqDesc& uni,

@@ -351,7 +351,7 @@ void launch_raygen(const Launch& l, const Queues& q, const ReqDesc& r, const Req
     if (n) hipLaunchKernelGGL(k_raygen, dim3(grid_of(n, 256)), dim3(256), 0, l.st, q, r, slot, g0, n);
 }
 void launch_trace(const Launch& l, const Queues& q, int cur, const ReqDesc& uni, const ReqDesc* table,
-                  int64_t n_upper, int) {
+                  int64_t n_upper) {
     const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
     if (q.stats) {
         if (table) hipLaunchKernelGGL((k_trace<false, true>), g, b, 0, l.st, q, cur, uni, table);

@@ -42,13 +42,13 @@ void* scratch(dpcs_context ctx, const char* name, size_t bytes, dpcs_status* st)
             *st = DPCS_E_DEVICE;
             return nullptr;
         }
-        hipFree(it->second.first);
+        (void)hipFree(it->second.first);
         ctx->scratch_bytes -= old;
         ctx->pool.erase(it);
     }
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
-        hipGetLastError();
+        (void)hipGetLastError();
         *st = fail(ctx, DPCS_E_OOM, std::string("hipMalloc failed for buffer ") + name);
         return nullptr;
     }
@@ -240,7 +240,6 @@ bool fill_desc(dpcs_context, ReqDesc& r, const dpcs_render_params* p, dpcs_scene
     r.tri_uv = sc->tri_uv;
     r.emission = sc->emission;
     r.tmin = sc->tmin;
-    r.stack_hint = stack_for(sc);
     r.brdf = p->brdf;
     r.tw = p->tex_w;
     r.th = p->tex_h;
@@ -270,7 +269,6 @@ bool fill_desc(dpcs_context, ReqDesc& r, const dpcs_render_params* p, dpcs_scene
     return true;
 }
 
-int stack_for(dpcs_scene sc) { return sc->depth <= 32 ? 32 : 64; }
 
 static hipEvent_t prof_event(dpcs_context ctx) {
     if (ctx->ev_used == ctx->ev_pool.size()) {
@@ -285,7 +283,7 @@ int prof_begin(dpcs_context ctx, int stage) {
     if (!ctx->prof_mode) return -1;
     hipEvent_t a = prof_event(ctx), b = prof_event(ctx);
     if (!a || !b) return -1;
-    hipEventRecord(a, ctx->stream);
+    (void)hipEventRecord(a, ctx->stream);
     ctx->prof.push_back({stage, a, b, -1, 0});
     return (int)ctx->prof.size() - 1;
 }
@@ -293,11 +291,11 @@ int prof_begin(dpcs_context ctx, int stage) {
 void prof_end(dpcs_context ctx, int rec, const uint32_t* dev_count, int64_t host_count) {
     if (rec < 0) return;
     auto& r = ctx->prof[rec];
-    hipEventRecord(r.b, ctx->stream);
+    (void)hipEventRecord(r.b, ctx->stream);
     r.host_count = host_count;
     if (dev_count && ctx->pinned && ctx->pinned_used < ctx->pinned_cap) {
         r.slot = ctx->pinned_used++;
-        hipMemcpyAsync(ctx->pinned + r.slot, dev_count, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream);
+        (void)hipMemcpyAsync(ctx->pinned + r.slot, dev_count, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream);
     }
 }
 
@@ -314,7 +312,7 @@ extern "C" dpcs_status dpcs_context_create(int32_t device, void* hip_stream, siz
     *out = nullptr;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
-        hipGetLastError();
+        (void)hipGetLastError();
         return DPCS_E_INVALID;
     }
     if (hipSetDevice(device) != hipSuccess) return DPCS_E_DEVICE;
@@ -330,12 +328,12 @@ extern "C" dpcs_status dpcs_context_create(int32_t device, void* hip_stream, siz
 
 extern "C" void dpcs_context_destroy(dpcs_context ctx) {
     if (!ctx) return;
-    hipSetDevice(ctx->device);
-    hipStreamSynchronize(ctx->stream);
-    for (auto& kv : ctx->pool) hipFree(kv.second.first);
-    for (auto e : ctx->ev_pool) hipEventDestroy(e);
-    if (ctx->pinned) hipHostFree(ctx->pinned);
-    if (ctx->dstats) hipFree(ctx->dstats);
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->pool) (void)hipFree(kv.second.first);
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->dstats) (void)hipFree(ctx->dstats);
     delete ctx;
 }
 
@@ -344,7 +342,7 @@ extern "C" const char* dpcs_last_error(dpcs_context ctx) { return ctx ? ctx->err
 extern "C" dpcs_status dpcs_context_synchronize(dpcs_context ctx) {
     if (!ctx) return DPCS_E_INVALID;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    hipSetDevice(ctx->device);
+    if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
     if (!hip_ok(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize")) return DPCS_E_DEVICE;
     return ctx->sticky ? DPCS_E_DEVICE : DPCS_OK;
 }
@@ -470,7 +468,7 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
             clo[k] = std::min(clo[k], (double)c);
             chi[k] = std::max(chi[k], (double)c);
         }
-    hipSetDevice(ctx->device);
+    if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
     auto* sc = new dpcs_scene_s();
     sc->ctx = ctx;
     sc->nt = nt;
@@ -488,7 +486,7 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
     auto dmalloc = [&](void** p, size_t b) {
         if (!ok) return;
         if (hipMalloc(p, std::max<size_t>(b, 16)) != hipSuccess) {
-            hipGetLastError();
+            (void)hipGetLastError();
             ok = false;
         }
     };
@@ -514,19 +512,19 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
     for (size_t b : tmp_parts) tmp_bytes += r256(b);
     dmalloc(&tmp, tmp_bytes);
     auto cleanup_tmp = [&]() {
-        hipFree(dV);
-        hipFree(dF);
-        hipFree(dUV);
-        if (dLe) hipFree(dLe);
-        hipFree(tmp);
+        (void)hipFree(dV);
+        (void)hipFree(dF);
+        (void)hipFree(dUV);
+        if (dLe) (void)hipFree(dLe);
+        (void)hipFree(tmp);
     };
     auto destroy_scene = [&]() {
-        hipFree(sc->nodes);
-        if (sc->nodes4) hipFree(sc->nodes4);
-        hipFree(sc->tris);
-        hipFree(sc->tri_uv);
-        if (sc->emission) hipFree(sc->emission);
-        hipFree(sc->leaf_of_prim);
+        (void)hipFree(sc->nodes);
+        if (sc->nodes4) (void)hipFree(sc->nodes4);
+        (void)hipFree(sc->tris);
+        (void)hipFree(sc->tri_uv);
+        if (sc->emission) (void)hipFree(sc->emission);
+        (void)hipFree(sc->leaf_of_prim);
         delete sc;
     };
     if (!ok) {
@@ -569,9 +567,14 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
     bo.emission = sc->emission;
     bo.leaf_of_prim = sc->leaf_of_prim;
     hipStream_t st = ctx->stream;
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipGetLastError();
+        if (e0) (void)hipEventDestroy(e0);
+        cleanup_tmp();
+        destroy_scene();
+        return fail(ctx, DPCS_E_DEVICE, "scene build: hipEventCreate failed");
+    }
     const char* step = "upload";
     hipError_t e = hipMemcpyAsync(dV, m->positions, sizeof(float) * 3 * nv, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dF, m->triangles, sizeof(int) * 3 * nt, hipMemcpyHostToDevice, st);
@@ -587,9 +590,9 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
     }
     if (e == hipSuccess) {
         step = "build kernels";
-        hipEventRecord(e0, st);
+        (void)hipEventRecord(e0, st);
         e = build_bvh(st, in, bo);
-        hipEventRecord(e1, st);
+        (void)hipEventRecord(e1, st);
     }
     if (e == hipSuccess) {
         step = "synchronize";
@@ -601,9 +604,9 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
     if (e == hipSuccess && nt > 1) e = hipMemcpy(child.data(), in.child, sizeof(int) * 2 * ni, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(order.data(), bo.order, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost);
     float ms = 0.f;
-    if (e == hipSuccess) hipEventElapsedTime(&ms, e0, e1);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    if (e == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     cleanup_tmp();
     if (e != hipSuccess) {
         hip_ok(ctx, e, (std::string("scene build (") + step + ")").c_str());
@@ -679,8 +682,8 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
                     sc->nnodes4 = (int)(n4.size() / 8);
                     sc->bytes += (int64_t)sizeof(float4) * n4.size();
                 } else {
-                    hipGetLastError();
-                    if (sc->nodes4) hipFree(sc->nodes4);
+                    (void)hipGetLastError();
+                    if (sc->nodes4) (void)hipFree(sc->nodes4);
                     sc->nodes4 = nullptr;   // the binary BVH serves
                 }
             }
@@ -717,14 +720,14 @@ extern "C" dpcs_status dpcs_scene_destroy(dpcs_scene s) {
     if (s->refs.load() > 0) return fail(s->ctx, DPCS_E_BUSY, "scene still used by queued server requests");
     dpcs_context ctx = s->ctx;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    hipSetDevice(ctx->device);
-    hipStreamSynchronize(ctx->stream);
-    hipFree(s->nodes);
-    if (s->nodes4) hipFree(s->nodes4);
-    hipFree(s->tris);
-    hipFree(s->tri_uv);
-    if (s->emission) hipFree(s->emission);
-    hipFree(s->leaf_of_prim);
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(s->nodes);
+    if (s->nodes4) (void)hipFree(s->nodes4);
+    (void)hipFree(s->tris);
+    (void)hipFree(s->tri_uv);
+    if (s->emission) (void)hipFree(s->emission);
+    (void)hipFree(s->leaf_of_prim);
     delete s;
     return DPCS_OK;
 }
@@ -749,7 +752,6 @@ bool prepare_request(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, 
 
 void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t b, bool finalize) {
     Launch l{ctx->stream, ctx->grid_cap};
-    const int stack = r.stack_hint;
     const uint32_t n = (b - a) * (uint32_t)r.spp;
     r.g_base = a * (uint32_t)r.spp;
     r.sid_base = 0;
@@ -762,7 +764,7 @@ void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t 
         launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);   // next path queue and shadow queues empty
         q.stats = prof_stats(ctx, DPCS_STAGE_TRACE);
         pr = prof_begin(ctx, DPCS_STAGE_TRACE);
-        launch_trace(l, q, cur, r, nullptr, n, stack);
+        launch_trace(l, q, cur, r, nullptr, n);
         prof_end(ctx, pr, q.cnt + cur, 0);
         pr = prof_begin(ctx, DPCS_STAGE_SHADE);
         launch_shade(l, q, cur, d, r, nullptr, n);
@@ -786,7 +788,6 @@ void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t 
 void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, uint32_t a, uint32_t b,
                   const float* sample_L) {
     Launch l{ctx->stream, ctx->grid_cap};
-    const int stack = r.stack_hint;
     const uint32_t n = (b - a) * (uint32_t)r.spp;
     r.g_base = a * (uint32_t)r.spp;
     r.sid_base = 0;
@@ -815,7 +816,7 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
         launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
         q.stats = prof_stats(ctx, DPCS_STAGE_TRACE);
         pr = prof_begin(ctx, DPCS_STAGE_TRACE);
-        launch_trace(l, q, cur, r, nullptr, n, stack);
+        launch_trace(l, q, cur, r, nullptr, n);
         prof_end(ctx, pr, q.cnt + cur, 0);
         pr = prof_begin(ctx, DPCS_STAGE_ADJ_SHADE);
         launch_adj_shade(l, q, aq, cur, d, r, nullptr, n);
@@ -823,7 +824,7 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
         q.stats = prof_stats(ctx, DPCS_STAGE_ADJ_SHADOW);
         for (int w = 0; w < (r.env_on ? 2 : 1); ++w) {
             pr = prof_begin(ctx, DPCS_STAGE_ADJ_SHADOW);
-            launch_adj_shadow(l, q, aq, w, cur ^ 1, r, nullptr, n, stack);
+            launch_adj_shadow(l, q, aq, w, cur ^ 1, r, nullptr, n);
             prof_end(ctx, pr, q.cnt + 2 + w, 0);
         }
         q.stats = nullptr;
@@ -849,7 +850,7 @@ extern "C" dpcs_status dpcs_render(dpcs_context ctx, dpcs_scene scene, const dpc
     ReqDesc r;
     std::string why;
     if (!fill_desc(ctx, r, params, scene, proj_image, &why)) return fail(ctx, DPCS_E_INVALID, why);
-    hipSetDevice(ctx->device);
+    if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
     r.out_image = out_image;
     if (aux) {
         r.out_linear = aux->linear;
@@ -879,7 +880,7 @@ extern "C" dpcs_status dpcs_debug_intersect(dpcs_context ctx, dpcs_scene scene, 
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (ctx->sticky) return DPCS_E_DEVICE;
     if (!scene || !rays || !prim || n < 0) return fail(ctx, DPCS_E_INVALID, "bad debug_intersect arguments");
-    hipSetDevice(ctx->device);
+    if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
     (void)hipGetLastError();
     Launch l{ctx->stream, ctx->grid_cap};
     if (use_bvh < 0 || use_bvh > 4) return fail(ctx, DPCS_E_INVALID, "debug_intersect mode must be in 0..4");
@@ -893,7 +894,7 @@ extern "C" dpcs_status dpcs_debug_philox(dpcs_context ctx, uint64_t seed, const 
     if (!ctx) return DPCS_E_INVALID;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (!ctr || !out || n < 0) return fail(ctx, DPCS_E_INVALID, "bad debug_philox arguments");
-    hipSetDevice(ctx->device);
+    if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
     (void)hipGetLastError();
     Launch l{ctx->stream, ctx->grid_cap};
     launch_debug_philox(l, seed, ctr, n, out);
@@ -904,26 +905,26 @@ extern "C" dpcs_status dpcs_debug_philox(dpcs_context ctx, uint64_t seed, const 
 extern "C" dpcs_status dpcs_context_set_profiling(dpcs_context ctx, int32_t mode) {
     if (!ctx || mode < 0 || mode > 2) return DPCS_E_INVALID;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    hipSetDevice(ctx->device);
-    hipStreamSynchronize(ctx->stream);
+    if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
+    (void)hipStreamSynchronize(ctx->stream);
     ctx->prof.clear();
     ctx->ev_used = 0;
     ctx->pinned_used = 0;
     if (mode && !ctx->pinned) {
         ctx->pinned_cap = 1 << 16;
         if (hipHostMalloc((void**)&ctx->pinned, sizeof(uint32_t) * ctx->pinned_cap) != hipSuccess) {
-            hipGetLastError();
+            (void)hipGetLastError();
             ctx->pinned = nullptr;
             ctx->pinned_cap = 0;
         }
     }
     if (mode >= 2 && !ctx->dstats) {
         if (hipMalloc((void**)&ctx->dstats, sizeof(unsigned long long) * 2 * DPCS_NUM_STAGES) != hipSuccess) {
-            hipGetLastError();
+            (void)hipGetLastError();
             return fail(ctx, DPCS_E_OOM, "profiling counters");
         }
     }
-    if (ctx->dstats) hipMemset(ctx->dstats, 0, sizeof(unsigned long long) * 2 * DPCS_NUM_STAGES);
+    if (ctx->dstats) (void)hipMemset(ctx->dstats, 0, sizeof(unsigned long long) * 2 * DPCS_NUM_STAGES);
     ctx->prof_mode = mode;
     return DPCS_OK;
 }
@@ -931,24 +932,24 @@ extern "C" dpcs_status dpcs_context_set_profiling(dpcs_context ctx, int32_t mode
 extern "C" dpcs_status dpcs_context_get_profile(dpcs_context ctx, dpcs_profile* out) {
     if (!ctx || !out) return DPCS_E_INVALID;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    hipSetDevice(ctx->device);
+    if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
     if (!hip_ok(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize")) return DPCS_E_DEVICE;
     std::memset(out, 0, sizeof *out);
     for (const auto& r : ctx->prof) {
         float ms = 0.f;
-        hipEventElapsedTime(&ms, r.a, r.b);
+        (void)hipEventElapsedTime(&ms, r.a, r.b);
         out->launches[r.stage] += 1;
         out->ms[r.stage] += ms;
         out->items[r.stage] += r.slot >= 0 ? (int64_t)ctx->pinned[r.slot] : r.host_count;
     }
     if (ctx->dstats) {
         unsigned long long h[2 * DPCS_NUM_STAGES];
-        hipMemcpy(h, ctx->dstats, sizeof h, hipMemcpyDeviceToHost);
+        (void)hipMemcpy(h, ctx->dstats, sizeof h, hipMemcpyDeviceToHost);
         for (int k = 0; k < DPCS_NUM_STAGES; ++k) {
             out->nodes[k] = (int64_t)h[2 * k];
             out->tris[k] = (int64_t)h[2 * k + 1];
         }
-        hipMemset(ctx->dstats, 0, sizeof h);
+        (void)hipMemset(ctx->dstats, 0, sizeof h);
     }
     ctx->prof.clear();
     ctx->ev_used = 0;

@@ -66,7 +66,6 @@ void* scratch(dpcs_context ctx, const char* name, size_t bytes, dpcs_status* st)
 // fills a request descriptor from validated params; false + message on invalid input
 bool fill_desc(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, dpcs_scene sc, const float* proj_image,
                std::string* why);
-int stack_for(dpcs_scene sc);
 
 // profiling hooks around one stage launch (no-ops when profiling is off)
 int prof_begin(dpcs_context ctx, int stage);

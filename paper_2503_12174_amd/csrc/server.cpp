@@ -181,7 +181,7 @@ void dpcs_server_s::wave(Launch& l) {
     if (order.empty()) return;
     std::vector<Seg> segs;
     int64_t used = 0, n_adj = 0;
-    int max_depth = 1, stack = 32;
+    int max_depth = 1;
     bool env = false, any_adj = false;
     const int64_t share = std::max<int64_t>(1, cap / (int64_t)order.size());
     for (Req* q : order) {
@@ -198,7 +198,6 @@ void dpcs_server_s::wave(Launch& l) {
         if (q->adjoint) n_adj = used, any_adj = true;
         q->next_pixel += px;
         max_depth = std::max(max_depth, q->r.max_depth);
-        stack = std::max(stack, q->r.stack_hint);
         env = env || q->r.env_on;
     }
     if (segs.empty()) return;
@@ -210,7 +209,7 @@ void dpcs_server_s::wave(Launch& l) {
     int cur = 0;
     for (int d = 0; d < max_depth; ++d) {
         launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
-        launch_trace(l, q, cur, any, table, used, stack);
+        launch_trace(l, q, cur, any, table, used);
         launch_shade(l, q, cur, d, any, table, used);
         launch_shadow(l, q, 0, any, table, used, d);
         if (env) launch_shadow(l, q, 1, any, table, used, d);
@@ -227,10 +226,10 @@ void dpcs_server_s::wave(Launch& l) {
         cur = 0;
         for (int d = 0; d < max_depth; ++d) {
             launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
-            launch_trace(l, q, cur, any, table, n_adj, stack);
+            launch_trace(l, q, cur, any, table, n_adj);
             launch_adj_shade(l, q, aq, cur, d, any, table, n_adj);
-            launch_adj_shadow(l, q, aq, 0, cur ^ 1, any, table, n_adj, stack);
-            if (env) launch_adj_shadow(l, q, aq, 1, cur ^ 1, any, table, n_adj, stack);
+            launch_adj_shadow(l, q, aq, 0, cur ^ 1, any, table, n_adj);
+            if (env) launch_adj_shadow(l, q, aq, 1, cur ^ 1, any, table, n_adj);
             cur ^= 1;
         }
     }
@@ -243,20 +242,20 @@ void dpcs_server_s::wave(Launch& l) {
             if (q->adjoint)
                 launch_adj_finish(l, q->r, q->grads.d_proj_image, q->grads.d_albedo, q->grads.d_roughness,
                                   q->grads.d_specular, q->grads.d_scalars, q->r.d_acc);
-            hipEventRecord(q->done, st);
+            (void)hipEventRecord(q->done, st);
         }
     }
     if (hipGetLastError() != hipSuccess) err = "kernel launch failed in the server loop";
 }
 
 void dpcs_server_s::run() {
-    hipSetDevice(ctx->device);
+    (void)hipSetDevice(ctx->device);
     Launch l{st, ctx->grid_cap};
     std::deque<hipEvent_t> inflight;
     std::vector<hipEvent_t> ev_pool;
     for (int k = 0; k < 4; ++k) {
         hipEvent_t e;
-        hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
         ev_pool.push_back(e);
     }
     size_t ev_next = 0;
@@ -288,10 +287,10 @@ void dpcs_server_s::run() {
         }
         if (launched) {
             hipEvent_t e = ev_pool[ev_next++ % ev_pool.size()];
-            hipEventRecord(e, st);
+            (void)hipEventRecord(e, st);
             inflight.push_back(e);
             while (inflight.size() > 2) {   // keep at most two waves queued on the device
-                hipEventSynchronize(inflight.front());
+                (void)hipEventSynchronize(inflight.front());
                 inflight.pop_front();
             }
         } else if (!finishing.empty()) {
@@ -314,13 +313,13 @@ void dpcs_server_s::run() {
             admitted_bytes -= q->bytes;
             free_slots.push_back(q->slot);
             q->scene->refs.fetch_sub(1);
-            hipEventDestroy(q->done);
+            (void)hipEventDestroy(q->done);
             delete q;
             it = finishing.erase(it);
         }
     }
-    hipStreamSynchronize(st);
-    for (auto e : ev_pool) hipEventDestroy(e);
+    (void)hipStreamSynchronize(st);
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
 }
 
 extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget_bytes, int32_t max_slots,
@@ -329,7 +328,7 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     *out = nullptr;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (ctx->sticky) return DPCS_E_DEVICE;
-    hipSetDevice(ctx->device);
+    (void)hipSetDevice(ctx->device);
     (void)hipGetLastError();
     auto* s = new dpcs_server_s();
     s->ctx = ctx;
@@ -353,10 +352,10 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     ok = ok && hipMalloc(&s->qbuf, qbytes) == hipSuccess;
     ok = ok && hipMalloc((void**)&s->arena_base, arena_bytes) == hipSuccess;
     if (!ok) {
-        hipGetLastError();
-        if (s->table) hipFree(s->table);
-        if (s->qbuf) hipFree(s->qbuf);
-        if (s->st) hipStreamDestroy(s->st);
+        (void)hipGetLastError();
+        if (s->table) (void)hipFree(s->table);
+        if (s->qbuf) (void)hipFree(s->qbuf);
+        if (s->st) (void)hipStreamDestroy(s->st);
         delete s;
         return fail(ctx, DPCS_E_OOM, "server allocation failed");
     }
@@ -405,7 +404,7 @@ extern "C" dpcs_status dpcs_server_submit(dpcs_server s, const dpcs_request* rq)
     if (!s || !rq) return DPCS_E_INVALID;
     dpcs_context ctx = s->ctx;
     if (!rq->scene || rq->scene->ctx != ctx || !rq->out_image) return DPCS_E_INVALID;
-    hipSetDevice(ctx->device);
+    (void)hipSetDevice(ctx->device);
     auto* q = new Req();
     std::string why;
     if (!fill_desc(ctx, q->r, &rq->params, rq->scene, rq->proj_image, &why)) {
@@ -491,12 +490,12 @@ extern "C" dpcs_status dpcs_server_destroy(dpcs_server s) {
         s->cv.notify_all();
     }
     s->worker.join();
-    hipSetDevice(s->ctx->device);
-    hipStreamSynchronize(s->st);
-    hipFree(s->arena_base);
-    hipFree(s->qbuf);
-    hipFree(s->table);
-    hipStreamDestroy(s->st);
+    (void)hipSetDevice(s->ctx->device);
+    (void)hipStreamSynchronize(s->st);
+    (void)hipFree(s->arena_base);
+    (void)hipFree(s->qbuf);
+    (void)hipFree(s->table);
+    (void)hipStreamDestroy(s->st);
     const bool failed = !s->err.empty();
     delete s;
     return failed ? DPCS_E_DEVICE : DPCS_OK;

@@ -23,7 +23,7 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     ReqDesc r;
     std::string why;
     if (!fill_desc(ctx, r, params, scene, proj_image, &why)) return fail(ctx, DPCS_E_INVALID, why);
-    hipSetDevice(ctx->device);
+    if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
     r.grad_image = grad_image;
     dpcs_status st = DPCS_OK;
     if (!prepare_request(ctx, r, params, "vjp", &st)) return st;
