@@ -154,7 +154,8 @@ def serving_bench(ctx, n_req, n_alone, warmup=20, rate=50.0):
         "alone_p50_ms": round(float(np.percentile(alone, 50)), 2),
         "alone_p99_ms": round(float(np.percentile(alone, 99)), 2), "alone_requests": len(alone),
         "waves": stats["waves"], "peak_admitted_bytes": stats["peak_bytes"],
-        "scenes_tris": [int(i.num_triangles) for i in infos],
+        "scenes_tris": [int(i.num_triangles) for i in infos], "scenes_wide_nodes": [int(i.wide_nodes) for i in infos],
+        "scenes_bvh_depth": [int(i.max_depth) for i in infos],
         "bvh_build_ms": [round(i.build_ms, 2) for i in infos], "setup_s": round(setup_s, 1),
         "note": "samples count fwd + replay for compensation steps; latency = submit to device completion",
     }

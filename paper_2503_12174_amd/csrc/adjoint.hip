@@ -749,6 +749,7 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
         // E_p cotangent of this vertex's projector term
         double e_pu = 0.0, e_pv = 0.0;
         float eg[3] = {0.f, 0.f, 0.f};
+        int lslot = -1;   // request slot of this lane's path (-1: no path)
         const ReqDesc* rp = &sel<UNI>(uni, table, 0);
         if (i < n) {
             PathO o;
@@ -773,6 +774,7 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
             }
             const ReqDesc& r = sel<UNI>(uni, table, o.slot);
             rp = &r;
+            lslot = o.slot;
             const uint32_t g = dd.g;
             const uint32_t sid = g - r.g_base + r.sid_base;
             const uint32_t rec = r.rec[(size_t)(g - r.rec_g0) * r.max_depth + depth];
@@ -897,9 +899,20 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
             scatter_tex(*rp, b_on, b_u, b_v, bg);
             if (rp->dEp) scatter_ep(*rp, e_on, e_pu, e_pv, eg);
         } else {
-            if (a_on) scatter_tex_lane(*rp, a_u, a_v, ag);
-            if (b_on) scatter_tex_lane(*rp, b_u, b_v, bg);
-            if (e_on) scatter_ep_lane(*rp, e_pu, e_pv, eg);
+            // several requests: when every path of this wave belongs to one of them (the
+            // usual case, segments are contiguous) the wave still sums shared texels
+            const unsigned long long vm = __ballot(lslot >= 0);
+            const int s0 = vm ? __shfl(lslot, __ffsll(vm) - 1) : -1;
+            if (s0 >= 0 && __ballot(lslot >= 0 && lslot != s0) == 0ull) {
+                const ReqDesc& rr = table[s0];
+                scatter_tex(rr, a_on, a_u, a_v, ag);
+                scatter_tex(rr, b_on, b_u, b_v, bg);
+                if (rr.dEp) scatter_ep(rr, e_on, e_pu, e_pv, eg);
+            } else {
+                if (a_on) scatter_tex_lane(*rp, a_u, a_v, ag);
+                if (b_on) scatter_tex_lane(*rp, b_u, b_v, bg);
+                if (e_on) scatter_ep_lane(*rp, e_pu, e_pv, eg);
+            }
         }
         const bool pred[1] = {cont};
         uint32_t* const ctr[1] = {&q.cnt[nxt]};

@@ -117,6 +117,8 @@ struct dpcs_server_s {
     void* qbuf = nullptr;
     Queues q{};
     AdjQueues aq{};
+    uint32_t* rec = nullptr;     // path records of a wave's compensation segments
+    int64_t rec_cap = 0;         // words
     std::vector<int> free_slots;
     std::mutex mu;
     std::condition_variable cv;
@@ -192,7 +194,6 @@ void dpcs_server_s::wave(Launch& l) {
         Seg s{q, (uint32_t)q->next_pixel, (uint32_t)(q->next_pixel + px)};
         q->r.g_base = s.a * (uint32_t)spp;
         q->r.sid_base = (uint32_t)used;
-        launch_set_desc(l, table, q->slot, q->r);
         segs.push_back(s);
         used += px * spp;
         if (q->adjoint) n_adj = used, any_adj = true;
@@ -201,6 +202,24 @@ void dpcs_server_s::wave(Launch& l) {
         env = env || q->r.env_on;
     }
     if (segs.empty()) return;
+    // path records for the compensation segments, when they fit: the replay then reads
+    // hits and shadow visibility instead of tracing again
+    int64_t rec_need = 0;
+    for (const Seg& s : segs)
+        if (s.q->adjoint) rec_need += (int64_t)(s.b - s.a) * s.q->r.spp * s.q->r.max_depth;
+    const bool replay = any_adj && rec_need <= rec_cap;
+    int64_t rec_off = 0;
+    for (const Seg& s : segs) {
+        Req* q = s.q;
+        if (replay && q->adjoint) {
+            q->r.rec = rec + rec_off;
+            q->r.rec_g0 = s.a * (uint32_t)q->r.spp;
+            rec_off += (int64_t)(s.b - s.a) * q->r.spp * q->r.max_depth;
+        } else {
+            q->r.rec = nullptr;
+        }
+        launch_set_desc(l, table, q->slot, q->r);
+    }
     const ReqDesc& any = segs[0].q->r;
     // forward over the shared queues
     launch_set_count(l, q.cnt, 0, (uint32_t)used, 1, 4);
@@ -226,10 +245,14 @@ void dpcs_server_s::wave(Launch& l) {
         cur = 0;
         for (int d = 0; d < max_depth; ++d) {
             launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
-            launch_trace(l, q, cur, any, table, n_adj);
-            launch_adj_shade(l, q, aq, cur, d, any, table, n_adj);
-            launch_adj_shadow(l, q, aq, 0, cur ^ 1, any, table, n_adj);
-            if (env) launch_adj_shadow(l, q, aq, 1, cur ^ 1, any, table, n_adj);
+            if (replay) {
+                launch_adj_replay(l, q, aq, cur, d, any, table, n_adj);
+            } else {
+                launch_trace(l, q, cur, any, table, n_adj);
+                launch_adj_shade(l, q, aq, cur, d, any, table, n_adj);
+                launch_adj_shadow(l, q, aq, 0, cur ^ 1, any, table, n_adj);
+                if (env) launch_adj_shadow(l, q, aq, 1, cur ^ 1, any, table, n_adj);
+            }
             cur ^= 1;
         }
     }
@@ -339,8 +362,9 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     const int64_t fit = (int64_t)(memory_budget_bytes / 4 / per_path);
     s->cap = std::max<int64_t>(1024, std::min<int64_t>({ctx->capacity, int64_t(1) << 22, fit}));
     const size_t c = (size_t)s->cap;
-    // + 256 bytes of alignment slack per part (38 parts)
-    const size_t qbytes = c * per_path + 64 * 256 + 4 * spill_ints(ctx->grid_cap);
+    // + 256 bytes of alignment slack per part (38 parts); path records for up to 8
+    // vertices per path of a wave
+    const size_t qbytes = c * per_path + 64 * 256 + 4 * spill_ints(ctx->grid_cap) + 4 * 8 * c;
     s->shared_bytes = qbytes + sizeof(ReqDesc) * (size_t)max_slots;
     if (s->shared_bytes >= s->budget) {
         delete s;
@@ -392,6 +416,8 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     s->aq.eb = MapBins{};
     s->q.cnt = (uint32_t*)take(16);
     s->q.spill = (int*)take(4 * spill_ints(ctx->grid_cap));
+    s->rec = (uint32_t*)take(4 * 8 * c);
+    s->rec_cap = 8 * (int64_t)c;
     s->q.cap = s->cap;
     s->q.stats = nullptr;
     for (int k = max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
