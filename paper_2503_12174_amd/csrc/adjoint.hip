@@ -159,14 +159,17 @@ __device__ __forceinline__ bool put_ep_rec(const MapBins& mb, uint32_t slot, dou
 }
 
 // ---------------------------------------------------------------- per pixel
-// Eq. 5 backward: y = g_c w E_c, I_c = y^gamma_c;  Eq. 12 backward per sample
-__global__ void k_adj_pixel(Queues q, AdjQueues aq, ReqDesc r, uint32_t p0, uint32_t p1, const float* sample_L) {
-    const uint32_t p = p0 + blockIdx.x * blockDim.x + threadIdx.x;
+// Eq. 5 backward: y = g_c w E_c, I_c = y^gamma_c;  Eq. 12 backward per sample.
+// PIX_LANES lanes per pixel stride over its samples, reductions inside the lane group.
+__global__ void __launch_bounds__(BLOCK) k_adj_pixel(Queues q, AdjQueues aq, ReqDesc r, uint32_t p0, uint32_t p1,
+                                                     const float* sample_L) {
+    const uint32_t p = p0 + (blockIdx.x * BLOCK + threadIdx.x) / PIX_LANES;
+    const int lane = threadIdx.x & (PIX_LANES - 1);
     float acc[7] = {0, 0, 0, 0, 0, 0, 0};   // d gamma_c[3], d w[3], d threshold
-    if (p < p1) {
+    if (p < p1) {   // uniform per lane group
         const float thr = clip_threshold(r);
         float Ls[3] = {0.f, 0.f, 0.f};
-        for (int s = 0; s < r.spp; ++s) {
+        for (int s = lane; s < r.spp; s += PIX_LANES) {
             const uint32_t g = p * (uint32_t)r.spp + (uint32_t)s;
             float4 L;
             if (sample_L) {
@@ -179,6 +182,10 @@ __global__ void k_adj_pixel(Queues q, AdjQueues aq, ReqDesc r, uint32_t p0, uint
             Ls[1] += r.clip ? fminf(L.y, thr) : L.y;
             Ls[2] += r.clip ? fminf(L.z, thr) : L.z;
         }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int off = PIX_LANES / 2; off > 0; off >>= 1) Ls[c] += __shfl_xor(Ls[c], off);
         float dE[3];
         for (int c = 0; c < 3; ++c) {
             const float Ec = Ls[c] / (float)r.spp;
@@ -195,11 +202,13 @@ __global__ void k_adj_pixel(Queues q, AdjQueues aq, ReqDesc r, uint32_t p0, uint
             if (y > 0.f && G != 0.f) {
                 const float dy = G * gc * powf(y, gc - 1.f);
                 dE[c] = dy * r.crf_gain * w;
-                acc[c] += G * powf(y, gc) * logf(y);
-                acc[3 + c] += dy * r.crf_gain * Ec;
+                if (lane == 0) {   // per-pixel terms, once
+                    acc[c] += G * powf(y, gc) * logf(y);
+                    acc[3 + c] += dy * r.crf_gain * Ec;
+                }
             }
         }
-        for (int s = 0; s < r.spp; ++s) {
+        for (int s = lane; s < r.spp; s += PIX_LANES) {
             const uint32_t g = p * (uint32_t)r.spp + (uint32_t)s;
             const uint32_t sid = g - r.g_base + r.sid_base;
             const float4 L = q.L[sid];
@@ -219,11 +228,11 @@ __global__ void k_adj_pixel(Queues q, AdjQueues aq, ReqDesc r, uint32_t p0, uint
     }
     // block reduction of the scalar partials, one atomic per value per workgroup
     __shared__ float red[7][BLOCK / 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wv = threadIdx.x >> 6;
     for (int k = 0; k < 7; ++k) {
         float v = acc[k];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) red[k][wv] = v;
+        if ((threadIdx.x & 63) == 0) red[k][wv] = v;
     }
     __syncthreads();
     if (threadIdx.x < 7) {
@@ -1013,8 +1022,8 @@ static inline unsigned grid_cap(const Launch& l, int64_t n, int b) {
 void launch_adj_pixel(const Launch& l, const Queues& q, const AdjQueues& aq, const ReqDesc& r, uint32_t p0,
                       uint32_t p1, const float* sample_L) {
     if (p1 > p0)
-        hipLaunchKernelGGL(k_adj_pixel, dim3(grid_of(p1 - p0, BLOCK)), dim3(BLOCK), 0, l.st, q, aq, r, p0, p1,
-                           sample_L);
+        hipLaunchKernelGGL(k_adj_pixel, dim3(grid_of((int64_t)(p1 - p0) * PIX_LANES, BLOCK)), dim3(BLOCK), 0, l.st, q, aq, r,
+                           p0, p1, sample_L);
 }
 void launch_adj_raygen(const Launch& l, const Queues& q, const AdjQueues& aq, const ReqDesc& r, int slot, uint32_t g0,
                        uint32_t n) {

@@ -17,6 +17,7 @@
 namespace dpcs {
 
 constexpr int BLOCK = 256;          // threads per workgroup (4 wave64)
+constexpr int PIX_LANES = 8;        // lanes per pixel in the per-pixel sample reductions
 constexpr double PI = 3.14159265358979323846;
 constexpr double P_SPEC = 0.25;     // probability of sampling the GGX lobe
 constexpr double ALPHA_MIN = 1e-3;  // GGX alpha floor

@@ -257,12 +257,16 @@ __device__ __forceinline__ float crf(const ReqDesc& r, int c, float Ec) {
     return y > 0.0f ? powf(y, scalar(r, 12 + c)) : 0.0f;
 }
 
-__global__ void k_finalize(Queues q, ReqDesc r, uint32_t p0, uint32_t p1) {
-    const uint32_t p = p0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= p1) return;
+// PIX_LANES lanes per pixel stride over its samples (neighbouring lanes read neighbouring
+// samples), then a reduction inside the lane group; the per-pixel math stays spread
+// over 64 / PIX_LANES pixels per wave.
+__global__ void __launch_bounds__(256) k_finalize(Queues q, ReqDesc r, uint32_t p0, uint32_t p1) {
+    const uint32_t p = p0 + (blockIdx.x * 256u + threadIdx.x) / PIX_LANES;
+    if (p >= p1) return;   // uniform per lane group
+    const int lane = threadIdx.x & (PIX_LANES - 1);
     const float thr = clip_threshold(r);
     float acc[3] = {0.0f, 0.0f, 0.0f};
-    for (int s = 0; s < r.spp; ++s) {
+    for (int s = lane; s < r.spp; s += PIX_LANES) {
         const uint32_t g = p * (uint32_t)r.spp + (uint32_t)s;
         const float4 L = q.L[g - r.g_base + r.sid_base];
         const float l[3] = {L.x, L.y, L.z};
@@ -271,11 +275,16 @@ __global__ void k_finalize(Queues q, ReqDesc r, uint32_t p0, uint32_t p1) {
             acc[c] += r.clip ? fminf(l[c], thr) : l[c];
         }
     }
-    for (int c = 0; c < 3; ++c) {
-        const float Ec = acc[c] / (float)r.spp;
-        if (r.out_linear) r.out_linear[3 * (size_t)p + c] = Ec;
-        if (r.out_image) r.out_image[3 * (size_t)p + c] = crf(r, c, Ec);
-    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int off = PIX_LANES / 2; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off);
+    if (lane == 0)
+        for (int c = 0; c < 3; ++c) {
+            const float Ec = acc[c] / (float)r.spp;
+            if (r.out_linear) r.out_linear[3 * (size_t)p + c] = Ec;
+            if (r.out_image) r.out_image[3 * (size_t)p + c] = crf(r, c, Ec);
+        }
 }
 
 // ---------------------------------------------------------------- debug
@@ -380,7 +389,8 @@ void launch_shadow(const Launch& l, const Queues& q, int which, const ReqDesc& u
 }
 void launch_finalize(const Launch& l, const Queues& q, const ReqDesc& r, const ReqDesc*, int, uint32_t p0,
                      uint32_t p1) {
-    if (p1 > p0) hipLaunchKernelGGL(k_finalize, dim3(grid_of(p1 - p0, 256)), dim3(256), 0, l.st, q, r, p0, p1);
+    if (p1 > p0)
+        hipLaunchKernelGGL(k_finalize, dim3(grid_of((int64_t)(p1 - p0) * PIX_LANES, 256)), dim3(256), 0, l.st, q, r, p0, p1);
 }
 void launch_debug_intersect(const Launch& l, const float4* nodes4, const float4* nodes, const float4* tris,
                             const int* leaf_of_prim, int nt, float tmin, const float* rays, int64_t n, int mode,
