@@ -174,23 +174,35 @@ void dpcs_server_s::admit_locked(Launch& l) {
 }
 
 void dpcs_server_s::wave(Launch& l) {
-    // share the wave's capacity among active requests, whole pixels each, adjoint first
-    std::vector<Req*> order;
+    // Fill the wave's capacity with whole pixels, least remaining work first (shortest
+    // remaining processing time: small requests finish within a wave or two instead of
+    // sharing every wave with the large ones); then order the segments with the
+    // compensation steps first so their replay has a dense queue prefix.
+    std::vector<Req*> pick;
     for (Req* q : active)
-        if (q->adjoint && !q->scheduled_all) order.push_back(q);
-    for (Req* q : active)
-        if (!q->adjoint && !q->scheduled_all) order.push_back(q);
-    if (order.empty()) return;
+        if (!q->scheduled_all) pick.push_back(q);
+    if (pick.empty()) return;
+    auto remaining = [](const Req* q) {
+        return (q->npix - q->next_pixel) * (int64_t)q->r.spp * (q->adjoint ? 2 : 1);
+    };
+    std::stable_sort(pick.begin(), pick.end(), [&](const Req* a, const Req* b) { return remaining(a) < remaining(b); });
+    std::vector<std::pair<Req*, int64_t>> take;   // request, pixels this wave
+    int64_t room = cap;
+    for (Req* q : pick) {
+        const int64_t px = std::min<int64_t>(q->npix - q->next_pixel, room / q->r.spp);
+        if (px <= 0) continue;
+        take.push_back({q, px});
+        room -= px * q->r.spp;
+    }
+    std::stable_partition(take.begin(), take.end(), [](const std::pair<Req*, int64_t>& t) { return t.first->adjoint; });
     std::vector<Seg> segs;
     int64_t used = 0, n_adj = 0;
     int max_depth = 1;
     bool env = false, any_adj = false;
-    const int64_t share = std::max<int64_t>(1, cap / (int64_t)order.size());
-    for (Req* q : order) {
+    for (const auto& t : take) {
+        Req* q = t.first;
         const int spp = q->r.spp;
-        int64_t px = std::min<int64_t>(q->npix - q->next_pixel, std::max<int64_t>(1, share / spp));
-        px = std::min<int64_t>(px, (cap - used) / spp);
-        if (px <= 0) continue;
+        const int64_t px = t.second;
         Seg s{q, (uint32_t)q->next_pixel, (uint32_t)(q->next_pixel + px)};
         q->r.g_base = s.a * (uint32_t)spp;
         q->r.sid_base = (uint32_t)used;
