@@ -253,7 +253,8 @@ __global__ void k_adj_raygen(Queues q, AdjQueues aq, ReqDesc r, int slot, uint32
     q.pd[0][sid] = PathD{d.x, d.y, d.z, g, 0u};
     q.pb[0][sid] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
     aq.rl[0][sid] = q.L[sid];
-    aq.pend[0][sid] = make_float4(0.f, 0.f, 0.f, 0.f);
+    aq.pend[0][sid] = make_float2(0.f, 0.f);
+    aq.puv[0][sid] = make_double2(0.0, 0.0);
     aq.penda[0][sid] = make_float4(0.f, 0.f, 0.f, -1.f);   // w < 0: no pending bounce
     aq.pn[0][sid] = make_float4(0.f, 0.f, 0.f, 0.f);
     aq.pns[0][sid] = 0.f;
@@ -274,9 +275,11 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
         bool cont = false, shp = false, she = false;
         PathO no{};
         PathD nd{};
-        float4 nb = {}, nrl = {}, npend = {}, npenda = {};
-        float4 po = {}, pd = {}, pc = {}, px = {}, pg = {}, pa = {};
-        float4 eo = {}, ed = {}, ec = {}, ex = {}, ea = {};
+        float4 nb = {}, nrl = {}, npenda = {};
+        float2 npend = {};
+        double2 npuv = {}, pxp = {}, pxt = {}, ext = {};
+        float4 po = {}, pd = {}, pc = {}, pg = {}, pa = {};
+        float4 eo = {}, ed = {}, ec = {}, ea = {};
         float ptmax = 0.f, ps = 0.f, es = 0.f;
         bool pend_on = false;
         double pend_u = 0.0, pend_v = 0.0;
@@ -295,21 +298,23 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
             const D3 delta = d3(dl.x, dl.y, dl.z);
             const D3 beta = d3(b.x, b.y, b.z);
             float4 rl = aq.rl[cur][i];
-            const float4 pend = aq.pend[cur][i], penda = aq.penda[cur][i];
+            const float4 penda = aq.penda[cur][i];
             if (leaf >= 0) {
                 const Surf s = surface(r, leaf, d3(o.x, o.y, o.z), d3(dd.x, dd.y, dd.z));
                 // the previous vertex's bounce: d/df of beta_k f cos/pdf R_{k+1} = L_r / f
                 if (penda.w >= 0.f) {
                     const D3 t = delta * d3(rl.x, rl.y, rl.z) * d3(penda.x, penda.y, penda.z);
                     const double sum = t.x + t.y + t.z;
+                    const float2 pend = aq.pend[cur][i];
+                    const double2 puv = aq.puv[cur][i];
                     pend_on = true;
-                    pend_u = pend.x;
-                    pend_v = pend.y;
+                    pend_u = puv.x;
+                    pend_v = puv.y;
                     pend_g[0] = (float)(t.x * (1.0 / PI));
                     pend_g[1] = (float)(t.y * (1.0 / PI));
                     pend_g[2] = (float)(t.z * (1.0 / PI));
-                    pend_g[3] = (float)(sum * pend.z);
-                    pend_g[4] = (float)(sum * pend.w);
+                    pend_g[3] = (float)(sum * pend.x);
+                    pend_g[4] = (float)(sum * pend.y);
                 }
                 if (r.emission) {
                     const float4 e = r.emission[leaf];
@@ -331,7 +336,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
                     po = f4(to_f(s.x), __int_as_float(o.slot));
                     pd = f4(to_f(p.wp), __int_as_float(s.prim));
                     pc = f4(to_f(C), __int_as_float(-1));   // w: next-queue index, set below
-                    px = make_float4((float)p.pu, (float)p.pv, (float)s.u, (float)s.v);
+                    pxp = make_double2(p.pu, p.pv);
+                    pxt = make_double2(s.u, s.v);
                     pg = f4(to_f(gE), 0.f);
                     pa = f4(to_f(ga), (float)(sx * f.ds_dr));
                     ps = (float)(sx * f.ds_dsp);
@@ -349,7 +355,7 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
                     eo = f4(to_f(s.x), __int_as_float(o.slot));
                     ed = f4(to_f(we), __int_as_float(s.prim));
                     ec = f4(to_f(C), __int_as_float(-1));
-                    ex = make_float4(0.f, 0.f, (float)s.u, (float)s.v);
+                    ext = make_double2(s.u, s.v);
                     ea = f4(to_f(ga), (float)(sx * f.ds_dr));
                     es = (float)(sx * f.ds_dsp);
                 }
@@ -366,7 +372,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
                         nd = PathD{wi.x, wi.y, wi.z, g, 0u};
                         nb = make_float4((float)nbeta.x, (float)nbeta.y, (float)nbeta.z, 0.0f);
                         nrl = rl;
-                        npend = make_float4((float)s.u, (float)s.v, (float)f.ds_dr, (float)f.ds_dsp);
+                        npuv = make_double2(s.u, s.v);
+                        npend = make_float2((float)f.ds_dr, (float)f.ds_dsp);
                         npenda = make_float4(f.f.x > 0.0 ? (float)(1.0 / f.f.x) : 0.f,
                                              f.f.y > 0.0 ? (float)(1.0 / f.f.y) : 0.f,
                                              f.f.z > 0.0 ? (float)(1.0 / f.f.z) : 0.f, 1.f);
@@ -393,6 +400,7 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
             q.pb[nxt][jn] = nb;
             aq.rl[nxt][jn] = nrl;
             aq.pend[nxt][jn] = npend;
+            aq.puv[nxt][jn] = npuv;
             aq.penda[nxt][jn] = npenda;
         }
         const int next_idx = cont ? (int)jn : -1;
@@ -402,7 +410,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
             q.sd[0][jp] = pd;
             q.sc[0][jp] = pc;
             q.st[0][jp] = ptmax;
-            aq.sx[0][jp] = px;
+            aq.sproj[0][jp] = pxp;
+            aq.suv[0][jp] = pxt;
             aq.sg[0][jp] = pg;
             aq.sa[0][jp] = pa;
             aq.ss[0][jp] = ps;
@@ -413,7 +422,7 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
             q.sd[1][je] = ed;
             q.sc[1][je] = ec;
             q.st[1][je] = __builtin_inff();
-            aq.sx[1][je] = ex;
+            aq.suv[1][je] = ext;
             aq.sg[1][je] = make_float4(0.f, 0.f, 0.f, 0.f);
             aq.sa[1][je] = ea;
             aq.ss[1][je] = es;
@@ -447,7 +456,9 @@ __global__ void __launch_bounds__(TB) k_adj_shadow(Queues q, AdjQueues aq, int w
                 atomicAdd(&q.stats[1], (unsigned long long)vis.tris);
             }
         }
-        const float4 c = q.sc[which][ii], x = aq.sx[which][ii], a = aq.sa[which][ii];
+        const float4 c = q.sc[which][ii], a = aq.sa[which][ii];
+        const double2 xt = aq.suv[which][ii];
+        const double2 xp = which == 0 ? aq.sproj[0][ii] : make_double2(0.0, 0.0);
         const float sv = aq.ss[which][ii];
         if (!occ) {
             const int j = __float_as_int(c.w);
@@ -465,9 +476,9 @@ __global__ void __launch_bounds__(TB) k_adj_shadow(Queues q, AdjQueues aq, int w
                 if (which == 0 && r.dEp) {
                     const float4 gE = aq.sg[which][i];
                     const float ge[3] = {gE.x, gE.y, gE.z};
-                    scatter_ep_lane(r, x.x, x.y, ge);
+                    scatter_ep_lane(r, xp.x, xp.y, ge);
                 }
-                scatter_tex_lane(r, x.z, x.w, gt);
+                scatter_tex_lane(r, xt.x, xt.y, gt);
             }
             continue;
         }
@@ -478,11 +489,11 @@ __global__ void __launch_bounds__(TB) k_adj_shadow(Queues q, AdjQueues aq, int w
             uint32_t* const ctr[2] = {aq.tb.count, aq.eb.count};
             uint32_t at[2];
             block_append<2, TB>(pred, ctr, at);
-            if (vis && !put_tex_rec(aq.tb, at[0], x.z, x.w, gt)) scatter_tex_lane(r, x.z, x.w, gt);
+            if (vis && !put_tex_rec(aq.tb, at[0], xt.x, xt.y, gt)) scatter_tex_lane(r, xt.x, xt.y, gt);
             if (vis && which == 0 && r.dEp) {
                 const float4 gE = aq.sg[which][i];
                 const float ge[3] = {gE.x, gE.y, gE.z};
-                if (!(to_e && put_ep_rec(aq.eb, at[1], x.x, x.y, ge))) scatter_ep_lane(r, x.x, x.y, ge);
+                if (!(to_e && put_ep_rec(aq.eb, at[1], xp.x, xp.y, ge))) scatter_ep_lane(r, xp.x, xp.y, ge);
             }
             continue;
         }
@@ -490,9 +501,9 @@ __global__ void __launch_bounds__(TB) k_adj_shadow(Queues q, AdjQueues aq, int w
         if (which == 0 && r.dEp) {   // d/dE_p at the four projector texels
             const float4 gE = aq.sg[which][ii];
             const float ge[3] = {gE.x, gE.y, gE.z};
-            scatter_ep(r, !occ, x.x, x.y, ge);
+            scatter_ep(r, !occ, xp.x, xp.y, ge);
         }
-        scatter_tex(r, !occ, x.z, x.w, gt);
+        scatter_tex(r, !occ, xt.x, xt.y, gt);
     }
 }
 
@@ -749,11 +760,13 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
         bool cont = false;
         PathO no{};
         PathD nd{};
-        float4 nb = {}, nrl = {}, npend = {}, npenda = {}, npn = {};
+        float4 nb = {}, nrl = {}, npenda = {}, npn = {};
+        float2 npend = {};
+        double2 npuv = {};
         float npns = 0.f;
         // map cotangents of the previous vertex (a) and of this one when the path ends here (b)
         bool a_on = false, b_on = false, e_on = false;
-        float a_u = 0.f, a_v = 0.f, b_u = 0.f, b_v = 0.f;
+        double a_u = 0.0, a_v = 0.0, b_u = 0.0, b_v = 0.0;
         float ag[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, bg[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
         // E_p cotangent of this vertex's projector term
         double e_pu = 0.0, e_pv = 0.0;
@@ -794,11 +807,13 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
             if (penda.w >= 0.f) {
                 // previous vertex: its next-event cotangents plus d/df of its bounce,
                 // beta_k f cos/pdf R_{k+1} -> R_{k+1} / f (zero when this ray escaped)
-                const float4 pend = aq.pend[cur][i], pn = aq.pn[cur][i];
+                const float2 pend = aq.pend[cur][i];
+                const double2 puv = aq.puv[cur][i];
+                const float4 pn = aq.pn[cur][i];
                 const float pns = aq.pns[cur][i];
                 a_on = true;
-                a_u = pend.x;
-                a_v = pend.y;
+                a_u = puv.x;
+                a_v = puv.y;
                 double ga0 = pn.x, ga1 = pn.y, ga2 = pn.z, gr = pn.w, gs = pns;
                 if (leaf >= 0) {
                     const D3 t = delta * d3(rl.x, rl.y, rl.z) * d3(penda.x, penda.y, penda.z);
@@ -806,8 +821,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
                     ga0 += t.x * (1.0 / PI);
                     ga1 += t.y * (1.0 / PI);
                     ga2 += t.z * (1.0 / PI);
-                    gr += sum * pend.z;
-                    gs += sum * pend.w;
+                    gr += sum * pend.x;
+                    gs += sum * pend.y;
                 }
                 ag[0] = (float)ga0;
                 ag[1] = (float)ga1;
@@ -874,7 +889,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
                         nd = PathD{wi.x, wi.y, wi.z, g, 0u};
                         nb = make_float4((float)nbeta.x, (float)nbeta.y, (float)nbeta.z, 0.0f);
                         nrl = rl;
-                        npend = make_float4((float)s.u, (float)s.v, (float)f.ds_dr, (float)f.ds_dsp);
+                        npuv = make_double2(s.u, s.v);
+                        npend = make_float2((float)f.ds_dr, (float)f.ds_dsp);
                         npenda = make_float4(f.f.x > 0.0 ? (float)(1.0 / f.f.x) : 0.f,
                                              f.f.y > 0.0 ? (float)(1.0 / f.f.y) : 0.f,
                                              f.f.z > 0.0 ? (float)(1.0 / f.f.z) : 0.f, 1.f);
@@ -884,8 +900,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
                 }
                 if (!cont) {   // the path ends here: its next-event cotangents go out now
                     b_on = true;
-                    b_u = (float)s.u;
-                    b_v = (float)s.v;
+                    b_u = s.u;
+                    b_v = s.v;
                     bg[0] = (float)nga.x;
                     bg[1] = (float)nga.y;
                     bg[2] = (float)nga.z;
@@ -933,6 +949,7 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
             q.pb[nxt][jn] = nb;
             aq.rl[nxt][jn] = nrl;
             aq.pend[nxt][jn] = npend;
+            aq.puv[nxt][jn] = npuv;
             aq.penda[nxt][jn] = npenda;
             aq.pn[nxt][jn] = npn;
             aq.pns[nxt][jn] = npns;

@@ -84,13 +84,15 @@ struct MapBins {
 struct AdjQueues {
     float4* rl[2];     // remaining radiance L_r of the path (rgb, -), follows the path queue
     float4* delta;     // per batch sample cotangent of its radiance (rgb, -)
-    float4* sx[2];     // shadow: projector (u, v) and texture (u, v) of the vertex
+    double2* sproj[2]; // shadow: projector pixel position (pu, pv) of the vertex
+    double2* suv[2];   // shadow: texture coordinate (u, v) of the vertex (FP64: 1k+ maps)
     float4* sg[2];     // shadow: E_p cotangent weight per channel (w: -)
     float4* sa[2];     // shadow: albedo cotangent rgb (w: roughness cotangent)
     float* ss[2];      // shadow: specular cotangent
     float4* pn[2];     // replay: pending next-event cotangents of the previous vertex (albedo rgb, roughness)
     float* pns[2];     // replay: pending next-event specular cotangent
-    float4* pend[2];   // pending bounce: (u, v, dr, dsp) cotangent scale of the previous vertex
+    double2* puv[2];   // pending bounce: texture coordinate (u, v) of the previous vertex
+    float2* pend[2];   // pending bounce: (dr, dsp) cotangent scale of the previous vertex
     float4* penda[2];  // pending bounce: albedo cotangent scale rgb
     MapBins tb;        // BRDF-map cotangent records (C = 5, 8 floats per record)
     MapBins eb;        // E_p cotangent records (C = 3, 6 floats per record)

@@ -89,8 +89,8 @@ bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpc
 
 bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues& aq, dpcs_status* st) {
     const size_t c = (size_t)cap;
-    // + 256 bytes of alignment slack per part (19 parts)
-    const size_t bytes = c * (2 * 48 + 16 + 2 * 52 + 2 * 20) + 32 * 256;
+    // per path 2 x 144 + 16 bytes; + 256 bytes of alignment slack per part (23 parts)
+    const size_t bytes = c * (2 * 144 + 16) + 32 * 256;
     char* b = (char*)scratch(ctx, name, bytes, st);
     if (!b) return false;
     auto take = [&](size_t n) {
@@ -100,9 +100,11 @@ bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues&
     };
     for (int k = 0; k < 2; ++k) {
         aq.rl[k] = (float4*)take(16 * c);
-        aq.pend[k] = (float4*)take(16 * c);
+        aq.puv[k] = (double2*)take(16 * c);
+        aq.pend[k] = (float2*)take(8 * c);
         aq.penda[k] = (float4*)take(16 * c);
-        aq.sx[k] = (float4*)take(16 * c);
+        aq.sproj[k] = (double2*)take(16 * c);
+        aq.suv[k] = (double2*)take(16 * c);
         aq.sg[k] = (float4*)take(16 * c);
         aq.sa[k] = (float4*)take(16 * c);
         aq.ss[k] = (float*)take(4 * c);

@@ -370,11 +370,11 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     s->budget = memory_budget_bytes;
     s->max_slots = max_slots;
     // shared wave queues take at most a quarter of the budget
-    const size_t per_path = (2 * 80 + 4 + 2 * 52 + 16) + (2 * 48 + 16 + 2 * 52 + 2 * 20);
+    const size_t per_path = (2 * 80 + 4 + 2 * 52 + 16) + (2 * 144 + 16);
     const int64_t fit = (int64_t)(memory_budget_bytes / 4 / per_path);
     s->cap = std::max<int64_t>(1024, std::min<int64_t>({ctx->capacity, int64_t(1) << 22, fit}));
     const size_t c = (size_t)s->cap;
-    // + 256 bytes of alignment slack per part (38 parts); path records for up to 8
+    // + 256 bytes of alignment slack per part (42 parts); path records for up to 8
     // vertices per path of a wave
     const size_t qbytes = c * per_path + 64 * 256 + 4 * spill_ints(ctx->grid_cap) + 4 * 8 * c;
     s->shared_bytes = qbytes + sizeof(ReqDesc) * (size_t)max_slots;
@@ -412,9 +412,11 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
         s->q.sc[k] = (float4*)take(16 * c);
         s->q.st[k] = (float*)take(4 * c);
         s->aq.rl[k] = (float4*)take(16 * c);
-        s->aq.pend[k] = (float4*)take(16 * c);
+        s->aq.puv[k] = (double2*)take(16 * c);
+        s->aq.pend[k] = (float2*)take(8 * c);
         s->aq.penda[k] = (float4*)take(16 * c);
-        s->aq.sx[k] = (float4*)take(16 * c);
+        s->aq.sproj[k] = (double2*)take(16 * c);
+        s->aq.suv[k] = (double2*)take(16 * c);
         s->aq.sg[k] = (float4*)take(16 * c);
         s->aq.sa[k] = (float4*)take(16 * c);
         s->aq.ss[k] = (float*)take(4 * c);

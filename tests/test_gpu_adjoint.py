@@ -141,3 +141,21 @@ def test_path_records_match_hits():
     assert ((rec[hp == -1] >> np.uint32(30)) == 0).all()   # no shadow rays from an escaped vertex
     assert (rec[hp >= 0] >> np.uint32(31)).any()           # some projector shadow rays are unoccluded
     np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_vjp_unbinned_large_maps():
+    """BRDF maps and projector image above 1024^2 are not binned: every replay mode
+    scatters their cotangents with wave-aggregated atomics instead."""
+    import math
+    w = scenes.c3_ggx(spp=4, seed=11, max_depth=3)
+    w.albedo, w.roughness, w.specular = synth.ggx_textures(909, 1040)
+    ang = math.radians(30.0)
+    eye_p = (-0.6 * math.sin(ang), 0.0, 0.6 * math.cos(ang))
+    w.projector = synth.pinhole(eye_p, (0, 0, 0), 60.0, 1040, 1040, up=(0, 1, 0))
+    w.proj_image = np.random.default_rng(910).uniform(0, 1, (1040, 1040, 3)).astype(np.float32)
+    sc = O.Scene(w)
+    G = _clean_cotangent(w, 7, sc)
+    ref = O.render_vjp(sc, G)
+    run = GpuRun(w)
+    for mode in VJP_MODES:
+        compare_grads(run_vjp(run, G, mode=mode), ref)
