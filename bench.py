@@ -73,7 +73,7 @@ def serving_bench(ctx, n_req, n_alone, warmup=20, rate=50.0):
 
     t = time.perf_counter()
     meshes = synth.serving_scenes()
-    scenes = [dpcs.Scene(ctx, m) for m in meshes]
+    scenes = [dpcs.Scene(ctx, m, bvh="sah") for m in meshes]
     infos = [sc.info() for sc in scenes]
     alb, rough, spec = (torch.as_tensor(x).cuda() for x in synth.ggx_textures(503, 512))
     reqs = synth.serving_requests(warmup + n_req, seed=501, rate=rate)
@@ -175,7 +175,7 @@ def main():
 
     w = synth.corner_50k()
     ctx = dpcs.Context(0)
-    scene = dpcs.Scene(ctx, w.mesh)
+    scene = dpcs.Scene(ctx, w.mesh, bvh="sah")
     info = scene.info()
     dev = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.float32)).cuda()
     alb, rough, spec, proj = dev(w.albedo), dev(w.roughness), dev(w.specular), dev(w.proj_image)
@@ -307,7 +307,7 @@ def main():
         "vs_baseline": None, "dtype": "f32 traversal + f64 shading", "data": "synthetic",
         "config": {"workload": w.name, "camera": [W, H], "projector": [w.projector.width, w.projector.height],
                    "spp": w.spp, "max_depth": w.max_depth, "triangles": info.num_triangles,
-                   "bvh_build_ms": round(info.build_ms, 3),
+                   "bvh": "binned SAH (host) collapsed to 4-wide", "bvh_build_ms": round(info.build_ms, 3),
                    "step": "forward render keeping per-sample radiance and 4-byte path records + VJP "
                            "replaying the same samples"},
         "fwd_samples_per_s": round(fwd_sps, 1), "fwd_ms": round(ms_fwd, 4),

@@ -87,7 +87,12 @@ typedef struct {
     int32_t num_triangles;
     const float* corner_uvs;    /* num_triangles x 3 x 2 texture coordinates */
     const float* emission;      /* NULL, or num_triangles x 3 surface radiance (test scenes) */
+    int32_t bvh_kind;           /* DPCS_BVH_LBVH (0): Morton LBVH built on the device;
+                                   DPCS_BVH_SAH (1): binned-SAH tree built on the host.
+                                   Either is then collapsed to the 4-wide traversal tree. */
 } dpcs_mesh_desc;
+
+enum { DPCS_BVH_LBVH = 0, DPCS_BVH_SAH = 1 };
 
 typedef struct {
     int32_t num_triangles;

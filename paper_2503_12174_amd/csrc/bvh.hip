@@ -246,6 +246,14 @@ __global__ void k_leaf_records(const float* __restrict__ V, const int* __restric
 // ---------------------------------------------------------------- host side
 static inline unsigned grid_of(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+hipError_t build_leaf_records(hipStream_t st, const BvhInputs& in, const uint32_t* order, BvhOutputs& out) {
+    const int n = in.nt;
+    out.order = order;
+    hipLaunchKernelGGL(k_leaf_records, dim3(grid_of(n, 256)), dim3(256), 0, st, in.V, in.F, in.UV, in.Le, order, n,
+                       out.tris, out.tri_uv, out.emission, out.leaf_of_prim);
+    return hipGetLastError();
+}
+
 hipError_t build_bvh(hipStream_t st, const BvhInputs& in, BvhOutputs& out) {
     const int n = in.nt;
     const int ntiles = (n + SORT_TILE - 1) / SORT_TILE;

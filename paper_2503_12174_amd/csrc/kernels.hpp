@@ -34,6 +34,8 @@ struct BvhOutputs {
     const uint32_t* order;   // leaf -> original triangle (points into keys/vals scratch)
 };
 hipError_t build_bvh(hipStream_t st, const BvhInputs& in, BvhOutputs& out);
+// leaf-ordered triangle / UV / emission records for a leaf order built elsewhere
+hipError_t build_leaf_records(hipStream_t st, const BvhInputs& in, const uint32_t* order, BvhOutputs& out);
 
 // ------------------------------------------------------------------ path queues
 // Structure-of-arrays queues in HBM.  Path state is FP64 position/direction (PathO,

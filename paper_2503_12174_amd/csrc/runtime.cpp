@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -449,6 +450,8 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
     if (!m->positions || !m->triangles || !m->corner_uvs || m->num_vertices <= 0 || m->num_triangles <= 0)
         return fail(ctx, DPCS_E_INVALID, "mesh needs positions, triangles, corner_uvs and positive counts");
     if (m->num_triangles > (1 << 29)) return fail(ctx, DPCS_E_UNSUPPORTED, "too many triangles");
+    if (m->bvh_kind != DPCS_BVH_LBVH && m->bvh_kind != DPCS_BVH_SAH)
+        return fail(ctx, DPCS_E_INVALID, "bvh_kind must be DPCS_BVH_LBVH or DPCS_BVH_SAH");
     const int nt = m->num_triangles, nv = m->num_vertices;
     for (int64_t i = 0; i < 3 * (int64_t)nt; ++i)
         if (m->triangles[i] < 0 || m->triangles[i] >= nv)
@@ -577,6 +580,18 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
         destroy_scene();
         return fail(ctx, DPCS_E_DEVICE, "scene build: hipEventCreate failed");
     }
+    // host SAH build: the tree and leaf order come from the host, the device only
+    // writes the leaf records
+    const bool sah = m->bvh_kind == DPCS_BVH_SAH && nt > 1;
+    std::vector<float4> sah_nodes;
+    std::vector<int> child(2 * (size_t)ni);
+    std::vector<uint32_t> order(nt);
+    double sah_ms = 0.0;
+    if (sah) {
+        const auto t0 = std::chrono::steady_clock::now();
+        sah_build(m->positions, m->triangles, nt, sah_nodes, child, order);
+        sah_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
     const char* step = "upload";
     hipError_t e = hipMemcpyAsync(dV, m->positions, sizeof(float) * 3 * nv, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dF, m->triangles, sizeof(int) * 3 * nt, hipMemcpyHostToDevice, st);
@@ -584,29 +599,46 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
     if (e == hipSuccess && m->emission)
         e = hipMemcpyAsync(dLe, m->emission, sizeof(float) * 3 * nt, hipMemcpyHostToDevice, st);
     Launch l{st, ctx->grid_cap};
-    if (e == hipSuccess) {
-        step = "init";
-        launch_zero(l, (float*)in.flags, ni);
-        e = hipMemsetAsync(in.parent_int, 0xff, sizeof(int) * ni, st);   // -1: no parent (root)
-        if (e == hipSuccess) e = hipGetLastError();
+    if (sah) {
+        if (e == hipSuccess) {
+            step = "upload tree";
+            e = hipMemcpyAsync(sc->nodes, sah_nodes.data(), sizeof(float4) * sah_nodes.size(), hipMemcpyHostToDevice,
+                               st);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(in.vals[0], order.data(), sizeof(uint32_t) * nt, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) {
+            step = "leaf records";
+            e = build_leaf_records(st, in, in.vals[0], bo);
+        }
+        if (e == hipSuccess) {
+            step = "synchronize";
+            e = hipStreamSynchronize(st);   // the host vectors are read by the copies above
+        }
+    } else {
+        if (e == hipSuccess) {
+            step = "init";
+            launch_zero(l, (float*)in.flags, ni);
+            e = hipMemsetAsync(in.parent_int, 0xff, sizeof(int) * ni, st);   // -1: no parent (root)
+            if (e == hipSuccess) e = hipGetLastError();
+        }
+        if (e == hipSuccess) {
+            step = "build kernels";
+            (void)hipEventRecord(e0, st);
+            e = build_bvh(st, in, bo);
+            (void)hipEventRecord(e1, st);
+        }
+        if (e == hipSuccess) {
+            step = "synchronize";
+            e = hipStreamSynchronize(st);
+        }
+        // the tree back on the host for validation, depth and the 4-wide collapse
+        if (e == hipSuccess && nt > 1)
+            e = hipMemcpy(child.data(), in.child, sizeof(int) * 2 * ni, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(order.data(), bo.order, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost);
     }
-    if (e == hipSuccess) {
-        step = "build kernels";
-        (void)hipEventRecord(e0, st);
-        e = build_bvh(st, in, bo);
-        (void)hipEventRecord(e1, st);
-    }
-    if (e == hipSuccess) {
-        step = "synchronize";
-        e = hipStreamSynchronize(st);
-    }
-    // depth of the tree (the traversal stack bound)
-    std::vector<int> child(2 * (size_t)ni);
-    std::vector<uint32_t> order(nt);
-    if (e == hipSuccess && nt > 1) e = hipMemcpy(child.data(), in.child, sizeof(int) * 2 * ni, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(order.data(), bo.order, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost);
-    float ms = 0.f;
-    if (e == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+    float ms = (float)sah_ms;
+    if (e == hipSuccess && !sah) (void)hipEventElapsedTime(&ms, e0, e1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     cleanup_tmp();

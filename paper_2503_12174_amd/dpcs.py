@@ -28,7 +28,11 @@ class DpcsError(RuntimeError):
 
 class MeshDesc(C.Structure):
     _fields_ = [("positions", C.c_void_p), ("num_vertices", C.c_int32), ("triangles", C.c_void_p),
-                ("num_triangles", C.c_int32), ("corner_uvs", C.c_void_p), ("emission", C.c_void_p)]
+                ("num_triangles", C.c_int32), ("corner_uvs", C.c_void_p), ("emission", C.c_void_p),
+                ("bvh_kind", C.c_int32)]
+
+
+BVH_LBVH, BVH_SAH = 0, 1
 
 
 class SceneInfo(C.Structure):
@@ -186,16 +190,18 @@ class Context:
 
 
 class Scene:
-    """Resident mesh + BVH (dpcs_scene) built from a synth.Mesh-like object."""
+    """Resident mesh + BVH (dpcs_scene) built from a synth.Mesh-like object;
+    bvh = "lbvh" (Morton build on the device) or "sah" (binned SAH on the host)."""
 
-    def __init__(self, ctx: Context, mesh):
+    def __init__(self, ctx: Context, mesh, bvh: str = "lbvh"):
         self.ctx = ctx
         V = np.ascontiguousarray(mesh.vertices, np.float32)
         F = np.ascontiguousarray(mesh.triangles, np.int32)
         UV = np.ascontiguousarray(mesh.corner_uvs, np.float32)
         E = None if mesh.emission is None else np.ascontiguousarray(mesh.emission, np.float32)
+        kind = {"lbvh": BVH_LBVH, "sah": BVH_SAH}[bvh]
         d = MeshDesc(V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], UV.ctypes.data,
-                     None if E is None else E.ctypes.data)
+                     None if E is None else E.ctypes.data, kind)
         h = C.c_void_p()
         ctx.check(lib().dpcs_scene_create(ctx.h, C.byref(d), C.byref(h)))
         self.h = h

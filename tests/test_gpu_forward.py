@@ -58,15 +58,17 @@ MESHES = {
 }
 
 
+@pytest.mark.parametrize("bvh", ["lbvh", "sah"])
 @pytest.mark.parametrize("name", list(MESHES))
-def test_bvh_traversal_equals_brute_force(name):
-    """Closest hit through the BVH == brute force over all triangles, same FP32 arithmetic."""
+def test_bvh_traversal_equals_brute_force(name, bvh):
+    """Closest hit through the BVH == brute force over all triangles, same FP32 arithmetic,
+    for the device Morton build and the host SAH build."""
     import torch
     from paper_2503_12174_amd import dpcs
     mesh = MESHES[name]()
     if name == "single":
         mesh = synth.Mesh(mesh.vertices, mesh.triangles[:1], mesh.corner_uvs[:1])
-    sc = dpcs.Scene(ctx(), mesh)
+    sc = dpcs.Scene(ctx(), mesh, bvh=bvh)
     rng = np.random.default_rng(1)
     rays = _rays_for(mesh, 20000, rng)
     r = dev(rays)
