@@ -308,6 +308,7 @@ def main():
         "config": {"workload": w.name, "camera": [W, H], "projector": [w.projector.width, w.projector.height],
                    "spp": w.spp, "max_depth": w.max_depth, "triangles": info.num_triangles,
                    "bvh": "binned SAH (host) collapsed to 4-wide", "bvh_build_ms": round(info.build_ms, 3),
+                   "bvh_wide_nodes": int(info.wide_nodes),
                    "step": "forward render keeping per-sample radiance and 4-byte path records + VJP "
                            "replaying the same samples"},
         "fwd_samples_per_s": round(fwd_sps, 1), "fwd_ms": round(ms_fwd, 4),
