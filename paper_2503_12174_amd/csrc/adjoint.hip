@@ -128,7 +128,6 @@ __device__ __forceinline__ void scatter_ep(const ReqDesc& r, bool active, double
 // (bits 0..27), x1 - x0 (bit 28) and y1 - y0 (bit 29), then the offsets ax, ay and the
 // C cotangent values.
 constexpr int TEX_RS = 8, EP_RS = 6;   // floats per record (C = 5, C = 3)
-constexpr int BIN_CHUNK = 16384;       // records per workgroup in the counting passes
 
 __device__ __forceinline__ uint32_t map_head(const Corners& c, int W) {
     return (uint32_t)(c.y0 * W + c.x0) | ((uint32_t)(c.x1 - c.x0) << 28) | ((uint32_t)(c.y1 - c.y0) << 29);
@@ -431,12 +430,12 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
 }
 
 // ---------------------------------------------------------------- shadows
-// PROF only names a separate instantiation for the counting pass (q.stats set); same code
+// PROF: the counting pass's instantiation (visit counters summed into q.stats)
 template <bool UNI, bool PROF>
-__global__ void __launch_bounds__(TB) k_adj_shadow(Queues q, AdjQueues aq, int which, int nxt, ReqDesc uni,
+__global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_adj_shadow(Queues q, AdjQueues aq, int which, int nxt, ReqDesc uni,
                                                    const ReqDesc* __restrict__ table) {
-    __shared__ int stack[SHORT_STACK * TB];
-    int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL + threadIdx.x;
+    __shared__ int stack[(SHORT_STACK + 1) * TB];
+    int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL;
     const uint32_t n = q.cnt[2 + which];
     // the loop bound is uniform per workgroup so every lane reaches the wave-level scatter
     for (uint32_t base = blockIdx.x * TB; base < n; base += gridDim.x * TB) {
@@ -448,13 +447,14 @@ __global__ void __launch_bounds__(TB) k_adj_shadow(Queues q, AdjQueues aq, int w
         bool occ = true;
         if (live) {
             Hit h;
-            Visits vis;
+            Visits<PROF> vis;
             occ = trace_ray<true, SHORT_STACK, TB>(r.nodes4, r.nodes, r.tris, xyz(o), xyz(d), r.tmin, q.st[which][i],
-                                                  __float_as_int(d.w), h, stack + threadIdx.x, spill, vis);
-            if (q.stats) {
-                atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
-                atomicAdd(&q.stats[1], (unsigned long long)vis.tris);
-            }
+                                                  __float_as_int(d.w), h, stack, spill, threadIdx.x, vis);
+            if constexpr (PROF)
+                if (q.stats) {
+                    atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
+                    atomicAdd(&q.stats[1], (unsigned long long)vis.tris);
+                }
         }
         const float4 c = q.sc[which][ii], a = aq.sa[which][ii];
         const double2 xt = aq.suv[which][ii];
@@ -535,8 +535,10 @@ __device__ __forceinline__ uint32_t map_records(const MapBins& mb) {
     return (int64_t)n < mb.cap ? n : (uint32_t)mb.cap;
 }
 
-// records per tile: workgroup histogram in LDS, one atomic per touched tile; also the
-// largest |cotangent| of any record (for the fixed-point accumulation)
+// records per tile: workgroup histogram in LDS, then one returning atomic per touched
+// tile, whose old value -- where this chunk's records start inside the tile's range --
+// goes to rowbase for the placement; also the largest |cotangent| of any record (for
+// the fixed-point accumulation)
 template <int C, int RS>
 __global__ void __launch_bounds__(256) k_bin_hist(MapBins mb) {
     __shared__ uint32_t h[MAP_MAX_BINS];
@@ -563,16 +565,16 @@ __global__ void __launch_bounds__(256) k_bin_hist(MapBins mb) {
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
     if (__lane_id() == 0) atomicMax(&hmax, __float_as_uint(m));   // non-negative floats order as integers
     __syncthreads();
+    uint32_t* const rb = mb.rowbase + (size_t)blockIdx.x * mb.nb;
     for (int k = threadIdx.x; k < mb.nb; k += 256)
-        if (h[k]) atomicAdd(&mb.bins[k], h[k]);
+        if (h[k]) rb[k] = atomicAdd(&mb.bins[k], h[k]);
     if (threadIdx.x == 0 && hmax) atomicMax(&mb.bins[3 * mb.nb + 1], hmax);
 }
 
-// tile offsets (exclusive scan of the counts, nb <= 4096); clears counts and fill
+// tile offsets (exclusive scan of the counts, nb <= 4096); clears the counts
 __global__ void __launch_bounds__(1024) k_bin_scan(MapBins mb) {
     __shared__ uint32_t part[1024];
     uint32_t* off = mb.bins + mb.nb;
-    uint32_t* fill = off + mb.nb + 1;
     const int per = (mb.nb + 1023) / 1024;
     const int b = threadIdx.x * per, e = min(b + per, mb.nb);
     uint32_t s = 0;
@@ -591,13 +593,14 @@ __global__ void __launch_bounds__(1024) k_bin_scan(MapBins mb) {
         off[i] = run;
         run += v;
         mb.bins[i] = 0u;
-        fill[i] = 0u;
     }
     if (threadIdx.x == 1023) off[mb.nb] = part[1023];
 }
 
-// copy every record to its tile's range: the workgroup's base inside each touched tile
-// from one global atomic, ranks inside the workgroup from LDS atomics
+// copy every record to its tile's range: the chunk's start inside each tile from the
+// histogram pass (rowbase), ranks inside the chunk from LDS atomics in the same record
+// order as the histogram's count (entries of tiles the chunk does not touch are stale
+// and never read)
 template <int RS>
 __global__ void __launch_bounds__(256) k_bin_place(MapBins mb) {
     __shared__ uint32_t cnt[MAP_MAX_BINS];
@@ -605,21 +608,9 @@ __global__ void __launch_bounds__(256) k_bin_place(MapBins mb) {
     const uint32_t b0 = blockIdx.x * BIN_CHUNK;
     if (b0 >= n) return;   // uniform per workgroup
     const uint32_t e = min(n, b0 + BIN_CHUNK);
-    for (int k = threadIdx.x; k < mb.nb; k += 256) cnt[k] = 0u;
-    __syncthreads();
-    for (uint32_t base = b0; base < e; base += 256) {
-        const uint32_t i = base + threadIdx.x;
-        const bool valid = i < e;
-        const uint32_t bin = valid ? (uint32_t)map_bin(mb, __float_as_uint(mb.rec[(size_t)i * RS])) : 0u;
-        lds_bin_add(cnt, valid, bin);
-    }
-    __syncthreads();
     const uint32_t* off = mb.bins + mb.nb;
-    uint32_t* fill = mb.bins + 2 * mb.nb + 1;
-    for (int k = threadIdx.x; k < mb.nb; k += 256) {
-        const uint32_t c = cnt[k];
-        if (c) cnt[k] = off[k] + atomicAdd(&fill[k], c);
-    }
+    const uint32_t* rb = mb.rowbase + (size_t)blockIdx.x * mb.nb;
+    for (int k = threadIdx.x; k < mb.nb; k += 256) cnt[k] = off[k] + rb[k];
     __syncthreads();
     for (uint32_t base = b0; base < e; base += 256) {
         const uint32_t i = base + threadIdx.x;

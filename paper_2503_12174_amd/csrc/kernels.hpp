@@ -60,6 +60,9 @@ struct Queues {
 constexpr int SHORT_STACK = 8;                 // LDS stack entries per thread
 constexpr int SPILL = 64 - SHORT_STACK;        // overflow entries per thread
 constexpr int TRACE_TB = 128;                  // threads per workgroup of the traversal kernels
+// traversal kernels are compiled for 8 waves per SIMD (at most 64 VGPRs): the loop is
+// latency-bound enough that occupancy pays more than the odd spilled register costs
+#define TRAVERSAL_OCCUPANCY __attribute__((amdgpu_waves_per_eu(8, 8)))
 inline size_t spill_ints(int grid_cap) { return (size_t)grid_cap * TRACE_TB * SPILL; }
 
 // Binned accumulation of the cotangent of one texel map (BRDF maps or E_p): the replay
@@ -72,12 +75,14 @@ constexpr int MAP_MAX_T = 16;   // tile side 8 or 16: maps up to 1024 x 1024 are
 constexpr int BIN_DEPTHS = 4;   // replay depths between flushes (record capacity follows)
 constexpr int ACC_CHUNK = 4096; // records per workgroup of the accumulation; the stage holds
                                 // ceil(cap / ACC_CHUNK) + nb blocks of (T + 1)^2 x C floats
+constexpr int BIN_CHUNK = 16384;// records per workgroup of the histogram and the placement
 struct MapBins {
     float* rec;          // records of rs floats (null: binning off, the replay scatters directly)
     float* sorted;       // the same records grouped by tile
     float* stage;        // per (chunk, tile) pair (T + 1)^2 x C sums (tile plus one halo row/column)
     uint32_t* count;     // records appended since the last flush (may exceed cap)
-    uint32_t* bins;      // counts[nb], offsets[nb + 1], fill[nb], largest |value| (float bits)
+    uint32_t* bins;      // counts[nb], offsets[nb + 1], (unused)[nb], largest |value| (float bits)
+    uint32_t* rowbase;   // per (BIN_CHUNK chunk, tile): where the chunk's records start in the tile
     int64_t cap;         // record capacity
     int W, H, T, nbx, nby, nb;
 };

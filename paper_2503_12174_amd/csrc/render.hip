@@ -76,28 +76,28 @@ __global__ void k_raygen(Queues q, ReqDesc r, int slot, uint32_t g0, uint32_t n)
 }
 
 // ---------------------------------------------------------------- closest hit
-// PROF only names a separate instantiation for the counting pass (q.stats set), so a
-// profiler reports those launches apart from the timed ones; the code is the same
-// (the runtime test of q.stats is kept: folding it away made this loop slower)
+// PROF: the counting pass's instantiation (node and triangle visit counters, summed
+// into q.stats), which a profiler reports apart from the timed launches
 template <bool UNI, bool PROF>
-__global__ void __launch_bounds__(TB) k_trace(Queues q, int cur, ReqDesc uni, const ReqDesc* __restrict__ table) {
-    __shared__ int stack[SHORT_STACK * TB];
-    int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL + threadIdx.x;
+__global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_trace(Queues q, int cur, ReqDesc uni, const ReqDesc* __restrict__ table) {
+    __shared__ int stack[(SHORT_STACK + 1) * TB];
+    int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL;
     const uint32_t n = q.cnt[cur];
     for (uint32_t i = blockIdx.x * TB + threadIdx.x; i < n; i += gridDim.x * TB) {
         const PathO o = q.po[cur][i];
         const PathD d = q.pd[cur][i];
         const ReqDesc& r = sel<UNI>(uni, table, o.slot);
         Hit h;
-        Visits vis;
+        Visits<PROF> vis;
         trace_ray<false, SHORT_STACK, TB>(r.nodes4, r.nodes, r.tris, v3((float)o.x, (float)o.y, (float)o.z),
                                          v3((float)d.x, (float)d.y, (float)d.z), r.tmin, __builtin_inff(), o.skip,
-                                         h, stack + threadIdx.x, spill, vis);
+                                         h, stack, spill, threadIdx.x, vis);
         q.hit[i] = h.leaf;
-        if (q.stats) {
-            atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
-            atomicAdd(&q.stats[1], (unsigned long long)vis.tris);
-        }
+        if constexpr (PROF)
+            if (q.stats) {
+                atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
+                atomicAdd(&q.stats[1], (unsigned long long)vis.tris);
+            }
     }
 }
 
@@ -190,9 +190,10 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
             }
         }
         const bool pred[3] = {cont, shp, she};
+        const int key[3] = {octant(nd.x, nd.y, nd.z), 0, octant(ed.x, ed.y, ed.z)};
         uint32_t* const ctr[3] = {&q.cnt[nxt], &q.cnt[2], &q.cnt[3]};
         uint32_t at[3];
-        block_append<3>(pred, ctr, at);
+        block_append_keyed<3, 8>(pred, key, ctr, at);
         const uint32_t jn = at[0], jp = at[1], je = at[2];
         if (cont) {
             q.po[nxt][jn] = no;
@@ -215,26 +216,26 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
 }
 
 // ---------------------------------------------------------------- shadows
-// PROF only names a separate instantiation for the counting pass (q.stats set), so a
-// profiler reports those launches apart from the timed ones; the code is the same
-// (the runtime test of q.stats is kept: folding it away made this loop slower)
+// PROF: the counting pass's instantiation (node and triangle visit counters, summed
+// into q.stats), which a profiler reports apart from the timed launches
 template <bool UNI, bool PROF>
-__global__ void __launch_bounds__(TB) k_shadow(Queues q, int which, int depth, ReqDesc uni,
+__global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_shadow(Queues q, int which, int depth, ReqDesc uni,
                                                const ReqDesc* __restrict__ table) {
-    __shared__ int stack[SHORT_STACK * TB];
-    int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL + threadIdx.x;
+    __shared__ int stack[(SHORT_STACK + 1) * TB];
+    int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL;
     const uint32_t n = q.cnt[2 + which];
     for (uint32_t i = blockIdx.x * TB + threadIdx.x; i < n; i += gridDim.x * TB) {
         const float4 o = q.so[which][i], d = q.sd[which][i];
         const ReqDesc& r = sel<UNI>(uni, table, __float_as_int(o.w));
         Hit h;
-        Visits vis;
+        Visits<PROF> vis;
         const bool occ = trace_ray<true, SHORT_STACK, TB>(r.nodes4, r.nodes, r.tris, xyz(o), xyz(d), r.tmin, q.st[which][i],
-                                                         __float_as_int(d.w), h, stack + threadIdx.x, spill, vis);
-        if (q.stats) {
-            atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
-            atomicAdd(&q.stats[1], (unsigned long long)vis.tris);
-        }
+                                                         __float_as_int(d.w), h, stack, spill, threadIdx.x, vis);
+        if constexpr (PROF)
+            if (q.stats) {
+                atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
+                atomicAdd(&q.stats[1], (unsigned long long)vis.tris);
+            }
         if (!occ) {
             const float4 c = q.sc[which][i];
             const uint32_t sid = __float_as_uint(c.w);
@@ -297,20 +298,21 @@ __global__ void __launch_bounds__(TB) k_debug_intersect(const float4* __restrict
                                                         const int* __restrict__ leaf_of_prim, int nt, float tmin,
                                                         const float* __restrict__ rays, int64_t n, int mode,
                                                         int32_t* prim, float* t, float* b1, float* b2) {
-    __shared__ int stack[MAX_STACK * TB];
+    __shared__ int stack[(MAX_STACK + 1) * TB];
     const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (i >= n) return;
     const float* ry = rays + 8 * i;
     const V3 o = v3(ry[0], ry[1], ry[2]), d = v3(ry[3], ry[4], ry[5]);
     Hit h;
-    Visits vis;
-    int* st = stack + threadIdx.x;
+    Visits<false> vis;
+    int* st = stack;
+    const int lane = threadIdx.x;
     if (mode == 1)
-        trace_ray<false, MAX_STACK, TB>(nodes4, nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, st, nullptr, vis);
+        trace_ray<false, MAX_STACK, TB>(nodes4, nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, st, nullptr, lane, vis);
     else if (mode == 2)
-        traverse<false, MAX_STACK, TB>(nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, st, nullptr, vis);
+        traverse<false, MAX_STACK, TB>(nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, st, nullptr, lane, vis);
     else if (mode == 3)
-        trace_ray<true, MAX_STACK, TB>(nodes4, nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, st, nullptr, vis);
+        trace_ray<true, MAX_STACK, TB>(nodes4, nodes, tris, o, d, tmin, ry[6], (int)ry[7], h, st, nullptr, lane, vis);
     else if (mode == 4)
         brute_force<true>(tris, leaf_of_prim, nt, o, d, tmin, ry[6], (int)ry[7], h);
     else

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <vector>
 
 using namespace dpcs;
@@ -129,7 +130,8 @@ void make_map_bins(dpcs_context ctx, const Launch& l, MapBins& mb, const char* n
     cap = std::min<int64_t>(cap, int64_t(1) << 31);
     const int nb = nbx * nby;
     const size_t rec = 4 * (size_t)RS * cap, stage = 4 * (size_t)((cap + ACC_CHUNK - 1) / ACC_CHUNK + nb) * (T + 1) * (T + 1) * C;
-    const size_t bytes = 2 * rec + stage + 4 * (3 * (size_t)nb + 2) + 8 * 256;
+    const size_t rows = 4 * (size_t)((cap + BIN_CHUNK - 1) / BIN_CHUNK) * nb;
+    const size_t bytes = 2 * rec + stage + rows + 4 * (3 * (size_t)nb + 2) + 8 * 256;
     dpcs_status st = DPCS_OK;
     char* b = (char*)scratch(ctx, name, bytes, &st);
     if (!b) {   // run without binning
@@ -146,6 +148,7 @@ void make_map_bins(dpcs_context ctx, const Launch& l, MapBins& mb, const char* n
     mb.stage = (float*)take(stage);
     mb.count = (uint32_t*)take(4);
     mb.bins = (uint32_t*)take(4 * (3 * (size_t)nb + 2));
+    mb.rowbase = (uint32_t*)take(rows);
     mb.cap = cap;
     mb.W = W;
     mb.H = H;
@@ -362,7 +365,7 @@ extern "C" dpcs_status dpcs_context_set_capacity(dpcs_context ctx, int64_t paths
 // surface area until it holds four.  Leaves stay single triangles.  stack_bound is the
 // most traversal stack entries any ray can hold: along a root-to-node path, each node
 // pushes at most (its internal children - 1).
-static std::vector<float4> collapse4(const std::vector<float4>& bn, int& stack_bound, int& depth4) {
+static std::vector<float4> collapse4(const std::vector<float4>& bn, int nt, int& stack_bound, int& depth4) {
     struct Kid {
         int ref;
         float b[6];   // lo.xyz, hi.xyz
@@ -427,9 +430,12 @@ static std::vector<float4> collapse4(const std::vector<float4>& bn, int& stack_b
                 } else {
                     refs[j] = kids[j].ref;
                 }
-            } else {
-                for (int a = 0; a < 6; ++a) box[a][j] = 0.f;
-                refs[j] = (int)0x80000000;   // empty slot
+            } else {   // empty slot: inverted box far away (never entered), dummy leaf nt
+                for (int a = 0; a < 3; ++a) {
+                    box[a][j] = 1e30f;
+                    box[a + 3][j] = -1e30f;
+                }
+                refs[j] = ~nt;
             }
         }
         float4* o = &out[8 * (size_t)w.node];
@@ -496,12 +502,12 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
         }
     };
     dmalloc((void**)&sc->nodes, sizeof(float4) * 4 * ni);
-    dmalloc((void**)&sc->tris, sizeof(float4) * 3 * nt);
+    dmalloc((void**)&sc->tris, sizeof(float4) * 3 * (nt + 1));   // + the dummy leaf of empty BVH4 slots
     dmalloc((void**)&sc->tri_uv, sizeof(float4) * 2 * nt);
     if (m->emission) dmalloc((void**)&sc->emission, sizeof(float4) * nt);
     dmalloc((void**)&sc->leaf_of_prim, sizeof(int) * nt);
     sc->nnodes = ni;
-    sc->bytes = (int64_t)sizeof(float4) * (4 * ni + 3 * nt + 2 * nt + (m->emission ? nt : 0)) + 4 * nt;
+    sc->bytes = (int64_t)sizeof(float4) * (4 * ni + 3 * (nt + 1) + 2 * nt + (m->emission ? nt : 0)) + 4 * nt;
     // build temporaries
     void *dV = nullptr, *dF = nullptr, *dUV = nullptr, *dLe = nullptr, *tmp = nullptr;
     dmalloc(&dV, sizeof(float) * 3 * nv);
@@ -701,15 +707,24 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
         destroy_scene();
         return fail(ctx, DPCS_E_UNSUPPORTED, "BVH deeper than 64 levels");
     }
-    // 4-wide BVH for the traversal kernels, when its worst-case stack fits
+    // 4-wide BVH for the traversal kernels, when its worst-case stack fits and its
+    // byte size fits the 32-bit node offsets the traversal loads with
     if (nt > 1) {
         std::vector<float4> bn(4 * (size_t)ni);
         hipError_t e4 = hipMemcpy(bn.data(), sc->nodes, sizeof(float4) * bn.size(), hipMemcpyDeviceToHost);
         if (e4 == hipSuccess) {
             int bound = 0, depth4 = 0;
-            const std::vector<float4> n4 = collapse4(bn, bound, depth4);
-            if (bound <= MAX_STACK) {
-                e4 = hipMalloc((void**)&sc->nodes4, sizeof(float4) * n4.size());
+            const std::vector<float4> n4 = collapse4(bn, nt, bound, depth4);
+            if (bound <= MAX_STACK && sizeof(float4) * n4.size() <= (size_t)UINT32_MAX) {
+                // the dummy leaf's triangle: NaN vertices, which no ray hits
+                const float qn = std::numeric_limits<float>::quiet_NaN();
+                int none = -1;
+                float none_f;
+                std::memcpy(&none_f, &none, 4);
+                const float4 dummy[3] = {make_float4(qn, qn, qn, none_f), make_float4(qn, qn, qn, 0.f),
+                                         make_float4(qn, qn, qn, 0.f)};
+                e4 = hipMemcpy(sc->tris + 3 * (size_t)nt, dummy, sizeof(dummy), hipMemcpyHostToDevice);
+                if (e4 == hipSuccess) e4 = hipMalloc((void**)&sc->nodes4, sizeof(float4) * n4.size());
                 if (e4 == hipSuccess)
                     e4 = hipMemcpy(sc->nodes4, n4.data(), sizeof(float4) * n4.size(), hipMemcpyHostToDevice);
                 if (e4 == hipSuccess) {

@@ -58,6 +58,52 @@ __device__ __forceinline__ void block_append(const bool* pred, uint32_t* const* 
     for (int q = 0; q < NQ; ++q) idx[q] = wbase[q][wv] + (uint32_t)__popcll(m[q] & below);
 }
 
+// block_append whose entries of one workgroup are grouped by a key in [0, NK) (key
+// order, then wave and lane order): rays appended with their direction octant as key
+// leave the workgroup as runs of like-signed directions, so the waves that trace them
+// next take more similar paths through the BVH.  Still one atomic per queue.
+template <int NQ, int NK, int NT = BLOCK>
+__device__ __forceinline__ void block_append_keyed(const bool* pred, const int* key, uint32_t* const* counter,
+                                                   uint32_t* idx) {
+    constexpr int NW = NT / 64;
+    __shared__ uint32_t wcount[NQ][NK][NW];
+    __shared__ uint32_t wbase[NQ][NK][NW];
+    const int lane = __lane_id(), wv = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long mine[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        mine[q] = 0ull;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            const unsigned long long m = __ballot(pred[q] && key[q] == k);
+            if (lane == 0) wcount[q][k][wv] = (uint32_t)__popcll(m);
+            if (key[q] == k) mine[q] = m;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < NQ) {
+        const int q = threadIdx.x;
+        uint32_t total = 0;
+        for (int k = 0; k < NK; ++k)
+            for (int w = 0; w < NW; ++w) total += wcount[q][k][w];
+        uint32_t run = total ? atomicAdd(counter[q], total) : 0u;
+        for (int k = 0; k < NK; ++k)
+            for (int w = 0; w < NW; ++w) {
+                wbase[q][k][w] = run;
+                run += wcount[q][k][w];
+            }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) idx[q] = wbase[q][key[q]][wv] + (uint32_t)__popcll(mine[q] & below);
+}
+
+// octant of a direction (sign bits of x, y, z)
+__device__ __forceinline__ int octant(double x, double y, double z) {
+    return (x < 0.0 ? 1 : 0) | (y < 0.0 ? 2 : 0) | (z < 0.0 ? 4 : 0);
+}
+
 // camera ray of global sample g (pixel = g / spp, sample = g % spp), Eq. 6 inverted
 __device__ __forceinline__ D3 camera_dir(const ReqDesc& r, uint32_t g) {
     const uint32_t pixel = g / (uint32_t)r.spp, s = g - pixel * (uint32_t)r.spp;

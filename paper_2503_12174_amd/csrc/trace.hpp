@@ -7,8 +7,10 @@
 // BVH4 node (128 B, one cache line, 8 x float4): the four children's boxes as
 // structure of arrays, lo.x[4], lo.y[4], lo.z[4], hi.x[4], hi.y[4], hi.z[4], then the
 // four child references and 16 unused bytes.
-// child >= 0: internal node index; child < 0: leaf ~child (one triangle, leaf order);
-// WIDE_EMPTY: unused slot of a BVH4 node.
+// child >= 0: internal node index; child < 0: leaf ~child (one triangle, leaf order).
+// An unused slot of a BVH4 node holds an inverted box far from the scene, which the
+// 4-wide box test never enters, and the dummy leaf nt (one record past the mesh's
+// triangles, NaN vertices), which no ray hits, so the loop needs no test for them.
 // Triangle record (48 B): v0 (w = original triangle index bits), v1, v2.
 //
 // Closest hit: smallest t in (tmin, tmax); equal t -> smaller original triangle
@@ -23,7 +25,7 @@ namespace dpcs {
 // watertight ray / triangle test (Woop, Benthin, Wald, JCGT 2013)
 struct WtRay {
     V3 o;
-    int kx, ky, kz;
+    uint32_t k;          // axis permutation kx | ky << 2 | kz << 4
     float Sx, Sy, Sz;
 };
 
@@ -40,9 +42,7 @@ __device__ __forceinline__ WtRay wt_setup(V3 o, V3 d) {
         kx = ky;
         ky = tmp;
     }
-    r.kx = kx;
-    r.ky = ky;
-    r.kz = kz;
+    r.k = (uint32_t)kx | (uint32_t)ky << 2 | (uint32_t)kz << 4;
     r.Sx = comp(d, kx) / dz;
     r.Sy = comp(d, ky) / dz;
     r.Sz = 1.0f / dz;
@@ -51,11 +51,12 @@ __device__ __forceinline__ WtRay wt_setup(V3 o, V3 d) {
 
 // returns false on a miss; on a hit t and the barycentrics (b1 of v1, b2 of v2)
 __device__ __forceinline__ bool wt_intersect(const WtRay& r, V3 v0, V3 v1, V3 v2, float& t, float& b1, float& b2) {
+    const int kx = (int)(r.k & 3u), ky = (int)((r.k >> 2) & 3u), kz = (int)(r.k >> 4);
     const V3 A = v0 - r.o, B = v1 - r.o, C = v2 - r.o;
-    const float Akz = comp(A, r.kz), Bkz = comp(B, r.kz), Ckz = comp(C, r.kz);
-    const float Ax = comp(A, r.kx) - r.Sx * Akz, Ay = comp(A, r.ky) - r.Sy * Akz;
-    const float Bx = comp(B, r.kx) - r.Sx * Bkz, By = comp(B, r.ky) - r.Sy * Bkz;
-    const float Cx = comp(C, r.kx) - r.Sx * Ckz, Cy = comp(C, r.ky) - r.Sy * Ckz;
+    const float Akz = comp(A, kz), Bkz = comp(B, kz), Ckz = comp(C, kz);
+    const float Ax = comp(A, kx) - r.Sx * Akz, Ay = comp(A, ky) - r.Sy * Akz;
+    const float Bx = comp(B, kx) - r.Sx * Bkz, By = comp(B, ky) - r.Sy * Bkz;
+    const float Cx = comp(C, kx) - r.Sx * Ckz, Cy = comp(C, ky) - r.Sy * Ckz;
     float U = Cx * By - Cy * Bx;
     float V = Ax * Cy - Ay * Cx;
     float W = Bx * Ay - By * Ax;
@@ -111,19 +112,34 @@ __device__ __forceinline__ void load_tri(const float4* __restrict__ tris, int le
     prim = __float_as_int(a.w);
 }
 
-// Traversal stack of internal node indices: the first SHORT entries live in LDS
-// (entry k of thread tid at lds[k * TBK + tid], consecutive lanes on consecutive banks);
+// Traversal stack of internal node indices: the first SHORT entries live in LDS, entry
+// k of lane `lane` at stack[k * TBK + lane] (consecutive lanes on consecutive banks),
+// plus one more LDS entry per lane (k = SHORT) that the 4-wide push writes candidates
+// it does not keep to;
 // deeper entries -- rare with near-child-first order -- go to the workgroup's region of
-// global memory with the same interleaving (spill[k * TBK + tid]).  The host only
-// launches on trees of depth <= 64, so at most 64 entries are ever live.
+// global memory with the same interleaving, spill[(k - SHORT) * TBK + lane].  Both
+// bases are uniform, so a lane holds only its index.  The host only launches on trees
+// whose stack bound is <= 64, so at most 64 entries are ever live.
+//
+// Node and triangle visit counters for the profiler's counting pass; the timed
+// kernels use Visits<false>, which keeps no registers.
+template <bool ON>
 struct Visits {
     uint32_t nodes = 0, tris = 0;
+    __device__ __forceinline__ void node() { ++nodes; }
+    __device__ __forceinline__ void tri() { ++tris; }
+};
+template <>
+struct Visits<false> {
+    static constexpr uint32_t nodes = 0, tris = 0;
+    __device__ __forceinline__ void node() {}
+    __device__ __forceinline__ void tri() {}
 };
 
-template <bool ANY, int SHORT, int TBK>
+template <bool ANY, int SHORT, int TBK, class VIS>
 __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const float4* __restrict__ tris, V3 o, V3 d,
-                                         float tmin, float tmax, int skip, Hit& h, int* stack, int* spill,
-                                         Visits& vis) {
+                                         float tmin, float tmax, int skip, Hit& h, int* stack, int* spill, int lane,
+                                         VIS& vis) {
     const BoxRay br = box_setup(o, d);
     const WtRay wr = wt_setup(o, d);
     float best_t = tmax;
@@ -131,8 +147,8 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
     float bb1 = 0.f, bb2 = 0.f;
     int sp = 0;
     int node = 0;
-    while (true) {
-        ++vis.nodes;
+    while (node >= 0) {   // the only exit (see traverse4)
+        vis.node();
         const float4 n0 = nodes[4 * node], n1 = nodes[4 * node + 1], n2 = nodes[4 * node + 2];
         const int4 n3 = *reinterpret_cast<const int4*>(&nodes[4 * node + 3]);
         float t0 = box_enter(br, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tmin, best_t);
@@ -146,7 +162,7 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
                 const int leaf = ~c;
                 V3 v0, v1, v2;
                 int prim;
-                ++vis.tris;
+                vis.tri();
                 load_tri(tris, leaf, v0, v1, v2, prim);
                 float t, b1, b2;
                 if (prim != skip && wt_intersect(wr, v0, v1, v2, t, b1, b2) && t > tmin &&
@@ -156,26 +172,20 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
                     best_leaf = leaf;
                     bb1 = b1;
                     bb2 = b2;
-                    if (ANY) {
-                        h.t = t;
-                        h.leaf = leaf;
-                        h.prim = prim;
-                        h.b1 = b1;
-                        h.b2 = b2;
-                        return true;
-                    }
                 }
             }
         }
         // a missed box reports +inf, which must not pass while best_t is still +inf
         const bool h0 = c0 >= 0 && t0 < __builtin_inff() && t0 <= best_t;
         const bool h1 = c1 >= 0 && t1 < __builtin_inff() && t1 <= best_t;
-        if (h0 && h1) {
+        if (ANY && best_leaf >= 0) {   // any hit ends the query
+            node = -1;
+        } else if (h0 && h1) {
             const bool first0 = t0 <= t1;
             const int far = first0 ? c1 : c0;
-            if (sp < SHORT) stack[sp * TBK] = far;
+            if (sp < SHORT) stack[sp * TBK + lane] = far;
             else if constexpr (SHORT < MAX_STACK) {
-                if (sp < MAX_STACK) spill[(sp - SHORT) * TBK] = far;
+                if (sp < MAX_STACK) spill[(sp - SHORT) * TBK + lane] = far;
             }
             sp = sp < MAX_STACK ? sp + 1 : sp;   // depth <= 64 is checked on the host
             node = first0 ? c0 : c1;
@@ -183,11 +193,13 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
             node = c0;
         } else if (h1) {
             node = c1;
-        } else {
-            if (sp == 0) break;
+        } else if (sp > 0) {
             --sp;
-            if constexpr (SHORT < MAX_STACK) node = sp < SHORT ? stack[sp * TBK] : spill[(sp - SHORT) * TBK];
-            else node = stack[sp * TBK];
+            node = stack[min(sp, SHORT - 1) * TBK + lane];
+            if constexpr (SHORT < MAX_STACK)
+                if (sp >= SHORT) node = spill[(sp - SHORT) * TBK + lane];
+        } else {
+            node = -1;
         }
     }
     h.t = best_t;
@@ -197,8 +209,6 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
     h.b2 = bb2;
     return best_leaf >= 0;
 }
-
-constexpr int WIDE_EMPTY = (int)0x80000000;
 
 // compare-exchange on (key, ref) pairs, smaller key first
 __device__ __forceinline__ void cmpx(float& ka, int& ra, float& kb, int& rb) {
@@ -212,81 +222,146 @@ __device__ __forceinline__ void cmpx(float& ka, int& ra, float& kb, int& rb) {
     }
 }
 
+// Ray constants of the 4-wide box tests.  Per axis, the sign of the direction says
+// which of a child's two planes the ray meets first, so a node load fetches the near
+// and the far coordinates directly (byte offsets below) and each slab takes one FMA,
+// plane * (1 / d) + off, with no min/max per axis.  off is -o / d rounded outward:
+// down by at least the rounding error of o / d for near planes, up for far planes.
+// With that, a slab value can only err by the relative rounding of 1 / d and of the
+// FMA, which the relative widening in the test covers; it needs no absolute term
+// that would grow for near-axis-parallel rays.  Degenerate axes (d = 0) give NaN or
+// infinite slab values, which the min/max below drop or keep in the conservative
+// direction.  The relative widening multiplies (t x (1 -+ 4e-6)) rather than adding
+// a multiple of |t|, so infinite slab values stay infinite instead of turning NaN,
+// and an inverted box (lo = +1e30, hi = -1e30: every near plane ahead of every far
+// plane) is always missed.
+struct Box4Ray {
+    float ix, iy, iz;             // 1 / d
+    float anx, any, anz;          // near-plane offsets
+    float afx, afy, afz;          // far-plane offsets
+    uint32_t onx, ony, onz;       // byte offset of the near coordinate float4 in a node
+};
+// the far coordinate float4 of each axis sits at the near one's offset XOR these
+// (x: 0 <-> 48, y: 16 <-> 64, z: 32 <-> 80)
+constexpr uint32_t FAR_X = 48u, FAR_Y = 80u, FAR_Z = 112u;
+
+__device__ __forceinline__ Box4Ray box4_setup(V3 o, V3 d) {
+    Box4Ray r;
+    r.ix = 1.0f / d.x;
+    r.iy = 1.0f / d.y;
+    r.iz = 1.0f / d.z;
+    // |fl(o / d) - o / d| <= 2^-24 |fl(o / d)| (1 + 2^-23); 2^-21 also covers the
+    // rounding of the two sums below
+    const float px = o.x * r.ix, py = o.y * r.iy, pz = o.z * r.iz;
+    const float ex = fabsf(px) * 0x1p-21f, ey = fabsf(py) * 0x1p-21f, ez = fabsf(pz) * 0x1p-21f;
+    r.anx = -px - ex;
+    r.any = -py - ey;
+    r.anz = -pz - ez;
+    r.afx = -px + ex;
+    r.afy = -py + ey;
+    r.afz = -pz + ez;
+    // node float4s: 0 lo.x, 1 lo.y, 2 lo.z, 3 hi.x, 4 hi.y, 5 hi.z
+    const bool sx = __builtin_signbit(r.ix), sy = __builtin_signbit(r.iy), sz = __builtin_signbit(r.iz);
+    r.onx = sx ? 48u : 0u;
+    r.ony = sy ? 64u : 16u;
+    r.onz = sz ? 80u : 32u;
+    return r;
+}
+
+// entry distance of the ray into a child box of a node (near / far planes as loaded),
+// widened by 4e-6 relative like box_enter; NaN where missed, so a single test
+// `t <= bound` both checks the hit and the bound.  (A negative entry or exit is
+// scaled the wrong way, which the clamp to tmin > 0 makes irrelevant.)
+__device__ __forceinline__ float box4_enter(const Box4Ray& r, float nx, float ny, float nz, float fx, float fy,
+                                            float fz, float tmin, float tmax) {
+    float tn = fmaxf(fmaxf(fmaf(nx, r.ix, r.anx), fmaf(ny, r.iy, r.any)), fmaf(nz, r.iz, r.anz));
+    float tf = fminf(fminf(fmaf(fx, r.ix, r.afx), fmaf(fy, r.iy, r.afy)), fmaf(fz, r.iz, r.afz));
+    tn = fmaxf(tn * (1.0f - 4e-6f), tmin);
+    tf = fminf(tf * (1.0f + 4e-6f), tmax);
+    return tn <= tf ? tn : __builtin_nanf("");
+}
+
 // Same query on the 4-wide BVH: per node, four box tests; leaf children are tested at
 // once, internal children still in range are visited nearest first (the others pushed,
 // farthest first).  The host only builds a BVH4 whose worst-case stack fits MAX_STACK.
-template <bool ANY, int SHORT, int TBK>
+template <bool ANY, int SHORT, int TBK, class VIS>
 __device__ __forceinline__ bool traverse4(const float4* __restrict__ nodes, const float4* __restrict__ tris, V3 o,
                                           V3 d, float tmin, float tmax, int skip, Hit& h, int* stack, int* spill,
-                                          Visits& vis) {
-    const BoxRay br = box_setup(o, d);
+                                          int lane, VIS& vis) {
+    const Box4Ray br = box4_setup(o, d);
     const WtRay wr = wt_setup(o, d);
     float best_t = tmax;
-    int best_prim = 0x7fffffff, best_leaf = -1;
-    float bb1 = 0.f, bb2 = 0.f;
+    int best_leaf = -1;
     int sp = 0;
     int node = 0;
-    while (true) {
-        ++vis.nodes;
-        const float4* nd = nodes + 8 * (size_t)node;
-        const float4 lx = nd[0], ly = nd[1], lz = nd[2], hx = nd[3], hy = nd[4], hz = nd[5];
-        const int4 cr = *reinterpret_cast<const int4*>(nd + 6);
+    // the only exit is the loop test (node < 0 once the stack is empty or an any-hit
+    // query has its hit): with no break inside, the compiler keeps the pop an ordinary
+    // branch of the one loop, instead of a nested loop whose lanes wait until every
+    // lane of the wave needs a pop
+    while (node >= 0) {
+        vis.node();
+        // 32-bit byte offsets from the tree's base (the host keeps 128 x nodes < 2^32),
+        // so each load is base + one 32-bit register
+        const uint32_t nb = (uint32_t)node * 128u;
+        const char* base = reinterpret_cast<const char*>(nodes);
+        const uint32_t ax = nb | br.onx, ay = nb | br.ony, az = nb | br.onz;
+        const float4 nx = *reinterpret_cast<const float4*>(base + ax);
+        const float4 ny = *reinterpret_cast<const float4*>(base + ay);
+        const float4 nz = *reinterpret_cast<const float4*>(base + az);
+        const float4 fx = *reinterpret_cast<const float4*>(base + (ax ^ FAR_X));
+        const float4 fy = *reinterpret_cast<const float4*>(base + (ay ^ FAR_Y));
+        const float4 fz = *reinterpret_cast<const float4*>(base + (az ^ FAR_Z));
+        const int4 cr = *reinterpret_cast<const int4*>(base + (nb + 96u));
         const int cc[4] = {cr.x, cr.y, cr.z, cr.w};
         float tc[4];
-        tc[0] = box_enter(br, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, tmin, best_t);
-        tc[1] = box_enter(br, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, tmin, best_t);
-        tc[2] = box_enter(br, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, tmin, best_t);
-        tc[3] = box_enter(br, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, tmin, best_t);
-        // Leaf children whose box is hit.  Closest hit: every slot unrolled, so the
-        // triangle fetches of all four are in flight together.  Any hit: one test per
-        // pass of a loop, the wave runs it as often as its busiest lane needs.
+        tc[0] = box4_enter(br, nx.x, ny.x, nz.x, fx.x, fy.x, fz.x, tmin, best_t);
+        tc[1] = box4_enter(br, nx.y, ny.y, nz.y, fx.y, fy.y, fz.y, tmin, best_t);
+        tc[2] = box4_enter(br, nx.z, ny.z, nz.z, fx.z, fy.z, fz.z, tmin, best_t);
+        tc[3] = box4_enter(br, nx.w, ny.w, nz.w, fx.w, fy.w, fz.w, tmin, best_t);
+        // Leaf children whose box is hit, tested one per pass; the wave runs as many
+        // passes as its busiest lane needs.
         uint32_t lm = 0u;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (cc[k] == WIDE_EMPTY) tc[k] = __builtin_inff();
-            if (cc[k] < 0 && tc[k] < __builtin_inff()) lm |= 1u << k;
-        }
+        for (int k = 0; k < 4; ++k)
+            if (cc[k] < 0 && tc[k] <= best_t) lm |= 1u << k;
         auto test_leaf = [&](int leaf) {
             V3 v0, v1, v2;
             int prim;
-            ++vis.tris;
+            vis.tri();
             load_tri(tris, leaf, v0, v1, v2, prim);
             float t, b1, b2;
-            if (prim != skip && wt_intersect(wr, v0, v1, v2, t, b1, b2) && t > tmin &&
-                (t < best_t || (t == best_t && best_leaf >= 0 && prim < best_prim))) {
+            if (prim == skip || !wt_intersect(wr, v0, v1, v2, t, b1, b2) || !(t > tmin)) return;
+            bool take = t < best_t;
+            if constexpr (!ANY) {
+                // equal t: the smaller original index wins (the current best's index is
+                // read back from its record, so no register holds it)
+                if (!take && t == best_t && best_leaf >= 0) take = prim < __float_as_int(tris[3 * best_leaf].w);
+            }
+            if (take) {
                 best_t = t;
-                best_prim = prim;
                 best_leaf = leaf;
-                bb1 = b1;
-                bb2 = b2;
-                return true;
             }
-            return false;
         };
-        if constexpr (ANY) {
-            while (lm) {
-                const int k = __builtin_ctz(lm);
-                lm &= lm - 1u;
-                if (test_leaf(~(k == 0 ? cc[0] : (k == 1 ? cc[1] : (k == 2 ? cc[2] : cc[3]))))) {
-                    h.t = best_t;
-                    h.leaf = best_leaf;
-                    h.prim = best_prim;
-                    h.b1 = bb1;
-                    h.b2 = bb2;
-                    return true;
-                }
-            }
-        } else {
+        {
+            // the lane's hit leaves compacted: pass j runs when some lane has more than
+            // j of them (fewer passes than one per slot any lane uses)
+            const int nl = __popc(lm);
+            uint32_t m = lm;
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (lm & (1u << k)) test_leaf(~cc[k]);
+            for (int j = 0; j < 4; ++j)
+                if (j < nl) {
+                    const int k = __builtin_ctz(m);
+                    m &= m - 1u;
+                    test_leaf(~(k == 0 ? cc[0] : (k == 1 ? cc[1] : (k == 2 ? cc[2] : cc[3]))));
+                }
         }
-        // internal children still in range (a missed box reports +inf)
+        // internal children still in range (a missed box reports NaN; one entered only
+        // at +inf is dropped like a miss)
         float key[4];
         int ref[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const bool in = cc[k] >= 0 && tc[k] < __builtin_inff() && tc[k] <= best_t;
+            const bool in = cc[k] >= 0 && tc[k] <= best_t;
             key[k] = in ? tc[k] : __builtin_inff();
             ref[k] = cc[k];
         }
@@ -295,39 +370,57 @@ __device__ __forceinline__ bool traverse4(const float4* __restrict__ nodes, cons
         cmpx(key[0], ref[0], key[2], ref[2]);
         cmpx(key[1], ref[1], key[3], ref[3]);
         cmpx(key[1], ref[1], key[2], ref[2]);
-        if (key[0] < __builtin_inff()) {
+        if (ANY && best_leaf >= 0) {   // any hit ends the query
+            node = -1;
+        } else if (key[0] < __builtin_inff()) {
             node = ref[0];
+            // every candidate is written to LDS, at sp, or at the lane's extra entry
+            // SHORT once the LDS part is full (a write that is not kept is overwritten or
+            // never read), so only the rare spill to global memory is a branch
 #pragma unroll
             for (int k = 3; k >= 1; --k) {
-                if (!(key[k] < __builtin_inff())) continue;
-                if (sp < SHORT) stack[sp * TBK] = ref[k];
-                else if constexpr (SHORT < MAX_STACK) {
-                    if (sp < MAX_STACK) spill[(sp - SHORT) * TBK] = ref[k];
-                }
-                sp = sp < MAX_STACK ? sp + 1 : sp;
+                const bool v = key[k] < __builtin_inff();
+                stack[min(sp, SHORT) * TBK + lane] = ref[k];
+                if constexpr (SHORT < MAX_STACK)
+                    if (v && sp >= SHORT && sp < MAX_STACK) spill[(sp - SHORT) * TBK + lane] = ref[k];
+                sp = v && sp < MAX_STACK ? sp + 1 : sp;
             }
-        } else {
-            if (sp == 0) break;
+        } else if (sp > 0) {
             --sp;
-            if constexpr (SHORT < MAX_STACK) node = sp < SHORT ? stack[sp * TBK] : spill[(sp - SHORT) * TBK];
-            else node = stack[sp * TBK];
+            // an LDS read always (clamped index) and a global read only for spilled
+            // entries: two plain loads rather than one generic (flat) load
+            node = stack[min(sp, SHORT - 1) * TBK + lane];
+            if constexpr (SHORT < MAX_STACK)
+                if (sp >= SHORT) node = spill[(sp - SHORT) * TBK + lane];
+        } else {
+            node = -1;
         }
+    }
+    // the barycentrics of the hit: the same test on its triangle again (same
+    // arithmetic, same bits), which keeps them out of the loop's registers
+    float bb1 = 0.f, bb2 = 0.f;
+    int best_prim = -1;
+    if (best_leaf >= 0) {
+        V3 v0, v1, v2;
+        float t;
+        load_tri(tris, best_leaf, v0, v1, v2, best_prim);
+        wt_intersect(wr, v0, v1, v2, t, bb1, bb2);
     }
     h.t = best_t;
     h.leaf = best_leaf;
-    h.prim = best_leaf >= 0 ? best_prim : -1;
+    h.prim = best_prim;
     h.b1 = bb1;
     h.b2 = bb2;
     return best_leaf >= 0;
 }
 
 // closest or any hit on the request's BVH (4-wide when built)
-template <bool ANY, int SHORT, int TBK>
+template <bool ANY, int SHORT, int TBK, class VIS>
 __device__ __forceinline__ bool trace_ray(const float4* __restrict__ nodes4, const float4* __restrict__ nodes,
                                           const float4* __restrict__ tris, V3 o, V3 d, float tmin, float tmax,
-                                          int skip, Hit& h, int* stack, int* spill, Visits& vis) {
-    if (nodes4) return traverse4<ANY, SHORT, TBK>(nodes4, tris, o, d, tmin, tmax, skip, h, stack, spill, vis);
-    return traverse<ANY, SHORT, TBK>(nodes, tris, o, d, tmin, tmax, skip, h, stack, spill, vis);
+                                          int skip, Hit& h, int* stack, int* spill, int lane, VIS& vis) {
+    if (nodes4) return traverse4<ANY, SHORT, TBK>(nodes4, tris, o, d, tmin, tmax, skip, h, stack, spill, lane, vis);
+    return traverse<ANY, SHORT, TBK>(nodes, tris, o, d, tmin, tmax, skip, h, stack, spill, lane, vis);
 }
 
 // reference: every triangle in original order, same arithmetic and tie rule
