@@ -540,18 +540,18 @@ __device__ __forceinline__ uint32_t map_records(const MapBins& mb) {
 // goes to rowbase for the placement; also the largest |cotangent| of any record (for
 // the fixed-point accumulation)
 template <int C, int RS>
-__global__ void __launch_bounds__(256) k_bin_hist(MapBins mb) {
+__global__ void __launch_bounds__(BIN_TB) k_bin_hist(MapBins mb) {
     __shared__ uint32_t h[MAP_MAX_BINS];
     __shared__ uint32_t hmax;
     const uint32_t n = map_records(mb);
     const uint32_t b0 = blockIdx.x * BIN_CHUNK;
     if (b0 >= n) return;   // uniform per workgroup
-    for (int k = threadIdx.x; k < mb.nb; k += 256) h[k] = 0u;
+    for (int k = threadIdx.x; k < mb.nb; k += BIN_TB) h[k] = 0u;
     if (threadIdx.x == 0) hmax = 0u;
     __syncthreads();
     const uint32_t e = min(n, b0 + BIN_CHUNK);
     float m = 0.f;
-    for (uint32_t base = b0; base < e; base += 256) {
+    for (uint32_t base = b0; base < e; base += BIN_TB) {
         const uint32_t i = base + threadIdx.x;
         const bool valid = i < e;
         const float* p = mb.rec + (size_t)(valid ? i : b0) * RS;
@@ -566,7 +566,7 @@ __global__ void __launch_bounds__(256) k_bin_hist(MapBins mb) {
     if (__lane_id() == 0) atomicMax(&hmax, __float_as_uint(m));   // non-negative floats order as integers
     __syncthreads();
     uint32_t* const rb = mb.rowbase + (size_t)blockIdx.x * mb.nb;
-    for (int k = threadIdx.x; k < mb.nb; k += 256)
+    for (int k = threadIdx.x; k < mb.nb; k += BIN_TB)
         if (h[k]) rb[k] = atomicAdd(&mb.bins[k], h[k]);
     if (threadIdx.x == 0 && hmax) atomicMax(&mb.bins[3 * mb.nb + 1], hmax);
 }
@@ -602,7 +602,7 @@ __global__ void __launch_bounds__(1024) k_bin_scan(MapBins mb) {
 // order as the histogram's count (entries of tiles the chunk does not touch are stale
 // and never read)
 template <int RS>
-__global__ void __launch_bounds__(256) k_bin_place(MapBins mb) {
+__global__ void __launch_bounds__(BIN_TB) k_bin_place(MapBins mb) {
     __shared__ uint32_t cnt[MAP_MAX_BINS];
     const uint32_t n = map_records(mb);
     const uint32_t b0 = blockIdx.x * BIN_CHUNK;
@@ -610,9 +610,9 @@ __global__ void __launch_bounds__(256) k_bin_place(MapBins mb) {
     const uint32_t e = min(n, b0 + BIN_CHUNK);
     const uint32_t* off = mb.bins + mb.nb;
     const uint32_t* rb = mb.rowbase + (size_t)blockIdx.x * mb.nb;
-    for (int k = threadIdx.x; k < mb.nb; k += 256) cnt[k] = off[k] + rb[k];
+    for (int k = threadIdx.x; k < mb.nb; k += BIN_TB) cnt[k] = off[k] + rb[k];
     __syncthreads();
-    for (uint32_t base = b0; base < e; base += 256) {
+    for (uint32_t base = b0; base < e; base += BIN_TB) {
         const uint32_t i = base + threadIdx.x;
         const bool valid = i < e;
         const float2* src = (const float2*)(mb.rec + (size_t)(valid ? i : b0) * RS);
@@ -1072,9 +1072,9 @@ bool map_tiling(int W, int H, int& T, int& nbx, int& nby) {
 template <int C, int RS>
 static void flush_one(const Launch& l, const MapBins& mb, float* out, int stride) {
     const unsigned g = (unsigned)((mb.cap + BIN_CHUNK - 1) / BIN_CHUNK);
-    hipLaunchKernelGGL((k_bin_hist<C, RS>), dim3(g), dim3(256), 0, l.st, mb);
+    hipLaunchKernelGGL((k_bin_hist<C, RS>), dim3(g), dim3(BIN_TB), 0, l.st, mb);
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, l.st, mb);
-    hipLaunchKernelGGL(k_bin_place<RS>, dim3(g), dim3(256), 0, l.st, mb);
+    hipLaunchKernelGGL(k_bin_place<RS>, dim3(g), dim3(BIN_TB), 0, l.st, mb);
     hipLaunchKernelGGL((k_bin_accum<C, RS>), dim3((unsigned)((mb.cap + ACC_CHUNK - 1) / ACC_CHUNK)), dim3(256), 0,
                        l.st, mb);
     hipLaunchKernelGGL(k_bin_gather<C>, dim3(grid_of((int64_t)mb.W * mb.H, 256)), dim3(256), 0, l.st, mb, out,

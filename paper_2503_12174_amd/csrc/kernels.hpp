@@ -76,6 +76,8 @@ constexpr int BIN_DEPTHS = 4;   // replay depths between flushes (record capacit
 constexpr int ACC_CHUNK = 4096; // records per workgroup of the accumulation; the stage holds
                                 // ceil(cap / ACC_CHUNK) + nb blocks of (T + 1)^2 x C floats
 constexpr int BIN_CHUNK = 16384;// records per workgroup of the histogram and the placement
+constexpr int BIN_TB = 1024;    // their threads per workgroup: 16 waves share one LDS
+                                // histogram, so the few chunks of a flush still fill the chip
 struct MapBins {
     float* rec;          // records of rs floats (null: binning off, the replay scatters directly)
     float* sorted;       // the same records grouped by tile

@@ -76,6 +76,34 @@ __device__ __forceinline__ bool wt_intersect(const WtRay& r, V3 v0, V3 v1, V3 v2
     return true;
 }
 
+// The traversal loops decide hits with this cheaper form of the same test: no
+// barycentrics, and t = (Sz T') * rcp(det) with T' = U Akz + V Bkz + W Ckz (the hardware
+// reciprocal, not the correctly rounded quotient).  Every query -- BVH or brute force --
+// decides with it and then recomputes the reported t and barycentrics of its winner with
+// wt_intersect, so all of them agree bit for bit.
+__device__ __forceinline__ bool wt_hit(const WtRay& r, V3 v0, V3 v1, V3 v2, float& t) {
+    const int kx = (int)(r.k & 3u), ky = (int)((r.k >> 2) & 3u), kz = (int)(r.k >> 4);
+    const V3 A = v0 - r.o, B = v1 - r.o, C = v2 - r.o;
+    const float Akz = comp(A, kz), Bkz = comp(B, kz), Ckz = comp(C, kz);
+    const float Ax = comp(A, kx) - r.Sx * Akz, Ay = comp(A, ky) - r.Sy * Akz;
+    const float Bx = comp(B, kx) - r.Sx * Bkz, By = comp(B, ky) - r.Sy * Bkz;
+    const float Cx = comp(C, kx) - r.Sx * Ckz, Cy = comp(C, ky) - r.Sy * Ckz;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {  // edge case: decide in double
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    const float det = U + V + W;
+    if (det == 0.0f) return false;
+    const float T = U * Akz + V * Bkz + W * Ckz;
+    t = (T * r.Sz) * __builtin_amdgcn_rcpf(det);
+    return true;
+}
+
 struct Hit {
     float t;
     int leaf;   // leaf-order triangle index, -1 on a miss
@@ -144,7 +172,6 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
     const WtRay wr = wt_setup(o, d);
     float best_t = tmax;
     int best_prim = 0x7fffffff, best_leaf = -1;
-    float bb1 = 0.f, bb2 = 0.f;
     int sp = 0;
     int node = 0;
     while (node >= 0) {   // the only exit (see traverse4)
@@ -164,14 +191,12 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
                 int prim;
                 vis.tri();
                 load_tri(tris, leaf, v0, v1, v2, prim);
-                float t, b1, b2;
-                if (prim != skip && wt_intersect(wr, v0, v1, v2, t, b1, b2) && t > tmin &&
+                float t;
+                if (prim != skip && wt_hit(wr, v0, v1, v2, t) && t > tmin &&
                     (t < best_t || (t == best_t && best_leaf >= 0 && prim < best_prim))) {
                     best_t = t;
                     best_prim = prim;
                     best_leaf = leaf;
-                    bb1 = b1;
-                    bb2 = b2;
                 }
             }
         }
@@ -201,6 +226,13 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
         } else {
             node = -1;
         }
+    }
+    float bb1 = 0.f, bb2 = 0.f;
+    if (best_leaf >= 0) {   // reported t and barycentrics: the exact test on the winner
+        V3 v0, v1, v2;
+        int prim;
+        load_tri(tris, best_leaf, v0, v1, v2, prim);
+        wt_intersect(wr, v0, v1, v2, best_t, bb1, bb2);
     }
     h.t = best_t;
     h.leaf = best_leaf;
@@ -329,8 +361,8 @@ __device__ __forceinline__ bool traverse4(const float4* __restrict__ nodes, cons
             int prim;
             vis.tri();
             load_tri(tris, leaf, v0, v1, v2, prim);
-            float t, b1, b2;
-            if (prim == skip || !wt_intersect(wr, v0, v1, v2, t, b1, b2) || !(t > tmin)) return;
+            float t;
+            if (prim == skip || !wt_hit(wr, v0, v1, v2, t) || !(t > tmin)) return;
             bool take = t < best_t;
             if constexpr (!ANY) {
                 // equal t: the smaller original index wins (the current best's index is
@@ -402,9 +434,8 @@ __device__ __forceinline__ bool traverse4(const float4* __restrict__ nodes, cons
     int best_prim = -1;
     if (best_leaf >= 0) {
         V3 v0, v1, v2;
-        float t;
         load_tri(tris, best_leaf, v0, v1, v2, best_prim);
-        wt_intersect(wr, v0, v1, v2, t, bb1, bb2);
+        wt_intersect(wr, v0, v1, v2, best_t, bb1, bb2);
     }
     h.t = best_t;
     h.leaf = best_leaf;
@@ -430,23 +461,27 @@ __device__ __forceinline__ bool brute_force(const float4* __restrict__ tris, con
     const WtRay wr = wt_setup(o, d);
     float best_t = tmax;
     int best = -1, best_leaf = -1;
-    float bb1 = 0.f, bb2 = 0.f;
     for (int p = 0; p < ntri; ++p) {
         if (p == skip) continue;
         const int leaf = leaf_of_prim[p];
         V3 v0, v1, v2;
         int prim;
         load_tri(tris, leaf, v0, v1, v2, prim);
-        float t, b1, b2;
+        float t;
         // triangles are visited in increasing original index, so on equal t the first wins
-        if (wt_intersect(wr, v0, v1, v2, t, b1, b2) && t > tmin && t < best_t) {
+        if (wt_hit(wr, v0, v1, v2, t) && t > tmin && t < best_t) {
             best_t = t;
             best = prim;
             best_leaf = leaf;
-            bb1 = b1;
-            bb2 = b2;
             if (ANY) break;
         }
+    }
+    float bb1 = 0.f, bb2 = 0.f;
+    if (best_leaf >= 0) {
+        V3 v0, v1, v2;
+        int prim;
+        load_tri(tris, best_leaf, v0, v1, v2, prim);
+        wt_intersect(wr, v0, v1, v2, best_t, bb1, bb2);
     }
     h.t = best_t;
     h.leaf = best_leaf;
