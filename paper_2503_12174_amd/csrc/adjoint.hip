@@ -632,7 +632,7 @@ __global__ void __launch_bounds__(BIN_TB) k_bin_place(MapBins mb) {
 // records in LDS over the tile plus one halo row/column and stores the (T + 1)^2 x C
 // block at pair index chunk + tile (unique: both grow along the sorted records).
 template <int C, int RS>
-__global__ void __launch_bounds__(256) k_bin_accum(MapBins mb) {
+__global__ void __launch_bounds__(ACC_TB) k_bin_accum(MapBins mb) {
     // Sums in 64-bit fixed point (integer LDS atomics are exact and much faster than
     // FP32 ones): values scaled by 2^E with |chunk sum| < 2^62 for every texel, i.e.
     // 2^-50 of the largest record value as resolution.
@@ -659,11 +659,11 @@ __global__ void __launch_bounds__(256) k_bin_accum(MapBins mb) {
     const int S = mb.T + 1, SS = S * S * C;
     for (;;) {
         const uint32_t s0 = max(off[b], i0), s1 = min(off[b + 1], i1);
-        for (int k = threadIdx.x; k < SS; k += 256) t[k] = 0;
+        for (int k = threadIdx.x; k < SS; k += ACC_TB) t[k] = 0;
         __syncthreads();
         const int tx0 = (b % mb.nbx) * mb.T, ty0 = (b / mb.nbx) * mb.T;
         bool bad = false;
-        for (uint32_t i = s0 + threadIdx.x; i < s1; i += 256) {
+        for (uint32_t i = s0 + threadIdx.x; i < s1; i += ACC_TB) {
             const float* p = mb.sorted + (size_t)i * RS;
             const uint32_t head = __float_as_uint(p[0]);
             const uint32_t base = head & 0x0fffffffu;
@@ -686,7 +686,7 @@ __global__ void __launch_bounds__(256) k_bin_accum(MapBins mb) {
         }
         const bool any_bad = __syncthreads_or(bad);
         float* st = mb.stage + (size_t)(c + b) * SS;
-        for (int k = threadIdx.x; k < SS; k += 256)
+        for (int k = threadIdx.x; k < SS; k += ACC_TB)
             st[k] = any_bad ? __builtin_nanf("") : (float)((double)t[k] * down);
         __syncthreads();
         if (off[b + 1] >= i1) break;
@@ -1075,7 +1075,7 @@ static void flush_one(const Launch& l, const MapBins& mb, float* out, int stride
     hipLaunchKernelGGL((k_bin_hist<C, RS>), dim3(g), dim3(BIN_TB), 0, l.st, mb);
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, l.st, mb);
     hipLaunchKernelGGL(k_bin_place<RS>, dim3(g), dim3(BIN_TB), 0, l.st, mb);
-    hipLaunchKernelGGL((k_bin_accum<C, RS>), dim3((unsigned)((mb.cap + ACC_CHUNK - 1) / ACC_CHUNK)), dim3(256), 0,
+    hipLaunchKernelGGL((k_bin_accum<C, RS>), dim3((unsigned)((mb.cap + ACC_CHUNK - 1) / ACC_CHUNK)), dim3(ACC_TB), 0,
                        l.st, mb);
     hipLaunchKernelGGL(k_bin_gather<C>, dim3(grid_of((int64_t)mb.W * mb.H, 256)), dim3(256), 0, l.st, mb, out,
                        stride);

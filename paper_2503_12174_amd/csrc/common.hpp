@@ -177,13 +177,13 @@ struct Brdf {
 };
 
 __device__ __forceinline__ double ggx_alpha(double r) { return fmax(r * r, ALPHA_MIN); }
-// D(h) from cos^2 and sin^2 of the half-vector angle
-__device__ __forceinline__ double ggx_D(double c2, double s2, double a) {
-    const double a2 = a * a;
-    const double k = a2 * c2 + s2;
-    return a2 / (PI * k * k);
-}
 
+// The GGX terms use the unnormalised half vector v = wi + wo (|v|^2 = vv): with h =
+// v / |v|, cos^2 = (n.v)^2 / vv, sin^2 = |n x v|^2 / vv and, wi and wo being unit,
+// wi.h = sqrt(vv) / 2.  D G / (4 ci co), with D = a^2 / (pi k^2) and the Smith factors
+// G1 = 2c / (c + q), q = sqrt(a^2 + (1 - a^2) c^2), is then
+// a^2 vv^2 / (pi kv^2 (ci + qi)(co + qo)) with kv = k vv: two square roots and one
+// division per evaluation.
 template <bool GRAD>
 __device__ __forceinline__ Brdf brdf_eval(int kind, D3 n, D3 wo, D3 wi, D3 alb, double r, double sp) {
     Brdf b{d3(0., 0., 0.), 0., 0.};
@@ -191,33 +191,28 @@ __device__ __forceinline__ Brdf brdf_eval(int kind, D3 n, D3 wo, D3 wi, D3 alb, 
     if (ci <= 0.0 || co <= 0.0) return b;
     b.f = alb * (1.0 / PI);
     if (kind == 0) return b;
-    const D3 h = normalize(wi + wo);
-    const double nh = dot(n, h), ih = dot(wi, h);
-    const D3 nxh = cross(n, h);
-    const double c2 = nh * nh, s2 = dot(nxh, nxh);
+    const D3 v = wi + wo;
+    const double vv = dot(v, v), nv = dot(n, v);
+    const D3 nxv = cross(n, v);
+    const double c2v = nv * nv, s2v = dot(nxv, nxv);
     const double a = ggx_alpha(r);
     const double a2 = a * a;
-    const double k = a2 * c2 + s2;
-    const double D = a2 / (PI * k * k);
+    const double kv = a2 * c2v + s2v;
     const double qi = sqrt(a2 + (1.0 - a2) * ci * ci), qo = sqrt(a2 + (1.0 - a2) * co * co);
-    const double G1i = 2.0 * ci / (ci + qi), G1o = 2.0 * co / (co + qo);
-    const double G = G1i * G1o;
     const double F0 = 0.08 * sp;
-    const double m = 1.0 - ih;
+    const double m = 1.0 - 0.5 * sqrt(vv);
     const double m5 = m * m * m * m * m;
     const double F = F0 + (1.0 - F0) * m5;
-    const double inv_den = 1.0 / (4.0 * ci * co);
-    const double s = F * D * G * inv_den;
+    const double DGw = a2 * vv * vv / (PI * kv * kv * (ci + qi) * (co + qo));   // D G / (4 ci co)
+    const double s = F * DGw;
     b.f = b.f + d3(s, s, s);
     if (GRAD) {
-        // dD/da = 2a/(pi k^2) (1 - 2 a^2 cos^2 / k);  dG1/da = -2c (a (1 - c^2)/q) / (c + q)^2
-        const double dD = 2.0 * a / (PI * k * k) * (1.0 - 2.0 * a2 * c2 / k);
-        const double dG1i = -2.0 * ci * (a * (1.0 - ci * ci) / qi) / ((ci + qi) * (ci + qi));
-        const double dG1o = -2.0 * co * (a * (1.0 - co * co) / qo) / ((co + qo) * (co + qo));
-        const double dG = dG1i * G1o + G1i * dG1o;
+        // d ln D / da = (2 / a)(1 - 2 a^2 cos^2 / k);  d ln G1 / da = -a (1 - c^2) / (q (c + q))
+        const double dlnD = 2.0 / a * (1.0 - 2.0 * a2 * c2v / kv);
+        const double dlnG = -a * ((1.0 - ci * ci) / (qi * (ci + qi)) + (1.0 - co * co) / (qo * (co + qo)));
         const double da_dr = (r * r > ALPHA_MIN) ? 2.0 * r : 0.0;
-        b.ds_dr = F * (dD * G + D * dG) * inv_den * da_dr;
-        b.ds_dsp = 0.08 * (1.0 - m5) * D * G * inv_den;
+        b.ds_dr = s * (dlnD + dlnG) * da_dr;
+        b.ds_dsp = 0.08 * (1.0 - m5) * DGw;
     }
     return b;
 }
@@ -260,14 +255,21 @@ __device__ __forceinline__ D3 sample_bounce(int kind, D3 n, D3 wo, double r, dou
 
 // density of sample_bounce (solid angle); the microfacet normal that produced wi is
 // the one of +-(wi + wo) on n's side
+// (GGX part: D(h) |n.h| / (4 |wo.h|) = a^2 vv^2 |n.v| / (4 pi kv^2 |wo.v|), v = wi + wo as
+// in brdf_eval)
 __device__ __forceinline__ double bounce_pdf(int kind, D3 n, D3 wo, D3 wi, double r) {
     const double ci = dot(n, wi);
     const double pd = ci > 0.0 ? ci * (1.0 / PI) : 0.0;
     if (kind == 0) return pd;
-    const D3 h = normalize(wi + wo);
-    const double nh = fabs(dot(n, h)), oh = fabs(dot(wo, h));
-    const D3 nxh = cross(n, h);
-    const double ps = (nh > 0.0 && oh > 0.0) ? ggx_D(nh * nh, dot(nxh, nxh), ggx_alpha(r)) * nh / (4.0 * oh) : 0.0;
+    const D3 v = wi + wo;
+    const double nv = fabs(dot(n, v)), ov = fabs(dot(wo, v));
+    double ps = 0.0;
+    if (nv > 0.0 && ov > 0.0) {
+        const D3 nxv = cross(n, v);
+        const double vv = dot(v, v), a = ggx_alpha(r), a2 = a * a;
+        const double kv = a2 * nv * nv + dot(nxv, nxv);
+        ps = a2 * vv * vv * nv / (4.0 * PI * kv * kv * ov);
+    }
     return (1.0 - P_SPEC) * pd + P_SPEC * ps;
 }
 

@@ -75,6 +75,7 @@ constexpr int MAP_MAX_T = 16;   // tile side 8 or 16: maps up to 1024 x 1024 are
 constexpr int BIN_DEPTHS = 4;   // replay depths between flushes (record capacity follows)
 constexpr int ACC_CHUNK = 4096; // records per workgroup of the accumulation; the stage holds
                                 // ceil(cap / ACC_CHUNK) + nb blocks of (T + 1)^2 x C floats
+constexpr int ACC_TB = 1024;    // threads per workgroup of the accumulation
 constexpr int BIN_CHUNK = 16384;// records per workgroup of the histogram and the placement
 constexpr int BIN_TB = 1024;    // their threads per workgroup: 16 waves share one LDS
                                 // histogram, so the few chunks of a flush still fill the chip
