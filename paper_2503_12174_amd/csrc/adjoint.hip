@@ -779,11 +779,11 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
                 rl = q.L[i];                                  // remaining radiance = the sample's total
                 penda = make_float4(0.f, 0.f, 0.f, -1.f);     // no pending bounce
             } else {
-                o = q.po[cur][i];
-                dd = q.pd[cur][i];
-                b = q.pb[cur][i];
-                rl = aq.rl[cur][i];
-                penda = aq.penda[cur][i];
+                o = nt_ld(&q.po[cur][i]);
+                dd = nt_ld(&q.pd[cur][i]);
+                b = nt_ld(&q.pb[cur][i]);
+                rl = nt_ld(&aq.rl[cur][i]);
+                penda = nt_ld(&aq.penda[cur][i]);
             }
             const ReqDesc& r = sel<UNI>(uni, table, o.slot);
             rp = &r;
@@ -798,10 +798,10 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
             if (penda.w >= 0.f) {
                 // previous vertex: its next-event cotangents plus d/df of its bounce,
                 // beta_k f cos/pdf R_{k+1} -> R_{k+1} / f (zero when this ray escaped)
-                const float2 pend = aq.pend[cur][i];
-                const double2 puv = aq.puv[cur][i];
-                const float4 pn = aq.pn[cur][i];
-                const float pns = aq.pns[cur][i];
+                const float2 pend = nt_ld(&aq.pend[cur][i]);
+                const double2 puv = nt_ld(&aq.puv[cur][i]);
+                const float4 pn = nt_ld(&aq.pn[cur][i]);
+                const float pns = nt_ld(&aq.pns[cur][i]);
                 a_on = true;
                 a_u = puv.x;
                 a_v = puv.y;
@@ -935,15 +935,15 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
         uint32_t jn;
         block_append<1>(pred, ctr, &jn);
         if (cont) {
-            q.po[nxt][jn] = no;
-            q.pd[nxt][jn] = nd;
-            q.pb[nxt][jn] = nb;
-            aq.rl[nxt][jn] = nrl;
-            aq.pend[nxt][jn] = npend;
-            aq.puv[nxt][jn] = npuv;
-            aq.penda[nxt][jn] = npenda;
-            aq.pn[nxt][jn] = npn;
-            aq.pns[nxt][jn] = npns;
+            nt_st(&q.po[nxt][jn], no);
+            nt_st(&q.pd[nxt][jn], nd);
+            nt_st(&q.pb[nxt][jn], nb);
+            nt_st(&aq.rl[nxt][jn], nrl);
+            nt_st(&aq.pend[nxt][jn], npend);
+            nt_st(&aq.puv[nxt][jn], npuv);
+            nt_st(&aq.penda[nxt][jn], npenda);
+            nt_st(&aq.pn[nxt][jn], npn);
+            nt_st(&aq.pns[nxt][jn], npns);
         }
     }
 }

@@ -83,6 +83,43 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
 // top 24 bits -> [0, 1), exact in float and double
 __device__ __forceinline__ double u24(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
 
+// Non-temporal (streaming) access to queue records that a kernel reads or writes once:
+// the line is not kept in the caches, which then keep more of what is reused -- BVH
+// nodes and triangle records during traversal, texture and projector maps in shading.
+template <int B> struct NtChunk;   // unsigned vector of B bytes
+template <> struct NtChunk<16> { typedef unsigned int type __attribute__((ext_vector_type(4))); };
+template <> struct NtChunk<8> { typedef unsigned int type __attribute__((ext_vector_type(2))); };
+template <> struct NtChunk<4> { typedef unsigned int type; };
+template <class T>
+constexpr int nt_chunk() { return sizeof(T) % 16 == 0 ? 16 : (sizeof(T) % 8 == 0 ? 8 : 4); }
+template <class T>
+__device__ __forceinline__ T nt_ld(const T* p) {
+    constexpr int B = nt_chunk<T>();
+    static_assert(sizeof(T) % 4 == 0, "streamed records are 4-byte multiples");
+    typedef typename NtChunk<B>::type C;
+    T v;
+    const C* s = reinterpret_cast<const C*>(p);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / B); ++k) {
+        const C x = __builtin_nontemporal_load(s + k);
+        __builtin_memcpy(reinterpret_cast<char*>(&v) + B * k, &x, B);
+    }
+    return v;
+}
+template <class T>
+__device__ __forceinline__ void nt_st(T* p, const T& v) {
+    constexpr int B = nt_chunk<T>();
+    static_assert(sizeof(T) % 4 == 0, "streamed records are 4-byte multiples");
+    typedef typename NtChunk<B>::type C;
+    C* d = reinterpret_cast<C*>(p);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / B); ++k) {
+        C x;
+        __builtin_memcpy(&x, reinterpret_cast<const char*>(&v) + B * k, B);
+        __builtin_nontemporal_store(x, d + k);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // path state in HBM: 80 bytes per path
 // ---------------------------------------------------------------------------

@@ -84,15 +84,15 @@ __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_trace(Queues q, int 
     int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL;
     const uint32_t n = q.cnt[cur];
     for (uint32_t i = blockIdx.x * TB + threadIdx.x; i < n; i += gridDim.x * TB) {
-        const PathO o = q.po[cur][i];
-        const PathD d = q.pd[cur][i];
+        const PathO o = nt_ld(&q.po[cur][i]);
+        const PathD d = nt_ld(&q.pd[cur][i]);
         const ReqDesc& r = sel<UNI>(uni, table, o.slot);
         Hit h;
         Visits<PROF> vis;
         trace_ray<false, SHORT_STACK, TB>(r.nodes4, r.nodes, r.tris, v3((float)o.x, (float)o.y, (float)o.z),
                                          v3((float)d.x, (float)d.y, (float)d.z), r.tmin, __builtin_inff(), o.skip,
                                          h, stack, spill, threadIdx.x, vis);
-        q.hit[i] = h.leaf;
+        __builtin_nontemporal_store(h.leaf, &q.hit[i]);
         if constexpr (PROF)
             if (q.stats) {
                 atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
@@ -119,10 +119,10 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
         float4 nb = {}, po = {}, pd = {}, pc = {}, eo = {}, ed = {}, ec = {};
         float ptmax = 0.0f;
         if (i < n) {
-            const PathO o = q.po[cur][i];
-            const PathD dd = q.pd[cur][i];
-            const float4 b = q.pb[cur][i];
-            const int leaf = q.hit[i];
+            const PathO o = nt_ld(&q.po[cur][i]);
+            const PathD dd = nt_ld(&q.pd[cur][i]);
+            const float4 b = nt_ld(&q.pb[cur][i]);
+            const int leaf = __builtin_nontemporal_load(&q.hit[i]);
             const ReqDesc& r = sel<UNI>(uni, table, o.slot);
             const uint32_t g = dd.g;
             const uint32_t sid = g - r.g_base + r.sid_base;
@@ -196,21 +196,21 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
         block_append_keyed<3, 8>(pred, key, ctr, at);
         const uint32_t jn = at[0], jp = at[1], je = at[2];
         if (cont) {
-            q.po[nxt][jn] = no;
-            q.pd[nxt][jn] = nd;
-            q.pb[nxt][jn] = nb;
+            nt_st(&q.po[nxt][jn], no);
+            nt_st(&q.pd[nxt][jn], nd);
+            nt_st(&q.pb[nxt][jn], nb);
         }
         if (shp) {
-            q.so[0][jp] = po;
-            q.sd[0][jp] = pd;
-            q.sc[0][jp] = pc;
-            q.st[0][jp] = ptmax;
+            nt_st(&q.so[0][jp], po);
+            nt_st(&q.sd[0][jp], pd);
+            nt_st(&q.sc[0][jp], pc);
+            __builtin_nontemporal_store(ptmax, &q.st[0][jp]);
         }
         if (she) {
-            q.so[1][je] = eo;
-            q.sd[1][je] = ed;
-            q.sc[1][je] = ec;
-            q.st[1][je] = __builtin_inff();
+            nt_st(&q.so[1][je], eo);
+            nt_st(&q.sd[1][je], ed);
+            nt_st(&q.sc[1][je], ec);
+            __builtin_nontemporal_store(__builtin_inff(), &q.st[1][je]);
         }
     }
 }
@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_shadow(Queues q, int
     int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL;
     const uint32_t n = q.cnt[2 + which];
     for (uint32_t i = blockIdx.x * TB + threadIdx.x; i < n; i += gridDim.x * TB) {
-        const float4 o = q.so[which][i], d = q.sd[which][i];
+        const float4 o = nt_ld(&q.so[which][i]), d = nt_ld(&q.sd[which][i]);
         const ReqDesc& r = sel<UNI>(uni, table, __float_as_int(o.w));
         Hit h;
         Visits<PROF> vis;
