@@ -142,8 +142,8 @@ __device__ __forceinline__ bool put_tex_rec(const MapBins& mb, uint32_t slot, do
     if ((int64_t)slot >= mb.cap) return false;
     const Corners c = bilinear_corners(u * mb.W - 0.5, v * mb.H - 0.5, mb.W, mb.H);
     float4* p = (float4*)(mb.rec + (size_t)slot * TEX_RS);
-    p[0] = make_float4(__uint_as_float(map_head(c, mb.W)), (float)c.ax, (float)c.ay, g[0]);
-    p[1] = make_float4(g[1], g[2], g[3], g[4]);
+    nt_st(p, make_float4(__uint_as_float(map_head(c, mb.W)), (float)c.ax, (float)c.ay, g[0]));
+    nt_st(p + 1, make_float4(g[1], g[2], g[3], g[4]));
     return true;
 }
 // E_p record at projector pixel position (pu, pv); false when the buffer is full
@@ -151,9 +151,9 @@ __device__ __forceinline__ bool put_ep_rec(const MapBins& mb, uint32_t slot, dou
     if ((int64_t)slot >= mb.cap) return false;
     const Corners c = bilinear_corners(pu - 0.5, pv - 0.5, mb.W, mb.H);
     float2* p = (float2*)(mb.rec + (size_t)slot * EP_RS);
-    p[0] = make_float2(__uint_as_float(map_head(c, mb.W)), (float)c.ax);
-    p[1] = make_float2((float)c.ay, g[0]);
-    p[2] = make_float2(g[1], g[2]);
+    nt_st(p, make_float2(__uint_as_float(map_head(c, mb.W)), (float)c.ax));
+    nt_st(p + 1, make_float2((float)c.ay, g[0]));
+    nt_st(p + 2, make_float2(g[1], g[2]));
     return true;
 }
 
@@ -790,7 +790,7 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
             lslot = o.slot;
             const uint32_t g = dd.g;
             const uint32_t sid = g - r.g_base + r.sid_base;
-            const uint32_t rec = r.rec[(size_t)(g - r.rec_g0) * r.max_depth + depth];
+            const uint32_t rec = __builtin_nontemporal_load(&r.rec[(size_t)(g - r.rec_g0) * r.max_depth + depth]);
             const int leaf = (int)(rec & REC_LEAF) - 1;
             const float4 dl = aq.delta[sid];
             const D3 delta = d3(dl.x, dl.y, dl.z);

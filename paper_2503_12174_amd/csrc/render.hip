@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
             const uint32_t g = dd.g;
             const uint32_t sid = g - r.g_base + r.sid_base;
             const D3 beta = d3(b.x, b.y, b.z);
-            if (r.rec) r.rec[(size_t)(g - r.rec_g0) * r.max_depth + depth] = (uint32_t)(leaf + 1);
+            if (r.rec) __builtin_nontemporal_store((uint32_t)(leaf + 1), &r.rec[(size_t)(g - r.rec_g0) * r.max_depth + depth]);
             if (leaf < 0) {
                 if (r.out_hits) r.out_hits[(size_t)g * r.max_depth + depth] = -1;
                 if (depth == 0 && r.env_on) {   // a camera ray that escapes sees the environment
@@ -229,7 +229,7 @@ __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_shadow(Queues q, int
         const ReqDesc& r = sel<UNI>(uni, table, __float_as_int(o.w));
         Hit h;
         Visits<PROF> vis;
-        const bool occ = trace_ray<true, SHORT_STACK, TB>(r.nodes4, r.nodes, r.tris, xyz(o), xyz(d), r.tmin, q.st[which][i],
+        const bool occ = trace_ray<true, SHORT_STACK, TB>(r.nodes4, r.nodes, r.tris, xyz(o), xyz(d), r.tmin, nt_ld(&q.st[which][i]),
                                                          __float_as_int(d.w), h, stack, spill, threadIdx.x, vis);
         if constexpr (PROF)
             if (q.stats) {
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_shadow(Queues q, int
                 atomicAdd(&q.stats[1], (unsigned long long)vis.tris);
             }
         if (!occ) {
-            const float4 c = q.sc[which][i];
+            const float4 c = nt_ld(&q.sc[which][i]);
             const uint32_t sid = __float_as_uint(c.w);
             float4 L = q.L[sid];
             L.x += c.x;
