@@ -205,6 +205,18 @@ DPCS_API dpcs_status dpcs_debug_intersect(dpcs_context ctx, dpcs_scene scene, co
 /* Philox4x32-10 of n counters (device: ctr n x 4, out n x 4). */
 DPCS_API dpcs_status dpcs_debug_philox(dpcs_context ctx, uint64_t seed, const uint32_t* ctr, int64_t n,
                               uint32_t* out);
+/* The surface reflectance f_r of the rendering equation (Sec. 3.2, Eq. 3) as this
+ * library models it (brdf: DPCS_BRDF_LAMBERT, or Lambert + GGX microfacet lobe), its
+ * derivatives, and the bounce sampler with its density, evaluated by the same device
+ * code the renderer and the VJP use, for n rows of FP64 input.
+ * in  (device, n x 17): normal xyz, outgoing direction xyz, incoming direction xyz (all
+ *     unit), albedo rgb, roughness, specular, sampler numbers (lobe, u1, u2) in [0, 1).
+ * out (device, n x 11): f rgb, d(specular term)/d roughness, d(specular term)/d specular,
+ *     density of sampling the incoming direction, a direction sampled from the three
+ *     numbers (xyz) and its density, and f.r as the forward (non-derivative) evaluation
+ *     computes it.  The caller owns both buffers; DPCS_E_INVALID on a bad kind or null
+ *     pointer with n > 0. */
+DPCS_API dpcs_status dpcs_debug_brdf(dpcs_context ctx, int32_t brdf, const double* in, int64_t n, double* out);
 
 /* -------------------------------------------------------------- profiling */
 

@@ -289,6 +289,32 @@ __global__ void __launch_bounds__(256) k_finalize(Queues q, ReqDesc r, uint32_t 
 }
 
 // ---------------------------------------------------------------- debug
+// BRDF value and derivatives, bounce density and a bounce sample, on rows of FP64 input
+// (17 per row in, 11 per row out; the layout is the C ABI's)
+__global__ void k_debug_brdf(int kind, const double* __restrict__ in, int64_t n, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double* x = in + 17 * i;
+    const D3 nn = d3(x[0], x[1], x[2]), wo = d3(x[3], x[4], x[5]), wi = d3(x[6], x[7], x[8]);
+    const D3 alb = d3(x[9], x[10], x[11]);
+    const double r = x[12], sp = x[13];
+    const Brdf f = brdf_eval<true>(kind, nn, wo, wi, alb, r, sp);
+    const Brdf f0 = brdf_eval<false>(kind, nn, wo, wi, alb, r, sp);
+    const D3 ws = sample_bounce(kind, nn, wo, r, x[14], x[15], x[16]);
+    double* y = out + 11 * i;
+    y[0] = f.f.x;
+    y[1] = f.f.y;
+    y[2] = f.f.z;
+    y[3] = f.ds_dr;
+    y[4] = f.ds_dsp;
+    y[5] = bounce_pdf(kind, nn, wo, wi, r);
+    y[6] = ws.x;
+    y[7] = ws.y;
+    y[8] = ws.z;
+    y[9] = bounce_pdf(kind, nn, wo, ws, r);
+    y[10] = f0.f.x;
+}
+
 // full 64-entry LDS stack (no spill region needed: the host checks the stack bound).
 // mode: 0 brute force, 1 the BVH the renderer uses (4-wide when built), 2 the binary
 // BVH, 3 any hit on the renderer's BVH, 4 any hit by brute force
@@ -400,6 +426,9 @@ void launch_debug_intersect(const Launch& l, const float4* nodes4, const float4*
     if (n <= 0) return;
     hipLaunchKernelGGL(k_debug_intersect, dim3(grid_of(n, TB)), dim3(TB), 0, l.st, nodes4, nodes, tris, leaf_of_prim,
                        nt, tmin, rays, n, mode, prim, t, b1, b2);
+}
+void launch_debug_brdf(const Launch& l, int kind, const double* in, int64_t n, double* out) {
+    if (n > 0) hipLaunchKernelGGL(k_debug_brdf, dim3(grid_of(n, 256)), dim3(256), 0, l.st, kind, in, n, out);
 }
 void launch_debug_philox(const Launch& l, uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out) {
     if (n > 0)

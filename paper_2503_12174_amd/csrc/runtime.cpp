@@ -950,6 +950,19 @@ extern "C" dpcs_status dpcs_debug_philox(dpcs_context ctx, uint64_t seed, const 
     return hip_ok(ctx, hipGetLastError(), "debug_philox") ? DPCS_OK : DPCS_E_DEVICE;
 }
 
+extern "C" dpcs_status dpcs_debug_brdf(dpcs_context ctx, int32_t brdf, const double* in, int64_t n, double* out) {
+    if (!ctx) return DPCS_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (n < 0 || (n > 0 && (!in || !out)) || (brdf != DPCS_BRDF_LAMBERT && brdf != DPCS_BRDF_GGX))
+        return fail(ctx, DPCS_E_INVALID, "bad debug_brdf arguments");
+    if (n > (int64_t(1) << 31)) return fail(ctx, DPCS_E_INVALID, "debug_brdf: too many rows");
+    if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
+    (void)hipGetLastError();
+    Launch l{ctx->stream, ctx->grid_cap};
+    launch_debug_brdf(l, brdf, in, n, out);
+    return hip_ok(ctx, hipGetLastError(), "debug_brdf") ? DPCS_OK : DPCS_E_DEVICE;
+}
+
 // ====================================================================== profiling
 extern "C" dpcs_status dpcs_context_set_profiling(dpcs_context ctx, int32_t mode) {
     if (!ctx || mode < 0 || mode > 2) return DPCS_E_INVALID;

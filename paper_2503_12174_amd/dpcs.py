@@ -90,7 +90,7 @@ class Request(C.Structure):
 # every symbol the header declares (a test checks the library exports all of them)
 SYMBOLS = ["dpcs_context_create", "dpcs_context_destroy", "dpcs_last_error", "dpcs_context_synchronize",
            "dpcs_context_set_capacity", "dpcs_scene_create", "dpcs_scene_get_info", "dpcs_scene_destroy",
-           "dpcs_render", "dpcs_render_vjp", "dpcs_debug_intersect", "dpcs_debug_philox",
+           "dpcs_render", "dpcs_render_vjp", "dpcs_debug_intersect", "dpcs_debug_philox", "dpcs_debug_brdf",
            "dpcs_context_set_profiling", "dpcs_context_get_profile", "dpcs_server_create",
            "dpcs_server_submit", "dpcs_server_poll", "dpcs_server_stats", "dpcs_server_destroy"]
 
@@ -118,6 +118,7 @@ def lib():
             "dpcs_render_vjp": ([P, P, C.POINTER(RenderParams), P, P, P, P, C.POINTER(Grads)], S),
             "dpcs_debug_intersect": ([P, P, P, I64, I32, P, P, P, P], S),
             "dpcs_debug_philox": ([P, C.c_uint64, P, I64, P], S),
+            "dpcs_debug_brdf": ([P, I32, P, I64, P], S),
             "dpcs_context_set_profiling": ([P, I32], S),
             "dpcs_context_get_profile": ([P, C.POINTER(Profile)], S),
             "dpcs_server_create": ([P, C.c_size_t, I32, C.POINTER(P)], S),
@@ -287,6 +288,11 @@ def dpcs_debug_intersect(ctx: Context, scene: Scene, rays, use_bvh, prim, t=None
 
 def dpcs_debug_philox(ctx: Context, seed: int, ctr, out):
     return ctx.check(lib().dpcs_debug_philox(ctx.h, int(seed), _ptr(ctr), int(ctr.shape[0]), _ptr(out)))
+
+
+def dpcs_debug_brdf(ctx: Context, brdf: int, inputs, out):
+    """inputs: device float64 (n, 17); out: device float64 (n, 11) (layout in dpcs.h)."""
+    return ctx.check(lib().dpcs_debug_brdf(ctx.h, int(brdf), _ptr(inputs), int(inputs.shape[0]), _ptr(out)))
 
 
 class Server:
