@@ -164,8 +164,8 @@ def serving_bench(ctx, n_req, n_alone, warmup=20, rate=50.0):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {a.gpus} is not supported "
-              "(the path shards by pixels/samples across GPUs; see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported "
+              "(the path would shard by pixels and samples across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
