@@ -51,7 +51,7 @@ typedef enum {
     DPCS_E_INVALID = -1,      /* bad argument; nothing was launched */
     DPCS_E_OOM = -2,          /* scratch limit or device memory exhausted; outputs undefined */
     DPCS_E_DEVICE = -3,       /* a HIP call or kernel failed (sticky on the context) */
-    DPCS_E_UNSUPPORTED = -4,  /* valid request this build cannot serve (e.g. BVH too deep) */
+    DPCS_E_UNSUPPORTED = -4,  /* valid request the library cannot serve (e.g. BVH too deep) */
     DPCS_E_BUSY = -5,         /* object still referenced by queued work */
     DPCS_E_REJECTED = -6      /* server: the request can never fit the memory budget */
 } dpcs_status;
