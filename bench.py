@@ -44,6 +44,10 @@ RAY_IO_BYTES = 64 + 4
 NODE_BYTES = 64       # binary BVH node: two child boxes + two child references
 NODE4_BYTES = 128     # 4-wide BVH node: four child boxes (SoA) + four references + pad
 TRI_BYTES = 48
+UV_BYTES = 32          # corner UVs of a triangle
+SHADE_STATE_IN = 84    # PathO + PathD + throughput + hit index
+PATH_STATE = 80        # PathO + PathD + throughput written for a continuing path
+SHADOW_RECORD = 52     # shadow origin, direction, contribution float4s + t_max
 
 
 def parse():
@@ -263,6 +267,30 @@ def main():
         if sh["items"]:
             stages["shadow"]["nodes_per_ray"] = round(sh["nodes"] / sh["items"], 2)
             stages["shadow"]["tris_per_ray"] = round(sh["tris"] / sh["items"], 2)
+        roof["rays_per_s"] = round(rays_per_launch / (avg_ms * 1e-3), 1)
+        # shading's model bytes over the profiled steps (layout above): every vertex reads its
+        # path state, triangle and UV records, 4 packed albedo/roughness texels, 4 specular
+        # texels and writes a path record; each projector shadow record adds 4 projector
+        # texels read and the record written; each continuing path writes its next state
+        sd = prof["shade"]
+        cont = tr["items"] - prof["raygen"]["items"]
+        shade_bytes = (sd["items"] * (SHADE_STATE_IN + TRI_BYTES + UV_BYTES + 4 * 16 + 4 * 4 + 4)
+                       + prof["shadow"]["items"] * (4 * 16 + SHADOW_RECORD) + cont * PATH_STATE)
+        roof["shade_model_GBps"] = round(shade_bytes / (sd["ms"] * 1e-3) / 1e9, 1)
+        # measured device-copy bandwidth (1 GiB read + 1 GiB written), beside the spec peak
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        roof["copy_GBps"] = round(5 * 2 * x.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+        roof["frac_of_copy"] = round(achieved / roof["copy_GBps"], 4)
+        del x, y
 
     if a.calib_copy:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
