@@ -241,8 +241,10 @@ __global__ void __launch_bounds__(BLOCK) k_adj_pixel(Queues q, AdjQueues aq, Req
     }
 }
 
-// replay camera rays; the remaining radiance starts at the sample's total
-__global__ void k_adj_raygen(Queues q, AdjQueues aq, ReqDesc r, int slot, uint32_t g0, uint32_t n) {
+// replay camera rays at queue index = batch sample index (the depth-0 shading takes
+// the remaining radiance, the sample's total, from q.L at that index and starts with
+// no pending bounce, so nothing else is written here)
+__global__ void k_adj_raygen(Queues q, AdjQueues, ReqDesc r, int slot, uint32_t g0, uint32_t n) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const uint32_t g = g0 + k;
@@ -251,12 +253,6 @@ __global__ void k_adj_raygen(Queues q, AdjQueues aq, ReqDesc r, int slot, uint32
     q.po[0][sid] = PathO{r.cam_o[0], r.cam_o[1], r.cam_o[2], slot, -1};
     q.pd[0][sid] = PathD{d.x, d.y, d.z, g, 0u};
     q.pb[0][sid] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
-    aq.rl[0][sid] = q.L[sid];
-    aq.pend[0][sid] = make_float2(0.f, 0.f);
-    aq.puv[0][sid] = make_double2(0.0, 0.0);
-    aq.penda[0][sid] = make_float4(0.f, 0.f, 0.f, -1.f);   // w < 0: no pending bounce
-    aq.pn[0][sid] = make_float4(0.f, 0.f, 0.f, 0.f);
-    aq.pns[0][sid] = 0.f;
 }
 
 // ---------------------------------------------------------------- shading
@@ -296,8 +292,10 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
             const float4 dl = aq.delta[sid];
             const D3 delta = d3(dl.x, dl.y, dl.z);
             const D3 beta = d3(b.x, b.y, b.z);
-            float4 rl = aq.rl[cur][i];
-            const float4 penda = aq.penda[cur][i];
+            // depth 0: the camera wave (queue index = batch sample index) starts from the
+            // sample's total radiance with no pending bounce
+            float4 rl = depth == 0 ? q.L[i] : aq.rl[cur][i];
+            const float4 penda = depth == 0 ? make_float4(0.f, 0.f, 0.f, -1.f) : aq.penda[cur][i];
             if (leaf >= 0) {
                 const Surf s = surface(r, leaf, d3(o.x, o.y, o.z), d3(dd.x, dd.y, dd.z));
                 // the previous vertex's bounce: d/df of beta_k f cos/pdf R_{k+1} = L_r / f
@@ -782,8 +780,13 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
                 o = nt_ld(&q.po[cur][i]);
                 dd = nt_ld(&q.pd[cur][i]);
                 b = nt_ld(&q.pb[cur][i]);
-                rl = nt_ld(&aq.rl[cur][i]);
-                penda = nt_ld(&aq.penda[cur][i]);
+                if (depth == 0) {   // camera wave of several requests: as above, from the queue's rays
+                    rl = q.L[i];
+                    penda = make_float4(0.f, 0.f, 0.f, -1.f);
+                } else {
+                    rl = nt_ld(&aq.rl[cur][i]);
+                    penda = nt_ld(&aq.penda[cur][i]);
+                }
             }
             const ReqDesc& r = sel<UNI>(uni, table, o.slot);
             rp = &r;
