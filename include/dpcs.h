@@ -270,9 +270,11 @@ DPCS_API dpcs_status dpcs_server_submit(dpcs_server srv, const dpcs_request* req
  * to completion on the device; latency_ms may be NULL).  Returns the count. */
 DPCS_API int32_t dpcs_server_poll(dpcs_server srv, uint64_t* done_ids, int32_t* done_status, double* latency_ms,
                          int32_t max);
-/* Counters: [0] submitted, [1] completed, [2] rejected, [3] active, [4] queued,
- * [5] launch waves, [6] samples traced, [7] peak admitted bytes. */
-DPCS_API dpcs_status dpcs_server_stats(dpcs_server srv, int64_t* out8);
+/* Counters (out: 10 int64 on the host): [0] submitted, [1] completed, [2] rejected,
+ * [3] active, [4] queued, [5] launch waves, [6] samples traced, [7] peak admitted bytes,
+ * [8] waves whose compensation segments replayed path records, [9] waves whose
+ * compensation segments re-traced (their paths did not fit the wave's records). */
+DPCS_API dpcs_status dpcs_server_stats(dpcs_server srv, int64_t* out10);
 /* Waits for every admitted request, then stops the loop. */
 DPCS_API dpcs_status dpcs_server_destroy(dpcs_server srv);
 

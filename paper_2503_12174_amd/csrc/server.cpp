@@ -127,6 +127,7 @@ struct dpcs_server_s {
     std::deque<std::tuple<uint64_t, int32_t, double>> completed;
     bool stop = false;
     int64_t st_submitted = 0, st_completed = 0, st_rejected = 0, st_waves = 0, st_samples = 0, st_peak = 0;
+    int64_t st_replayed = 0, st_retraced = 0;   // waves whose compensation segments replayed / re-traced
     std::thread worker;
     std::string err;
     void run();
@@ -270,6 +271,7 @@ void dpcs_server_s::wave(Launch& l) {
     }
     ++st_waves;
     st_samples += used + n_adj;
+    if (any_adj) ++(replay ? st_replayed : st_retraced);
     for (const Seg& s : segs) {
         Req* q = s.q;
         if (q->next_pixel >= q->npix) {
@@ -508,7 +510,7 @@ extern "C" int32_t dpcs_server_poll(dpcs_server s, uint64_t* ids, int32_t* statu
     return n;
 }
 
-extern "C" dpcs_status dpcs_server_stats(dpcs_server s, int64_t* o) {
+extern "C" dpcs_status dpcs_server_stats(dpcs_server s, int64_t* o) {   // o: 10 counters
     if (!s || !o) return DPCS_E_INVALID;
     std::lock_guard<std::mutex> lk(s->mu);
     o[0] = s->st_submitted;
@@ -519,6 +521,8 @@ extern "C" dpcs_status dpcs_server_stats(dpcs_server s, int64_t* o) {
     o[5] = s->st_waves;
     o[6] = s->st_samples;
     o[7] = s->st_peak;
+    o[8] = s->st_replayed;
+    o[9] = s->st_retraced;
     return DPCS_OK;
 }
 

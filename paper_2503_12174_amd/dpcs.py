@@ -330,9 +330,10 @@ class Server:
         return out
 
     def stats(self) -> dict:
-        v = (C.c_int64 * 8)()
+        v = (C.c_int64 * 10)()
         self.ctx.check(lib().dpcs_server_stats(self.h, v))
-        keys = ["submitted", "completed", "rejected", "active", "queued", "waves", "samples", "peak_bytes"]
+        keys = ["submitted", "completed", "rejected", "active", "queued", "waves", "samples", "peak_bytes",
+                "replayed_waves", "retraced_waves"]
         return dict(zip(keys, [int(x) for x in v]))
 
     def close(self):
