@@ -21,6 +21,9 @@
  *   Eq. 12  radiance clipping min(L, k / min(w)) per camera sample
  *   Eq. 9/13 gradients of the rendered image w.r.t. I_p, the BRDF maps, the PRF and
  *            CRF parameters (the adjoint below), for scene fitting and compensation.
+ *   Eq. 9   the L1 data term and the map regulariser L(m) with their gradients
+ *   Eq. 11  the cross-bilateral denoiser D, its adjoint, and the per-pixel guide
+ *            features (first-hit albedo, normal, distance) it is steered by.
  *
  * Structure: every camera sample is traced by a scalar loop; every ray is tested
  * against every triangle (no acceleration structure), the nearest hit wins, equal
@@ -1024,4 +1027,152 @@ void orc_pdf_batch(int32_t kind, const double* n, const double* wo, double r, in
     v3 N = mk(n[0], n[1], n[2]), WO = mk(wo[0], wo[1], wo[2]);
     for (int64_t k = 0; k < count; ++k)
         out[k] = bounce_pdf(kind, N, WO, mk(wi[3 * k], wi[3 * k + 1], wi[3 * k + 2]), r);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Eq. 11: the cross-bilateral denoiser D and its adjoint                     */
+/* ------------------------------------------------------------------------- */
+/* The paper applies a differentiable cross-bilateral filter to the rendered
+ * image before the loss and fixes neither its window nor its weights.  Reading
+ * taken here: over the (2r+1) x (2r+1) window around pixel p, clipped to the image,
+ *     D(I)_p = sum_q w(p,q) I_q / W_p,     W_p = sum_q w(p,q),
+ *     w(p,q) = exp(-a_s |p - q|^2 - sum_k a_k (g_k(p) - g_k(q))^2),
+ * where g is a per-pixel guide image of G channels and a = 1 / (2 sigma^2) per
+ * channel.  The guide carries no gradient, so D is linear in I and its VJP is the
+ * transposed operator:  (D^T G)_q = sum_p w(p,q) G_p / W_p.
+ * Images are H x W x 3 and guides H x W x G, row-major. */
+static double bil_weight(const double* guide, int32_t G, const double* a_g, double a_s, int32_t W,
+                         int32_t px, int32_t py, int32_t qx, int32_t qy) {
+    double e = a_s * ((double)(px - qx) * (px - qx) + (double)(py - qy) * (py - qy));
+    const double* gp = guide + (size_t)G * ((size_t)py * W + px);
+    const double* gq = guide + (size_t)G * ((size_t)qy * W + qx);
+    for (int32_t k = 0; k < G; ++k) e += a_g[k] * (gp[k] - gq[k]) * (gp[k] - gq[k]);
+    return exp(-e);
+}
+
+static double bil_norm(const double* guide, int32_t G, const double* a_g, double a_s, int32_t W, int32_t H,
+                       int32_t r, int32_t px, int32_t py) {
+    double s = 0;
+    for (int32_t qy = py - r; qy <= py + r; ++qy)
+        for (int32_t qx = px - r; qx <= px + r; ++qx)
+            if (qx >= 0 && qx < W && qy >= 0 && qy < H)
+                s += bil_weight(guide, G, a_g, a_s, W, px, py, qx, qy);
+    return s;
+}
+
+void orc_denoise(const double* img, const double* guide, int32_t W, int32_t H, int32_t G, const double* a_g,
+                 double a_s, int32_t r, double* out) {
+#pragma omp parallel for schedule(static)
+    for (int32_t py = 0; py < H; ++py)
+        for (int32_t px = 0; px < W; ++px) {
+            double acc[3] = {0, 0, 0}, wsum = 0;
+            for (int32_t qy = py - r; qy <= py + r; ++qy)
+                for (int32_t qx = px - r; qx <= px + r; ++qx) {
+                    if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
+                    double w = bil_weight(guide, G, a_g, a_s, W, px, py, qx, qy);
+                    wsum += w;
+                    for (int c = 0; c < 3; ++c) acc[c] += w * img[3 * ((size_t)qy * W + qx) + c];
+                }
+            for (int c = 0; c < 3; ++c) out[3 * ((size_t)py * W + px) + c] = acc[c] / wsum;
+        }
+}
+
+void orc_denoise_vjp(const double* grad, const double* guide, int32_t W, int32_t H, int32_t G,
+                     const double* a_g, double a_s, int32_t r, double* out) {
+    /* output pixel q gathers from every p whose window holds q */
+#pragma omp parallel for schedule(static)
+    for (int32_t qy = 0; qy < H; ++qy)
+        for (int32_t qx = 0; qx < W; ++qx) {
+            double acc[3] = {0, 0, 0};
+            for (int32_t py = qy - r; py <= qy + r; ++py)
+                for (int32_t px = qx - r; px <= qx + r; ++px) {
+                    if (px < 0 || px >= W || py < 0 || py >= H) continue;
+                    double w = bil_weight(guide, G, a_g, a_s, W, px, py, qx, qy) /
+                               bil_norm(guide, G, a_g, a_s, W, H, r, px, py);
+                    for (int c = 0; c < 3; ++c) acc[c] += w * grad[3 * ((size_t)py * W + px) + c];
+                }
+            for (int c = 0; c < 3; ++c) out[3 * ((size_t)qy * W + qx) + c] = acc[c];
+        }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Eq. 9: regulariser L(m) and data term                                      */
+/* ------------------------------------------------------------------------- */
+static double sgn(double x) { return x > 0 ? 1.0 : (x < 0 ? -1.0 : 0.0); }
+
+/* L(m) for an h x w x c map: the paper calls it a total-variation loss without a
+ * formula.  Reading taken here: the anisotropic L1 form, mean |m(y+1,x) - m(y,x)|
+ * over all c (h-1) w vertical pairs plus mean |m(y,x+1) - m(y,x)| over all
+ * c h (w-1) horizontal pairs (a term without pairs is 0).  grad (may be NULL,
+ * h x w x c) receives dL/dm with d|x|/dx = sign(x), sign(0) = 0. */
+double orc_tv(const double* m, int32_t h, int32_t w, int32_t c, double* grad) {
+    const double nv = (double)c * (h - 1) * w, nh = (double)c * h * (w - 1);
+    double sv = 0, sh = 0;
+    if (grad) memset(grad, 0, sizeof(double) * (size_t)h * w * c);
+    for (int32_t y = 0; y < h; ++y)
+        for (int32_t x = 0; x < w; ++x)
+            for (int32_t k = 0; k < c; ++k) {
+                size_t i = ((size_t)y * w + x) * c + k;
+                if (y + 1 < h) {
+                    size_t j = i + (size_t)w * c;
+                    double dv = m[j] - m[i];
+                    sv += absd(dv);
+                    if (grad) { grad[j] += sgn(dv) / nv; grad[i] -= sgn(dv) / nv; }
+                }
+                if (x + 1 < w) {
+                    size_t j = i + (size_t)c;
+                    double dh = m[j] - m[i];
+                    sh += absd(dh);
+                    if (grad) { grad[j] += sgn(dh) / nh; grad[i] -= sgn(dh) / nh; }
+                }
+            }
+    return (nv > 0 ? sv / nv : 0.0) + (nh > 0 ? sh / nh : 0.0);
+}
+
+/* data term of Eq. 9 for one image pair: mean |a - b| over n values;
+ * grad (may be NULL) receives d/da = sign(a - b) / n with sign(0) = 0. */
+double orc_l1(const double* a, const double* b, int64_t n, double* grad) {
+    double s = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        s += absd(a[i] - b[i]);
+        if (grad) grad[i] = sgn(a[i] - b[i]) / (double)n;
+    }
+    return n > 0 ? s / (double)n : 0.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* guide features for D: one camera ray through each pixel centre (Eq. 6)     */
+/* ------------------------------------------------------------------------- */
+/* out: npix x 8 = albedo rgb of the first hit (bilinear texture lookup), unit
+ * geometric normal turned toward the camera, hit distance t, 1; all 8 are 0 where
+ * the ray escapes.  margin (may be NULL): the hit decision's normalised margin. */
+void orc_gbuffer(const orc_desc* d, int32_t npix, const int32_t* pixels, double* out, double* margin) {
+    ctx_t cx;
+    ctx_init(&cx, d);
+    int nth = nthreads_of(d);
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nth)
+    for (int32_t q = 0; q < npix; ++q) {
+        int32_t pixel = pixels ? pixels[q] : q;
+        int32_t i = pixel % d->Wc, j = pixel / d->Wc;
+        v3 dir = nrm(mattv(d->Rc, matv(cx.Kc_inv, mk(i + 0.5, j + 0.5, 1.0))));
+        tri_isect h;
+        double m;
+        int prim = closest_hit(d, &cx.sc, cx.cam_o, dir, 1e300, -1, &h, &m);
+        double* o = out + 8 * (size_t)q;
+        for (int k = 0; k < 8; ++k) o[k] = 0.0;
+        if (margin) margin[q] = m;
+        if (prim < 0) continue;
+        v3 v0 = vtx(d, d->F[3 * prim]), v1 = vtx(d, d->F[3 * prim + 1]), v2 = vtx(d, d->F[3 * prim + 2]);
+        v3 n = nrm(cross(sub(v1, v0), sub(v2, v0)));
+        if (dot(n, dir) > 0) n = scl(n, -1.0);
+        const float* uvp = d->UV + 6 * (size_t)prim;
+        double tu = h.b0 * uvp[0] + h.b1 * uvp[2] + h.b2 * uvp[4];
+        double tv = h.b0 * uvp[1] + h.b1 * uvp[3] + h.b2 * uvp[5];
+        bilin tb = tex_lookup(d, tu, tv);
+        fetch3(d->albedo, &tb, o);
+        o[3] = n.x; o[4] = n.y; o[5] = n.z;
+        o[6] = h.t;
+        o[7] = 1.0;
+    }
+    ctx_free(&cx);
 }

@@ -77,6 +77,13 @@ def lib():
         L.orc_threads.argtypes = [C.POINTER(Desc)]
         L.orc_first_hit.argtypes = [C.POINTER(Desc), C.c_int32, C.c_int32, P]
         L.orc_pdf_batch.argtypes = [C.c_int32, P, P, C.c_double, C.c_int64, P, P]
+        L.orc_denoise.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_double, C.c_int32, P]
+        L.orc_denoise_vjp.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_double, C.c_int32, P]
+        L.orc_tv.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P]
+        L.orc_tv.restype = C.c_double
+        L.orc_l1.argtypes = [P, P, C.c_int64, P]
+        L.orc_l1.restype = C.c_double
+        L.orc_gbuffer.argtypes = [C.POINTER(Desc), C.c_int32, P, P, P]
         _lib = L
     return _lib
 
@@ -270,3 +277,64 @@ def pdf_batch(kind, n, wo, r, wi):
     out = np.zeros(wi.shape[0])
     lib().orc_pdf_batch(kind, _p(f(n)), _p(f(wo)), float(r), wi.shape[0], _p(wi), _p(out))
     return out
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, np.float64)
+
+
+def _guide(img, guide, coef):
+    img = _f64(img)
+    H, W = img.shape[:2]
+    guide = _f64(np.zeros((H, W, 0)) if guide is None else guide).reshape(H, W, -1)
+    coef = _f64(np.zeros(0) if coef is None else coef).reshape(-1)
+    if coef.shape[0] != guide.shape[2]:
+        raise ValueError("one guide coefficient per guide channel")
+    return img, guide, coef, H, W
+
+
+def denoise(img, guide, coef, spatial, radius):
+    """Eq. 11: cross-bilateral filter of an H x W x 3 image steered by an H x W x G guide;
+    coef[k] and spatial are the 1 / (2 sigma^2) factors of the weights."""
+    img, guide, coef, H, W = _guide(img, guide, coef)
+    out = np.zeros_like(img)
+    lib().orc_denoise(_p(img), _p(guide), W, H, guide.shape[2], _p(coef), float(spatial), int(radius), _p(out))
+    return out
+
+
+def denoise_vjp(grad, guide, coef, spatial, radius):
+    """Transpose of denoise() (the guide is a constant): cotangent of the input image."""
+    grad, guide, coef, H, W = _guide(grad, guide, coef)
+    out = np.zeros_like(grad)
+    lib().orc_denoise_vjp(_p(grad), _p(guide), W, H, guide.shape[2], _p(coef), float(spatial), int(radius),
+                          _p(out))
+    return out
+
+
+def tv(m):
+    """Eq. 9 regulariser of an h x w (x c) map: (loss, dloss/dm)."""
+    m = _f64(m)
+    h, w = m.shape[:2]
+    c = 1 if m.ndim == 2 else m.shape[2]
+    g = np.zeros_like(m)
+    loss = lib().orc_tv(_p(m), h, w, c, _p(g))
+    return loss, g
+
+
+def l1(a, b):
+    """Eq. 9 data term: (mean |a - b|, d/da)."""
+    a, b = _f64(a), _f64(b)
+    g = np.zeros_like(a)
+    loss = lib().orc_l1(_p(a), _p(b), a.size, _p(g))
+    return loss, g
+
+
+def gbuffer(sc: Scene, pixels=None):
+    """Guide features through each pixel centre: (npix x 8 features, npix margins)."""
+    d = sc.desc()
+    npix = d.Wc * d.Hc if pixels is None else len(pixels)
+    px = None if pixels is None else np.ascontiguousarray(pixels, np.int32)
+    out = np.zeros((npix, 8))
+    margin = np.zeros(npix)
+    lib().orc_gbuffer(C.byref(d), npix, _p(px), _p(out), _p(margin))
+    return out, margin
