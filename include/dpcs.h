@@ -7,6 +7,7 @@
  *
  *   forward rendering   I_c = R(I_p, theta)                       (Eq. 7)
  *   inverse rendering   {I_p, theta} = R^-1(I_c) by gradients      (Eq. 8, 9, 13)
+ *   training objective  L1 data term, map regulariser L(m), denoiser D (Eq. 9, 11)
  *
  * with the projector response E_p = g_p M I_p^gamma_p (Eq. 1; M = I gives Eq. 1
  * exactly), a pinhole projector emitter (Eq. 2, 6), multi-bounce Monte-Carlo light
@@ -192,6 +193,67 @@ DPCS_API dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const d
                             const float* proj_image, const float* grad_image,
                             const float* sample_radiance, const uint32_t* path_records,
                             const dpcs_grads* grads);
+
+/* -------------------------------------------------- training objective */
+
+/* Eq. 9 fits theta by minimising the mean L1 distance between denoised renderings and
+ * captures plus lambda_reg L(m); Eq. 11 denoises the rendering with a cross-bilateral
+ * filter D first.  The paper fixes neither D's window and weights nor L's formula; the
+ * library's readings are stated with each call.  All buffers below are DEVICE pointers
+ * owned by the caller; every call is asynchronous on the context's stream. */
+
+enum { DPCS_DENOISE_MAX_GUIDE = 8, DPCS_DENOISE_MAX_RADIUS = 8 };
+
+typedef struct {
+    int32_t width, height;      /* image size, 1..16384 each */
+    int32_t guide_channels;     /* G, 0..DPCS_DENOISE_MAX_GUIDE */
+    int32_t radius;             /* r: the window is (2r+1) x (2r+1), 0..DPCS_DENOISE_MAX_RADIUS */
+    float spatial;              /* a_s = 1 / (2 sigma_s^2) in 1/pixel^2, >= 0 */
+    float guide[DPCS_DENOISE_MAX_GUIDE]; /* a_k = 1 / (2 sigma_k^2) per guide channel, >= 0 */
+} dpcs_denoise_params;
+
+/* D of Eq. 11 on an H x W x 3 image steered by an H x W x G guide (G = 0: guide may be
+ * NULL):  out_p = sum_q w(p,q) image_q / sum_q w(p,q) over the window around p clipped
+ * to the image, w(p,q) = exp(-a_s |p - q|^2 - sum_k a_k (guide_k(p) - guide_k(q))^2).
+ * The centre weight is 1, so the sum never vanishes.  Guide values must be finite.
+ * out must not overlap image.  FP32 arithmetic. */
+DPCS_API dpcs_status dpcs_denoise(dpcs_context ctx, const dpcs_denoise_params* p, const float* image,
+                                  const float* guide, float* out);
+/* VJP of dpcs_denoise with the same p and guide (the guide is a constant of D, so D is
+ * linear): grad_image_q = sum_p w(p,q) grad_out_p / sum_q' w(p,q'), OVERWRITTEN.
+ * Uses an H x W x 4 float scratch buffer of the context.  grad_image must not overlap
+ * grad_out. */
+DPCS_API dpcs_status dpcs_denoise_vjp(dpcs_context ctx, const dpcs_denoise_params* p, const float* grad_out,
+                                      const float* guide, float* grad_image);
+
+/* Guide features for dpcs_denoise: one camera ray through the centre of each pixel
+ * (Eq. 6 inverted, no jitter), closest hit on the scene.  gbuffer (Hc x Wc x 8 float):
+ * albedo rgb at the hit (bilinear lookup of params->albedo), unit geometric normal
+ * turned toward the camera (xyz), hit distance along the unit ray, 1; all eight are 0
+ * where the ray escapes.  Only the camera, the albedo map and its size are read from
+ * params. */
+DPCS_API dpcs_status dpcs_render_gbuffer(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
+                                         float* gbuffer);
+
+/* L(m) of Eq. 9 for one h x w x c map (c = 1 for roughness or specular, 3 for albedo),
+ * read as the anisotropic L1 total variation:  mean |m(y+1,x) - m(y,x)| over the
+ * c (h-1) w vertical pairs plus mean |m(y,x+1) - m(y,x)| over the c h (w-1) horizontal
+ * pairs (a direction without pairs adds 0).  Sums in FP64 in a fixed order (the result
+ * does not vary between runs); loss (device, 1 float) is written.  h, w, c >= 1,
+ * h w c < 2^31. */
+DPCS_API dpcs_status dpcs_tv_loss(dpcs_context ctx, const float* map, int32_t h, int32_t w, int32_t c,
+                                  float* loss);
+/* grad_map = grad_loss[0] * dL/dm (h x w x c, OVERWRITTEN), with d|x|/dx = sign(x) and
+ * sign(0) = 0; grad_loss is a device scalar (the loss's cotangent). */
+DPCS_API dpcs_status dpcs_tv_vjp(dpcs_context ctx, const float* map, int32_t h, int32_t w, int32_t c,
+                                 const float* grad_loss, float* grad_map);
+
+/* Data term of Eq. 9 for one image pair: loss = mean |a - b| over n values (FP64 sums
+ * in a fixed order; 1 float written).  1 <= n < 2^31. */
+DPCS_API dpcs_status dpcs_l1_loss(dpcs_context ctx, const float* a, const float* b, int64_t n, float* loss);
+/* grad_a = grad_loss[0] * sign(a - b) / n (OVERWRITTEN; sign(0) = 0). */
+DPCS_API dpcs_status dpcs_l1_vjp(dpcs_context ctx, const float* a, const float* b, int64_t n,
+                                 const float* grad_loss, float* grad_a);
 
 /* ------------------------------------------------------------ debug/test */
 

@@ -158,6 +158,8 @@ void launch_debug_intersect(const Launch& l, const float4* nodes4, const float4*
                             const int* leaf_of_prim, int nt, float tmin, const float* rays, int64_t n, int mode,
                             int32_t* prim, float* t, float* b1, float* b2);
 void launch_debug_brdf(const Launch& l, int kind, const double* in, int64_t n, double* out);
+// guide features through the pixel centres (out: Wc x Hc x 8 floats, 16-byte aligned)
+void launch_gbuffer(const Launch& l, const ReqDesc& r, float* out);
 void launch_debug_philox(const Launch& l, uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out);
 
 }  // namespace dpcs

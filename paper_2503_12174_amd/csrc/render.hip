@@ -288,6 +288,34 @@ __global__ void __launch_bounds__(256) k_finalize(Queues q, ReqDesc r, uint32_t 
         }
 }
 
+// ---------------------------------------------------------------- guide features
+// One camera ray through each pixel centre; closest hit through the renderer's BVH with
+// a full LDS stack (no spill region), hit attributes in FP64 as the shading uses them.
+// Per pixel two float4: (albedo rgb, n.x), (n.y, n.z, t, 1); zeros on a miss.
+__global__ void __launch_bounds__(TB) k_gbuffer(ReqDesc r, float4* __restrict__ out) {
+    __shared__ int stack[(MAX_STACK + 1) * TB];
+    const int64_t npix = (int64_t)r.Wc * r.Hc;
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < npix; i += (int64_t)gridDim.x * TB) {
+        const int px = (int)(i % r.Wc), py = (int)(i / r.Wc);
+        const D3 o = d3(r.cam_o[0], r.cam_o[1], r.cam_o[2]);
+        const D3 d = normalize(mat3(r.cam_M, d3(px + 0.5, py + 0.5, 1.0)));
+        Hit h;
+        Visits<false> vis;
+        trace_ray<false, MAX_STACK, TB>(r.nodes4, r.nodes, r.tris, v3((float)o.x, (float)o.y, (float)o.z),
+                                        v3((float)d.x, (float)d.y, (float)d.z), r.tmin, __builtin_inff(), -1, h,
+                                        stack, nullptr, threadIdx.x, vis);
+        float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a;
+        if (h.leaf >= 0) {
+            const Surf s = surface(r, h.leaf, o, d);
+            const double t = dot(s.x - o, d);
+            a = make_float4((float)s.alb.x, (float)s.alb.y, (float)s.alb.z, (float)s.n.x);
+            b = make_float4((float)s.n.y, (float)s.n.z, (float)t, 1.0f);
+        }
+        out[2 * i] = a;
+        out[2 * i + 1] = b;
+    }
+}
+
 // ---------------------------------------------------------------- debug
 // BRDF value and derivatives, bounce density and a bounce sample, on rows of FP64 input
 // (17 per row in, 11 per row out; the layout is the C ABI's)
@@ -426,6 +454,10 @@ void launch_debug_intersect(const Launch& l, const float4* nodes4, const float4*
     if (n <= 0) return;
     hipLaunchKernelGGL(k_debug_intersect, dim3(grid_of(n, TB)), dim3(TB), 0, l.st, nodes4, nodes, tris, leaf_of_prim,
                        nt, tmin, rays, n, mode, prim, t, b1, b2);
+}
+void launch_gbuffer(const Launch& l, const ReqDesc& r, float* out) {
+    const int64_t n = (int64_t)r.Wc * r.Hc;
+    hipLaunchKernelGGL(k_gbuffer, dim3(grid_cap(l, n, TB)), dim3(TB), 0, l.st, r, reinterpret_cast<float4*>(out));
 }
 void launch_debug_brdf(const Launch& l, int kind, const double* in, int64_t n, double* out) {
     if (n > 0) hipLaunchKernelGGL(k_debug_brdf, dim3(grid_of(n, 256)), dim3(256), 0, l.st, kind, in, n, out);

@@ -198,7 +198,7 @@ static bool pinhole_ok(const dpcs_pinhole& p, const char* what, std::string* why
 }
 
 bool fill_desc(dpcs_context, ReqDesc& r, const dpcs_render_params* p, dpcs_scene sc, const float* proj_image,
-               std::string* why) {
+               std::string* why, bool need_proj) {
     std::memset(&r, 0, sizeof r);
     if (!p) return *why = "params is NULL", false;
     if (!pinhole_ok(p->camera, "camera", why) || !pinhole_ok(p->projector, "projector", why)) return false;
@@ -210,7 +210,7 @@ bool fill_desc(dpcs_context, ReqDesc& r, const dpcs_render_params* p, dpcs_scene
         return *why = "tex_w/tex_h must be in 1..16384", false;
     if (p->spp < 1 || p->spp > 65536) return *why = "spp must be in 1..65536", false;
     if (p->max_depth < 1 || p->max_depth > 64) return *why = "max_depth must be in 1..64", false;
-    if (!proj_image) return *why = "proj_image is NULL", false;
+    if (need_proj && !proj_image) return *why = "proj_image is NULL", false;
     if (!p->device_scalars) {
         for (int c = 0; c < 3; ++c) {
             if (!(p->prf_gamma[c] > 0.f) || !(p->crf_gamma[c] > 0.f)) return *why = "gammas must be > 0", false;
@@ -918,6 +918,31 @@ extern "C" dpcs_status dpcs_render(dpcs_context ctx, dpcs_scene scene, const dpc
     if (!make_queues(ctx, "fwd.queues", ppw * r.spp, q, &st)) return st;
     for (int64_t a = 0; a < npix; a += ppw) forward_wave(ctx, q, r, (uint32_t)a, (uint32_t)std::min(npix, a + ppw), true);
     if (!hip_ok(ctx, hipGetLastError(), "kernel launch")) return DPCS_E_DEVICE;
+    ctx->err.clear();
+    return DPCS_OK;
+}
+
+extern "C" dpcs_status dpcs_render_gbuffer(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
+                                           float* gbuffer) {
+    if (!ctx) return DPCS_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (ctx->sticky) return DPCS_E_DEVICE;
+    if (!scene || scene->ctx != ctx) return fail(ctx, DPCS_E_INVALID, "scene is NULL or from another context");
+    if (!gbuffer) return fail(ctx, DPCS_E_INVALID, "gbuffer is NULL");
+    if (reinterpret_cast<uintptr_t>(gbuffer) % 16) return fail(ctx, DPCS_E_INVALID, "gbuffer must be 16-byte aligned");
+    (void)hipGetLastError();
+    ReqDesc r;
+    std::string why;
+    if (!fill_desc(ctx, r, params, scene, nullptr, &why, false)) return fail(ctx, DPCS_E_INVALID, why);
+    if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
+    dpcs_status st = DPCS_OK;
+    float4* tex = (float4*)scratch(ctx, "gbuf.tex", sizeof(float4) * (size_t)r.tw * r.th, &st);
+    if (!tex) return st;
+    Launch l{ctx->stream, ctx->grid_cap};
+    launch_pack_tex(l, r, params->albedo, nullptr, tex);
+    r.tex4 = tex;
+    launch_gbuffer(l, r, gbuffer);
+    if (!hip_ok(ctx, hipGetLastError(), "render_gbuffer")) return DPCS_E_DEVICE;
     ctx->err.clear();
     return DPCS_OK;
 }

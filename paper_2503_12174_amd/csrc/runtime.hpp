@@ -64,8 +64,9 @@ bool hip_ok(dpcs_context ctx, hipError_t e, const char* what);
 // named scratch buffer of at least `bytes` (grows; never shrinks)
 void* scratch(dpcs_context ctx, const char* name, size_t bytes, dpcs_status* st);
 // fills a request descriptor from validated params; false + message on invalid input
+// (need_proj false: the projector image is not read and may be NULL)
 bool fill_desc(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, dpcs_scene sc, const float* proj_image,
-               std::string* why);
+               std::string* why, bool need_proj = true);
 
 // binary BVH by binned SAH on the host (bvh_sah.cpp): nodes in the device layout,
 // child references and the leaf order (leaf l is triangle order[l]); nt >= 2

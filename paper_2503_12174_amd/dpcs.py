@@ -87,12 +87,32 @@ class Request(C.Structure):
                 ("grads", C.POINTER(Grads)), ("request_id", C.c_uint64)]
 
 
+class DenoiseParams(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("guide_channels", C.c_int32), ("radius", C.c_int32),
+                ("spatial", C.c_float), ("guide", C.c_float * 8)]
+
+
+def denoise_params(width: int, height: int, radius: int, spatial: float, guide=()) -> DenoiseParams:
+    """Window radius r, a_s = 1 / (2 sigma_s^2), and a_k = 1 / (2 sigma_k^2) per guide channel."""
+    g = [float(x) for x in guide]
+    if len(g) > 8:
+        raise ValueError("at most 8 guide channels")
+    p = DenoiseParams()
+    p.width, p.height, p.radius, p.spatial = int(width), int(height), int(radius), float(spatial)
+    p.guide_channels = len(g)
+    for k, x in enumerate(g):
+        p.guide[k] = x
+    return p
+
+
 # every symbol the header declares (a test checks the library exports all of them)
 SYMBOLS = ["dpcs_context_create", "dpcs_context_destroy", "dpcs_last_error", "dpcs_context_synchronize",
            "dpcs_context_set_capacity", "dpcs_scene_create", "dpcs_scene_get_info", "dpcs_scene_destroy",
            "dpcs_render", "dpcs_render_vjp", "dpcs_debug_intersect", "dpcs_debug_philox", "dpcs_debug_brdf",
            "dpcs_context_set_profiling", "dpcs_context_get_profile", "dpcs_server_create",
-           "dpcs_server_submit", "dpcs_server_poll", "dpcs_server_stats", "dpcs_server_destroy"]
+           "dpcs_server_submit", "dpcs_server_poll", "dpcs_server_stats", "dpcs_server_destroy",
+           "dpcs_denoise", "dpcs_denoise_vjp", "dpcs_render_gbuffer", "dpcs_tv_loss", "dpcs_tv_vjp",
+           "dpcs_l1_loss", "dpcs_l1_vjp"]
 
 _lib = None
 
@@ -126,6 +146,13 @@ def lib():
             "dpcs_server_poll": ([P, P, P, P, I32], I32),
             "dpcs_server_stats": ([P, P], S),
             "dpcs_server_destroy": ([P], S),
+            "dpcs_denoise": ([P, C.POINTER(DenoiseParams), P, P, P], S),
+            "dpcs_denoise_vjp": ([P, C.POINTER(DenoiseParams), P, P, P], S),
+            "dpcs_render_gbuffer": ([P, P, C.POINTER(RenderParams), P], S),
+            "dpcs_tv_loss": ([P, P, I32, I32, I32, P], S),
+            "dpcs_tv_vjp": ([P, P, I32, I32, I32, P, P], S),
+            "dpcs_l1_loss": ([P, P, P, I64, P], S),
+            "dpcs_l1_vjp": ([P, P, P, I64, P, P], S),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -293,6 +320,41 @@ def dpcs_debug_philox(ctx: Context, seed: int, ctr, out):
 def dpcs_debug_brdf(ctx: Context, brdf: int, inputs, out):
     """inputs: device float64 (n, 17); out: device float64 (n, 11) (layout in dpcs.h)."""
     return ctx.check(lib().dpcs_debug_brdf(ctx.h, int(brdf), _ptr(inputs), int(inputs.shape[0]), _ptr(out)))
+
+
+def dpcs_denoise(ctx: Context, p: DenoiseParams, image, guide, out):
+    return ctx.check(lib().dpcs_denoise(ctx.h, C.byref(p), _ptr(image), _ptr(guide), _ptr(out)))
+
+
+def dpcs_denoise_vjp(ctx: Context, p: DenoiseParams, grad_out, guide, grad_image):
+    return ctx.check(lib().dpcs_denoise_vjp(ctx.h, C.byref(p), _ptr(grad_out), _ptr(guide), _ptr(grad_image)))
+
+
+def dpcs_render_gbuffer(ctx: Context, scene: Scene, params: RenderParams, gbuffer):
+    return ctx.check(lib().dpcs_render_gbuffer(ctx.h, scene.h, C.byref(params), _ptr(gbuffer)))
+
+
+def _map_shape(m):
+    h, w = int(m.shape[0]), int(m.shape[1])
+    return h, w, (1 if m.dim() == 2 else int(m.shape[2]))
+
+
+def dpcs_tv_loss(ctx: Context, m, loss):
+    h, w, c = _map_shape(m)
+    return ctx.check(lib().dpcs_tv_loss(ctx.h, _ptr(m), h, w, c, _ptr(loss)))
+
+
+def dpcs_tv_vjp(ctx: Context, m, grad_loss, grad_m):
+    h, w, c = _map_shape(m)
+    return ctx.check(lib().dpcs_tv_vjp(ctx.h, _ptr(m), h, w, c, _ptr(grad_loss), _ptr(grad_m)))
+
+
+def dpcs_l1_loss(ctx: Context, a, b, loss):
+    return ctx.check(lib().dpcs_l1_loss(ctx.h, _ptr(a), _ptr(b), int(a.numel()), _ptr(loss)))
+
+
+def dpcs_l1_vjp(ctx: Context, a, b, grad_loss, grad_a):
+    return ctx.check(lib().dpcs_l1_vjp(ctx.h, _ptr(a), _ptr(b), int(a.numel()), _ptr(grad_loss), _ptr(grad_a)))
 
 
 class Server:

@@ -33,9 +33,9 @@ def test_struct_layouts_match_the_header():
 #include <stdio.h>
 #include "dpcs.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(dpcs_mesh_desc), sizeof(dpcs_scene_info), sizeof(dpcs_pinhole),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(dpcs_mesh_desc), sizeof(dpcs_scene_info), sizeof(dpcs_pinhole),
          sizeof(dpcs_render_params), sizeof(dpcs_render_aux), sizeof(dpcs_grads), sizeof(dpcs_request),
-         sizeof(dpcs_profile), __builtin_offsetof(dpcs_render_params, seed));
+         sizeof(dpcs_profile), sizeof(dpcs_denoise_params), __builtin_offsetof(dpcs_render_params, seed));
   return 0;
 }
 '''
@@ -47,7 +47,8 @@ int main(void) {
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         got = [int(x) for x in subprocess.check_output([exe]).split()]
     want = [ctypes.sizeof(t) for t in (dpcs.MeshDesc, dpcs.SceneInfo, dpcs.Pinhole, dpcs.RenderParams,
-                                       dpcs.RenderAux, dpcs.Grads, dpcs.Request, dpcs.Profile)]
+                                       dpcs.RenderAux, dpcs.Grads, dpcs.Request, dpcs.Profile,
+                                       dpcs.DenoiseParams)]
     want.append(dpcs.RenderParams.seed.offset)
     assert got == want
 
