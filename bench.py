@@ -10,6 +10,8 @@ Prints ONE JSON line.  Inputs are synthetic and resident in HBM before timing.
   roofline       live HIP-event timing of the dominant kernel (closest-hit
                  traversal) against its algorithmic bytes (HBM bound)
   cpu_baseline   the FP64 CPU oracle timed on a bounded pixel sample
+  objective      the training objective's operators (denoiser D and its VJP, guide
+                 features, L1 data term, map regulariser), timed apart from the step
 """
 from __future__ import annotations
 
@@ -61,7 +63,73 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="skip the profiled passes")
     ap.add_argument("--serving-requests", type=int, default=300, help="0 disables the serving run")
     ap.add_argument("--serving-alone", type=int, default=60, help="requests also timed alone")
+    ap.add_argument("--no-objective", action="store_true", help="skip the training-objective operators")
     return ap.parse_args()
+
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X vector FP32 (packed); the build disables packed FP32: 78.6
+
+
+def objective_bench(ctx, scene, params, image, maps, reps=50):
+    """The training objective's device operators on this workload (Eq. 9, 11): guide
+    features, D and its VJP on the 256 x 256 rendering, L1 against a capture and L(m) of
+    the three BRDF maps with their VJPs, each timed with events on the context's stream
+    (the torch stream it was created on); D alone also on a 2048 x 2048 image, where the
+    launch fills the chip, against its arithmetic model (4G + 9 FP32 flops per window
+    tap: G guide channels of sub, mul, fma; exp2; the weight sum; three fmas)."""
+    import numpy as np
+    import torch
+
+    from paper_2503_12174_amd import dpcs
+    from paper_2503_12174_amd import objective as Ob
+
+    cfg = Ob.DenoiseConfig()
+    H, W = image.shape[:2]
+    guide = Ob.gbuffer(ctx, scene, params)
+    p = cfg.params(W, H, guide.shape[2])
+    den, gimg = torch.empty_like(image), torch.empty_like(image)
+    tgt = torch.as_tensor(np.random.default_rng(8).uniform(0, 1, (H, W, 3)).astype(np.float32)).cuda()
+    loss, gl, gl1 = torch.empty((), device="cuda"), torch.ones((), device="cuda"), torch.empty_like(image)
+    gmaps = [torch.empty_like(m) for m in maps]
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ops = {
+        "gbuffer": lambda: dpcs.dpcs_render_gbuffer(ctx, scene, params, guide),
+        "denoise": lambda: dpcs.dpcs_denoise(ctx, p, image, guide, den),
+        "l1": lambda: dpcs.dpcs_l1_loss(ctx, den, tgt, loss),
+        "l1_vjp": lambda: dpcs.dpcs_l1_vjp(ctx, den, tgt, gl, gl1),
+        "denoise_vjp": lambda: dpcs.dpcs_denoise_vjp(ctx, p, gl1, guide, gimg),
+        "tv_3maps": lambda: [dpcs.dpcs_tv_loss(ctx, m, loss) for m in maps],
+        "tv_vjp_3maps": lambda: [dpcs.dpcs_tv_vjp(ctx, m, gl, g) for m, g in zip(maps, gmaps)],
+    }
+    res = {k: round(timed(f), 5) for k, f in ops.items()}
+    res["objective_step_ms"] = round(sum(v for k, v in res.items() if k != "gbuffer"), 4)
+
+    # D on a 2048 x 2048 image with an 8-channel guide: arithmetic throughput
+    N = 2048
+    g = torch.Generator(device="cuda").manual_seed(9)
+    big = torch.rand((N, N, 3), device="cuda", generator=g)
+    bguide = torch.rand((N, N, 8), device="cuda", generator=g)
+    bout = torch.empty_like(big)
+    bp = cfg.params(N, N, 8)
+    ms = timed(lambda: dpcs.dpcs_denoise(ctx, bp, big, bguide, bout))
+    r = cfg.radius
+    taps = float(N * (2 * r + 1) - r * (r + 1)) ** 2   # window taps summed over pixels (clipped at borders)
+    flops = taps * (4 * 8 + 9)
+    tf = flops / (ms * 1e-3) / 1e12
+    res["denoise_2048"] = {"ms": round(ms, 4), "taps_per_s": round(taps / (ms * 1e-3), 1),
+                           "bound": "alu", "achieved": round(tf, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4)}
+    return res
 
 
 def serving_bench(ctx, n_req, n_alone, warmup=20, rate=50.0):
@@ -299,6 +367,12 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
 
+    objective = None
+    if not a.no_objective:
+        objective = objective_bench(ctx, scene, params, out, (alb, rough, spec))
+        print(f"[bench] objective {objective['objective_step_ms']} ms per step; D at 2048^2 "
+              f"{objective['denoise_2048']['ms']} ms", file=sys.stderr, flush=True)
+
     serving = None
     if a.serving_requests > 0:
         serving = serving_bench(ctx, a.serving_requests, a.serving_alone)
@@ -342,7 +416,7 @@ def main():
         "fwd_samples_per_s": round(fwd_sps, 1), "fwd_ms": round(ms_fwd, 4),
         "fwd_adj_samples_per_s": round(step_sps, 1),
         "fwd_adj_retrace_samples_per_s": round(rt_sps, 1), "fwd_adj_retrace_ms": round(ms_rt, 4),
-        "roofline": roof, "cpu_baseline": cpu, "serving": serving, "stages": stages,
+        "roofline": roof, "cpu_baseline": cpu, "serving": serving, "stages": stages, "objective": objective,
     }
     print(json.dumps(line))
 

@@ -3,8 +3,12 @@
 compensate()  projector compensation, Eq. 13: find I_p whose rendering matches a
               target camera image, by Adam on an L2 loss, I_p clamped to [0, 1]
 fit()         scene-parameter fit, Eq. 9: BRDF maps and PRF/CRF scalars from image
-              pairs, L2 loss, with the paper's constraints on gamma_p, gamma_c, w
-              (Sec. 3.2: gamma_p in [2, 3], gamma_c in [1/3, 1], w in (0.2, 2.5))
+              pairs, with the paper's constraints on gamma_p, gamma_c, w
+              (Sec. 3.2: gamma_p in [2, 3], gamma_c in [1/3, 1], w in (0.2, 2.5));
+              objective "l2": mean squared error of the raw renderings; "paper": Eq. 9
+              as written, the L1 distance of denoised renderings (Eq. 11, guided by the
+              scene's first-hit features under the current albedo) plus tv_weight times
+              the total variation of the three BRDF maps
 Each optimisation step uses its own Philox seed (base seed + step), so a run is
 reproducible and resumable from any step.
 """
@@ -14,6 +18,8 @@ import copy
 
 import torch
 
+from . import dpcs
+from . import objective as Ob
 from .autograd import render, scalars_from
 
 
@@ -34,7 +40,7 @@ def compensate(ctx, scene, cfg, target, albedo, roughness, specular, steps=100, 
         opt.step()
         with torch.no_grad():
             ip.clamp_(0.0, 1.0)
-        losses.append(float(loss))
+        losses.append(float(loss.detach()))
         if callback:
             callback(k, losses[-1], ip)
     return ip.detach(), losses
@@ -48,8 +54,11 @@ def project_constraints(scal: torch.Tensor, clamp_gamma_p=True):
         scal[15:18].clamp_(0.2 + 1e-4, 2.5 - 1e-4)
 
 
-def fit(ctx, scene, cfg, images, targets, steps=50, lr=0.02, base_seed=0, clamp_gamma_p=True, init=None):
+def fit(ctx, scene, cfg, images, targets, steps=50, lr=0.02, base_seed=0, clamp_gamma_p=True, init=None,
+        objective="l2", tv_weight=0.0, denoise: Ob.DenoiseConfig | None = None):
     """Fit albedo/roughness/specular maps and the 18 response scalars to (image, target) pairs."""
+    if objective not in ("l2", "paper"):
+        raise ValueError("objective must be 'l2' or 'paper'")
     th, tw = cfg.albedo.shape[:2]
     dev = lambda x: torch.as_tensor(x, dtype=torch.float32, device="cuda").clone().requires_grad_(True)
     init = init or {}
@@ -63,10 +72,18 @@ def fit(ctx, scene, cfg, images, targets, steps=50, lr=0.02, base_seed=0, clamp_
         c = copy.copy(cfg)
         c.seed = base_seed + k
         loss = 0.0
+        guide = None
+        if objective == "paper":   # guide features under the current albedo (a constant of D)
+            guide = Ob.gbuffer(ctx, scene, dpcs.params_from(c, alb.detach(), rough.detach(), spec.detach()))
         for ip, tgt in zip(images, targets):
             out = render(ctx, scene, c, ip, alb, rough, spec, scal)
-            loss = loss + ((out - tgt) ** 2).mean()
+            if objective == "paper":
+                loss = loss + Ob.l1(ctx, Ob.denoise(ctx, out, guide, denoise), tgt)
+            else:
+                loss = loss + ((out - tgt) ** 2).mean()
         loss = loss / len(images)
+        if tv_weight:
+            loss = loss + tv_weight * (Ob.tv(ctx, alb) + Ob.tv(ctx, rough) + Ob.tv(ctx, spec))
         opt.zero_grad()
         loss.backward()
         opt.step()
@@ -75,5 +92,5 @@ def fit(ctx, scene, cfg, images, targets, steps=50, lr=0.02, base_seed=0, clamp_
             rough.clamp_(0.05, 1.0)
             spec.clamp_(0.0, 1.0)
         project_constraints(scal, clamp_gamma_p)
-        losses.append(float(loss))
+        losses.append(float(loss.detach()))
     return dict(albedo=alb.detach(), roughness=rough.detach(), specular=spec.detach(), scalars=scal.detach()), losses

@@ -56,22 +56,53 @@ def test_compensation_reduces_the_loss():
     assert float(ip.min()) >= 0.0 and float(ip.max()) <= 1.0
 
 
+_FIT = {}
+
+
+def _fit_problem():
+    """Targets rendered by the FP64 oracle from hidden maps and responses (cached)."""
+    if not _FIT:
+        truth = synth.fit_truth(301)
+        imgs = synth.fit_images(0, count=2)
+        targets = []
+        for im in imgs:
+            tw = synth.fit_scene(spp=64)
+            for k, v in truth.items():
+                setattr(tw, {"roughness": "roughness", "specular": "specular"}.get(k, k), v)
+            targets.append(O.render(O.Scene(tw, proj_image=im), want=("Ic",))["Ic"].reshape(64, 64, 3))
+        _FIT.update(imgs=imgs, targets=targets)
+    return _FIT["imgs"], _FIT["targets"]
+
+
 def test_scene_fit_reduces_the_loss_on_oracle_targets():
-    """Eq. 9 scene-parameter fit: targets rendered by the FP64 oracle from hidden maps and
-    responses, fitted from the initial guess with fwd + VJP steps."""
+    """Eq. 9 scene-parameter fit from the initial guess with fwd + VJP steps."""
     import torch
     from paper_2503_12174_amd import drivers, dpcs
-    truth = synth.fit_truth(301)
+    imgs, targets = _fit_problem()
     w = synth.fit_scene(spp=8)
-    imgs = synth.fit_images(0, count=2)
-    targets = []
-    for im in imgs:
-        tw = synth.fit_scene(spp=64)
-        for k, v in truth.items():
-            setattr(tw, {"roughness": "roughness", "specular": "specular"}.get(k, k), v)
-        targets.append(O.render(O.Scene(tw, proj_image=im), want=("Ic",))["Ic"].reshape(64, 64, 3))
     scene = dpcs.Scene(ctx(), w.mesh)
     f = torch.float32
     params, losses = drivers.fit(ctx(), scene, w, [dev(i, f) for i in imgs], [dev(t, f) for t in targets],
                                  steps=25, lr=0.03, clamp_gamma_p=False)
     assert losses[-1] < 0.5 * losses[0], losses
+
+
+def test_scene_fit_with_the_papers_objective():
+    """Eq. 9 as written: L1 of denoised renderings (Eq. 11) + lambda_reg L(m).  The loss
+    falls, and a large lambda_reg leaves smoother maps than lambda_reg = 0."""
+    import torch
+    from paper_2503_12174_amd import drivers, dpcs
+    from paper_2503_12174_amd import objective as Ob
+    imgs, targets = _fit_problem()
+    w = synth.fit_scene(spp=8)
+    scene = dpcs.Scene(ctx(), w.mesh)
+    f = torch.float32
+    tv = {}
+    for lam in (0.0, 0.05):
+        params, losses = drivers.fit(ctx(), scene, w, [dev(i, f) for i in imgs], [dev(t, f) for t in targets],
+                                     steps=25, lr=0.03, clamp_gamma_p=False, objective="paper", tv_weight=lam)
+        assert all(np.isfinite(losses))
+        # the maps start constant (L(m) = 0), so with lambda_reg > 0 the total falls less
+        assert losses[-1] < (0.8 if lam == 0.0 else 0.95) * losses[0], (lam, losses)
+        tv[lam] = sum(float(Ob.tv(ctx(), params[k])) for k in ("albedo", "roughness", "specular"))
+    assert tv[0.05] < tv[0.0], tv

@@ -53,6 +53,13 @@ def _vjp_bound(r, scale):
     return (4 * n * n + 8 * n) * U32 * scale
 
 
+def _tol(bound, want):
+    """Both the derived worst-case bound and the path's stated bar, 1e-4 relative to the
+    output's scale, must hold (the bound of D^T grows as n^2 and is the looser one from
+    r = 2 on; measured errors are ~5e-7 relative)."""
+    return min(bound, 1e-4 * np.abs(want).max())
+
+
 CASES = [  # (H, W, G, r): ragged tiles, several tiles, every guide packing, radius 0..8
     (1, 1, 0, 2),
     (5, 3, 1, 0),
@@ -86,7 +93,7 @@ def test_denoise_matches_oracle(H, W, G, r):
     sp = float(np.float32(0.2))
     got = _denoise_dev(img, guide, coef, sp, r)
     want = O.denoise(img, guide, coef, sp, r)
-    np.testing.assert_allclose(got, want, rtol=0, atol=_fwd_bound(r, np.abs(img).max()))
+    np.testing.assert_allclose(got, want, rtol=0, atol=_tol(_fwd_bound(r, np.abs(img).max()), want))
 
 
 @pytest.mark.parametrize("H,W,G,r", CASES)
@@ -96,7 +103,7 @@ def test_denoise_vjp_matches_oracle(H, W, G, r):
     sp = float(np.float32(0.2))
     got = _denoise_dev(G_, guide, coef, sp, r, vjp=True)
     want = O.denoise_vjp(G_, guide, coef, sp, r)
-    np.testing.assert_allclose(got, want, rtol=0, atol=_vjp_bound(r, np.abs(G_).max()))
+    np.testing.assert_allclose(got, want, rtol=0, atol=_tol(_vjp_bound(r, np.abs(G_).max()), want))
 
 
 def test_denoise_adjoint_identity_at_scale():
@@ -116,7 +123,7 @@ def test_denoise_adjoint_identity_at_scale():
     y0, x0, h, w = 300, 500, 24, 40
     crop = O.denoise(img[y0 - r:y0 + h + r, x0 - r:x0 + w + r], guide[y0 - r:y0 + h + r, x0 - r:x0 + w + r],
                      coef, sp, r)[r:-r, r:-r]
-    np.testing.assert_allclose(a[y0:y0 + h, x0:x0 + w], crop, rtol=0, atol=_fwd_bound(r, 1.0))
+    np.testing.assert_allclose(a[y0:y0 + h, x0:x0 + w], crop, rtol=0, atol=_tol(_fwd_bound(r, 1.0), crop))
 
 
 def test_denoise_rejects_bad_params():
@@ -275,4 +282,4 @@ def test_objective_functions_backpropagate():
     dd = _denoise_dev(img, guide, coef, sp, cfg.radius)
     assert np.array_equal(np.sign(dd - tgt), np.sign(d - tgt))
     gx = O.denoise_vjp(g1, guide, coef, sp, cfg.radius)
-    np.testing.assert_allclose(x.grad.cpu().numpy(), gx, rtol=0, atol=_vjp_bound(cfg.radius, np.abs(g1).max()))
+    np.testing.assert_allclose(x.grad.cpu().numpy(), gx, rtol=0, atol=_tol(_vjp_bound(cfg.radius, np.abs(g1).max()), gx))
