@@ -12,6 +12,8 @@ Prints ONE JSON line.  Inputs are synthetic and resident in HBM before timing.
   cpu_baseline   the FP64 CPU oracle timed on a bounded pixel sample
   objective      the training objective's operators (denoiser D and its VJP, guide
                  features, L1 data term, map regulariser), timed apart from the step
+  configs        the other synthetic setups end to end (quad+cube forward, 200k-triangle
+                 512^2 forward and fwd+VJP, 100 compensation steps, a scene-fit step)
 """
 from __future__ import annotations
 
@@ -64,6 +66,7 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=300, help="0 disables the serving run")
     ap.add_argument("--serving-alone", type=int, default=60, help="requests also timed alone")
     ap.add_argument("--no-objective", action="store_true", help="skip the training-objective operators")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other setups (quad+cube, 200k corner, fit)")
     return ap.parse_args()
 
 
@@ -129,6 +132,93 @@ def objective_bench(ctx, scene, params, image, maps, reps=50):
     res["denoise_2048"] = {"ms": round(ms, 4), "taps_per_s": round(taps / (ms * 1e-3), 1),
                            "bound": "alu", "achieved": round(tf, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
                            "unit": "TFLOP/s", "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4)}
+    return res
+
+
+def configs_bench(ctx, steps=5):
+    """The other synthetic setups, timed end to end (context beside the headline step):
+    the oracle-scale quad-and-cube forward, the 200k-triangle 512^2 compensation-scale
+    forward and forward + VJP step at 16 spp, 100 Adam steps of projector compensation
+    on it, and one scene-fit step (8 image pairs, 32 spp forward + VJP each)."""
+    import copy
+
+    import numpy as np
+    import torch
+
+    from paper_2503_12174_amd import drivers, dpcs, synth
+
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.float32)).cuda()
+
+    def wall(fn, k):
+        fn()
+        ctx.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        ctx.synchronize()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / k
+
+    res = {}
+    # quad + cube, 64^2, 4 spp, depth 3 (launch-bound: a render is ~16k samples)
+    w = synth.quad_cube()
+    sc = dpcs.Scene(ctx, w.mesh)
+    alb, rough, spec, proj = dev(w.albedo), dev(w.roughness), dev(w.specular), dev(w.proj_image)
+    p = dpcs.params_from(w, alb, rough, spec)
+    out = torch.zeros((64, 64, 3), device="cuda")
+    ms = wall(lambda: dpcs.dpcs_render(ctx, sc, p, proj, out), 50)
+    res["quad_cube_forward"] = {"ms": round(ms, 4), "samples_per_s": round(64 * 64 * w.spp / (ms * 1e-3), 1)}
+
+    # 200k-triangle corner, 512^2 camera and projector, 16 spp, depth 4
+    w = synth.corner_200k()
+    sc = dpcs.Scene(ctx, w.mesh, bvh="sah")
+    alb, rough, spec, proj = dev(w.albedo), dev(w.roughness), dev(w.specular), dev(w.proj_image)
+    p = dpcs.params_from(w, alb, rough, spec)
+    H, W = w.camera.height, w.camera.width
+    n = H * W * w.spp
+    out = torch.zeros((H, W, 3), device="cuda")
+    Ls = torch.zeros((H, W, w.spp, 3), device="cuda")
+    rec = torch.zeros((H, W, w.spp, w.max_depth), dtype=torch.int32, device="cuda")
+    G = dev(np.random.default_rng(11).normal(size=(H, W, 3)))
+    grads = dict(d_proj_image=torch.zeros_like(proj), d_albedo=torch.zeros_like(alb),
+                 d_roughness=torch.zeros_like(rough), d_specular=torch.zeros_like(spec),
+                 d_scalars=torch.zeros(18, device="cuda"))
+
+    def step():
+        dpcs.dpcs_render(ctx, sc, p, proj, out, sample_radiance=Ls, path_records=rec)
+        dpcs.dpcs_render_vjp(ctx, sc, p, proj, G, sample_radiance=Ls, path_records=rec, **grads)
+
+    ms_f = wall(lambda: dpcs.dpcs_render(ctx, sc, p, proj, out), steps)
+    ms_s = wall(step, steps)
+    res["corner_200k_512px_16spp"] = {"triangles": int(sc.info().num_triangles),
+                                      "forward_ms": round(ms_f, 4), "forward_samples_per_s": round(n / (ms_f * 1e-3), 1),
+                                      "fwd_vjp_ms": round(ms_s, 4), "fwd_vjp_samples_per_s": round(n / (ms_s * 1e-3), 1)}
+    del Ls, rec
+    # projector compensation: 100 Adam steps (lr 0.01) of fwd + VJP at 16 spp
+    tgt = dev(synth.compensation_target(512))
+    drivers.compensate(ctx, sc, w, tgt, alb, rough, spec, steps=3, lr=0.01)   # scratch and allocator warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, losses = drivers.compensate(ctx, sc, w, tgt, alb, rough, spec, steps=100, lr=0.01)
+    torch.cuda.synchronize()
+    res["compensation_100_steps"] = {"s": round(time.perf_counter() - t0, 3),
+                                     "loss_first_last": [round(losses[0], 5), round(losses[-1], 5)]}
+    del sc
+
+    # scene fit step: 8 pairs at 64^2, 32 spp, GGX maps and 18 scalars
+    w = synth.fit_scene(spp=32)
+    sc = dpcs.Scene(ctx, w.mesh)
+    imgs = [dev(i) for i in synth.fit_images(0, 8)]
+    tg = [dev(np.random.default_rng(40 + k).uniform(0, 1, (64, 64, 3))) for k in range(8)]
+    c = copy.copy(w)
+    drivers.fit(ctx, sc, c, imgs, tg, steps=2, lr=0.02)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    drivers.fit(ctx, sc, c, imgs, tg, steps=10, lr=0.02)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / 10
+    res["fit_step_8x64px_32spp"] = {"ms": round(ms, 3), "samples_per_s": round(8 * 64 * 64 * 32 / (ms * 1e-3), 1)}
     return res
 
 
@@ -373,6 +463,11 @@ def main():
         print(f"[bench] objective {objective['objective_step_ms']} ms per step; D at 2048^2 "
               f"{objective['denoise_2048']['ms']} ms", file=sys.stderr, flush=True)
 
+    configs = None
+    if not a.no_configs:
+        configs = configs_bench(ctx)
+        print(f"[bench] configs {json.dumps(configs)}", file=sys.stderr, flush=True)
+
     serving = None
     if a.serving_requests > 0:
         serving = serving_bench(ctx, a.serving_requests, a.serving_alone)
@@ -417,6 +512,7 @@ def main():
         "fwd_adj_samples_per_s": round(step_sps, 1),
         "fwd_adj_retrace_samples_per_s": round(rt_sps, 1), "fwd_adj_retrace_ms": round(ms_rt, 4),
         "roofline": roof, "cpu_baseline": cpu, "serving": serving, "stages": stages, "objective": objective,
+        "configs": configs,
     }
     print(json.dumps(line))
 
