@@ -433,8 +433,12 @@ template <bool UNI, bool PROF>
 __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_adj_shadow(Queues q, AdjQueues aq, int which, int nxt, ReqDesc uni,
                                                    const ReqDesc* __restrict__ table) {
     __shared__ int stack[(SHORT_STACK + 1) * TB];
+    __shared__ float4 ltop[UNI ? 8 * TOP_NODES : 1];
     int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL;
     const uint32_t n = q.cnt[2 + which];
+    TopNodes top{nullptr, 0u};
+    if constexpr (UNI)   // one tree for the whole launch: stage its top levels
+        if (uni.nodes4) top = stage_top<TB>(ltop, uni.nodes4, uni.top_nodes);
     // the loop bound is uniform per workgroup so every lane reaches the wave-level scatter
     for (uint32_t base = blockIdx.x * TB; base < n; base += gridDim.x * TB) {
         const uint32_t i = base + threadIdx.x;
@@ -447,7 +451,7 @@ __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_adj_shadow(Queues q,
             Hit h;
             Visits<PROF> vis;
             occ = trace_ray<true, SHORT_STACK, TB>(r.nodes4, r.nodes, r.tris, xyz(o), xyz(d), r.tmin, q.st[which][i],
-                                                  __float_as_int(d.w), h, stack, spill, threadIdx.x, vis);
+                                                  __float_as_int(d.w), h, stack, spill, threadIdx.x, vis, top);
             if constexpr (PROF)
                 if (q.stats) {
                     atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);

@@ -22,6 +22,7 @@ constexpr double PI = 3.14159265358979323846;
 constexpr double P_SPEC = 0.25;     // probability of sampling the GGX lobe
 constexpr double ALPHA_MIN = 1e-3;  // GGX alpha floor
 constexpr int MAX_STACK = 64;       // traversal stack entries a ray may hold (checked per scene)
+constexpr int TOP_NODES = 32;       // top 4-wide nodes a traversal workgroup stages in LDS
 
 // ---------------------------------------------------------------------------
 // vectors
@@ -149,6 +150,7 @@ struct ReqDesc {
     const float4* nodes;     // binary BVH (4 float4 per node)
     const float4* nodes4;    // 4-wide BVH (8 float4 per node), or null: traverse the binary one
     const float4* tris;      // 3 float4 per leaf: v0 (w = prim id bits), v1, v2
+    int32_t top_nodes;       // leading 4-wide nodes (breadth-first order) staged in LDS, <= TOP_NODES
     const float4* tri_uv;    // 2 float4 per leaf: (u0 v0 u1 v1), (u2 v2 - -)
     const float4* emission;  // per leaf (rgb, -) or null
     float tmin;

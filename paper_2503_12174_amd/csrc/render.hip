@@ -81,8 +81,12 @@ __global__ void k_raygen(Queues q, ReqDesc r, int slot, uint32_t g0, uint32_t n)
 template <bool UNI, bool PROF>
 __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_trace(Queues q, int cur, ReqDesc uni, const ReqDesc* __restrict__ table) {
     __shared__ int stack[(SHORT_STACK + 1) * TB];
+    __shared__ float4 ltop[UNI ? 8 * TOP_NODES : 1];
     int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL;
     const uint32_t n = q.cnt[cur];
+    TopNodes top{nullptr, 0u};
+    if constexpr (UNI)   // one tree for the whole launch: stage its top levels
+        if (uni.nodes4) top = stage_top<TB>(ltop, uni.nodes4, uni.top_nodes);
     for (uint32_t i = blockIdx.x * TB + threadIdx.x; i < n; i += gridDim.x * TB) {
         const PathO o = nt_ld(&q.po[cur][i]);
         const PathD d = nt_ld(&q.pd[cur][i]);
@@ -91,7 +95,7 @@ __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_trace(Queues q, int 
         Visits<PROF> vis;
         trace_ray<false, SHORT_STACK, TB>(r.nodes4, r.nodes, r.tris, v3((float)o.x, (float)o.y, (float)o.z),
                                          v3((float)d.x, (float)d.y, (float)d.z), r.tmin, __builtin_inff(), o.skip,
-                                         h, stack, spill, threadIdx.x, vis);
+                                         h, stack, spill, threadIdx.x, vis, top);
         __builtin_nontemporal_store(h.leaf, &q.hit[i]);
         if constexpr (PROF)
             if (q.stats) {
@@ -222,15 +226,19 @@ template <bool UNI, bool PROF>
 __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_shadow(Queues q, int which, int depth, ReqDesc uni,
                                                const ReqDesc* __restrict__ table) {
     __shared__ int stack[(SHORT_STACK + 1) * TB];
+    __shared__ float4 ltop[UNI ? 8 * TOP_NODES : 1];
     int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL;
     const uint32_t n = q.cnt[2 + which];
+    TopNodes top{nullptr, 0u};
+    if constexpr (UNI)
+        if (uni.nodes4) top = stage_top<TB>(ltop, uni.nodes4, uni.top_nodes);
     for (uint32_t i = blockIdx.x * TB + threadIdx.x; i < n; i += gridDim.x * TB) {
         const float4 o = nt_ld(&q.so[which][i]), d = nt_ld(&q.sd[which][i]);
         const ReqDesc& r = sel<UNI>(uni, table, __float_as_int(o.w));
         Hit h;
         Visits<PROF> vis;
         const bool occ = trace_ray<true, SHORT_STACK, TB>(r.nodes4, r.nodes, r.tris, xyz(o), xyz(d), r.tmin, nt_ld(&q.st[which][i]),
-                                                         __float_as_int(d.w), h, stack, spill, threadIdx.x, vis);
+                                                         __float_as_int(d.w), h, stack, spill, threadIdx.x, vis, top);
         if constexpr (PROF)
             if (q.stats) {
                 atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <deque>
 #include <vector>
 
 using namespace dpcs;
@@ -243,6 +244,7 @@ bool fill_desc(dpcs_context, ReqDesc& r, const dpcs_render_params* p, dpcs_scene
     r.nodes = sc->nodes;
     r.nodes4 = sc->nodes4;
     r.tris = sc->tris;
+    r.top_nodes = sc->nodes4 ? std::min(TOP_NODES, sc->nnodes4) : 0;
     r.tri_uv = sc->tri_uv;
     r.emission = sc->emission;
     r.tmin = sc->tmin;
@@ -393,12 +395,14 @@ static std::vector<float4> collapse4(const std::vector<float4>& bn, int nt, int&
     struct Work {
         int bin, node, acc, depth;
     };
-    std::vector<Work> work{{0, alloc(), 0, 1}};
+    // first in, first out: nodes are numbered level by level, so the top of the tree is
+    // the leading block of nodes (what a traversal workgroup stages in LDS)
+    std::deque<Work> work{{0, alloc(), 0, 1}};
     stack_bound = 0;
     depth4 = 0;
     while (!work.empty()) {
-        const Work w = work.back();
-        work.pop_back();
+        const Work w = work.front();
+        work.pop_front();
         std::vector<Kid> kids{kid(w.bin, 0), kid(w.bin, 1)};
         while (kids.size() < 4) {
             int best = -1;

@@ -316,10 +316,27 @@ __device__ __forceinline__ float box4_enter(const Box4Ray& r, float nx, float ny
 // Same query on the 4-wide BVH: per node, four box tests; leaf children are tested at
 // once, internal children still in range are visited nearest first (the others pushed,
 // farthest first).  The host only builds a BVH4 whose worst-case stack fits MAX_STACK.
+// The top of the 4-wide tree in LDS: the host numbers nodes breadth first, so nodes
+// [0, n) are its top levels; a workgroup copies them once and every ray that passes
+// them reads LDS instead of L2.  bytes = 128 n (0: nothing staged).
+struct TopNodes {
+    const float4* lds;
+    uint32_t bytes;
+};
+
+
+// all threads of the workgroup call it (it ends with a barrier); n <= TOP_NODES
+template <int TBK>
+__device__ __forceinline__ TopNodes stage_top(float4* lds, const float4* __restrict__ nodes4, int n) {
+    for (int k = threadIdx.x; k < 8 * n; k += TBK) lds[k] = nodes4[k];
+    __syncthreads();
+    return TopNodes{lds, 128u * (uint32_t)n};
+}
+
 template <bool ANY, int SHORT, int TBK, class VIS>
 __device__ __forceinline__ bool traverse4(const float4* __restrict__ nodes, const float4* __restrict__ tris, V3 o,
                                           V3 d, float tmin, float tmax, int skip, Hit& h, int* stack, int* spill,
-                                          int lane, VIS& vis) {
+                                          int lane, VIS& vis, TopNodes top) {
     const Box4Ray br = box4_setup(o, d);
     const WtRay wr = wt_setup(o, d);
     float best_t = tmax;
@@ -335,15 +352,32 @@ __device__ __forceinline__ bool traverse4(const float4* __restrict__ nodes, cons
         // 32-bit byte offsets from the tree's base (the host keeps 128 x nodes < 2^32),
         // so each load is base + one 32-bit register
         const uint32_t nb = (uint32_t)node * 128u;
-        const char* base = reinterpret_cast<const char*>(nodes);
         const uint32_t ax = nb | br.onx, ay = nb | br.ony, az = nb | br.onz;
-        const float4 nx = *reinterpret_cast<const float4*>(base + ax);
-        const float4 ny = *reinterpret_cast<const float4*>(base + ay);
-        const float4 nz = *reinterpret_cast<const float4*>(base + az);
-        const float4 fx = *reinterpret_cast<const float4*>(base + (ax ^ FAR_X));
-        const float4 fy = *reinterpret_cast<const float4*>(base + (ay ^ FAR_Y));
-        const float4 fz = *reinterpret_cast<const float4*>(base + (az ^ FAR_Z));
-        const int4 cr = *reinterpret_cast<const int4*>(base + (nb + 96u));
+        float4 nx, ny, nz, fx, fy, fz;
+        int4 cr;
+        // the empty asm ends the LDS branch differently from the global one: otherwise the
+        // compiler sinks the two sets of loads into one generic (flat) load of a selected
+        // address, which is slower for the global case
+        if (nb < top.bytes) {   // staged top levels: same byte offsets from the LDS copy
+            const char* lb = reinterpret_cast<const char*>(top.lds);
+            nx = *reinterpret_cast<const float4*>(lb + ax);
+            ny = *reinterpret_cast<const float4*>(lb + ay);
+            nz = *reinterpret_cast<const float4*>(lb + az);
+            fx = *reinterpret_cast<const float4*>(lb + (ax ^ FAR_X));
+            fy = *reinterpret_cast<const float4*>(lb + (ay ^ FAR_Y));
+            fz = *reinterpret_cast<const float4*>(lb + (az ^ FAR_Z));
+            cr = *reinterpret_cast<const int4*>(lb + (nb + 96u));
+            asm volatile("");
+        } else {
+            const char* base = reinterpret_cast<const char*>(nodes);
+            nx = *reinterpret_cast<const float4*>(base + ax);
+            ny = *reinterpret_cast<const float4*>(base + ay);
+            nz = *reinterpret_cast<const float4*>(base + az);
+            fx = *reinterpret_cast<const float4*>(base + (ax ^ FAR_X));
+            fy = *reinterpret_cast<const float4*>(base + (ay ^ FAR_Y));
+            fz = *reinterpret_cast<const float4*>(base + (az ^ FAR_Z));
+            cr = *reinterpret_cast<const int4*>(base + (nb + 96u));
+        }
         const int cc[4] = {cr.x, cr.y, cr.z, cr.w};
         float tc[4];
         tc[0] = box4_enter(br, nx.x, ny.x, nz.x, fx.x, fy.x, fz.x, tmin, best_t);
@@ -449,8 +483,10 @@ __device__ __forceinline__ bool traverse4(const float4* __restrict__ nodes, cons
 template <bool ANY, int SHORT, int TBK, class VIS>
 __device__ __forceinline__ bool trace_ray(const float4* __restrict__ nodes4, const float4* __restrict__ nodes,
                                           const float4* __restrict__ tris, V3 o, V3 d, float tmin, float tmax,
-                                          int skip, Hit& h, int* stack, int* spill, int lane, VIS& vis) {
-    if (nodes4) return traverse4<ANY, SHORT, TBK>(nodes4, tris, o, d, tmin, tmax, skip, h, stack, spill, lane, vis);
+                                          int skip, Hit& h, int* stack, int* spill, int lane, VIS& vis,
+                                          TopNodes top = TopNodes{nullptr, 0u}) {
+    if (nodes4)
+        return traverse4<ANY, SHORT, TBK>(nodes4, tris, o, d, tmin, tmax, skip, h, stack, spill, lane, vis, top);
     return traverse<ANY, SHORT, TBK>(nodes, tris, o, d, tmin, tmax, skip, h, stack, spill, lane, vis);
 }
 
