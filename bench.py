@@ -139,7 +139,8 @@ def configs_bench(ctx, steps=5):
     """The other synthetic setups, timed end to end (context beside the headline step):
     the oracle-scale quad-and-cube forward, the 200k-triangle 512^2 compensation-scale
     forward and forward + VJP step at 16 spp, 100 Adam steps of projector compensation
-    on it, and one scene-fit step (8 image pairs, 32 spp forward + VJP each)."""
+    on it, a relighting render at the paper's capture resolutions, and one scene-fit
+    step (8 image pairs, 32 spp forward + VJP each)."""
     import copy
 
     import numpy as np
@@ -199,11 +200,27 @@ def configs_bench(ctx, steps=5):
     tgt = dev(synth.compensation_target(512))
     drivers.compensate(ctx, sc, w, tgt, alb, rough, spec, steps=3, lr=0.01)   # scratch and allocator warm-up
     torch.cuda.synchronize()
+    stamps = []
     t0 = time.perf_counter()
-    _, losses = drivers.compensate(ctx, sc, w, tgt, alb, rough, spec, steps=100, lr=0.01)
+    _, losses = drivers.compensate(ctx, sc, w, tgt, alb, rough, spec, steps=100, lr=0.01,
+                                   callback=lambda k, l, ip: stamps.append(time.perf_counter()))
     torch.cuda.synchronize()
     res["compensation_100_steps"] = {"s": round(time.perf_counter() - t0, 3),
+                                     "median_step_ms": round(float(np.median(np.diff(stamps))) * 1e3, 3),
                                      "loss_first_last": [round(losses[0], 5), round(losses[-1], 5)]}
+    del sc
+
+    # relighting render at the paper's capture resolutions (camera 640x360, projector
+    # 800x600, 16 spp): the paper's own figure for one such render is 2.48 s on an
+    # RTX 3090 (real scene, render resolution unstated) -- context, not a like-for-like
+    w = synth.corner_capture_res()
+    sc = dpcs.Scene(ctx, w.mesh, bvh="sah")
+    alb, rough, spec, proj = dev(w.albedo), dev(w.roughness), dev(w.specular), dev(w.proj_image)
+    p = dpcs.params_from(w, alb, rough, spec)
+    out = torch.zeros((w.camera.height, w.camera.width, 3), device="cuda")
+    ms = wall(lambda: dpcs.dpcs_render(ctx, sc, p, proj, out), steps)
+    n = w.camera.width * w.camera.height * w.spp
+    res["relight_640x360_proj800x600_16spp"] = {"ms": round(ms, 4), "samples_per_s": round(n / (ms * 1e-3), 1)}
     del sc
 
     # scene fit step: 8 pairs at 64^2, 32 spp, GGX maps and 18 scalars

@@ -407,6 +407,18 @@ def corner_50k(spp: int = 64, max_depth: int = 4, seed: int = 0, env: float = 0.
                     env=np.full(3, env), spp=spp, max_depth=max_depth, seed=seed)
 
 
+def corner_capture_res(spp: int = 16, max_depth: int = 4, seed: int = 0) -> Workload:
+    """The 50k-triangle corner at the paper's capture resolutions (Sec. 4): camera
+    640x360, projector 800x600, 16 spp (its training and relighting sample count)."""
+    w = corner_50k(spp=spp, max_depth=max_depth, seed=seed)
+    w.camera = pinhole((0.85, 0.0, 0.85), (0.3, 0.0, 0.3), 60.0, 640, 360)
+    w.projector = pinhole((0.85, 0.15, 0.85), (0.3, 0.0, 0.3), 45.0, 800, 600)
+    w.proj_image = blob_image(600, 800, 205)
+    w.name = (f"folded corner {w.mesh.num_triangles} tris + 3 boxes, GGX 512^2 textures, cam 640x360, "
+              f"proj 800x600, {spp} spp, D={max_depth}")
+    return w
+
+
 def fit_truth(seed: int = 301):
     """Hidden ground truth for the scene-parameter fit (textures 64^2, PRF/CRF, mixing, WB)."""
     rng = np.random.default_rng(seed)

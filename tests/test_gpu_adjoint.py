@@ -44,6 +44,30 @@ def test_vjp_matches_oracle_ggx(clip, env):
         print(f"{mode}: worst global relative gradient error {worst:.2e}")
 
 
+def test_vjp_non_square_devices_and_maps():
+    """Camera, projector and maps of different, non-square sizes (the capture aspect
+    ratios of the paper's setup, scaled down): a swapped width and height anywhere in
+    the projector image, the maps or their gradients fails here."""
+    import math
+    w = scenes.c3_ggx(spp=4, seed=31, max_depth=3)
+    w.camera = synth.pinhole((0, 0, 0.8), (0, 0, 0), 60.0, 64, 36, up=(0, 1, 0))
+    ang = math.radians(30.0)
+    w.projector = synth.pinhole((-0.6 * math.sin(ang), 0.0, 0.6 * math.cos(ang)), (0, 0, 0), 60.0, 80, 60,
+                                up=(0, 1, 0))
+    rng = np.random.default_rng(32)
+    w.proj_image = rng.uniform(0, 1, (60, 80, 3)).astype(np.float32)
+    w.albedo = rng.uniform(0.2, 0.8, (24, 40, 3)).astype(np.float32)
+    w.roughness = rng.uniform(0.2, 0.9, (24, 40)).astype(np.float32)
+    w.specular = rng.uniform(0.0, 1.0, (24, 40)).astype(np.float32)
+    w.env = np.array([0.03, 0.04, 0.05])
+    sc = O.Scene(w)
+    G = _clean_cotangent(w, 33, sc)
+    ref = O.render_vjp(sc, G)
+    run = GpuRun(w)
+    for mode in VJP_MODES:
+        compare_grads(run_vjp(run, G, mode=mode), ref)
+
+
 def test_vjp_lambert_quad_cube():
     w = synth.quad_cube()
     sc = O.Scene(w)

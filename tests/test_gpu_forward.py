@@ -157,6 +157,24 @@ def test_ragged_and_tiny_images():
         compare_forward(g, ref, min_clean=0.9)
 
 
+def test_non_square_projector_and_maps():
+    """Projector 80 x 60 and maps 40 x 24 beside a 64 x 36 camera."""
+    import math
+    w = scenes.c3_ggx(spp=4, seed=35, max_depth=3)
+    w.camera = synth.pinhole((0, 0, 0.8), (0, 0, 0), 60.0, 64, 36, up=(0, 1, 0))
+    ang = math.radians(30.0)
+    w.projector = synth.pinhole((-0.6 * math.sin(ang), 0.0, 0.6 * math.cos(ang)), (0, 0, 0), 60.0, 80, 60,
+                                up=(0, 1, 0))
+    rng = np.random.default_rng(36)
+    w.proj_image = rng.uniform(0, 1, (60, 80, 3)).astype(np.float32)
+    w.albedo = rng.uniform(0.2, 0.8, (24, 40, 3)).astype(np.float32)
+    w.roughness = rng.uniform(0.2, 0.9, (24, 40)).astype(np.float32)
+    w.specular = rng.uniform(0.0, 1.0, (24, 40)).astype(np.float32)
+    g = GpuRun(w).render()
+    ref = O.render(O.Scene(w))
+    compare_forward(g, ref)
+
+
 def test_single_triangle_scene_and_direct_only():
     w = scenes.plane_workload(max_depth=1)
     w.mesh = synth.Mesh(w.mesh.vertices, w.mesh.triangles[:1], w.mesh.corner_uvs[:1])
