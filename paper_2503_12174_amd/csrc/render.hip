@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
 // PROF: the counting pass's instantiation (node and triangle visit counters, summed
 // into q.stats), which a profiler reports apart from the timed launches
 template <bool UNI, bool PROF>
-__global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_shadow(Queues q, int which, int depth, ReqDesc uni,
+__global__ void __launch_bounds__(TB) SHADOW_OCCUPANCY k_shadow(Queues q, int which, int depth, ReqDesc uni,
                                                const ReqDesc* __restrict__ table) {
     __shared__ int stack[(SHORT_STACK + 1) * TB];
     __shared__ float4 ltop[UNI ? 8 * TOP_NODES : 1];
