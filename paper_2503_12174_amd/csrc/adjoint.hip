@@ -19,6 +19,8 @@
 //   adj_replay  with the forward's path records: adj_shade and adj_shadow in one pass,
 //               visibility and hit leaf read from the records instead of traced
 //   adj_finish  PRF backward (Eq. 1) per texel and the scalar reductions
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "shade.hpp"
 
@@ -237,7 +239,27 @@ __global__ void __launch_bounds__(BLOCK) k_adj_pixel(Queues q, AdjQueues aq, Req
     if (threadIdx.x < 7) {
         float v = 0.f;
         for (int k = 0; k < BLOCK / 64; ++k) v += red[threadIdx.x][k];
-        if (v != 0.f) atomicAdd(&r.d_acc[threadIdx.x], v);
+        if (r.d_part) r.d_part[8 * (size_t)blockIdx.x + threadIdx.x] = v;
+        else if (v != 0.f) atomicAdd(&r.d_acc[threadIdx.x], v);
+    }
+}
+
+// dst[k] += the sum over nb workgroup partials part[b * stride + k], k < nv, in a fixed
+// order (FP64), so the scalar gradients are the same on every run
+__global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ part, int nb, int stride, int nv,
+                                                      float* __restrict__ dst) {
+    __shared__ double red[256];
+    for (int k = 0; k < nv; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += 256) s += part[(size_t)b * stride + k];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && red[0] != 0.0) dst[k] += (float)red[0];
+        __syncthreads();
     }
 }
 
@@ -637,7 +659,9 @@ template <int C, int RS>
 __global__ void __launch_bounds__(ACC_TB) k_bin_accum(MapBins mb) {
     // Sums in 64-bit fixed point (integer LDS atomics are exact and much faster than
     // FP32 ones): values scaled by 2^E with |chunk sum| < 2^62 for every texel, i.e.
-    // 2^-50 of the largest record value as resolution.
+    // 2^-50 of the largest record value as resolution.  The chunk sums are stored as
+    // integers, so the texel totals the gather forms do not depend on how the records
+    // were split into chunks (which varies with the order atomics placed them in).
     __shared__ long long t[(MAP_MAX_T + 1) * (MAP_MAX_T + 1) * C];
     const uint32_t* off = mb.bins + mb.nb;
     const uint32_t total = off[mb.nb];
@@ -650,7 +674,8 @@ __global__ void __launch_bounds__(ACC_TB) k_bin_accum(MapBins mb) {
     int ge = 0;
     frexpf(gmax, &ge);                              // gmax < 2^ge
     const int E = 62 - 12 - ge;                     // ACC_CHUNK = 2^12 contributions at most
-    const double up = ldexp(1.0, E), down = ldexp(1.0, -E);
+    const double up = ldexp(1.0, E);
+    if (c == 0 && threadIdx.x == 0) mb.bins[2 * mb.nb + 1] = (uint32_t)E;   // for the gather
     int lo = 0, hi = mb.nb;   // the tile holding record i0: last b with off[b] <= i0
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -687,9 +712,8 @@ __global__ void __launch_bounds__(ACC_TB) k_bin_accum(MapBins mb) {
             }
         }
         const bool any_bad = __syncthreads_or(bad);
-        float* st = mb.stage + (size_t)(c + b) * SS;
-        for (int k = threadIdx.x; k < SS; k += ACC_TB)
-            st[k] = any_bad ? __builtin_nanf("") : (float)((double)t[k] * down);
+        long long* st = mb.stage + (size_t)(c + b) * SS;
+        for (int k = threadIdx.x; k < SS; k += ACC_TB) st[k] = any_bad ? STAGE_NAN : t[k];
         __syncthreads();
         if (off[b + 1] >= i1) break;
         ++b;
@@ -709,27 +733,51 @@ __global__ void k_bin_gather(MapBins mb, float* __restrict__ out, int stride) {
     const int T = mb.T, S = T + 1, SS = S * S * C;
     const int tx = x / T, ty = y / T, lx = x - tx * T, ly = y - ty * T;
     const uint32_t* off = mb.bins + mb.nb;
-    float v[C];
+    // exact 128-bit two's-complement totals of the integer block sums (a texel can take
+    // more blocks than 64 bits hold), converted to floating point once
+    unsigned long long lo[C];
+    long long hi[C];
+    bool nan = false;
 #pragma unroll
-    for (int ch = 0; ch < C; ++ch) v[ch] = 0.f;
+    for (int ch = 0; ch < C; ++ch) {
+        lo[ch] = 0ull;
+        hi[ch] = 0ll;
+    }
     auto add = [&](int bx, int by, int ix, int iy) {
         const int b = by * mb.nbx + bx;
         const uint32_t a = off[b], e = off[b + 1];
         if (a == e) return;
         for (uint32_t c = a / ACC_CHUNK; c <= (e - 1) / ACC_CHUNK; ++c) {
-            const float* p = mb.stage + (size_t)(c + b) * SS + ((size_t)iy * S + ix) * C;
+            const long long* p = mb.stage + (size_t)(c + b) * SS + ((size_t)iy * S + ix) * C;
 #pragma unroll
-            for (int ch = 0; ch < C; ++ch) v[ch] += p[ch];
+            for (int ch = 0; ch < C; ++ch) {
+                const long long q = p[ch];
+                nan = nan || q == STAGE_NAN;
+                const unsigned long long s = lo[ch] + (unsigned long long)q;
+                hi[ch] += (q < 0 ? -1ll : 0ll) + (s < lo[ch] ? 1ll : 0ll);
+                lo[ch] = s;
+            }
         }
     };
     add(tx, ty, lx, ly);
     if (lx == 0 && tx > 0) add(tx - 1, ty, T, ly);
     if (ly == 0 && ty > 0) add(tx, ty - 1, lx, T);
     if (lx == 0 && ly == 0 && tx > 0 && ty > 0) add(tx - 1, ty - 1, T, T);
+    const double down = ldexp(1.0, -(int)mb.bins[2 * mb.nb + 1]);
     float* o = out + (size_t)t * stride;
 #pragma unroll
-    for (int ch = 0; ch < C; ++ch)
-        if (v[ch] != 0.f) o[ch] += v[ch];
+    for (int ch = 0; ch < C; ++ch) {
+        // magnitude and sign (no cancellation between the two halves), then 2^-E
+        const bool neg = hi[ch] < 0;
+        unsigned long long ml = lo[ch], mh = (unsigned long long)hi[ch];
+        if (neg) {
+            ml = ~ml + 1ull;
+            mh = ~mh + (ml == 0ull ? 1ull : 0ull);
+        }
+        const double m = ((double)mh * 0x1p64 + (double)ml) * down;
+        const float v = nan ? __builtin_nanf("") : (float)(neg ? -m : m);
+        if (v != 0.f) o[ch] += v;
+    }
 }
 
 // ---------------------------------------------------------------- replay from records
@@ -993,7 +1041,8 @@ __global__ void k_adj_prf(ReqDesc r, float* __restrict__ d_proj, float* __restri
     if (threadIdx.x < 12) {
         float v = 0.f;
         for (int k = 0; k < BLOCK / 64; ++k) v += red[threadIdx.x][k];
-        if (v != 0.f) atomicAdd(&acc[8 + threadIdx.x], v);
+        if (r.d_part) r.d_part[12 * (size_t)blockIdx.x + threadIdx.x] = v;
+        else if (v != 0.f) atomicAdd(&acc[8 + threadIdx.x], v);
     }
 }
 
@@ -1036,9 +1085,13 @@ static inline unsigned grid_cap(const Launch& l, int64_t n, int b) {
 
 void launch_adj_pixel(const Launch& l, const Queues& q, const AdjQueues& aq, const ReqDesc& r, uint32_t p0,
                       uint32_t p1, const float* sample_L) {
-    if (p1 > p0)
-        hipLaunchKernelGGL(k_adj_pixel, dim3(grid_of((int64_t)(p1 - p0) * PIX_LANES, BLOCK)), dim3(BLOCK), 0, l.st, q, aq, r,
-                           p0, p1, sample_L);
+    if (p1 <= p0) return;
+    const unsigned g = grid_of((int64_t)(p1 - p0) * PIX_LANES, BLOCK);
+    hipLaunchKernelGGL(k_adj_pixel, dim3(g), dim3(BLOCK), 0, l.st, q, aq, r, p0, p1, sample_L);
+    if (r.d_part) hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, l.st, r.d_part, (int)g, 8, 7, r.d_acc);
+}
+size_t partial_floats(int64_t pixels_per_wave, int64_t proj_pixels) {
+    return std::max<size_t>(8 * (size_t)grid_of(pixels_per_wave * PIX_LANES, BLOCK), 12 * (size_t)grid_of(proj_pixels, BLOCK));
 }
 void launch_adj_raygen(const Launch& l, const Queues& q, const AdjQueues& aq, const ReqDesc& r, int slot, uint32_t g0,
                        uint32_t n) {
@@ -1093,7 +1146,9 @@ void launch_map_flush(const Launch& l, const AdjQueues& aq, const ReqDesc& r) {
 }
 void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* d_albedo, float* d_rough,
                        float* d_spec, float* d_scalars, float* acc) {
-    hipLaunchKernelGGL(k_adj_prf, dim3(grid_of((int64_t)r.Wp * r.Hp, BLOCK)), dim3(BLOCK), 0, l.st, r, d_proj, acc);
+    const unsigned g = grid_of((int64_t)r.Wp * r.Hp, BLOCK);
+    hipLaunchKernelGGL(k_adj_prf, dim3(g), dim3(BLOCK), 0, l.st, r, d_proj, acc);
+    if (r.d_part) hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, l.st, r.d_part, (int)g, 12, 12, acc + 8);
     if (d_albedo || d_rough || d_spec)
         hipLaunchKernelGGL(k_adj_maps, dim3(grid_of((int64_t)r.tw * r.th, 256)), dim3(256), 0, l.st, r, d_albedo,
                            d_rough, d_spec);

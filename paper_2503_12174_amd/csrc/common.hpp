@@ -186,6 +186,8 @@ struct ReqDesc {
     float* dEp;                // cotangent of E_p, 4 floats per texel
     float* d_tex;              // cotangent of (albedo rgb, roughness, specular), 5 floats per texel
     float* d_acc;              // 8 floats: d gamma_c[3], d w[3], d threshold, pad
+    float* d_part;             // per-workgroup partials of the scalar sums (summed in a fixed
+                               // order by a second kernel), or null: float atomics into d_acc
     // path records: one word per (sample, depth) at rec[(g - rec_g0) * max_depth + depth];
     // the forward writes them when rec is set, the replay adjoint reads them
     uint32_t* rec;

@@ -82,12 +82,15 @@ constexpr int ACC_TB = 1024;    // threads per workgroup of the accumulation
 constexpr int BIN_CHUNK = 16384;// records per workgroup of the histogram and the placement
 constexpr int BIN_TB = 1024;    // their threads per workgroup: 16 waves share one LDS
                                 // histogram, so the few chunks of a flush still fill the chip
+constexpr long long STAGE_NAN = -0x7fffffffffffffffll - 1;   // INT64_MIN
 struct MapBins {
     float* rec;          // records of rs floats (null: binning off, the replay scatters directly)
     float* sorted;       // the same records grouped by tile
-    float* stage;        // per (chunk, tile) pair (T + 1)^2 x C sums (tile plus one halo row/column)
+    long long* stage;    // per (chunk, tile) pair (T + 1)^2 x C exact fixed-point sums (tile plus one
+                         // halo row/column); STAGE_NAN marks a chunk with a non-finite value
     uint32_t* count;     // records appended since the last flush (may exceed cap)
-    uint32_t* bins;      // counts[nb], offsets[nb + 1], (unused)[nb], largest |value| (float bits)
+    uint32_t* bins;      // counts[nb], offsets[nb + 1], fixed-point exponent E, (unused)[nb - 1],
+                         // largest |value| (float bits)
     uint32_t* rowbase;   // per (BIN_CHUNK chunk, tile): where the chunk's records start in the tile
     int64_t cap;         // record capacity
     int W, H, T, nbx, nby, nb;
@@ -135,6 +138,9 @@ void launch_finalize(const Launch& l, const Queues& q, const ReqDesc& r, const R
 void launch_set_desc(const Launch& l, ReqDesc* table, int slot, const ReqDesc& r);
 
 // adjoint kernels
+// floats of the scalar-partials buffer (ReqDesc::d_part) for waves of up to
+// pixels_per_wave pixels and a projector of proj_pixels pixels
+size_t partial_floats(int64_t pixels_per_wave, int64_t proj_pixels);
 void launch_adj_pixel(const Launch& l, const Queues& q, const AdjQueues& aq, const ReqDesc& r, uint32_t p0,
                       uint32_t p1, const float* sample_L);
 void launch_adj_raygen(const Launch& l, const Queues& q, const AdjQueues& aq, const ReqDesc& r, int slot, uint32_t g0,

@@ -130,7 +130,7 @@ void make_map_bins(dpcs_context ctx, const Launch& l, MapBins& mb, const char* n
     if (!map_tiling(W, H, T, nbx, nby)) return;
     cap = std::min<int64_t>(cap, int64_t(1) << 31);
     const int nb = nbx * nby;
-    const size_t rec = 4 * (size_t)RS * cap, stage = 4 * (size_t)((cap + ACC_CHUNK - 1) / ACC_CHUNK + nb) * (T + 1) * (T + 1) * C;
+    const size_t rec = 4 * (size_t)RS * cap, stage = 8 * (size_t)((cap + ACC_CHUNK - 1) / ACC_CHUNK + nb) * (T + 1) * (T + 1) * C;
     const size_t rows = 4 * (size_t)((cap + BIN_CHUNK - 1) / BIN_CHUNK) * nb;
     const size_t bytes = 2 * rec + stage + rows + 4 * (3 * (size_t)nb + 2) + 8 * 256;
     dpcs_status st = DPCS_OK;
@@ -146,7 +146,7 @@ void make_map_bins(dpcs_context ctx, const Launch& l, MapBins& mb, const char* n
     };
     mb.rec = (float*)take(rec);
     mb.sorted = (float*)take(rec);
-    mb.stage = (float*)take(stage);
+    mb.stage = (long long*)take(stage);
     mb.count = (uint32_t*)take(4);
     mb.bins = (uint32_t*)take(4 * (3 * (size_t)nb + 2));
     mb.rowbase = (uint32_t*)take(rows);

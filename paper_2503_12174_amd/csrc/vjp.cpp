@@ -44,6 +44,9 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     const int64_t npix = (int64_t)r.Wc * r.Hc;
     const int64_t cap = std::min<int64_t>(std::max<int64_t>(ctx->capacity, r.spp), npix * r.spp);
     const int64_t ppw = std::max<int64_t>(1, cap / r.spp);
+    // scalar sums reduced in a fixed order: the same gradients on every run
+    r.d_part = (float*)scratch(ctx, "vjp.partials", sizeof(float) * partial_floats(ppw, (int64_t)nEp), &st);
+    if (!r.d_part) return st;
     Queues q{};
     AdjQueues aq{};
     if (!make_queues(ctx, "fwd.queues", ppw * r.spp, q, &st)) return st;
