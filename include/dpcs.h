@@ -230,8 +230,8 @@ DPCS_API dpcs_status dpcs_denoise_vjp(dpcs_context ctx, const dpcs_denoise_param
  * (Eq. 6 inverted, no jitter), closest hit on the scene.  gbuffer (Hc x Wc x 8 float):
  * albedo rgb at the hit (bilinear lookup of params->albedo), unit geometric normal
  * turned toward the camera (xyz), hit distance along the unit ray, 1; all eight are 0
- * where the ray escapes.  Only the camera, the albedo map and its size are read from
- * params. */
+ * where the ray escapes.  params must be valid as for dpcs_render (no projector image is
+ * needed); the call uses its camera and BRDF maps.  gbuffer must be 16-byte aligned. */
 DPCS_API dpcs_status dpcs_render_gbuffer(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
                                          float* gbuffer);
 
