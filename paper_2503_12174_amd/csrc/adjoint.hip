@@ -452,7 +452,7 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
 // ---------------------------------------------------------------- shadows
 // PROF: the counting pass's instantiation (visit counters summed into q.stats)
 template <bool UNI, bool PROF>
-__global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_adj_shadow(Queues q, AdjQueues aq, int which, int nxt, ReqDesc uni,
+__global__ void __launch_bounds__(TB) ADJ_SHADOW_OCCUPANCY k_adj_shadow(Queues q, AdjQueues aq, int which, int nxt, ReqDesc uni,
                                                    const ReqDesc* __restrict__ table) {
     __shared__ int stack[(SHORT_STACK + 1) * TB];
     __shared__ float4 ltop[UNI ? 8 * TOP_NODES : 1];

@@ -66,6 +66,10 @@ constexpr int TRACE_TB = 128;                  // threads per workgroup of the t
 // except the forward's shadow rays: with the staged tree top their any-hit loop spills a
 // few registers at 64 VGPRs; at 7 waves (71 VGPRs, no spill) they run ~3 % faster
 #define SHADOW_OCCUPANCY __attribute__((amdgpu_waves_per_eu(7, 7)))
+// and the re-tracing replay's shadow rays, whose gradient bookkeeping after the query
+// spilled ~150 bytes per lane at 64 VGPRs: at 4 waves (105 VGPRs) nothing spills and
+// the re-tracing step is ~1.5 % faster
+#define ADJ_SHADOW_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4, 4)))
 inline size_t spill_ints(int grid_cap) { return (size_t)grid_cap * TRACE_TB * SPILL; }
 
 // Binned accumulation of the cotangent of one texel map (BRDF maps or E_p): the replay
