@@ -143,6 +143,16 @@ def test_denoise_rejects_bad_params():
         dpcs.dpcs_denoise(c, dpcs.denoise_params(8, 8, 2, 0.1, (1.0, 1.0)), img, None, out)
     with pytest.raises(Exception):   # in place
         dpcs.dpcs_denoise(c, dpcs.denoise_params(8, 8, 2, 0.1, (1.0, 1.0)), img, guide, img)
+    with pytest.raises(Exception):   # beyond the largest image side
+        dpcs.dpcs_denoise(c, dpcs.denoise_params(16385, 1, 2, 0.1, (1.0, 1.0)), img, guide, out)
+    loss = torch.zeros((), device="cuda")
+    with pytest.raises(Exception):   # an empty map
+        c.check(dpcs.lib().dpcs_tv_loss(c.h, dpcs._ptr(img), 0, 8, 3, dpcs._ptr(loss)))
+    with pytest.raises(Exception):   # no values
+        c.check(dpcs.lib().dpcs_l1_loss(c.h, dpcs._ptr(img), dpcs._ptr(out), 0, dpcs._ptr(loss)))
+    # the context still works after rejected calls
+    dpcs.dpcs_denoise(c, dpcs.denoise_params(8, 8, 2, 0.1, (1.0, 1.0)), img, guide, out)
+    c.synchronize()
 
 
 # ------------------------------------------------------------------ guide features
