@@ -126,6 +126,39 @@ def test_denoise_adjoint_identity_at_scale():
     np.testing.assert_allclose(a[y0:y0 + h, x0:x0 + w], crop, rtol=0, atol=_tol(_fwd_bound(r, 1.0), crop))
 
 
+def test_denoise_of_the_benchmark_rendering():
+    """D with its default parameters on a 256 x 256 rendering of the 50k-triangle corner,
+    steered by that scene's guide features, and its VJP, against the oracle over the
+    whole image."""
+    import torch
+    from paper_2503_12174_amd import dpcs
+    from paper_2503_12174_amd import objective as Ob
+    c = ctx()
+    w = synth.corner_50k(spp=4)
+    sc = dpcs.Scene(c, w.mesh, bvh="sah")
+    f = torch.float32
+    alb, rough, spec, proj = dev(w.albedo, f), dev(w.roughness, f), dev(w.specular, f), dev(w.proj_image, f)
+    p = dpcs.params_from(w, alb, rough, spec)
+    img = torch.zeros((256, 256, 3), device="cuda")
+    dpcs.dpcs_render(c, sc, p, proj, img)
+    guide = Ob.gbuffer(c, sc, p)
+    cfg = Ob.DenoiseConfig()
+    x = img.clone().requires_grad_(True)
+    den = Ob.denoise(c, x, guide, cfg)
+    G = torch.as_tensor(np.random.default_rng(51).normal(size=(256, 256, 3)).astype(np.float32)).cuda()
+    den.backward(G)
+    c.synchronize()
+    f64 = lambda t: t.detach().cpu().numpy().astype(np.float64)
+    coef, sp = _f32(cfg.guide), float(np.float32(cfg.spatial))
+    want = O.denoise(f64(img), f64(guide), coef, sp, cfg.radius)
+    np.testing.assert_allclose(f64(den), want, rtol=0, atol=_tol(_fwd_bound(cfg.radius, np.abs(f64(img)).max()), want))
+    want_g = O.denoise_vjp(f64(G), f64(guide), coef, sp, cfg.radius)
+    np.testing.assert_allclose(f64(x.grad), want_g, rtol=0,
+                               atol=_tol(_vjp_bound(cfg.radius, np.abs(f64(G)).max()), want_g))
+    # the camera sees the surface almost everywhere (coverage channel)
+    assert float(guide[..., 7].mean()) > 0.9
+
+
 def test_denoise_rejects_bad_params():
     import torch
     from paper_2503_12174_amd import dpcs
