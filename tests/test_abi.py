@@ -61,3 +61,19 @@ def test_calls_without_a_device_fail_cleanly():
     h = ctypes.c_void_p()
     st = dpcs.lib().dpcs_context_create(0, None, 0, ctypes.byref(h))
     assert st != dpcs.OK and not h.value
+
+
+def test_denoise_params_marshalling():
+    """The binding's parameter block for the denoiser: one factor per guide channel, at
+    most eight, and the default configuration matches the eight guide features."""
+    import pytest
+    from paper_2503_12174_amd import objective
+    p = dpcs.denoise_params(640, 360, 3, 0.125, (1.0, 2.0, 3.0))
+    assert (p.width, p.height, p.radius, p.guide_channels) == (640, 360, 3, 3)
+    assert list(p.guide)[:3] == [1.0, 2.0, 3.0] and list(p.guide)[3:] == [0.0] * 5
+    with pytest.raises(ValueError):
+        dpcs.denoise_params(8, 8, 1, 0.1, [1.0] * 9)
+    cfg = objective.DenoiseConfig()
+    assert cfg.params(256, 256, 8).guide_channels == 8
+    with pytest.raises(ValueError):
+        cfg.params(256, 256, 7)
