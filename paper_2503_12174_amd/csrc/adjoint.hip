@@ -1105,7 +1105,7 @@ void launch_adj_shade(const Launch& l, const Queues& q, const AdjQueues& aq, int
 }
 void launch_adj_shadow(const Launch& l, const Queues& q, const AdjQueues& aq, int which, int nxt, const ReqDesc& uni,
                        const ReqDesc* table, int64_t n_upper) {
-    const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
+    const dim3 g(grid_cap(Launch{l.st, q.trace_blocks}, n_upper, TB)), b(TB);
     if (q.stats) {
         if (table) hipLaunchKernelGGL((k_adj_shadow<false, true>), g, b, 0, l.st, q, aq, which, nxt, uni, table);
         else hipLaunchKernelGGL((k_adj_shadow<true, true>), g, b, 0, l.st, q, aq, which, nxt, uni, table);

@@ -55,11 +55,12 @@ struct Queues {
     int64_t cap;       // path capacity
     unsigned long long* stats;   // null, or [0] nodes visited, [1] triangles tested (profiling)
     int* spill;        // traversal stack overflow: SPILL ints per thread of a capped grid
+    int trace_blocks;  // workgroups the spill region covers: the traversal grid cap
 };
 
 constexpr int SHORT_STACK = 8;                 // LDS stack entries per thread
 constexpr int SPILL = 64 - SHORT_STACK;        // overflow entries per thread
-constexpr int TRACE_TB = 128;                  // threads per workgroup of the traversal kernels
+constexpr int TRACE_TB = 256;                  // threads per workgroup of the traversal kernels
 // traversal kernels are compiled for 8 waves per SIMD (at most 64 VGPRs): the loop is
 // latency-bound enough that occupancy pays more than the odd spilled register costs
 #define TRAVERSAL_OCCUPANCY __attribute__((amdgpu_waves_per_eu(8, 8)))
@@ -70,7 +71,18 @@ constexpr int TRACE_TB = 128;                  // threads per workgroup of the t
 // spilled ~150 bytes per lane at 64 VGPRs: at 4 waves (105 VGPRs) nothing spills and
 // the re-tracing step is ~1.5 % faster
 #define ADJ_SHADOW_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4, 4)))
-inline size_t spill_ints(int grid_cap) { return (size_t)grid_cap * TRACE_TB * SPILL; }
+// Traversal grids are capped at `rounds` x grid_cap x 128 threads (grid_cap x 128 threads
+// is one resident round at 8 waves per SIMD); the spill region holds SPILL ints for every
+// thread of that grid.  Several rounds let workgroups that finish early be replaced
+// while others still trace long paths (4 rounds: traversal -7 %), at 224 B of spill
+// space per thread: the single-request path uses TRACE_ROUNDS, the request loop one round
+// (its queues count against its memory budget).
+constexpr int TRACE_ROUNDS = 4;
+inline int trace_grid_cap(int grid_cap, int rounds) {
+    const int g = grid_cap * 128 / TRACE_TB * rounds;
+    return g > 0 ? g : 1;
+}
+inline size_t spill_ints(int grid_cap, int rounds) { return (size_t)trace_grid_cap(grid_cap, rounds) * TRACE_TB * SPILL; }
 
 // Binned accumulation of the cotangent of one texel map (BRDF maps or E_p): the replay
 // writes one record per (vertex, map) -- bilinear base texel and offsets plus the C

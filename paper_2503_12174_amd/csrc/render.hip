@@ -425,7 +425,7 @@ void launch_raygen(const Launch& l, const Queues& q, const ReqDesc& r, const Req
 }
 void launch_trace(const Launch& l, const Queues& q, int cur, const ReqDesc& uni, const ReqDesc* table,
                   int64_t n_upper) {
-    const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
+    const dim3 g(grid_cap(Launch{l.st, q.trace_blocks}, n_upper, TB)), b(TB);
     if (q.stats) {
         if (table) hipLaunchKernelGGL((k_trace<false, true>), g, b, 0, l.st, q, cur, uni, table);
         else hipLaunchKernelGGL((k_trace<true, true>), g, b, 0, l.st, q, cur, uni, table);
@@ -442,7 +442,7 @@ void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const Re
 }
 void launch_shadow(const Launch& l, const Queues& q, int which, const ReqDesc& uni, const ReqDesc* table,
                    int64_t n_upper, int depth) {
-    const dim3 g(grid_cap(l, n_upper, TB)), b(TB);
+    const dim3 g(grid_cap(Launch{l.st, q.trace_blocks}, n_upper, TB)), b(TB);
     if (q.stats) {
         if (table) hipLaunchKernelGGL((k_shadow<false, true>), g, b, 0, l.st, q, which, depth, uni, table);
         else hipLaunchKernelGGL((k_shadow<true, true>), g, b, 0, l.st, q, which, depth, uni, table);

@@ -64,7 +64,7 @@ bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpc
     const size_t c = (size_t)cap;
     // per path: 2 x (PathO 32 + PathD 32 + beta 16) + hit 4 + 2 x shadow (48 + 4) + L 16
     // + 256 bytes of alignment slack per part (18 parts)
-    const size_t bytes = c * (2 * 80 + 4 + 2 * 52 + 16) + 4 * spill_ints(ctx->grid_cap) + 32 * 256;
+    const size_t bytes = c * (2 * 80 + 4 + 2 * 52 + 16) + 4 * spill_ints(ctx->grid_cap, TRACE_ROUNDS) + 32 * 256;
     char* b = (char*)scratch(ctx, name, bytes, st);
     if (!b) return false;
     auto take = [&](size_t n) {   // 256-byte aligned parts
@@ -84,7 +84,8 @@ bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpc
     q.hit = (int*)take(4 * c);
     q.L = (float4*)take(16 * c);
     q.cnt = (uint32_t*)take(16);
-    q.spill = (int*)take(4 * spill_ints(ctx->grid_cap));
+    q.spill = (int*)take(4 * spill_ints(ctx->grid_cap, TRACE_ROUNDS));
+    q.trace_blocks = trace_grid_cap(ctx->grid_cap, TRACE_ROUNDS);
     q.cap = cap;
     q.stats = nullptr;
     return true;
