@@ -60,7 +60,7 @@ struct Queues {
 
 constexpr int SHORT_STACK = 8;                 // LDS stack entries per thread
 constexpr int SPILL = 64 - SHORT_STACK;        // overflow entries per thread
-constexpr int TRACE_TB = 256;                  // threads per workgroup of the traversal kernels
+constexpr int TRACE_TB = 128;                  // threads per workgroup of the traversal kernels
 // traversal kernels are compiled for 8 waves per SIMD (at most 64 VGPRs): the loop is
 // latency-bound enough that occupancy pays more than the odd spilled register costs
 #define TRAVERSAL_OCCUPANCY __attribute__((amdgpu_waves_per_eu(8, 8)))
