@@ -188,7 +188,10 @@ typedef struct {
  *   both given          replay from the caller's records, no tracing;
  *   sample_radiance     replay that traces every bounce and shadow ray again.
  *   only
- * path_records without sample_radiance is DPCS_E_INVALID. */
+ * path_records without sample_radiance is DPCS_E_INVALID.
+ * The same inputs give the same gradient bits on every call (map cotangents are summed
+ * in exact fixed point, scalar sums in a fixed order); maps larger than 1024 x 1024 fall
+ * back to float atomics, whose summation order varies. */
 DPCS_API dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
                             const float* proj_image, const float* grad_image,
                             const float* sample_radiance, const uint32_t* path_records,
