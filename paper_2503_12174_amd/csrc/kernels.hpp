@@ -75,8 +75,8 @@ constexpr int TRACE_TB = 128;                  // threads per workgroup of the t
 // is one resident round at 8 waves per SIMD); the spill region holds SPILL ints for every
 // thread of that grid.  Several rounds let workgroups that finish early be replaced
 // while others still trace long paths (4 rounds: traversal -7 %), at 224 B of spill
-// space per thread: the single-request path uses TRACE_ROUNDS, the request loop one round
-// (its queues count against its memory budget).
+// space per thread: the single-request path uses TRACE_ROUNDS, the request loop two
+// rounds (its queues count against its memory budget).
 constexpr int TRACE_ROUNDS = 4;
 inline int trace_grid_cap(int grid_cap, int rounds) {
     const int g = grid_cap * 128 / TRACE_TB * rounds;

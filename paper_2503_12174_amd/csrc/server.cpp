@@ -378,7 +378,7 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     const size_t c = (size_t)s->cap;
     // + 256 bytes of alignment slack per part (42 parts); path records for up to 8
     // vertices per path of a wave
-    const size_t qbytes = c * per_path + 64 * 256 + 4 * spill_ints(ctx->grid_cap, 1) + 4 * 8 * c;
+    const size_t qbytes = c * per_path + 64 * 256 + 4 * spill_ints(ctx->grid_cap, 2) + 4 * 8 * c;
     s->shared_bytes = qbytes + sizeof(ReqDesc) * (size_t)max_slots;
     if (s->shared_bytes >= s->budget) {
         delete s;
@@ -431,8 +431,8 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     s->aq.tb = MapBins{};   // the request loop replays by tracing and scatters directly
     s->aq.eb = MapBins{};
     s->q.cnt = (uint32_t*)take(16);
-    s->q.spill = (int*)take(4 * spill_ints(ctx->grid_cap, 1));
-    s->q.trace_blocks = trace_grid_cap(ctx->grid_cap, 1);
+    s->q.spill = (int*)take(4 * spill_ints(ctx->grid_cap, 2));
+    s->q.trace_blocks = trace_grid_cap(ctx->grid_cap, 2);
     s->rec = (uint32_t*)take(4 * 8 * c);
     s->rec_cap = 8 * (int64_t)c;
     s->q.cap = s->cap;
