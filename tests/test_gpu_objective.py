@@ -214,11 +214,15 @@ def _compare_gbuffer(got, want, margin):
     return int(clean.sum())
 
 
-@pytest.mark.parametrize("name", ["quad+cube", "plane"])
+@pytest.mark.parametrize("name", ["quad+cube", "plane", "sphere"])
 def test_gbuffer_matches_oracle(name):
-    w = synth.quad_cube() if name == "quad+cube" else scenes.plane_workload(
-        tex=np.random.default_rng(4).uniform(0.1, 0.9, (16, 16, 3)).astype(np.float32), half=0.3,
-        cam_eye=(0.05, 0.1, 0.6), res=48, cam_fov=70.0)
+    tex = np.random.default_rng(4).uniform(0.1, 0.9, (16, 16, 3)).astype(np.float32)
+    if name == "quad+cube":
+        w = synth.quad_cube()
+    else:
+        w = scenes.plane_workload(tex=tex, half=0.3, cam_eye=(0.05, 0.1, 0.6), res=48, cam_fov=70.0)
+        if name == "sphere":   # 1,280 facets, silhouette against the background
+            w.mesh = synth.icosphere(3, 0.25)
     got = _gbuffer_dev(w)
     want, margin = O.gbuffer(O.Scene(w))
     n = _compare_gbuffer(got, want, margin)
