@@ -7,6 +7,7 @@ with the GPU library.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -18,14 +19,14 @@ SRC = os.path.join(HERE, "dpcs_oracle.c")
 LIB = os.path.join(HERE, "libdpcs_oracle.so")
 
 
-def build(force: bool = True) -> str:
+def build(force: bool = True, src: str = SRC, out: str = LIB) -> str:
     """Compile the oracle with gcc (plain C99, FP64, OpenMP over pixels)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
+        tmp = out + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fopenmp", "-ffp-contract=off",
-                               "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, src, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class Desc(C.Structure):
@@ -58,34 +59,51 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
-        P = C.c_void_p
-        L.orc_render.argtypes = [C.POINTER(Desc), C.c_int32, P, P, P, P, P, P, P, P]
-        L.orc_render_vjp.argtypes = [C.POINTER(Desc), P, C.c_int32, P, P, P, P, P, P, P]
-        L.orc_philox_batch.argtypes = [C.c_uint64, C.c_int64, P, P]
-        L.orc_intersect.argtypes = [C.POINTER(Desc), C.c_int64, P, P, P, P, P, P]
-        L.orc_brdf.argtypes = [C.c_int32, P, P, P, P, C.c_double, C.c_double, P]
-        L.orc_sample.argtypes = [C.c_int32, P, P, C.c_double, C.c_int64, P, P, P]
-        L.orc_pdf.argtypes = [C.c_int32, P, P, P, C.c_double]
-        L.orc_pdf.restype = C.c_double
-        L.orc_ggx_D.argtypes = [C.c_double, C.c_double]
-        L.orc_ggx_D.restype = C.c_double
-        L.orc_ggx_G1.argtypes = [C.c_double, C.c_double]
-        L.orc_ggx_G1.restype = C.c_double
-        L.orc_prf.argtypes = [C.POINTER(Desc), P]
-        L.orc_bilinear.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int64, P, P]
-        L.orc_threads.argtypes = [C.POINTER(Desc)]
-        L.orc_first_hit.argtypes = [C.POINTER(Desc), C.c_int32, C.c_int32, P]
-        L.orc_pdf_batch.argtypes = [C.c_int32, P, P, C.c_double, C.c_int64, P, P]
-        L.orc_denoise.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_double, C.c_int32, P]
-        L.orc_denoise_vjp.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_double, C.c_int32, P]
-        L.orc_tv.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P]
-        L.orc_tv.restype = C.c_double
-        L.orc_l1.argtypes = [P, P, C.c_int64, P]
-        L.orc_l1.restype = C.c_double
-        L.orc_gbuffer.argtypes = [C.POINTER(Desc), C.c_int32, P, P, P]
-        _lib = L
+        _lib = _load(LIB)
     return _lib
+
+
+@contextlib.contextmanager
+def library(path: str):
+    """Run the wrapper on another build of the oracle for the duration of the block (the
+    tests that plant a mistake in a copy of the source and check that a pin catches it)."""
+    global _lib
+    saved = _lib
+    _lib = _load(path)
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
+def _load(path: str):
+    L = C.CDLL(path)
+    P = C.c_void_p
+    L.orc_render.argtypes = [C.POINTER(Desc), C.c_int32, P, P, P, P, P, P, P, P]
+    L.orc_render_vjp.argtypes = [C.POINTER(Desc), P, C.c_int32, P, P, P, P, P, P, P]
+    L.orc_philox_batch.argtypes = [C.c_uint64, C.c_int64, P, P]
+    L.orc_intersect.argtypes = [C.POINTER(Desc), C.c_int64, P, P, P, P, P, P]
+    L.orc_brdf.argtypes = [C.c_int32, P, P, P, P, C.c_double, C.c_double, P]
+    L.orc_sample.argtypes = [C.c_int32, P, P, C.c_double, C.c_int64, P, P, P]
+    L.orc_pdf.argtypes = [C.c_int32, P, P, P, C.c_double]
+    L.orc_pdf.restype = C.c_double
+    L.orc_ggx_D.argtypes = [C.c_double, C.c_double]
+    L.orc_ggx_D.restype = C.c_double
+    L.orc_ggx_G1.argtypes = [C.c_double, C.c_double]
+    L.orc_ggx_G1.restype = C.c_double
+    L.orc_prf.argtypes = [C.POINTER(Desc), P]
+    L.orc_bilinear.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int64, P, P]
+    L.orc_threads.argtypes = [C.POINTER(Desc)]
+    L.orc_first_hit.argtypes = [C.POINTER(Desc), C.c_int32, C.c_int32, P]
+    L.orc_pdf_batch.argtypes = [C.c_int32, P, P, C.c_double, C.c_int64, P, P]
+    L.orc_denoise.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_double, C.c_int32, P]
+    L.orc_denoise_vjp.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_double, C.c_int32, P]
+    L.orc_tv.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P]
+    L.orc_tv.restype = C.c_double
+    L.orc_l1.argtypes = [P, P, C.c_int64, P]
+    L.orc_l1.restype = C.c_double
+    L.orc_gbuffer.argtypes = [C.POINTER(Desc), C.c_int32, P, P, P]
+    return L
 
 
 def _p(a):

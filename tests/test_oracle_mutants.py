@@ -1,0 +1,75 @@
+"""The pins catch planted mistakes.
+
+Each case copies the oracle's source, plants one plausible mistake (a dropped factor, a
+swapped index, a transposed size, a missing term of the adjoint), builds the copy with
+gcc into a temporary directory and runs the pin that is meant to catch it against that
+build: the pin must fail.  The real oracle passes the same pins elsewhere in the suite.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+from . import test_oracle_pins as P
+from . import test_oracle_pins_lights as PL
+
+SRC = open(O.SRC).read()
+
+# (name, text in the oracle, planted replacement, the pin that must fail)
+MUTANTS = [
+    ("environment NEE without its pi",
+     "L[c] += beta[c] * fb.f[c] * d->env[c] * PI;",
+     "L[c] += beta[c] * fb.f[c] * d->env[c];",
+     lambda: PL.test_environment_on_a_lambert_plane(1)),
+    ("environment added on escaped bounce rays",
+     "if (depth == 0)\n                for (int c = 0; c < 3; ++c) L[c] += beta[c] * d->env[c];",
+     "if (depth >= 0)\n                for (int c = 0; c < 3; ++c) L[c] += beta[c] * d->env[c];",
+     lambda: PL.test_environment_on_a_lambert_plane(3)),
+    ("environment shadow ray ignored",
+     "int occ = occluded(d, &cx->sc, x, we, 1e300, prim, &mo);",
+     "int occ = 0 * occluded(d, &cx->sc, x, we, 1e300, prim, &mo);",
+     PL.test_environment_occlusion_under_a_ceiling),
+    ("projector lookup with u and v swapped",
+     "bilinear_at(pu - 0.5, pv - 0.5, d->Wp, d->Hp)",
+     "bilinear_at(pv - 0.5, pu - 0.5, d->Wp, d->Hp)",
+     lambda: PL.test_projector_lookup_with_a_non_constant_image(0.0, 40, 24)),
+    ("projector lookup without the half-texel offset",
+     "bilinear_at(pu - 0.5, pv - 0.5, d->Wp, d->Hp)",
+     "bilinear_at(pu, pv, d->Wp, d->Hp)",
+     lambda: PL.test_projector_lookup_with_a_non_constant_image(0.0, 40, 24)),
+    ("projector lookup with W_p and H_p transposed",
+     "bilinear_at(pu - 0.5, pv - 0.5, d->Wp, d->Hp)",
+     "bilinear_at(pu - 0.5, pv - 0.5, d->Hp, d->Wp)",
+     lambda: PL.test_projector_lookup_with_a_non_constant_image(0.0, 17, 29)),
+    ("projector NEE after a bounce without the path throughput",
+     "L[c] += beta[c] * fb.f[c] * E[c] * geom;",
+     "L[c] += fb.f[c] * E[c] * geom;",
+     PL.test_integrating_sphere),
+    ("projector intensity without 1/cos^3",
+     "double geom = cp / (ca * ca * ca * dist * dist);",
+     "double geom = cp / (dist * dist);",
+     PL.test_integrating_sphere),
+    ("adjoint: environment term missing from the albedo gradient",
+     "ga[c] += bd * Ee / PI;",
+     "ga[c] += 0.0 * Ee;",
+     lambda: P.test_adjoint_matches_central_differences(False, 0.4)),
+    ("adjoint: environment term missing from the roughness gradient",
+     "gr += bd * Ee * v->eds_dr;",
+     "gr += 0.0 * v->eds_dr;",
+     lambda: P.test_adjoint_matches_central_differences(False, 0.4)),
+]
+
+
+@pytest.mark.parametrize("name,orig,planted,pin", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pin_catches_planted_mistake(tmp_path, name, orig, planted, pin):
+    assert SRC.count(orig) == 1, f"the text to mutate is not unique in the oracle: {orig!r}"
+    src = os.path.join(tmp_path, "mutant.c")
+    with open(src, "w") as f:
+        f.write(SRC.replace(orig, planted))
+    lib = O.build(force=True, src=src, out=os.path.join(tmp_path, "libmutant.so"))
+    with O.library(lib):
+        with pytest.raises(AssertionError):
+            with np.errstate(all="ignore"):
+                pin()

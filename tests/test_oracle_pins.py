@@ -534,13 +534,16 @@ def _loss(w, G, overrides):
     return float((O.render(O.Scene(w, **overrides), want=("Ic",))["Ic"].reshape(G.shape) * G).sum())
 
 
-@pytest.mark.parametrize("clip", [False, True])
-def test_adjoint_matches_central_differences(clip):
+@pytest.mark.parametrize("clip,env", [(False, 0.0), (True, 0.0), (False, 0.4)])
+def test_adjoint_matches_central_differences(clip, env):
     """64 random parameters, central differences h = 1e-3 of the frozen-path estimator
-    (directions sampled with the unperturbed roughness)."""
+    (directions sampled with the unperturbed roughness); with env > 0 every vertex also
+    samples the environment (GGX lobes, occlusion by the cube), so the adjoint of that
+    next-event term is checked as well."""
     w = scenes.c3_ggx(spp=3, seed=17)
     w.clip = clip
     w.clip_k = 0.35 if clip else 1.0
+    w.env = np.array([1.0, 0.8, 0.6]) * env
     rng = np.random.default_rng(302)
     G = rng.normal(size=(64, 64, 3))
     base = dict(proj_image=w.proj_image.astype(np.float64), albedo=w.albedo.astype(np.float64),
