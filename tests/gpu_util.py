@@ -64,8 +64,9 @@ class GpuRun:
 
 
 def compare_forward(gpu, ref, pixels=None, gain=1.0, rtol=1e-4, min_clean=0.95):
-    """Parity on clean samples: identical hit triangles per vertex, and radiance within
-    rtol relative to the radiance vector's largest channel (infinity norm over RGB).
+    """Parity on clean samples: identical hit triangles per vertex, and radiance per
+    channel within |gpu - ref| <= rtol |ref| + 1e-7 g_p (g_p = gain, the projector gain
+    that scales every radiance).
 
     gpu: full-image results; ref: oracle results for `pixels` (None: all pixels).
     Returns (clean fraction, max relative error per sample, per pixel).
@@ -79,7 +80,9 @@ def compare_forward(gpu, ref, pixels=None, gain=1.0, rtol=1e-4, min_clean=0.95):
     floor = 1e-7 * gain
 
     def rel(a, b):
-        return np.abs(a - b).max(-1) / np.maximum(np.abs(b).max(-1), floor)
+        # per channel |a - b| / (|b| + floor / rtol): at most rtol exactly when
+        # |a - b| <= rtol |b| + floor; the worst channel of each sample or pixel
+        return (np.abs(a - b) / (np.abs(b) + floor / rtol)).max(-1)
 
     rs = rel(gpu["L"][idx].astype(np.float64), ref["L"])
     worst_s = float(rs[clean].max()) if clean.any() else 0.0

@@ -151,26 +151,28 @@ def test_scene_in_use_cannot_be_destroyed():
 def test_retraced_adjoint_in_the_mix():
     """Compensation steps whose paths are too deep for the wave's path records (depth 10,
     records hold 8 vertices per path): the loop re-traces their adjoint instead of
-    replaying records; each result still equals the request run alone."""
+    replaying records; each result still equals the request run alone.  Each request
+    alone (128^2 x 16 samples) fills a wave, so its first wave re-traces whatever the
+    arrival timing."""
     import torch
     from paper_2503_12174_amd import dpcs
     scenes, albedo, rough, spec = _setup(1)
     reqs = []
     for k in range(4):
-        w = synth.corner_50k(spp=16, max_depth=10, res=64, n_quads=8)
+        w = synth.corner_50k(spp=16, max_depth=10, res=128, n_quads=8)
         w.projector = synth.pinhole((0.85, 0.15, 0.85), (0.3, 0.0, 0.3), 45.0, 64, 64)
         w.seed = 40 + k
         p = dpcs.params_from(w, albedo, rough, spec)
         ip = dev(synth.blob_image(64, 64, 300 + k), torch.float32)
-        out = torch.zeros((64, 64, 3), device="cuda")
-        target = dev(synth.blob_image(64, 64, 400 + k, lo=0.1, hi=0.9), torch.float32)
+        out = torch.zeros((128, 128, 3), device="cuda")
+        target = dev(synth.blob_image(128, 128, 400 + k, lo=0.1, hi=0.9), torch.float32)
         grads = dict(d_proj_image=torch.zeros_like(ip), d_albedo=torch.zeros_like(albedo),
                      d_roughness=torch.zeros_like(rough), d_specular=torch.zeros_like(spec),
                      d_scalars=torch.zeros(18, device="cuda"))
         reqs.append((k, w, p, ip, out, target, grads))
     torch.cuda.synchronize()
-    # 512 MiB: ~228k paths per wave, records for 8 x that many vertices; four requests of
-    # 64^2 x 16 samples fill a wave with adjoint paths needing 10 vertices each
+    # 512 MiB: ~228k paths per wave, records for 8 x that many vertices; a request of
+    # 128^2 x 16 = 262k samples fills a wave with adjoint paths needing 10 vertices each
     srv = dpcs.Server(ctx(), budget_bytes=512 << 20, max_slots=8)
     for k, w, p, ip, out, target, grads in reqs:
         assert srv.submit(k, scenes[0], p, ip, out, target=target, grads=grads) == dpcs.OK
@@ -181,11 +183,11 @@ def test_retraced_adjoint_in_the_mix():
     srv.close()
     for k, w, p, ip, out, target, grads in reqs:
         alone = torch.zeros_like(out)
-        L = torch.zeros((64, 64, w.spp, 3), device="cuda")
+        L = torch.zeros((128, 128, w.spp, 3), device="cuda")
         dpcs.dpcs_render(ctx(), scenes[0], p, ip, alone, sample_radiance=L)
         ctx().synchronize()
         np.testing.assert_array_equal(out.cpu().numpy(), alone.cpu().numpy(), err_msg=f"request {k}")
-        G = 2.0 * (alone - target) / (3 * 64 * 64)
+        G = 2.0 * (alone - target) / (3 * 128 * 128)
         g2 = {k2: torch.zeros_like(v) for k2, v in grads.items()}
         dpcs.dpcs_render_vjp(ctx(), scenes[0], p, ip, G.contiguous(), sample_radiance=L, **g2)
         ctx().synchronize()
