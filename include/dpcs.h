@@ -168,6 +168,25 @@ typedef struct {
 DPCS_API dpcs_status dpcs_render(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
                         const float* proj_image, float* out_image, const dpcs_render_aux* aux);
 
+/* dpcs_render for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, same
+ * checks and the same results bit for bit (the same samples, summed in the same order);
+ * the call itself allocates nothing: E_p, the packed maps and the launch wave's queues
+ * (with the traversal's stack spill space) are carved from a static device array of
+ * DPCS_NOALLOC_SCRATCH_BYTES that every GPU the library runs on holds from context
+ * creation until the process ends, and each wave holds as many paths as fit (at most
+ * the context's capacity).  Profiling is suspended during the call.
+ * Limit: 16 bytes per projector pixel + 16 bytes per map texel + 508 bytes per camera
+ * sample of one pixel must fit in the array, else DPCS_E_INVALID before any launch.
+ * Every call on a device shares that device's array and leaves its contents there (all
+ * of it is written before it is read, nothing has to start at zero): calls on one device
+ * whose work overlaps on the GPU (different streams, e.g. two contexts) race; order them
+ * on one stream or synchronise between them.  DPCS_E_DEVICE if the array's address could
+ * not be looked up when the context was created. */
+enum { DPCS_NOALLOC_SCRATCH_BYTES = 64 << 20 };
+DPCS_API dpcs_status dpcs_render_noalloc(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
+                                         const float* proj_image, float* out_image, const dpcs_render_aux* aux);
+
 /* Gradient buffers of dpcs_render_vjp (device pointers, OVERWRITTEN, any may be NULL). */
 typedef struct {
     float* d_proj_image;        /* Hp x Wp x 3 */

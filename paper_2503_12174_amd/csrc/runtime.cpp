@@ -8,11 +8,23 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
-#include <limits>
 #include <deque>
+#include <limits>
+#include <mutex>
+#include <string>
 #include <vector>
 
 using namespace dpcs;
+
+// Scratch of dpcs_render_noalloc: one copy per device, held until the process ends.  Host
+// code never uses this name as an address (here it is a host-side stand-in); the device
+// address of each GPU's copy is looked up once per device at context creation and kept in
+// noalloc_ptr.
+constexpr size_t NOALLOC_BYTES = size_t(DPCS_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char noalloc_scratch[NOALLOC_BYTES];
+static std::mutex noalloc_mu;
+static std::vector<void*> noalloc_ptr;          // per device, null until looked up
+static std::vector<hipError_t> noalloc_status;  // per device: result of the lookup
 
 namespace dpcs {
 
@@ -60,13 +72,15 @@ void* scratch(dpcs_context ctx, const char* name, size_t bytes, dpcs_status* st)
     return p;
 }
 
-bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpcs_status* st) {
+size_t queue_bytes(int64_t cap, int trace_blocks) {
+    // per path: 2 x (PathO 32 + PathD 32 + beta 16) + hit 4 + 2 x shadow (48 + 4) + L 16,
+    // the traversal spill region of trace_blocks workgroups, and 256 bytes of alignment
+    // slack per part (18 parts)
+    return (size_t)cap * (2 * 80 + 4 + 2 * 52 + 16) + 4 * (size_t)trace_blocks * TRACE_TB * SPILL + 32 * 256;
+}
+
+void carve_queues(char* b, int64_t cap, int trace_blocks, Queues& q) {
     const size_t c = (size_t)cap;
-    // per path: 2 x (PathO 32 + PathD 32 + beta 16) + hit 4 + 2 x shadow (48 + 4) + L 16
-    // + 256 bytes of alignment slack per part (18 parts)
-    const size_t bytes = c * (2 * 80 + 4 + 2 * 52 + 16) + 4 * spill_ints(ctx->grid_cap, TRACE_ROUNDS) + 32 * 256;
-    char* b = (char*)scratch(ctx, name, bytes, st);
-    if (!b) return false;
     auto take = [&](size_t n) {   // 256-byte aligned parts
         char* p = b;
         b += (n + 255) & ~size_t(255);
@@ -84,10 +98,17 @@ bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpc
     q.hit = (int*)take(4 * c);
     q.L = (float4*)take(16 * c);
     q.cnt = (uint32_t*)take(16);
-    q.spill = (int*)take(4 * spill_ints(ctx->grid_cap, TRACE_ROUNDS));
-    q.trace_blocks = trace_grid_cap(ctx->grid_cap, TRACE_ROUNDS);
+    q.spill = (int*)take(4 * (size_t)trace_blocks * TRACE_TB * SPILL);
+    q.trace_blocks = trace_blocks;
     q.cap = cap;
     q.stats = nullptr;
+}
+
+bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpcs_status* st) {
+    const int tb = trace_grid_cap(ctx->grid_cap, TRACE_ROUNDS);
+    char* b = (char*)scratch(ctx, name, queue_bytes(cap, tb), st);
+    if (!b) return false;
+    carve_queues(b, cap, tb, q);
     return true;
 }
 
@@ -325,8 +346,27 @@ extern "C" dpcs_status dpcs_context_create(int32_t device, void* hip_stream, siz
         return DPCS_E_INVALID;
     }
     if (hipSetDevice(device) != hipSuccess) return DPCS_E_DEVICE;
+    hipError_t na = hipSuccess;
+    void* na_ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(noalloc_mu);
+        if ((int)noalloc_ptr.size() < n) {
+            noalloc_ptr.resize(n, nullptr);
+            noalloc_status.resize(n, hipErrorNotReady);
+        }
+        if (!noalloc_ptr[device]) {
+            void* p = nullptr;
+            noalloc_status[device] = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+            if (noalloc_status[device] == hipSuccess) noalloc_ptr[device] = p;
+            else (void)hipGetLastError();
+        }
+        na = noalloc_status[device];
+        na_ptr = noalloc_ptr[device];
+    }
     auto* c = new dpcs_context_s();
     c->device = device;
+    c->noalloc = na_ptr;
+    c->noalloc_err = (int)na;
     c->stream = (hipStream_t)hip_stream;
     c->scratch_limit = scratch_limit_bytes;
     hipDeviceProp_t prop;
@@ -893,8 +933,11 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
 
 }  // namespace dpcs
 
-extern "C" dpcs_status dpcs_render(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
-                                   const float* proj_image, float* out_image, const dpcs_render_aux* aux) {
+// The forward render (Eq. 7) in launch waves of whole pixels.  noalloc: the PRF'd
+// projector image, the packed maps and the wave's queues are carved from this device's
+// copy of noalloc_scratch instead of the context's pool, and the wave shrinks to fit.
+static dpcs_status render_impl(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
+                               const float* proj_image, float* out_image, const dpcs_render_aux* aux, bool noalloc) {
     if (!ctx) return DPCS_E_INVALID;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (ctx->sticky) return DPCS_E_DEVICE;
@@ -904,7 +947,6 @@ extern "C" dpcs_status dpcs_render(dpcs_context ctx, dpcs_scene scene, const dpc
     ReqDesc r;
     std::string why;
     if (!fill_desc(ctx, r, params, scene, proj_image, &why)) return fail(ctx, DPCS_E_INVALID, why);
-    if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
     r.out_image = out_image;
     if (aux) {
         r.out_linear = aux->linear;
@@ -914,17 +956,62 @@ extern "C" dpcs_status dpcs_render(dpcs_context ctx, dpcs_scene scene, const dpc
         r.rec_g0 = 0;
     }
     if (r.rec && scene->nt >= (int)REC_LEAF) return fail(ctx, DPCS_E_UNSUPPORTED, "path records need < 2^30 triangles");
-    dpcs_status st = DPCS_OK;
-    if (!prepare_request(ctx, r, params, "fwd", &st)) return st;
     const int64_t npix = (int64_t)r.Wc * r.Hc;
-    const int64_t cap = std::min<int64_t>(std::max<int64_t>(ctx->capacity, r.spp), npix * r.spp);
-    const int64_t ppw = std::max<int64_t>(1, cap / r.spp);   // whole pixels per wave
+    int64_t cap = std::min<int64_t>(std::max<int64_t>(ctx->capacity, r.spp), npix * r.spp);
     Queues q;
-    if (!make_queues(ctx, "fwd.queues", ppw * r.spp, q, &st)) return st;
+    float4 *na_Ep = nullptr, *na_tex = nullptr;
+    if (noalloc) {
+        if (!ctx->noalloc)
+            return fail(ctx, DPCS_E_DEVICE, std::string("no-alloc scratch of this device unavailable: ") +
+                                                hipGetErrorString((hipError_t)ctx->noalloc_err));
+        const size_t ep_b = (sizeof(float4) * (size_t)r.Wp * r.Hp + 255) & ~size_t(255);
+        const size_t tex_b = (sizeof(float4) * (size_t)r.tw * r.th + 255) & ~size_t(255);
+        // every path takes its queue entries and a traversal thread's spill space
+        const size_t per_path = queue_bytes(1, 0) - 32 * 256 + 4 * (size_t)SPILL;
+        const size_t fixed = 32 * 256 + 4 * (size_t)TRACE_TB * SPILL;
+        if (ep_b + tex_b + fixed + per_path * (size_t)r.spp > NOALLOC_BYTES)
+            return fail(ctx, DPCS_E_INVALID, "dpcs_render_noalloc: projector image, maps and one pixel's samples exceed "
+                                             "the " + std::to_string(NOALLOC_BYTES >> 20) + " MiB no-alloc scratch");
+        cap = std::min<int64_t>(cap, (int64_t)((NOALLOC_BYTES - ep_b - tex_b - fixed) / per_path));
+        cap = std::max<int64_t>(r.spp, cap / r.spp * r.spp);
+        const int tb = (int)((cap + TRACE_TB - 1) / TRACE_TB);
+        char* base = (char*)ctx->noalloc;
+        na_Ep = (float4*)base;
+        na_tex = (float4*)(base + ep_b);
+        r.Ep = na_Ep;
+        r.tex4 = na_tex;
+        if (ep_b + tex_b + queue_bytes(cap, tb) > NOALLOC_BYTES)
+            return fail(ctx, DPCS_E_INVALID, "dpcs_render_noalloc: internal sizing error");
+        carve_queues(base + ep_b + tex_b, cap, tb, q);
+    }
+    if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
+    dpcs_status st = DPCS_OK;
+    const int prof_mode = ctx->prof_mode;
+    if (noalloc) {
+        Launch l{ctx->stream, ctx->grid_cap};
+        launch_prf(l, r, na_Ep);
+        launch_pack_tex(l, r, params->albedo, params->brdf == DPCS_BRDF_GGX ? params->roughness : nullptr, na_tex);
+        ctx->prof_mode = 0;   // profiling records events and pinned counts; not on this path
+    } else {
+        if (!prepare_request(ctx, r, params, "fwd", &st)) return st;
+        if (!make_queues(ctx, "fwd.queues", cap, q, &st)) return st;
+    }
+    const int64_t ppw = std::max<int64_t>(1, cap / r.spp);   // whole pixels per wave
     for (int64_t a = 0; a < npix; a += ppw) forward_wave(ctx, q, r, (uint32_t)a, (uint32_t)std::min(npix, a + ppw), true);
+    ctx->prof_mode = prof_mode;
     if (!hip_ok(ctx, hipGetLastError(), "kernel launch")) return DPCS_E_DEVICE;
     ctx->err.clear();
     return DPCS_OK;
+}
+
+extern "C" dpcs_status dpcs_render(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
+                                   const float* proj_image, float* out_image, const dpcs_render_aux* aux) {
+    return render_impl(ctx, scene, params, proj_image, out_image, aux, false);
+}
+
+extern "C" dpcs_status dpcs_render_noalloc(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,
+                                           const float* proj_image, float* out_image, const dpcs_render_aux* aux) {
+    return render_impl(ctx, scene, params, proj_image, out_image, aux, true);
 }
 
 extern "C" dpcs_status dpcs_render_gbuffer(dpcs_context ctx, dpcs_scene scene, const dpcs_render_params* params,

@@ -37,6 +37,8 @@ struct dpcs_context_s {
     uint32_t* pinned = nullptr;            // queue-size snapshots
     int pinned_cap = 0, pinned_used = 0;
     unsigned long long* dstats = nullptr;  // device [DPCS_NUM_STAGES][2]
+    void* noalloc = nullptr;               // this device's copy of the no-alloc scratch array
+    int noalloc_err = 0;                   // hipError_t of its address lookup
 };
 
 struct dpcs_scene_s {
@@ -80,6 +82,10 @@ unsigned long long* prof_stats(dpcs_context ctx, int stage);
 
 // path queues for `cap` paths carved from one scratch buffer (prefix selects the buffer)
 bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpcs_status* st);
+// bytes of the queues of `cap` paths with a traversal grid capped at trace_blocks
+// workgroups, and their layout from base (256-byte aligned)
+size_t queue_bytes(int64_t cap, int trace_blocks);
+void carve_queues(char* base, int64_t cap, int trace_blocks, Queues& q);
 bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues& aq, dpcs_status* st);
 void make_map_bins(dpcs_context ctx, const Launch& l, MapBins& mb, const char* name, int W, int H, int C, int RS,
                    int64_t cap);

@@ -18,6 +18,7 @@ OK, E_INVALID, E_OOM, E_DEVICE, E_UNSUPPORTED, E_BUSY, E_REJECTED = 0, -1, -2, -
 STATUS = {0: "OK", -1: "INVALID", -2: "OOM", -3: "DEVICE", -4: "UNSUPPORTED", -5: "BUSY", -6: "REJECTED"}
 LAMBERT, GGX = 0, 1
 NUM_SCALARS = 18
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class DpcsError(RuntimeError):
@@ -112,7 +113,7 @@ SYMBOLS = ["dpcs_context_create", "dpcs_context_destroy", "dpcs_last_error", "dp
            "dpcs_context_set_profiling", "dpcs_context_get_profile", "dpcs_server_create",
            "dpcs_server_submit", "dpcs_server_poll", "dpcs_server_stats", "dpcs_server_destroy",
            "dpcs_denoise", "dpcs_denoise_vjp", "dpcs_render_gbuffer", "dpcs_tv_loss", "dpcs_tv_vjp",
-           "dpcs_l1_loss", "dpcs_l1_vjp"]
+           "dpcs_l1_loss", "dpcs_l1_vjp", "dpcs_render_noalloc"]
 
 _lib = None
 
@@ -135,6 +136,7 @@ def lib():
             "dpcs_scene_get_info": ([P, C.POINTER(SceneInfo)], S),
             "dpcs_scene_destroy": ([P], S),
             "dpcs_render": ([P, P, C.POINTER(RenderParams), P, P, C.POINTER(RenderAux)], S),
+            "dpcs_render_noalloc": ([P, P, C.POINTER(RenderParams), P, P, C.POINTER(RenderAux)], S),
             "dpcs_render_vjp": ([P, P, C.POINTER(RenderParams), P, P, P, P, C.POINTER(Grads)], S),
             "dpcs_debug_intersect": ([P, P, P, I64, I32, P, P, P, P], S),
             "dpcs_debug_philox": ([P, C.c_uint64, P, I64, P], S),
@@ -296,6 +298,13 @@ def dpcs_render(ctx: Context, scene: Scene, params: RenderParams, proj_image, ou
     aux = RenderAux(_ptr(linear), _ptr(sample_radiance), _ptr(hit_prims), _ptr(path_records))
     return ctx.check(lib().dpcs_render(ctx.h, scene.h, C.byref(params), _ptr(proj_image), _ptr(out_image),
                                        C.byref(aux)))
+
+
+def dpcs_render_noalloc(ctx: Context, scene: Scene, params: RenderParams, proj_image, out_image, linear=None,
+                        sample_radiance=None, hit_prims=None, path_records=None):
+    aux = RenderAux(_ptr(linear), _ptr(sample_radiance), _ptr(hit_prims), _ptr(path_records))
+    return ctx.check(lib().dpcs_render_noalloc(ctx.h, scene.h, C.byref(params), _ptr(proj_image),
+                                               _ptr(out_image), C.byref(aux)))
 
 
 def dpcs_render_vjp(ctx: Context, scene: Scene, params: RenderParams, proj_image, grad_image, sample_radiance=None,
