@@ -8,7 +8,9 @@ vector-Jacobian product by path replay of the same samples.
 Prints ONE JSON line.  Inputs are synthetic and resident in HBM before timing.
   value          path samples/s of the timed fwd+VJP steps (fwd_samples_per_s: forward alone)
   roofline       live HIP-event timing of the dominant kernel (closest-hit
-                 traversal) against its algorithmic bytes (HBM bound)
+                 traversal) against its algorithmic operations and the vector-ALU
+                 issue peak (its DRAM traffic is ~0.1 of HBM: the tree lives in L2 / MALL),
+                 with the HBM byte model and the counters' DRAM bytes beside it
   cpu_baseline   the FP64 CPU oracle timed on a bounded pixel sample
   objective      the training objective's operators (denoiser D and its VJP, guide
                  features, L1 data term, map regulariser), timed apart from the step
@@ -29,7 +31,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "path samples/s fwd and fwd+adjoint (1 GPU, ≤1e-4 rel err); p50/p99 relight latency"
 HBM_PEAK_GBS = 8000.0
+# vector ALU issue of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit VALU
+# operation per lane per clock (the published 157.3 TFLOP/s counts an FMA as two flops and
+# packed FP32 as two lanes' worth, neither of which a traversal loop issues)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_traffic_corner50k_256px.md")
+COUNTER_FILE = os.path.join(ROOT, "profiles", "hot_kernel_counters_corner50k_256px.md")
 KERNEL_SOURCES = ["render.hip", "trace.hpp", "shade.hpp", "common.hpp"]
 
 
@@ -52,6 +59,18 @@ UV_BYTES = 32          # corner UVs of a triangle
 SHADE_STATE_IN = 84    # PathO + PathD + throughput + hit index
 PATH_STATE = 80        # PathO + PathD + throughput written for a continuing path
 SHADOW_RECORD = 52     # shadow origin, direction, contribution float4s + t_max
+
+# algorithmic FP32 operations of one closest-hit query (each add, mul, FMA, min, max,
+# compare or select is one operation; a component permutation is a register choice):
+#   per ray      box setup (3 reciprocals, 3 products, 3 error bounds, 6 offsets), the
+#                watertight setup (axis choice 4, 3 quotients), the exact test of the
+#                winner for t and the barycentrics (33 + 3) = 15 + 7 + 36
+#   per node     4 children x (6 slab FMAs, 4 ops of the two 3-way max / min, 2 widenings,
+#                2 clamps, 1 compare) + 5 compare-exchanges ordering the children (3 each)
+#   per triangle 9 subtractions, 6 FMAs of the shear, 6 of the edge functions, 2 of the
+#                sign test, 2 for the determinant, 3 for T, 3 for t = T Sz / det, 2 range
+#                compares
+OPS_RAY, OPS_NODE4, OPS_NODE2, OPS_TRI = 58, 75, 31, 33
 
 
 def parse():
@@ -421,21 +440,42 @@ def main():
         per_ray = RAY_IO_BYTES + node_bytes * nodes_per_ray + TRI_BYTES * tris_per_ray
         rays_per_launch = tr["items"] / max(tr["launches"], 1)
         avg_ms = tr["ms"] / max(tr["launches"], 1)
-        achieved = per_ray * rays_per_launch / (avg_ms * 1e-3) / 1e9
-        traffic = None
-        if os.path.exists(TRAFFIC_FILE):
-            # the summary ends with a fenced json block: kernel_hash, bytes_per_launch
-            txt = open(TRAFFIC_FILE).read()
-            blk = txt.rsplit("```json", 1)[-1].split("```", 1)[0] if "```json" in txt else "{}"
-            tf = json.loads(blk)
-            if tf.get("kernel_hash") == kernel_hash():
-                traffic = tf.get("bytes_per_launch")
-        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        model_GBps = per_ray * rays_per_launch / (avg_ms * 1e-3) / 1e9
+        ops_per_ray = OPS_RAY + (OPS_NODE4 if info.wide_nodes else OPS_NODE2) * nodes_per_ray + OPS_TRI * tris_per_ray
+        achieved = ops_per_ray * rays_per_launch / (avg_ms * 1e-3) / 1e12
+
+        def summary_json(path):
+            """The fenced json block that ends a profile summary, if it was taken on
+            the kernels as they are now (same source hash), else None."""
+            if not os.path.exists(path):
+                return None
+            txt = open(path).read()
+            if "```json" not in txt:
+                return None
+            blk = json.loads(txt.rsplit("```json", 1)[-1].split("```", 1)[0])
+            return blk if blk.get("kernel_hash") == kernel_hash() else None
+
+        tf = summary_json(TRAFFIC_FILE)
+        traffic = tf.get("bytes_per_launch") if tf else None
+        cf = summary_json(COUNTER_FILE)
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s",
+                "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": traffic,
                 "kernel": "k_trace (closest-hit traversal, %s BVH)" % ("4-wide" if info.wide_nodes else "binary"),
-                "bytes_per_ray": round(per_ray, 1), "nodes_per_ray": round(nodes_per_ray, 2),
+                "ops_per_ray": round(ops_per_ray, 1), "nodes_per_ray": round(nodes_per_ray, 2),
                 "tris_per_ray": round(tris_per_ray, 2), "rays_per_launch": round(rays_per_launch),
-                "avg_launch_ms": round(avg_ms, 4)}
+                "avg_launch_ms": round(avg_ms, 4),
+                "hbm_model_bytes_per_ray": round(per_ray, 1), "hbm_model_GBps": round(model_GBps, 1)}
+        if traffic:
+            roof["dram_GBps"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+            roof["dram_frac"] = round(roof["dram_GBps"] / HBM_PEAK_GBS, 4)
+        if cf:
+            # the issue-bound decomposition from the counters of the same kernel:
+            # frac ~= VALU busy x lane utilisation x (algorithmic / issued lane operations)
+            issued = cf["valu_insts_per_launch"] * 64 * cf["lane_util"] / rays_per_launch
+            roof.update(valu_busy=cf["valu_busy"], lane_util=cf["lane_util"],
+                        valu_wave_insts_per_ray=round(cf["valu_insts_per_launch"] / rays_per_launch, 2),
+                        valu_lane_ops_per_node=round(issued / max(nodes_per_ray, 1e-9), 1),
+                        algorithmic_per_issued=round(ops_per_ray / issued, 3))
         stages = {k: {"launches": v["launches"], "ms": round(v["ms"], 3), "items": v["items"]}
                   for k, v in prof.items() if v["launches"]}
         sh = vis["shadow"]
@@ -464,7 +504,8 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         roof["copy_GBps"] = round(5 * 2 * x.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
-        roof["frac_of_copy"] = round(achieved / roof["copy_GBps"], 4)
+        if traffic:
+            roof["dram_frac_of_copy"] = round(roof["dram_GBps"] / roof["copy_GBps"], 4)
         del x, y
 
     if a.calib_copy:
@@ -510,7 +551,14 @@ def main():
         t = time.perf_counter()
         oracle_step(order[8:8 + n])
         dt = time.perf_counter() - t
+        model = "unknown"
+        if os.path.exists("/proc/cpuinfo"):
+            for ln in open("/proc/cpuinfo"):
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
         cpu = {"value": round(n * w.spp / dt, 2), "unit": "samples/s", "cores": O.threads(sc), "kind": "oracle",
+               "cpu_model": model, "host_cpus": os.cpu_count(),
                "sample": f"forward + VJP of {n} random pixels x {w.spp} spp of the same scene "
                          f"({n * w.spp} samples, {dt:.1f} s)"}
         print(f"[bench] oracle {cpu['value']:.1f} samples/s on {cpu['cores']} threads", file=sys.stderr, flush=True)
