@@ -82,8 +82,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--quick", action="store_true", help="skip the profiled passes")
-    ap.add_argument("--serving-requests", type=int, default=300, help="0 disables the serving run")
+    ap.add_argument("--serving-requests", type=int, default=2000, help="0 disables the serving run")
     ap.add_argument("--serving-alone", type=int, default=60, help="requests also timed alone")
+    ap.add_argument("--no-serving-sweep", action="store_true", help="skip the serving runs at higher rates")
     ap.add_argument("--no-objective", action="store_true", help="skip the training-objective operators")
     ap.add_argument("--no-configs", action="store_true", help="skip the other setups (quad+cube, 200k corner, fit)")
     return ap.parse_args()
@@ -258,10 +259,13 @@ def configs_bench(ctx, steps=5):
     return res
 
 
-def serving_bench(ctx, n_req, n_alone, warmup=20, rate=50.0):
-    """Serving run: 4 resident corners (10k/50k/200k/500k triangles),
-    Poisson arrivals, resolution in {128, 256, 512}^2, spp in {16, 64, 256}, depth 4,
-    half relighting and half compensation steps (fwd + VJP of an L2 loss)."""
+def serving_bench(ctx, n_req, n_alone, warmup=100, rate=50.0, sweep=(30.0, 40.0, 100.0, 200.0), n_sweep=400):
+    """Serving run: 4 resident corners (10k/50k/200k/500k triangles), Poisson arrivals,
+    resolution in {128, 256, 512}^2, spp in {16, 64, 256}, depth 4, half relighting and
+    half compensation steps (fwd + VJP of an L2 loss).  n_req requests after `warmup` at
+    `rate` req/s, then shorter runs at the `sweep` rates (n_sweep requests each after 50
+    warm-up) for the highest rate whose p99 stays bounded, then n_alone of the same
+    requests alone through the plain entry points."""
     import threading
 
     import numpy as np
@@ -274,58 +278,94 @@ def serving_bench(ctx, n_req, n_alone, warmup=20, rate=50.0):
     scenes = [dpcs.Scene(ctx, m, bvh="sah") for m in meshes]
     infos = [sc.info() for sc in scenes]
     alb, rough, spec = (torch.as_tensor(x).cuda() for x in synth.ggx_textures(503, 512))
-    reqs = synth.serving_requests(warmup + n_req, seed=501, rate=rate)
-    prep = []
-    for k, rq in enumerate(reqs):
-        res = rq["res"]
-        w = synth.corner_50k(spp=rq["spp"], max_depth=rq["depth"], res=res)
-        w.mesh = meshes[rq["scene"]]
+    # inputs and outputs from pools (16 images per resolution; one output set per
+    # request slot of 128 in rotation: requests 128 apart are never in flight together
+    # below the saturated rates, and above them only the timing is read)
+    pool = {}
+    for res in (128, 256, 512):
+        rng = np.random.default_rng(res)
+        pool[res] = dict(
+            ip=[torch.as_tensor(rng.uniform(0, 1, (res, res, 3)).astype(np.float32)).cuda() for _ in range(16)],
+            target=[torch.as_tensor(synth.blob_image(res, res, 700 + k, lo=0.1, hi=0.9)).cuda() for k in range(4)])
+    outs = {}
+
+    def out_for(k, res, comp):
+        key = (k % 128, res)
+        if key not in outs:
+            outs[key] = dict(out=torch.zeros((res, res, 3), device="cuda"),
+                             grads=dict(d_proj_image=torch.zeros((res, res, 3), device="cuda"),
+                                        d_albedo=torch.zeros_like(alb), d_roughness=torch.zeros_like(rough),
+                                        d_specular=torch.zeros_like(spec), d_scalars=torch.zeros(18, device="cuda")))
+        o = outs[key]
+        return o["out"], (o["grads"] if comp else None)
+
+    templates = {}
+    for res in (128, 256, 512):   # camera, projector and response parameters per resolution
+        w = synth.corner_50k(res=res)
         w.projector = synth.pinhole((0.85, 0.15, 0.85), (0.3, 0.0, 0.3), 45.0, res, res)
-        w.seed = k
-        p = dpcs.params_from(w, alb, rough, spec)
-        ip = torch.as_tensor(np.random.default_rng(rq["image_seed"]).uniform(0, 1, (res, res, 3)).astype(np.float32)).cuda()
-        out = torch.zeros((res, res, 3), device="cuda")
-        grads = target = None
-        if rq["compensation"]:
-            target = torch.as_tensor(synth.blob_image(res, res, rq["image_seed"] % 1000, lo=0.1, hi=0.9)).cuda()
-            grads = dict(d_proj_image=torch.zeros_like(ip), d_albedo=torch.zeros_like(alb),
-                         d_roughness=torch.zeros_like(rough), d_specular=torch.zeros_like(spec),
-                         d_scalars=torch.zeros(18, device="cuda"))
-        prep.append((k, rq, p, ip, out, target, grads, res * res * rq["spp"]))
-    torch.cuda.synchronize()
+        templates[res] = w
+
+    def prepare(reqs):
+        prep = []
+        for k, rq in enumerate(reqs):
+            res = rq["res"]
+            p = dpcs.params_from(templates[res], alb, rough, spec, spp=rq["spp"], max_depth=rq["depth"], seed=k)
+            ip = pool[res]["ip"][rq["image_seed"] % 16]
+            out, grads = out_for(k, res, rq["compensation"])
+            target = pool[res]["target"][rq["image_seed"] % 4] if rq["compensation"] else None
+            prep.append((k, rq, p, ip, out, target, grads, res * res * rq["spp"]))
+        return prep
+
+    def run(reqs, warmup):
+        prep = prepare(reqs)
+        torch.cuda.synchronize()
+        srv = dpcs.Server(ctx, budget_bytes=64 << 30, max_slots=64)
+        lat = {}
+        t0 = time.perf_counter()
+
+        def client():
+            for k, rq, p, ip, out, target, grads, _ in prep:
+                dt = rq["arrival"] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                st = srv.submit(k, scenes[rq["scene"]], p, ip, out, target=target, grads=grads)
+                if st != dpcs.OK:
+                    lat[k] = None
+
+        th = threading.Thread(target=client)
+        th.start()
+        last_print = time.perf_counter()
+        while len(lat) < len(prep):
+            for k, st, ms in srv.poll():
+                lat[k] = ms if st == dpcs.OK else None
+            if time.perf_counter() - last_print > 10:
+                print(f"[bench] serving: {len(lat)}/{len(prep)} done", file=sys.stderr, flush=True)
+                last_print = time.perf_counter()
+            time.sleep(0.001)
+        th.join()
+        wall = time.perf_counter() - t0
+        stats = srv.stats()
+        srv.close()
+        measured = [k for k, *_ in prep[warmup:]]
+        ok = [lat[k] for k in measured if lat[k] is not None]
+        span = wall - reqs[warmup]["arrival"]
+        samples = sum(x[-1] * (2 if x[1]["compensation"] else 1) for x in prep[warmup:])
+        offered = sum(x[-1] * (2 if x[1]["compensation"] else 1) for x in prep) / reqs[-1]["arrival"]
+        done = max(stats["completed"], 1)
+        return prep, {
+            "requests": len(measured), "warmup_requests": warmup, "completed_ok": len(ok),
+            "p50_ms": round(float(np.percentile(ok, 50)), 2), "p99_ms": round(float(np.percentile(ok, 99)), 2),
+            "mean_ms": round(float(np.mean(ok)), 2), "achieved_req_s": round(len(ok) / span, 2),
+            "samples_per_s": round(samples / span, 1), "offered_samples_per_s": round(offered, 1),
+            "mean_queue_wait_ms": round(stats["wait_us"] / done / 1e3, 3),
+            "mean_admit_to_first_wave_ms": round(stats["admit_us"] / done / 1e3, 3),
+            "mean_first_wave_to_done_ms": round(stats["run_us"] / done / 1e3, 3),
+            "waves": stats["waves"], "peak_admitted_bytes": stats["peak_bytes"]}
+
     setup_s = time.perf_counter() - t
-
-    srv = dpcs.Server(ctx, budget_bytes=64 << 30, max_slots=64)
-    lat = {}
-    t0 = time.perf_counter()
-
-    def client():
-        for k, rq, p, ip, out, target, grads, _ in prep:
-            dt = rq["arrival"] - (time.perf_counter() - t0)
-            if dt > 0:
-                time.sleep(dt)
-            st = srv.submit(k, scenes[rq["scene"]], p, ip, out, target=target, grads=grads)
-            if st != dpcs.OK:
-                lat[k] = None
-
-    th = threading.Thread(target=client)
-    th.start()
-    last_print = time.perf_counter()
-    while len(lat) < len(prep):
-        for k, st, ms in srv.poll():
-            lat[k] = ms if st == dpcs.OK else None
-        if time.perf_counter() - last_print > 20:
-            print(f"[bench] serving: {len(lat)}/{len(prep)} done", file=sys.stderr, flush=True)
-            last_print = time.perf_counter()
-        time.sleep(0.001)
-    th.join()
-    wall = time.perf_counter() - t0
-    stats = srv.stats()
-    srv.close()
-    measured = [k for k, *_ in prep[warmup:]]
-    ok = [lat[k] for k in measured if lat[k] is not None]
-    span = wall - reqs[warmup]["arrival"]
-    samples = sum(x[-1] * (2 if x[1]["compensation"] else 1) for x in prep[warmup:])
+    reqs = synth.serving_requests(warmup + n_req, seed=501, rate=rate)
+    prep, main = run(reqs, warmup)
+    main["rate_req_s"] = rate
 
     # the same requests alone through the plain entry points (a subset, back to back)
     alone = []
@@ -343,20 +383,32 @@ def serving_bench(ctx, n_req, n_alone, warmup=20, rate=50.0):
             dpcs.dpcs_render_vjp(ctx, sc, p, ip, G, sample_radiance=L, path_records=rc, **grads)
         ctx.synchronize()
         alone.append((time.perf_counter() - ta) * 1e3)
-    offered = sum(x[-1] * (2 if x[1]["compensation"] else 1) for x in prep) / reqs[-1]["arrival"]
-    return {
-        "requests": len(measured), "warmup_requests": warmup, "rate_req_s": rate, "completed_ok": len(ok),
-        "p50_ms": round(float(np.percentile(ok, 50)), 2), "p99_ms": round(float(np.percentile(ok, 99)), 2),
-        "mean_ms": round(float(np.mean(ok)), 2), "achieved_req_s": round(len(ok) / span, 2),
-        "samples_per_s": round(samples / span, 1), "offered_samples_per_s": round(offered, 1),
-        "alone_p50_ms": round(float(np.percentile(alone, 50)), 2),
-        "alone_p99_ms": round(float(np.percentile(alone, 99)), 2), "alone_requests": len(alone),
-        "waves": stats["waves"], "peak_admitted_bytes": stats["peak_bytes"],
-        "scenes_tris": [int(i.num_triangles) for i in infos], "scenes_wide_nodes": [int(i.wide_nodes) for i in infos],
-        "scenes_bvh_depth": [int(i.max_depth) for i in infos],
-        "bvh_build_ms": [round(i.build_ms, 2) for i in infos], "setup_s": round(setup_s, 1),
-        "note": "samples count fwd + replay for compensation steps; latency = submit to device completion",
-    }
+    alone_p99 = float(np.percentile(alone, 99))
+    main.update(alone_p50_ms=round(float(np.percentile(alone, 50)), 2), alone_p99_ms=round(alone_p99, 2),
+                alone_requests=len(alone))
+
+    # rate sweep: bounded = the loop keeps up (>= 95 % of the offered request rate) and
+    # p99 stays within 3x the p99 of the same request mix run alone
+    table = [{"rate_req_s": rate, "p50_ms": main["p50_ms"], "p99_ms": main["p99_ms"],
+              "achieved_req_s": main["achieved_req_s"], "samples_per_s": main["samples_per_s"]}]
+    for r in sweep:
+        rq = synth.serving_requests(50 + n_sweep, seed=601 + int(r), rate=r)
+        _, st = run(rq, 50)
+        table.append({"rate_req_s": r, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                      "achieved_req_s": st["achieved_req_s"], "samples_per_s": st["samples_per_s"]})
+        print(f"[bench] serving sweep {r} req/s: p50 {st['p50_ms']} p99 {st['p99_ms']} ms, "
+              f"{st['achieved_req_s']} req/s", file=sys.stderr, flush=True)
+    for row in table:
+        row["bounded"] = bool(row["achieved_req_s"] >= 0.95 * row["rate_req_s"] and row["p99_ms"] <= 3 * alone_p99)
+    ok_rates = [row["rate_req_s"] for row in table if row["bounded"]]
+    main.update(sweep=table, max_rate_bounded_p99=max(ok_rates) if ok_rates else None,
+                bounded_rule="achieved >= 0.95 x offered req/s and p99 <= 3 x alone p99",
+                scenes_tris=[int(i.num_triangles) for i in infos],
+                scenes_wide_nodes=[int(i.wide_nodes) for i in infos],
+                scenes_bvh_depth=[int(i.max_depth) for i in infos],
+                bvh_build_ms=[round(i.build_ms, 2) for i in infos], setup_s=round(setup_s, 1),
+                note="samples count fwd + replay for compensation steps; latency = submit to device completion")
+    return main
 
 
 def main():
@@ -528,7 +580,8 @@ def main():
 
     serving = None
     if a.serving_requests > 0:
-        serving = serving_bench(ctx, a.serving_requests, a.serving_alone)
+        serving = serving_bench(ctx, a.serving_requests, a.serving_alone,
+                                sweep=() if a.no_serving_sweep else (30.0, 40.0, 100.0, 200.0))
         print(f"[bench] serving p50 {serving['p50_ms']} ms p99 {serving['p99_ms']} ms", file=sys.stderr, flush=True)
 
     cpu = None

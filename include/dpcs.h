@@ -346,19 +346,29 @@ typedef struct {
     const float* target;
     const dpcs_grads* grads;
     uint64_t request_id;
+    void* input_stream;         /* HIP stream on which the caller produced the request's inputs
+                                   (projector image, maps, device scalars, target or cotangent);
+                                   NULL: the context's stream.  The request's first launch waits
+                                   for all work queued on it before the submit call. */
 } dpcs_request;
 
-/* Non-blocking.  DPCS_E_REJECTED if the request alone exceeds the budget. */
+/* Non-blocking.  DPCS_E_REJECTED if the request alone exceeds the budget.  While a
+ * request is alone in the loop its waves fill the whole capacity; while others are
+ * active or queued, waves are cut to at most 2^20 paths so a newcomer waits for short
+ * waves only. */
 DPCS_API dpcs_status dpcs_server_submit(dpcs_server srv, const dpcs_request* req);
 /* Non-blocking: up to max finished requests (ids, statuses, latency in ms from submit
  * to completion on the device; latency_ms may be NULL).  Returns the count. */
 DPCS_API int32_t dpcs_server_poll(dpcs_server srv, uint64_t* done_ids, int32_t* done_status, double* latency_ms,
                          int32_t max);
-/* Counters (out: 10 int64 on the host): [0] submitted, [1] completed, [2] rejected,
+/* Counters (out: 13 int64 on the host): [0] submitted, [1] completed, [2] rejected,
  * [3] active, [4] queued, [5] launch waves, [6] samples traced, [7] peak admitted bytes,
  * [8] waves whose compensation segments replayed path records, [9] waves whose
- * compensation segments re-traced (their paths did not fit the wave's records). */
-DPCS_API dpcs_status dpcs_server_stats(dpcs_server srv, int64_t* out10);
+ * compensation segments re-traced (their paths did not fit the wave's records), and
+ * the latency of the completed requests summed in microseconds, in three parts:
+ * [10] submit to admission (queued for memory or a slot), [11] admission to the launch
+ * of the request's first wave, [12] from there to completion on the device. */
+DPCS_API dpcs_status dpcs_server_stats(dpcs_server srv, int64_t* out13);
 /* Waits for every admitted request, then stops the loop. */
 DPCS_API dpcs_status dpcs_server_destroy(dpcs_server srv);
 

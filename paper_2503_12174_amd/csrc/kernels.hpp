@@ -75,8 +75,8 @@ constexpr int TRACE_TB = 128;                  // threads per workgroup of the t
 // is one resident round at 8 waves per SIMD); the spill region holds SPILL ints for every
 // thread of that grid.  Several rounds let workgroups that finish early be replaced
 // while others still trace long paths (4 rounds: traversal -7 %), at 224 B of spill
-// space per thread: the single-request path uses TRACE_ROUNDS, the request loop two
-// rounds (its queues count against its memory budget).
+// space per thread (never more threads than paths of a wave in the request loop, whose
+// queues count against its memory budget).
 constexpr int TRACE_ROUNDS = 4;
 inline int trace_grid_cap(int grid_cap, int rounds) {
     const int g = grid_cap * 128 / TRACE_TB * rounds;
@@ -146,9 +146,10 @@ void launch_trace(const Launch& l, const Queues& q, int cur, const ReqDesc& uni,
                   int64_t n_upper);
 void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const ReqDesc& uni, const ReqDesc* table,
                   int64_t n_upper);
-// depth: the bounce the shadow rays leave from (for the path records)
+// depth: the bounce the shadow rays leave from (for the path records); one_tree (with a
+// table): every ray is on the tree of `uni` (several requests of one scene)
 void launch_shadow(const Launch& l, const Queues& q, int which, const ReqDesc& uni, const ReqDesc* table,
-                   int64_t n_upper, int depth);
+                   int64_t n_upper, int depth, bool one_tree = false);
 void launch_finalize(const Launch& l, const Queues& q, const ReqDesc& r, const ReqDesc* table, int slot,
                      uint32_t p0, uint32_t p1);
 void launch_set_desc(const Launch& l, ReqDesc* table, int slot, const ReqDesc& r);

@@ -222,23 +222,27 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
 // ---------------------------------------------------------------- shadows
 // PROF: the counting pass's instantiation (node and triangle visit counters, summed
 // into q.stats), which a profiler reports apart from the timed launches
-template <bool UNI, bool PROF>
+// TREE: every ray of the launch is on the tree of `uni` (several requests of one scene):
+// the tree's top is staged and its pointers come from `uni`, the rest from the table
+template <bool UNI, bool PROF, bool TREE = UNI>
 __global__ void __launch_bounds__(TB) SHADOW_OCCUPANCY k_shadow(Queues q, int which, int depth, ReqDesc uni,
                                                const ReqDesc* __restrict__ table) {
     __shared__ int stack[(SHORT_STACK + 1) * TB];
-    __shared__ float4 ltop[UNI ? 8 * TOP_NODES : 1];
+    __shared__ float4 ltop[TREE ? 8 * TOP_NODES : 1];
     int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL;
     const uint32_t n = q.cnt[2 + which];
     TopNodes top{nullptr, 0u};
-    if constexpr (UNI)
+    if constexpr (TREE)
         if (uni.nodes4) top = stage_top<TB>(ltop, uni.nodes4, uni.top_nodes);
     for (uint32_t i = blockIdx.x * TB + threadIdx.x; i < n; i += gridDim.x * TB) {
         const float4 o = nt_ld(&q.so[which][i]), d = nt_ld(&q.sd[which][i]);
         const ReqDesc& r = sel<UNI>(uni, table, __float_as_int(o.w));
+        const ReqDesc& tr = TREE ? uni : r;
         Hit h;
         Visits<PROF> vis;
-        const bool occ = trace_ray<true, SHORT_STACK, TB>(r.nodes4, r.nodes, r.tris, xyz(o), xyz(d), r.tmin, nt_ld(&q.st[which][i]),
-                                                         __float_as_int(d.w), h, stack, spill, threadIdx.x, vis, top);
+        const bool occ = trace_ray<true, SHORT_STACK, TB>(tr.nodes4, tr.nodes, tr.tris, xyz(o), xyz(d), tr.tmin,
+                                                         nt_ld(&q.st[which][i]), __float_as_int(d.w), h, stack,
+                                                         spill, threadIdx.x, vis, top);
         if constexpr (PROF)
             if (q.stats) {
                 atomicAdd(&q.stats[0], (unsigned long long)vis.nodes);
@@ -441,8 +445,12 @@ void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const Re
     else hipLaunchKernelGGL((k_shade<true>), g, b, 0, l.st, q, cur, depth, uni, table);
 }
 void launch_shadow(const Launch& l, const Queues& q, int which, const ReqDesc& uni, const ReqDesc* table,
-                   int64_t n_upper, int depth) {
+                   int64_t n_upper, int depth, bool one_tree) {
     const dim3 g(grid_cap(Launch{l.st, q.trace_blocks}, n_upper, TB)), b(TB);
+    if (table && one_tree) {
+        hipLaunchKernelGGL((k_shadow<false, false, true>), g, b, 0, l.st, q, which, depth, uni, table);
+        return;
+    }
     if (q.stats) {
         if (table) hipLaunchKernelGGL((k_shadow<false, true>), g, b, 0, l.st, q, which, depth, uni, table);
         else hipLaunchKernelGGL((k_shadow<true, true>), g, b, 0, l.st, q, which, depth, uni, table);

@@ -85,7 +85,9 @@ struct Req {
     int64_t npix = 0, next_pixel = 0;
     size_t bytes = 0, off = 0;
     int slot = -1;
-    clk::time_point t_submit;
+    clk::time_point t_submit, t_admit, t_launch;   // submit, admission, first wave launched
+    bool launched = false;
+    hipEvent_t ready = nullptr;   // recorded on the caller's input stream at submit
     hipEvent_t done = nullptr;
     int32_t status = DPCS_OK;
     bool scheduled_all = false;
@@ -128,6 +130,8 @@ struct dpcs_server_s {
     bool stop = false;
     int64_t st_submitted = 0, st_completed = 0, st_rejected = 0, st_waves = 0, st_samples = 0, st_peak = 0;
     int64_t st_replayed = 0, st_retraced = 0;   // waves whose compensation segments replayed / re-traced
+    int64_t st_wait_us = 0, st_admit_us = 0, st_run_us = 0;   // summed latency parts of completed requests
+    int64_t lat_cap = 0;         // wave size while several requests share the loop
     std::thread worker;
     std::string err;
     void run();
@@ -147,6 +151,10 @@ void dpcs_server_s::admit_locked(Launch& l) {
         free_slots.pop_back();
         admitted_bytes += q->bytes;
         st_peak = std::max<int64_t>(st_peak, (int64_t)(admitted_bytes + shared_bytes));
+        q->t_admit = clk::now();
+        // the request's inputs were produced on the caller's stream: the loop's first
+        // launch for it waits for everything queued there before submit
+        (void)hipStreamWaitEvent(l.st, q->ready, 0);
         // carve the request's device state from its arena region
         char* base = arena_base + off;
         auto take = [&](size_t n) {
@@ -187,8 +195,17 @@ void dpcs_server_s::wave(Launch& l) {
         return (q->npix - q->next_pixel) * (int64_t)q->r.spp * (q->adjoint ? 2 : 1);
     };
     std::stable_sort(pick.begin(), pick.end(), [&](const Req* a, const Req* b) { return remaining(a) < remaining(b); });
+    // one scene per wave (the scene of the request with the least remaining work): every
+    // ray of the wave is then on one tree, whose top levels the traversal stages in LDS,
+    // and the wave's node and triangle reads share one tree in L2
+    const dpcs_scene scene = pick.front()->scene;
+    pick.erase(std::remove_if(pick.begin(), pick.end(), [&](const Req* q) { return q->scene != scene; }), pick.end());
     std::vector<std::pair<Req*, int64_t>> take;   // request, pixels this wave
-    int64_t room = cap;
+    // a request alone fills whole waves (throughput); while others are active or
+    // queued, waves are cut to lat_cap paths so that a newcomer waits for short waves
+    // only (a full wave of 4M paths at depth 4 with its adjoint takes ~3.5 ms)
+    int64_t room = (pick.size() > 1 || !queued.empty()) ? std::min(cap, lat_cap) : cap;
+    room = std::max<int64_t>(room, pick.front()->r.spp);
     for (Req* q : pick) {
         const int64_t px = std::min<int64_t>(q->npix - q->next_pixel, room / q->r.spp);
         if (px <= 0) continue;
@@ -222,6 +239,12 @@ void dpcs_server_s::wave(Launch& l) {
         if (s.q->adjoint) rec_need += (int64_t)(s.b - s.a) * s.q->r.spp * s.q->r.max_depth;
     const bool replay = any_adj && rec_need <= rec_cap;
     int64_t rec_off = 0;
+    const clk::time_point now = clk::now();
+    for (const Seg& s : segs)
+        if (!s.q->launched) {
+            s.q->launched = true;
+            s.q->t_launch = now;
+        }
     for (const Seg& s : segs) {
         Req* q = s.q;
         if (replay && q->adjoint) {
@@ -233,6 +256,8 @@ void dpcs_server_s::wave(Launch& l) {
         }
         launch_set_desc(l, table, q->slot, q->r);
     }
+    // the tree of the wave's scene (every segment's descriptor holds it): closest-hit
+    // queries read nothing else of a descriptor, so they run in the one-request form
     const ReqDesc& any = segs[0].q->r;
     // forward over the shared queues
     launch_set_count(l, q.cnt, 0, (uint32_t)used, 1, 4);
@@ -241,10 +266,10 @@ void dpcs_server_s::wave(Launch& l) {
     int cur = 0;
     for (int d = 0; d < max_depth; ++d) {
         launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
-        launch_trace(l, q, cur, any, table, used);
+        launch_trace(l, q, cur, any, nullptr, used);
         launch_shade(l, q, cur, d, any, table, used);
-        launch_shadow(l, q, 0, any, table, used, d);
-        if (env) launch_shadow(l, q, 1, any, table, used, d);
+        launch_shadow(l, q, 0, any, table, used, d, true);
+        if (env) launch_shadow(l, q, 1, any, table, used, d, true);
         cur ^= 1;
     }
     for (const Seg& s : segs) launch_finalize(l, q, s.q->r, table, s.q->slot, s.a, s.b);
@@ -261,7 +286,7 @@ void dpcs_server_s::wave(Launch& l) {
             if (replay) {
                 launch_adj_replay(l, q, aq, cur, d, any, table, n_adj);
             } else {
-                launch_trace(l, q, cur, any, table, n_adj);
+                launch_trace(l, q, cur, any, nullptr, n_adj);
                 launch_adj_shade(l, q, aq, cur, d, any, table, n_adj);
                 launch_adj_shadow(l, q, aq, 0, cur ^ 1, any, table, n_adj);
                 if (env) launch_adj_shadow(l, q, aq, 1, cur ^ 1, any, table, n_adj);
@@ -342,7 +367,14 @@ void dpcs_server_s::run() {
                 ++it;
                 continue;
             }
-            const double ms = std::chrono::duration<double, std::milli>(clk::now() - q->t_submit).count();
+            const clk::time_point t_done = clk::now();
+            const double ms = std::chrono::duration<double, std::milli>(t_done - q->t_submit).count();
+            auto us = [](clk::time_point a, clk::time_point b) {
+                return (int64_t)std::chrono::duration_cast<std::chrono::microseconds>(b - a).count();
+            };
+            st_wait_us += us(q->t_submit, q->t_admit);
+            st_admit_us += us(q->t_admit, q->t_launch);
+            st_run_us += us(q->t_launch, t_done);
             const int32_t status = e == hipSuccess && err.empty() ? DPCS_OK : DPCS_E_DEVICE;
             completed.emplace_back(q->id, status, ms);
             ++st_completed;
@@ -351,6 +383,7 @@ void dpcs_server_s::run() {
             free_slots.push_back(q->slot);
             q->scene->refs.fetch_sub(1);
             (void)hipEventDestroy(q->done);
+            (void)hipEventDestroy(q->ready);
             delete q;
             it = finishing.erase(it);
         }
@@ -375,10 +408,15 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     const size_t per_path = (2 * 80 + 4 + 2 * 52 + 16) + (2 * 144 + 16);
     const int64_t fit = (int64_t)(memory_budget_bytes / 4 / per_path);
     s->cap = std::max<int64_t>(1024, std::min<int64_t>({ctx->capacity, int64_t(1) << 22, fit}));
+    s->lat_cap = std::min<int64_t>(s->cap, int64_t(1) << 20);
     const size_t c = (size_t)s->cap;
     // + 256 bytes of alignment slack per part (42 parts); path records for up to 8
     // vertices per path of a wave
-    const size_t qbytes = c * per_path + 64 * 256 + 4 * spill_ints(ctx->grid_cap, 2) + 4 * 8 * c;
+    // traversal grids: four resident rounds, but never more workgroups than one per
+    // TRACE_TB paths of a wave
+    const int tblocks = (int)std::min<int64_t>(trace_grid_cap(ctx->grid_cap, TRACE_ROUNDS), (s->cap + TRACE_TB - 1) / TRACE_TB);
+    const size_t spill_bytes = 4 * (size_t)tblocks * TRACE_TB * SPILL;
+    const size_t qbytes = c * per_path + 64 * 256 + spill_bytes + 4 * 8 * c;
     s->shared_bytes = qbytes + sizeof(ReqDesc) * (size_t)max_slots;
     if (s->shared_bytes >= s->budget) {
         delete s;
@@ -431,8 +469,8 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     s->aq.tb = MapBins{};   // the request loop replays by tracing and scatters directly
     s->aq.eb = MapBins{};
     s->q.cnt = (uint32_t*)take(16);
-    s->q.spill = (int*)take(4 * spill_ints(ctx->grid_cap, 2));
-    s->q.trace_blocks = trace_grid_cap(ctx->grid_cap, 2);
+    s->q.spill = (int*)take(spill_bytes);
+    s->q.trace_blocks = tblocks;
     s->rec = (uint32_t*)take(4 * 8 * c);
     s->rec_cap = 8 * (int64_t)c;
     s->q.cap = s->cap;
@@ -490,6 +528,14 @@ extern "C" dpcs_status dpcs_server_submit(dpcs_server s, const dpcs_request* rq)
         delete q;
         return DPCS_E_DEVICE;
     }
+    if (hipEventCreateWithFlags(&q->ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(q->ready, rq->input_stream ? (hipStream_t)rq->input_stream : ctx->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipEventDestroy(q->done);
+        if (q->ready) (void)hipEventDestroy(q->ready);
+        delete q;
+        return DPCS_E_DEVICE;
+    }
     q->scene->refs.fetch_add(1);
     s->queued.push_back(q);
     s->cv.notify_one();
@@ -511,7 +557,7 @@ extern "C" int32_t dpcs_server_poll(dpcs_server s, uint64_t* ids, int32_t* statu
     return n;
 }
 
-extern "C" dpcs_status dpcs_server_stats(dpcs_server s, int64_t* o) {   // o: 10 counters
+extern "C" dpcs_status dpcs_server_stats(dpcs_server s, int64_t* o) {   // o: 13 counters
     if (!s || !o) return DPCS_E_INVALID;
     std::lock_guard<std::mutex> lk(s->mu);
     o[0] = s->st_submitted;
@@ -524,6 +570,9 @@ extern "C" dpcs_status dpcs_server_stats(dpcs_server s, int64_t* o) {   // o: 10
     o[7] = s->st_peak;
     o[8] = s->st_replayed;
     o[9] = s->st_retraced;
+    o[10] = s->st_wait_us;
+    o[11] = s->st_admit_us;
+    o[12] = s->st_run_us;
     return DPCS_OK;
 }
 

@@ -85,7 +85,7 @@ class Profile(C.Structure):
 class Request(C.Structure):
     _fields_ = [("scene", C.c_void_p), ("params", RenderParams), ("proj_image", C.c_void_p),
                 ("out_image", C.c_void_p), ("grad_image", C.c_void_p), ("target", C.c_void_p),
-                ("grads", C.POINTER(Grads)), ("request_id", C.c_uint64)]
+                ("grads", C.POINTER(Grads)), ("request_id", C.c_uint64), ("input_stream", C.c_void_p)]
 
 
 class DenoiseParams(C.Structure):
@@ -377,13 +377,18 @@ class Server:
         self._keep = {}
 
     def submit(self, request_id: int, scene: Scene, params: RenderParams, proj_image, out_image, grad_image=None,
-               target=None, grads: dict | None = None, keep=None) -> int:
+               target=None, grads: dict | None = None, keep=None, stream=None) -> int:
+        """Queues one request; its first launch waits for the work queued on `stream`
+        (default: torch's current stream) at this call, so inputs written there are ready."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
         g = None
         if grads is not None:
             g = Grads(_ptr(grads.get("d_proj_image")), _ptr(grads.get("d_albedo")), _ptr(grads.get("d_roughness")),
                       _ptr(grads.get("d_specular")), _ptr(grads.get("d_scalars")))
         rq = Request(scene.h, params, _ptr(proj_image), _ptr(out_image), _ptr(grad_image), _ptr(target),
-                     C.pointer(g) if g is not None else None, int(request_id))
+                     C.pointer(g) if g is not None else None, int(request_id), C.c_void_p(stream.cuda_stream))
         st = lib().dpcs_server_submit(self.h, C.byref(rq))
         if st == OK:
             self._keep[int(request_id)] = (params, proj_image, out_image, grad_image, target, grads, g, keep)
@@ -401,10 +406,10 @@ class Server:
         return out
 
     def stats(self) -> dict:
-        v = (C.c_int64 * 10)()
+        v = (C.c_int64 * 13)()
         self.ctx.check(lib().dpcs_server_stats(self.h, v))
         keys = ["submitted", "completed", "rejected", "active", "queued", "waves", "samples", "peak_bytes",
-                "replayed_waves", "retraced_waves"]
+                "replayed_waves", "retraced_waves", "wait_us", "admit_us", "run_us"]
         return dict(zip(keys, [int(x) for x in v]))
 
     def close(self):

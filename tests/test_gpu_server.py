@@ -195,3 +195,41 @@ def test_retraced_adjoint_in_the_mix():
             a, b = grads[name].cpu().numpy(), g2[name].cpu().numpy()
             scale = np.abs(b).max() + 1e-30
             np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-5 * scale, err_msg=f"request {k} {name}")
+
+
+def test_request_waits_for_its_input_stream():
+    """The projector image is written on a side stream behind ~10 ms of other work and
+    the request is submitted at once with that stream: the loop's first launch waits for
+    it, so the result equals a plain render of the final image; the latency parts of
+    the completed request add up to no more than its latency."""
+    import torch
+    from paper_2503_12174_amd import dpcs
+    scenes, albedo, rough, spec = _setup(1)
+    w = synth.corner_50k(spp=4, max_depth=2, res=64, n_quads=8)
+    w.projector = synth.pinhole((0.85, 0.15, 0.85), (0.3, 0.0, 0.3), 45.0, 64, 64)
+    p = dpcs.params_from(w, albedo, rough, spec)
+    final = dev(synth.blob_image(64, 64, 77), torch.float32)
+    ip = torch.zeros_like(final)
+    out = torch.zeros((64, 64, 3), device="cuda")
+    a = torch.randn(4096, 4096, device="cuda")
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    srv = dpcs.Server(ctx(), budget_bytes=512 << 20, max_slots=4)
+    with torch.cuda.stream(side):
+        acc = a
+        for _ in range(8):
+            acc = (acc @ a) * 1e-3
+        ip.copy_(final)
+    assert srv.submit(0, scenes[0], p, ip, out, stream=side) == dpcs.OK
+    done = _wait(srv, 1)
+    assert len(done) == 1 and done[0][1] == dpcs.OK
+    st = srv.stats()
+    srv.close()
+    torch.cuda.synchronize()
+    alone = torch.zeros_like(out)
+    dpcs.dpcs_render(ctx(), scenes[0], p, final, alone)
+    ctx().synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), alone.cpu().numpy())
+    assert 0 <= st["wait_us"] and 0 <= st["admit_us"] and 0 <= st["run_us"]
+    assert (st["wait_us"] + st["admit_us"] + st["run_us"]) * 1e-3 <= done[0][2] + 1.0
+    del acc
