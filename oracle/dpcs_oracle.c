@@ -83,6 +83,15 @@ typedef struct {
     uint32_t sample_offset;
     int32_t nthreads;
     double tmin;           /* ray epsilon; <= 0 selects 1e-5 * scene diagonal */
+    /* the principled BRDF's further maps (Sec. 3.2: theta holds the maps m and the normal
+       map v_n; Sec. 4.3 lists base colour, roughness, metallic and the normal map), th x tw:
+       metallic (NULL: 0 everywhere) and the normal map (x 3, NULL: none), whose stored
+       values in [0, 1] decode to t = 2 v - 1 in the tangent frame of the surface, so
+       (0.5, 0.5, 1) leaves the normal unchanged */
+    const double* metal;
+    const double* nmap;
+    const double* nmap_sample; /* normal map whose shading normal samples directions and
+                                  pdfs (NULL: nmap); the frozen-path estimator of the tests */
 } orc_desc;
 
 /* margin scales (see header comment); all margins are divided by these */
@@ -318,12 +327,6 @@ static void fetch3(const double* tex, const bilin* b, double out[3]) {
 #define P_SPEC 0.25
 #define ALPHA_MIN 1e-3
 
-typedef struct {
-    double f[3];     /* BRDF value per channel */
-    double ds_dr;    /* d(specular term)/d(roughness) */
-    double ds_dsp;   /* d(specular term)/d(specular) */
-} brdf_val;
-
 static double ggx_alpha(double r) { double a = r * r; return a > ALPHA_MIN ? a : ALPHA_MIN; }
 static double ggx_dalpha(double r) { return r * r > ALPHA_MIN ? 2.0 * r : 0.0; }
 
@@ -344,27 +347,74 @@ static double ggx_dG1(double c, double a) {
     return -2.0 * c * dq / ((c + q) * (c + q));
 }
 
-/* f(wo, wi) at a surface with normal n (two-sided: n already faces wo) */
-static brdf_val brdf_eval(int kind, v3 n, v3 wo, v3 wi, const double a[3], double r, double sp) {
-    brdf_val b;
+/* dD/d(n.h) at fixed alpha: D = a^2 / (pi k^2), k = c^2 (a^2 - 1) + 1 */
+static double ggx_dD_dc(double c, double a) {
+    double k = c * c * (a * a - 1.0) + 1.0;
+    return -4.0 * a * a * c * (a * a - 1.0) / (PI * k * k * k);
+}
+/* dG1/dc at fixed alpha: G1 = 2c / (c + q), q = sqrt(a^2 + (1 - a^2) c^2) */
+static double ggx_dG1_dc(double c, double a) {
+    double q = sqrt(a * a + (1.0 - a * a) * c * c);
+    return 2.0 * a * a / (q * (c + q) * (c + q));
+}
+
+/* The principled BRDF with a metallic parameter and a shading normal (Sec. 3.2, Burley's
+ * reading): base colour a, metallic mu, roughness r, specular sp,
+ *   f_c = (1 - mu) a_c / pi + F_c D G / (4 cos_i cos_o),
+ *   F_c = F0_c + (1 - F0_c)(1 - wi.h)^5,  F0_c = (1 - mu) 0.08 sp + mu a_c,
+ * with the cosines taken about the shading normal ns.  f = 0 unless wi and wo lie above
+ * ns and wi lies above the geometric normal ng (no light through the surface).  The
+ * Lambert kind is a_c / pi (metallic does not apply).  Returned with the derivatives the
+ * adjoint needs, every one of them of f_c (or of f_c times the cosine c = ns.wi, the
+ * factor of the rendering equation, for the normal). */
+typedef struct {
+    double f[3];     /* f_c */
+    double c;        /* ns . wi */
+    double dfa;      /* d f_c / d a_c (the same for every channel) */
+    double dfr[3];   /* d f_c / d r */
+    double dfs;      /* d f_c / d sp (the same for every channel) */
+    double dfm[3];   /* d f_c / d mu */
+    v3 dfcn[3];      /* d (f_c c) / d ns */
+} brdf_full_t;
+
+static brdf_full_t brdf_full(int kind, v3 ng, v3 ns, v3 wo, v3 wi, const double a[3], double r, double sp,
+                             double mu) {
+    brdf_full_t b;
     memset(&b, 0, sizeof b);
-    double ci = dot(n, wi), co = dot(n, wo);
-    if (ci <= 0.0 || co <= 0.0) return b;
-    for (int c = 0; c < 3; ++c) b.f[c] = a[c] / PI;
-    if (kind == 0) return b;
+    double ci = dot(ns, wi), co = dot(ns, wo);
+    b.c = ci;
+    if (ci <= 0.0 || co <= 0.0 || dot(ng, wi) <= 0.0) return b;
+    if (kind == 0) {
+        b.dfa = 1.0 / PI;
+        for (int c = 0; c < 3; ++c) {
+            b.f[c] = a[c] / PI;
+            b.dfcn[c] = scl(wi, a[c] / PI);
+        }
+        return b;
+    }
     v3 h = nrm(add(wi, wo));
-    double nh = dot(n, h), ih = dot(wi, h);
+    double nh = dot(ns, h), ih = dot(wi, h);
     double al = ggx_alpha(r), dal = ggx_dalpha(r);
     double D = ggx_D(nh, al), G1i = ggx_G1(ci, al), G1o = ggx_G1(co, al), G = G1i * G1o;
-    double F0 = 0.08 * sp;
     double m5 = pow(1.0 - ih, 5.0);
-    double F = F0 + (1.0 - F0) * m5;
     double den = 4.0 * ci * co;
-    double s = F * D * G / den;
-    for (int c = 0; c < 3; ++c) b.f[c] += s;
+    double DGw = D * G / den;
     double dG = ggx_dG1(ci, al) * G1o + G1i * ggx_dG1(co, al);
-    b.ds_dr = F * (ggx_dD(nh, al) * G + D * dG) / den * dal;
-    b.ds_dsp = 0.08 * (1.0 - m5) * D * G / den;
+    double dDGw_dr = (ggx_dD(nh, al) * G + D * dG) / den * dal;
+    /* S = D G / (4 co) = DGw ci: the microfacet part of f_c c without F_c */
+    double S = D * G / (4.0 * co);
+    v3 dS = add(add(scl(h, ggx_dD_dc(nh, al) * G / (4.0 * co)), scl(wi, D * ggx_dG1_dc(ci, al) * G1o / (4.0 * co))),
+                scl(wo, D * G1i * ggx_dG1_dc(co, al) / (4.0 * co) - S / co));
+    b.dfa = (1.0 - mu) / PI + mu * (1.0 - m5) * DGw;
+    b.dfs = (1.0 - mu) * 0.08 * (1.0 - m5) * DGw;
+    for (int c = 0; c < 3; ++c) {
+        double F0 = (1.0 - mu) * (0.08 * sp) + mu * a[c];
+        double F = F0 + (1.0 - F0) * m5;
+        b.f[c] = (1.0 - mu) * a[c] / PI + F * DGw;
+        b.dfr[c] = F * dDGw_dr;
+        b.dfm[c] = -a[c] / PI + (a[c] - 0.08 * sp) * (1.0 - m5) * DGw;
+        b.dfcn[c] = add(scl(wi, (1.0 - mu) * a[c] / PI), scl(dS, F));
+    }
     return b;
 }
 
@@ -425,18 +475,24 @@ typedef struct {
     double beta[3];
     double Le[3];
     bilin tex;                  /* texture footprint of the vertex */
-    double alb[3], r, sp;
-    /* projector next-event estimation */
+    double alb[3], r, sp, mu;
+    /* normal map: tangent frame (T, B, geometric n) and the decoded t / |t|, |t| */
+    int nm;
+    v3 fT, fB, fN, th;
+    double tlen;
+    /* projector next-event estimation: BRDF at (wo, wp), bilinear E_p, 1/(cos^3 d^2) */
     int proj;                   /* unoccluded and inside the frustum */
     bilin ptex;                 /* projector image footprint */
-    double pf[3], pgeom, pE[3]; /* f(wo, wp), (1/cos^3) cos/d^2, bilinear E_p */
-    double pds_dr, pds_dsp;
-    /* environment next-event estimation */
+    brdf_full_t pf;
+    double pE[3], pg0;
+    /* environment next-event estimation: BRDF at (wo, we), pi / (sampling cosine) */
     int env;
-    double ef[3], eds_dr, eds_dsp;
-    /* bounce to the next vertex */
+    brdf_full_t ef;
+    double es;
+    /* bounce to the next vertex: BRDF at (wo, wi), the sampler's pdf (held fixed) */
     int bounced;
-    double bf[3], bw, bds_dr, bds_dsp; /* f(wo, wi), cos/pdf (pdf held fixed) */
+    brdf_full_t bf;
+    double bpdf;
 } vrec;
 
 typedef struct {
@@ -447,9 +503,54 @@ typedef struct {
 } sample_out;
 
 /* check ids: 1 closest hit, 2 facing sign, 3 projector depth, 4 frustum border,
- * 5 projector cosine sign, 6 projector shadow ray, 7 environment shadow ray, 8 bounce sign */
+ * 5 projector cosine sign, 6 projector shadow ray, 7 environment shadow ray, 8 bounce sign,
+ * with a normal map also 9 outgoing side of the shading normal, 10 environment direction
+ * side of the geometric normal, 11 bounce direction side of the shading normal */
 static void UPD(sample_out* so, int depth, double m, int check) {
     if (m < so->margin) { so->margin = m; so->reason = 10 * depth + check; }
+}
+
+/* Tangent frame of the normal map at a hit (Sec. 3.2: v_n is given relative to the
+ * surface normal): T along dP/du of the triangle's texture parameterisation, made
+ * orthogonal to the two-sided geometric normal n (the Duff et al. basis when the
+ * parameterisation is degenerate), and B = n x T. */
+static void tangent_frame(const orc_desc* d, int32_t prim, v3 n, v3* T, v3* B) {
+    v3 v0 = vtx(d, d->F[3 * prim]), v1 = vtx(d, d->F[3 * prim + 1]), v2 = vtx(d, d->F[3 * prim + 2]);
+    v3 e1 = sub(v1, v0), e2 = sub(v2, v0);
+    const float* uv = d->UV + 6 * (size_t)prim;
+    double du1 = (double)uv[2] - uv[0], dv1 = (double)uv[3] - uv[1];
+    double du2 = (double)uv[4] - uv[0], dv2 = (double)uv[5] - uv[1];
+    double det = du1 * dv2 - du2 * dv1;
+    v3 t = mk(0, 0, 0);
+    if (det != 0.0) {
+        v3 dpdu = scl(sub(scl(e1, dv2), scl(e2, dv1)), 1.0 / det);
+        t = sub(dpdu, scl(n, dot(n, dpdu)));
+    }
+    double l = len(t);
+    if (l > 0.0) {
+        *T = scl(t, 1.0 / l);
+    } else {
+        v3 b2;
+        onb(n, T, &b2);
+    }
+    *B = cross(n, *T);
+}
+
+/* shading normal of the map value v at footprint tb: t = 2 v - 1 in the frame (T, B, n),
+ * normalised; n itself when t = 0.  th, tlen receive t / |t| and |t|. */
+static v3 shading_normal(const double* map, const bilin* tb, v3 T, v3 B, v3 n, v3* th, double* tlen) {
+    double v[3];
+    fetch3(map, tb, v);
+    v3 t = mk(2.0 * v[0] - 1.0, 2.0 * v[1] - 1.0, 2.0 * v[2] - 1.0);
+    double l = len(t);
+    if (!(l > 0.0)) {
+        *th = mk(0, 0, 1);
+        *tlen = 0.0;
+        return n;
+    }
+    *th = scl(t, 1.0 / l);
+    *tlen = l;
+    return add(add(scl(T, th->x), scl(B, th->y)), scl(n, th->z));
 }
 
 typedef struct {
@@ -552,18 +653,41 @@ static sample_out trace_sample(const ctx_t* cx, int32_t pixel, int32_t s, vrec* 
         double tu = h.b0 * uvp[0] + h.b1 * uvp[2] + h.b2 * uvp[4];
         double tv = h.b0 * uvp[1] + h.b1 * uvp[3] + h.b2 * uvp[5];
         bilin tb = tex_lookup(d, tu, tv);
-        double alb[3], r = 0, sp = 0, rs = 0;
+        double alb[3], r = 0, sp = 0, rs = 0, mu = 0;
         fetch3(d->albedo, &tb, alb);
         if (d->brdf == 1) {
             r = fetch1(d->rough, &tb);
             sp = fetch1(d->spec, &tb);
             rs = d->rough_sample ? fetch1(d->rough_sample, &tb) : r;
+            if (d->metal) mu = fetch1(d->metal, &tb);
+        }
+        /* shading normal (evaluation) and the one that samples directions and pdfs */
+        v3 ns = n, nss = n, fT = n, fB = n, th = mk(0, 0, 1);
+        double tlen = 0.0;
+        if (d->nmap) {
+            tangent_frame(d, prim, n, &fT, &fB);
+            ns = shading_normal(d->nmap, &tb, fT, fB, n, &th, &tlen);
+            if (d->nmap_sample) {
+                v3 th2;
+                double tl2;
+                nss = shading_normal(d->nmap_sample, &tb, fT, fB, n, &th2, &tl2);
+            } else {
+                nss = ns;
+            }
+            UPD(&so, depth, absd(dot(ns, wo)) / TAU_COS, 9);
         }
         if (vr) {
             vr->tex = tb;
             for (int c = 0; c < 3; ++c) vr->alb[c] = alb[c];
             vr->r = r;
             vr->sp = sp;
+            vr->mu = mu;
+            vr->nm = d->nmap != NULL;
+            vr->fT = fT;
+            vr->fB = fB;
+            vr->fN = n;
+            vr->th = th;
+            vr->tlen = tlen;
         }
 
         /* surface emission (white-furnace test scenes only) */
@@ -590,6 +714,7 @@ static sample_out trace_sample(const ctx_t* cx, int32_t pixel, int32_t s, vrec* 
                     v3 wp = scl(tow, 1.0 / dist);
                     double cp = dot(n, wp);
                     UPD(&so, depth, absd(cp) / TAU_COS, 5);
+                    if (d->nmap) UPD(&so, depth, absd(dot(ns, wp)) / TAU_COS, 5);
                     if (cp > 0) {
                         double mo;
                         int occ = occluded(d, &cx->sc, x, wp, dist - cx->sc.tmin, prim, &mo);
@@ -599,16 +724,16 @@ static sample_out trace_sample(const ctx_t* cx, int32_t pixel, int32_t s, vrec* 
                             double E[3];
                             fetch3(cx->Ep, &pb, E);
                             double ca = xp.z / len(xp);              /* cos alpha off the axis */
-                            double geom = cp / (ca * ca * ca * dist * dist);
-                            brdf_val fb = brdf_eval(d->brdf, n, wo, wp, alb, r, sp);
+                            brdf_full_t fb = brdf_full(d->brdf, n, ns, wo, wp, alb, r, sp, mu);
+                            /* the cosine of the rendering equation is taken about ns */
+                            double geom = fb.c / (ca * ca * ca * dist * dist);
                             for (int c = 0; c < 3; ++c) L[c] += beta[c] * fb.f[c] * E[c] * geom;
                             if (vr) {
                                 vr->proj = 1;
                                 vr->ptex = pb;
-                                vr->pgeom = geom;
-                                for (int c = 0; c < 3; ++c) { vr->pf[c] = fb.f[c]; vr->pE[c] = E[c]; }
-                                vr->pds_dr = fb.ds_dr;
-                                vr->pds_dsp = fb.ds_dsp;
+                                vr->pf = fb;
+                                vr->pg0 = 1.0 / (ca * ca * ca * dist * dist);
+                                for (int c = 0; c < 3; ++c) vr->pE[c] = E[c];
                             }
                         }
                     }
@@ -616,46 +741,48 @@ static sample_out trace_sample(const ctx_t* cx, int32_t pixel, int32_t s, vrec* 
             }
         }
 
-        /* next-event estimation toward a constant environment (only if it is non-zero) */
+        /* next-event estimation toward a constant environment (only if it is non-zero):
+           direction cosine-distributed about the sampling normal, pdf = cos / pi */
         if (d->env[0] != 0 || d->env[1] != 0 || d->env[2] != 0) {
             double ue[4];
             uniforms(d, (uint32_t)pixel, (uint32_t)s, 2u + 2u * depth, ue);
-            v3 we = sample_cosine(n, ue[0], ue[1]);
+            v3 we = sample_cosine(nss, ue[0], ue[1]);
+            if (d->nmap) UPD(&so, depth, absd(dot(n, we)) / TAU_COS, 10);
             double mo;
             int occ = occluded(d, &cx->sc, x, we, 1e300, prim, &mo);
             UPD(&so, depth, mo, 7);
             if (!occ) {
-                brdf_val fb = brdf_eval(d->brdf, n, wo, we, alb, r, sp);
-                /* f * L_env * cos / (cos / pi) */
-                for (int c = 0; c < 3; ++c) L[c] += beta[c] * fb.f[c] * d->env[c] * PI;
+                brdf_full_t fb = brdf_full(d->brdf, n, ns, wo, we, alb, r, sp, mu);
+                /* f * L_env * cos / (cos_sample / pi): pi when both normals are the same */
+                double es = d->nmap_sample ? PI * fb.c / dot(nss, we) : PI;
+                for (int c = 0; c < 3; ++c) L[c] += beta[c] * fb.f[c] * d->env[c] * es;
                 if (vr) {
                     vr->env = 1;
-                    for (int c = 0; c < 3; ++c) vr->ef[c] = fb.f[c];
-                    vr->eds_dr = fb.ds_dr;
-                    vr->eds_dsp = fb.ds_dsp;
+                    vr->ef = fb;
+                    vr->es = d->nmap_sample ? PI / dot(nss, we) : (fb.c > 0 ? PI / fb.c : 0.0);
                 }
             }
         }
 
         if (depth == d->max_depth - 1) break;
 
-        /* bounce: sample a direction, pdf and lobe choice held fixed (detached) */
+        /* bounce: sample a direction, pdf and lobe choice held fixed (detached); the path
+           goes on while the direction leaves above the geometric surface */
         double ub[4];
         uniforms(d, (uint32_t)pixel, (uint32_t)s, 1u + 2u * depth, ub);
-        v3 wi = sample_bounce(d->brdf, n, wo, rs, ub[0], ub[1], ub[2]);
+        v3 wi = sample_bounce(d->brdf, nss, wo, rs, ub[0], ub[1], ub[2]);
         double ci = dot(n, wi);
         UPD(&so, depth, absd(ci) / TAU_COS, 8);
-        double pdf = bounce_pdf(d->brdf, n, wo, wi, rs);
+        if (d->nmap) UPD(&so, depth, absd(dot(ns, wi)) / TAU_COS, 11);
+        double pdf = bounce_pdf(d->brdf, nss, wo, wi, rs);
         if (ci <= 0 || pdf <= 0) break;
-        brdf_val fb = brdf_eval(d->brdf, n, wo, wi, alb, r, sp);
-        double w = ci / pdf;
+        brdf_full_t fb = brdf_full(d->brdf, n, ns, wo, wi, alb, r, sp, mu);
+        double w = fb.c / pdf;
         for (int c = 0; c < 3; ++c) beta[c] *= fb.f[c] * w;
         if (vr) {
             vr->bounced = 1;
-            vr->bw = w;
-            for (int c = 0; c < 3; ++c) vr->bf[c] = fb.f[c];
-            vr->bds_dr = fb.ds_dr;
-            vr->bds_dsp = fb.ds_dsp;
+            vr->bf = fb;
+            vr->bpdf = pdf;
         }
         o = x;
         dir = wi;
@@ -741,20 +868,22 @@ int orc_render(const orc_desc* d, int32_t npix, const int32_t* pixels, double* o
 /*   differentiated, i.e. G is taken as zero elsewhere.                       */
 /*   Outputs are overwritten (any may be NULL):                                */
 /*     d_Ip Hp*Wp*3, d_albedo th*tw*3, d_rough th*tw, d_spec th*tw,            */
-/*     d_scalars[18] = gamma_p(3), M(9 row-major), gamma_c(3), w(3)            */
+/*     d_scalars[18] = gamma_p(3), M(9 row-major), gamma_c(3), w(3),           */
+/*     d_metal th*tw, d_nmap th*tw*3 (the stored normal-map values)            */
 /*   d_Ep (optional, Hp*Wp*3) receives the cotangent of E_p before the PRF.    */
 /* ------------------------------------------------------------------------- */
 int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32_t* pixels,
                    double* d_Ip, double* d_albedo, double* d_rough, double* d_spec, double* d_scalars,
-                   double* d_Ep_out) {
+                   double* d_Ep_out, double* d_metal, double* d_nmap) {
     ctx_t cx;
     ctx_init(&cx, d);
     int thr_arg;
     double thr = clip_threshold(d, &thr_arg);
     int nth = nthreads_of(d);
     size_t nEp = 3 * (size_t)d->Wp * d->Hp, nT = (size_t)d->tw * d->th;
-    /* per-thread accumulators: dEp, dalb (3), drough, dspec, 6 CRF scalars, 1 threshold */
-    size_t per = nEp + 3 * nT + nT + nT + 7;
+    /* per-thread accumulators: dEp, dalb (3), drough, dspec, dmetal, dnmap (3), 6 CRF
+       scalars, 1 threshold */
+    size_t per = nEp + 3 * nT + nT + nT + nT + 3 * nT + 7;
     double* acc = (double*)calloc((size_t)nth * per, sizeof(double));
     int npix_all = d->Wc * d->Hc;
     if (!pixels) npix = npix_all;
@@ -770,7 +899,9 @@ int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32
         double* galb = gEp + nEp;
         double* grough = galb + 3 * nT;
         double* gspec = grough + nT;
-        double* gsc = gspec + nT;  /* gamma_c(3), w(3), threshold(1) */
+        double* gmetal = gspec + nT;
+        double* gnmap = gmetal + nT;
+        double* gsc = gnmap + 3 * nT;  /* gamma_c(3), w(3), threshold(1) */
         vrec* rec = (vrec*)malloc(sizeof(vrec) * (size_t)d->spp * d->max_depth);
         sample_out* so = (sample_out*)malloc(sizeof(sample_out) * (size_t)d->spp);
 #pragma omp for schedule(dynamic, 1)
@@ -816,40 +947,54 @@ int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32
                 if (delta[0] == 0 && delta[1] == 0 && delta[2] == 0) continue;
                 vrec* pr = rec + (size_t)s * d->max_depth;
                 int nv = so[s].nv;
-                /* R[k]: radiance leaving vertex k toward the previous vertex, unit throughput */
+                /* R[k]: radiance leaving vertex k toward the previous vertex, unit throughput.
+                   Every term of a vertex is beta_c f_c c S_c with c the cosine about the
+                   shading normal and S_c its remaining factor: E_c / (cos^3 alpha d^2) for
+                   the projector, L_env pi / c_sample for the environment, R_{k+1} / pdf for
+                   the bounce; its derivative w.r.t. a map value is beta_c (d(f_c c)) S_c. */
                 double Rn[3] = {0, 0, 0};   /* R of vertex k+1 */
                 for (int k = nv - 1; k >= 0; --k) {
                     vrec* v = &pr[k];
                     double Rk[3];
-                    double ga[3] = {0, 0, 0}, gr = 0, gs = 0;
+                    double ga[3] = {0, 0, 0}, gr = 0, gs = 0, gm = 0;
+                    v3 gn = mk(0, 0, 0);
+                    const brdf_full_t* fv[3] = {v->proj ? &v->pf : NULL, v->env ? &v->ef : NULL,
+                                                v->bounced ? &v->bf : NULL};
+                    double S[3][3];
+                    for (int c = 0; c < 3; ++c) {
+                        S[0][c] = v->pE[c] * v->pg0;
+                        S[1][c] = d->env[c] * v->es;
+                        S[2][c] = v->bounced ? Rn[c] / v->bpdf : 0.0;
+                    }
                     for (int c = 0; c < 3; ++c) {
                         double own = v->Le[c];
                         double bd = delta[c] * v->beta[c];  /* dL/d(term of vertex k) */
+                        for (int j = 0; j < 3; ++j) {
+                            const brdf_full_t* b = fv[j];
+                            if (!b) continue;
+                            double cs = b->c * S[j][c];
+                            own += b->f[c] * cs;
+                            ga[c] += bd * b->dfa * cs;
+                            gr += bd * b->dfr[c] * cs;
+                            gs += bd * b->dfs * cs;
+                            gm += bd * b->dfm[c] * cs;
+                            gn = add(gn, scl(b->dfcn[c], bd * S[j][c]));
+                        }
                         if (v->proj) {
-                            double Ex = v->pE[c] * v->pgeom;
-                            own += v->pf[c] * Ex;
                             /* d/dE_p through the bilinear weights */
-                            double gE = bd * v->pf[c] * v->pgeom;
+                            double gE = bd * v->pf.f[c] * v->pf.c * v->pg0;
                             for (int t = 0; t < 4; ++t) gEp[3 * (size_t)v->ptex.idx[t] + c] += gE * v->ptex.w[t];
-                            ga[c] += bd * Ex / PI;
-                            gr += bd * Ex * v->pds_dr;
-                            gs += bd * Ex * v->pds_dsp;
-                        }
-                        if (v->env) {
-                            double Ee = d->env[c] * PI;
-                            own += v->ef[c] * Ee;
-                            ga[c] += bd * Ee / PI;
-                            gr += bd * Ee * v->eds_dr;
-                            gs += bd * Ee * v->eds_dsp;
-                        }
-                        if (v->bounced) {
-                            double Ei = v->bw * Rn[c];
-                            own += v->bf[c] * Ei;
-                            ga[c] += bd * Ei / PI;
-                            gr += bd * Ei * v->bds_dr;
-                            gs += bd * Ei * v->bds_dsp;
                         }
                         Rk[c] = own;
+                    }
+                    /* the normal's cotangent in map values: ns = F t / |t|, t = 2 v - 1 */
+                    double gnm[3] = {0, 0, 0};
+                    if (v->nm && v->tlen > 0) {
+                        v3 gl = mk(dot(v->fT, gn), dot(v->fB, gn), dot(v->fN, gn));
+                        v3 gt = scl(sub(gl, scl(v->th, dot(v->th, gl))), 1.0 / v->tlen);
+                        gnm[0] = 2.0 * gt.x;
+                        gnm[1] = 2.0 * gt.y;
+                        gnm[2] = 2.0 * gt.z;
                     }
                     for (int t = 0; t < 4; ++t) {
                         size_t ti = (size_t)v->tex.idx[t];
@@ -858,7 +1003,9 @@ int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32
                         if (d->brdf == 1) {
                             grough[ti] += gr * w;
                             gspec[ti] += gs * w;
+                            gmetal[ti] += gm * w;
                         }
+                        for (int c = 0; c < 3; ++c) gnmap[3 * ti + c] += gnm[c] * w;
                     }
                     for (int c = 0; c < 3; ++c) Rn[c] = Rk[c];
                 }
@@ -875,7 +1022,9 @@ int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32
     double* galb = gEp + nEp;
     double* grough = galb + 3 * nT;
     double* gspec = grough + nT;
-    double* gsc = gspec + nT;
+    double* gmetal = gspec + nT;
+    double* gnmap = gmetal + nT;
+    double* gsc = gnmap + 3 * nT;
     double sc[18];
     memset(sc, 0, sizeof sc);
     for (int c = 0; c < 3; ++c) { sc[12 + c] = gsc[c]; sc[15 + c] = gsc[3 + c]; }
@@ -909,6 +1058,8 @@ int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32
     if (d_albedo) memcpy(d_albedo, galb, sizeof(double) * 3 * nT);
     if (d_rough) memcpy(d_rough, grough, sizeof(double) * nT);
     if (d_spec) memcpy(d_spec, gspec, sizeof(double) * nT);
+    if (d_metal) memcpy(d_metal, gmetal, sizeof(double) * nT);
+    if (d_nmap) memcpy(d_nmap, gnmap, sizeof(double) * 3 * nT);
     if (d_scalars) memcpy(d_scalars, sc, sizeof sc);
     free(tot);
     free(acc);
@@ -945,8 +1096,46 @@ void orc_intersect(const orc_desc* d, int64_t n, const double* rays, int32_t* pr
 /* BRDF value and its derivatives: out[0..2] f, out[3] ds/dr, out[4] ds/dsp */
 void orc_brdf(int32_t kind, const double* n, const double* wo, const double* wi, const double* a, double r,
               double sp, double* out) {
-    brdf_val b = brdf_eval(kind, mk(n[0], n[1], n[2]), mk(wo[0], wo[1], wo[2]), mk(wi[0], wi[1], wi[2]), a, r, sp);
-    out[0] = b.f[0]; out[1] = b.f[1]; out[2] = b.f[2]; out[3] = b.ds_dr; out[4] = b.ds_dsp;
+    v3 N = mk(n[0], n[1], n[2]);
+    brdf_full_t b = brdf_full(kind, N, N, mk(wo[0], wo[1], wo[2]), mk(wi[0], wi[1], wi[2]), a, r, sp, 0.0);
+    /* without metallic the specular term is the same in every channel */
+    out[0] = b.f[0]; out[1] = b.f[1]; out[2] = b.f[2]; out[3] = b.dfr[0]; out[4] = b.dfs;
+}
+
+/* the principled BRDF with metallic and a shading normal: out[0..2] f, [3] cos(ns, wi),
+ * [4] df/da, [5..7] df/dr, [8] df/dsp, [9..11] df/dmu, [12..20] d(f_c cos)/dns (c-major) */
+void orc_brdf_full(int32_t kind, const double* ng, const double* ns, const double* wo, const double* wi,
+                   const double* a, double r, double sp, double mu, double* out) {
+    brdf_full_t b = brdf_full(kind, mk(ng[0], ng[1], ng[2]), mk(ns[0], ns[1], ns[2]), mk(wo[0], wo[1], wo[2]),
+                              mk(wi[0], wi[1], wi[2]), a, r, sp, mu);
+    for (int c = 0; c < 3; ++c) {
+        out[c] = b.f[c];
+        out[5 + c] = b.dfr[c];
+        out[9 + c] = b.dfm[c];
+        out[12 + 3 * c] = b.dfcn[c].x;
+        out[13 + 3 * c] = b.dfcn[c].y;
+        out[14 + 3 * c] = b.dfcn[c].z;
+    }
+    out[3] = b.c;
+    out[4] = b.dfa;
+    out[8] = b.dfs;
+}
+
+/* tangent frame and shading normal of one hit, for tests: out[0..2] T, [3..5] B,
+ * [6..8] n (two-sided, facing -dir), [9..11] ns (n when the descriptor has no normal map) */
+void orc_shading_frame(const orc_desc* d, int32_t prim, const double* dir, const double* uv, double* out) {
+    v3 v0 = vtx(d, d->F[3 * prim]), v1 = vtx(d, d->F[3 * prim + 1]), v2 = vtx(d, d->F[3 * prim + 2]);
+    v3 n = nrm(cross(sub(v1, v0), sub(v2, v0)));
+    if (dot(n, mk(dir[0], dir[1], dir[2])) > 0) n = scl(n, -1.0);
+    v3 T, B, th, ns = n;
+    double tl;
+    tangent_frame(d, prim, n, &T, &B);
+    if (d->nmap) {
+        bilin tb = tex_lookup(d, uv[0], uv[1]);
+        ns = shading_normal(d->nmap, &tb, T, B, n, &th, &tl);
+    }
+    v3 o[4] = {T, B, n, ns};
+    for (int k = 0; k < 4; ++k) { out[3 * k] = o[k].x; out[3 * k + 1] = o[k].y; out[3 * k + 2] = o[k].z; }
 }
 
 /* bounce sampler: u[3] = (lobe, u1, u2) -> wi, pdf */

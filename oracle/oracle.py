@@ -48,6 +48,7 @@ class Desc(C.Structure):
         ("seed", C.c_uint64), ("sample_offset", C.c_uint32),
         ("nthreads", C.c_int32),
         ("tmin", C.c_double),
+        ("metal", C.c_void_p), ("nmap", C.c_void_p), ("nmap_sample", C.c_void_p),
     ]
 
 
@@ -80,7 +81,9 @@ def _load(path: str):
     L = C.CDLL(path)
     P = C.c_void_p
     L.orc_render.argtypes = [C.POINTER(Desc), C.c_int32, P, P, P, P, P, P, P, P]
-    L.orc_render_vjp.argtypes = [C.POINTER(Desc), P, C.c_int32, P, P, P, P, P, P, P]
+    L.orc_render_vjp.argtypes = [C.POINTER(Desc), P, C.c_int32, P, P, P, P, P, P, P, P, P]
+    L.orc_brdf_full.argtypes = [C.c_int32, P, P, P, P, P, C.c_double, C.c_double, C.c_double, P]
+    L.orc_shading_frame.argtypes = [C.POINTER(Desc), C.c_int32, P, P, P]
     L.orc_philox_batch.argtypes = [C.c_uint64, C.c_int64, P, P]
     L.orc_intersect.argtypes = [C.POINTER(Desc), C.c_int64, P, P, P, P, P, P]
     L.orc_brdf.argtypes = [C.c_int32, P, P, P, P, C.c_double, C.c_double, P]
@@ -133,6 +136,12 @@ class Scene:
         self.spec = np.ascontiguousarray(g("specular"), np.float64)
         self.rough_sample = None if over.get("rough_sample") is None else \
             np.ascontiguousarray(over["rough_sample"], np.float64)
+        mt = over["metallic"] if "metallic" in over else getattr(w, "metallic", None)
+        nm = over["normal_map"] if "normal_map" in over else getattr(w, "normal_map", None)
+        self.metal = None if mt is None else np.ascontiguousarray(mt, np.float64)
+        self.nmap = None if nm is None else np.ascontiguousarray(nm, np.float64)
+        self.nmap_sample = None if over.get("normal_sample") is None else \
+            np.ascontiguousarray(over["normal_sample"], np.float64)
         self.Ip = np.ascontiguousarray(g("proj_image"), np.float64)
         self.prf_gamma = np.asarray(g("prf_gamma"), np.float64)
         self.prf_gain = float(g("prf_gain"))
@@ -173,6 +182,7 @@ class Scene:
         d.seed, d.sample_offset = self.seed, self.sample_offset
         d.nthreads = self.nthreads
         d.tmin = self.tmin
+        d.metal, d.nmap, d.nmap_sample = _p(self.metal), _p(self.nmap), _p(self.nmap_sample)
         self._d = d
         return d
 
@@ -203,9 +213,11 @@ def render_vjp(sc: Scene, G, pixels=None):
     n = 0 if pixels is None else len(pixels)
     th, tw = sc.albedo.shape[:2]
     out = dict(Ip=np.zeros(sc.Ip.shape), albedo=np.zeros((th, tw, 3)), roughness=np.zeros((th, tw)),
-               specular=np.zeros((th, tw)), scalars=np.zeros(18), Ep=np.zeros(sc.Ip.shape))
+               specular=np.zeros((th, tw)), scalars=np.zeros(18), Ep=np.zeros(sc.Ip.shape),
+               metallic=np.zeros((th, tw)), normal_map=np.zeros((th, tw, 3)))
     lib().orc_render_vjp(C.byref(d), _p(G), n, _p(px), _p(out["Ip"]), _p(out["albedo"]), _p(out["roughness"]),
-                         _p(out["specular"]), _p(out["scalars"]), _p(out["Ep"]))
+                         _p(out["specular"]), _p(out["scalars"]), _p(out["Ep"]), _p(out["metallic"]),
+                         _p(out["normal_map"]))
     s = out.pop("scalars")
     out.update(prf_gamma=s[0:3], prf_mix=s[3:12].reshape(3, 3), crf_gamma=s[12:15], white_balance=s[15:18])
     return out
@@ -235,6 +247,26 @@ def brdf(kind, n, wo, wi, a, r, sp):
     f = lambda v: np.ascontiguousarray(v, np.float64)
     lib().orc_brdf(kind, _p(f(n)), _p(f(wo)), _p(f(wi)), _p(f(a)), float(r), float(sp), _p(out))
     return out
+
+
+def brdf_full(kind, ng, ns, wo, wi, a, r, sp, mu):
+    """The principled BRDF with metallic mu and shading normal ns: dict of f (3), the cosine
+    about ns, df/da, df/dr (3), df/dsp, df/dmu (3) and d(f_c cos)/dns (3 x 3, row c)."""
+    out = np.zeros(21)
+    f = lambda v: np.ascontiguousarray(v, np.float64)
+    lib().orc_brdf_full(kind, _p(f(ng)), _p(f(ns)), _p(f(wo)), _p(f(wi)), _p(f(a)), float(r), float(sp), float(mu),
+                        _p(out))
+    return dict(f=out[0:3], c=out[3], dfa=out[4], dfr=out[5:8], dfs=out[8], dfm=out[9:12],
+                dfcn=out[12:21].reshape(3, 3))
+
+
+def shading_frame(sc: Scene, prim: int, direction, uv):
+    """Tangent frame (T, B, n) and shading normal of a hit on triangle prim."""
+    d = sc.desc()
+    out = np.zeros(12)
+    f = lambda v: np.ascontiguousarray(v, np.float64)
+    lib().orc_shading_frame(C.byref(d), int(prim), _p(f(direction)), _p(f(uv)), _p(out))
+    return dict(T=out[0:3], B=out[3:6], n=out[6:9], ns=out[9:12])
 
 
 def sample(kind, n, wo, r, u):

@@ -357,6 +357,8 @@ class Workload:
     max_depth: int = 3
     seed: int = 0
     sample_offset: int = 0
+    metallic: np.ndarray | None = None     # [Ht,Wt] metallic map (GGX), None: 0
+    normal_map: np.ndarray | None = None   # [Ht,Wt,3] stored normal map in [0,1], None: none
 
     def scalars(self):
         return dict(prf_gamma=self.prf_gamma, prf_gain=self.prf_gain, prf_mix=self.prf_mix,

@@ -13,6 +13,7 @@ import pytest
 from oracle import oracle as O
 
 from . import test_oracle_pins as P
+from . import test_oracle_pins_brdf2 as PB
 from . import test_oracle_pins_lights as PL
 
 SRC = open(O.SRC).read()
@@ -20,8 +21,8 @@ SRC = open(O.SRC).read()
 # (name, text in the oracle, planted replacement, the pin that must fail)
 MUTANTS = [
     ("environment NEE without its pi",
-     "L[c] += beta[c] * fb.f[c] * d->env[c] * PI;",
-     "L[c] += beta[c] * fb.f[c] * d->env[c];",
+     "double es = d->nmap_sample ? PI * fb.c / dot(nss, we) : PI;",
+     "double es = d->nmap_sample ? PI * fb.c / dot(nss, we) : 1.0;",
      lambda: PL.test_environment_on_a_lambert_plane(1)),
     ("environment added on escaped bounce rays",
      "if (depth == 0)\n                for (int c = 0; c < 3; ++c) L[c] += beta[c] * d->env[c];",
@@ -48,17 +49,49 @@ MUTANTS = [
      "L[c] += fb.f[c] * E[c] * geom;",
      PL.test_integrating_sphere),
     ("projector intensity without 1/cos^3",
-     "double geom = cp / (ca * ca * ca * dist * dist);",
-     "double geom = cp / (dist * dist);",
+     "double geom = fb.c / (ca * ca * ca * dist * dist);",
+     "double geom = fb.c / (dist * dist);",
      PL.test_integrating_sphere),
-    ("adjoint: environment term missing from the albedo gradient",
-     "ga[c] += bd * Ee / PI;",
-     "ga[c] += 0.0 * Ee;",
+    ("adjoint: environment terms dropped",
+     "S[1][c] = d->env[c] * v->es;",
+     "S[1][c] = 0.0 * v->es;",
      lambda: P.test_adjoint_matches_central_differences(False, 0.4)),
-    ("adjoint: environment term missing from the roughness gradient",
-     "gr += bd * Ee * v->eds_dr;",
-     "gr += 0.0 * v->eds_dr;",
+    ("adjoint: roughness terms dropped",
+     "gr += bd * b->dfr[c] * cs;",
+     "gr += 0.0 * cs;",
      lambda: P.test_adjoint_matches_central_differences(False, 0.4)),
+    ("metallic does not scale the diffuse lobe",
+     "b.f[c] = (1.0 - mu) * a[c] / PI + F * DGw;",
+     "b.f[c] = a[c] / PI + F * DGw;",
+     PB.test_metallic_peak_at_normal_incidence),
+    ("metallic does not tint the Fresnel reflectance",
+     "double F0 = (1.0 - mu) * (0.08 * sp) + mu * a[c];",
+     "double F0 = 0.08 * sp;",
+     PB.test_metallic_peak_at_normal_incidence),
+    ("normal-map frame with the wrong handedness",
+     "*B = cross(n, *T);",
+     "*B = cross(*T, n);",
+     lambda: PB.test_normal_map_tilts_the_shading_normal_on_a_plane(False)),
+    ("normal map read without decoding 2 v - 1",
+     "v3 t = mk(2.0 * v[0] - 1.0, 2.0 * v[1] - 1.0, 2.0 * v[2] - 1.0);",
+     "v3 t = mk(v[0], v[1], v[2]);",
+     lambda: PB.test_normal_map_tilts_the_shading_normal_on_a_plane(False)),
+    ("projector cosine about the geometric normal under a normal map",
+     "double geom = fb.c / (ca * ca * ca * dist * dist);",
+     "double geom = cp / (ca * ca * ca * dist * dist);",
+     lambda: PB.test_normal_map_tilts_the_shading_normal_on_a_plane(True)),
+    ("adjoint: normal cotangent not projected onto the unit sphere",
+     "v3 gt = scl(sub(gl, scl(v->th, dot(v->th, gl))), 1.0 / v->tlen);",
+     "v3 gt = scl(gl, 1.0 / v->tlen);",
+     PB.test_adjoint_on_metallic_and_normal_map_matches_central_differences),
+    ("adjoint: metallic terms dropped",
+     "gm += bd * b->dfm[c] * cs;",
+     "gm += 0.0 * cs;",
+     PB.test_adjoint_on_metallic_and_normal_map_matches_central_differences),
+    ("adjoint: cosine derivative missing from the normal cotangent",
+     "b.dfcn[c] = add(scl(wi, (1.0 - mu) * a[c] / PI), scl(dS, F));",
+     "b.dfcn[c] = scl(dS, F);",
+     PB.test_adjoint_on_metallic_and_normal_map_matches_central_differences),
 ]
 
 
