@@ -148,6 +148,23 @@ typedef struct {
     int32_t max_depth;                    /* surface vertices per path, 1..64 (1: direct only) */
     uint64_t seed;                        /* Philox key */
     uint32_t sample_offset;               /* added to the sample index of every counter */
+    /* The principled BRDF's further maps (Sec. 3.2: theta holds the BRDF maps and the
+     * normal map v_n; Sec. 4.3: base colour, roughness, metallic, normal map), tex_h x
+     * tex_w, both optional:
+     *   metallic    (GGX only; NULL: 0) blends the dielectric specular colour 0.08 x
+     *               specular into the base colour, F0 = (1 - mu) 0.08 sp + mu a, and
+     *               scales the diffuse lobe by (1 - mu);
+     *   normal_map  (x 3, NULL: none) values v in [0, 1] decode to t = 2 v - 1 in the
+     *               tangent frame T = dP/du (the triangle's texture parameterisation,
+     *               orthogonal to the two-sided geometric normal n), B = n x T, and tilt
+     *               the shading normal to ns = (t_x T + t_y B + t_z n) / |t|; (0.5, 0.5, 1)
+     *               changes nothing.  The BRDF, the rendering equation's cosine and the
+     *               sampled directions are taken about ns; a direction counts only above
+     *               both ns and the geometric surface.
+     * With either map dpcs_render_vjp needs path records (its own or the caller's): the
+     * re-tracing mode and the request loop return DPCS_E_UNSUPPORTED. */
+    const float* metallic;
+    const float* normal_map;
 } dpcs_render_params;
 
 /* Optional per-call outputs of dpcs_render (any field may be NULL). */
@@ -176,8 +193,9 @@ DPCS_API dpcs_status dpcs_render(dpcs_context ctx, dpcs_scene scene, const dpcs_
  * DPCS_NOALLOC_SCRATCH_BYTES that every GPU the library runs on holds from context
  * creation until the process ends, and each wave holds as many paths as fit (at most
  * the context's capacity).  Profiling is suspended during the call.
- * Limit: 16 bytes per projector pixel + 16 bytes per map texel + 508 bytes per camera
- * sample of one pixel must fit in the array, else DPCS_E_INVALID before any launch.
+ * Limit: 16 bytes per projector pixel + 16 bytes per map texel (32 with the metallic or
+ * normal map) + 508 bytes per camera sample of one pixel must fit in the array, else
+ * DPCS_E_INVALID before any launch.
  * Every call on a device shares that device's array and leaves its contents there (all
  * of it is written before it is read, nothing has to start at zero): calls on one device
  * whose work overlaps on the GPU (different streams, e.g. two contexts) race; order them
@@ -194,6 +212,8 @@ typedef struct {
     float* d_roughness;         /* tex_h x tex_w */
     float* d_specular;          /* tex_h x tex_w */
     float* d_scalars;           /* DPCS_NUM_SCALARS, layout of device_scalars */
+    float* d_metallic;          /* tex_h x tex_w (needs params->metallic) */
+    float* d_normal_map;        /* tex_h x tex_w x 3, of the stored values v (needs params->normal_map) */
 } dpcs_grads;
 
 /* Vector-Jacobian product of dpcs_render at the same params (same seed: the same

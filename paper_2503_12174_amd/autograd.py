@@ -3,8 +3,9 @@
 Forward keeps each camera sample's radiance and the path records (hit leaf and
 shadow visibility per vertex, 4 B) so backward replays the same Philox paths
 without recomputing the forward samples or tracing.  Differentiable inputs: projector
-image, albedo, roughness, specular maps and the 18 response scalars
-(gamma_p[3], M[9], gamma_c[3], w[3]) as one device tensor.
+image, albedo, roughness, specular maps, the 18 response scalars
+(gamma_p[3], M[9], gamma_c[3], w[3]) as one device tensor, and optionally the metallic
+map and the normal map (stored values) of the principled BRDF.
 """
 from __future__ import annotations
 
@@ -22,33 +23,37 @@ def scalars_from(w, device="cuda") -> torch.Tensor:
 
 class DPCSRender(torch.autograd.Function):
     @staticmethod
-    def forward(fctx, proj_image, albedo, roughness, specular, scalars, ctx, scene, cfg):
+    def forward(fctx, proj_image, albedo, roughness, specular, scalars, metallic, normal_map, ctx, scene, cfg):
         proj_image, albedo = proj_image.contiguous(), albedo.contiguous()
         roughness, specular, scalars = roughness.contiguous(), specular.contiguous(), scalars.contiguous()
-        p = dpcs.params_from(cfg, albedo, roughness, specular, device_scalars=scalars)
+        metallic = None if metallic is None else metallic.contiguous()
+        normal_map = None if normal_map is None else normal_map.contiguous()
+        p = dpcs.params_from(cfg, albedo, roughness, specular, device_scalars=scalars, metallic=metallic,
+                             normal_map=normal_map)
         H, W = p.camera.height, p.camera.width
         out = torch.empty((H, W, 3), dtype=torch.float32, device=proj_image.device)
         L = torch.empty((H, W, p.spp, 3), dtype=torch.float32, device=proj_image.device)
         rec = torch.empty((H, W, p.spp, p.max_depth), dtype=torch.int32, device=proj_image.device)
         dpcs.dpcs_render(ctx, scene, p, proj_image, out, sample_radiance=L, path_records=rec)
-        fctx.save_for_backward(proj_image, albedo, roughness, specular, scalars, L, rec)
+        fctx.save_for_backward(proj_image, albedo, roughness, specular, scalars, metallic, normal_map, L, rec)
         fctx.ctx, fctx.scene, fctx.cfg = ctx, scene, cfg
         return out
 
     @staticmethod
     def backward(fctx, grad_out):
-        proj_image, albedo, roughness, specular, scalars, L, rec = fctx.saved_tensors
-        p = dpcs.params_from(fctx.cfg, albedo, roughness, specular, device_scalars=scalars)
+        proj_image, albedo, roughness, specular, scalars, metallic, normal_map, L, rec = fctx.saved_tensors
+        p = dpcs.params_from(fctx.cfg, albedo, roughness, specular, device_scalars=scalars, metallic=metallic,
+                             normal_map=normal_map)
         need = fctx.needs_input_grad
-        z = lambda t, k: torch.empty_like(t) if need[k] else None
+        z = lambda t, k: torch.empty_like(t) if (t is not None and need[k]) else None
         d_proj, d_alb, d_rough, d_spec = z(proj_image, 0), z(albedo, 1), z(roughness, 2), z(specular, 3)
-        d_scal = torch.empty_like(scalars) if need[4] else None
+        d_scal, d_metal, d_nmap = z(scalars, 4), z(metallic, 5), z(normal_map, 6)
         dpcs.dpcs_render_vjp(fctx.ctx, fctx.scene, p, proj_image, grad_out.contiguous(), sample_radiance=L,
                              path_records=rec, d_proj_image=d_proj, d_albedo=d_alb, d_roughness=d_rough, d_specular=d_spec,
-                             d_scalars=d_scal)
-        return d_proj, d_alb, d_rough, d_spec, d_scal, None, None, None
+                             d_scalars=d_scal, d_metallic=d_metal, d_normal_map=d_nmap)
+        return d_proj, d_alb, d_rough, d_spec, d_scal, d_metal, d_nmap, None, None, None
 
 
-def render(ctx, scene, cfg, proj_image, albedo, roughness, specular, scalars):
+def render(ctx, scene, cfg, proj_image, albedo, roughness, specular, scalars, metallic=None, normal_map=None):
     """I_c = R(I_p, theta) (paper Eq. 7) with gradients for every tensor argument."""
-    return DPCSRender.apply(proj_image, albedo, roughness, specular, scalars, ctx, scene, cfg)
+    return DPCSRender.apply(proj_image, albedo, roughness, specular, scalars, metallic, normal_map, ctx, scene, cfg)

@@ -148,6 +148,46 @@ __device__ __forceinline__ bool put_tex_rec(const MapBins& mb, uint32_t slot, do
     nt_st(p + 1, make_float4(g[1], g[2], g[3], g[4]));
     return true;
 }
+// BRDF-map record with the metallic and normal-map cotangents (C = 9)
+constexpr int TEX9_RS = 12;
+__device__ __forceinline__ bool put_tex9_rec(const MapBins& mb, uint32_t slot, double u, double v, const float* g) {
+    if ((int64_t)slot >= mb.cap) return false;
+    const Corners c = bilinear_corners(u * mb.W - 0.5, v * mb.H - 0.5, mb.W, mb.H);
+    float4* p = (float4*)(mb.rec + (size_t)slot * TEX9_RS);
+    nt_st(p, make_float4(__uint_as_float(map_head(c, mb.W)), (float)c.ax, (float)c.ay, g[0]));
+    nt_st(p + 1, make_float4(g[1], g[2], g[3], g[4]));
+    nt_st(p + 2, make_float4(g[5], g[6], g[7], g[8]));
+    return true;
+}
+// per-lane and wave-uniform scatter of the 9 cotangents (stride 9 per texel)
+__device__ __forceinline__ void scatter_tex9_lane(const ReqDesc& r, double u, double v, const float* gv) {
+    if (!r.d_tex) return;
+    const Bilin b = bilinear(u * r.tw - 0.5, v * r.th - 0.5, r.tw, r.th);
+    const int idx[4] = {b.i00, b.i10, b.i01, b.i11};
+    const double wt[4] = {b.w00, b.w10, b.w01, b.w11};
+    for (int k = 0; k < 4; ++k) {
+        if (wt[k] == 0.0) continue;
+        float* t = r.d_tex + 9 * (size_t)idx[k];
+        for (int j = 0; j < 9; ++j) {
+            const float val = (float)(gv[j] * wt[k]);
+            if (val != 0.0f) atomicAdd(t + j, val);
+        }
+    }
+}
+__device__ __forceinline__ void scatter_tex9(const ReqDesc& r, bool active, double u, double v, const float* gv) {
+    if (!r.d_tex) return;
+    Bilin b = bilinear(active ? u * r.tw - 0.5 : 0.0, active ? v * r.th - 0.5 : 0.0, r.tw, r.th);
+    const int idx[4] = {b.i00, b.i10, b.i01, b.i11};
+    const double wt[4] = {b.w00, b.w10, b.w01, b.w11};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float val[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) val[j] = (float)(gv[j] * wt[k]);
+        wave_scatter_add<9>(active && wt[k] != 0.0, idx[k], r.d_tex, 9, val);
+    }
+}
+
 // E_p record at projector pixel position (pu, pv); false when the buffer is full
 __device__ __forceinline__ bool put_ep_rec(const MapBins& mb, uint32_t slot, double pu, double pv, const float* g) {
     if ((int64_t)slot >= mb.cap) return false;
@@ -1003,6 +1043,215 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
     }
 }
 
+// ---------------------------------------------------------------- replay, metallic and normal maps
+// k_adj_replay for a request with the metallic and normal maps (one request per launch).
+// Every term of a vertex is beta_c f_c c S_c with c the cosine about the shading normal
+// and S_c its remaining factor: E_c / (cos^3 alpha d^2) for the projector, L_env pi / c
+// for the environment (the sampling pdf c / pi held fixed), R_{k+1} / pdf for the bounce;
+// its derivative w.r.t. a map value is beta_c d(f_c c) S_c.  For the bounce S_c is only
+// known at the next vertex, where beta_c f_c c S_c = its remaining radiance rl_c: the
+// vertex leaves the coefficients d(f_c c)/d theta / (f_c c) (PendX), the next one
+// multiplies them by delta_c rl_c.  Normal cotangents are carried in the stored map
+// values (through the vertex's frame), so the records hold 9 channels.
+__global__ void __launch_bounds__(BLOCK) k_adj_replay_ext(Queues q, AdjQueues aq, int cur, int depth, ReqDesc r) {
+    const int nxt = cur ^ 1;
+    const uint32_t n = q.cnt[cur];
+    const uint32_t base = blockIdx.x * BLOCK;
+    if (base >= n) return;   // uniform per workgroup
+    const uint32_t i = base + threadIdx.x;
+    bool cont = false;
+    PathO no{};
+    PathD nd{};
+    float4 nb = {}, nrl = {}, npn = {}, npnx = {};
+    PendX npx{};
+    double2 npuv = {};
+    float npns = 0.f;
+    bool a_on = false, b_on = false, e_on = false;
+    double a_u = 0.0, a_v = 0.0, b_u = 0.0, b_v = 0.0;
+    float ag[9] = {}, bg[9] = {};
+    double e_pu = 0.0, e_pv = 0.0;
+    float eg[3] = {0.f, 0.f, 0.f};
+    if (i < n) {
+        PathO o;
+        PathD dd;
+        float4 b, rl, penda;
+        if (depth == 0) {   // the dense camera wave, regenerated as the forward's raygen made it
+            const uint32_t g = i - r.sid_base + r.g_base;
+            const D3 cd = camera_dir(r, g);
+            o = PathO{r.cam_o[0], r.cam_o[1], r.cam_o[2], 0, -1};
+            dd = PathD{cd.x, cd.y, cd.z, g, 0u};
+            b = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
+            rl = q.L[i];
+            penda = make_float4(0.f, 0.f, 0.f, -1.f);
+        } else {
+            o = nt_ld(&q.po[cur][i]);
+            dd = nt_ld(&q.pd[cur][i]);
+            b = nt_ld(&q.pb[cur][i]);
+            rl = nt_ld(&aq.rl[cur][i]);
+            penda = nt_ld(&aq.penda[cur][i]);
+        }
+        const uint32_t g = dd.g;
+        const uint32_t sid = g - r.g_base + r.sid_base;
+        const uint32_t rec = __builtin_nontemporal_load(&r.rec[(size_t)(g - r.rec_g0) * r.max_depth + depth]);
+        const int leaf = (int)(rec & REC_LEAF) - 1;
+        const float4 dl = aq.delta[sid];
+        const D3 delta = d3(dl.x, dl.y, dl.z);
+        const D3 beta = d3(b.x, b.y, b.z);
+        if (penda.w >= 0.f) {   // settle the previous vertex: its next-event cotangents and its bounce
+            const double2 puv = nt_ld(&aq.puv[cur][i]);
+            const float4 pn = nt_ld(&aq.pn[cur][i]);
+            const float pns = nt_ld(&aq.pns[cur][i]);
+            const float4 pnx = nt_ld(&aq.pnx[cur][i]);
+            a_on = true;
+            a_u = puv.x;
+            a_v = puv.y;
+            double ga[9] = {pn.x, pn.y, pn.z, pn.w, pns, pnx.x, pnx.y, pnx.z, pnx.w};
+            if (leaf >= 0) {
+                const PendX P = nt_ld(&aq.px[cur][i]);
+                const double w[3] = {delta.x * rl.x, delta.y * rl.y, delta.z * rl.z};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    ga[c] += w[c] * P.a[c];
+                    ga[3] += w[c] * P.r[c];
+                    ga[4] += w[c] * P.s[c];
+                    ga[5] += w[c] * P.m[c];
+                    ga[6] += w[c] * P.n[3 * c];
+                    ga[7] += w[c] * P.n[3 * c + 1];
+                    ga[8] += w[c] * P.n[3 * c + 2];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 9; ++j) ag[j] = (float)ga[j];
+        }
+        if (leaf >= 0) {
+            const Surf s = surface(r, leaf, d3(o.x, o.y, o.z), d3(dd.x, dd.y, dd.z));
+            const Shading sh = shading(r, leaf, s);
+            if (r.emission) {
+                const float4 e = r.emission[leaf];
+                rl.x -= (float)(beta.x * e.x);
+                rl.y -= (float)(beta.y * e.y);
+                rl.z -= (float)(beta.z * e.z);
+            }
+            const D3 db = delta * beta;
+            double ng[6] = {0., 0., 0., 0., 0., 0.};   // albedo rgb, roughness, specular, metallic
+            D3 gnv = d3(0., 0., 0.);                   // cotangent of the shading normal
+            auto term = [&](const BrdfX& f, D3 S) {    // cotangents of beta_c f_c c S_c
+                const D3 cs = S * f.c;
+                ng[0] += db.x * f.dfa * cs.x;
+                ng[1] += db.y * f.dfa * cs.y;
+                ng[2] += db.z * f.dfa * cs.z;
+                ng[3] += db.x * f.dfr.x * cs.x + db.y * f.dfr.y * cs.y + db.z * f.dfr.z * cs.z;
+                ng[4] += (db.x * cs.x + db.y * cs.y + db.z * cs.z) * f.dfs;
+                ng[5] += db.x * f.dfm.x * cs.x + db.y * f.dfm.y * cs.y + db.z * f.dfm.z * cs.z;
+                gnv = gnv + f.dn[0] * (db.x * S.x) + f.dn[1] * (db.y * S.y) + f.dn[2] * (db.z * S.z);
+            };
+            ProjNee p;
+            if ((rec & REC_PRJ) && projector_nee(r, s, p)) {
+                const D4 E = fetch4(r.Ep, p.pb);
+                const BrdfX f = brdf_x<true>(r.brdf, s.n, sh.ns, s.wo, p.wp, s.alb, s.rough, s.spec, sh.metal);
+                const D3 S = d3(E.x, E.y, E.z) * p.g0;
+                const D3 C = beta * f.f * S * f.c;
+                const D3 gE = db * f.f * (f.c * p.g0);   // d/dE_p before the bilinear weights
+                e_on = r.dEp != nullptr;
+                e_pu = p.pu;
+                e_pv = p.pv;
+                eg[0] = (float)gE.x;
+                eg[1] = (float)gE.y;
+                eg[2] = (float)gE.z;
+                term(f, S);
+                rl.x -= (float)C.x;
+                rl.y -= (float)C.y;
+                rl.z -= (float)C.z;
+            }
+            if (r.env_on && (rec & REC_ENV)) {
+                const U4 x = vertex_rng(r, g, 2u + 2u * depth);
+                const D3 we = sample_cosine(sh.ns, u24(x.x), u24(x.y));
+                const BrdfX f = brdf_x<true>(r.brdf, s.n, sh.ns, s.wo, we, s.alb, s.rough, s.spec, sh.metal);
+                const D3 Le = d3(r.env[0], r.env[1], r.env[2]);
+                const D3 C = beta * f.f * Le * PI;
+                if (f.c > 0.0) term(f, Le * (PI / f.c));
+                rl.x -= (float)C.x;
+                rl.y -= (float)C.y;
+                rl.z -= (float)C.z;
+            }
+            const D3 gnm = nmap_cotangent(sh, s.n, gnv);
+            if (depth < r.max_depth - 1) {
+                const U4 x = vertex_rng(r, g, 1u + 2u * depth);
+                const D3 wi = sample_bounce(r.brdf, sh.ns, s.wo, s.rough, u24(x.x), u24(x.y), u24(x.z));
+                const double ci = dot(s.n, wi);
+                const double pdf = bounce_pdf(r.brdf, sh.ns, s.wo, wi, s.rough);
+                if (ci > 0.0 && pdf > 0.0) {
+                    const BrdfX f = brdf_x<true>(r.brdf, s.n, sh.ns, s.wo, wi, s.alb, s.rough, s.spec, sh.metal);
+                    const D3 nbeta = beta * (f.f * (f.c / pdf));
+                    cont = true;
+                    no = PathO{s.x.x, s.x.y, s.x.z, o.slot, s.prim};
+                    nd = PathD{wi.x, wi.y, wi.z, g, 0u};
+                    nb = make_float4((float)nbeta.x, (float)nbeta.y, (float)nbeta.z, 0.0f);
+                    nrl = rl;
+                    npuv = make_double2(s.u, s.v);
+                    const double fv[3] = {f.f.x, f.f.y, f.f.z};
+                    const double dfr[3] = {f.dfr.x, f.dfr.y, f.dfr.z}, dfm[3] = {f.dfm.x, f.dfm.y, f.dfm.z};
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const double inv = fv[c] > 0.0 ? 1.0 / fv[c] : 0.0;
+                        npx.a[c] = (float)(f.dfa * inv);
+                        npx.r[c] = (float)(dfr[c] * inv);
+                        npx.s[c] = (float)(f.dfs * inv);
+                        npx.m[c] = (float)(dfm[c] * inv);
+                        const D3 pn = nmap_cotangent(sh, s.n, f.dn[c]) * (inv / f.c);
+                        npx.n[3 * c] = (float)pn.x;
+                        npx.n[3 * c + 1] = (float)pn.y;
+                        npx.n[3 * c + 2] = (float)pn.z;
+                    }
+                    npn = make_float4((float)ng[0], (float)ng[1], (float)ng[2], (float)ng[3]);
+                    npns = (float)ng[4];
+                    npnx = make_float4((float)ng[5], (float)gnm.x, (float)gnm.y, (float)gnm.z);
+                }
+            }
+            if (!cont) {   // the path ends here: its next-event cotangents go out now
+                b_on = true;
+                b_u = s.u;
+                b_v = s.v;
+#pragma unroll
+                for (int j = 0; j < 6; ++j) bg[j] = (float)ng[j];
+                bg[6] = (float)gnm.x;
+                bg[7] = (float)gnm.y;
+                bg[8] = (float)gnm.z;
+            }
+        }
+    }
+    if (aq.tb.rec) {   // records for the binned flush (direct atomics if full)
+        const bool to_e = e_on && aq.eb.rec;
+        const bool pred[3] = {a_on, b_on, to_e};
+        uint32_t* const ctr[3] = {aq.tb.count, aq.tb.count, aq.eb.count};
+        uint32_t at[3];
+        block_append<3>(pred, ctr, at);
+        if (a_on && !put_tex9_rec(aq.tb, at[0], a_u, a_v, ag)) scatter_tex9_lane(r, a_u, a_v, ag);
+        if (b_on && !put_tex9_rec(aq.tb, at[1], b_u, b_v, bg)) scatter_tex9_lane(r, b_u, b_v, bg);
+        if (e_on && !(to_e && put_ep_rec(aq.eb, at[2], e_pu, e_pv, eg))) scatter_ep_lane(r, e_pu, e_pv, eg);
+    } else {
+        scatter_tex9(r, a_on, a_u, a_v, ag);
+        scatter_tex9(r, b_on, b_u, b_v, bg);
+        if (r.dEp) scatter_ep(r, e_on, e_pu, e_pv, eg);
+    }
+    const bool pred[1] = {cont};
+    uint32_t* const ctr[1] = {&q.cnt[nxt]};
+    uint32_t jn;
+    block_append<1>(pred, ctr, &jn);
+    if (cont) {
+        nt_st(&q.po[nxt][jn], no);
+        nt_st(&q.pd[nxt][jn], nd);
+        nt_st(&q.pb[nxt][jn], nb);
+        nt_st(&aq.rl[nxt][jn], nrl);
+        nt_st(&aq.puv[nxt][jn], npuv);
+        nt_st(&aq.penda[nxt][jn], make_float4(0.f, 0.f, 0.f, 1.f));
+        nt_st(&aq.pn[nxt][jn], npn);
+        nt_st(&aq.pns[nxt][jn], npns);
+        nt_st(&aq.pnx[nxt][jn], npnx);
+        nt_st(&aq.px[nxt][jn], npx);
+    }
+}
+
 // ---------------------------------------------------------------- finish
 // Eq. 1 backward per texel: z = g_p M y, y = I_p^gamma_p, E_p = max(0, z)
 __global__ void k_adj_prf(ReqDesc r, float* __restrict__ d_proj, float* __restrict__ acc) {
@@ -1047,10 +1296,26 @@ __global__ void k_adj_prf(ReqDesc r, float* __restrict__ d_proj, float* __restri
 }
 
 // scalar gradients and the de-interleaving of the map cotangents
-__global__ void k_adj_maps(ReqDesc r, float* d_albedo, float* d_rough, float* d_spec) {
+__global__ void k_adj_maps(ReqDesc r, float* d_albedo, float* d_rough, float* d_spec, float* d_metal,
+                           float* d_nmap) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= r.tw * r.th) return;
-    const float* s = r.d_tex + 5 * (size_t)t;
+    const float* s = r.d_tex + (size_t)r.dtex_c * t;
+    if (r.dtex_c == 9) {
+        if (d_metal) d_metal[t] = r.brdf ? s[5] : 0.f;
+        if (d_nmap) {
+            d_nmap[3 * (size_t)t] = s[6];
+            d_nmap[3 * (size_t)t + 1] = s[7];
+            d_nmap[3 * (size_t)t + 2] = s[8];
+        }
+    } else {
+        if (d_metal) d_metal[t] = 0.f;
+        if (d_nmap) {
+            d_nmap[3 * (size_t)t] = 0.f;
+            d_nmap[3 * (size_t)t + 1] = 0.f;
+            d_nmap[3 * (size_t)t + 2] = 0.f;
+        }
+    }
     if (d_albedo) {
         d_albedo[3 * (size_t)t] = s[0];
         d_albedo[3 * (size_t)t + 1] = s[1];
@@ -1117,6 +1382,10 @@ void launch_adj_shadow(const Launch& l, const Queues& q, const AdjQueues& aq, in
 void launch_adj_replay(const Launch& l, const Queues& q, const AdjQueues& aq, int cur, int depth, const ReqDesc& uni,
                        const ReqDesc* table, int64_t n_upper) {
     const dim3 g(grid_of(n_upper, BLOCK)), b(BLOCK);
+    if (!table && uni.tex4b) {
+        hipLaunchKernelGGL(k_adj_replay_ext, g, b, 0, l.st, q, aq, cur, depth, uni);
+        return;
+    }
     if (table) hipLaunchKernelGGL((k_adj_replay<false>), g, b, 0, l.st, q, aq, cur, depth, uni, table);
     else hipLaunchKernelGGL((k_adj_replay<true>), g, b, 0, l.st, q, aq, cur, depth, uni, table);
 }
@@ -1141,17 +1410,20 @@ static void flush_one(const Launch& l, const MapBins& mb, float* out, int stride
                        stride);
 }
 void launch_map_flush(const Launch& l, const AdjQueues& aq, const ReqDesc& r) {
-    if (aq.tb.rec && r.d_tex) flush_one<5, TEX_RS>(l, aq.tb, r.d_tex, 5);
+    if (aq.tb.rec && r.d_tex) {
+        if (r.dtex_c == 9) flush_one<9, TEX9_RS>(l, aq.tb, r.d_tex, 9);
+        else flush_one<5, TEX_RS>(l, aq.tb, r.d_tex, 5);
+    }
     if (aq.eb.rec && r.dEp) flush_one<3, EP_RS>(l, aq.eb, r.dEp, 4);
 }
 void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* d_albedo, float* d_rough,
-                       float* d_spec, float* d_scalars, float* acc) {
+                       float* d_spec, float* d_scalars, float* acc, float* d_metal, float* d_nmap) {
     const unsigned g = grid_of((int64_t)r.Wp * r.Hp, BLOCK);
     hipLaunchKernelGGL(k_adj_prf, dim3(g), dim3(BLOCK), 0, l.st, r, d_proj, acc);
     if (r.d_part) hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, l.st, r.d_part, (int)g, 12, 12, acc + 8);
-    if (d_albedo || d_rough || d_spec)
+    if (d_albedo || d_rough || d_spec || d_metal || d_nmap)
         hipLaunchKernelGGL(k_adj_maps, dim3(grid_of((int64_t)r.tw * r.th, 256)), dim3(256), 0, l.st, r, d_albedo,
-                           d_rough, d_spec);
+                           d_rough, d_spec, d_metal, d_nmap);
     hipLaunchKernelGGL(k_adj_scalars, dim3(1), dim3(64), 0, l.st, r, (const float*)acc, d_scalars);
 }
 

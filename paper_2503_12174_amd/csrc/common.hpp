@@ -159,6 +159,8 @@ struct ReqDesc {
     int32_t tw, th;
     const float4* tex4;      // packed (albedo rgb, roughness) per texel
     const float* spec;       // specular per texel
+    const float4* tex4b;     // packed (normal map rgb, metallic) per texel, or null: neither map
+    int32_t dtex_c;          // cotangent channels per texel of d_tex: 5, or 9 with tex4b
     // lights
     const float4* Ep;        // projector irradiance after the PRF, per texel (rgb, -)
     float env[3];
@@ -184,7 +186,8 @@ struct ReqDesc {
     const float* grad_image;   // dLoss/dI_c, or null with target set
     const float* target;       // L2 target (server compensation step)
     float* dEp;                // cotangent of E_p, 4 floats per texel
-    float* d_tex;              // cotangent of (albedo rgb, roughness, specular), 5 floats per texel
+    float* d_tex;              // cotangent of (albedo rgb, roughness, specular[, metallic, normal
+                               // map rgb]), dtex_c floats per texel
     float* d_acc;              // 8 floats: d gamma_c[3], d w[3], d threshold, pad
     float* d_part;             // per-workgroup partials of the scalar sums (summed in a fixed
                                // order by a second kernel), or null: float atomics into d_acc
@@ -254,6 +257,88 @@ __device__ __forceinline__ Brdf brdf_eval(int kind, D3 n, D3 wo, D3 wi, D3 alb, 
         const double da_dr = (r * r > ALPHA_MIN) ? 2.0 * r : 0.0;
         b.ds_dr = s * (dlnD + dlnG) * da_dr;
         b.ds_dsp = 0.08 * (1.0 - m5) * DGw;
+    }
+    return b;
+}
+
+// The principled BRDF with metallic mu and a shading normal ns (Sec. 3.2; the readings of
+// Burley's model and of the normal map are stated with dpcs_render_params): base colour
+// a, f_c = (1 - mu) a_c / pi + F_c D G / (4 cos_i cos_o), F0_c = (1 - mu) 0.08 sp + mu a_c,
+// cosines about ns; f = 0 unless wi and wo lie above ns and wi above the geometric
+// normal ng.  GRAD adds the derivatives the adjoint needs: of f_c w.r.t. a_c, r, sp, mu
+// and of f_c times c = ns.wi w.r.t. ns (as a free vector).  Same unnormalised-half-vector
+// evaluation as brdf_eval.
+struct BrdfX {
+    D3 f;
+    double c;       // ns . wi
+    double dfa;     // d f_c / d a_c (every channel)
+    D3 dfr;         // d f_c / d r
+    double dfs;     // d f_c / d sp (every channel)
+    D3 dfm;         // d f_c / d mu
+    D3 dn[3];       // d (f_c c) / d ns, per channel
+};
+template <bool GRAD>
+__device__ __forceinline__ BrdfX brdf_x(int kind, D3 ng, D3 ns, D3 wo, D3 wi, D3 alb, double r, double sp,
+                                        double mu) {
+    BrdfX b;
+    b.f = d3(0., 0., 0.);
+    b.c = dot(ns, wi);
+    b.dfa = b.dfs = 0.0;
+    b.dfr = b.dfm = d3(0., 0., 0.);
+    b.dn[0] = b.dn[1] = b.dn[2] = d3(0., 0., 0.);
+    const double ci = b.c, co = dot(ns, wo);
+    if (ci <= 0.0 || co <= 0.0 || dot(ng, wi) <= 0.0) return b;
+    if (kind == 0) {
+        b.f = alb * (1.0 / PI);
+        if (GRAD) {
+            b.dfa = 1.0 / PI;
+            b.dn[0] = wi * (alb.x / PI);
+            b.dn[1] = wi * (alb.y / PI);
+            b.dn[2] = wi * (alb.z / PI);
+        }
+        return b;
+    }
+    const D3 v = wi + wo;
+    const double vv = dot(v, v), nv = dot(ns, v);
+    const D3 nxv = cross(ns, v);
+    const double c2v = nv * nv, s2v = dot(nxv, nxv);
+    const double a = ggx_alpha(r);
+    const double a2 = a * a;
+    const double kv = a2 * c2v + s2v;
+    const double qi = sqrt(a2 + (1.0 - a2) * ci * ci), qo = sqrt(a2 + (1.0 - a2) * co * co);
+    const double m = 1.0 - 0.5 * sqrt(vv);
+    const double m5 = m * m * m * m * m;
+    const double DGw = a2 * vv * vv / (PI * kv * kv * (ci + qi) * (co + qo));   // D G / (4 ci co)
+    const double kd = 1.0 - mu;
+    const D3 F0 = d3(kd * (0.08 * sp) + mu * alb.x, kd * (0.08 * sp) + mu * alb.y, kd * (0.08 * sp) + mu * alb.z);
+    const D3 F = d3(F0.x + (1.0 - F0.x) * m5, F0.y + (1.0 - F0.y) * m5, F0.z + (1.0 - F0.z) * m5);
+    b.f = alb * (kd / PI) + F * DGw;
+    if (GRAD) {
+        const double dlnD = 2.0 / a * (1.0 - 2.0 * a2 * c2v / kv);
+        const double dlnG = -a * ((1.0 - ci * ci) / (qi * (ci + qi)) + (1.0 - co * co) / (qo * (co + qo)));
+        const double da_dr = (r * r > ALPHA_MIN) ? 2.0 * r : 0.0;
+        const double dDGw_dr = DGw * (dlnD + dlnG) * da_dr;
+        b.dfa = kd / PI + mu * (1.0 - m5) * DGw;
+        b.dfr = F * dDGw_dr;
+        b.dfs = kd * 0.08 * (1.0 - m5) * DGw;
+        b.dfm = alb * (-1.0 / PI) + (alb - d3(0.08 * sp, 0.08 * sp, 0.08 * sp)) * ((1.0 - m5) * DGw);
+        // f_c c = (1 - mu) a_c c / pi + F_c S, S = D G1i G1o / (4 co) = DGw ci; with
+        // c_h = ns.h (h = v / |v|): dD/dc_h = -4 a^2 c_h (a^2 - 1) / (pi k^3), k = kv / vv,
+        // dG1/dc = 2 a^2 / (q (c + q)^2), and dS/dns = (dD/dc_h h G1i G1o + D dG1i wi G1o
+        // + D G1i dG1o wo) / (4 co) - S / co wo
+        const double iv = 1.0 / sqrt(vv);
+        const double ch = nv * iv;
+        const double k = kv / vv;
+        const double D = a2 / (PI * k * k);
+        const double G1i = 2.0 * ci / (ci + qi), G1o = 2.0 * co / (co + qo);
+        const double dD = -4.0 * a2 * ch * (a2 - 1.0) / (PI * k * k * k);
+        const double dG1i = 2.0 * a2 / (qi * (ci + qi) * (ci + qi)), dG1o = 2.0 * a2 / (qo * (co + qo) * (co + qo));
+        const double S = DGw * ci;
+        const double i4 = 1.0 / (4.0 * co);
+        const D3 dS = v * (dD * G1i * G1o * i4 * iv) + wi * (D * dG1i * G1o * i4) + wo * (D * G1i * dG1o * i4 - S / co);
+        b.dn[0] = wi * (kd * alb.x / PI) + dS * F.x;
+        b.dn[1] = wi * (kd * alb.y / PI) + dS * F.y;
+        b.dn[2] = wi * (kd * alb.z / PI) + dS * F.z;
     }
     return b;
 }

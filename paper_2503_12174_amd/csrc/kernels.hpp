@@ -113,6 +113,9 @@ struct MapBins {
 };
 
 // adjoint additions (see adjoint.hip)
+struct alignas(16) PendX {   // per channel c: albedo, roughness, specular, metallic, normal map (xyz)
+    float a[3], r[3], s[3], m[3], n[9], pad[3];
+};
 struct AdjQueues {
     float4* rl[2];     // remaining radiance L_r of the path (rgb, -), follows the path queue
     float4* delta;     // per batch sample cotangent of its radiance (rgb, -)
@@ -126,7 +129,14 @@ struct AdjQueues {
     double2* puv[2];   // pending bounce: texture coordinate (u, v) of the previous vertex
     float2* pend[2];   // pending bounce: (dr, dsp) cotangent scale of the previous vertex
     float4* penda[2];  // pending bounce: albedo cotangent scale rgb
-    MapBins tb;        // BRDF-map cotangent records (C = 5, 8 floats per record)
+    // with the metallic and normal maps (replay only): the pending bounce's derivative
+    // coefficients (d(f_c c)/d theta) / (f_c c) for albedo, roughness, specular, metallic
+    // and the normal map's stored values (21 floats, PendX) and the pending next-event
+    // cotangents of metallic and the normal map (float4)
+    struct PendX* px[2];
+    float4* pnx[2];
+    MapBins tb;        // BRDF-map cotangent records (C = 5, 8 floats per record; C = 9, 12 floats
+                       // with the metallic and normal maps)
     MapBins eb;        // E_p cotangent records (C = 3, 6 floats per record)
 };
 
@@ -139,6 +149,7 @@ struct Launch {
 // belongs to one request (table == null), else descriptors are read from `table`.
 void launch_prf(const Launch& l, const ReqDesc& r, float4* Ep);
 void launch_pack_tex(const Launch& l, const ReqDesc& r, const float* albedo, const float* rough, float4* tex4);
+void launch_pack_tex_b(const Launch& l, const ReqDesc& r, const float* nmap, const float* metal, float4* tex4b);
 void launch_set_count(const Launch& l, uint32_t* cnt, int idx, uint32_t value, int zero_from, int zero_to);
 void launch_raygen(const Launch& l, const Queues& q, const ReqDesc& r, const ReqDesc* table, int slot,
                    uint32_t g0, uint32_t n, bool adjoint, const AdjQueues* aq);
@@ -176,7 +187,8 @@ void launch_map_flush(const Launch& l, const AdjQueues& aq, const ReqDesc& r);
 bool map_tiling(int W, int H, int& T, int& nbx, int& nby);
 // PRF backward, map de-interleave and scalar gradients; acc: 20 floats (see adjoint.hip)
 void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* d_albedo, float* d_rough,
-                       float* d_spec, float* d_scalars, float* acc);
+                       float* d_spec, float* d_scalars, float* acc, float* d_metal = nullptr,
+                       float* d_nmap = nullptr);
 void launch_zero(const Launch& l, float* p, int64_t n);
 
 // debug

@@ -44,6 +44,15 @@ __global__ void k_pack_tex(int n, const float* __restrict__ albedo, const float*
     tex4[t] = make_float4(albedo[3 * t], albedo[3 * t + 1], albedo[3 * t + 2], rough ? rough[t] : 0.0f);
 }
 
+// (normal map rgb, metallic) per texel; absent maps stand for no change / metallic 0
+__global__ void k_pack_tex_b(int n, const float* __restrict__ nmap, const float* __restrict__ metal,
+                             float4* __restrict__ tex4b) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    tex4b[t] = make_float4(nmap ? nmap[3 * t] : 0.5f, nmap ? nmap[3 * t + 1] : 0.5f, nmap ? nmap[3 * t + 2] : 1.0f,
+                           metal ? metal[t] : 0.0f);
+}
+
 __global__ void k_set_count(uint32_t* cnt, int idx, uint32_t value, int zero_from, int zero_to) {
     if (threadIdx.x == 0) {
         if (idx >= 0) cnt[idx] = value;
@@ -106,7 +115,9 @@ __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_trace(Queues q, int 
 }
 
 // ---------------------------------------------------------------- shading
-template <bool UNI>
+// EXT: the request has the metallic and normal maps (tex4b): BRDF, cosines and sampling
+// about the shading normal (one request per launch)
+template <bool UNI, bool EXT>
 __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, ReqDesc uni,
                                                  const ReqDesc* __restrict__ table) {
     const int nxt = cur ^ 1;
@@ -152,11 +163,20 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
                     L.z += (float)(beta.z * e.z);
                     q.L[sid] = L;
                 }
+                Shading sh{};
+                if constexpr (EXT) sh = shading(r, leaf, s);
+                const D3 ns = EXT ? sh.ns : s.n;
                 ProjNee p;
                 if (projector_nee(r, s, p)) {
                     const D4 E = fetch4(r.Ep, p.pb);
-                    const Brdf f = brdf_eval<false>(r.brdf, s.n, s.wo, p.wp, s.alb, s.rough, s.spec);
-                    const D3 C = beta * f.f * d3(E.x, E.y, E.z) * p.geom;
+                    D3 C;
+                    if constexpr (EXT) {
+                        const BrdfX f = brdf_x<false>(r.brdf, s.n, ns, s.wo, p.wp, s.alb, s.rough, s.spec, sh.metal);
+                        C = beta * f.f * d3(E.x, E.y, E.z) * (f.c * p.g0);
+                    } else {
+                        const Brdf f = brdf_eval<false>(r.brdf, s.n, s.wo, p.wp, s.alb, s.rough, s.spec);
+                        C = beta * f.f * d3(E.x, E.y, E.z) * p.geom;
+                    }
                     if (r.rec || C.x > 0.0 || C.y > 0.0 || C.z > 0.0) {
                         shp = true;
                         po = f4(to_f(s.x), __int_as_float(o.slot));
@@ -167,9 +187,11 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
                 }
                 if (r.env_on) {
                     const U4 x = vertex_rng(r, g, 2u + 2u * depth);
-                    const D3 we = sample_cosine(s.n, u24(x.x), u24(x.y));
-                    const Brdf f = brdf_eval<false>(r.brdf, s.n, s.wo, we, s.alb, s.rough, s.spec);
-                    const D3 C = beta * f.f * d3(r.env[0], r.env[1], r.env[2]) * PI;
+                    const D3 we = sample_cosine(ns, u24(x.x), u24(x.y));
+                    D3 fv;
+                    if constexpr (EXT) fv = brdf_x<false>(r.brdf, s.n, ns, s.wo, we, s.alb, s.rough, s.spec, sh.metal).f;
+                    else fv = brdf_eval<false>(r.brdf, s.n, s.wo, we, s.alb, s.rough, s.spec).f;
+                    const D3 C = beta * fv * d3(r.env[0], r.env[1], r.env[2]) * PI;
                     if (r.rec || C.x > 0.0 || C.y > 0.0 || C.z > 0.0) {
                         she = true;
                         eo = f4(to_f(s.x), __int_as_float(o.slot));
@@ -179,12 +201,18 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
                 }
                 if (depth < r.max_depth - 1) {
                     const U4 x = vertex_rng(r, g, 1u + 2u * depth);
-                    const D3 wi = sample_bounce(r.brdf, s.n, s.wo, s.rough, u24(x.x), u24(x.y), u24(x.z));
-                    const double ci = dot(s.n, wi);
-                    const double pdf = bounce_pdf(r.brdf, s.n, s.wo, wi, s.rough);
+                    const D3 wi = sample_bounce(r.brdf, ns, s.wo, s.rough, u24(x.x), u24(x.y), u24(x.z));
+                    const double ci = dot(s.n, wi);   // the path goes on above the geometric surface
+                    const double pdf = bounce_pdf(r.brdf, ns, s.wo, wi, s.rough);
                     if (ci > 0.0 && pdf > 0.0) {
-                        const Brdf f = brdf_eval<false>(r.brdf, s.n, s.wo, wi, s.alb, s.rough, s.spec);
-                        const D3 nbeta = beta * (f.f * (ci / pdf));
+                        D3 nbeta;
+                        if constexpr (EXT) {
+                            const BrdfX f = brdf_x<false>(r.brdf, s.n, ns, s.wo, wi, s.alb, s.rough, s.spec, sh.metal);
+                            nbeta = beta * (f.f * (f.c / pdf));
+                        } else {
+                            const Brdf f = brdf_eval<false>(r.brdf, s.n, s.wo, wi, s.alb, s.rough, s.spec);
+                            nbeta = beta * (f.f * (ci / pdf));
+                        }
                         cont = true;
                         no = PathO{s.x.x, s.x.y, s.x.z, o.slot, s.prim};
                         nd = PathD{wi.x, wi.y, wi.z, g, 0u};
@@ -414,6 +442,10 @@ void launch_pack_tex(const Launch& l, const ReqDesc& r, const float* albedo, con
     const int n = r.tw * r.th;
     hipLaunchKernelGGL(k_pack_tex, dim3(grid_of(n, 256)), dim3(256), 0, l.st, n, albedo, rough, tex4);
 }
+void launch_pack_tex_b(const Launch& l, const ReqDesc& r, const float* nmap, const float* metal, float4* tex4b) {
+    const int n = r.tw * r.th;
+    hipLaunchKernelGGL(k_pack_tex_b, dim3(grid_of(n, 256)), dim3(256), 0, l.st, n, nmap, metal, tex4b);
+}
 void launch_set_count(const Launch& l, uint32_t* cnt, int idx, uint32_t value, int zero_from, int zero_to) {
     hipLaunchKernelGGL(k_set_count, dim3(1), dim3(64), 0, l.st, cnt, idx, value, zero_from, zero_to);
 }
@@ -441,8 +473,9 @@ void launch_trace(const Launch& l, const Queues& q, int cur, const ReqDesc& uni,
 void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const ReqDesc& uni, const ReqDesc* table,
                   int64_t n_upper) {
     const dim3 g(grid_of(n_upper, BLOCK)), b(BLOCK);
-    if (table) hipLaunchKernelGGL((k_shade<false>), g, b, 0, l.st, q, cur, depth, uni, table);
-    else hipLaunchKernelGGL((k_shade<true>), g, b, 0, l.st, q, cur, depth, uni, table);
+    if (table) hipLaunchKernelGGL((k_shade<false, false>), g, b, 0, l.st, q, cur, depth, uni, table);
+    else if (uni.tex4b) hipLaunchKernelGGL((k_shade<true, true>), g, b, 0, l.st, q, cur, depth, uni, table);
+    else hipLaunchKernelGGL((k_shade<true, false>), g, b, 0, l.st, q, cur, depth, uni, table);
 }
 void launch_shadow(const Launch& l, const Queues& q, int which, const ReqDesc& uni, const ReqDesc* table,
                    int64_t n_upper, int depth, bool one_tree) {

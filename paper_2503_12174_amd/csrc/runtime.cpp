@@ -112,10 +112,11 @@ bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpc
     return true;
 }
 
-bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues& aq, dpcs_status* st) {
+bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues& aq, dpcs_status* st, bool ext) {
     const size_t c = (size_t)cap;
-    // per path 2 x 144 + 16 bytes; + 256 bytes of alignment slack per part (23 parts)
-    const size_t bytes = c * (2 * 144 + 16) + 32 * 256;
+    // per path 2 x 144 + 16 bytes (+ 2 x 112 with the metallic / normal maps); + 256 bytes
+    // of alignment slack per part (27 parts)
+    const size_t bytes = c * (2 * 144 + 16 + (ext ? 2 * (sizeof(PendX) + 16) : 0)) + 32 * 256;
     char* b = (char*)scratch(ctx, name, bytes, st);
     if (!b) return false;
     auto take = [&](size_t n) {
@@ -135,6 +136,8 @@ bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues&
         aq.ss[k] = (float*)take(4 * c);
         aq.pn[k] = (float4*)take(16 * c);
         aq.pns[k] = (float*)take(4 * c);
+        aq.px[k] = ext ? (PendX*)take(sizeof(PendX) * c) : nullptr;
+        aq.pnx[k] = ext ? (float4*)take(16 * c) : nullptr;
     }
     aq.delta = (float4*)take(16 * c);
     aq.tb = MapBins{};
@@ -296,6 +299,7 @@ bool fill_desc(dpcs_context, ReqDesc& r, const dpcs_render_params* p, dpcs_scene
     for (int k = 0; k < 9; ++k) r.scal[3 + k] = p->prf_mix[k];
     r.dscal = p->device_scalars;
     r.proj_image = proj_image;
+    r.dtex_c = (p->metallic || p->normal_map) ? 9 : 5;   // tex4b is set where the maps are packed
     return true;
 }
 
@@ -832,15 +836,22 @@ namespace dpcs {
 // Per-request resident inputs of a render: E_p after the PRF and the packed maps.
 bool prepare_request(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, const char* tag, dpcs_status* st) {
     Launch l{ctx->stream, ctx->grid_cap};
-    std::string a = std::string(tag) + ".Ep", b = std::string(tag) + ".tex";
+    std::string a = std::string(tag) + ".Ep", b = std::string(tag) + ".tex", c = std::string(tag) + ".texb";
     float4* Ep = (float4*)scratch(ctx, a.c_str(), sizeof(float4) * (size_t)r.Wp * r.Hp, st);
     if (!Ep) return false;
     float4* tex = (float4*)scratch(ctx, b.c_str(), sizeof(float4) * (size_t)r.tw * r.th, st);
     if (!tex) return false;
+    float4* texb = nullptr;
+    if (p->metallic || p->normal_map) {
+        texb = (float4*)scratch(ctx, c.c_str(), sizeof(float4) * (size_t)r.tw * r.th, st);
+        if (!texb) return false;
+    }
     launch_prf(l, r, Ep);
     launch_pack_tex(l, r, p->albedo, p->brdf == DPCS_BRDF_GGX ? p->roughness : nullptr, tex);
+    if (texb) launch_pack_tex_b(l, r, p->normal_map, p->brdf == DPCS_BRDF_GGX ? p->metallic : nullptr, texb);
     r.Ep = Ep;
     r.tex4 = tex;
+    r.tex4b = texb;
     return true;
 }
 
@@ -959,13 +970,15 @@ static dpcs_status render_impl(dpcs_context ctx, dpcs_scene scene, const dpcs_re
     const int64_t npix = (int64_t)r.Wc * r.Hc;
     int64_t cap = std::min<int64_t>(std::max<int64_t>(ctx->capacity, r.spp), npix * r.spp);
     Queues q;
-    float4 *na_Ep = nullptr, *na_tex = nullptr;
+    float4 *na_Ep = nullptr, *na_tex = nullptr, *na_texb = nullptr;
     if (noalloc) {
         if (!ctx->noalloc)
             return fail(ctx, DPCS_E_DEVICE, std::string("no-alloc scratch of this device unavailable: ") +
                                                 hipGetErrorString((hipError_t)ctx->noalloc_err));
         const size_t ep_b = (sizeof(float4) * (size_t)r.Wp * r.Hp + 255) & ~size_t(255);
-        const size_t tex_b = (sizeof(float4) * (size_t)r.tw * r.th + 255) & ~size_t(255);
+        const bool ext = params->metallic || params->normal_map;
+        const size_t tex1 = (sizeof(float4) * (size_t)r.tw * r.th + 255) & ~size_t(255);
+        const size_t tex_b = ext ? 2 * tex1 : tex1;
         // every path takes its queue entries and a traversal thread's spill space
         const size_t per_path = queue_bytes(1, 0) - 32 * 256 + 4 * (size_t)SPILL;
         const size_t fixed = 32 * 256 + 4 * (size_t)TRACE_TB * SPILL;
@@ -978,8 +991,10 @@ static dpcs_status render_impl(dpcs_context ctx, dpcs_scene scene, const dpcs_re
         char* base = (char*)ctx->noalloc;
         na_Ep = (float4*)base;
         na_tex = (float4*)(base + ep_b);
+        na_texb = ext ? (float4*)(base + ep_b + tex1) : nullptr;
         r.Ep = na_Ep;
         r.tex4 = na_tex;
+        r.tex4b = na_texb;
         if (ep_b + tex_b + queue_bytes(cap, tb) > NOALLOC_BYTES)
             return fail(ctx, DPCS_E_INVALID, "dpcs_render_noalloc: internal sizing error");
         carve_queues(base + ep_b + tex_b, cap, tb, q);
@@ -991,6 +1006,9 @@ static dpcs_status render_impl(dpcs_context ctx, dpcs_scene scene, const dpcs_re
         Launch l{ctx->stream, ctx->grid_cap};
         launch_prf(l, r, na_Ep);
         launch_pack_tex(l, r, params->albedo, params->brdf == DPCS_BRDF_GGX ? params->roughness : nullptr, na_tex);
+        if (na_texb)
+            launch_pack_tex_b(l, r, params->normal_map, params->brdf == DPCS_BRDF_GGX ? params->metallic : nullptr,
+                              na_texb);
         ctx->prof_mode = 0;   // profiling records events and pinned counts; not on this path
     } else {
         if (!prepare_request(ctx, r, params, "fwd", &st)) return st;

@@ -86,7 +86,9 @@ bool make_queues(dpcs_context ctx, const char* name, int64_t cap, Queues& q, dpc
 // workgroups, and their layout from base (256-byte aligned)
 size_t queue_bytes(int64_t cap, int trace_blocks);
 void carve_queues(char* base, int64_t cap, int trace_blocks, Queues& q);
-bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues& aq, dpcs_status* st);
+// ext: also the pending buffers of the metallic / normal-map replay
+bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues& aq, dpcs_status* st,
+                     bool ext = false);
 void make_map_bins(dpcs_context ctx, const Launch& l, MapBins& mb, const char* name, int W, int H, int C, int RS,
                    int64_t cap);
 

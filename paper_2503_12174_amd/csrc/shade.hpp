@@ -122,6 +122,60 @@ struct Surf {
     double rough, spec;
 };
 
+// The normal map's shading frame and the metallic value at a hit (requests with tex4b):
+// T along dP/du of the triangle's texture parameterisation, orthogonal to the two-sided
+// geometric normal n (the Duff et al. basis when the parameterisation is degenerate),
+// B = n x T; the map value v decodes to t = 2 v - 1 and ns = (t_x T + t_y B + t_z n) / |t|
+// (n itself when t = 0).  th = t / |t|, tlen = |t| for the chain rule back to v.
+struct Shading {
+    D3 ns, T, B, th;
+    double tlen, metal;
+};
+__device__ __forceinline__ Shading shading(const ReqDesc& r, int leaf, const Surf& s) {
+    Shading h;
+    V3 f0, f1, f2;
+    int prim;
+    load_tri(r.tris, leaf, f0, f1, f2, prim);
+    const D3 e1 = to_d(f1) - to_d(f0), e2 = to_d(f2) - to_d(f0);
+    const float4 ua = r.tri_uv[2 * leaf], ub = r.tri_uv[2 * leaf + 1];
+    const double du1 = (double)ua.z - ua.x, dv1 = (double)ua.w - ua.y;
+    const double du2 = (double)ub.x - ua.x, dv2 = (double)ub.y - ua.y;
+    const double det = du1 * dv2 - du2 * dv1;
+    D3 t = d3(0., 0., 0.);
+    if (det != 0.0) {
+        const D3 dpdu = (e1 * dv2 - e2 * dv1) * (1.0 / det);
+        t = dpdu - s.n * dot(s.n, dpdu);
+    }
+    const double tl = sqrt(dot(t, t));
+    if (tl > 0.0) {
+        h.T = t * (1.0 / tl);
+    } else {   // first axis of the Duff et al. basis of n
+        const double sg = copysign(1.0, s.n.z);
+        const double a = -1.0 / (sg + s.n.z);
+        h.T = d3(1.0 + sg * s.n.x * s.n.x * a, sg * s.n.x * s.n.y * a, -sg * s.n.x);
+    }
+    h.B = cross(s.n, h.T);
+    const D4 m = fetch4(r.tex4b, s.tb);
+    h.metal = r.brdf ? m.w : 0.0;
+    const D3 tv = d3(2.0 * m.x - 1.0, 2.0 * m.y - 1.0, 2.0 * m.z - 1.0);
+    h.tlen = sqrt(dot(tv, tv));
+    if (h.tlen > 0.0) {
+        h.th = tv * (1.0 / h.tlen);
+        h.ns = h.T * h.th.x + h.B * h.th.y + s.n * h.th.z;
+    } else {
+        h.th = d3(0., 0., 1.);
+        h.ns = s.n;
+    }
+    return h;
+}
+// cotangent of the stored map value v from a cotangent g of ns: ns = F t / |t|, t = 2 v - 1
+__device__ __forceinline__ D3 nmap_cotangent(const Shading& h, const D3& n, D3 g) {
+    if (!(h.tlen > 0.0)) return d3(0., 0., 0.);
+    const D3 gl = d3(dot(h.T, g), dot(h.B, g), dot(n, g));
+    const D3 gt = (gl - h.th * dot(h.th, gl)) * (1.0 / h.tlen);
+    return gt * 2.0;
+}
+
 // Hit attributes of the ray (o, d) on the leaf the FP32 traversal found: barycentrics
 // re-solved in FP64 (Cramer's rule on o + t d = v0 + b1 e1 + b2 e2), flat two-sided
 // normal facing the incoming ray, bilinear BRDF maps at the interpolated UV.
@@ -162,6 +216,7 @@ __device__ __forceinline__ Surf surface(const ReqDesc& r, int leaf, D3 o, D3 d) 
 struct ProjNee {
     D3 wp;
     double dist, geom;   // (1/cos^3 alpha) cos theta / d^2
+    double g0;           // 1 / (cos^3 alpha d^2): geom without the cosine
     double pu, pv;
     Bilin pb;
 };
@@ -179,6 +234,7 @@ __device__ __forceinline__ bool projector_nee(const ReqDesc& r, const Surf& s, P
     if (!(cp > 0.0)) return false;
     const double ca = xp.z / sqrt(dot(xp, xp));
     p.geom = cp / (ca * ca * ca * p.dist * p.dist);
+    p.g0 = 1.0 / (ca * ca * ca * p.dist * p.dist);
     p.pb = bilinear(p.pu - 0.5, p.pv - 0.5, r.Wp, r.Hp);
     return true;
 }

@@ -23,6 +23,10 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     ReqDesc r;
     std::string why;
     if (!fill_desc(ctx, r, params, scene, proj_image, &why)) return fail(ctx, DPCS_E_INVALID, why);
+    const bool ext = params->metallic || params->normal_map;
+    if (ext && sample_radiance && !path_records)
+        return fail(ctx, DPCS_E_UNSUPPORTED, "with the metallic or normal map the VJP replays path records: pass the "
+                                             "forward's path_records with sample_radiance, or neither");
     if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
     r.grad_image = grad_image;
     dpcs_status st = DPCS_OK;
@@ -30,13 +34,14 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     const size_t nEp = (size_t)r.Wp * r.Hp, nT = (size_t)r.tw * r.th;
     float* dEp = (float*)scratch(ctx, "vjp.dEp", sizeof(float) * 4 * nEp, &st);
     if (!dEp) return st;
-    float* dtex = (float*)scratch(ctx, "vjp.dtex", sizeof(float) * 5 * nT, &st);
+    const int C = r.dtex_c;   // cotangent channels per texel: 5, or 9 with the metallic / normal maps
+    float* dtex = (float*)scratch(ctx, "vjp.dtex", sizeof(float) * C * nT, &st);
     if (!dtex) return st;
     float* acc = (float*)scratch(ctx, "vjp.acc", sizeof(float) * 32, &st);
     if (!acc) return st;
     Launch l{ctx->stream, ctx->grid_cap};
     launch_zero(l, dEp, 4 * (int64_t)nEp);
-    launch_zero(l, dtex, 5 * (int64_t)nT);
+    launch_zero(l, dtex, C * (int64_t)nT);
     launch_zero(l, acc, 32);
     r.dEp = dEp;
     r.d_tex = dtex;
@@ -50,7 +55,7 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     Queues q{};
     AdjQueues aq{};
     if (!make_queues(ctx, "fwd.queues", ppw * r.spp, q, &st)) return st;
-    if (!make_adj_queues(ctx, "vjp.queues", ppw * r.spp, aq, &st)) return st;
+    if (!make_adj_queues(ctx, "vjp.queues", ppw * r.spp, aq, &st, ext)) return st;
     // Path records: the caller's (whole image, from the forward call that produced
     // sample_radiance), or this call's own per wave when it runs the forward itself.
     // With sample_radiance alone the replay traces again.
@@ -68,7 +73,8 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
         // vertex -- and one E_p record per vertex
         const int64_t k = std::min(r.max_depth, BIN_DEPTHS);
         const int64_t per = (own_rec || path_records) ? k + 1 : 3 * k;
-        make_map_bins(ctx, l, aq.tb, "vjp.tex_bins", r.tw, r.th, 5, 8, ppw * r.spp * per);
+        if (ext) make_map_bins(ctx, l, aq.tb, "vjp.tex9_bins", r.tw, r.th, 9, 12, ppw * r.spp * per);
+        else make_map_bins(ctx, l, aq.tb, "vjp.tex_bins", r.tw, r.th, 5, 8, ppw * r.spp * per);
         make_map_bins(ctx, l, aq.eb, "vjp.ep_bins", r.Wp, r.Hp, 3, 6, ppw * r.spp * k);
     }
     for (int64_t a = 0; a < npix; a += ppw) {
@@ -84,7 +90,7 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
         adjoint_wave(ctx, q, aq, r, (uint32_t)a, b, sample_radiance);
     }
     launch_adj_finish(l, r, grads->d_proj_image, grads->d_albedo, grads->d_roughness, grads->d_specular,
-                      grads->d_scalars, acc);
+                      grads->d_scalars, acc, grads->d_metallic, grads->d_normal_map);
     if (!hip_ok(ctx, hipGetLastError(), "kernel launch")) return DPCS_E_DEVICE;
     ctx->err.clear();
     return DPCS_OK;

@@ -55,7 +55,8 @@ class RenderParams(C.Structure):
                 ("crf_gamma", C.c_float * 3), ("crf_gain", C.c_float), ("white_balance", C.c_float * 3),
                 ("device_scalars", C.c_void_p), ("env_radiance", C.c_float * 3),
                 ("clip_enable", C.c_int32), ("clip_k", C.c_float), ("spp", C.c_int32), ("max_depth", C.c_int32),
-                ("seed", C.c_uint64), ("sample_offset", C.c_uint32)]
+                ("seed", C.c_uint64), ("sample_offset", C.c_uint32), ("metallic", C.c_void_p),
+                ("normal_map", C.c_void_p)]
 
 
 class RenderAux(C.Structure):
@@ -65,7 +66,8 @@ class RenderAux(C.Structure):
 
 class Grads(C.Structure):
     _fields_ = [("d_proj_image", C.c_void_p), ("d_albedo", C.c_void_p), ("d_roughness", C.c_void_p),
-                ("d_specular", C.c_void_p), ("d_scalars", C.c_void_p)]
+                ("d_specular", C.c_void_p), ("d_scalars", C.c_void_p), ("d_metallic", C.c_void_p),
+                ("d_normal_map", C.c_void_p)]
 
 
 NUM_STAGES = 9
@@ -265,8 +267,10 @@ def pinhole(p) -> Pinhole:
     return ph
 
 
-def params_from(w, albedo, roughness=None, specular=None, device_scalars=None, **over) -> RenderParams:
-    """RenderParams from a synth.Workload-like object and device tensors for the maps."""
+def params_from(w, albedo, roughness=None, specular=None, device_scalars=None, metallic=None, normal_map=None,
+                **over) -> RenderParams:
+    """RenderParams from a synth.Workload-like object and device tensors for the maps
+    (metallic and normal_map: optional device tensors of the further principled maps)."""
     g = lambda k: over[k] if k in over else getattr(w, k)
     p = RenderParams()
     p.camera = pinhole(g("camera"))
@@ -288,6 +292,7 @@ def params_from(w, albedo, roughness=None, specular=None, device_scalars=None, *
     p.max_depth = int(g("max_depth"))
     p.seed = int(g("seed"))
     p.sample_offset = int(g("sample_offset"))
+    p.metallic, p.normal_map = _ptr(metallic), _ptr(normal_map)
     return p
 
 
@@ -309,8 +314,9 @@ def dpcs_render_noalloc(ctx: Context, scene: Scene, params: RenderParams, proj_i
 
 def dpcs_render_vjp(ctx: Context, scene: Scene, params: RenderParams, proj_image, grad_image, sample_radiance=None,
                     d_proj_image=None, d_albedo=None, d_roughness=None, d_specular=None, d_scalars=None,
-                    path_records=None):
-    g = Grads(_ptr(d_proj_image), _ptr(d_albedo), _ptr(d_roughness), _ptr(d_specular), _ptr(d_scalars))
+                    path_records=None, d_metallic=None, d_normal_map=None):
+    g = Grads(_ptr(d_proj_image), _ptr(d_albedo), _ptr(d_roughness), _ptr(d_specular), _ptr(d_scalars),
+              _ptr(d_metallic), _ptr(d_normal_map))
     return ctx.check(lib().dpcs_render_vjp(ctx.h, scene.h, C.byref(params), _ptr(proj_image), _ptr(grad_image),
                                            _ptr(sample_radiance), _ptr(path_records), C.byref(g)))
 

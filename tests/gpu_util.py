@@ -38,9 +38,14 @@ class GpuRun:
         self.rough = dev(over.get("roughness", w.roughness), f32)
         self.spec = dev(over.get("specular", w.specular), f32)
         self.proj = dev(over.get("proj_image", w.proj_image), f32)
+        mt = over.get("metallic", getattr(w, "metallic", None))
+        nm = over.get("normal_map", getattr(w, "normal_map", None))
+        self.metal = None if mt is None else dev(mt, f32)
+        self.nmap = None if nm is None else dev(nm, f32)
         self.over = {k: v for k, v in over.items() if k not in ("mesh", "albedo", "roughness", "specular",
-                                                               "proj_image")}
-        self.params = dpcs.params_from(w, self.albedo, self.rough, self.spec, **self.over)
+                                                               "proj_image", "metallic", "normal_map")}
+        self.params = dpcs.params_from(w, self.albedo, self.rough, self.spec, metallic=self.metal,
+                                       normal_map=self.nmap, **self.over)
         if capacity is not None:
             self.c.check(dpcs.lib().dpcs_context_set_capacity(self.c.h, int(capacity)))
 
@@ -112,6 +117,11 @@ def run_vjp(run: GpuRun, G, sample_radiance=None, mode="own"):
     out = dict(Ip=torch.zeros_like(run.proj), albedo=torch.zeros_like(run.albedo),
                roughness=torch.zeros_like(run.rough), specular=torch.zeros_like(run.spec),
                scalars=torch.zeros(dpcs.NUM_SCALARS, device="cuda"))
+    ext = {}
+    if run.metal is not None:
+        out["metallic"] = ext["d_metallic"] = torch.zeros_like(run.metal)
+    if run.nmap is not None:
+        out["normal_map"] = ext["d_normal_map"] = torch.zeros_like(run.nmap)
     g = dev(G, torch.float32)
     rec = None
     if mode in ("records", "retrace") and sample_radiance is None:
@@ -123,7 +133,7 @@ def run_vjp(run: GpuRun, G, sample_radiance=None, mode="own"):
         dpcs.dpcs_render(run.c, run.scene, p, run.proj, img, sample_radiance=sample_radiance, path_records=rec)
     dpcs.dpcs_render_vjp(run.c, run.scene, p, run.proj, g, sample_radiance=sample_radiance, path_records=rec,
                          d_proj_image=out["Ip"], d_albedo=out["albedo"], d_roughness=out["roughness"],
-                         d_specular=out["specular"], d_scalars=out["scalars"])
+                         d_specular=out["specular"], d_scalars=out["scalars"], **ext)
     run.c.synchronize()
     res = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
     s = res.pop("scalars")
