@@ -113,6 +113,16 @@ DPCS_API dpcs_status dpcs_scene_get_info(dpcs_scene s, dpcs_scene_info* out);
 /* Frees the scene after the context's stream has drained; DPCS_E_BUSY while a server
  * still holds requests on it. */
 DPCS_API dpcs_status dpcs_scene_destroy(dpcs_scene s);
+/* Moves the scene's vertices (Sec. 4.4: editing the mesh simulates projection on a moving
+ * surface, and compensation for it, frame by frame).  positions: DEVICE pointer,
+ * num_vertices x 3 float32, same triangles and texture coordinates.  The BVH keeps its
+ * topology: its boxes are refitted bottom-up on the device (binary and 4-wide) and the
+ * leaf records rewritten, asynchronously on the context's stream, with no host copy.
+ * The ray epsilon and the reported bounds stay those of creation; traversal slows as
+ * the shape departs from the one the tree was built for (create a new scene for large
+ * changes).  Non-finite positions are the caller's to avoid.  DPCS_E_BUSY while a
+ * server holds requests on the scene. */
+DPCS_API dpcs_status dpcs_scene_refit(dpcs_context ctx, dpcs_scene s, const float* positions);
 
 /* ----------------------------------------------------------------- render */
 

@@ -9,6 +9,8 @@
 //  4. Bounds bottom-up: a thread per leaf climbs; the second thread to reach a node
 //     (atomic arrival counter) writes the node's two child boxes and continues.
 //  5. Leaf-ordered 48-byte triangle records and UV / emission records.
+#include <climits>
+
 #include "kernels.hpp"
 
 namespace dpcs {
@@ -243,6 +245,53 @@ __global__ void k_leaf_records(const float* __restrict__ V, const int* __restric
     leaf_of_prim[p] = l;
 }
 
+// the leaf records' vertices at new positions (original index bits in v0.w kept)
+__global__ void k_refit_tris(const float* __restrict__ V, const int* __restrict__ F, const uint32_t* __restrict__ order,
+                             int n, float4* __restrict__ tris) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n || order[l] >= (uint32_t)n) return;
+    const int p = (int)order[l];
+    const int a = F[3 * p], b = F[3 * p + 1], c = F[3 * p + 2];
+    tris[3 * l] = make_float4(V[3 * a], V[3 * a + 1], V[3 * a + 2], __int_as_float(p));
+    tris[3 * l + 1] = make_float4(V[3 * b], V[3 * b + 1], V[3 * b + 2], 0.0f);
+    tris[3 * l + 2] = make_float4(V[3 * c], V[3 * c + 1], V[3 * c + 2], 0.0f);
+}
+
+// one thread per 4-wide child slot: the box of the binary node behind it (the union of
+// the two child boxes that node stores) or of its leaf triangle; empty slots keep
+// their inverted box
+__global__ void k_refit_wide(const float4* __restrict__ nodes, const float4* __restrict__ tris,
+                             const int* __restrict__ map4, int nnodes4, int nt, float4* __restrict__ nodes4) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 4 * nnodes4) return;
+    const int w = k >> 2, j = k & 3;
+    const int ref = map4[k];
+    if (ref == INT_MIN) return;
+    float b[6];
+    if (ref >= 0) {
+        if (ref >= nt - 1) return;
+        const float4 n0 = nodes[4 * ref], n1 = nodes[4 * ref + 1], n2 = nodes[4 * ref + 2];
+        const float c0[6] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y}, c1[6] = {n1.z, n1.w, n2.x, n2.y, n2.z, n2.w};
+        for (int q = 0; q < 3; ++q) {
+            b[q] = fminf(c0[q], c1[q]);
+            b[3 + q] = fmaxf(c0[3 + q], c1[3 + q]);
+        }
+    } else {
+        const int l = ~ref;
+        if (l >= nt) return;
+        const float4 a = tris[3 * l], c = tris[3 * l + 1], e = tris[3 * l + 2];
+        const float x[3] = {a.x, c.x, e.x}, y[3] = {a.y, c.y, e.y}, z[3] = {a.z, c.z, e.z};
+        b[0] = fminf(x[0], fminf(x[1], x[2]));
+        b[1] = fminf(y[0], fminf(y[1], y[2]));
+        b[2] = fminf(z[0], fminf(z[1], z[2]));
+        b[3] = fmaxf(x[0], fmaxf(x[1], x[2]));
+        b[4] = fmaxf(y[0], fmaxf(y[1], y[2]));
+        b[5] = fmaxf(z[0], fmaxf(z[1], z[2]));
+    }
+    float* o = reinterpret_cast<float*>(nodes4 + 8 * (size_t)w);
+    for (int a = 0; a < 6; ++a) o[4 * a + j] = b[a];
+}
+
 // ---------------------------------------------------------------- host side
 static inline unsigned grid_of(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -251,6 +300,21 @@ hipError_t build_leaf_records(hipStream_t st, const BvhInputs& in, const uint32_
     out.order = order;
     hipLaunchKernelGGL(k_leaf_records, dim3(grid_of(n, 256)), dim3(256), 0, st, in.V, in.F, in.UV, in.Le, order, n,
                        out.tris, out.tri_uv, out.emission, out.leaf_of_prim);
+    return hipGetLastError();
+}
+
+hipError_t refit_bvh(hipStream_t st, const RefitArgs& a) {
+    const int n = a.nt;
+    if (n == 1) {
+        hipLaunchKernelGGL(k_single_node, dim3(1), dim3(1), 0, st, a.V, a.F, a.nodes);
+    } else {
+        hipLaunchKernelGGL(k_bounds, dim3(grid_of(n, 256)), dim3(256), 0, st, a.V, a.F, a.order, n, a.child,
+                           a.parent_int, a.parent_leaf, a.flags, a.node_box, a.nodes);
+    }
+    hipLaunchKernelGGL(k_refit_tris, dim3(grid_of(n, 256)), dim3(256), 0, st, a.V, a.F, a.order, n, a.tris);
+    if (a.nodes4 && a.nnodes4 > 0)
+        hipLaunchKernelGGL(k_refit_wide, dim3(grid_of(4 * (int64_t)a.nnodes4, 256)), dim3(256), 0, st, a.nodes, a.tris,
+                           a.map4, a.nnodes4, n, a.nodes4);
     return hipGetLastError();
 }
 

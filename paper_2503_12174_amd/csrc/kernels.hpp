@@ -36,6 +36,26 @@ struct BvhOutputs {
 hipError_t build_bvh(hipStream_t st, const BvhInputs& in, BvhOutputs& out);
 // leaf-ordered triangle / UV / emission records for a leaf order built elsewhere
 hipError_t build_leaf_records(hipStream_t st, const BvhInputs& in, const uint32_t* order, BvhOutputs& out);
+// new vertex positions on a fixed topology: the binary node boxes bottom-up (flags: ni
+// zeroed ints, node_box: 6 ni floats of scratch), the leaf records' vertices, and the
+// 4-wide nodes' child boxes from map4 (4 per node: binary node, ~leaf, or INT_MIN empty)
+struct RefitArgs {
+    const float* V;
+    const int* F;
+    const uint32_t* order;
+    const int* child;
+    const int* parent_int;
+    const int* parent_leaf;
+    int* flags;
+    float* node_box;
+    int nt;
+    float4* nodes;
+    float4* tris;
+    float4* nodes4;
+    const int* map4;
+    int nnodes4;
+};
+hipError_t refit_bvh(hipStream_t st, const RefitArgs& a);
 
 // ------------------------------------------------------------------ path queues
 // Structure-of-arrays queues in HBM.  Path state is FP64 position/direction (PathO,

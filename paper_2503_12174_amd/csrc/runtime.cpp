@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -412,7 +413,8 @@ extern "C" dpcs_status dpcs_context_set_capacity(dpcs_context ctx, int64_t paths
 // surface area until it holds four.  Leaves stay single triangles.  stack_bound is the
 // most traversal stack entries any ray can hold: along a root-to-node path, each node
 // pushes at most (its internal children - 1).
-static std::vector<float4> collapse4(const std::vector<float4>& bn, int nt, int& stack_bound, int& depth4) {
+static std::vector<float4> collapse4(const std::vector<float4>& bn, int nt, int& stack_bound, int& depth4,
+                                     std::vector<int>& map4) {
     struct Kid {
         int ref;
         float b[6];   // lo.xyz, hi.xyz
@@ -443,6 +445,7 @@ static std::vector<float4> collapse4(const std::vector<float4>& bn, int nt, int&
     // first in, first out: nodes are numbered level by level, so the top of the tree is
     // the leading block of nodes (what a traversal workgroup stages in LDS)
     std::deque<Work> work{{0, alloc(), 0, 1}};
+    map4.assign(4, INT_MIN);
     stack_bound = 0;
     depth4 = 0;
     while (!work.empty()) {
@@ -473,8 +476,10 @@ static std::vector<float4> collapse4(const std::vector<float4>& bn, int nt, int&
         for (int j = 0; j < 4; ++j) {
             if (j < (int)kids.size()) {
                 for (int a = 0; a < 6; ++a) box[a][j] = kids[j].b[a];
+                map4[4 * (size_t)w.node + j] = kids[j].ref;   // the binary node or ~leaf behind the slot
                 if (kids[j].ref >= 0) {
                     refs[j] = alloc();
+                    map4.resize(out.size() / 2, INT_MIN);
                     work.push_back({kids[j].ref, refs[j], acc, w.depth + 1});
                 } else {
                     refs[j] = kids[j].ref;
@@ -555,8 +560,15 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
     dmalloc((void**)&sc->tri_uv, sizeof(float4) * 2 * nt);
     if (m->emission) dmalloc((void**)&sc->emission, sizeof(float4) * nt);
     dmalloc((void**)&sc->leaf_of_prim, sizeof(int) * nt);
+    dmalloc((void**)&sc->F, sizeof(int) * 3 * nt);
+    dmalloc((void**)&sc->order, sizeof(uint32_t) * nt);
+    dmalloc((void**)&sc->child, sizeof(int) * 2 * ni);
+    dmalloc((void**)&sc->parent_int, sizeof(int) * ni);
+    dmalloc((void**)&sc->parent_leaf, sizeof(int) * nt);
+    sc->nv = nv;
     sc->nnodes = ni;
-    sc->bytes = (int64_t)sizeof(float4) * (4 * ni + 3 * (nt + 1) + 2 * nt + (m->emission ? nt : 0)) + 4 * nt;
+    sc->bytes = (int64_t)sizeof(float4) * (4 * ni + 3 * (nt + 1) + 2 * nt + (m->emission ? nt : 0)) + 4 * nt +
+                4 * (3 * (int64_t)nt + nt + 2 * (int64_t)ni + ni + nt);
     // build temporaries
     void *dV = nullptr, *dF = nullptr, *dUV = nullptr, *dLe = nullptr, *tmp = nullptr;
     dmalloc(&dV, sizeof(float) * 3 * nv);
@@ -585,6 +597,9 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
         (void)hipFree(sc->tri_uv);
         if (sc->emission) (void)hipFree(sc->emission);
         (void)hipFree(sc->leaf_of_prim);
+        for (void* q : {(void*)sc->F, (void*)sc->order, (void*)sc->child, (void*)sc->parent_int, (void*)sc->parent_leaf,
+                        (void*)sc->map4})
+            if (q) (void)hipFree(q);
         delete sc;
     };
     if (!ok) {
@@ -666,6 +681,22 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
             step = "leaf records";
             e = build_leaf_records(st, in, in.vals[0], bo);
         }
+        // topology kept for refits: children from the host build, parents derived here
+        std::vector<int> par_int(ni, -1), par_leaf(nt, -1);
+        for (int k = 0; k < ni && nt > 1; ++k)
+            for (int j = 0; j < 2; ++j) {
+                const int c = child[2 * (size_t)k + j];
+                if (c < 0 && ~c < nt) par_leaf[~c] = k;
+                else if (c >= 0 && c < ni) par_int[c] = k;
+            }
+        if (e == hipSuccess) {
+            step = "topology";
+            e = hipMemcpyAsync(sc->child, child.data(), sizeof(int) * 2 * ni, hipMemcpyHostToDevice, st);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(sc->parent_int, par_int.data(), sizeof(int) * ni, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(sc->parent_leaf, par_leaf.data(), sizeof(int) * nt, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(sc->order, in.vals[0], sizeof(uint32_t) * nt, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(sc->F, dF, sizeof(int) * 3 * nt, hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess) {
             step = "synchronize";
             e = hipStreamSynchronize(st);   // the host vectors are read by the copies above
@@ -682,6 +713,16 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
             (void)hipEventRecord(e0, st);
             e = build_bvh(st, in, bo);
             (void)hipEventRecord(e1, st);
+        }
+        if (e == hipSuccess) {   // topology kept for refits
+            step = "topology";
+            e = hipMemcpyAsync(sc->child, in.child, sizeof(int) * 2 * ni, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(sc->parent_int, in.parent_int, sizeof(int) * ni, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(sc->parent_leaf, in.parent_leaf, sizeof(int) * nt, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(sc->order, bo.order, sizeof(uint32_t) * nt, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(sc->F, dF, sizeof(int) * 3 * nt, hipMemcpyDeviceToDevice, st);
         }
         if (e == hipSuccess) {
             step = "synchronize";
@@ -763,7 +804,8 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
         hipError_t e4 = hipMemcpy(bn.data(), sc->nodes, sizeof(float4) * bn.size(), hipMemcpyDeviceToHost);
         if (e4 == hipSuccess) {
             int bound = 0, depth4 = 0;
-            const std::vector<float4> n4 = collapse4(bn, nt, bound, depth4);
+            std::vector<int> map4;
+            const std::vector<float4> n4 = collapse4(bn, nt, bound, depth4, map4);
             if (bound <= MAX_STACK && sizeof(float4) * n4.size() <= (size_t)UINT32_MAX) {
                 // the dummy leaf's triangle: NaN vertices, which no ray hits
                 const float qn = std::numeric_limits<float>::quiet_NaN();
@@ -776,13 +818,18 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
                 if (e4 == hipSuccess) e4 = hipMalloc((void**)&sc->nodes4, sizeof(float4) * n4.size());
                 if (e4 == hipSuccess)
                     e4 = hipMemcpy(sc->nodes4, n4.data(), sizeof(float4) * n4.size(), hipMemcpyHostToDevice);
+                if (e4 == hipSuccess) e4 = hipMalloc((void**)&sc->map4, sizeof(int) * map4.size());
+                if (e4 == hipSuccess)
+                    e4 = hipMemcpy(sc->map4, map4.data(), sizeof(int) * map4.size(), hipMemcpyHostToDevice);
                 if (e4 == hipSuccess) {
                     sc->nnodes4 = (int)(n4.size() / 8);
-                    sc->bytes += (int64_t)sizeof(float4) * n4.size();
+                    sc->bytes += (int64_t)sizeof(float4) * n4.size() + (int64_t)sizeof(int) * map4.size();
                 } else {
                     (void)hipGetLastError();
                     if (sc->nodes4) (void)hipFree(sc->nodes4);
+                    if (sc->map4) (void)hipFree(sc->map4);
                     sc->nodes4 = nullptr;   // the binary BVH serves
+                    sc->map4 = nullptr;
                 }
             }
         }
@@ -826,7 +873,34 @@ extern "C" dpcs_status dpcs_scene_destroy(dpcs_scene s) {
     (void)hipFree(s->tri_uv);
     if (s->emission) (void)hipFree(s->emission);
     (void)hipFree(s->leaf_of_prim);
+    for (void* q : {(void*)s->F, (void*)s->order, (void*)s->child, (void*)s->parent_int, (void*)s->parent_leaf,
+                    (void*)s->map4})
+        if (q) (void)hipFree(q);
     delete s;
+    return DPCS_OK;
+}
+
+extern "C" dpcs_status dpcs_scene_refit(dpcs_context ctx, dpcs_scene s, const float* positions) {
+    if (!ctx) return DPCS_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (ctx->sticky) return DPCS_E_DEVICE;
+    if (!s || s->ctx != ctx) return fail(ctx, DPCS_E_INVALID, "scene is NULL or from another context");
+    if (!positions) return fail(ctx, DPCS_E_INVALID, "positions is NULL");
+    if (s->refs.load() > 0) return fail(ctx, DPCS_E_BUSY, "scene still used by queued server requests");
+    (void)hipGetLastError();
+    if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
+    dpcs_status st = DPCS_OK;
+    const int ni = s->nnodes;
+    int* flags = (int*)scratch(ctx, "refit.flags", sizeof(int) * ni, &st);
+    if (!flags) return st;
+    float* box = (float*)scratch(ctx, "refit.box", sizeof(float) * 6 * ni, &st);
+    if (!box) return st;
+    Launch l{ctx->stream, ctx->grid_cap};
+    launch_zero(l, (float*)flags, ni);
+    RefitArgs a{positions, s->F, s->order, s->child, s->parent_int, s->parent_leaf, flags, box, s->nt,
+                s->nodes, s->tris, s->nodes4, s->map4, s->nodes4 ? s->nnodes4 : 0};
+    if (!hip_ok(ctx, refit_bvh(ctx->stream, a), "scene refit")) return DPCS_E_DEVICE;
+    ctx->err.clear();
     return DPCS_OK;
 }
 

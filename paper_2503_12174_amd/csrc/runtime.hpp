@@ -49,6 +49,15 @@ struct dpcs_scene_s {
     float4* tri_uv = nullptr;
     float4* emission = nullptr;
     int* leaf_of_prim = nullptr;
+    // topology kept for dpcs_scene_refit: triangles, leaf order, binary children and
+    // parents, and the binary node (>= 0) or leaf (~l) behind every 4-wide child slot
+    int* F = nullptr;
+    uint32_t* order = nullptr;
+    int* child = nullptr;
+    int* parent_int = nullptr;
+    int* parent_leaf = nullptr;
+    int* map4 = nullptr;
+    int nv = 0;
     int nt = 0, nnodes = 0, nnodes4 = 0, depth = 0;
     float tmin = 0.0f;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};

@@ -115,7 +115,7 @@ SYMBOLS = ["dpcs_context_create", "dpcs_context_destroy", "dpcs_last_error", "dp
            "dpcs_context_set_profiling", "dpcs_context_get_profile", "dpcs_server_create",
            "dpcs_server_submit", "dpcs_server_poll", "dpcs_server_stats", "dpcs_server_destroy",
            "dpcs_denoise", "dpcs_denoise_vjp", "dpcs_render_gbuffer", "dpcs_tv_loss", "dpcs_tv_vjp",
-           "dpcs_l1_loss", "dpcs_l1_vjp", "dpcs_render_noalloc"]
+           "dpcs_l1_loss", "dpcs_l1_vjp", "dpcs_render_noalloc", "dpcs_scene_refit"]
 
 _lib = None
 
@@ -137,6 +137,7 @@ def lib():
             "dpcs_scene_create": ([P, C.POINTER(MeshDesc), C.POINTER(P)], S),
             "dpcs_scene_get_info": ([P, C.POINTER(SceneInfo)], S),
             "dpcs_scene_destroy": ([P], S),
+            "dpcs_scene_refit": ([P, P, P], S),
             "dpcs_render": ([P, P, C.POINTER(RenderParams), P, P, C.POINTER(RenderAux)], S),
             "dpcs_render_noalloc": ([P, P, C.POINTER(RenderParams), P, P, C.POINTER(RenderAux)], S),
             "dpcs_render_vjp": ([P, P, C.POINTER(RenderParams), P, P, P, P, C.POINTER(Grads)], S),
@@ -237,6 +238,13 @@ class Scene:
         h = C.c_void_p()
         ctx.check(lib().dpcs_scene_create(ctx.h, C.byref(d), C.byref(h)))
         self.h = h
+
+    def refit(self, positions):
+        """New vertex positions (device tensor, num_vertices x 3 float32) on the same
+        topology: the BVH is refitted on the device."""
+        if positions.dtype != __import__("torch").float32 or not positions.is_contiguous():
+            raise ValueError("positions must be a contiguous float32 device tensor")
+        return self.ctx.check(lib().dpcs_scene_refit(self.ctx.h, self.h, _ptr(positions)))
 
     def info(self) -> SceneInfo:
         i = SceneInfo()

@@ -2,6 +2,8 @@
 
 compensate()  projector compensation, Eq. 13: find I_p whose rendering matches a
               target camera image, by Adam on an L2 loss, I_p clamped to [0, 1]
+compensate_morphing()  the same on a moving surface, frame by frame (Sec. 4.4), the
+              BVH refitted on the device for each frame's vertex positions
 fit()         scene-parameter fit, Eq. 9: BRDF maps and PRF/CRF scalars from image
               pairs, with the paper's constraints on gamma_p, gamma_c, w
               (Sec. 3.2: gamma_p in [2, 3], gamma_c in [1/3, 1], w in (0.2, 2.5));
@@ -44,6 +46,37 @@ def compensate(ctx, scene, cfg, target, albedo, roughness, specular, steps=100, 
         if callback:
             callback(k, losses[-1], ip)
     return ip.detach(), losses
+
+
+def compensate_morphing(ctx, scene, cfg, frames, target, albedo, roughness, specular, steps_per_frame=10,
+                        lr=0.01, init=0.5, base_seed=0):
+    """Projector compensation on a moving surface (Sec. 4.4): for each frame's vertex
+    positions (device tensors on the scene's topology) the scene's BVH is refitted on
+    the device and the projector image, warm-started from the previous frame, takes
+    steps_per_frame Adam steps of Eq. 13 toward the target.  Returns the images and
+    the per-frame losses."""
+    scal = scalars_from(cfg)
+    H, W = cfg.projector.height, cfg.projector.width
+    ip = torch.full((H, W, 3), init, device="cuda", requires_grad=True)
+    images, losses = [], []
+    for f, pos in enumerate(frames):
+        scene.refit(pos)
+        opt = torch.optim.Adam([ip], lr=lr)
+        fl = []
+        for k in range(steps_per_frame):
+            c = copy.copy(cfg)
+            c.seed = base_seed + f * steps_per_frame + k
+            out = render(ctx, scene, c, ip, albedo, roughness, specular, scal)
+            loss = ((out - target) ** 2).mean()
+            opt.zero_grad()
+            loss.backward()
+            opt.step()
+            with torch.no_grad():
+                ip.clamp_(0.0, 1.0)
+            fl.append(float(loss.detach()))
+        images.append(ip.detach().clone())
+        losses.append(fl)
+    return images, losses
 
 
 def project_constraints(scal: torch.Tensor, clamp_gamma_p=True):
