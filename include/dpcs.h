@@ -88,12 +88,16 @@ typedef struct {
     int32_t num_triangles;
     const float* corner_uvs;    /* num_triangles x 3 x 2 texture coordinates */
     const float* emission;      /* NULL, or num_triangles x 3 surface radiance (test scenes) */
-    int32_t bvh_kind;           /* DPCS_BVH_LBVH (0): Morton LBVH built on the device;
-                                   DPCS_BVH_SAH (1): binned-SAH tree built on the host.
-                                   Either is then collapsed to the 4-wide traversal tree. */
+    int32_t bvh_kind;           /* DPCS_BVH_LBVH (0): radix tree over Morton codes;
+                                   DPCS_BVH_SAH (1): top-down binned SAH (32 bins, the
+                                   fewest node visits per ray);
+                                   DPCS_BVH_PLOC (2): locally-ordered clustering over the
+                                   Morton order (between the two).  All are built on the
+                                   device and collapsed there to the 4-wide traversal
+                                   tree; DPCS_E_UNSUPPORTED for a tree deeper than 64. */
 } dpcs_mesh_desc;
 
-enum { DPCS_BVH_LBVH = 0, DPCS_BVH_SAH = 1 };
+enum { DPCS_BVH_LBVH = 0, DPCS_BVH_SAH = 1, DPCS_BVH_PLOC = 2 };
 
 typedef struct {
     int32_t num_triangles;
@@ -101,13 +105,15 @@ typedef struct {
     int32_t max_depth;          /* deepest leaf */
     int32_t wide_nodes;         /* nodes of the 4-wide BVH the renderer traverses (0: binary) */
     int64_t device_bytes;       /* resident bytes (BVH + triangle records + attributes) */
-    double build_ms;            /* GPU time of the BVH build */
+    double build_ms;            /* wall time of the device build (sort, hierarchy, leaf
+                                   records, 4-wide collapse and checks), uploads excluded */
     float bbox_lo[3], bbox_hi[3];
     float tmin;                 /* ray epsilon: 1e-5 x bounding-box diagonal */
 } dpcs_scene_info;
 
-/* Uploads the mesh and builds its BVH on the device (Morton codes, radix sort,
- * binary radix tree, bottom-up bounds).  Synchronises the context's stream. */
+/* Uploads the mesh and builds its BVH on the device (Morton codes, radix sort, then the
+ * binary radix tree with bottom-up bounds or clustering, then the 4-wide collapse); the
+ * tree never leaves the device.  Synchronises the context's stream. */
 DPCS_API dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc* mesh, dpcs_scene* out);
 DPCS_API dpcs_status dpcs_scene_get_info(dpcs_scene s, dpcs_scene_info* out);
 /* Frees the scene after the context's stream has drained; DPCS_E_BUSY while a server

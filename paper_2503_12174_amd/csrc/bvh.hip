@@ -318,8 +318,16 @@ hipError_t refit_bvh(hipStream_t st, const RefitArgs& a) {
     return hipGetLastError();
 }
 
-hipError_t build_bvh(hipStream_t st, const BvhInputs& in, BvhOutputs& out) {
+hipError_t build_bvh(hipStream_t st, const BvhInputs& in, BvhOutputs& out, BvhBuild kind, void* scratch,
+                     uint64_t* host_word) {
     const int n = in.nt;
+    if (kind == BvhBuild::SAH && n > 1) {
+        const uint32_t* order = nullptr;
+        const hipError_t e = build_sah(st, in, scratch, host_word, out.nodes, &order);
+        if (e != hipSuccess) return e;
+        out.order = order;
+        return build_leaf_records(st, in, order, out);
+    }
     const int ntiles = (n + SORT_TILE - 1) / SORT_TILE;
     hipLaunchKernelGGL(k_morton, dim3(grid_of(n, 256)), dim3(256), 0, st, in.V, in.F, n, in.lo[0], in.lo[1],
                        in.lo[2], in.scale[0], in.scale[1], in.scale[2], in.keys[0], in.vals[0]);
@@ -337,6 +345,9 @@ hipError_t build_bvh(hipStream_t st, const BvhInputs& in, BvhOutputs& out) {
     out.order = order;
     if (n == 1) {
         hipLaunchKernelGGL(k_single_node, dim3(1), dim3(1), 0, st, in.V, in.F, out.nodes);
+    } else if (kind == BvhBuild::PLOC) {
+        const hipError_t e = build_ploc(st, in, order, scratch, host_word, out.nodes);
+        if (e != hipSuccess) return e;
     } else {
         hipLaunchKernelGGL(k_hierarchy, dim3(grid_of(n - 1, 256)), dim3(256), 0, st, codes, n, in.child,
                            in.parent_int, in.parent_leaf);

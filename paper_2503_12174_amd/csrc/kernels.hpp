@@ -33,7 +33,43 @@ struct BvhOutputs {
     int* leaf_of_prim;       // nt
     const uint32_t* order;   // leaf -> original triangle (points into keys/vals scratch)
 };
-hipError_t build_bvh(hipStream_t st, const BvhInputs& in, BvhOutputs& out);
+// The binary hierarchy with its bounds, then the leaf records.  LBVH: the radix tree over
+// the Morton-sorted codes; PLOC: clustering over the Morton order (scratch of
+// ploc_scratch_bytes); SAH: top-down binned SAH (scratch of sah_scratch_bytes).  PLOC and
+// SAH read one count per round into host_word[0..1].  child / parent_int / parent_leaf
+// receive the topology (parent_int must hold -1 everywhere beforehand); out.order points
+// into in.vals (LBVH, PLOC) or into the scratch (SAH).  SAH returns hipErrorNotSupported
+// for a tree deeper than 64 levels.
+enum class BvhBuild { LBVH, PLOC, SAH };
+hipError_t build_bvh(hipStream_t st, const BvhInputs& in, BvhOutputs& out, BvhBuild kind = BvhBuild::LBVH,
+                     void* scratch = nullptr, uint64_t* host_word = nullptr);
+size_t ploc_scratch_bytes(int nt);
+hipError_t build_ploc(hipStream_t st, const BvhInputs& in, const uint32_t* order, void* scratch, uint64_t* host_word,
+                      float4* nodes);
+size_t sah_scratch_bytes(int nt);
+hipError_t build_sah(hipStream_t st, const BvhInputs& in, void* scratch, uint64_t* host_word, float4* nodes,
+                     const uint32_t** order_out);
+// the 4-wide BVH of a binary one (nt >= 2) and the tree's checks, in scratch of
+// wide_scratch_bytes(nt): result nodes4 (8 float4 per node) and map4 (4 ints per node)
+// point into the scratch; the host reads one count per level into host_words (>= 2)
+struct WideArgs {
+    const float4* nodes;
+    const int* parent_int;
+    const int* parent_leaf;
+    const uint32_t* order;
+    int nt;
+};
+struct WideResult {
+    float4* nodes4;
+    int* map4;
+    int nnodes4, depth4;   // 4-wide nodes and levels
+    int stack_bound;       // most stack entries a traversal holds
+    int depth;             // binary depth (internal nodes on the longest root-to-leaf path)
+    bool malformed;        // a leaf reached other than once, a parent chain off the root, or
+                           // a leaf order that is not a permutation
+};
+size_t wide_scratch_bytes(int nt);
+hipError_t build_wide(hipStream_t st, const WideArgs& a, void* scratch, uint64_t* host_words, WideResult& res);
 // leaf-ordered triangle / UV / emission records for a leaf order built elsewhere
 hipError_t build_leaf_records(hipStream_t st, const BvhInputs& in, const uint32_t* order, BvhOutputs& out);
 // new vertex positions on a fixed topology: the binary node boxes bottom-up (flags: ni

@@ -9,7 +9,6 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
-#include <deque>
 #include <limits>
 #include <mutex>
 #include <string>
@@ -408,98 +407,6 @@ extern "C" dpcs_status dpcs_context_set_capacity(dpcs_context ctx, int64_t paths
 }
 
 // ====================================================================== scene
-// 4-wide BVH from the binary one (host, after the device build): each node starts from
-// a binary node's two children and keeps opening the internal child with the largest
-// surface area until it holds four.  Leaves stay single triangles.  stack_bound is the
-// most traversal stack entries any ray can hold: along a root-to-node path, each node
-// pushes at most (its internal children - 1).
-static std::vector<float4> collapse4(const std::vector<float4>& bn, int nt, int& stack_bound, int& depth4,
-                                     std::vector<int>& map4) {
-    struct Kid {
-        int ref;
-        float b[6];   // lo.xyz, hi.xyz
-    };
-    auto kid = [&](int node, int k) {
-        const float4* n = &bn[4 * (size_t)node];
-        const float v[12] = {n[0].x, n[0].y, n[0].z, n[0].w, n[1].x, n[1].y, n[1].z, n[1].w,
-                             n[2].x, n[2].y, n[2].z, n[2].w};
-        Kid c;
-        for (int j = 0; j < 6; ++j) c.b[j] = v[6 * k + j];
-        float r;
-        std::memcpy(&r, k == 0 ? &n[3].x : &n[3].y, 4);
-        std::memcpy(&c.ref, &r, 4);
-        return c;
-    };
-    auto area = [](const Kid& c) {
-        const double dx = c.b[3] - c.b[0], dy = c.b[4] - c.b[1], dz = c.b[5] - c.b[2];
-        return dx * dy + dy * dz + dz * dx;
-    };
-    std::vector<float4> out;
-    auto alloc = [&]() {
-        out.resize(out.size() + 8, make_float4(0.f, 0.f, 0.f, 0.f));
-        return (int)(out.size() / 8 - 1);
-    };
-    struct Work {
-        int bin, node, acc, depth;
-    };
-    // first in, first out: nodes are numbered level by level, so the top of the tree is
-    // the leading block of nodes (what a traversal workgroup stages in LDS)
-    std::deque<Work> work{{0, alloc(), 0, 1}};
-    map4.assign(4, INT_MIN);
-    stack_bound = 0;
-    depth4 = 0;
-    while (!work.empty()) {
-        const Work w = work.front();
-        work.pop_front();
-        std::vector<Kid> kids{kid(w.bin, 0), kid(w.bin, 1)};
-        while (kids.size() < 4) {
-            int best = -1;
-            double ba = -1.0;
-            for (size_t j = 0; j < kids.size(); ++j)
-                if (kids[j].ref >= 0 && area(kids[j]) > ba) {
-                    ba = area(kids[j]);
-                    best = (int)j;
-                }
-            if (best < 0) break;
-            const int c = kids[best].ref;
-            kids.erase(kids.begin() + best);
-            kids.push_back(kid(c, 0));
-            kids.push_back(kid(c, 1));
-        }
-        int internal = 0;
-        for (const Kid& k : kids) internal += k.ref >= 0;
-        const int acc = w.acc + std::max(internal - 1, 0);
-        stack_bound = std::max(stack_bound, acc);
-        depth4 = std::max(depth4, w.depth);
-        int refs[4];
-        float box[6][4];
-        for (int j = 0; j < 4; ++j) {
-            if (j < (int)kids.size()) {
-                for (int a = 0; a < 6; ++a) box[a][j] = kids[j].b[a];
-                map4[4 * (size_t)w.node + j] = kids[j].ref;   // the binary node or ~leaf behind the slot
-                if (kids[j].ref >= 0) {
-                    refs[j] = alloc();
-                    map4.resize(out.size() / 2, INT_MIN);
-                    work.push_back({kids[j].ref, refs[j], acc, w.depth + 1});
-                } else {
-                    refs[j] = kids[j].ref;
-                }
-            } else {   // empty slot: inverted box far away (never entered), dummy leaf nt
-                for (int a = 0; a < 3; ++a) {
-                    box[a][j] = 1e30f;
-                    box[a + 3][j] = -1e30f;
-                }
-                refs[j] = ~nt;
-            }
-        }
-        float4* o = &out[8 * (size_t)w.node];
-        for (int a = 0; a < 6; ++a) o[a] = make_float4(box[a][0], box[a][1], box[a][2], box[a][3]);
-        float rf[4];
-        std::memcpy(rf, refs, 16);
-        o[6] = make_float4(rf[0], rf[1], rf[2], rf[3]);
-    }
-    return out;
-}
 
 extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc* m, dpcs_scene* out) {
     if (!ctx || !m || !out) return DPCS_E_INVALID;
@@ -510,8 +417,8 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
     if (!m->positions || !m->triangles || !m->corner_uvs || m->num_vertices <= 0 || m->num_triangles <= 0)
         return fail(ctx, DPCS_E_INVALID, "mesh needs positions, triangles, corner_uvs and positive counts");
     if (m->num_triangles > (1 << 29)) return fail(ctx, DPCS_E_UNSUPPORTED, "too many triangles");
-    if (m->bvh_kind != DPCS_BVH_LBVH && m->bvh_kind != DPCS_BVH_SAH)
-        return fail(ctx, DPCS_E_INVALID, "bvh_kind must be DPCS_BVH_LBVH or DPCS_BVH_SAH");
+    if (m->bvh_kind != DPCS_BVH_LBVH && m->bvh_kind != DPCS_BVH_SAH && m->bvh_kind != DPCS_BVH_PLOC)
+        return fail(ctx, DPCS_E_INVALID, "bvh_kind must be DPCS_BVH_LBVH, DPCS_BVH_SAH or DPCS_BVH_PLOC");
     const int nt = m->num_triangles, nv = m->num_vertices;
     for (int64_t i = 0; i < 3 * (int64_t)nt; ++i)
         if (m->triangles[i] < 0 || m->triangles[i] >= nv)
@@ -569,26 +476,35 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
     sc->nnodes = ni;
     sc->bytes = (int64_t)sizeof(float4) * (4 * ni + 3 * (nt + 1) + 2 * nt + (m->emission ? nt : 0)) + 4 * nt +
                 4 * (3 * (int64_t)nt + nt + 2 * (int64_t)ni + ni + nt);
-    // build temporaries
-    void *dV = nullptr, *dF = nullptr, *dUV = nullptr, *dLe = nullptr, *tmp = nullptr;
+    // build temporaries: the uploaded vertices, uvs and emission, the sort and bounds
+    // buffers carved from one allocation (each part rounded up to 256 bytes), and the
+    // clustering / collapse scratch (used one after the other)
+    const BvhBuild kind = m->bvh_kind == DPCS_BVH_SAH    ? BvhBuild::SAH
+                          : m->bvh_kind == DPCS_BVH_PLOC ? BvhBuild::PLOC
+                                                         : BvhBuild::LBVH;
+    void *dV = nullptr, *dUV = nullptr, *dLe = nullptr, *tmp = nullptr, *bscr = nullptr;
     dmalloc(&dV, sizeof(float) * 3 * nv);
-    dmalloc(&dF, sizeof(int) * 3 * nt);
     dmalloc(&dUV, sizeof(float) * 6 * nt);
     if (m->emission) dmalloc(&dLe, sizeof(float) * 3 * nt);
-    // build temporaries are carved from one buffer, each part rounded up to 256 bytes
     auto r256 = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t tmp_parts[] = {4 * (size_t)nt, 4 * (size_t)nt, 4 * (size_t)nt, 4 * (size_t)nt,
-                                4 * 256 * (size_t)ntiles, 8 * (size_t)ni, 4 * (size_t)ni, 4 * (size_t)nt,
-                                4 * (size_t)ni, 24 * (size_t)ni};
+                                4 * 256 * (size_t)ntiles, 4 * (size_t)ni, 24 * (size_t)ni};
     size_t tmp_bytes = 0;
     for (size_t b : tmp_parts) tmp_bytes += r256(b);
     dmalloc(&tmp, tmp_bytes);
+    if (nt > 1) {
+        const size_t hier = kind == BvhBuild::SAH    ? sah_scratch_bytes(nt)
+                            : kind == BvhBuild::PLOC ? ploc_scratch_bytes(nt)
+                                                     : 0;
+        dmalloc(&bscr, std::max(hier, wide_scratch_bytes(nt)));
+    }
     auto cleanup_tmp = [&]() {
+        (void)hipStreamSynchronize(ctx->stream);   // no build kernel or copy still reads them
         (void)hipFree(dV);
-        (void)hipFree(dF);
         (void)hipFree(dUV);
         if (dLe) (void)hipFree(dLe);
         (void)hipFree(tmp);
+        if (bscr) (void)hipFree(bscr);
     };
     auto destroy_scene = [&]() {
         (void)hipFree(sc->nodes);
@@ -621,13 +537,13 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
     in.vals[0] = (uint32_t*)take();
     in.vals[1] = (uint32_t*)take();
     in.hist = (uint32_t*)take();
-    in.child = (int*)take();
-    in.parent_int = (int*)take();
-    in.parent_leaf = (int*)take();
     in.flags = (int*)take();
     in.node_box = (float*)take();
+    in.child = sc->child;
+    in.parent_int = sc->parent_int;
+    in.parent_leaf = sc->parent_leaf;
     in.V = (const float*)dV;
-    in.F = (const int*)dF;
+    in.F = sc->F;
     in.UV = (const float*)dUV;
     in.Le = (const float*)dLe;
     in.nt = nt;
@@ -642,203 +558,91 @@ extern "C" dpcs_status dpcs_scene_create(dpcs_context ctx, const dpcs_mesh_desc*
     bo.emission = sc->emission;
     bo.leaf_of_prim = sc->leaf_of_prim;
     hipStream_t st = ctx->stream;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        (void)hipGetLastError();
-        if (e0) (void)hipEventDestroy(e0);
-        cleanup_tmp();
-        destroy_scene();
-        return fail(ctx, DPCS_E_DEVICE, "scene build: hipEventCreate failed");
-    }
-    // host SAH build: the tree and leaf order come from the host, the device only
-    // writes the leaf records
-    const bool sah = m->bvh_kind == DPCS_BVH_SAH && nt > 1;
-    std::vector<float4> sah_nodes;
-    std::vector<int> child(2 * (size_t)ni);
-    std::vector<uint32_t> order(nt);
-    double sah_ms = 0.0;
-    if (sah) {
-        const auto t0 = std::chrono::steady_clock::now();
-        sah_build(m->positions, m->triangles, nt, sah_nodes, child, order);
-        sah_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    }
+    // the whole build runs on the device: Morton sort, the hierarchy (radix tree, or PLOC
+    // clustering for the SAH-quality tree), leaf records, the 4-wide collapse and the
+    // tree's checks; the host reads back counts, never the tree
+    uint64_t host_words[2] = {0, 0};
     const char* step = "upload";
     hipError_t e = hipMemcpyAsync(dV, m->positions, sizeof(float) * 3 * nv, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(dF, m->triangles, sizeof(int) * 3 * nt, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(sc->F, m->triangles, sizeof(int) * 3 * nt, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dUV, m->corner_uvs, sizeof(float) * 6 * nt, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && m->emission)
         e = hipMemcpyAsync(dLe, m->emission, sizeof(float) * 3 * nt, hipMemcpyHostToDevice, st);
     Launch l{st, ctx->grid_cap};
-    if (sah) {
-        if (e == hipSuccess) {
-            step = "upload tree";
-            e = hipMemcpyAsync(sc->nodes, sah_nodes.data(), sizeof(float4) * sah_nodes.size(), hipMemcpyHostToDevice,
-                               st);
-        }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(in.vals[0], order.data(), sizeof(uint32_t) * nt, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) {
-            step = "leaf records";
-            e = build_leaf_records(st, in, in.vals[0], bo);
-        }
-        // topology kept for refits: children from the host build, parents derived here
-        std::vector<int> par_int(ni, -1), par_leaf(nt, -1);
-        for (int k = 0; k < ni && nt > 1; ++k)
-            for (int j = 0; j < 2; ++j) {
-                const int c = child[2 * (size_t)k + j];
-                if (c < 0 && ~c < nt) par_leaf[~c] = k;
-                else if (c >= 0 && c < ni) par_int[c] = k;
-            }
-        if (e == hipSuccess) {
-            step = "topology";
-            e = hipMemcpyAsync(sc->child, child.data(), sizeof(int) * 2 * ni, hipMemcpyHostToDevice, st);
-        }
-        if (e == hipSuccess) e = hipMemcpyAsync(sc->parent_int, par_int.data(), sizeof(int) * ni, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(sc->parent_leaf, par_leaf.data(), sizeof(int) * nt, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(sc->order, in.vals[0], sizeof(uint32_t) * nt, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(sc->F, dF, sizeof(int) * 3 * nt, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) {
-            step = "synchronize";
-            e = hipStreamSynchronize(st);   // the host vectors are read by the copies above
-        }
-    } else {
-        if (e == hipSuccess) {
-            step = "init";
-            launch_zero(l, (float*)in.flags, ni);
-            e = hipMemsetAsync(in.parent_int, 0xff, sizeof(int) * ni, st);   // -1: no parent (root)
-            if (e == hipSuccess) e = hipGetLastError();
-        }
-        if (e == hipSuccess) {
-            step = "build kernels";
-            (void)hipEventRecord(e0, st);
-            e = build_bvh(st, in, bo);
-            (void)hipEventRecord(e1, st);
-        }
-        if (e == hipSuccess) {   // topology kept for refits
-            step = "topology";
-            e = hipMemcpyAsync(sc->child, in.child, sizeof(int) * 2 * ni, hipMemcpyDeviceToDevice, st);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(sc->parent_int, in.parent_int, sizeof(int) * ni, hipMemcpyDeviceToDevice, st);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(sc->parent_leaf, in.parent_leaf, sizeof(int) * nt, hipMemcpyDeviceToDevice, st);
-            if (e == hipSuccess) e = hipMemcpyAsync(sc->order, bo.order, sizeof(uint32_t) * nt, hipMemcpyDeviceToDevice, st);
-            if (e == hipSuccess) e = hipMemcpyAsync(sc->F, dF, sizeof(int) * 3 * nt, hipMemcpyDeviceToDevice, st);
-        }
-        if (e == hipSuccess) {
-            step = "synchronize";
-            e = hipStreamSynchronize(st);
-        }
-        // the tree back on the host for validation, depth and the 4-wide collapse
-        if (e == hipSuccess && nt > 1)
-            e = hipMemcpy(child.data(), in.child, sizeof(int) * 2 * ni, hipMemcpyDeviceToHost);
-        if (e == hipSuccess) e = hipMemcpy(order.data(), bo.order, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) {
+        step = "init";
+        launch_zero(l, (float*)in.flags, ni);
+        e = hipMemsetAsync(sc->parent_int, 0xff, sizeof(int) * ni, st);   // -1: no parent (root)
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);   // the clock starts after the uploads
     }
-    float ms = (float)sah_ms;
-    if (e == hipSuccess && !sah) (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    cleanup_tmp();
+    const auto t0 = std::chrono::steady_clock::now();
+    if (e == hipSuccess) {
+        step = "build kernels";
+        e = build_bvh(st, in, bo, kind, bscr, host_words);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(sc->order, bo.order, sizeof(uint32_t) * nt, hipMemcpyDeviceToDevice, st);
+    WideResult wr{};
+    if (e == hipSuccess && nt > 1) {
+        step = "4-wide collapse";
+        // (the SAH build's leaf order lives in the scratch the collapse reuses: read the copy)
+        e = build_wide(st, WideArgs{sc->nodes, sc->parent_int, sc->parent_leaf, sc->order, nt}, bscr, host_words, wr);
+    }
+    if (e == hipSuccess) {
+        step = "synchronize";
+        e = hipStreamSynchronize(st);
+    }
+    sc->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (e == hipErrorNotSupported) {   // the SAH build stops at a tree deeper than 64 levels
+        (void)hipGetLastError();
+        cleanup_tmp();
+        destroy_scene();
+        return fail(ctx, DPCS_E_UNSUPPORTED, "BVH deeper than 64 levels");
+    }
     if (e != hipSuccess) {
+        cleanup_tmp();
         hip_ok(ctx, e, (std::string("scene build (") + step + ")").c_str());
         destroy_scene();
         return DPCS_E_DEVICE;
     }
-    // validate the tree before any traversal runs on it: the leaf order is a permutation,
-    // every internal node and every leaf is reached exactly once from the root
-    {
-        std::vector<char> seen(nt, 0);
-        bool perm = true;
-        for (int k = 0; k < nt && perm; ++k) {
-            if (order[k] >= (uint32_t)nt || seen[order[k]]) perm = false;
-            else seen[order[k]] = 1;
-        }
-        if (!perm) {
-            destroy_scene();
-            return fail(ctx, DPCS_E_DEVICE, "BVH build: sorted order is not a permutation");
-        }
+    if (wr.malformed) {
+        cleanup_tmp();
+        destroy_scene();
+        return fail(ctx, DPCS_E_DEVICE, "BVH build produced an invalid tree");
     }
-    int maxd = 1;
-    if (nt > 1) {
-        std::vector<char> seen_node(ni, 0), seen_leaf(nt, 0);
-        std::vector<std::pair<int, int>> stk{{0, 0}};
-        seen_node[0] = 1;
-        bool valid = true;
-        int64_t steps = 0;
-        while (!stk.empty() && valid) {
-            auto [nd, dd] = stk.back();
-            stk.pop_back();
-            if (++steps > 2 * (int64_t)nt) valid = false;
-            for (int k = 0; k < 2 && valid; ++k) {
-                const int c = child[2 * nd + k];
-                if (c < 0) {
-                    const int lf = ~c;
-                    if (lf >= nt || seen_leaf[lf]) valid = false;
-                    else seen_leaf[lf] = 1;
-                    maxd = std::max(maxd, dd + 1);
-                } else {
-                    if (c >= ni || seen_node[c]) valid = false;
-                    else {
-                        seen_node[c] = 1;
-                        stk.push_back({c, dd + 1});
-                    }
-                }
-            }
-        }
-        for (int k = 0; k < ni && valid; ++k) valid = seen_node[k];
-        for (int k = 0; k < nt && valid; ++k) valid = seen_leaf[k];
-        if (!valid) {
-            destroy_scene();
-            return fail(ctx, DPCS_E_DEVICE, "BVH build produced an invalid tree");
-        }
-    }
-    sc->depth = maxd;
-    sc->build_ms = ms;
-    if (maxd > 64) {
+    sc->depth = nt > 1 ? wr.depth : 1;
+    if (sc->depth > 64) {
+        cleanup_tmp();
         destroy_scene();
         return fail(ctx, DPCS_E_UNSUPPORTED, "BVH deeper than 64 levels");
     }
-    // 4-wide BVH for the traversal kernels, when its worst-case stack fits and its
-    // byte size fits the 32-bit node offsets the traversal loads with
-    if (nt > 1) {
-        std::vector<float4> bn(4 * (size_t)ni);
-        hipError_t e4 = hipMemcpy(bn.data(), sc->nodes, sizeof(float4) * bn.size(), hipMemcpyDeviceToHost);
-        if (e4 == hipSuccess) {
-            int bound = 0, depth4 = 0;
-            std::vector<int> map4;
-            const std::vector<float4> n4 = collapse4(bn, nt, bound, depth4, map4);
-            if (bound <= MAX_STACK && sizeof(float4) * n4.size() <= (size_t)UINT32_MAX) {
-                // the dummy leaf's triangle: NaN vertices, which no ray hits
-                const float qn = std::numeric_limits<float>::quiet_NaN();
-                int none = -1;
-                float none_f;
-                std::memcpy(&none_f, &none, 4);
-                const float4 dummy[3] = {make_float4(qn, qn, qn, none_f), make_float4(qn, qn, qn, 0.f),
-                                         make_float4(qn, qn, qn, 0.f)};
-                e4 = hipMemcpy(sc->tris + 3 * (size_t)nt, dummy, sizeof(dummy), hipMemcpyHostToDevice);
-                if (e4 == hipSuccess) e4 = hipMalloc((void**)&sc->nodes4, sizeof(float4) * n4.size());
-                if (e4 == hipSuccess)
-                    e4 = hipMemcpy(sc->nodes4, n4.data(), sizeof(float4) * n4.size(), hipMemcpyHostToDevice);
-                if (e4 == hipSuccess) e4 = hipMalloc((void**)&sc->map4, sizeof(int) * map4.size());
-                if (e4 == hipSuccess)
-                    e4 = hipMemcpy(sc->map4, map4.data(), sizeof(int) * map4.size(), hipMemcpyHostToDevice);
-                if (e4 == hipSuccess) {
-                    sc->nnodes4 = (int)(n4.size() / 8);
-                    sc->bytes += (int64_t)sizeof(float4) * n4.size() + (int64_t)sizeof(int) * map4.size();
-                } else {
-                    (void)hipGetLastError();
-                    if (sc->nodes4) (void)hipFree(sc->nodes4);
-                    if (sc->map4) (void)hipFree(sc->map4);
-                    sc->nodes4 = nullptr;   // the binary BVH serves
-                    sc->map4 = nullptr;
-                }
-            }
-        }
+    // the 4-wide BVH for the traversal kernels, when its worst-case stack fits and its byte
+    // size fits the 32-bit node offsets the traversal loads with; else the binary BVH serves
+    if (nt > 1 && wr.stack_bound <= MAX_STACK && sizeof(float4) * 8 * (size_t)wr.nnodes4 <= (size_t)UINT32_MAX) {
+        // the dummy leaf's triangle: NaN vertices, which no ray hits
+        const float qn = std::numeric_limits<float>::quiet_NaN();
+        int none = -1;
+        float none_f;
+        std::memcpy(&none_f, &none, 4);
+        const float4 dummy[3] = {make_float4(qn, qn, qn, none_f), make_float4(qn, qn, qn, 0.f),
+                                 make_float4(qn, qn, qn, 0.f)};
+        const size_t b4 = sizeof(float4) * 8 * (size_t)wr.nnodes4, bm = sizeof(int) * 4 * (size_t)wr.nnodes4;
+        hipError_t e4 = hipMemcpy(sc->tris + 3 * (size_t)nt, dummy, sizeof(dummy), hipMemcpyHostToDevice);
+        if (e4 == hipSuccess) e4 = hipMalloc((void**)&sc->nodes4, b4);
+        if (e4 == hipSuccess) e4 = hipMalloc((void**)&sc->map4, bm);
+        if (e4 == hipSuccess) e4 = hipMemcpyAsync(sc->nodes4, wr.nodes4, b4, hipMemcpyDeviceToDevice, st);
+        if (e4 == hipSuccess) e4 = hipMemcpyAsync(sc->map4, wr.map4, bm, hipMemcpyDeviceToDevice, st);
+        if (e4 == hipSuccess) e4 = hipStreamSynchronize(st);
         if (e4 != hipSuccess) {
+            cleanup_tmp();
             hip_ok(ctx, e4, "scene build (4-wide BVH)");
             destroy_scene();
             return DPCS_E_DEVICE;
         }
+        sc->nnodes4 = wr.nnodes4;
+        sc->bytes += (int64_t)(b4 + bm);
     }
+    cleanup_tmp();
     *out = sc;
     return DPCS_OK;
 }

@@ -79,11 +79,6 @@ void* scratch(dpcs_context ctx, const char* name, size_t bytes, dpcs_status* st)
 bool fill_desc(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, dpcs_scene sc, const float* proj_image,
                std::string* why, bool need_proj = true);
 
-// binary BVH by binned SAH on the host (bvh_sah.cpp): nodes in the device layout,
-// child references and the leaf order (leaf l is triangle order[l]); nt >= 2
-void sah_build(const float* V, const int* F, int nt, std::vector<float4>& nodes, std::vector<int>& child,
-               std::vector<uint32_t>& order);
-
 // profiling hooks around one stage launch (no-ops when profiling is off)
 int prof_begin(dpcs_context ctx, int stage);
 void prof_end(dpcs_context ctx, int rec, const uint32_t* dev_count, int64_t host_count);

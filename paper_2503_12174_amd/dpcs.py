@@ -33,7 +33,7 @@ class MeshDesc(C.Structure):
                 ("bvh_kind", C.c_int32)]
 
 
-BVH_LBVH, BVH_SAH = 0, 1
+BVH_LBVH, BVH_SAH, BVH_PLOC = 0, 1, 2
 
 
 class SceneInfo(C.Structure):
@@ -224,7 +224,7 @@ class Context:
 
 class Scene:
     """Resident mesh + BVH (dpcs_scene) built from a synth.Mesh-like object;
-    bvh = "lbvh" (Morton build on the device) or "sah" (binned SAH on the host)."""
+    bvh = "lbvh" (Morton radix tree), "sah" (binned SAH) or "ploc" (clustering); all built on the device."""
 
     def __init__(self, ctx: Context, mesh, bvh: str = "lbvh"):
         self.ctx = ctx
@@ -232,7 +232,7 @@ class Scene:
         F = np.ascontiguousarray(mesh.triangles, np.int32)
         UV = np.ascontiguousarray(mesh.corner_uvs, np.float32)
         E = None if mesh.emission is None else np.ascontiguousarray(mesh.emission, np.float32)
-        kind = {"lbvh": BVH_LBVH, "sah": BVH_SAH}[bvh]
+        kind = {"lbvh": BVH_LBVH, "sah": BVH_SAH, "ploc": BVH_PLOC}[bvh]
         d = MeshDesc(V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], UV.ctypes.data,
                      None if E is None else E.ctypes.data, kind)
         h = C.c_void_p()

@@ -58,11 +58,11 @@ MESHES = {
 }
 
 
-@pytest.mark.parametrize("bvh", ["lbvh", "sah"])
+@pytest.mark.parametrize("bvh", ["lbvh", "sah", "ploc"])
 @pytest.mark.parametrize("name", list(MESHES))
 def test_bvh_traversal_equals_brute_force(name, bvh):
     """Closest hit through the BVH == brute force over all triangles, same FP32 arithmetic,
-    for the device Morton build and the host SAH build."""
+    for every device build (Morton radix tree, binned SAH, clustering)."""
     import torch
     from paper_2503_12174_amd import dpcs
     mesh = MESHES[name]()
@@ -103,6 +103,60 @@ def test_bvh_traversal_equals_brute_force(name, bvh):
     # FP32 t carries ~1 ulp of the ray origin's magnitude: relative and absolute parts
     diag = float(np.linalg.norm(mesh.vertices.max(0) - mesh.vertices.min(0)))
     np.testing.assert_allclose(outs[1][1][hit], t_o[hit], rtol=1e-5, atol=1e-6 * diag)
+
+
+def _coincident_mesh(nested: bool):
+    """A displaced corner plus 2100 triangles sharing one centroid -- more than a build
+    chunk holds: copies of one triangle, or that triangle scaled about its centroid from
+    0.2 to 1.8 (nested boxes)."""
+    base = synth.folded_corner(12, 1, 2)
+    V = base.vertices.astype(np.float64)
+    t0 = V[base.triangles[5]]
+    c = t0.mean(0)
+    parts_v, parts_f = [V], [base.triangles]
+    nv = len(V)
+    for k in range(2100):
+        s = 0.2 + 1.6 * k / 2100 if nested else 1.0
+        parts_v.append(c + (t0 - c) * s)
+        parts_f.append(np.arange(3, dtype=np.int32)[None] + nv)
+        nv += 3
+    tris = np.concatenate(parts_f).astype(np.int32)
+    uvs = np.concatenate([base.corner_uvs, np.tile(base.corner_uvs[5:6], (2100, 1, 1))])
+    return synth.Mesh(np.concatenate(parts_v).astype(np.float32), tris, uvs.astype(np.float32))
+
+
+@pytest.mark.parametrize("bvh", ["lbvh", "sah", "ploc"])
+@pytest.mark.parametrize("nested", [False, True], ids=["copies", "nested"])
+def test_bvh_with_coincident_centroids(nested, bvh):
+    """Builds over a shared centroid (the binned SAH splits such a range at its middle, on
+    the multi-workgroup path too) answer every query exactly as brute force.  Clustering
+    merges nested boxes one at a time, a chain deeper than the traversal allows: that
+    build is refused, not truncated."""
+    import torch
+    from paper_2503_12174_amd import dpcs
+    mesh = _coincident_mesh(nested)
+    if nested and bvh == "ploc":
+        with pytest.raises(dpcs.DpcsError, match="deeper than 64"):
+            dpcs.Scene(ctx(), mesh, bvh=bvh)
+        return
+    sc = dpcs.Scene(ctx(), mesh, bvh=bvh)
+    info = sc.info()
+    assert info.wide_nodes > 0 and info.max_depth <= 64
+    rays = _rays_for(mesh, 20000, np.random.default_rng(3))
+    r = dev(rays)
+    res = {}
+    for mode in (0, 1, 2, 3):
+        prim = torch.zeros(len(rays), dtype=torch.int32, device="cuda")
+        t = torch.zeros(len(rays), dtype=torch.float32, device="cuda")
+        b1, b2 = torch.zeros_like(t), torch.zeros_like(t)
+        dpcs.dpcs_debug_intersect(ctx(), sc, r, mode, prim, t, b1, b2)
+        ctx().synchronize()
+        res[mode] = [x.cpu().numpy() for x in (prim, t, b1, b2)]
+    for mode in (1, 2):
+        for a, b in zip(res[mode], res[0]):
+            np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(res[3][0] >= 0, res[0][0] >= 0)
+    assert (res[0][0] >= 0).mean() > 0.3
 
 
 def test_forward_parity_quad_cube_full_image():
@@ -183,7 +237,7 @@ def test_single_triangle_scene_and_direct_only():
     compare_forward(g, ref, min_clean=0.9)
 
 
-@pytest.mark.parametrize("bvh", ["lbvh", "sah"])
+@pytest.mark.parametrize("bvh", ["lbvh", "sah", "ploc"])
 def test_forward_corner_50k_sampled_pixels(bvh):
     """Full paper-scale render (50k triangles, 256^2, 64 spp, depth 4) on the GPU with
     either BVH build, checked on 48 random pixels the oracle computes one by one."""

@@ -39,7 +39,7 @@ def _rays(V, n, rng):
     return rays
 
 
-@pytest.mark.parametrize("bvh", ["lbvh", "sah"])
+@pytest.mark.parametrize("bvh", ["lbvh", "sah", "ploc"])
 def test_refit_queries_equal_brute_force(bvh):
     import torch
     from paper_2503_12174_amd import dpcs
