@@ -313,12 +313,10 @@ __device__ __forceinline__ float box4_enter(const Box4Ray& r, float nx, float ny
     return tn <= tf ? tn : __builtin_nanf("");
 }
 
-// Same query on the 4-wide BVH: per node, four box tests; leaf children are tested at
-// once, internal children still in range are visited nearest first (the others pushed,
-// farthest first).  The host only builds a BVH4 whose worst-case stack fits MAX_STACK.
-// The top of the 4-wide tree in LDS: the host numbers nodes breadth first, so nodes
-// [0, n) are its top levels; a workgroup copies them once and every ray that passes
-// them reads LDS instead of L2.  bytes = 128 n (0: nothing staged).
+// The top of the 4-wide tree in LDS: the collapse numbers nodes breadth first, so nodes
+// [0, n) are its top levels; a workgroup copies them once and every ray that passes them
+// reads LDS instead of L2.  bytes = 128 n (0: nothing staged).  (The scene only keeps a
+// 4-wide tree whose worst-case stack fits MAX_STACK.)
 struct TopNodes {
     const float4* lds;
     uint32_t bytes;
@@ -333,150 +331,178 @@ __device__ __forceinline__ TopNodes stage_top(float4* lds, const float4* __restr
     return TopNodes{lds, 128u * (uint32_t)n};
 }
 
+// One 4-wide query's state: the ray constants, the best hit so far, the stack depth and
+// the next node (-1: the query has ended).
+struct Trav4 {
+    Box4Ray br;
+    WtRay wr;
+    float tmin, best_t;
+    int skip, best_leaf, sp, node;
+};
+
+__device__ __forceinline__ void trav4_start(Trav4& s, V3 o, V3 d, float tmin, float tmax, int skip) {
+    s.br = box4_setup(o, d);
+    s.wr = wt_setup(o, d);
+    s.tmin = tmin;
+    s.best_t = tmax;
+    s.skip = skip;
+    s.best_leaf = -1;
+    s.sp = 0;
+    s.node = 0;
+}
+
+// One node of the query (s.node >= 0): its four box tests, the leaf children hit tested
+// at once, the internal children still in range visited nearest first (the others
+// pushed, farthest first); s.node becomes the next node, or -1 when the query ends.
+template <bool ANY, int SHORT, int TBK, class VIS>
+__device__ __forceinline__ void trav4_visit(Trav4& s, const float4* __restrict__ nodes, const float4* __restrict__ tris,
+                                            int* stack, int* spill, int lane, VIS& vis, TopNodes top) {
+    vis.node();
+    // 32-bit byte offsets from the tree's base (the build keeps 128 x nodes < 2^32), so
+    // each load is base + one 32-bit register
+    const uint32_t nb = (uint32_t)s.node * 128u;
+    const uint32_t ax = nb | s.br.onx, ay = nb | s.br.ony, az = nb | s.br.onz;
+    float4 nx, ny, nz, fx, fy, fz;
+    int4 cr;
+    // the empty asm ends the LDS branch differently from the global one: otherwise the
+    // compiler sinks the two sets of loads into one generic (flat) load of a selected
+    // address, which is slower for the global case
+    if (nb < top.bytes) {   // staged top levels: same byte offsets from the LDS copy
+        const char* lb = reinterpret_cast<const char*>(top.lds);
+        nx = *reinterpret_cast<const float4*>(lb + ax);
+        ny = *reinterpret_cast<const float4*>(lb + ay);
+        nz = *reinterpret_cast<const float4*>(lb + az);
+        fx = *reinterpret_cast<const float4*>(lb + (ax ^ FAR_X));
+        fy = *reinterpret_cast<const float4*>(lb + (ay ^ FAR_Y));
+        fz = *reinterpret_cast<const float4*>(lb + (az ^ FAR_Z));
+        cr = *reinterpret_cast<const int4*>(lb + (nb + 96u));
+        asm volatile("");
+    } else {
+        const char* base = reinterpret_cast<const char*>(nodes);
+        nx = *reinterpret_cast<const float4*>(base + ax);
+        ny = *reinterpret_cast<const float4*>(base + ay);
+        nz = *reinterpret_cast<const float4*>(base + az);
+        fx = *reinterpret_cast<const float4*>(base + (ax ^ FAR_X));
+        fy = *reinterpret_cast<const float4*>(base + (ay ^ FAR_Y));
+        fz = *reinterpret_cast<const float4*>(base + (az ^ FAR_Z));
+        cr = *reinterpret_cast<const int4*>(base + (nb + 96u));
+    }
+    const int cc[4] = {cr.x, cr.y, cr.z, cr.w};
+    float tc[4];
+    tc[0] = box4_enter(s.br, nx.x, ny.x, nz.x, fx.x, fy.x, fz.x, s.tmin, s.best_t);
+    tc[1] = box4_enter(s.br, nx.y, ny.y, nz.y, fx.y, fy.y, fz.y, s.tmin, s.best_t);
+    tc[2] = box4_enter(s.br, nx.z, ny.z, nz.z, fx.z, fy.z, fz.z, s.tmin, s.best_t);
+    tc[3] = box4_enter(s.br, nx.w, ny.w, nz.w, fx.w, fy.w, fz.w, s.tmin, s.best_t);
+    // Leaf children whose box is hit, tested one per pass; the wave runs as many passes
+    // as its busiest lane needs.
+    uint32_t lm = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (cc[k] < 0 && tc[k] <= s.best_t) lm |= 1u << k;
+    auto test_leaf = [&](int leaf) {
+        V3 v0, v1, v2;
+        int prim;
+        vis.tri();
+        load_tri(tris, leaf, v0, v1, v2, prim);
+        float t;
+        if (prim == s.skip || !wt_hit(s.wr, v0, v1, v2, t) || !(t > s.tmin)) return;
+        bool take = t < s.best_t;
+        if constexpr (!ANY) {
+            // equal t: the smaller original index wins (the current best's index is read
+            // back from its record, so no register holds it)
+            if (!take && t == s.best_t && s.best_leaf >= 0) take = prim < __float_as_int(tris[3 * s.best_leaf].w);
+        }
+        if (take) {
+            s.best_t = t;
+            s.best_leaf = leaf;
+        }
+    };
+    {
+        // the lane's hit leaves compacted: pass j runs when some lane has more than j of
+        // them (fewer passes than one per slot any lane uses)
+        const int nl = __popc(lm);
+        uint32_t m = lm;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < nl) {
+                const int k = __builtin_ctz(m);
+                m &= m - 1u;
+                test_leaf(~(k == 0 ? cc[0] : (k == 1 ? cc[1] : (k == 2 ? cc[2] : cc[3]))));
+            }
+    }
+    // internal children still in range (a missed box reports NaN; one entered only at
+    // +inf is dropped like a miss)
+    float key[4];
+    int ref[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool in = cc[k] >= 0 && tc[k] <= s.best_t;
+        key[k] = in ? tc[k] : __builtin_inff();
+        ref[k] = cc[k];
+    }
+    cmpx(key[0], ref[0], key[1], ref[1]);
+    cmpx(key[2], ref[2], key[3], ref[3]);
+    cmpx(key[0], ref[0], key[2], ref[2]);
+    cmpx(key[1], ref[1], key[3], ref[3]);
+    cmpx(key[1], ref[1], key[2], ref[2]);
+    if (ANY && s.best_leaf >= 0) {   // any hit ends the query
+        s.node = -1;
+    } else if (key[0] < __builtin_inff()) {
+        s.node = ref[0];
+        // every candidate is written to LDS, at sp, or at the lane's extra entry SHORT
+        // once the LDS part is full (a write that is not kept is overwritten or never
+        // read), so only the rare spill to global memory is a branch
+#pragma unroll
+        for (int k = 3; k >= 1; --k) {
+            const bool v = key[k] < __builtin_inff();
+            stack[min(s.sp, SHORT) * TBK + lane] = ref[k];
+            if constexpr (SHORT < MAX_STACK)
+                if (v && s.sp >= SHORT && s.sp < MAX_STACK) spill[(s.sp - SHORT) * TBK + lane] = ref[k];
+            s.sp = v && s.sp < MAX_STACK ? s.sp + 1 : s.sp;
+        }
+    } else if (s.sp > 0) {
+        --s.sp;
+        // an LDS read always (clamped index) and a global read only for spilled entries:
+        // two plain loads rather than one generic (flat) load
+        int nn = stack[min(s.sp, SHORT - 1) * TBK + lane];
+        if constexpr (SHORT < MAX_STACK)
+            if (s.sp >= SHORT)   // (a relaxed atomic load: the compiler cannot fold it with the
+                                 // LDS read into one generic load of a selected address,
+                                 // which would wait on every memory counter each pop)
+                nn = __hip_atomic_load(&spill[(s.sp - SHORT) * TBK + lane], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+        s.node = nn;
+    } else {
+        s.node = -1;
+    }
+}
+
 template <bool ANY, int SHORT, int TBK, class VIS>
 __device__ __forceinline__ bool traverse4(const float4* __restrict__ nodes, const float4* __restrict__ tris, V3 o,
                                           V3 d, float tmin, float tmax, int skip, Hit& h, int* stack, int* spill,
                                           int lane, VIS& vis, TopNodes top) {
-    const Box4Ray br = box4_setup(o, d);
-    const WtRay wr = wt_setup(o, d);
-    float best_t = tmax;
-    int best_leaf = -1;
-    int sp = 0;
-    int node = 0;
+    Trav4 s;
+    trav4_start(s, o, d, tmin, tmax, skip);
     // the only exit is the loop test (node < 0 once the stack is empty or an any-hit
     // query has its hit): with no break inside, the compiler keeps the pop an ordinary
     // branch of the one loop, instead of a nested loop whose lanes wait until every
     // lane of the wave needs a pop
-    while (node >= 0) {
-        vis.node();
-        // 32-bit byte offsets from the tree's base (the host keeps 128 x nodes < 2^32),
-        // so each load is base + one 32-bit register
-        const uint32_t nb = (uint32_t)node * 128u;
-        const uint32_t ax = nb | br.onx, ay = nb | br.ony, az = nb | br.onz;
-        float4 nx, ny, nz, fx, fy, fz;
-        int4 cr;
-        // the empty asm ends the LDS branch differently from the global one: otherwise the
-        // compiler sinks the two sets of loads into one generic (flat) load of a selected
-        // address, which is slower for the global case
-        if (nb < top.bytes) {   // staged top levels: same byte offsets from the LDS copy
-            const char* lb = reinterpret_cast<const char*>(top.lds);
-            nx = *reinterpret_cast<const float4*>(lb + ax);
-            ny = *reinterpret_cast<const float4*>(lb + ay);
-            nz = *reinterpret_cast<const float4*>(lb + az);
-            fx = *reinterpret_cast<const float4*>(lb + (ax ^ FAR_X));
-            fy = *reinterpret_cast<const float4*>(lb + (ay ^ FAR_Y));
-            fz = *reinterpret_cast<const float4*>(lb + (az ^ FAR_Z));
-            cr = *reinterpret_cast<const int4*>(lb + (nb + 96u));
-            asm volatile("");
-        } else {
-            const char* base = reinterpret_cast<const char*>(nodes);
-            nx = *reinterpret_cast<const float4*>(base + ax);
-            ny = *reinterpret_cast<const float4*>(base + ay);
-            nz = *reinterpret_cast<const float4*>(base + az);
-            fx = *reinterpret_cast<const float4*>(base + (ax ^ FAR_X));
-            fy = *reinterpret_cast<const float4*>(base + (ay ^ FAR_Y));
-            fz = *reinterpret_cast<const float4*>(base + (az ^ FAR_Z));
-            cr = *reinterpret_cast<const int4*>(base + (nb + 96u));
-        }
-        const int cc[4] = {cr.x, cr.y, cr.z, cr.w};
-        float tc[4];
-        tc[0] = box4_enter(br, nx.x, ny.x, nz.x, fx.x, fy.x, fz.x, tmin, best_t);
-        tc[1] = box4_enter(br, nx.y, ny.y, nz.y, fx.y, fy.y, fz.y, tmin, best_t);
-        tc[2] = box4_enter(br, nx.z, ny.z, nz.z, fx.z, fy.z, fz.z, tmin, best_t);
-        tc[3] = box4_enter(br, nx.w, ny.w, nz.w, fx.w, fy.w, fz.w, tmin, best_t);
-        // Leaf children whose box is hit, tested one per pass; the wave runs as many
-        // passes as its busiest lane needs.
-        uint32_t lm = 0u;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (cc[k] < 0 && tc[k] <= best_t) lm |= 1u << k;
-        auto test_leaf = [&](int leaf) {
-            V3 v0, v1, v2;
-            int prim;
-            vis.tri();
-            load_tri(tris, leaf, v0, v1, v2, prim);
-            float t;
-            if (prim == skip || !wt_hit(wr, v0, v1, v2, t) || !(t > tmin)) return;
-            bool take = t < best_t;
-            if constexpr (!ANY) {
-                // equal t: the smaller original index wins (the current best's index is
-                // read back from its record, so no register holds it)
-                if (!take && t == best_t && best_leaf >= 0) take = prim < __float_as_int(tris[3 * best_leaf].w);
-            }
-            if (take) {
-                best_t = t;
-                best_leaf = leaf;
-            }
-        };
-        {
-            // the lane's hit leaves compacted: pass j runs when some lane has more than
-            // j of them (fewer passes than one per slot any lane uses)
-            const int nl = __popc(lm);
-            uint32_t m = lm;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (j < nl) {
-                    const int k = __builtin_ctz(m);
-                    m &= m - 1u;
-                    test_leaf(~(k == 0 ? cc[0] : (k == 1 ? cc[1] : (k == 2 ? cc[2] : cc[3]))));
-                }
-        }
-        // internal children still in range (a missed box reports NaN; one entered only
-        // at +inf is dropped like a miss)
-        float key[4];
-        int ref[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const bool in = cc[k] >= 0 && tc[k] <= best_t;
-            key[k] = in ? tc[k] : __builtin_inff();
-            ref[k] = cc[k];
-        }
-        cmpx(key[0], ref[0], key[1], ref[1]);
-        cmpx(key[2], ref[2], key[3], ref[3]);
-        cmpx(key[0], ref[0], key[2], ref[2]);
-        cmpx(key[1], ref[1], key[3], ref[3]);
-        cmpx(key[1], ref[1], key[2], ref[2]);
-        if (ANY && best_leaf >= 0) {   // any hit ends the query
-            node = -1;
-        } else if (key[0] < __builtin_inff()) {
-            node = ref[0];
-            // every candidate is written to LDS, at sp, or at the lane's extra entry
-            // SHORT once the LDS part is full (a write that is not kept is overwritten or
-            // never read), so only the rare spill to global memory is a branch
-#pragma unroll
-            for (int k = 3; k >= 1; --k) {
-                const bool v = key[k] < __builtin_inff();
-                stack[min(sp, SHORT) * TBK + lane] = ref[k];
-                if constexpr (SHORT < MAX_STACK)
-                    if (v && sp >= SHORT && sp < MAX_STACK) spill[(sp - SHORT) * TBK + lane] = ref[k];
-                sp = v && sp < MAX_STACK ? sp + 1 : sp;
-            }
-        } else if (sp > 0) {
-            --sp;
-            // an LDS read always (clamped index) and a global read only for spilled
-            // entries: two plain loads rather than one generic (flat) load
-            node = stack[min(sp, SHORT - 1) * TBK + lane];
-            if constexpr (SHORT < MAX_STACK)
-                if (sp >= SHORT) node = spill[(sp - SHORT) * TBK + lane];
-        } else {
-            node = -1;
-        }
-    }
-    // the barycentrics of the hit: the same test on its triangle again (same
-    // arithmetic, same bits), which keeps them out of the loop's registers
+    while (s.node >= 0) trav4_visit<ANY, SHORT, TBK>(s, nodes, tris, stack, spill, lane, vis, top);
+    // the barycentrics of the hit: the same test on its triangle again (same arithmetic,
+    // same bits), which keeps them out of the loop's registers
     float bb1 = 0.f, bb2 = 0.f;
     int best_prim = -1;
-    if (best_leaf >= 0) {
+    if (s.best_leaf >= 0) {
         V3 v0, v1, v2;
-        load_tri(tris, best_leaf, v0, v1, v2, best_prim);
-        wt_intersect(wr, v0, v1, v2, best_t, bb1, bb2);
+        load_tri(tris, s.best_leaf, v0, v1, v2, best_prim);
+        wt_intersect(s.wr, v0, v1, v2, s.best_t, bb1, bb2);
     }
-    h.t = best_t;
-    h.leaf = best_leaf;
+    h.t = s.best_t;
+    h.leaf = s.best_leaf;
     h.prim = best_prim;
     h.b1 = bb1;
     h.b2 = bb2;
-    return best_leaf >= 0;
+    return s.best_leaf >= 0;
 }
 
 // closest or any hit on the request's BVH (4-wide when built)
