@@ -493,6 +493,9 @@ typedef struct {
     int bounced;
     brdf_full_t bf;
     double bpdf;
+    /* the sampled environment and bounce directions (held fixed by the camera-pose
+       derivative) */
+    v3 we, wi;
 } vrec;
 
 typedef struct {
@@ -758,6 +761,7 @@ static sample_out trace_sample(const ctx_t* cx, int32_t pixel, int32_t s, vrec* 
                 for (int c = 0; c < 3; ++c) L[c] += beta[c] * fb.f[c] * d->env[c] * es;
                 if (vr) {
                     vr->env = 1;
+                    vr->we = we;
                     vr->ef = fb;
                     vr->es = d->nmap_sample ? PI / dot(nss, we) : (fb.c > 0 ? PI / fb.c : 0.0);
                 }
@@ -781,6 +785,7 @@ static sample_out trace_sample(const ctx_t* cx, int32_t pixel, int32_t s, vrec* 
         for (int c = 0; c < 3; ++c) beta[c] *= fb.f[c] * w;
         if (vr) {
             vr->bounced = 1;
+            vr->wi = wi;
             vr->bf = fb;
             vr->bpdf = pdf;
         }
@@ -790,6 +795,77 @@ static sample_out trace_sample(const ctx_t* cx, int32_t pixel, int32_t s, vrec* 
     }
     return so;
 }
+
+/* The camera vertex's radiance for a camera pose (R, t) other than the forward's (Sec.
+ * 3.2: R_c, t_c are part of theta and refined with it), everything the forward decided
+ * held at its value: the camera ray of the same jittered pixel position meets the plane of
+ * the forward's triangle at x; the projector term is evaluated there in full (texture and
+ * normal map at the new texture coordinates, projector coordinates, distance, cosines,
+ * BRDF toward the camera), while the environment and bounce terms keep their sampled
+ * directions and remaining factors Se = L_env pi / c_sample and Sb = R_1 / pdf.  Its
+ * derivative w.r.t. (R, t) is the interior part of the camera-pose gradient: the
+ * visibility decisions and the later vertices of the path are held fixed. */
+static void camera_vertex(const ctx_t* cx, int32_t pixel, int32_t s, const double* Rc, const double* tc,
+                          const vrec* v, const double Se[3], const double Sb[3], double out[3]) {
+    const orc_desc* d = cx->d;
+    int32_t i = pixel % d->Wc, j = pixel / d->Wc;
+    double u[4];
+    uniforms(d, (uint32_t)pixel, (uint32_t)s, 0u, u);
+    v3 dir = nrm(mattv(Rc, matv(cx->Kc_inv, mk(i + u[0], j + u[1], 1.0))));
+    v3 o = scl(mattv(Rc, mk(tc[0], tc[1], tc[2])), -1.0);
+    int32_t prim = v->prim;
+    v3 v0 = vtx(d, d->F[3 * prim]), v1 = vtx(d, d->F[3 * prim + 1]), v2 = vtx(d, d->F[3 * prim + 2]);
+    v3 e1 = sub(v1, v0), e2 = sub(v2, v0);
+    v3 n = v->fN;                                        /* the forward's two-sided normal */
+    v3 x = add(o, scl(dir, dot(n, sub(v0, o)) / dot(n, dir)));
+    /* barycentrics of x in the triangle's plane (normal equations of x - v0 = b1 e1 + b2 e2) */
+    v3 p = sub(x, v0);
+    double a11 = dot(e1, e1), a12 = dot(e1, e2), a22 = dot(e2, e2), r1 = dot(p, e1), r2 = dot(p, e2);
+    double den = a11 * a22 - a12 * a12;
+    double b1 = (a22 * r1 - a12 * r2) / den, b2 = (a11 * r2 - a12 * r1) / den, b0 = 1.0 - b1 - b2;
+    const float* uvp = d->UV + 6 * (size_t)prim;
+    bilin tb = tex_lookup(d, b0 * uvp[0] + b1 * uvp[2] + b2 * uvp[4], b0 * uvp[1] + b1 * uvp[3] + b2 * uvp[5]);
+    double alb[3], r = 0, sp = 0, mu = 0;
+    fetch3(d->albedo, &tb, alb);
+    if (d->brdf == 1) {
+        r = fetch1(d->rough, &tb);
+        sp = fetch1(d->spec, &tb);
+        if (d->metal) mu = fetch1(d->metal, &tb);
+    }
+    v3 ns = n;
+    if (d->nmap) {
+        v3 th;
+        double tlen;
+        ns = shading_normal(d->nmap, &tb, v->fT, v->fB, n, &th, &tlen);
+    }
+    v3 wo = scl(dir, -1.0);
+    for (int c = 0; c < 3; ++c) out[c] = 0.0;
+    if (v->proj) {
+        v3 xp = add(matv(d->Rp, x), mk(d->tp[0], d->tp[1], d->tp[2]));
+        double pu = (d->Kp[0] * xp.x + d->Kp[1] * xp.y + d->Kp[2] * xp.z) / xp.z;
+        double pv = (d->Kp[3] * xp.x + d->Kp[4] * xp.y + d->Kp[5] * xp.z) / xp.z;
+        v3 tow = sub(cx->proj_o, x);
+        double dist = len(tow);
+        v3 wp = scl(tow, 1.0 / dist);
+        bilin pb = bilinear_at(pu - 0.5, pv - 0.5, d->Wp, d->Hp);
+        double E[3];
+        fetch3(cx->Ep, &pb, E);
+        double ca = xp.z / len(xp);
+        brdf_full_t fb = brdf_full(d->brdf, n, ns, wo, wp, alb, r, sp, mu);
+        for (int c = 0; c < 3; ++c) out[c] += fb.f[c] * fb.c * E[c] / (ca * ca * ca * dist * dist);
+    }
+    if (v->env) {
+        brdf_full_t fb = brdf_full(d->brdf, n, ns, wo, v->we, alb, r, sp, mu);
+        for (int c = 0; c < 3; ++c) out[c] += fb.f[c] * fb.c * Se[c];
+    }
+    if (v->bounced) {
+        brdf_full_t fb = brdf_full(d->brdf, n, ns, wo, v->wi, alb, r, sp, mu);
+        for (int c = 0; c < 3; ++c) out[c] += fb.f[c] * fb.c * Sb[c];
+    }
+}
+
+/* central-difference step of the camera-pose derivative (entries of R and t) */
+#define CAM_FD_H 1e-7
 
 static double clip_threshold(const orc_desc* d, int* argmin) {
     int a = 0;
@@ -874,7 +950,7 @@ int orc_render(const orc_desc* d, int32_t npix, const int32_t* pixels, double* o
 /* ------------------------------------------------------------------------- */
 int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32_t* pixels,
                    double* d_Ip, double* d_albedo, double* d_rough, double* d_spec, double* d_scalars,
-                   double* d_Ep_out, double* d_metal, double* d_nmap) {
+                   double* d_Ep_out, double* d_metal, double* d_nmap, double* d_cam) {
     ctx_t cx;
     ctx_init(&cx, d);
     int thr_arg;
@@ -882,8 +958,8 @@ int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32
     int nth = nthreads_of(d);
     size_t nEp = 3 * (size_t)d->Wp * d->Hp, nT = (size_t)d->tw * d->th;
     /* per-thread accumulators: dEp, dalb (3), drough, dspec, dmetal, dnmap (3), 6 CRF
-       scalars, 1 threshold */
-    size_t per = nEp + 3 * nT + nT + nT + nT + 3 * nT + 7;
+       scalars, 1 threshold, 12 camera-pose entries (R row-major, t) */
+    size_t per = nEp + 3 * nT + nT + nT + nT + 3 * nT + 7 + 12;
     double* acc = (double*)calloc((size_t)nth * per, sizeof(double));
     int npix_all = d->Wc * d->Hc;
     if (!pixels) npix = npix_all;
@@ -902,6 +978,7 @@ int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32
         double* gmetal = gspec + nT;
         double* gnmap = gmetal + nT;
         double* gsc = gnmap + 3 * nT;  /* gamma_c(3), w(3), threshold(1) */
+        double* gcam = gsc + 7;
         vrec* rec = (vrec*)malloc(sizeof(vrec) * (size_t)d->spp * d->max_depth);
         sample_out* so = (sample_out*)malloc(sizeof(sample_out) * (size_t)d->spp);
 #pragma omp for schedule(dynamic, 1)
@@ -966,6 +1043,27 @@ int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32
                         S[1][c] = d->env[c] * v->es;
                         S[2][c] = v->bounced ? Rn[c] / v->bpdf : 0.0;
                     }
+                    if (d_cam && k == 0) {
+                        /* camera pose: central differences of the camera vertex's radiance
+                           over the 12 entries of (R, t), contracted with the cotangent */
+                        double pose[12], Se[3], Sb[3];
+                        memcpy(pose, d->Rc, sizeof(double) * 9);
+                        memcpy(pose + 9, d->tc, sizeof(double) * 3);
+                        for (int c = 0; c < 3; ++c) {
+                            Se[c] = S[1][c];
+                            Sb[c] = S[2][c];
+                        }
+                        for (int e = 0; e < 12; ++e) {
+                            double vp[3], vm[3], keep = pose[e];
+                            pose[e] = keep + CAM_FD_H;
+                            camera_vertex(&cx, pixel, s, pose, pose + 9, v, Se, Sb, vp);
+                            pose[e] = keep - CAM_FD_H;
+                            camera_vertex(&cx, pixel, s, pose, pose + 9, v, Se, Sb, vm);
+                            pose[e] = keep;
+                            for (int c = 0; c < 3; ++c)
+                                gcam[e] += delta[c] * v->beta[c] * (vp[c] - vm[c]) / (2.0 * CAM_FD_H);
+                        }
+                    }
                     for (int c = 0; c < 3; ++c) {
                         double own = v->Le[c];
                         double bd = delta[c] * v->beta[c];  /* dL/d(term of vertex k) */
@@ -1025,6 +1123,7 @@ int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32
     double* gmetal = gspec + nT;
     double* gnmap = gmetal + nT;
     double* gsc = gnmap + 3 * nT;
+    if (d_cam) memcpy(d_cam, gsc + 7, sizeof(double) * 12);
     double sc[18];
     memset(sc, 0, sizeof sc);
     for (int c = 0; c < 3; ++c) { sc[12 + c] = gsc[c]; sc[15 + c] = gsc[3 + c]; }

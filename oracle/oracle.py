@@ -81,7 +81,7 @@ def _load(path: str):
     L = C.CDLL(path)
     P = C.c_void_p
     L.orc_render.argtypes = [C.POINTER(Desc), C.c_int32, P, P, P, P, P, P, P, P]
-    L.orc_render_vjp.argtypes = [C.POINTER(Desc), P, C.c_int32, P, P, P, P, P, P, P, P, P]
+    L.orc_render_vjp.argtypes = [C.POINTER(Desc), P, C.c_int32, P, P, P, P, P, P, P, P, P, P]
     L.orc_brdf_full.argtypes = [C.c_int32, P, P, P, P, P, C.c_double, C.c_double, C.c_double, P]
     L.orc_shading_frame.argtypes = [C.POINTER(Desc), C.c_int32, P, P, P]
     L.orc_philox_batch.argtypes = [C.c_uint64, C.c_int64, P, P]
@@ -205,8 +205,9 @@ def render(sc: Scene, pixels=None, want=("Ec", "Ic", "L", "hits", "margin", "mar
     return {k: v for k, v in out.items() if v is not None}
 
 
-def render_vjp(sc: Scene, G, pixels=None):
-    """VJP of the rendered image I_c with cotangent G (Hc x Wc x 3)."""
+def render_vjp(sc: Scene, G, pixels=None, camera=False):
+    """VJP of the rendered image I_c with cotangent G (Hc x Wc x 3); camera=True adds the
+    camera-pose gradient (camera_R, camera_t)."""
     d = sc.desc()
     G = np.ascontiguousarray(G, np.float64)
     px = None if pixels is None else np.ascontiguousarray(pixels, np.int32)
@@ -214,12 +215,15 @@ def render_vjp(sc: Scene, G, pixels=None):
     th, tw = sc.albedo.shape[:2]
     out = dict(Ip=np.zeros(sc.Ip.shape), albedo=np.zeros((th, tw, 3)), roughness=np.zeros((th, tw)),
                specular=np.zeros((th, tw)), scalars=np.zeros(18), Ep=np.zeros(sc.Ip.shape),
-               metallic=np.zeros((th, tw)), normal_map=np.zeros((th, tw, 3)))
+               metallic=np.zeros((th, tw)), normal_map=np.zeros((th, tw, 3)), camera=np.zeros(12))
     lib().orc_render_vjp(C.byref(d), _p(G), n, _p(px), _p(out["Ip"]), _p(out["albedo"]), _p(out["roughness"]),
                          _p(out["specular"]), _p(out["scalars"]), _p(out["Ep"]), _p(out["metallic"]),
-                         _p(out["normal_map"]))
+                         _p(out["normal_map"]), _p(out["camera"]) if camera else None)
     s = out.pop("scalars")
+    cam = out.pop("camera")
     out.update(prf_gamma=s[0:3], prf_mix=s[3:12].reshape(3, 3), crf_gamma=s[12:15], white_balance=s[15:18])
+    if camera:   # the interior camera-pose gradient: d/dR (row-major 3x3) and d/dt
+        out.update(camera_R=cam[:9].reshape(3, 3), camera_t=cam[9:])
     return out
 
 

@@ -14,6 +14,7 @@ from oracle import oracle as O
 
 from . import test_oracle_pins as P
 from . import test_oracle_pins_brdf2 as PB
+from . import test_oracle_pins_camera as PC
 from . import test_oracle_pins_lights as PL
 
 SRC = open(O.SRC).read()
@@ -92,6 +93,18 @@ MUTANTS = [
      "b.dfcn[c] = add(scl(wi, (1.0 - mu) * a[c] / PI), scl(dS, F));",
      "b.dfcn[c] = scl(dS, F);",
      PB.test_adjoint_on_metallic_and_normal_map_matches_central_differences),
+    ("camera pose: camera centre +R^T t instead of -R^T t",
+     "v3 o = scl(mattv(Rc, mk(tc[0], tc[1], tc[2])), -1.0);",
+     "v3 o = scl(mattv(Rc, mk(tc[0], tc[1], tc[2])), 1.0);",
+     PC.test_camera_pose_gradient_on_a_lit_plane),
+    ("camera pose: projector term without the 1/cos^3 falloff",
+     "out[c] += fb.f[c] * fb.c * E[c] / (ca * ca * ca * dist * dist);",
+     "out[c] += fb.f[c] * fb.c * E[c] / (dist * dist);",
+     PC.test_camera_pose_gradient_on_a_lit_plane),
+    ("camera pose: bounce term dropped",
+     "out[c] += fb.f[c] * fb.c * Sb[c];",
+     "out[c] += 0.0 * Sb[c];",
+     PC.test_camera_pose_gradient_through_the_bounce),
 ]
 
 
