@@ -305,6 +305,12 @@ static bilin bilinear_at(double x, double y, int W, int H) {
     return b;
 }
 
+/* the projector image's bilinear footprint at projector pixel position (pu, pv), texel
+ * centres at half-integer pixel coordinates */
+static bilin projector_texels(const orc_desc* d, double pu, double pv) {
+    return bilinear_at(pu - 0.5, pv - 0.5, d->Wp, d->Hp);
+}
+
 static bilin tex_lookup(const orc_desc* d, double u, double v) {
     return bilinear_at(u * d->tw - 0.5, v * d->th - 0.5, d->tw, d->th);
 }
@@ -723,7 +729,7 @@ static sample_out trace_sample(const ctx_t* cx, int32_t pixel, int32_t s, vrec* 
                         int occ = occluded(d, &cx->sc, x, wp, dist - cx->sc.tmin, prim, &mo);
                         UPD(&so, depth, mo, 6);
                         if (!occ) {
-                            bilin pb = bilinear_at(pu - 0.5, pv - 0.5, d->Wp, d->Hp);
+                            bilin pb = projector_texels(d, pu, pv);
                             double E[3];
                             fetch3(cx->Ep, &pb, E);
                             double ca = xp.z / len(xp);              /* cos alpha off the axis */
@@ -847,7 +853,7 @@ static void camera_vertex(const ctx_t* cx, int32_t pixel, int32_t s, const doubl
         v3 tow = sub(cx->proj_o, x);
         double dist = len(tow);
         v3 wp = scl(tow, 1.0 / dist);
-        bilin pb = bilinear_at(pu - 0.5, pv - 0.5, d->Wp, d->Hp);
+        bilin pb = projector_texels(d, pu, pv);
         double E[3];
         fetch3(cx->Ep, &pb, E);
         double ca = xp.z / len(xp);
