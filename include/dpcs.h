@@ -230,6 +230,13 @@ typedef struct {
     float* d_scalars;           /* DPCS_NUM_SCALARS, layout of device_scalars */
     float* d_metallic;          /* tex_h x tex_w (needs params->metallic) */
     float* d_normal_map;        /* tex_h x tex_w x 3, of the stored values v (needs params->normal_map) */
+    float* d_camera;            /* 12: d/dR_c (row-major 3 x 3) then d/dt_c of the camera pose (Sec. 3.2:
+                                   R_c, t_c refined with theta).  The interior part: per camera
+                                   sample, the first vertex's radiance differentiated w.r.t. its hit
+                                   point and viewing direction with every visibility decision, the
+                                   sampled directions and the rest of the path held (no boundary
+                                   term at silhouettes or shadow edges).  Needs path records: with
+                                   sample_radiance alone DPCS_E_UNSUPPORTED; not in the server. */
 } dpcs_grads;
 
 /* Vector-Jacobian product of dpcs_render at the same params (same seed: the same

@@ -1409,6 +1409,9 @@ static void flush_one(const Launch& l, const MapBins& mb, float* out, int stride
     hipLaunchKernelGGL(k_bin_gather<C>, dim3(grid_of((int64_t)mb.W * mb.H, 256)), dim3(256), 0, l.st, mb, out,
                        stride);
 }
+void launch_sum_partials(const Launch& l, const float* part, int nb, int stride, int nv, float* dst) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, l.st, part, nb, stride, nv, dst);
+}
 void launch_map_flush(const Launch& l, const AdjQueues& aq, const ReqDesc& r) {
     if (aq.tb.rec && r.d_tex) {
         if (r.dtex_c == 9) flush_one<9, TEX9_RS>(l, aq.tb, r.d_tex, 9);

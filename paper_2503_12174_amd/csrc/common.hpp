@@ -140,6 +140,8 @@ struct ReqDesc {
     // camera: world direction of pixel position (px, py) is cam_M (px, py, 1)
     double cam_o[3];
     double cam_M[9];
+    // the camera pose and inverse intrinsics themselves (camera-pose gradient)
+    double cam_R[9], cam_t[3], cam_Ki[9];
     // projector: device coords R x + t, pixel (K (R x + t)).xy / z
     double prj_R[9];
     double prj_t[3];
@@ -189,6 +191,7 @@ struct ReqDesc {
     float* d_tex;              // cotangent of (albedo rgb, roughness, specular[, metallic, normal
                                // map rgb]), dtex_c floats per texel
     float* d_acc;              // 8 floats: d gamma_c[3], d w[3], d threshold, pad
+    float* d_cam_part;         // per-workgroup partials of the camera-pose gradient, or null: off
     float* d_part;             // per-workgroup partials of the scalar sums (summed in a fixed
                                // order by a second kernel), or null: float atomics into d_acc
     // path records: one word per (sample, depth) at rec[(g - rec_g0) * max_depth + depth];

@@ -242,6 +242,13 @@ void launch_map_flush(const Launch& l, const AdjQueues& aq, const ReqDesc& r);
 // tile side and bin count for a W x H map (false: too many tiles, bin nothing)
 bool map_tiling(int W, int H, int& T, int& nbx, int& nby);
 // PRF backward, map de-interleave and scalar gradients; acc: 20 floats (see adjoint.hip)
+// camera-pose gradient of a wave's camera samples (after launch_adj_pixel, with path
+// records): per-workgroup partials into r.d_cam_part (cam_partial_floats of the wave's
+// samples), summed in a fixed order into r.d_acc[20..32)
+size_t cam_partial_floats(int64_t samples_per_wave);
+void launch_cam_grad(const Launch& l, const Queues& q, const AdjQueues& aq, const ReqDesc& r, uint32_t p0, uint32_t p1);
+// dst[k] += the sum of nb partials part[b * stride + k], k < nv, in a fixed order
+void launch_sum_partials(const Launch& l, const float* part, int nb, int stride, int nv, float* dst);
 void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* d_albedo, float* d_rough,
                        float* d_spec, float* d_scalars, float* acc, float* d_metal = nullptr,
                        float* d_nmap = nullptr);

@@ -255,6 +255,11 @@ bool fill_desc(dpcs_context, ReqDesc& r, const dpcs_render_params* p, dpcs_scene
         for (int j = 0; j < 3; ++j) r.cam_M[3 * i + j] = R[i] * Ki[j] + R[3 + i] * Ki[3 + j] + R[6 + i] * Ki[6 + j];
     for (int i = 0; i < 3; ++i)
         r.cam_o[i] = -(R[i] * p->camera.t[0] + R[3 + i] * p->camera.t[1] + R[6 + i] * p->camera.t[2]);
+    for (int k = 0; k < 9; ++k) {
+        r.cam_R[k] = R[k];
+        r.cam_Ki[k] = Ki[k];
+    }
+    for (int i = 0; i < 3; ++i) r.cam_t[i] = p->camera.t[i];
     r.Wc = p->camera.width;
     r.Hc = p->camera.height;
     const double* Rp = p->projector.R;
@@ -776,6 +781,7 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
     r.sid_base = 0;
     int pr = prof_begin(ctx, DPCS_STAGE_ADJ_PIXEL);
     launch_adj_pixel(l, q, aq, r, a, b, sample_L);
+    launch_cam_grad(l, q, aq, r, a, b);   // (no-op unless the camera-pose gradient is asked for)
     prof_end(ctx, pr, nullptr, b - a);
     launch_set_count(l, q.cnt, 0, n, 1, 4);
     int cur = 0;

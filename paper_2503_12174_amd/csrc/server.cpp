@@ -486,6 +486,7 @@ extern "C" dpcs_status dpcs_server_submit(dpcs_server s, const dpcs_request* rq)
     dpcs_context ctx = s->ctx;
     if (!rq->scene || rq->scene->ctx != ctx || !rq->out_image) return DPCS_E_INVALID;
     if (rq->params.metallic || rq->params.normal_map) return DPCS_E_UNSUPPORTED;   // single-request path only
+    if (rq->grads && rq->grads->d_camera) return DPCS_E_UNSUPPORTED;               // likewise
     (void)hipSetDevice(ctx->device);
     auto* q = new Req();
     std::string why;

@@ -27,6 +27,9 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     if (ext && sample_radiance && !path_records)
         return fail(ctx, DPCS_E_UNSUPPORTED, "with the metallic or normal map the VJP replays path records: pass the "
                                              "forward's path_records with sample_radiance, or neither");
+    if (grads->d_camera && sample_radiance && !path_records)
+        return fail(ctx, DPCS_E_UNSUPPORTED, "the camera-pose gradient replays path records: pass the forward's "
+                                             "path_records with sample_radiance, or neither");
     if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
     r.grad_image = grad_image;
     dpcs_status st = DPCS_OK;
@@ -52,6 +55,10 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     // scalar sums reduced in a fixed order: the same gradients on every run
     r.d_part = (float*)scratch(ctx, "vjp.partials", sizeof(float) * partial_floats(ppw, (int64_t)nEp), &st);
     if (!r.d_part) return st;
+    if (grads->d_camera) {
+        r.d_cam_part = (float*)scratch(ctx, "vjp.camera_partials", sizeof(float) * cam_partial_floats(ppw * r.spp), &st);
+        if (!r.d_cam_part) return st;
+    }
     Queues q{};
     AdjQueues aq{};
     if (!make_queues(ctx, "fwd.queues", ppw * r.spp, q, &st)) return st;
@@ -91,6 +98,10 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     }
     launch_adj_finish(l, r, grads->d_proj_image, grads->d_albedo, grads->d_roughness, grads->d_specular,
                       grads->d_scalars, acc, grads->d_metallic, grads->d_normal_map);
+    if (grads->d_camera &&
+        !hip_ok(ctx, hipMemcpyAsync(grads->d_camera, acc + 20, 12 * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream),
+                "camera gradient copy"))
+        return DPCS_E_DEVICE;
     if (!hip_ok(ctx, hipGetLastError(), "kernel launch")) return DPCS_E_DEVICE;
     ctx->err.clear();
     return DPCS_OK;

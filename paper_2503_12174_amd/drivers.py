@@ -4,6 +4,9 @@ compensate()  projector compensation, Eq. 13: find I_p whose rendering matches a
               target camera image, by Adam on an L2 loss, I_p clamped to [0, 1]
 compensate_morphing()  the same on a moving surface, frame by frame (Sec. 4.4), the
               BVH refitted on the device for each frame's vertex positions
+refine_camera()  camera-pose refinement (R_c, t_c of theta, Sec. 3.2): a rotation
+              vector and a translation offset about the calibrated pose, by Adam on an L2
+              loss against captures, the maps and responses held
 fit()         scene-parameter fit, Eq. 9: BRDF maps and PRF/CRF scalars from image
               pairs, with the paper's constraints on gamma_p, gamma_c, w
               (Sec. 3.2: gamma_p in [2, 3], gamma_c in [1/3, 1], w in (0.2, 2.5));
@@ -85,6 +88,48 @@ def project_constraints(scal: torch.Tensor, clamp_gamma_p=True):
             scal[0:3].clamp_(2.0, 3.0)
         scal[12:15].clamp_(1.0 / 3.0, 1.0)
         scal[15:18].clamp_(0.2 + 1e-4, 2.5 - 1e-4)
+
+
+def pose_from(omega, dt, R0, t0):
+    """The 12 pose values (R row-major, t) of R = exp([omega]x) R0, t = t0 + dt (Rodrigues),
+    differentiable in omega and dt (float64 tensors on the host)."""
+    th = torch.sqrt((omega * omega).sum() + 1e-30)
+    k = omega / th
+    Kx = torch.zeros((3, 3), dtype=omega.dtype)
+    Kx = Kx.index_put((torch.tensor([0, 0, 1, 1, 2, 2]), torch.tensor([1, 2, 0, 2, 0, 1])),
+                      torch.stack([-k[2], k[1], k[2], -k[0], -k[1], k[0]]))
+    Rw = torch.eye(3, dtype=omega.dtype) + torch.sin(th) * Kx + (1 - torch.cos(th)) * (Kx @ Kx)
+    R = Rw @ torch.as_tensor(R0, dtype=omega.dtype)
+    t = torch.as_tensor(t0, dtype=omega.dtype) + dt
+    return torch.cat([R.reshape(-1), t])
+
+
+def refine_camera(ctx, scene, cfg, images, targets, albedo, roughness, specular, steps=40, lr=2e-3, base_seed=0,
+                  scalars=None):
+    """Refine the camera pose about cfg.camera so renderings of `images` match `targets`
+    (the interior gradient of the pose: suited to the minor corrections the paper makes).
+    Returns (R, t) and the losses."""
+    omega = torch.zeros(3, dtype=torch.float64, requires_grad=True)
+    dt = torch.zeros(3, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([omega, dt], lr=lr)
+    scal = scalars_from(cfg) if scalars is None else scalars
+    R0, t0 = cfg.camera.R, cfg.camera.t
+    losses = []
+    for k in range(steps):
+        c = copy.copy(cfg)
+        c.seed = base_seed + k
+        pose = pose_from(omega, dt, R0, t0)
+        loss = 0.0
+        for ip, tgt in zip(images, targets):
+            out = render(ctx, scene, c, ip, albedo, roughness, specular, scal, camera_pose=pose.float())
+            loss = loss + ((out - tgt) ** 2).mean()
+        loss = loss / len(images)
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        losses.append(float(loss.detach()))
+    pose = pose_from(omega, dt, R0, t0).detach().numpy()
+    return (pose[:9].reshape(3, 3), pose[9:]), losses
 
 
 def fit(ctx, scene, cfg, images, targets, steps=50, lr=0.02, base_seed=0, clamp_gamma_p=True, init=None,

@@ -104,7 +104,7 @@ def compare_forward(gpu, ref, pixels=None, gain=1.0, rtol=1e-4, min_clean=0.95):
 VJP_MODES = ("own", "records", "retrace")
 
 
-def run_vjp(run: GpuRun, G, sample_radiance=None, mode="own"):
+def run_vjp(run: GpuRun, G, sample_radiance=None, mode="own", camera=False):
     """dpcs_render_vjp through the C ABI; returns numpy gradients keyed like the oracle's.
 
     mode "own": the call recomputes the forward with its own path records;
@@ -122,6 +122,8 @@ def run_vjp(run: GpuRun, G, sample_radiance=None, mode="own"):
         out["metallic"] = ext["d_metallic"] = torch.zeros_like(run.metal)
     if run.nmap is not None:
         out["normal_map"] = ext["d_normal_map"] = torch.zeros_like(run.nmap)
+    if camera:
+        out["camera"] = ext["d_camera"] = torch.zeros(12, device="cuda")
     g = dev(G, torch.float32)
     rec = None
     if mode in ("records", "retrace") and sample_radiance is None:
@@ -138,6 +140,9 @@ def run_vjp(run: GpuRun, G, sample_radiance=None, mode="own"):
     res = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
     s = res.pop("scalars")
     res.update(prf_gamma=s[0:3], prf_mix=s[3:12].reshape(3, 3), crf_gamma=s[12:15], white_balance=s[15:18])
+    if camera:
+        cam = res.pop("camera")
+        res.update(camera_R=cam[:9].reshape(3, 3), camera_t=cam[9:])
     return res
 
 
