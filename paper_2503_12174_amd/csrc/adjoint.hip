@@ -599,6 +599,25 @@ __device__ __forceinline__ uint32_t map_records(const MapBins& mb) {
     return (int64_t)n < mb.cap ? n : (uint32_t)mb.cap;
 }
 
+// a record of RS floats into registers in 16-byte loads (8-byte ones for RS = 6); returns v
+template <int RS>
+__device__ __forceinline__ const float* load_record(const float* __restrict__ p, float* v) {
+    if constexpr (RS % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < RS / 4; ++k) {
+            const float4 x = ((const float4*)p)[k];
+            v[4 * k] = x.x, v[4 * k + 1] = x.y, v[4 * k + 2] = x.z, v[4 * k + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < RS / 2; ++k) {
+            const float2 x = ((const float2*)p)[k];
+            v[2 * k] = x.x, v[2 * k + 1] = x.y;
+        }
+    }
+    return v;
+}
+
 // records per tile: workgroup histogram in LDS, then one returning atomic per touched
 // tile, whose old value -- where this chunk's records start inside the tile's range --
 // goes to rowbase for the placement; also the largest |cotangent| of any record (for
@@ -619,11 +638,13 @@ __global__ void __launch_bounds__(BIN_TB) k_bin_hist(MapBins mb) {
         const uint32_t i = base + threadIdx.x;
         const bool valid = i < e;
         const float* p = mb.rec + (size_t)(valid ? i : b0) * RS;
-        const uint32_t bin = valid ? (uint32_t)map_bin(mb, __float_as_uint(p[0])) : 0u;
+        float v[RS];
+        load_record<RS>(p, v);
+        const uint32_t bin = valid ? (uint32_t)map_bin(mb, __float_as_uint(v[0])) : 0u;
         lds_bin_add(h, valid, bin);
         if (valid)
 #pragma unroll
-            for (int c = 0; c < C; ++c) m = fmaxf(m, fabsf(p[3 + c]));   // NaN is dropped here; see accum
+            for (int c = 0; c < C; ++c) m = fmaxf(m, fabsf(v[3 + c]));   // NaN is dropped here; see accum
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
@@ -685,9 +706,16 @@ __global__ void __launch_bounds__(BIN_TB) k_bin_place(MapBins mb) {
         const uint32_t pos = lds_bin_add(cnt, valid, bin);
         if (!valid || (int64_t)pos >= mb.cap) continue;   // pos < cap always for consistent counts
         float2* dst = (float2*)(mb.sorted + (size_t)pos * RS);
-        dst[0] = h;
+        if constexpr (RS % 4 == 0) {   // 16-byte copies (records are 16-byte aligned)
+            const float4* s4 = (const float4*)src;
+            float4* d4 = (float4*)dst;
 #pragma unroll
-        for (int k = 1; k < RS / 2; ++k) dst[k] = src[k];
+            for (int k = 0; k < RS / 4; ++k) d4[k] = s4[k];
+        } else {
+            dst[0] = h;
+#pragma unroll
+            for (int k = 1; k < RS / 2; ++k) dst[k] = src[k];
+        }
     }
 }
 
@@ -730,8 +758,9 @@ __global__ void __launch_bounds__(ACC_TB) k_bin_accum(MapBins mb) {
         __syncthreads();
         const int tx0 = (b % mb.nbx) * mb.T, ty0 = (b / mb.nbx) * mb.T;
         bool bad = false;
+        float rv[RS];
         for (uint32_t i = s0 + threadIdx.x; i < s1; i += ACC_TB) {
-            const float* p = mb.sorted + (size_t)i * RS;
+            const float* p = load_record<RS>(mb.sorted + (size_t)i * RS, rv);
             const uint32_t head = __float_as_uint(p[0]);
             const uint32_t base = head & 0x0fffffffu;
             const int y0 = (int)(base / (uint32_t)mb.W), x0 = (int)(base - (uint32_t)y0 * (uint32_t)mb.W);
