@@ -209,10 +209,12 @@ void launch_pack_tex_b(const Launch& l, const ReqDesc& r, const float* nmap, con
 void launch_set_count(const Launch& l, uint32_t* cnt, int idx, uint32_t value, int zero_from, int zero_to);
 void launch_raygen(const Launch& l, const Queues& q, const ReqDesc& r, const ReqDesc* table, int slot,
                    uint32_t g0, uint32_t n, bool adjoint, const AdjQueues* aq);
+// cam (one request, no table): the queue is the request's camera rays, generated by the
+// closest-hit and shading kernels themselves (no raygen launch, no path state read)
 void launch_trace(const Launch& l, const Queues& q, int cur, const ReqDesc& uni, const ReqDesc* table,
-                  int64_t n_upper);
+                  int64_t n_upper, bool cam = false);
 void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const ReqDesc& uni, const ReqDesc* table,
-                  int64_t n_upper);
+                  int64_t n_upper, bool cam = false);
 // depth: the bounce the shadow rays leave from (for the path records); one_tree (with a
 // table): every ray is on the tree of `uni` (several requests of one scene)
 void launch_shadow(const Launch& l, const Queues& q, int which, const ReqDesc& uni, const ReqDesc* table,

@@ -86,8 +86,10 @@ __global__ void k_raygen(Queues q, ReqDesc r, int slot, uint32_t g0, uint32_t n)
 
 // ---------------------------------------------------------------- closest hit
 // PROF: the counting pass's instantiation (node and triangle visit counters, summed
-// into q.stats), which a profiler reports apart from the timed launches
-template <bool UNI, bool PROF>
+// into q.stats), which a profiler reports apart from the timed launches.
+// CAM: the queue is one request's camera rays, entry i being sample g_base + i: each is
+// generated here (Eq. 6 inverted) instead of being read back from the path queue.
+template <bool UNI, bool PROF, bool CAM = false>
 __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_trace(Queues q, int cur, ReqDesc uni, const ReqDesc* __restrict__ table) {
     __shared__ int stack[(SHORT_STACK + 1) * TB];
     __shared__ float4 ltop[UNI ? 8 * TOP_NODES : 1];
@@ -97,8 +99,17 @@ __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_trace(Queues q, int 
     if constexpr (UNI)   // one tree for the whole launch: stage its top levels
         if (uni.nodes4) top = stage_top<TB>(ltop, uni.nodes4, uni.top_nodes);
     for (uint32_t i = blockIdx.x * TB + threadIdx.x; i < n; i += gridDim.x * TB) {
-        const PathO o = nt_ld(&q.po[cur][i]);
-        const PathD d = nt_ld(&q.pd[cur][i]);
+        PathO o;
+        PathD d;
+        if constexpr (CAM) {
+            const uint32_t g = uni.g_base + i;
+            const D3 cd = camera_dir(uni, g);
+            o = PathO{uni.cam_o[0], uni.cam_o[1], uni.cam_o[2], 0, -1};
+            d = PathD{cd.x, cd.y, cd.z, g, 0u};
+        } else {
+            o = nt_ld(&q.po[cur][i]);
+            d = nt_ld(&q.pd[cur][i]);
+        }
         const ReqDesc& r = sel<UNI>(uni, table, o.slot);
         Hit h;
         Visits<PROF> vis;
@@ -116,8 +127,10 @@ __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_trace(Queues q, int 
 
 // ---------------------------------------------------------------- shading
 // EXT: the request has the metallic and normal maps (tex4b): BRDF, cosines and sampling
-// about the shading normal (one request per launch)
-template <bool UNI, bool EXT>
+// about the shading normal (one request per launch).  CAM: depth 0 of one request, its
+// camera rays generated here as in k_trace (throughput 1, the sample's radiance started
+// at zero here)
+template <bool UNI, bool EXT, bool CAM = false>
 __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, ReqDesc uni,
                                                  const ReqDesc* __restrict__ table) {
     const int nxt = cur ^ 1;
@@ -134,14 +147,30 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
         float4 nb = {}, po = {}, pd = {}, pc = {}, eo = {}, ed = {}, ec = {};
         float ptmax = 0.0f;
         if (i < n) {
-            const PathO o = nt_ld(&q.po[cur][i]);
-            const PathD dd = nt_ld(&q.pd[cur][i]);
-            const float4 b = nt_ld(&q.pb[cur][i]);
+            PathO o;
+            PathD dd;
+            float4 b;
+            if constexpr (CAM) {
+                const uint32_t gc = uni.g_base + i;
+                const D3 cd = camera_dir(uni, gc);
+                o = PathO{uni.cam_o[0], uni.cam_o[1], uni.cam_o[2], 0, -1};
+                dd = PathD{cd.x, cd.y, cd.z, gc, 0u};
+                b = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
+            } else {
+                o = nt_ld(&q.po[cur][i]);
+                dd = nt_ld(&q.pd[cur][i]);
+                b = nt_ld(&q.pb[cur][i]);
+            }
             const int leaf = __builtin_nontemporal_load(&q.hit[i]);
             const ReqDesc& r = sel<UNI>(uni, table, o.slot);
             const uint32_t g = dd.g;
             const uint32_t sid = g - r.g_base + r.sid_base;
             const D3 beta = d3(b.x, b.y, b.z);
+            if constexpr (CAM) {
+                q.L[sid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (r.out_hits)
+                    for (int k = 1; k < r.max_depth; ++k) r.out_hits[(size_t)g * r.max_depth + k] = -2;
+            }
             if (r.rec) __builtin_nontemporal_store((uint32_t)(leaf + 1), &r.rec[(size_t)(g - r.rec_g0) * r.max_depth + depth]);
             if (leaf < 0) {
                 if (r.out_hits) r.out_hits[(size_t)g * r.max_depth + depth] = -1;
@@ -460,8 +489,13 @@ void launch_raygen(const Launch& l, const Queues& q, const ReqDesc& r, const Req
     if (n) hipLaunchKernelGGL(k_raygen, dim3(grid_of(n, 256)), dim3(256), 0, l.st, q, r, slot, g0, n);
 }
 void launch_trace(const Launch& l, const Queues& q, int cur, const ReqDesc& uni, const ReqDesc* table,
-                  int64_t n_upper) {
+                  int64_t n_upper, bool cam) {
     const dim3 g(grid_cap(Launch{l.st, q.trace_blocks}, n_upper, TB)), b(TB);
+    if (cam && !table) {
+        if (q.stats) hipLaunchKernelGGL((k_trace<true, true, true>), g, b, 0, l.st, q, cur, uni, table);
+        else hipLaunchKernelGGL((k_trace<true, false, true>), g, b, 0, l.st, q, cur, uni, table);
+        return;
+    }
     if (q.stats) {
         if (table) hipLaunchKernelGGL((k_trace<false, true>), g, b, 0, l.st, q, cur, uni, table);
         else hipLaunchKernelGGL((k_trace<true, true>), g, b, 0, l.st, q, cur, uni, table);
@@ -471,8 +505,13 @@ void launch_trace(const Launch& l, const Queues& q, int cur, const ReqDesc& uni,
     }
 }
 void launch_shade(const Launch& l, const Queues& q, int cur, int depth, const ReqDesc& uni, const ReqDesc* table,
-                  int64_t n_upper) {
+                  int64_t n_upper, bool cam) {
     const dim3 g(grid_of(n_upper, BLOCK)), b(BLOCK);
+    if (cam && !table) {
+        if (uni.tex4b) hipLaunchKernelGGL((k_shade<true, true, true>), g, b, 0, l.st, q, cur, depth, uni, table);
+        else hipLaunchKernelGGL((k_shade<true, false, true>), g, b, 0, l.st, q, cur, depth, uni, table);
+        return;
+    }
     if (table) hipLaunchKernelGGL((k_shade<false, false>), g, b, 0, l.st, q, cur, depth, uni, table);
     else if (uni.tex4b) hipLaunchKernelGGL((k_shade<true, true>), g, b, 0, l.st, q, cur, depth, uni, table);
     else hipLaunchKernelGGL((k_shade<true, false>), g, b, 0, l.st, q, cur, depth, uni, table);

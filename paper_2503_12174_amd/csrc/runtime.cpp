@@ -744,18 +744,19 @@ void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t 
     r.g_base = a * (uint32_t)r.spp;
     r.sid_base = 0;
     launch_set_count(l, q.cnt, 0, n, 1, 4);
+    // the camera rays are generated by the depth-0 closest-hit and shading kernels (no
+    // raygen launch); the stage record keeps the count of camera samples
     int pr = prof_begin(ctx, DPCS_STAGE_RAYGEN);
-    launch_raygen(l, q, r, nullptr, 0, r.g_base, n, false, nullptr);
     prof_end(ctx, pr, nullptr, n);
     int cur = 0;
     for (int d = 0; d < r.max_depth; ++d) {
         launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);   // next path queue and shadow queues empty
         q.stats = prof_stats(ctx, DPCS_STAGE_TRACE);
         pr = prof_begin(ctx, DPCS_STAGE_TRACE);
-        launch_trace(l, q, cur, r, nullptr, n);
+        launch_trace(l, q, cur, r, nullptr, n, d == 0);
         prof_end(ctx, pr, q.cnt + cur, 0);
         pr = prof_begin(ctx, DPCS_STAGE_SHADE);
-        launch_shade(l, q, cur, d, r, nullptr, n);
+        launch_shade(l, q, cur, d, r, nullptr, n, d == 0);
         prof_end(ctx, pr, q.cnt + cur, 0);
         q.stats = prof_stats(ctx, DPCS_STAGE_SHADOW);
         for (int w = 0; w < (r.env_on ? 2 : 1); ++w) {
