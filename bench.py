@@ -259,7 +259,8 @@ def configs_bench(ctx, steps=5):
     return res
 
 
-def serving_bench(ctx, n_req, n_alone, warmup=100, rate=50.0, sweep=(30.0, 40.0, 100.0, 200.0), n_sweep=400):
+def serving_bench(ctx, n_req, n_alone, warmup=100, rate=50.0, sweep=(30.0, 40.0, 100.0, 200.0), n_sweep=400,
+                  max_slots=64):
     """Serving run: 4 resident corners (10k/50k/200k/500k triangles), Poisson arrivals,
     resolution in {128, 256, 512}^2, spp in {16, 64, 256}, depth 4, half relighting and
     half compensation steps (fwd + VJP of an L2 loss).  n_req requests after `warmup` at
@@ -319,7 +320,7 @@ def serving_bench(ctx, n_req, n_alone, warmup=100, rate=50.0, sweep=(30.0, 40.0,
     def run(reqs, warmup):
         prep = prepare(reqs)
         torch.cuda.synchronize()
-        srv = dpcs.Server(ctx, budget_bytes=64 << 30, max_slots=64)
+        srv = dpcs.Server(ctx, budget_bytes=64 << 30, max_slots=max_slots)
         lat = {}
         t0 = time.perf_counter()
 

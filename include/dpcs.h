@@ -395,10 +395,8 @@ typedef struct {
                                    for all work queued on it before the submit call. */
 } dpcs_request;
 
-/* Non-blocking.  DPCS_E_REJECTED if the request alone exceeds the budget.  While a
- * request is alone in the loop its waves fill the whole capacity; while others are
- * active or queued, waves are cut to at most 2^20 paths so a newcomer waits for short
- * waves only. */
+/* Non-blocking.  DPCS_E_REJECTED if the request alone exceeds the budget.  Waves hold
+ * at most 2^21 paths, so a newcomer waits for short waves only. */
 DPCS_API dpcs_status dpcs_server_submit(dpcs_server srv, const dpcs_request* req);
 /* Non-blocking: up to max finished requests (ids, statuses, latency in ms from submit
  * to completion on the device; latency_ms may be NULL).  Returns the count. */
