@@ -623,7 +623,7 @@ def main():
         "vs_baseline": None, "dtype": "f32 traversal + f64 shading", "data": "synthetic",
         "config": {"workload": w.name, "camera": [W, H], "projector": [w.projector.width, w.projector.height],
                    "spp": w.spp, "max_depth": w.max_depth, "triangles": info.num_triangles,
-                   "bvh": "binned SAH (host) collapsed to 4-wide", "bvh_build_ms": round(info.build_ms, 3),
+                   "bvh": "binned SAH built on the device, collapsed to 4-wide", "bvh_build_ms": round(info.build_ms, 3),
                    "bvh_wide_nodes": int(info.wide_nodes),
                    "step": "forward render keeping per-sample radiance and 4-byte path records + VJP "
                            "replaying the same samples"},

@@ -608,9 +608,11 @@ static void ctx_init(ctx_t* cx, const orc_desc* d) {
 
 static void ctx_free(ctx_t* cx) { free(cx->Ep); }
 
-/* Trace one camera sample (Eq. 3, 6, 10).  rec (may be NULL) receives max_depth vertices;
- * hits (may be NULL) receives the hit triangle per vertex (-1 miss, -2 not reached). */
-static sample_out trace_sample(const ctx_t* cx, int32_t pixel, int32_t s, vrec* rec, int32_t* hits) {
+/* Trace one path that leaves the camera centre along dir (Eq. 3, 10); its random numbers
+ * are those of (pixel, s) under cx->d's key.  rec (may be NULL) receives max_depth
+ * vertices; hits (may be NULL) receives the hit triangle per vertex (-1 miss, -2 not
+ * reached). */
+static sample_out trace_path(const ctx_t* cx, v3 dir, int32_t pixel, int32_t s, vrec* rec, int32_t* hits) {
     const orc_desc* d = cx->d;
     sample_out so;
     memset(&so, 0, sizeof so);
@@ -618,13 +620,6 @@ static sample_out trace_sample(const ctx_t* cx, int32_t pixel, int32_t s, vrec* 
     const double tx = TAU_X * cx->sc.diag;
     if (hits)
         for (int k = 0; k < d->max_depth; ++k) hits[k] = -2;
-
-    /* camera ray through the jittered pixel position (Eq. 6 inverted) */
-    int32_t i = pixel % d->Wc, j = pixel / d->Wc;
-    double u[4];
-    uniforms(d, (uint32_t)pixel, (uint32_t)s, 0u, u);
-    v3 pix = mk(i + u[0], j + u[1], 1.0);
-    v3 dir = nrm(mattv(d->Rc, matv(cx->Kc_inv, pix)));
     v3 o = cx->cam_o;
     int skip = -1;
     double beta[3] = {1, 1, 1};
@@ -800,6 +795,16 @@ static sample_out trace_sample(const ctx_t* cx, int32_t pixel, int32_t s, vrec* 
         skip = prim;
     }
     return so;
+}
+
+/* Trace one camera sample: the ray through the jittered pixel position (Eq. 6 inverted). */
+static sample_out trace_sample(const ctx_t* cx, int32_t pixel, int32_t s, vrec* rec, int32_t* hits) {
+    const orc_desc* d = cx->d;
+    int32_t i = pixel % d->Wc, j = pixel / d->Wc;
+    double u[4];
+    uniforms(d, (uint32_t)pixel, (uint32_t)s, 0u, u);
+    v3 dir = nrm(mattv(d->Rc, matv(cx->Kc_inv, mk(i + u[0], j + u[1], 1.0))));
+    return trace_path(cx, dir, pixel, s, rec, hits);
 }
 
 /* The camera vertex's radiance for a camera pose (R, t) other than the forward's (Sec.
