@@ -92,6 +92,8 @@ typedef struct {
     const double* nmap;
     const double* nmap_sample; /* normal map whose shading normal samples directions and
                                   pdfs (NULL: nmap); the frozen-path estimator of the tests */
+    double edge_density;   /* camera-pose gradient: edge samples per pixel of edge length
+                              for the boundary part (0: interior part only) */
 } orc_desc;
 
 /* margin scales (see header comment); all margins are divided by these */
@@ -902,6 +904,266 @@ static int nthreads_of(const orc_desc* d) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* camera pose: the boundary part at the images of mesh edges                 */
+/* ------------------------------------------------------------------------- */
+/* A pixel (i, j) is the integral of the sample radiance over the square [i, i+1] x
+ * [j, j+1] of image coordinates x = (K X)_{1,2} / (K X)_3, X = R_c P + t_c (the uniform
+ * jitter of the camera samples, Eq. 6).  Where the radiance jumps along a curve of the
+ * image, moving the camera moves the curve, and the pixel's integral changes by the jump
+ * times the curve's normal speed: d I / d theta gains the line integral of
+ * (f- - f+) (n . dx/dtheta) over the curve's part inside the pixel, n the unit normal
+ * toward the f+ side (Reynolds transport).  The curves taken here are the images of the
+ * mesh edges across which the first surface seen changes discontinuously (vertices at the
+ * same position are one vertex here):
+ *   - edges of one face, or of three or more faces;
+ *   - edges whose two faces are not coplanar: creases, and every silhouette edge (two
+ *     faces that meet at a silhouette as seen from the camera centre, i.e. lie on one side
+ *     of the plane through it and the edge, are never coplanar unless folded flat);
+ *   - coplanar faces folded onto one side of the edge;
+ *   - seams: the texture coordinates or the emission differ across the edge.
+ * Shadow and projector-frustum boundaries on the surfaces are not among them.
+ * Each such edge, clipped to w >= tmin in front of the camera and to the image, gets
+ * n_e = ceil(density * l_e) stratified points, l_e its length in pixels: point k at
+ * (k + u) / n_e along the clipped segment, weight l_e / n_e; f-, f+ are the sample
+ * radiances (clipped as in Eq. 12) of two paths through x -/+ EDGE_EPS n that share the
+ * point's random numbers.  Edge samples are numbered over the edges in order of (lower,
+ * higher welded vertex index, a vertex's welded index being the lowest index at its
+ * position); sample k draws its uniforms from counter (k, 0, block, 0) under
+ * the key seed ^ EDGE_KEY (u is the first of block 0). */
+#define EDGE_EPS 1e-2
+#define EDGE_KEY 0x9E3779B97F4A7C15ull
+
+typedef struct { int32_t a, b, f0, f1, nf; } orc_edge;   /* a < b; f1 only when nf == 2 */
+
+static int cmp_edge_key(const void* x, const void* y) {
+    const int32_t* p = (const int32_t*)x;
+    const int32_t* q = (const int32_t*)y;
+    for (int k = 0; k < 3; ++k)
+        if (p[k] != q[k]) return p[k] < q[k] ? -1 : 1;
+    return 0;
+}
+
+typedef struct { float p[3]; int32_t i; } vpos_t;
+static int cmp_vertex_pos(const void* x, const void* y) {
+    const vpos_t* a = (const vpos_t*)x;
+    const vpos_t* b = (const vpos_t*)y;
+    for (int k = 0; k < 3; ++k)
+        if (a->p[k] != b->p[k]) return a->p[k] < b->p[k] ? -1 : 1;
+    return a->i < b->i ? -1 : (a->i > b->i);
+}
+
+/* canonical vertex of each vertex: the lowest index at the same position (a mesh that
+ * repeats vertices per face still has one edge where two faces meet) */
+static int32_t* weld_vertices(const orc_desc* d) {
+    vpos_t* v = (vpos_t*)malloc(sizeof(vpos_t) * (size_t)d->nv);
+    int32_t* canon = (int32_t*)malloc(sizeof(int32_t) * (size_t)d->nv);
+    for (int32_t i = 0; i < d->nv; ++i) {
+        for (int k = 0; k < 3; ++k) v[i].p[k] = d->V[3 * (size_t)i + k];
+        v[i].i = i;
+    }
+    qsort(v, (size_t)d->nv, sizeof(vpos_t), cmp_vertex_pos);
+    for (int32_t i = 0; i < d->nv; ++i) {
+        int same = i && v[i].p[0] == v[i - 1].p[0] && v[i].p[1] == v[i - 1].p[1] && v[i].p[2] == v[i - 1].p[2];
+        canon[v[i].i] = same ? canon[v[i - 1].i] : v[i].i;
+    }
+    free(v);
+    return canon;
+}
+
+/* the unique edges of the mesh with their faces, sorted by (a, b), over welded vertices */
+static orc_edge* mesh_edges(const orc_desc* d, const int32_t* canon, int64_t* ne) {
+    int32_t* key = (int32_t*)malloc(sizeof(int32_t) * 9 * (size_t)d->nt);
+    for (int32_t f = 0; f < d->nt; ++f)
+        for (int k = 0; k < 3; ++k) {
+            int32_t u = canon[d->F[3 * f + k]], v = canon[d->F[3 * f + (k + 1) % 3]];
+            int32_t* e = key + 3 * (3 * (size_t)f + k);
+            e[0] = u < v ? u : v;
+            e[1] = u < v ? v : u;
+            e[2] = f;
+        }
+    qsort(key, 3 * (size_t)d->nt, 3 * sizeof(int32_t), cmp_edge_key);
+    orc_edge* E = (orc_edge*)malloc(sizeof(orc_edge) * 3 * (size_t)d->nt);
+    int64_t n = 0;
+    for (int64_t i = 0; i < 3 * (int64_t)d->nt;) {
+        int64_t j = i;
+        while (j < 3 * (int64_t)d->nt && key[3 * j] == key[3 * i] && key[3 * j + 1] == key[3 * i + 1]) ++j;
+        orc_edge e = {key[3 * i], key[3 * i + 1], key[3 * i + 2], j - i > 1 ? key[3 * i + 5] : -1, (int32_t)(j - i)};
+        E[n++] = e;
+        i = j;
+    }
+    free(key);
+    *ne = n;
+    return E;
+}
+
+static int corner_of(const orc_desc* d, const int32_t* canon, int32_t f, int32_t v) {
+    for (int k = 0; k < 3; ++k)
+        if (canon[d->F[3 * f + k]] == v) return k;
+    return -1;
+}
+
+/* does the first surface seen change discontinuously across the edge's image? */
+static int edge_is_discontinuous(const ctx_t* cx, const int32_t* canon, const orc_edge* e) {
+    const orc_desc* d = cx->d;
+    if (e->nf != 2) return 1;
+    v3 A = vtx(d, e->a), B = vtx(d, e->b);
+    int a0 = corner_of(d, canon, e->f0, e->a), b0 = corner_of(d, canon, e->f0, e->b);
+    int a1 = corner_of(d, canon, e->f1, e->a), b1 = corner_of(d, canon, e->f1, e->b);
+    v3 C0 = vtx(d, d->F[3 * e->f0 + 3 - a0 - b0]), C1 = vtx(d, d->F[3 * e->f1 + 3 - a1 - b1]);
+    /* faces at an angle: a crease, or a silhouette from where the camera is */
+    v3 n0 = nrm(cross(sub(B, A), sub(C0, A))), n1 = nrm(cross(sub(B, A), sub(C1, A)));
+    if (len(cross(n0, n1)) > 1e-9) return 1;
+    /* coplanar faces folded onto the same side of the edge */
+    if (dot(sub(C0, A), sub(C1, A)) - dot(sub(C0, A), sub(B, A)) * dot(sub(C1, A), sub(B, A)) / dot(sub(B, A), sub(B, A)) > 0)
+        return 1;
+    const float* u0 = d->UV + 6 * (size_t)e->f0;
+    const float* u1 = d->UV + 6 * (size_t)e->f1;
+    if (u0[2 * a0] != u1[2 * a1] || u0[2 * a0 + 1] != u1[2 * a1 + 1] || u0[2 * b0] != u1[2 * b1] ||
+        u0[2 * b0 + 1] != u1[2 * b1 + 1])
+        return 1;
+    if (d->Le)
+        for (int c = 0; c < 3; ++c)
+            if (d->Le[3 * e->f0 + c] != d->Le[3 * e->f1 + c]) return 1;
+    return 0;
+}
+
+/* the edge's image, clipped: 3D end points A1, B1 with homogeneous depths wA, wB and
+ * their image points; the kept part of the image segment is lambda in [l0, l1] */
+typedef struct {
+    v3 A1, B1;
+    double wA, wB, ax, ay, dx, dy, l0, l1, len;
+} edge_clip;
+
+static v3 homog(const orc_desc* d, v3 P) {
+    return matv(d->Kc, add(matv(d->Rc, P), mk(d->tc[0], d->tc[1], d->tc[2])));
+}
+
+static int clip_edge(const ctx_t* cx, const orc_edge* e, edge_clip* c) {
+    const orc_desc* d = cx->d;
+    v3 A = vtx(d, e->a), B = vtx(d, e->b);
+    v3 hA = homog(d, A), hB = homog(d, B);
+    double wmin = cx->sc.tmin, s0 = 0, s1 = 1;
+    if (hA.z < wmin && hB.z < wmin) return 0;
+    if (hA.z < wmin) s0 = (wmin - hA.z) / (hB.z - hA.z);
+    if (hB.z < wmin) s1 = (wmin - hA.z) / (hB.z - hA.z);
+    c->A1 = add(A, scl(sub(B, A), s0));
+    c->B1 = add(A, scl(sub(B, A), s1));
+    v3 gA = add(hA, scl(sub(hB, hA), s0)), gB = add(hA, scl(sub(hB, hA), s1));
+    c->wA = gA.z;
+    c->wB = gB.z;
+    c->ax = gA.x / gA.z;
+    c->ay = gA.y / gA.z;
+    c->dx = gB.x / gB.z - c->ax;
+    c->dy = gB.y / gB.z - c->ay;
+    /* Liang-Barsky against [0, Wc] x [0, Hc] */
+    double p[4] = {-c->dx, c->dx, -c->dy, c->dy};
+    double q[4] = {c->ax, d->Wc - c->ax, c->ay, d->Hc - c->ay};
+    double l0 = 0, l1 = 1;
+    for (int k = 0; k < 4; ++k) {
+        if (p[k] == 0) {
+            if (q[k] < 0) return 0;
+        } else {
+            double r = q[k] / p[k];
+            if (p[k] < 0) {
+                if (r > l0) l0 = r;
+            } else if (r < l1) {
+                l1 = r;
+            }
+        }
+    }
+    if (!(l0 < l1)) return 0;
+    c->l0 = l0;
+    c->l1 = l1;
+    c->len = (l1 - l0) * sqrt(c->dx * c->dx + c->dy * c->dy);
+    return c->len > 0;
+}
+
+static int64_t edge_samples(const ctx_t* cx, const int32_t* canon, const orc_edge* e, double density,
+                            edge_clip* c) {
+    if (!edge_is_discontinuous(cx, canon, e) || !clip_edge(cx, e, c)) return 0;
+    return (int64_t)ceil(density * c->len);
+}
+
+/* The boundary part of d loss / d(R_c, t_c) (out12: R row-major, then t) for the
+ * per-pixel cotangents dE (Hc x Wc x 3) of the pixel means of the clipped sample
+ * radiance.  Per-edge sums are added in edge order. */
+int orc_camera_boundary(const orc_desc* d, const double* dE, double* out12, int64_t* n_samples) {
+    ctx_t cx;
+    ctx_init(&cx, d);
+    orc_desc de = *d;
+    de.seed = d->seed ^ EDGE_KEY;
+    de.sample_offset = 0;
+    ctx_t ce = cx;
+    ce.d = &de;
+    int64_t ne;
+    int32_t* canon = weld_vertices(d);
+    orc_edge* E = mesh_edges(d, canon, &ne);
+    int64_t* off = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ne + 1));
+    off[0] = 0;
+    for (int64_t i = 0; i < ne; ++i) {
+        edge_clip c;
+        off[i + 1] = off[i] + edge_samples(&cx, canon, &E[i], d->edge_density, &c);
+    }
+    double* per = (double*)calloc(12 * (size_t)ne, sizeof(double));
+    double thr = clip_threshold(d, NULL);
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads_of(d))
+    for (int64_t i = 0; i < ne; ++i) {
+        edge_clip c;
+        int64_t n = edge_samples(&cx, canon, &E[i], d->edge_density, &c);
+        if (n == 0) continue;
+        double el = sqrt(c.dx * c.dx + c.dy * c.dy);
+        double nx = -c.dy / el, ny = c.dx / el;     /* unit normal toward the f+ side */
+        for (int64_t k = 0; k < n; ++k) {
+            uint32_t gk = (uint32_t)(off[i] + k);
+            double u[4];
+            uniforms(&de, gk, 0u, 0u, u);
+            double lam = c.l0 + (c.l1 - c.l0) * ((double)k + u[0]) / (double)n;
+            double x = c.ax + lam * c.dx, y = c.ay + lam * c.dy;
+            double mu = lam * c.wA / (lam * c.wA + (1.0 - lam) * c.wB);
+            v3 P = add(c.A1, scl(sub(c.B1, c.A1), mu));
+            int32_t pi = (int32_t)floor(x), pj = (int32_t)floor(y);
+            if (pi > d->Wc - 1) pi = d->Wc - 1;
+            if (pj > d->Hc - 1) pj = d->Hc - 1;
+            if (pi < 0) pi = 0;
+            if (pj < 0) pj = 0;
+            const double* g = dE + 3 * ((size_t)pj * d->Wc + pi);
+            if (g[0] == 0 && g[1] == 0 && g[2] == 0) continue;
+            double f[2][3];
+            for (int side = 0; side < 2; ++side) {
+                double sg = side ? EDGE_EPS : -EDGE_EPS;
+                v3 dir = nrm(mattv(d->Rc, matv(cx.Kc_inv, mk(x + sg * nx, y + sg * ny, 1.0))));
+                sample_out so = trace_path(&ce, dir, (int32_t)gk, 0, NULL, NULL);
+                for (int ch = 0; ch < 3; ++ch) f[side][ch] = d->clip && so.L[ch] > thr ? thr : so.L[ch];
+            }
+            double J = 0;
+            for (int ch = 0; ch < 3; ++ch) J += g[ch] * (f[0][ch] - f[1][ch]);
+            J *= c.len / (double)n;
+            /* image speed of the edge point: dx/dR_ij = c_i P_j, dx/dt_i = c_i with
+               c_i = (K_{.i} - x K_{3i}) / w over the image rows */
+            v3 h = homog(d, P);
+            double Pj[3] = {P.x, P.y, P.z};
+            for (int r = 0; r < 3; ++r) {
+                double ci_x = (d->Kc[r] - x * d->Kc[6 + r]) / h.z;
+                double ci_y = (d->Kc[3 + r] - y * d->Kc[6 + r]) / h.z;
+                double a = nx * ci_x + ny * ci_y;
+                for (int j = 0; j < 3; ++j) per[12 * (size_t)i + 3 * r + j] += J * a * Pj[j];
+                per[12 * (size_t)i + 9 + r] += J * a;
+            }
+        }
+    }
+    for (int k = 0; k < 12; ++k) out12[k] = 0;
+    for (int64_t i = 0; i < ne; ++i)
+        for (int k = 0; k < 12; ++k) out12[k] += per[12 * (size_t)i + k];
+    if (n_samples) *n_samples = off[ne];
+    free(per);
+    free(off);
+    free(E);
+    free(canon);
+    ctx_free(&cx);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* forward render of a set of pixels                                           */
 /*   pixels: npix pixel indices (j*Wc + i), or NULL for all Wc*Hc in order     */
 /*   out_Ec/out_Ic: npix*3; out_L: npix*spp*3 unclipped sample radiance;       */
@@ -974,6 +1236,8 @@ int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32
     double* acc = (double*)calloc((size_t)nth * per, sizeof(double));
     int npix_all = d->Wc * d->Hc;
     if (!pixels) npix = npix_all;
+    /* per-pixel cotangents of the clipped pixel means (the camera pose's boundary part) */
+    double* dE_pix = d_cam && d->edge_density > 0 ? (double*)calloc(3 * (size_t)npix_all, sizeof(double)) : NULL;
 
 #pragma omp parallel num_threads(nth)
     {
@@ -1019,6 +1283,7 @@ int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32
                     gsc[c] += g * pow(y, gc) * log(y);
                     gsc[3 + c] += dy * d->crf_gain * Ec[c];
                 }
+                if (dE_pix) dE_pix[3 * (size_t)pixel + c] = dEc[c];
             }
             /* per sample: clip (Eq. 12) then the path's own reverse sweep */
             for (int32_t s = 0; s < d->spp; ++s) {
@@ -1135,6 +1400,12 @@ int orc_render_vjp(const orc_desc* d, const double* G, int32_t npix, const int32
     double* gnmap = gmetal + nT;
     double* gsc = gnmap + 3 * nT;
     if (d_cam) memcpy(d_cam, gsc + 7, sizeof(double) * 12);
+    if (dE_pix) {
+        double bnd[12];
+        orc_camera_boundary(d, dE_pix, bnd, NULL);
+        for (int k = 0; k < 12; ++k) d_cam[k] += bnd[k];
+        free(dE_pix);
+    }
     double sc[18];
     memset(sc, 0, sizeof sc);
     for (int c = 0; c < 3; ++c) { sc[12 + c] = gsc[c]; sc[15 + c] = gsc[3 + c]; }

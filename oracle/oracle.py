@@ -49,6 +49,7 @@ class Desc(C.Structure):
         ("nthreads", C.c_int32),
         ("tmin", C.c_double),
         ("metal", C.c_void_p), ("nmap", C.c_void_p), ("nmap_sample", C.c_void_p),
+        ("edge_density", C.c_double),
     ]
 
 
@@ -98,6 +99,7 @@ def _load(path: str):
     L.orc_bilinear.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int64, P, P]
     L.orc_threads.argtypes = [C.POINTER(Desc)]
     L.orc_first_hit.argtypes = [C.POINTER(Desc), C.c_int32, C.c_int32, P]
+    L.orc_camera_boundary.argtypes = [C.POINTER(Desc), P, P, C.POINTER(C.c_int64)]
     L.orc_pdf_batch.argtypes = [C.c_int32, P, P, C.c_double, C.c_int64, P, P]
     L.orc_denoise.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_double, C.c_int32, P]
     L.orc_denoise_vjp.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_double, C.c_int32, P]
@@ -158,6 +160,7 @@ class Scene:
         self.sample_offset = int(g("sample_offset"))
         self.nthreads = int(over.get("nthreads", 0))
         self.tmin = float(over.get("tmin", 0.0))
+        self.edge_density = float(over.get("edge_density", 0.0))
 
     def desc(self) -> Desc:
         d = Desc()
@@ -183,6 +186,7 @@ class Scene:
         d.nthreads = self.nthreads
         d.tmin = self.tmin
         d.metal, d.nmap, d.nmap_sample = _p(self.metal), _p(self.nmap), _p(self.nmap_sample)
+        d.edge_density = self.edge_density
         self._d = d
         return d
 
@@ -207,7 +211,8 @@ def render(sc: Scene, pixels=None, want=("Ec", "Ic", "L", "hits", "margin", "mar
 
 def render_vjp(sc: Scene, G, pixels=None, camera=False):
     """VJP of the rendered image I_c with cotangent G (Hc x Wc x 3); camera=True adds the
-    camera-pose gradient (camera_R, camera_t)."""
+    camera-pose gradient (camera_R, camera_t): its interior part, plus the boundary part at
+    the images of mesh edges when the scene has edge_density > 0."""
     d = sc.desc()
     G = np.ascontiguousarray(G, np.float64)
     px = None if pixels is None else np.ascontiguousarray(pixels, np.int32)
@@ -222,9 +227,21 @@ def render_vjp(sc: Scene, G, pixels=None, camera=False):
     s = out.pop("scalars")
     cam = out.pop("camera")
     out.update(prf_gamma=s[0:3], prf_mix=s[3:12].reshape(3, 3), crf_gamma=s[12:15], white_balance=s[15:18])
-    if camera:   # the interior camera-pose gradient: d/dR (row-major 3x3) and d/dt
+    if camera:   # the camera-pose gradient: d/dR (row-major 3x3) and d/dt
         out.update(camera_R=cam[:9].reshape(3, 3), camera_t=cam[9:])
     return out
+
+
+def camera_boundary(sc: Scene, dE):
+    """The boundary part of the camera-pose gradient alone, for per-pixel cotangents dE
+    (Hc x Wc x 3) of the pixel means of the clipped sample radiance; uses the scene's
+    edge_density.  Returns (12-vector: d/dR row-major then d/dt, number of edge samples)."""
+    d = sc.desc()
+    dE = np.ascontiguousarray(dE, np.float64)
+    out = np.zeros(12)
+    n = C.c_int64(0)
+    lib().orc_camera_boundary(C.byref(d), _p(dE), _p(out), C.byref(n))
+    return out, int(n.value)
 
 
 def philox(seed: int, counters: np.ndarray) -> np.ndarray:

@@ -15,6 +15,7 @@ from oracle import oracle as O
 from . import test_oracle_pins as P
 from . import test_oracle_pins_brdf2 as PB
 from . import test_oracle_pins_camera as PC
+from . import test_oracle_pins_camera_edges as PE
 from . import test_oracle_pins_lights as PL
 
 SRC = open(O.SRC).read()
@@ -105,6 +106,50 @@ MUTANTS = [
      "out[c] += fb.f[c] * fb.c * Sb[c];",
      "out[c] += 0.0 * Sb[c];",
      PC.test_camera_pose_gradient_through_the_bounce),
+    ("camera edges: jump taken as f+ - f-",
+     "for (int ch = 0; ch < 3; ++ch) J += g[ch] * (f[0][ch] - f[1][ch]);",
+     "for (int ch = 0; ch < 3; ++ch) J += g[ch] * (f[1][ch] - f[0][ch]);",
+     PE.test_square_silhouette_constant_cotangent),
+    ("camera edges: image parameter used as the 3D parameter",
+     "double mu = lam * c.wA / (lam * c.wA + (1.0 - lam) * c.wB);",
+     "double mu = lam;",
+     PE.test_square_silhouette_constant_cotangent),
+    ("camera edges: speed without the perspective division's x term",
+     "double ci_x = (d->Kc[r] - x * d->Kc[6 + r]) / h.z;",
+     "double ci_x = d->Kc[r] / h.z;",
+     PE.test_square_silhouette_constant_cotangent),
+    ("camera edges: sample weight without the segment length",
+     "J *= c.len / (double)n;",
+     "J *= 1.0 / (double)n;",
+     PE.test_square_silhouette_constant_cotangent),
+    ("camera edges: pixel indices transposed",
+     "const double* g = dE + 3 * ((size_t)pj * d->Wc + pi);",
+     "const double* g = dE + 3 * ((size_t)pi * d->Wc + pj);",
+     PE.test_square_silhouette_random_cotangent),
+    ("camera edges: faces at an angle not taken",
+     "if (len(cross(n0, n1)) > 1e-9) return 1;",
+     "if (len(cross(n0, n1)) > 1e9) return 1;",
+     PE.test_box_of_one_emission_without_seams),
+    ("camera edges: faces folded flat not taken",
+     "dot(sub(C1, A), sub(B, A)) / dot(sub(B, A), sub(B, A)) > 0)",
+     "dot(sub(C1, A), sub(B, A)) / dot(sub(B, A), sub(B, A)) > 1e300)",
+     PE.test_faces_folded_flat),
+    ("camera edges: texture seams not taken",
+     "if (u0[2 * a0] != u1[2 * a1] || u0[2 * a0 + 1] != u1[2 * a1 + 1] || u0[2 * b0] != u1[2 * b1] ||",
+     "if (0 && (u0[2 * a0] != u1[2 * a1] || u0[2 * a0 + 1] != u1[2 * a1 + 1] || u0[2 * b0] != u1[2 * b1]) &&",
+     PE.test_texture_seam_under_the_environment),
+    ("camera edges: emission seams not taken",
+     "if (d->Le[3 * e->f0 + c] != d->Le[3 * e->f1 + c]) return 1;",
+     "if (0 * d->Le[3 * e->f0 + c] != 0) return 1;",
+     PE.test_emission_seam_and_flat_fold),
+    ("camera edges: no welding of repeated vertices",
+     "canon[v[i].i] = same ? canon[v[i - 1].i] : v[i].i;",
+     "canon[v[i].i] = v[i].i + 0 * same;",
+     PE.test_closed_box),
+    ("camera edges: no clipping at the camera plane",
+     "if (hA.z < wmin) s0 = (wmin - hA.z) / (hB.z - hA.z);",
+     "if (0) s0 = (wmin - hA.z) / (hB.z - hA.z);",
+     PE.test_floor_reaching_behind_the_camera),
 ]
 
 
