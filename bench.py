@@ -159,8 +159,9 @@ def configs_bench(ctx, steps=5):
     """The other synthetic setups, timed end to end (context beside the headline step):
     the oracle-scale quad-and-cube forward, the 200k-triangle 512^2 compensation-scale
     forward and forward + VJP step at 16 spp, 100 Adam steps of projector compensation
-    on it, a relighting render at the paper's capture resolutions, and one scene-fit
-    step (8 image pairs, 32 spp forward + VJP each)."""
+    on it, a relighting render at the paper's capture resolutions, one scene-fit step
+    (8 image pairs, 32 spp forward + VJP each), and the VJP on the headline scene with the
+    camera-pose gradient's interior and boundary parts."""
     import copy
 
     import numpy as np
@@ -256,6 +257,33 @@ def configs_bench(ctx, steps=5):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / 10
     res["fit_step_8x64px_32spp"] = {"ms": round(ms, 3), "samples_per_s": round(8 * 64 * 64 * 32 / (ms * 1e-3), 1)}
+    del sc
+
+    # camera-pose gradient on the headline scene (VJP replaying the forward's records):
+    # without it, its interior part, and with the boundary part at 1 and 4 points per
+    # pixel of edge length
+    w = synth.corner_50k()
+    sc = dpcs.Scene(ctx, w.mesh, bvh="sah")
+    alb, rough, spec, proj = dev(w.albedo), dev(w.roughness), dev(w.specular), dev(w.proj_image)
+    p = dpcs.params_from(w, alb, rough, spec)
+    H, W = w.camera.height, w.camera.width
+    out = torch.zeros((H, W, 3), device="cuda")
+    Ls = torch.zeros((H, W, w.spp, 3), device="cuda")
+    rec = torch.zeros((H, W, w.spp, w.max_depth), dtype=torch.int32, device="cuda")
+    dpcs.dpcs_render(ctx, sc, p, proj, out, sample_radiance=Ls, path_records=rec)
+    G = dev(np.random.default_rng(12).normal(size=(H, W, 3)))
+    grads = dict(d_proj_image=torch.zeros_like(proj), d_albedo=torch.zeros_like(alb),
+                 d_roughness=torch.zeros_like(rough), d_specular=torch.zeros_like(spec),
+                 d_scalars=torch.zeros(18, device="cuda"))
+    d_cam = torch.zeros(12, device="cuda")
+    cam = {}
+    for key, pose, dens in (("vjp_ms", False, 0.0), ("with_interior_ms", True, 0.0), ("with_edges_1_ms", True, 1.0),
+                            ("with_edges_4_ms", True, 4.0)):
+        kw = dict(d_camera=d_cam, camera_edge_density=dens) if pose else {}
+        cam[key] = round(wall(lambda: dpcs.dpcs_render_vjp(ctx, sc, p, proj, G, sample_radiance=Ls, path_records=rec,
+                                                           **grads, **kw), steps), 4)
+    res["camera_pose_vjp_corner50k_256px_64spp"] = cam
+    del Ls, rec, sc
     return res
 
 

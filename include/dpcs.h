@@ -234,9 +234,24 @@ typedef struct {
                                    R_c, t_c refined with theta).  The interior part: per camera
                                    sample, the first vertex's radiance differentiated w.r.t. its hit
                                    point and viewing direction with every visibility decision, the
-                                   sampled directions and the rest of the path held (no boundary
-                                   term at silhouettes or shadow edges).  Needs path records: with
-                                   sample_radiance alone DPCS_E_UNSUPPORTED; not in the server. */
+                                   sampled directions and the rest of the path held; plus, when
+                                   camera_edge_density > 0, the boundary part below.  Needs path
+                                   records: with sample_radiance alone DPCS_E_UNSUPPORTED; not in
+                                   the server. */
+    double camera_edge_density; /* boundary part of d_camera (0: none; needs d_camera; <= 1e6):
+                                   points per pixel of image length on the images of the mesh edges
+                                   where the first surface seen jumps (vertices of triangles at one
+                                   position are one vertex; edges of one face or of three or more,
+                                   faces not coplanar -- creases and all silhouettes --, faces folded
+                                   flat, texture-coordinate and emission seams), clipped to the
+                                   image and in front of the camera.  Each point adds (f- - f+) times
+                                   the edge's normal speed in the image times its share of the
+                                   edge's length, f-/+ the clipped radiance of two paths 0.01 pixel
+                                   to either side that share the point's random numbers (their own
+                                   key: seed XOR 0x9E3779B97F4A7C15), weighted by its pixel's
+                                   cotangent.  Shadow and projector-frustum boundaries on surfaces
+                                   are not included.  The edge table is built on the host on first
+                                   use and after each refit; DPCS_E_UNSUPPORTED above 2^32 points. */
 } dpcs_grads;
 
 /* Vector-Jacobian product of dpcs_render at the same params (same seed: the same

@@ -913,8 +913,8 @@ static int nthreads_of(const orc_desc* d) {
  * times the curve's normal speed: d I / d theta gains the line integral of
  * (f- - f+) (n . dx/dtheta) over the curve's part inside the pixel, n the unit normal
  * toward the f+ side (Reynolds transport).  The curves taken here are the images of the
- * mesh edges across which the first surface seen changes discontinuously (vertices at the
- * same position are one vertex here):
+ * mesh edges across which the first surface seen changes discontinuously (vertices of
+ * triangles at the same position are one vertex here):
  *   - edges of one face, or of three or more faces;
  *   - edges whose two faces are not coplanar: creases, and every silhouette edge (two
  *     faces that meet at a silhouette as seen from the camera centre, i.e. lie on one side
@@ -952,21 +952,28 @@ static int cmp_vertex_pos(const void* x, const void* y) {
     return a->i < b->i ? -1 : (a->i > b->i);
 }
 
-/* canonical vertex of each vertex: the lowest index at the same position (a mesh that
- * repeats vertices per face still has one edge where two faces meet) */
+/* canonical vertex of each vertex that a triangle uses: the lowest such index at the same
+ * position (a mesh that repeats vertices per face still has one edge where two faces
+ * meet); vertices no triangle uses take no part */
 static int32_t* weld_vertices(const orc_desc* d) {
+    char* used = (char*)calloc((size_t)d->nv, 1);
+    for (int64_t k = 0; k < 3 * (int64_t)d->nt; ++k) used[d->F[k]] = 1;
     vpos_t* v = (vpos_t*)malloc(sizeof(vpos_t) * (size_t)d->nv);
     int32_t* canon = (int32_t*)malloc(sizeof(int32_t) * (size_t)d->nv);
+    int32_t n = 0;
     for (int32_t i = 0; i < d->nv; ++i) {
-        for (int k = 0; k < 3; ++k) v[i].p[k] = d->V[3 * (size_t)i + k];
-        v[i].i = i;
+        canon[i] = i;
+        if (!used[i]) continue;
+        for (int k = 0; k < 3; ++k) v[n].p[k] = d->V[3 * (size_t)i + k];
+        v[n++].i = i;
     }
-    qsort(v, (size_t)d->nv, sizeof(vpos_t), cmp_vertex_pos);
-    for (int32_t i = 0; i < d->nv; ++i) {
+    qsort(v, (size_t)n, sizeof(vpos_t), cmp_vertex_pos);
+    for (int32_t i = 0; i < n; ++i) {
         int same = i && v[i].p[0] == v[i - 1].p[0] && v[i].p[1] == v[i - 1].p[1] && v[i].p[2] == v[i - 1].p[2];
         canon[v[i].i] = same ? canon[v[i - 1].i] : v[i].i;
     }
     free(v);
+    free(used);
     return canon;
 }
 
@@ -1005,6 +1012,7 @@ static int corner_of(const orc_desc* d, const int32_t* canon, int32_t f, int32_t
 /* does the first surface seen change discontinuously across the edge's image? */
 static int edge_is_discontinuous(const ctx_t* cx, const int32_t* canon, const orc_edge* e) {
     const orc_desc* d = cx->d;
+    if (e->a == e->b) return 0;   /* a degenerate triangle's side of no length */
     if (e->nf != 2) return 1;
     v3 A = vtx(d, e->a), B = vtx(d, e->b);
     int a0 = corner_of(d, canon, e->f0, e->a), b0 = corner_of(d, canon, e->f0, e->b);

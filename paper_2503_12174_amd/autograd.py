@@ -6,8 +6,9 @@ without recomputing the forward samples or tracing.  Differentiable inputs: proj
 image, albedo, roughness, specular maps, the 18 response scalars
 (gamma_p[3], M[9], gamma_c[3], w[3]) as one device tensor, optionally the metallic
 map and the normal map (stored values) of the principled BRDF, and optionally the
-camera pose (R_c row-major then t_c, 12 values; read back to the host for each call,
-its gradient is the interior part).
+camera pose (R_c row-major then t_c, 12 values; read back to the host for each call;
+its gradient is the interior part, plus the boundary part at the images of mesh edges
+when camera_edge_density > 0).
 """
 from __future__ import annotations
 
@@ -40,7 +41,7 @@ def _with_pose(cfg, pose):
 class DPCSRender(torch.autograd.Function):
     @staticmethod
     def forward(fctx, proj_image, albedo, roughness, specular, scalars, metallic, normal_map, camera_pose, ctx, scene,
-                cfg):
+                cfg, camera_edge_density):
         proj_image, albedo = proj_image.contiguous(), albedo.contiguous()
         roughness, specular, scalars = roughness.contiguous(), specular.contiguous(), scalars.contiguous()
         metallic = None if metallic is None else metallic.contiguous()
@@ -56,6 +57,7 @@ class DPCSRender(torch.autograd.Function):
         fctx.save_for_backward(proj_image, albedo, roughness, specular, scalars, metallic, normal_map, L, rec)
         fctx.ctx, fctx.scene, fctx.cfg = ctx, scene, cfg
         fctx.pose_like = None if camera_pose is None else camera_pose.detach()
+        fctx.edge_density = float(camera_edge_density)
         return out
 
     @staticmethod
@@ -71,15 +73,18 @@ class DPCSRender(torch.autograd.Function):
         d_cam = torch.zeros(12, dtype=torch.float32, device=proj_image.device) if (pose is not None and need[7]) else None
         dpcs.dpcs_render_vjp(fctx.ctx, fctx.scene, p, proj_image, grad_out.contiguous(), sample_radiance=L,
                              path_records=rec, d_proj_image=d_proj, d_albedo=d_alb, d_roughness=d_rough, d_specular=d_spec,
-                             d_scalars=d_scal, d_metallic=d_metal, d_normal_map=d_nmap, d_camera=d_cam)
+                             d_scalars=d_scal, d_metallic=d_metal, d_normal_map=d_nmap, d_camera=d_cam,
+                             camera_edge_density=fctx.edge_density if d_cam is not None else 0.0)
         if d_cam is not None:
             d_cam = d_cam.to(device=pose.device, dtype=pose.dtype)
-        return d_proj, d_alb, d_rough, d_spec, d_scal, d_metal, d_nmap, d_cam, None, None, None
+        return d_proj, d_alb, d_rough, d_spec, d_scal, d_metal, d_nmap, d_cam, None, None, None, None
 
 
 def render(ctx, scene, cfg, proj_image, albedo, roughness, specular, scalars, metallic=None, normal_map=None,
-           camera_pose=None):
+           camera_pose=None, camera_edge_density=0.0):
     """I_c = R(I_p, theta) (paper Eq. 7) with gradients for every tensor argument
-    (camera_pose: 12 values, R_c row-major then t_c, overriding cfg's camera)."""
+    (camera_pose: 12 values, R_c row-major then t_c, overriding cfg's camera;
+    camera_edge_density: points per pixel of edge length for the pose gradient's boundary
+    part, 0: interior part only)."""
     return DPCSRender.apply(proj_image, albedo, roughness, specular, scalars, metallic, normal_map, camera_pose, ctx,
-                            scene, cfg)
+                            scene, cfg, camera_edge_density)

@@ -22,7 +22,7 @@ FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-f
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-munsafe-fp-atomics", "-ffp-contract=off", "-Wall", "-Wno-unused-function",
          "-I", os.path.join(ROOT, "include")]
-SOURCES = ["bvh.hip", "bvh_ploc.hip", "bvh_sah.hip", "render.hip", "adjoint.hip", "image.hip", "runtime.cpp", "vjp.cpp", "camera.hip",
+SOURCES = ["bvh.hip", "bvh_ploc.hip", "bvh_sah.hip", "render.hip", "adjoint.hip", "image.hip", "runtime.cpp", "vjp.cpp", "camera.hip", "edges.hip",
            "server.cpp"]
 
 

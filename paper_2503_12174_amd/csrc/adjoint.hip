@@ -203,7 +203,7 @@ __device__ __forceinline__ bool put_ep_rec(const MapBins& mb, uint32_t slot, dou
 // Eq. 5 backward: y = g_c w E_c, I_c = y^gamma_c;  Eq. 12 backward per sample.
 // PIX_LANES lanes per pixel stride over its samples, reductions inside the lane group.
 __global__ void __launch_bounds__(BLOCK) k_adj_pixel(Queues q, AdjQueues aq, ReqDesc r, uint32_t p0, uint32_t p1,
-                                                     const float* sample_L) {
+                                                     const float* sample_L, float4* pix_dE) {
     const uint32_t p = p0 + (blockIdx.x * BLOCK + threadIdx.x) / PIX_LANES;
     const int lane = threadIdx.x & (PIX_LANES - 1);
     float acc[7] = {0, 0, 0, 0, 0, 0, 0};   // d gamma_c[3], d w[3], d threshold
@@ -249,6 +249,7 @@ __global__ void __launch_bounds__(BLOCK) k_adj_pixel(Queues q, AdjQueues aq, Req
                 }
             }
         }
+        if (pix_dE && lane == 0) pix_dE[p] = make_float4(dE[0], dE[1], dE[2], 0.f);
         for (int s = lane; s < r.spp; s += PIX_LANES) {
             const uint32_t g = p * (uint32_t)r.spp + (uint32_t)s;
             const uint32_t sid = g - r.g_base + r.sid_base;
@@ -1378,10 +1379,10 @@ static inline unsigned grid_cap(const Launch& l, int64_t n, int b) {
 }
 
 void launch_adj_pixel(const Launch& l, const Queues& q, const AdjQueues& aq, const ReqDesc& r, uint32_t p0,
-                      uint32_t p1, const float* sample_L) {
+                      uint32_t p1, const float* sample_L, float4* pix_dE) {
     if (p1 <= p0) return;
     const unsigned g = grid_of((int64_t)(p1 - p0) * PIX_LANES, BLOCK);
-    hipLaunchKernelGGL(k_adj_pixel, dim3(g), dim3(BLOCK), 0, l.st, q, aq, r, p0, p1, sample_L);
+    hipLaunchKernelGGL(k_adj_pixel, dim3(g), dim3(BLOCK), 0, l.st, q, aq, r, p0, p1, sample_L, pix_dE);
     if (r.d_part) hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, l.st, r.d_part, (int)g, 8, 7, r.d_acc);
 }
 size_t partial_floats(int64_t pixels_per_wave, int64_t proj_pixels) {

@@ -227,8 +227,9 @@ void launch_set_desc(const Launch& l, ReqDesc* table, int slot, const ReqDesc& r
 // floats of the scalar-partials buffer (ReqDesc::d_part) for waves of up to
 // pixels_per_wave pixels and a projector of proj_pixels pixels
 size_t partial_floats(int64_t pixels_per_wave, int64_t proj_pixels);
+// pix_dE (optional): per-pixel cotangent of the clipped pixel mean (rgb, -), whole image
 void launch_adj_pixel(const Launch& l, const Queues& q, const AdjQueues& aq, const ReqDesc& r, uint32_t p0,
-                      uint32_t p1, const float* sample_L);
+                      uint32_t p1, const float* sample_L, float4* pix_dE = nullptr);
 void launch_adj_raygen(const Launch& l, const Queues& q, const AdjQueues& aq, const ReqDesc& r, int slot, uint32_t g0,
                        uint32_t n);
 void launch_adj_shade(const Launch& l, const Queues& q, const AdjQueues& aq, int cur, int depth, const ReqDesc& uni,

@@ -683,7 +683,7 @@ extern "C" dpcs_status dpcs_scene_destroy(dpcs_scene s) {
     if (s->emission) (void)hipFree(s->emission);
     (void)hipFree(s->leaf_of_prim);
     for (void* q : {(void*)s->F, (void*)s->order, (void*)s->child, (void*)s->parent_int, (void*)s->parent_leaf,
-                    (void*)s->map4})
+                    (void*)s->map4, (void*)s->edges})
         if (q) (void)hipFree(q);
     delete s;
     return DPCS_OK;
@@ -709,6 +709,7 @@ extern "C" dpcs_status dpcs_scene_refit(dpcs_context ctx, dpcs_scene s, const fl
     RefitArgs a{positions, s->F, s->order, s->child, s->parent_int, s->parent_leaf, flags, box, s->nt,
                 s->nodes, s->tris, s->nodes4, s->map4, s->nodes4 ? s->nnodes4 : 0};
     if (!hip_ok(ctx, refit_bvh(ctx->stream, a), "scene refit")) return DPCS_E_DEVICE;
+    s->edges_valid = false;   // vertices may have met or parted: the edge table is welded again
     ctx->err.clear();
     return DPCS_OK;
 }
@@ -775,13 +776,13 @@ void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t 
 }
 
 void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, uint32_t a, uint32_t b,
-                  const float* sample_L) {
+                  const float* sample_L, float4* pix_dE) {
     Launch l{ctx->stream, ctx->grid_cap};
     const uint32_t n = (b - a) * (uint32_t)r.spp;
     r.g_base = a * (uint32_t)r.spp;
     r.sid_base = 0;
     int pr = prof_begin(ctx, DPCS_STAGE_ADJ_PIXEL);
-    launch_adj_pixel(l, q, aq, r, a, b, sample_L);
+    launch_adj_pixel(l, q, aq, r, a, b, sample_L, pix_dE);
     launch_cam_grad(l, q, aq, r, a, b);   // (no-op unless the camera-pose gradient is asked for)
     prof_end(ctx, pr, nullptr, b - a);
     launch_set_count(l, q.cnt, 0, n, 1, 4);

@@ -63,6 +63,11 @@ struct dpcs_scene_s {
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     int64_t bytes = 0;
     double build_ms = 0.0;
+    // edge table of the camera-pose gradient's boundary part (built on first use, again
+    // after a refit): per welded edge (leaf0, leaf1, corners, faces)
+    int4* edges = nullptr;
+    int64_t n_edges = 0;
+    bool edges_valid = false;
     std::atomic<int> refs{0};              // requests of a server that still use the scene
 };
 
@@ -104,6 +109,11 @@ void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t 
 // one launch wave of the path-replay adjoint over pixels [a, b) (q.L holds the samples
 // unless sample_L is given)
 void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, uint32_t a, uint32_t b,
-                  const float* sample_L);
+                  const float* sample_L, float4* pix_dE = nullptr);
+// the boundary part of the camera-pose gradient at the images of mesh edges, added into
+// dst[0..11] (R row-major, t); pix_dE: per-pixel cotangent of the clipped pixel means;
+// K the camera intrinsics; q's paths are reused (at most q.cap / 2 edge points per wave)
+dpcs_status camera_edge_term(dpcs_context ctx, dpcs_scene sc, const ReqDesc& r, const Queues& q, double density,
+                             const double K[9], const float4* pix_dE, float* dst);
 
 }  // namespace dpcs

@@ -30,6 +30,11 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     if (grads->d_camera && sample_radiance && !path_records)
         return fail(ctx, DPCS_E_UNSUPPORTED, "the camera-pose gradient replays path records: pass the forward's "
                                              "path_records with sample_radiance, or neither");
+    const double edge_density = grads->camera_edge_density;
+    if (!(edge_density >= 0.0 && edge_density <= 1e6))
+        return fail(ctx, DPCS_E_INVALID, "camera_edge_density must be in [0, 1e6]");
+    if (edge_density > 0.0 && !grads->d_camera)
+        return fail(ctx, DPCS_E_INVALID, "camera_edge_density needs d_camera");
     if (!hip_ok(ctx, hipSetDevice(ctx->device), "hipSetDevice")) return DPCS_E_DEVICE;
     r.grad_image = grad_image;
     dpcs_status st = DPCS_OK;
@@ -58,6 +63,13 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     if (grads->d_camera) {
         r.d_cam_part = (float*)scratch(ctx, "vjp.camera_partials", sizeof(float) * cam_partial_floats(ppw * r.spp), &st);
         if (!r.d_cam_part) return st;
+    }
+    // the boundary part of the camera-pose gradient needs every pixel's cotangent
+    float4* pix_dE = nullptr;
+    if (edge_density > 0.0) {
+        pix_dE = (float4*)scratch(ctx, "vjp.pixel_cotangents", sizeof(float4) * npix, &st);
+        if (!pix_dE) return st;
+        launch_zero(l, (float*)pix_dE, 4 * npix);
     }
     Queues q{};
     AdjQueues aq{};
@@ -94,7 +106,11 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
             r.rec = const_cast<uint32_t*>(path_records);   // read only in the adjoint
             r.rec_g0 = 0;
         }
-        adjoint_wave(ctx, q, aq, r, (uint32_t)a, b, sample_radiance);
+        adjoint_wave(ctx, q, aq, r, (uint32_t)a, b, sample_radiance, pix_dE);
+    }
+    if (pix_dE) {
+        st = camera_edge_term(ctx, scene, r, q, edge_density, params->camera.K, pix_dE, acc + 20);
+        if (st != DPCS_OK) return st;
     }
     launch_adj_finish(l, r, grads->d_proj_image, grads->d_albedo, grads->d_roughness, grads->d_specular,
                       grads->d_scalars, acc, grads->d_metallic, grads->d_normal_map);

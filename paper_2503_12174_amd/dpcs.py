@@ -67,7 +67,7 @@ class RenderAux(C.Structure):
 class Grads(C.Structure):
     _fields_ = [("d_proj_image", C.c_void_p), ("d_albedo", C.c_void_p), ("d_roughness", C.c_void_p),
                 ("d_specular", C.c_void_p), ("d_scalars", C.c_void_p), ("d_metallic", C.c_void_p),
-                ("d_normal_map", C.c_void_p), ("d_camera", C.c_void_p)]
+                ("d_normal_map", C.c_void_p), ("d_camera", C.c_void_p), ("camera_edge_density", C.c_double)]
 
 
 NUM_STAGES = 9
@@ -322,10 +322,13 @@ def dpcs_render_noalloc(ctx: Context, scene: Scene, params: RenderParams, proj_i
 
 def dpcs_render_vjp(ctx: Context, scene: Scene, params: RenderParams, proj_image, grad_image, sample_radiance=None,
                     d_proj_image=None, d_albedo=None, d_roughness=None, d_specular=None, d_scalars=None,
-                    path_records=None, d_metallic=None, d_normal_map=None, d_camera=None):
-    """d_camera: 12 floats, d/dR_c (row-major) then d/dt_c of the camera pose (interior part)."""
+                    path_records=None, d_metallic=None, d_normal_map=None, d_camera=None,
+                    camera_edge_density=0.0):
+    """d_camera: 12 floats, d/dR_c (row-major) then d/dt_c of the camera pose: the interior
+    part, plus the boundary part at the images of mesh edges when camera_edge_density > 0
+    (points per pixel of edge length)."""
     g = Grads(_ptr(d_proj_image), _ptr(d_albedo), _ptr(d_roughness), _ptr(d_specular), _ptr(d_scalars),
-              _ptr(d_metallic), _ptr(d_normal_map), _ptr(d_camera))
+              _ptr(d_metallic), _ptr(d_normal_map), _ptr(d_camera), float(camera_edge_density))
     return ctx.check(lib().dpcs_render_vjp(ctx.h, scene.h, C.byref(params), _ptr(proj_image), _ptr(grad_image),
                                            _ptr(sample_radiance), _ptr(path_records), C.byref(g)))
 

@@ -105,9 +105,10 @@ def pose_from(omega, dt, R0, t0):
 
 
 def refine_camera(ctx, scene, cfg, images, targets, albedo, roughness, specular, steps=40, lr=2e-3, base_seed=0,
-                  scalars=None):
-    """Refine the camera pose about cfg.camera so renderings of `images` match `targets`
-    (the interior gradient of the pose: suited to the minor corrections the paper makes).
+                  scalars=None, edge_density=4.0):
+    """Refine the camera pose about cfg.camera so renderings of `images` match `targets`.
+    The pose gradient has its interior part and, with edge_density > 0 (points per pixel of
+    edge length), the boundary part where silhouettes, creases and seams move in the image.
     Returns (R, t) and the losses."""
     omega = torch.zeros(3, dtype=torch.float64, requires_grad=True)
     dt = torch.zeros(3, dtype=torch.float64, requires_grad=True)
@@ -121,7 +122,8 @@ def refine_camera(ctx, scene, cfg, images, targets, albedo, roughness, specular,
         pose = pose_from(omega, dt, R0, t0)
         loss = 0.0
         for ip, tgt in zip(images, targets):
-            out = render(ctx, scene, c, ip, albedo, roughness, specular, scal, camera_pose=pose.float())
+            out = render(ctx, scene, c, ip, albedo, roughness, specular, scal, camera_pose=pose.float(),
+                         camera_edge_density=edge_density)
             loss = loss + ((out - tgt) ** 2).mean()
         loss = loss / len(images)
         opt.zero_grad()

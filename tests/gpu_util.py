@@ -104,13 +104,14 @@ def compare_forward(gpu, ref, pixels=None, gain=1.0, rtol=1e-4, min_clean=0.95):
 VJP_MODES = ("own", "records", "retrace")
 
 
-def run_vjp(run: GpuRun, G, sample_radiance=None, mode="own", camera=False):
+def run_vjp(run: GpuRun, G, sample_radiance=None, mode="own", camera=False, edge_density=0.0):
     """dpcs_render_vjp through the C ABI; returns numpy gradients keyed like the oracle's.
 
     mode "own": the call recomputes the forward with its own path records;
     "records": a dpcs_render call first keeps per-sample radiance and path records,
     which the VJP replays without tracing; "retrace": the forward keeps per-sample
-    radiance only and the VJP traces every bounce and shadow ray again."""
+    radiance only and the VJP traces every bounce and shadow ray again.  edge_density > 0
+    adds the boundary part of the camera-pose gradient."""
     import torch
     from paper_2503_12174_amd import dpcs
     p = run.params
@@ -135,7 +136,8 @@ def run_vjp(run: GpuRun, G, sample_radiance=None, mode="own", camera=False):
         dpcs.dpcs_render(run.c, run.scene, p, run.proj, img, sample_radiance=sample_radiance, path_records=rec)
     dpcs.dpcs_render_vjp(run.c, run.scene, p, run.proj, g, sample_radiance=sample_radiance, path_records=rec,
                          d_proj_image=out["Ip"], d_albedo=out["albedo"], d_roughness=out["roughness"],
-                         d_specular=out["specular"], d_scalars=out["scalars"], **ext)
+                         d_specular=out["specular"], d_scalars=out["scalars"], camera_edge_density=edge_density,
+                         **ext)
     run.c.synchronize()
     res = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
     s = res.pop("scalars")
