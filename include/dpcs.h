@@ -417,14 +417,16 @@ DPCS_API dpcs_status dpcs_server_submit(dpcs_server srv, const dpcs_request* req
  * to completion on the device; latency_ms may be NULL).  Returns the count. */
 DPCS_API int32_t dpcs_server_poll(dpcs_server srv, uint64_t* done_ids, int32_t* done_status, double* latency_ms,
                          int32_t max);
-/* Counters (out: 13 int64 on the host): [0] submitted, [1] completed, [2] rejected,
+/* Counters (out: 14 int64 on the host): [0] submitted, [1] completed, [2] rejected,
  * [3] active, [4] queued, [5] launch waves, [6] samples traced, [7] peak admitted bytes,
  * [8] waves whose compensation segments replayed path records, [9] waves whose
- * compensation segments re-traced (their paths did not fit the wave's records), and
- * the latency of the completed requests summed in microseconds, in three parts:
- * [10] submit to admission (queued for memory or a slot), [11] admission to the launch
- * of the request's first wave, [12] from there to completion on the device. */
-DPCS_API dpcs_status dpcs_server_stats(dpcs_server srv, int64_t* out13);
+ * compensation segments re-traced (their paths did not fit the wave's records), the
+ * latency of the completed requests summed in microseconds, in three parts: [10] submit
+ * to admission (queued for memory or a slot), [11] admission to the launch of the
+ * request's first wave, [12] from there to completion on the device; [13] waves whose
+ * compensation paths, all of one request, binned their map cotangents (sorted by tile,
+ * summed in fixed point) instead of scattering them with atomics. */
+DPCS_API dpcs_status dpcs_server_stats(dpcs_server srv, int64_t* out14);
 /* Waits for every admitted request, then stops the loop. */
 DPCS_API dpcs_status dpcs_server_destroy(dpcs_server srv);
 

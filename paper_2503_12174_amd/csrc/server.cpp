@@ -98,6 +98,50 @@ struct Seg {
     uint32_t a, b;   // pixels
 };
 
+// Binning buffers of the loop's compensation waves (map cotangents sorted by tile and
+// summed in fixed point, as a single request's VJP does), carved for the largest binned
+// map (1024 x 1024: 16-texel tiles, 4096 of them); a wave binds them to its request's
+// map size.  Layout: records, sorted records, stage blocks, count, bins, chunk row bases.
+size_t loop_bins_bytes(int64_t cap, int C, int RS) {
+    const size_t rec = 4 * (size_t)RS * cap;
+    const size_t stage = 8 * (size_t)((cap + ACC_CHUNK - 1) / ACC_CHUNK + MAP_MAX_BINS) * (MAP_MAX_T + 1) *
+                         (MAP_MAX_T + 1) * C;
+    const size_t rows = 4 * (size_t)((cap + BIN_CHUNK - 1) / BIN_CHUNK) * MAP_MAX_BINS;
+    auto up = [](size_t n) { return (n + 255) & ~size_t(255); };
+    return 2 * up(rec) + up(stage) + up(4) + up(4 * (3 * (size_t)MAP_MAX_BINS + 2)) + up(rows);
+}
+
+// the buffers at base as bins of a W x H map (false: the map is too large to bin)
+bool loop_bins_view(char* base, int64_t cap, int C, int RS, int W, int H, MapBins& mb) {
+    mb = MapBins{};
+    int T = 0, nbx = 0, nby = 0;
+    if (!base || !map_tiling(W, H, T, nbx, nby)) return false;
+    auto up = [](size_t n) { return (n + 255) & ~size_t(255); };
+    const size_t rec = 4 * (size_t)RS * cap;
+    const size_t stage = 8 * (size_t)((cap + ACC_CHUNK - 1) / ACC_CHUNK + MAP_MAX_BINS) * (MAP_MAX_T + 1) *
+                         (MAP_MAX_T + 1) * C;
+    char* b = base;
+    mb.rec = (float*)b;
+    b += up(rec);
+    mb.sorted = (float*)b;
+    b += up(rec);
+    mb.stage = (long long*)b;
+    b += up(stage);
+    mb.count = (uint32_t*)b;
+    b += up(4);
+    mb.bins = (uint32_t*)b;
+    b += up(4 * (3 * (size_t)MAP_MAX_BINS + 2));
+    mb.rowbase = (uint32_t*)b;
+    mb.cap = cap;
+    mb.W = W;
+    mb.H = H;
+    mb.T = T;
+    mb.nbx = nbx;
+    mb.nby = nby;
+    mb.nb = nbx * nby;
+    return true;
+}
+
 size_t request_bytes(const ReqDesc& r, bool adjoint) {
     const size_t nEp = (size_t)r.Wp * r.Hp, nT = (size_t)r.tw * r.th;
     size_t b = 16 * nEp + 256 + 16 * nT + 256;          // E_p, packed maps
@@ -121,6 +165,10 @@ struct dpcs_server_s {
     AdjQueues aq{};
     uint32_t* rec = nullptr;     // path records of a wave's compensation segments
     int64_t rec_cap = 0;         // words
+    char* tex_bins = nullptr;    // binning buffers (texture maps, E_p) of one-request
+    char* ep_bins = nullptr;     // compensation waves, or null: every wave scatters directly
+    int64_t tex_bins_cap = 0, ep_bins_cap = 0;
+    int64_t st_binned = 0;       // waves whose compensation gradients were binned
     std::vector<int> free_slots;
     std::mutex mu;
     std::condition_variable cv;
@@ -276,6 +324,26 @@ void dpcs_server_s::wave(Launch& l) {
     for (const Seg& s : segs) launch_finalize(l, q, s.q->r, table, s.q->slot, s.a, s.b);
     // adjoint replay of the compensation-step segments (a dense prefix of the wave)
     if (any_adj) {
+        // compensation paths of one request, replayed from records, with maps the binning
+        // buffers hold: the replay runs in the one-request form and its map cotangents are
+        // binned and flushed into the request's maps like a single VJP's, instead of one
+        // global atomic per texel and channel
+        Req* binq = nullptr;
+        AdjQueues ab = aq;
+        if (replay) {
+            for (const Seg& s : segs)
+                if (s.q->adjoint) binq = binq == nullptr || binq == s.q ? s.q : (Req*)-1;
+            if (binq == (Req*)-1 || !loop_bins_view(tex_bins, tex_bins_cap, 5, 8, binq->r.tw, binq->r.th, ab.tb) ||
+                !loop_bins_view(ep_bins, ep_bins_cap, 3, 6, binq->r.Wp, binq->r.Hp, ab.eb)) {
+                binq = nullptr;
+            } else {   // a fresh histogram for this map size
+                launch_zero(l, (float*)ab.tb.count, 1);
+                launch_zero(l, (float*)ab.tb.bins, 3 * (int64_t)MAP_MAX_BINS + 2);
+                launch_zero(l, (float*)ab.eb.count, 1);
+                launch_zero(l, (float*)ab.eb.bins, 3 * (int64_t)MAP_MAX_BINS + 2);
+                ++st_binned;
+            }
+        }
         for (const Seg& s : segs)
             if (s.q->adjoint) launch_adj_pixel(l, q, aq, s.q->r, s.a, s.b, nullptr);
         launch_set_count(l, q.cnt, 0, (uint32_t)n_adj, 1, 4);
@@ -284,7 +352,10 @@ void dpcs_server_s::wave(Launch& l) {
         cur = 0;
         for (int d = 0; d < max_depth; ++d) {
             launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
-            if (replay) {
+            if (binq) {
+                launch_adj_replay(l, q, ab, cur, d, binq->r, nullptr, n_adj);
+                if ((d + 1) % BIN_DEPTHS == 0 || d == max_depth - 1) launch_map_flush(l, ab, binq->r);
+            } else if (replay) {
                 launch_adj_replay(l, q, aq, cur, d, any, table, n_adj);
             } else {
                 launch_trace(l, q, cur, any, nullptr, n_adj);
@@ -423,13 +494,26 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
         delete s;
         return fail(ctx, DPCS_E_INVALID, "memory budget smaller than the shared queues of one wave");
     }
+    // binning buffers for one-request compensation waves (records of up to BIN_DEPTHS + 1
+    // texture and BIN_DEPTHS E_p entries per path between flushes), when they take at most
+    // a quarter of the budget (~1.2 GB for 2^21-path waves)
+    s->tex_bins_cap = s->lat_cap * (BIN_DEPTHS + 1);
+    s->ep_bins_cap = s->lat_cap * BIN_DEPTHS;
+    const size_t bins_bytes = loop_bins_bytes(s->tex_bins_cap, 5, 8) + loop_bins_bytes(s->ep_bins_cap, 3, 6);
+    const bool binning = bins_bytes <= s->budget / 4 && s->shared_bytes + bins_bytes < s->budget;
+    if (binning) s->shared_bytes += bins_bytes;
     const size_t arena_bytes = s->budget - s->shared_bytes;
     bool ok = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipMalloc((void**)&s->table, sizeof(ReqDesc) * max_slots) == hipSuccess;
     ok = ok && hipMalloc(&s->qbuf, qbytes) == hipSuccess;
     ok = ok && hipMalloc((void**)&s->arena_base, arena_bytes) == hipSuccess;
+    if (ok && binning) {
+        ok = hipMalloc((void**)&s->tex_bins, bins_bytes) == hipSuccess;
+        s->ep_bins = ok ? s->tex_bins + loop_bins_bytes(s->tex_bins_cap, 5, 8) : nullptr;
+    }
     if (!ok) {
         (void)hipGetLastError();
+        if (s->arena_base) (void)hipFree(s->arena_base);
         if (s->table) (void)hipFree(s->table);
         if (s->qbuf) (void)hipFree(s->qbuf);
         if (s->st) (void)hipStreamDestroy(s->st);
@@ -467,8 +551,8 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     s->q.hit = (int*)take(4 * c);
     s->q.L = (float4*)take(16 * c);
     s->aq.delta = (float4*)take(16 * c);
-    s->aq.tb = MapBins{};   // the request loop replays by tracing and scatters directly
-    s->aq.eb = MapBins{};
+    s->aq.tb = MapBins{};   // several requests' compensation paths: direct scatter (a
+    s->aq.eb = MapBins{};   // wave of one request binds the binning buffers instead)
     s->q.cnt = (uint32_t*)take(16);
     s->q.spill = (int*)take(spill_bytes);
     s->q.trace_blocks = tblocks;
@@ -560,7 +644,7 @@ extern "C" int32_t dpcs_server_poll(dpcs_server s, uint64_t* ids, int32_t* statu
     return n;
 }
 
-extern "C" dpcs_status dpcs_server_stats(dpcs_server s, int64_t* o) {   // o: 13 counters
+extern "C" dpcs_status dpcs_server_stats(dpcs_server s, int64_t* o) {   // o: 14 counters
     if (!s || !o) return DPCS_E_INVALID;
     std::lock_guard<std::mutex> lk(s->mu);
     o[0] = s->st_submitted;
@@ -576,6 +660,7 @@ extern "C" dpcs_status dpcs_server_stats(dpcs_server s, int64_t* o) {   // o: 13
     o[10] = s->st_wait_us;
     o[11] = s->st_admit_us;
     o[12] = s->st_run_us;
+    o[13] = s->st_binned;
     return DPCS_OK;
 }
 
@@ -592,6 +677,7 @@ extern "C" dpcs_status dpcs_server_destroy(dpcs_server s) {
     (void)hipFree(s->arena_base);
     (void)hipFree(s->qbuf);
     (void)hipFree(s->table);
+    if (s->tex_bins) (void)hipFree(s->tex_bins);
     (void)hipStreamDestroy(s->st);
     const bool failed = !s->err.empty();
     delete s;

@@ -424,10 +424,10 @@ class Server:
         return out
 
     def stats(self) -> dict:
-        v = (C.c_int64 * 13)()
+        v = (C.c_int64 * 14)()
         self.ctx.check(lib().dpcs_server_stats(self.h, v))
         keys = ["submitted", "completed", "rejected", "active", "queued", "waves", "samples", "peak_bytes",
-                "replayed_waves", "retraced_waves", "wait_us", "admit_us", "run_us"]
+                "replayed_waves", "retraced_waves", "wait_us", "admit_us", "run_us", "binned_waves"]
         return dict(zip(keys, [int(x) for x in v]))
 
     def close(self):

@@ -89,6 +89,43 @@ def test_results_alone_equal_results_in_the_mix():
                 np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-5 * scale, err_msg=f"request {k} {name}")
 
 
+def test_one_request_waves_bin_their_gradients():
+    """Compensation steps submitted one at a time run alone in their waves: their map
+    cotangents are binned and flushed (no atomics), and the gradients equal the plain
+    VJP's."""
+    import torch
+    from paper_2503_12174_amd import dpcs
+    scenes, albedo, rough, spec = _setup(1)
+    rng = np.random.default_rng(5)
+    srv = dpcs.Server(ctx(), budget_bytes=8 << 30, max_slots=4)
+    for k in range(3):
+        w, img = _request(2 * k + 1, rng, albedo, rough, spec)
+        w.max_depth = 2 + k   # depths 2, 3 and 4
+        p = dpcs.params_from(w, albedo, rough, spec)
+        ip = dev(img, torch.float32)
+        out = torch.zeros((w.camera.height, w.camera.width, 3), device="cuda")
+        target = dev(synth.blob_image(w.camera.height, w.camera.width, 70 + k, lo=0.1, hi=0.9), torch.float32)
+        grads = dict(d_proj_image=torch.zeros_like(ip), d_albedo=torch.zeros_like(albedo),
+                     d_roughness=torch.zeros_like(rough), d_specular=torch.zeros_like(spec),
+                     d_scalars=torch.zeros(18, device="cuda"))
+        before = srv.stats()["binned_waves"]
+        assert srv.submit(k, scenes[0], p, ip, out, target=target, grads=grads) == dpcs.OK
+        done = _wait(srv, 1)
+        assert len(done) == 1 and done[0][1] == dpcs.OK
+        assert srv.stats()["binned_waves"] > before
+        L = torch.zeros((w.camera.height, w.camera.width, w.spp, 3), device="cuda")
+        alone = torch.zeros_like(out)
+        dpcs.dpcs_render(ctx(), scenes[0], p, ip, alone, sample_radiance=L)
+        G = 2.0 * (alone - target) / (3 * w.camera.height * w.camera.width)
+        g2 = {name: torch.zeros_like(v) for name, v in grads.items()}
+        dpcs.dpcs_render_vjp(ctx(), scenes[0], p, ip, G.contiguous(), sample_radiance=L, **g2)
+        ctx().synchronize()
+        for name in grads:
+            a, b = grads[name].cpu().numpy(), g2[name].cpu().numpy()
+            np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-5 * (np.abs(b).max() + 1e-30), err_msg=f"{k} {name}")
+    srv.close()
+
+
 def test_admission_by_memory_budget():
     import torch
     from paper_2503_12174_amd import dpcs
