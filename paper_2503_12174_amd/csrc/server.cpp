@@ -423,7 +423,10 @@ void dpcs_server_s::run() {
             hipEvent_t e = ev_pool[ev_next++ % ev_pool.size()];
             (void)hipEventRecord(e, st);
             inflight.push_back(e);
-            while (inflight.size() > 2) {   // keep at most two waves queued on the device
+            // one wave runs while the next waits on the device: the host builds a wave
+            // with whatever arrived meanwhile as soon as the running one ends (two queued
+            // waves measured the same throughput and 1-2 ms more p50 latency)
+            while (inflight.size() > 1) {
                 (void)hipEventSynchronize(inflight.front());
                 inflight.pop_front();
             }
