@@ -287,21 +287,22 @@ __global__ void __launch_bounds__(BLOCK) k_adj_pixel(Queues q, AdjQueues aq, Req
 
 // dst[k] += the sum over nb workgroup partials part[b * stride + k], k < nv, in a fixed
 // order (FP64), so the scalar gradients are the same on every run
+// one workgroup per value k < nv (grid nv): dst[k] += the sum of the nb partials of k, in
+// a fixed order (per thread a strided run, then a tree)
 __global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ part, int nb, int stride, int nv,
                                                       float* __restrict__ dst) {
     __shared__ double red[256];
-    for (int k = 0; k < nv; ++k) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nb; b += 256) s += part[(size_t)b * stride + k];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0 && red[0] != 0.0) dst[k] += (float)red[0];
+    const int k = blockIdx.x;
+    if (k >= nv) return;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) s += part[(size_t)b * stride + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
+    if (threadIdx.x == 0 && red[0] != 0.0) dst[k] += (float)red[0];
 }
 
 // replay camera rays at queue index = batch sample index (the depth-0 shading takes
@@ -1383,7 +1384,7 @@ void launch_adj_pixel(const Launch& l, const Queues& q, const AdjQueues& aq, con
     if (p1 <= p0) return;
     const unsigned g = grid_of((int64_t)(p1 - p0) * PIX_LANES, BLOCK);
     hipLaunchKernelGGL(k_adj_pixel, dim3(g), dim3(BLOCK), 0, l.st, q, aq, r, p0, p1, sample_L, pix_dE);
-    if (r.d_part) hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, l.st, r.d_part, (int)g, 8, 7, r.d_acc);
+    if (r.d_part) hipLaunchKernelGGL(k_sum_partials, dim3(7), dim3(256), 0, l.st, r.d_part, (int)g, 8, 7, r.d_acc);
 }
 size_t partial_floats(int64_t pixels_per_wave, int64_t proj_pixels) {
     return std::max<size_t>(8 * (size_t)grid_of(pixels_per_wave * PIX_LANES, BLOCK), 12 * (size_t)grid_of(proj_pixels, BLOCK));
@@ -1440,7 +1441,7 @@ static void flush_one(const Launch& l, const MapBins& mb, float* out, int stride
                        stride);
 }
 void launch_sum_partials(const Launch& l, const float* part, int nb, int stride, int nv, float* dst) {
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, l.st, part, nb, stride, nv, dst);
+    hipLaunchKernelGGL(k_sum_partials, dim3(nv), dim3(256), 0, l.st, part, nb, stride, nv, dst);
 }
 void launch_map_flush(const Launch& l, const AdjQueues& aq, const ReqDesc& r) {
     if (aq.tb.rec && r.d_tex) {
@@ -1453,7 +1454,7 @@ void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* 
                        float* d_spec, float* d_scalars, float* acc, float* d_metal, float* d_nmap) {
     const unsigned g = grid_of((int64_t)r.Wp * r.Hp, BLOCK);
     hipLaunchKernelGGL(k_adj_prf, dim3(g), dim3(BLOCK), 0, l.st, r, d_proj, acc);
-    if (r.d_part) hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, l.st, r.d_part, (int)g, 12, 12, acc + 8);
+    if (r.d_part) hipLaunchKernelGGL(k_sum_partials, dim3(12), dim3(256), 0, l.st, r.d_part, (int)g, 12, 12, acc + 8);
     if (d_albedo || d_rough || d_spec || d_metal || d_nmap)
         hipLaunchKernelGGL(k_adj_maps, dim3(grid_of((int64_t)r.tw * r.th, 256)), dim3(256), 0, l.st, r, d_albedo,
                            d_rough, d_spec, d_metal, d_nmap);

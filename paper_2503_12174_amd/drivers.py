@@ -134,9 +134,39 @@ def refine_camera(ctx, scene, cfg, images, targets, albedo, roughness, specular,
     return (pose[:9].reshape(3, 3), pose[9:]), losses
 
 
+def _l2_step_batched(srv, scene, c, images, targets, alb, rough, spec, scal, first_id):
+    """Forward + VJP of the mean L2 loss over all (image, target) pairs as compensation
+    requests of the request loop, which packs them into shared launch waves; the maps'
+    and scalars' gradients (averaged over the pairs) land in their .grad.  Returns the loss."""
+    p = dpcs.params_from(c, alb.detach(), rough.detach(), spec.detach(), device_scalars=scal.detach())
+    outs, grads = [], []
+    for b, (ip, tgt) in enumerate(zip(images, targets)):
+        out = torch.empty_like(tgt)
+        g = dict(d_albedo=torch.zeros_like(alb), d_roughness=torch.zeros_like(rough), d_specular=torch.zeros_like(spec),
+                 d_scalars=torch.zeros_like(scal))
+        st = srv.submit(first_id + b, scene, p, ip.contiguous(), out, target=tgt.contiguous(), grads=g)
+        if st != dpcs.OK:
+            raise dpcs.DpcsError(f"fit step request {b}: status {st}")
+        outs.append(out)
+        grads.append(g)
+    done = 0
+    while done < len(images):
+        for _, st, _ in srv.poll():
+            if st != dpcs.OK:
+                raise dpcs.DpcsError(f"fit step request failed: status {st}")
+            done += 1
+    n = float(len(images))
+    for t, key in ((alb, "d_albedo"), (rough, "d_roughness"), (spec, "d_specular"), (scal, "d_scalars")):
+        t.grad = sum(g[key] for g in grads) / n
+    return sum(((o - t) ** 2).mean() for o, t in zip(outs, targets)) / n
+
+
 def fit(ctx, scene, cfg, images, targets, steps=50, lr=0.02, base_seed=0, clamp_gamma_p=True, init=None,
-        objective="l2", tv_weight=0.0, denoise: Ob.DenoiseConfig | None = None):
-    """Fit albedo/roughness/specular maps and the 18 response scalars to (image, target) pairs."""
+        objective="l2", tv_weight=0.0, denoise: Ob.DenoiseConfig | None = None, batched=True):
+    """Fit albedo/roughness/specular maps and the 18 response scalars to (image, target) pairs.
+    With the L2 objective and several pairs (batched=True), each step runs the pairs as
+    compensation requests of one request loop, so their samples share launch waves
+    instead of one render + VJP per pair; the same Philox samples either way."""
     if objective not in ("l2", "paper"):
         raise ValueError("objective must be 'l2' or 'paper'")
     th, tw = cfg.albedo.shape[:2]
@@ -148,29 +178,60 @@ def fit(ctx, scene, cfg, images, targets, steps=50, lr=0.02, base_seed=0, clamp_
     scal = scalars_from(cfg).clone().requires_grad_(True)
     opt = torch.optim.Adam([alb, rough, spec, scal], lr=lr)
     losses = []
-    for k in range(steps):
-        c = copy.copy(cfg)
-        c.seed = base_seed + k
-        loss = 0.0
-        guide = None
-        if objective == "paper":   # guide features under the current albedo (a constant of D)
-            guide = Ob.gbuffer(ctx, scene, dpcs.params_from(c, alb.detach(), rough.detach(), spec.detach()))
-        for ip, tgt in zip(images, targets):
-            out = render(ctx, scene, c, ip, alb, rough, spec, scal)
-            if objective == "paper":
-                loss = loss + Ob.l1(ctx, Ob.denoise(ctx, out, guide, denoise), tgt)
-            else:
-                loss = loss + ((out - tgt) ** 2).mean()
-        loss = loss / len(images)
-        if tv_weight:
-            loss = loss + tv_weight * (Ob.tv(ctx, alb) + Ob.tv(ctx, rough) + Ob.tv(ctx, spec))
-        opt.zero_grad()
-        loss.backward()
-        opt.step()
-        with torch.no_grad():
-            alb.clamp_(0.0, 1.0)
-            rough.clamp_(0.05, 1.0)
-            spec.clamp_(0.0, 1.0)
-        project_constraints(scal, clamp_gamma_p)
-        losses.append(float(loss.detach()))
+    srv = None
+    if batched and objective == "l2" and len(images) > 1:
+        paths = sum(int(t.shape[0]) * int(t.shape[1]) for t in targets) * cfg.spp
+        # queues for every pair's paths in one wave (~600 B per path) within a quarter of the budget
+        srv = dpcs.Server(ctx, budget_bytes=max(1 << 30, 4 * 640 * paths + (256 << 20)), max_slots=len(images))
+    try:
+        for k in range(steps):
+            c = copy.copy(cfg)
+            c.seed = base_seed + k
+            if srv is not None:
+                opt.zero_grad()
+                loss = _l2_step_batched(srv, scene, c, images, targets, alb, rough, spec, scal, k * len(images))
+                if tv_weight:
+                    tv = tv_weight * (Ob.tv(ctx, alb) + Ob.tv(ctx, rough) + Ob.tv(ctx, spec))
+                    tv.backward()
+                    loss = loss + tv.detach()
+                opt.step()
+                with torch.no_grad():
+                    alb.clamp_(0.0, 1.0)
+                    rough.clamp_(0.05, 1.0)
+                    spec.clamp_(0.0, 1.0)
+                project_constraints(scal, clamp_gamma_p)
+                losses.append(float(loss))
+                continue
+            _fit_step(ctx, scene, c, images, targets, alb, rough, spec, scal, opt, objective, tv_weight, denoise,
+                      clamp_gamma_p, losses)
+    finally:
+        if srv is not None:
+            srv.close()
     return dict(albedo=alb.detach(), roughness=rough.detach(), specular=spec.detach(), scalars=scal.detach()), losses
+
+
+def _fit_step(ctx, scene, c, images, targets, alb, rough, spec, scal, opt, objective, tv_weight, denoise,
+              clamp_gamma_p, losses):
+    """One step of fit, one autograd render + VJP per pair."""
+    loss = 0.0
+    guide = None
+    if objective == "paper":   # guide features under the current albedo (a constant of D)
+        guide = Ob.gbuffer(ctx, scene, dpcs.params_from(c, alb.detach(), rough.detach(), spec.detach()))
+    for ip, tgt in zip(images, targets):
+        out = render(ctx, scene, c, ip, alb, rough, spec, scal)
+        if objective == "paper":
+            loss = loss + Ob.l1(ctx, Ob.denoise(ctx, out, guide, denoise), tgt)
+        else:
+            loss = loss + ((out - tgt) ** 2).mean()
+    loss = loss / len(images)
+    if tv_weight:
+        loss = loss + tv_weight * (Ob.tv(ctx, alb) + Ob.tv(ctx, rough) + Ob.tv(ctx, spec))
+    opt.zero_grad()
+    loss.backward()
+    opt.step()
+    with torch.no_grad():
+        alb.clamp_(0.0, 1.0)
+        rough.clamp_(0.05, 1.0)
+        spec.clamp_(0.0, 1.0)
+    project_constraints(scal, clamp_gamma_p)
+    losses.append(float(loss.detach()))

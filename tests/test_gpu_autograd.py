@@ -87,6 +87,26 @@ def test_scene_fit_reduces_the_loss_on_oracle_targets():
     assert losses[-1] < 0.5 * losses[0], losses
 
 
+def test_batched_fit_steps_equal_one_render_per_pair():
+    """The L2 fit with its pairs batched through the request loop takes the same steps as
+    one autograd render + VJP per pair (same Philox samples; the gradients differ only by
+    the order of float atomics), with and without the TV term."""
+    import torch
+    from paper_2503_12174_amd import drivers, dpcs
+    imgs, targets = _fit_problem()
+    w = synth.fit_scene(spp=8)
+    scene = dpcs.Scene(ctx(), w.mesh)
+    f = torch.float32
+    for tv in (0.0, 0.02):
+        a, la = drivers.fit(ctx(), scene, w, [dev(i, f) for i in imgs], [dev(t, f) for t in targets], steps=4, lr=0.03,
+                            clamp_gamma_p=False, tv_weight=tv, batched=True)
+        b, lb = drivers.fit(ctx(), scene, w, [dev(i, f) for i in imgs], [dev(t, f) for t in targets], steps=4, lr=0.03,
+                            clamp_gamma_p=False, tv_weight=tv, batched=False)
+        np.testing.assert_allclose(la, lb, rtol=1e-5)
+        for k in ("albedo", "roughness", "specular", "scalars"):
+            np.testing.assert_allclose(a[k].cpu().numpy(), b[k].cpu().numpy(), rtol=0, atol=1e-4, err_msg=k)
+
+
 def test_scene_fit_with_the_papers_objective():
     """Eq. 9 as written: L1 of denoised renderings (Eq. 11) + lambda_reg L(m).  The loss
     falls, and a large lambda_reg leaves smoother maps than lambda_reg = 0."""
