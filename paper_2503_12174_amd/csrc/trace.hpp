@@ -192,7 +192,8 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
                 vis.tri();
                 load_tri(tris, leaf, v0, v1, v2, prim);
                 float t;
-                if (prim != skip && wt_hit(wr, v0, v1, v2, t) && t > tmin &&
+                const bool hit = wt_hit(wr, v0, v1, v2, t);   // the skip test after it (one load)
+                if (hit & (prim != skip) & (t > tmin) &&
                     (t < best_t || (t == best_t && best_leaf >= 0 && prim < best_prim))) {
                     best_t = t;
                     best_prim = prim;
@@ -405,7 +406,11 @@ __device__ __forceinline__ void trav4_visit(Trav4& s, const float4* __restrict__
         vis.tri();
         load_tri(tris, leaf, v0, v1, v2, prim);
         float t;
-        if (prim == s.skip || !wt_hit(s.wr, v0, v1, v2, t) || !(t > s.tmin)) return;
+        // the triangle left is rejected after the test, not before it: checked first, the
+        // prim id was loaded alone and the vertices only after the compare (two dependent
+        // round trips to memory per test)
+        const bool hit = wt_hit(s.wr, v0, v1, v2, t);
+        if (!hit | !(t > s.tmin) | (prim == s.skip)) return;
         bool take = t < s.best_t;
         if constexpr (!ANY) {
             // equal t: the smaller original index wins (the current best's index is read
