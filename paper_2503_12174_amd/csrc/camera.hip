@@ -1,13 +1,15 @@
 // camera.hip -- the camera-pose part of the VJP: d loss / d (R_c, t_c) (Sec. 3.2, theta
 // holds the camera rotation and translation for refinement).
 //
-// Interior part only: per camera sample with a first hit, the camera vertex's radiance
+// The interior part (the boundary part, at the images of mesh edges, is edges.hip): per
+// camera sample with a first hit, the camera vertex's radiance
 // V(x, wo) -- projector next event, environment next event and the bounce factor, each as
 // the forward evaluated it, with every decision (visibilities, the path going on), the
 // sampled environment and bounce directions and everything beyond the first vertex held at
 // the forward's values -- is differentiated w.r.t. the hit point x (within the triangle's
-// plane) and the direction to the camera wo, by central differences in FP64 along two
-// in-plane and two tangent directions.  The camera geometry is then chained analytically:
+// plane) and the direction to the camera wo, by forward differences in FP64 along two
+// in-plane and two tangent directions (the point's texture and projector lookups are
+// reused for the direction steps).  The camera geometry is then chained analytically:
 // the ray o = -R^T t, d = q / |q| with q = R^T K^-1 (px, py, 1) meets the plane at
 // x = o + tau d, so dx = P (do + tau dd) with P = I - d n^T / (n.d), dwo = -dd and
 // dd = (I - d d^T) dq / |q|.  The bounce's remaining radiance is recovered from the
@@ -30,8 +32,14 @@ struct CamFrozen {
     D3 W;            // R_1 / pdf per channel: the bounce factor's weight
 };
 
-// the camera vertex's terms at hit point x (in the triangle's plane) seen along wo
-__device__ __forceinline__ void cam_terms(const ReqDesc& r, const CamFrozen& z, D3 x, D3 wo, D3& nee, D3& bnc) {
+// what the camera vertex's terms read at hit point x (in the triangle's plane): material,
+// shading normal and the projector's direction, irradiance and falloff
+struct CamSurf {
+    D3 alb, ns, wp, E;
+    double rough, spec, metal, g;   // g = 1 / (cos^3 alpha d^2)
+};
+
+__device__ __forceinline__ CamSurf cam_surface(const ReqDesc& r, const CamFrozen& z, D3 x) {
     Surf s;
     V3 f0, f1, f2;
     load_tri(r.tris, z.leaf, f0, f1, f2, s.prim);
@@ -42,24 +50,25 @@ __device__ __forceinline__ void cam_terms(const ReqDesc& r, const CamFrozen& z, 
     const double b1 = (a22 * r1 - a12 * r2) * inv, b2 = (a11 * r2 - a12 * r1) * inv, b0 = 1.0 - b1 - b2;
     s.x = x;
     s.n = z.n;
-    s.wo = wo;
     const float4 ua = r.tri_uv[2 * z.leaf], ub = r.tri_uv[2 * z.leaf + 1];
     s.u = b0 * ua.x + b1 * ua.z + b2 * ub.x;
     s.v = b0 * ua.y + b1 * ua.w + b2 * ub.y;
     s.tb = bilinear(s.u * r.tw - 0.5, s.v * r.th - 0.5, r.tw, r.th);
     const D4 t4 = fetch4(r.tex4, s.tb);
-    s.alb = d3(t4.x, t4.y, t4.z);
-    s.rough = t4.w;
-    s.spec = r.brdf ? fetch1(r.spec, s.tb) : 0.0;
-    D3 ns = z.n;
-    double metal = 0.0;
+    CamSurf c;
+    c.alb = d3(t4.x, t4.y, t4.z);
+    c.rough = t4.w;
+    c.spec = r.brdf ? fetch1(r.spec, s.tb) : 0.0;
+    c.ns = z.n;
+    c.metal = 0.0;
     if (r.tex4b) {
         const Shading sh = shading(r, z.leaf, s);
-        ns = sh.ns;
-        metal = sh.metal;
+        c.ns = sh.ns;
+        c.metal = sh.metal;
     }
-    nee = d3(0., 0., 0.);
-    bnc = d3(0., 0., 0.);
+    c.wp = d3(0., 0., 0.);
+    c.E = d3(0., 0., 0.);
+    c.g = 0.0;
     if (z.prj) {   // the projector term in full, the frustum and cosine decisions held
         const D3 xp = mat3(r.prj_R, x) + d3(r.prj_t[0], r.prj_t[1], r.prj_t[2]);
         const double iz = 1.0 / xp.z;
@@ -67,25 +76,38 @@ __device__ __forceinline__ void cam_terms(const ReqDesc& r, const CamFrozen& z, 
         const double pv = (r.prj_K[3] * xp.x + r.prj_K[4] * xp.y + r.prj_K[5] * xp.z) * iz;
         const D3 tow = d3(r.prj_o[0], r.prj_o[1], r.prj_o[2]) - x;
         const double dist = sqrt(dot(tow, tow));
-        const D3 wp = tow * (1.0 / dist);
+        c.wp = tow * (1.0 / dist);
         const double ca = xp.z / sqrt(dot(xp, xp));
         const D4 E = fetch4(r.Ep, bilinear(pu - 0.5, pv - 0.5, r.Wp, r.Hp));
-        const BrdfX f = brdf_x<false>(r.brdf, z.n, ns, wo, wp, s.alb, s.rough, s.spec, metal);
-        nee = f.f * d3(E.x, E.y, E.z) * (f.c / (ca * ca * ca * dist * dist));
+        c.E = d3(E.x, E.y, E.z);
+        c.g = 1.0 / (ca * ca * ca * dist * dist);
+    }
+    return c;
+}
+
+// the camera vertex's terms seen along wo from a surface point: next events and the
+// bounce factor f c (the bounce's weight applied by the caller)
+__device__ __forceinline__ void cam_eval(const ReqDesc& r, const CamFrozen& z, const CamSurf& c, D3 wo, D3& nee,
+                                         D3& bnc) {
+    nee = d3(0., 0., 0.);
+    bnc = d3(0., 0., 0.);
+    if (z.prj) {
+        const BrdfX f = brdf_x<false>(r.brdf, z.n, c.ns, wo, c.wp, c.alb, c.rough, c.spec, c.metal);
+        nee = f.f * c.E * (f.c * c.g);
     }
     if (z.env) {
-        const BrdfX f = brdf_x<false>(r.brdf, z.n, ns, wo, z.we, s.alb, s.rough, s.spec, metal);
+        const BrdfX f = brdf_x<false>(r.brdf, z.n, c.ns, wo, z.we, c.alb, c.rough, c.spec, c.metal);
         nee = nee + f.f * z.Se * f.c;
     }
     if (z.bounced) {
-        const BrdfX f = brdf_x<false>(r.brdf, z.n, ns, wo, z.wi, s.alb, s.rough, s.spec, metal);
+        const BrdfX f = brdf_x<false>(r.brdf, z.n, c.ns, wo, z.wi, c.alb, c.rough, c.spec, c.metal);
         bnc = f.f * f.c;
     }
 }
 
-__device__ __forceinline__ double cam_phi(const ReqDesc& r, const CamFrozen& z, D3 x, D3 wo, D3 delta) {
+__device__ __forceinline__ double cam_phi(const ReqDesc& r, const CamFrozen& z, const CamSurf& c, D3 wo, D3 delta) {
     D3 nee, bnc;
-    cam_terms(r, z, x, wo, nee, bnc);
+    cam_eval(r, z, c, wo, nee, bnc);
     return dot(delta, nee + bnc * z.W);
 }
 
@@ -139,7 +161,8 @@ __global__ void __launch_bounds__(CAM_TB) k_cam_grad(Queues q, AdjQueues aq, Req
             // the bounce's weight R_1 / pdf from the forward's sample radiance
             z.W = d3(0., 0., 0.);
             D3 nee0, b0;
-            cam_terms(r, z, s0.x, s0.wo, nee0, b0);
+            const CamSurf c0 = cam_surface(r, z, s0.x);
+            cam_eval(r, z, c0, s0.wo, nee0, b0);
             if (z.bounced) {
                 const float4 L = q.L[sid];
                 D3 rest = d3(L.x, L.y, L.z) - nee0;
@@ -155,24 +178,24 @@ __global__ void __launch_bounds__(CAM_TB) k_cam_grad(Queues q, AdjQueues aq, Req
             int prim;
             load_tri(r.tris, leaf, f0, f1, f2, prim);
             const D3 t1 = normalize(to_d(f1) - to_d(f0)), t2 = cross(s0.n, t1);
-            // steps: 1e-7 of the hit distance and 1e-6 rad, far below a texel or projector
-            // pixel (a step across a bilinear kink would average two slopes) and well above
-            // the FP64 rounding of the terms
+            // forward differences from the forward's own point and direction; steps 1e-8 of
+            // the hit distance and 1e-7 rad: far below a texel, a projector pixel or the
+            // narrowest GGX lobe (alpha >= 1e-3, so the one-sided error stays below ~1e-4),
+            // and far above the FP64 rounding of the terms (~1e-8 relative in the slope)
             const double tau = dot(s0.x - o, dir);
-            const double hx = 1e-7 * tau, hw = 1e-6;
+            const double hx = 1e-8 * tau, hw = 1e-7;
+            const double phi0 = cam_phi(r, z, c0, s0.wo, delta);
             D3 gx = d3(0., 0., 0.), gw = d3(0., 0., 0.);
             const D3 ta[2] = {t1, t2};
             for (int j = 0; j < 2; ++j) {
-                const double fp = cam_phi(r, z, s0.x + ta[j] * hx, s0.wo, delta);
-                const double fm = cam_phi(r, z, s0.x - ta[j] * hx, s0.wo, delta);
-                gx = gx + ta[j] * ((fp - fm) / (2.0 * hx));
+                const double fp = cam_phi(r, z, cam_surface(r, z, s0.x + ta[j] * hx), s0.wo, delta);
+                gx = gx + ta[j] * ((fp - phi0) / hx);
             }
             const D3 w1 = local_to_world(s0.wo, 1.0, 0.0, 0.0), w2 = local_to_world(s0.wo, 0.0, 1.0, 0.0);
             const D3 wa[2] = {w1, w2};
-            for (int j = 0; j < 2; ++j) {
-                const double fp = cam_phi(r, z, s0.x, normalize(s0.wo + wa[j] * hw), delta);
-                const double fm = cam_phi(r, z, s0.x, normalize(s0.wo - wa[j] * hw), delta);
-                gw = gw + wa[j] * ((fp - fm) / (2.0 * hw));
+            for (int j = 0; j < 2; ++j) {   // same point: its lookups reused
+                const double fp = cam_phi(r, z, c0, normalize(s0.wo + wa[j] * hw), delta);
+                gw = gw + wa[j] * ((fp - phi0) / hw);
             }
             // chain to (R, t): a = P^T gx, b = tau a - gw, c = (I - d d^T) b / |q|
             const D3 a = gx - s0.n * (dot(dir, gx) / dot(s0.n, dir));
