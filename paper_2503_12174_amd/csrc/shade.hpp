@@ -183,6 +183,9 @@ __device__ __forceinline__ Surf surface(const ReqDesc& r, int leaf, D3 o, D3 d) 
     Surf s;
     V3 f0, f1, f2;
     load_tri(r.tris, leaf, f0, f1, f2, s.prim);
+    // the corner texture coordinates load with the vertices (both need only the leaf): read
+    // after the barycentrics, they cost a second trip to memory
+    const float4 ua = r.tri_uv[2 * leaf], ub = r.tri_uv[2 * leaf + 1];
     const D3 v0 = to_d(f0), v1 = to_d(f1), v2 = to_d(f2);
     const D3 e1 = v1 - v0, e2 = v2 - v0;
     const D3 p = cross(d, e2);
@@ -200,7 +203,6 @@ __device__ __forceinline__ Surf surface(const ReqDesc& r, int leaf, D3 o, D3 d) 
     s.wo = -d;
     if (dot(n, s.wo) < 0.0) n = -n;
     s.n = n;
-    const float4 ua = r.tri_uv[2 * leaf], ub = r.tri_uv[2 * leaf + 1];
     s.u = b0 * ua.x + b1 * ua.z + b2 * ub.x;
     s.v = b0 * ua.y + b1 * ua.w + b2 * ub.y;
     s.tb = bilinear(s.u * r.tw - 0.5, s.v * r.th - 0.5, r.tw, r.th);
