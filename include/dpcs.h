@@ -241,7 +241,9 @@ typedef struct {
     double camera_edge_density; /* boundary part of d_camera (0: none; needs d_camera; <= 1e6):
                                    points per pixel of image length on the images of the mesh edges
                                    where the first surface seen jumps (vertices of triangles at one
-                                   position are one vertex; edges of one face or of three or more,
+                                   position are one vertex, faces of no area are left out, and
+                                   overlapping edges of different vertices each count; edges of one
+                                   face or of three or more,
                                    faces not coplanar -- creases and all silhouettes --, faces folded
                                    flat, texture-coordinate and emission seams), clipped to the
                                    image and in front of the camera.  Each point adds (f- - f+) times

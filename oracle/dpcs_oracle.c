@@ -914,7 +914,7 @@ static int nthreads_of(const orc_desc* d) {
  * (f- - f+) (n . dx/dtheta) over the curve's part inside the pixel, n the unit normal
  * toward the f+ side (Reynolds transport).  The curves taken here are the images of the
  * mesh edges across which the first surface seen changes discontinuously (vertices of
- * triangles at the same position are one vertex here):
+ * triangles at the same position are one vertex here, and faces of no area take no part):
  *   - edges of one face, or of three or more faces;
  *   - edges whose two faces are not coplanar: creases, and every silhouette edge (two
  *     faces that meet at a silhouette as seen from the camera centre, i.e. lie on one side
@@ -977,23 +977,34 @@ static int32_t* weld_vertices(const orc_desc* d) {
     return canon;
 }
 
-/* the unique edges of the mesh with their faces, sorted by (a, b), over welded vertices */
+/* does the triangle cover any area?  (exact: the cross product of float differences is
+ * computed without rounding in double) */
+static int has_area(const orc_desc* d, int32_t f) {
+    v3 a = vtx(d, d->F[3 * f]), b = vtx(d, d->F[3 * f + 1]), c = vtx(d, d->F[3 * f + 2]);
+    v3 m = cross(sub(b, a), sub(c, a));
+    return m.x != 0 || m.y != 0 || m.z != 0;
+}
+
+/* the unique edges of the mesh's faces of non-zero area with those faces, sorted by
+ * (a, b), over welded vertices (a face of no area is never seen, so it bounds nothing) */
 static orc_edge* mesh_edges(const orc_desc* d, const int32_t* canon, int64_t* ne) {
     int32_t* key = (int32_t*)malloc(sizeof(int32_t) * 9 * (size_t)d->nt);
+    int64_t nk = 0;
     for (int32_t f = 0; f < d->nt; ++f)
-        for (int k = 0; k < 3; ++k) {
-            int32_t u = canon[d->F[3 * f + k]], v = canon[d->F[3 * f + (k + 1) % 3]];
-            int32_t* e = key + 3 * (3 * (size_t)f + k);
-            e[0] = u < v ? u : v;
-            e[1] = u < v ? v : u;
-            e[2] = f;
-        }
-    qsort(key, 3 * (size_t)d->nt, 3 * sizeof(int32_t), cmp_edge_key);
-    orc_edge* E = (orc_edge*)malloc(sizeof(orc_edge) * 3 * (size_t)d->nt);
+        if (has_area(d, f))
+            for (int k = 0; k < 3; ++k) {
+                int32_t u = canon[d->F[3 * f + k]], v = canon[d->F[3 * f + (k + 1) % 3]];
+                int32_t* e = key + 3 * nk++;
+                e[0] = u < v ? u : v;
+                e[1] = u < v ? v : u;
+                e[2] = f;
+            }
+    qsort(key, (size_t)nk, 3 * sizeof(int32_t), cmp_edge_key);
+    orc_edge* E = (orc_edge*)malloc(sizeof(orc_edge) * ((size_t)nk + 1));
     int64_t n = 0;
-    for (int64_t i = 0; i < 3 * (int64_t)d->nt;) {
+    for (int64_t i = 0; i < nk;) {
         int64_t j = i;
-        while (j < 3 * (int64_t)d->nt && key[3 * j] == key[3 * i] && key[3 * j + 1] == key[3 * i + 1]) ++j;
+        while (j < nk && key[3 * j] == key[3 * i] && key[3 * j + 1] == key[3 * i + 1]) ++j;
         orc_edge e = {key[3 * i], key[3 * i + 1], key[3 * i + 2], j - i > 1 ? key[3 * i + 5] : -1, (int32_t)(j - i)};
         E[n++] = e;
         i = j;
@@ -1012,7 +1023,6 @@ static int corner_of(const orc_desc* d, const int32_t* canon, int32_t f, int32_t
 /* does the first surface seen change discontinuously across the edge's image? */
 static int edge_is_discontinuous(const ctx_t* cx, const int32_t* canon, const orc_edge* e) {
     const orc_desc* d = cx->d;
-    if (e->a == e->b) return 0;   /* a degenerate triangle's side of no length */
     if (e->nf != 2) return 1;
     v3 A = vtx(d, e->a), B = vtx(d, e->b);
     int a0 = corner_of(d, canon, e->f0, e->a), b0 = corner_of(d, canon, e->f0, e->b);

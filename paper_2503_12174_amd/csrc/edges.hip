@@ -7,7 +7,8 @@
 // moves the curve: d I_p / d theta gains the line integral of (f- - f+) (n . dx/dtheta)
 // over the curve's part inside the pixel, n the unit normal toward the f+ side.  The curves
 // are the images of the mesh edges across which the first surface seen changes
-// discontinuously -- vertices of triangles at one position being one vertex --: edges of
+// discontinuously -- vertices of triangles at one position being one vertex, faces of no
+// area left out --: edges of
 // one face or of three or more, edges whose faces are not coplanar (creases, and every
 // silhouette), coplanar faces folded onto one side, texture-coordinate and emission seams.
 // Shadow and projector-frustum boundaries on the surfaces are not among them.
@@ -307,12 +308,20 @@ bool build_edges(dpcs_context ctx, dpcs_scene sc, dpcs_status* st) {
     struct Key {
         int32_t a, b, f;
     };
-    std::vector<Key> key(3 * (size_t)nt);
-    for (int f = 0; f < nt; ++f)
+    // faces of no area are never seen and bound nothing (the cross product of float
+    // differences is exact in double, so the test is exact)
+    std::vector<Key> key;
+    key.reserve(3 * (size_t)nt);
+    for (int f = 0; f < nt; ++f) {
+        const float4* t = &tris[3 * (size_t)leaf[f]];
+        const double ax = (double)t[1].x - t[0].x, ay = (double)t[1].y - t[0].y, az = (double)t[1].z - t[0].z;
+        const double bx = (double)t[2].x - t[0].x, by = (double)t[2].y - t[0].y, bz = (double)t[2].z - t[0].z;
+        if (ay * bz - az * by == 0.0 && az * bx - ax * bz == 0.0 && ax * by - ay * bx == 0.0) continue;
         for (int k = 0; k < 3; ++k) {
             const int32_t u = canon[F[3 * (size_t)f + k]], v = canon[F[3 * (size_t)f + (k + 1) % 3]];
-            key[3 * (size_t)f + k] = Key{std::min(u, v), std::max(u, v), f};
+            key.push_back(Key{std::min(u, v), std::max(u, v), f});
         }
+    }
     std::sort(key.begin(), key.end(), [](const Key& x, const Key& y) {
         return x.a != y.a ? x.a < y.a : x.b != y.b ? x.b < y.b : x.f < y.f;
     });
@@ -326,10 +335,6 @@ bool build_edges(dpcs_context ctx, dpcs_scene sc, dpcs_status* st) {
     for (size_t i = 0; i < key.size();) {
         size_t j = i;
         while (j < key.size() && key[j].a == key[i].a && key[j].b == key[i].b) ++j;
-        if (key[i].a == key[i].b) {   // a degenerate triangle's side of no length
-            i = j;
-            continue;
-        }
         const int f0 = key[i].f, nf = (int)(j - i);
         const int f1 = nf > 1 ? key[i + 1].f : f0;
         const int cs = corner(f0, key[i].a) | corner(f0, key[i].b) << 2 | corner(f1, key[i].a) << 4 |

@@ -11,7 +11,8 @@ from paper_2503_12174_amd import synth
 from . import scenes
 from .gpu_util import GpuRun, run_vjp
 from .test_gpu_camera import _clean_cotangent
-from .test_oracle_pins_camera_edges import BACK, E1, SQUARE, _cam, _emissive, _exact_gradient, _square_image, _workload
+from .test_oracle_pins_camera_edges import (BACK, E1, SQUARE, _cam, _emissive, _exact_gradient, _square_image,
+                                            _with_degenerate_faces, _workload)
 
 pytestmark = pytest.mark.gpu
 
@@ -41,6 +42,8 @@ def _scene(name):
         return _box_scene()
     if name == "lambert square, depth 2":
         return _workload(synth.quad_mesh(SQUARE), _cam(), albedo=0.6, max_depth=2)
+    if name == "faces of no area":
+        return _workload(_with_degenerate_faces(_emissive(SQUARE, E1)), _cam())
     # quad + cube under the projector and the environment: textured GGX, occlusion,
     # three vertices, clipping on
     w = scenes.c3_ggx(spp=4, seed=21, max_depth=3)
@@ -50,7 +53,7 @@ def _scene(name):
 
 @pytest.mark.parametrize("name,density,rtol", [
     ("emissive square", 64, 1e-4), ("occluded squares", 64, 1e-4), ("closed box", 64, 1e-4),
-    ("lambert square, depth 2", 64, 1e-4), ("quad and cube", 8, 2e-3)])
+    ("lambert square, depth 2", 64, 1e-4), ("faces of no area", 64, 1e-4), ("quad and cube", 8, 2e-3)])
 def test_edge_term_matches_oracle(name, density, rtol):
     """Same edge table, points and random numbers on both sides: the totals agree up to
     FP32 radiance and the odd side path whose decision sits within rounding of a flip."""

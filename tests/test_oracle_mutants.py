@@ -146,6 +146,10 @@ MUTANTS = [
      "canon[v[i].i] = same ? canon[v[i - 1].i] : v[i].i;",
      "canon[v[i].i] = v[i].i + 0 * same;",
      PE.test_closed_box),
+    ("camera edges: faces of no area kept",
+     "    return m.x != 0 || m.y != 0 || m.z != 0;",
+     "    return 1 || m.x != 0 || m.y != 0 || m.z != 0;",
+     PE.test_faces_of_no_area_take_no_part),
     ("camera edges: no clipping at the camera plane",
      "if (hA.z < wmin) s0 = (wmin - hA.z) / (hB.z - hA.z);",
      "if (0) s0 = (wmin - hA.z) / (hB.z - hA.z);",

@@ -22,6 +22,7 @@ it.  The cases:
     between visible faces, edges hidden behind the solid), and one of a single emission
     without texture seams (only the silhouette jumps);
   * two coplanar triangles folded flat onto one side of their edge;
+  * faces of no area (a sliver on a silhouette edge, a repeated corner) that change nothing;
   * a floor that reaches behind the camera (edges clipped at the camera plane);
   * a Lambert square of albedo rho under the environment alone: its radiance is
     rho * L_env exactly (environment next event with cosine sampling, nothing above), so
@@ -315,6 +316,27 @@ def test_faces_folded_flat():
         return ENV + (E1 - ENV) * cov[..., None]
 
     _check(w, image, 1024, 2e-2)
+
+
+def _with_degenerate_faces(m):
+    """m plus a sliver glued to its first edge (third corner on that edge, its own vertex)
+    and a triangle with a repeated corner: neither covers any area."""
+    A, B = m.vertices[0], m.vertices[1]
+    V = np.concatenate([m.vertices, ((A + B) / 2)[None]]).astype(F32)
+    nv = m.vertices.shape[0]
+    T = np.concatenate([m.triangles, [[0, 1, nv], [1, 1, 2]]]).astype(np.int32)
+    UV = np.concatenate([m.corner_uvs, np.zeros((2, 3, 2), F32)]).astype(F32)
+    out = synth.Mesh(V, T, UV)
+    if m.emission is not None:
+        out.emission = np.concatenate([m.emission, np.repeat(m.emission[:1], 2, axis=0)]).astype(F32)
+    return out
+
+
+def test_faces_of_no_area_take_no_part():
+    """A sliver glued to the square's edge and a triangle with a repeated corner change
+    nothing: they are never seen, and the edge they share stays one silhouette."""
+    w = _workload(_with_degenerate_faces(_emissive(SQUARE, E1)), _cam())
+    _check(w, _square_image, 1024, 2e-2)
 
 
 def test_floor_reaching_behind_the_camera():
