@@ -889,6 +889,11 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
             PathO o;
             PathD dd;
             float4 b, rl, penda;
+            // the previous vertex's pending cotangents (read when penda.w >= 0)
+            float2 pend = {};
+            double2 puv = {};
+            float4 pn = {};
+            float pns = 0.f;
             if (UNI && depth == 0) {
                 // the dense camera wave (queue index = batch sample index): the ray is
                 // regenerated as the forward's raygen made it instead of read back
@@ -909,6 +914,13 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
                 } else {
                     rl = nt_ld(&aq.rl[cur][i]);
                     penda = nt_ld(&aq.penda[cur][i]);
+                    // loaded with the path state (every path past depth 0 bounced, so
+                    // they are nearly always used): behind the penda.w test they cost a
+                    // further trip to memory
+                    pend = nt_ld(&aq.pend[cur][i]);
+                    puv = nt_ld(&aq.puv[cur][i]);
+                    pn = nt_ld(&aq.pn[cur][i]);
+                    pns = nt_ld(&aq.pns[cur][i]);
                 }
             }
             const ReqDesc& r = sel<UNI>(uni, table, o.slot);
@@ -924,10 +936,6 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
             if (penda.w >= 0.f) {
                 // previous vertex: its next-event cotangents plus d/df of its bounce,
                 // beta_k f cos/pdf R_{k+1} -> R_{k+1} / f (zero when this ray escaped)
-                const float2 pend = nt_ld(&aq.pend[cur][i]);
-                const double2 puv = nt_ld(&aq.puv[cur][i]);
-                const float4 pn = nt_ld(&aq.pn[cur][i]);
-                const float pns = nt_ld(&aq.pns[cur][i]);
                 a_on = true;
                 a_u = puv.x;
                 a_v = puv.y;
