@@ -182,7 +182,14 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
                     q.L[sid] = L;
                 }
             } else {
-                const Surf s = surface(r, leaf, d3(o.x, o.y, o.z), d3(dd.x, dd.y, dd.z));
+                // the projector lookup needs only the point and normal: its texels load
+                // together with the maps' instead of after them
+                Surf s = surface_geo(r, leaf, d3(o.x, o.y, o.z), d3(dd.x, dd.y, dd.z));
+                ProjNee p;
+                const bool prj = projector_nee(r, s, p);
+                D4 E{};
+                if (prj) E = fetch4(r.Ep, p.pb);
+                surface_maps(r, s);
                 if (r.out_hits) r.out_hits[(size_t)g * r.max_depth + depth] = s.prim;
                 if (r.emission) {   // test scenes: surface emission
                     const float4 e = r.emission[leaf];
@@ -195,9 +202,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
                 Shading sh{};
                 if constexpr (EXT) sh = shading(r, leaf, s);
                 const D3 ns = EXT ? sh.ns : s.n;
-                ProjNee p;
-                if (projector_nee(r, s, p)) {
-                    const D4 E = fetch4(r.Ep, p.pb);
+                if (prj) {
                     D3 C;
                     if constexpr (EXT) {
                         const BrdfX f = brdf_x<false>(r.brdf, s.n, ns, s.wo, p.wp, s.alb, s.rough, s.spec, sh.metal);

@@ -179,7 +179,9 @@ __device__ __forceinline__ D3 nmap_cotangent(const Shading& h, const D3& n, D3 g
 // Hit attributes of the ray (o, d) on the leaf the FP32 traversal found: barycentrics
 // re-solved in FP64 (Cramer's rule on o + t d = v0 + b1 e1 + b2 e2), flat two-sided
 // normal facing the incoming ray, bilinear BRDF maps at the interpolated UV.
-__device__ __forceinline__ Surf surface(const ReqDesc& r, int leaf, D3 o, D3 d) {
+// the surface at a hit without its maps: point, two-sided normal, texture coordinates
+// and the bilinear corners of the maps (surface_maps reads them)
+__device__ __forceinline__ Surf surface_geo(const ReqDesc& r, int leaf, D3 o, D3 d) {
     Surf s;
     V3 f0, f1, f2;
     load_tri(r.tris, leaf, f0, f1, f2, s.prim);
@@ -206,10 +208,17 @@ __device__ __forceinline__ Surf surface(const ReqDesc& r, int leaf, D3 o, D3 d) 
     s.u = b0 * ua.x + b1 * ua.z + b2 * ub.x;
     s.v = b0 * ua.y + b1 * ua.w + b2 * ub.y;
     s.tb = bilinear(s.u * r.tw - 0.5, s.v * r.th - 0.5, r.tw, r.th);
+    return s;
+}
+__device__ __forceinline__ void surface_maps(const ReqDesc& r, Surf& s) {
     const D4 t4 = fetch4(r.tex4, s.tb);
     s.alb = d3(t4.x, t4.y, t4.z);
     s.rough = t4.w;
     s.spec = r.brdf ? fetch1(r.spec, s.tb) : 0.0;
+}
+__device__ __forceinline__ Surf surface(const ReqDesc& r, int leaf, D3 o, D3 d) {
+    Surf s = surface_geo(r, leaf, o, d);
+    surface_maps(r, s);
     return s;
 }
 
