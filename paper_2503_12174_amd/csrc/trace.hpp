@@ -43,9 +43,12 @@ __device__ __forceinline__ WtRay wt_setup(V3 o, V3 d) {
         ky = tmp;
     }
     r.k = (uint32_t)kx | (uint32_t)ky << 2 | (uint32_t)kz << 4;
-    r.Sx = comp(d, kx) / dz;
-    r.Sy = comp(d, ky) / dz;
-    r.Sz = 1.0f / dz;
+    // the shear need not be correctly rounded, only the same for every triangle a ray
+    // meets (watertightness), so the hardware reciprocal (within 1 ulp) stands in for the
+    // multi-instruction IEEE division; |dz| >= 1/sqrt(3) for a unit direction
+    r.Sz = __builtin_amdgcn_rcpf(dz);
+    r.Sx = comp(d, kx) * r.Sz;
+    r.Sy = comp(d, ky) * r.Sz;
     return r;
 }
 
@@ -114,7 +117,10 @@ struct Hit {
 struct BoxRay {
     V3 o, inv;
 };
-__device__ __forceinline__ BoxRay box_setup(V3 o, V3 d) { return BoxRay{o, v3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z)}; }
+// (hardware reciprocals, within 1 ulp: the 4e-6 widening of every slab covers it)
+__device__ __forceinline__ BoxRay box_setup(V3 o, V3 d) {
+    return BoxRay{o, v3(__builtin_amdgcn_rcpf(d.x), __builtin_amdgcn_rcpf(d.y), __builtin_amdgcn_rcpf(d.z))};
+}
 
 // conservative entry distance of the ray into [lo, hi]; returns +inf when missed
 __device__ __forceinline__ float box_enter(const BoxRay& r, float lx, float ly, float lz, float hx, float hy, float hz,
@@ -280,11 +286,12 @@ constexpr uint32_t FAR_X = 48u, FAR_Y = 80u, FAR_Z = 112u;
 
 __device__ __forceinline__ Box4Ray box4_setup(V3 o, V3 d) {
     Box4Ray r;
-    r.ix = 1.0f / d.x;
-    r.iy = 1.0f / d.y;
-    r.iz = 1.0f / d.z;
-    // |fl(o / d) - o / d| <= 2^-24 |fl(o / d)| (1 + 2^-23); 2^-21 also covers the
-    // rounding of the two sums below
+    // hardware reciprocals (within 1 ulp, +-inf for a zero component like 1 / d)
+    r.ix = __builtin_amdgcn_rcpf(d.x);
+    r.iy = __builtin_amdgcn_rcpf(d.y);
+    r.iz = __builtin_amdgcn_rcpf(d.z);
+    // |fl(o rcp(d)) - o / d| <= (2^-23 + 2^-24) |fl(o rcp(d))| (1 + 2^-23); 2^-21 also
+    // covers the rounding of the two sums below
     const float px = o.x * r.ix, py = o.y * r.iy, pz = o.z * r.iz;
     const float ex = fabsf(px) * 0x1p-21f, ey = fabsf(py) * 0x1p-21f, ez = fabsf(pz) * 0x1p-21f;
     r.anx = -px - ex;
