@@ -619,6 +619,17 @@ __device__ __forceinline__ const float* load_record(const float* __restrict__ p,
     }
     return v;
 }
+// the store of load_record (16-byte aligned records)
+template <int RS>
+__device__ __forceinline__ void store_record(float* __restrict__ p, const float* v) {
+    if constexpr (RS % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < RS / 4; ++k) ((float4*)p)[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < RS / 2; ++k) ((float2*)p)[k] = make_float2(v[2 * k], v[2 * k + 1]);
+    }
+}
 
 // records per tile: workgroup histogram in LDS, then one returning atomic per touched
 // tile, whose old value -- where this chunk's records start inside the tile's range --
@@ -685,9 +696,10 @@ __global__ void __launch_bounds__(1024) k_bin_scan(MapBins mb) {
 }
 
 // copy every record to its tile's range: the chunk's start inside each tile from the
-// histogram pass (rowbase), ranks inside the chunk from LDS atomics in the same record
-// order as the histogram's count (entries of tiles the chunk does not touch are stale
-// and never read)
+// histogram pass (rowbase), ranks inside the chunk from LDS atomics over the same records
+// the histogram counted (entries of tiles the chunk does not touch are stale and never
+// read).  The order of a tile's records does not matter: the accumulation's integer sums
+// are exact.
 template <int RS>
 __global__ void __launch_bounds__(BIN_TB) k_bin_place(MapBins mb) {
     __shared__ uint32_t cnt[MAP_MAX_BINS];
@@ -699,24 +711,21 @@ __global__ void __launch_bounds__(BIN_TB) k_bin_place(MapBins mb) {
     const uint32_t* rb = mb.rowbase + (size_t)blockIdx.x * mb.nb;
     for (int k = threadIdx.x; k < mb.nb; k += BIN_TB) cnt[k] = off[k] + rb[k];
     __syncthreads();
-    for (uint32_t base = b0; base < e; base += BIN_TB) {
-        const uint32_t i = base + threadIdx.x;
-        const bool valid = i < e;
-        const float2* src = (const float2*)(mb.rec + (size_t)(valid ? i : b0) * RS);
-        const float2 h = src[0];
-        const uint32_t bin = valid ? (uint32_t)map_bin(mb, __float_as_uint(h.x)) : 0u;
-        const uint32_t pos = lds_bin_add(cnt, valid, bin);
-        if (!valid || (int64_t)pos >= mb.cap) continue;   // pos < cap always for consistent counts
-        float2* dst = (float2*)(mb.sorted + (size_t)pos * RS);
-        if constexpr (RS % 4 == 0) {   // 16-byte copies (records are 16-byte aligned)
-            const float4* s4 = (const float4*)src;
-            float4* d4 = (float4*)dst;
+    for (uint32_t base = b0; base < e; base += BIN_TB * BIN_U) {
+        float v[BIN_U][RS];   // BIN_U whole records in flight per thread, stored from registers
+        bool valid[BIN_U];
 #pragma unroll
-            for (int k = 0; k < RS / 4; ++k) d4[k] = s4[k];
-        } else {
-            dst[0] = h;
+        for (int u = 0; u < BIN_U; ++u) {
+            const uint32_t i = base + u * BIN_TB + threadIdx.x;
+            valid[u] = i < e;
+            load_record<RS>(mb.rec + (size_t)(valid[u] ? i : b0) * RS, v[u]);
+        }
 #pragma unroll
-            for (int k = 1; k < RS / 2; ++k) dst[k] = src[k];
+        for (int u = 0; u < BIN_U; ++u) {
+            const uint32_t bin = valid[u] ? (uint32_t)map_bin(mb, __float_as_uint(v[u][0])) : 0u;
+            const uint32_t pos = lds_bin_add(cnt, valid[u], bin);
+            if (!valid[u] || (int64_t)pos >= mb.cap) continue;   // pos < cap always for consistent counts
+            store_record<RS>(mb.sorted + (size_t)pos * RS, v[u]);
         }
     }
 }

@@ -154,6 +154,8 @@ constexpr int ACC_TB = 1024;    // threads per workgroup of the accumulation
 constexpr int BIN_CHUNK = 16384;// records per workgroup of the histogram and the placement
 constexpr int BIN_TB = 1024;    // their threads per workgroup: 16 waves share one LDS
                                 // histogram, so the few chunks of a flush still fill the chip
+constexpr int BIN_U = 4;        // records a thread of the placement loads at once
+static_assert(BIN_CHUNK % (BIN_TB * BIN_U) == 0, "placement chunking");
 constexpr long long STAGE_NAN = -0x7fffffffffffffffll - 1;   // INT64_MIN
 struct MapBins {
     float* rec;          // records of rs floats (null: binning off, the replay scatters directly)
