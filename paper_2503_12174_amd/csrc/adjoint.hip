@@ -770,8 +770,15 @@ __global__ void __launch_bounds__(ACC_TB) k_bin_accum(MapBins mb) {
         const int tx0 = (b % mb.nbx) * mb.T, ty0 = (b / mb.nbx) * mb.T;
         bool bad = false;
         float rv[RS];
-        for (uint32_t i = s0 + threadIdx.x; i < s1; i += ACC_TB) {
-            const float* p = load_record<RS>(mb.sorted + (size_t)i * RS, rv);
+        // The samples of one pixel sit together in the sorted records and share texels,
+        // and an LDS atomic instruction whose lanes meet at one address is serialised: the
+        // lanes of a wave take records m = ceil(n / 64) apart (lane l: slot [l m, l m + m)
+        // of the tile's n records), i.e. from different pixels
+        const uint32_t n = s1 - s0, m = (n + 63u) >> 6;
+        for (uint32_t k = threadIdx.x; k < 64u * m; k += ACC_TB) {
+            const uint32_t j = (k & 63u) * m + (k >> 6);
+            if (j >= n) continue;
+            const float* p = load_record<RS>(mb.sorted + (size_t)(s0 + j) * RS, rv);
             const uint32_t head = __float_as_uint(p[0]);
             const uint32_t base = head & 0x0fffffffu;
             const int y0 = (int)(base / (uint32_t)mb.W), x0 = (int)(base - (uint32_t)y0 * (uint32_t)mb.W);
