@@ -423,8 +423,7 @@ dpcs_status camera_edge_term(dpcs_context ctx, dpcs_scene sc, const ReqDesc& r, 
             hipLaunchKernelGGL(k_edge_raygen, dim3((m + 255) / 256), dim3(256), 0, l.st, qe, re, a, side);
             int cur = 0;
             for (int d = 0; d < re.max_depth; ++d) {
-                launch_set_count(l, qe.cnt, cur ^ 1, 0, 2, 4);
-                launch_trace(l, qe, cur, re, nullptr, m);
+                launch_trace(l, qe, cur, re, nullptr, m);   // (empties the queues shading appends to)
                 launch_shade(l, qe, cur, d, re, nullptr, m);
                 for (int w = 0; w < (re.env_on ? 2 : 1); ++w) launch_shadow(l, qe, w, re, nullptr, m, d);
                 cur ^= 1;

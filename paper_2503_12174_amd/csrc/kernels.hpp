@@ -258,6 +258,21 @@ void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* 
                        float* d_spec, float* d_scalars, float* acc, float* d_metal = nullptr,
                        float* d_nmap = nullptr);
 void launch_zero(const Launch& l, float* p, int64_t n);
+// Float buffers cleared together by one launch on l's stream: add() collects them (a
+// full list is cleared at once and started again), launch() clears what is held.
+constexpr int ZERO_LIST_MAX = 8;
+struct ZeroArgs {
+    float* p[ZERO_LIST_MAX];
+    int64_t n[ZERO_LIST_MAX];
+};
+struct ZeroList {
+    explicit ZeroList(const Launch& l) : l(l) {}
+    void add(float* ptr, int64_t count);
+    void launch();
+    Launch l;
+    ZeroArgs a{};
+    int k = 0;
+};
 
 // debug
 void launch_debug_intersect(const Launch& l, const float4* nodes4, const float4* nodes, const float4* tris,

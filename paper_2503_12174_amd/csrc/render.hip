@@ -65,6 +65,14 @@ __global__ void k_zero(float* p, int64_t n) {
     if (i < n) p[i] = 0.0f;
 }
 
+// several buffers cleared by one launch: blockIdx.y picks the buffer
+__global__ void k_zero_list(ZeroArgs z) {
+    float* const p = z.p[blockIdx.y];
+    const int64_t n = z.n[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
 __global__ void k_set_desc(ReqDesc r, ReqDesc* table, int slot) {
     if (threadIdx.x == 0) table[slot] = r;
 }
@@ -95,6 +103,13 @@ __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_trace(Queues q, int 
     __shared__ float4 ltop[UNI ? 8 * TOP_NODES : 1];
     int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL;
     const uint32_t n = q.cnt[cur];
+    // the queues the shading after this launch appends to start empty (this kernel reads
+    // only its own queue's count, and whatever read the others ran before it)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        q.cnt[cur ^ 1] = 0u;
+        q.cnt[2] = 0u;
+        q.cnt[3] = 0u;
+    }
     TopNodes top{nullptr, 0u};
     if constexpr (UNI)   // one tree for the whole launch: stage its top levels
         if (uni.nodes4) top = stage_top<TB>(ltop, uni.nodes4, uni.top_nodes);
@@ -485,6 +500,21 @@ void launch_set_count(const Launch& l, uint32_t* cnt, int idx, uint32_t value, i
 }
 void launch_zero(const Launch& l, float* p, int64_t n) {
     if (n > 0) hipLaunchKernelGGL(k_zero, dim3(grid_of(n, 256)), dim3(256), 0, l.st, p, n);
+}
+void ZeroList::add(float* ptr, int64_t count) {
+    if (!ptr || count <= 0) return;
+    if (k == ZERO_LIST_MAX) launch();   // full: clear what is held and start again
+    a.p[k] = ptr;
+    a.n[k] = count;
+    ++k;
+}
+void ZeroList::launch() {
+    if (k == 0) return;
+    int64_t m = 0;
+    for (int j = 0; j < k; ++j) m = std::max(m, a.n[j]);
+    const unsigned gx = (unsigned)std::min<int64_t>(grid_of(m, 256), 4096);
+    hipLaunchKernelGGL(k_zero_list, dim3(gx, (unsigned)k), dim3(256), 0, l.st, a);
+    k = 0;
 }
 void launch_set_desc(const Launch& l, ReqDesc* table, int slot, const ReqDesc& r) {
     hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, l.st, r, table, slot);

@@ -146,9 +146,9 @@ bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues&
 }
 
 // Record buffers of the binned map-cotangent flush for a W x H map with C values per
-// texel; leaves mb empty (direct atomics) when the map has too many tiles or the
-// scratch allocation fails.
-void make_map_bins(dpcs_context ctx, const Launch& l, MapBins& mb, const char* name, int W, int H, int C, int RS,
+// texel (their counters go on zl to be cleared); leaves mb empty (direct atomics) when
+// the map has too many tiles or the scratch allocation fails.
+void make_map_bins(dpcs_context ctx, ZeroList& zl, MapBins& mb, const char* name, int W, int H, int C, int RS,
                    int64_t cap) {
     mb = MapBins{};
     int T = 0, nbx = 0, nby = 0;
@@ -182,8 +182,8 @@ void make_map_bins(dpcs_context ctx, const Launch& l, MapBins& mb, const char* n
     mb.nbx = nbx;
     mb.nby = nby;
     mb.nb = nb;
-    launch_zero(l, (float*)mb.count, 1);
-    launch_zero(l, (float*)mb.bins, 3 * (int64_t)nb + 2);
+    zl.add((float*)mb.count, 1);
+    zl.add((float*)mb.bins, 3 * (int64_t)nb + 2);
 }
 
 static void inv3(const double* m, double* o) {
@@ -751,7 +751,7 @@ void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t 
     prof_end(ctx, pr, nullptr, n);
     int cur = 0;
     for (int d = 0; d < r.max_depth; ++d) {
-        launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);   // next path queue and shadow queues empty
+        // (the closest-hit launch empties the next path queue and the shadow queues)
         q.stats = prof_stats(ctx, DPCS_STAGE_TRACE);
         pr = prof_begin(ctx, DPCS_STAGE_TRACE);
         launch_trace(l, q, cur, r, nullptr, n, d == 0);
@@ -804,7 +804,6 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
     }
     launch_adj_raygen(l, q, aq, r, 0, r.g_base, n);
     for (int d = 0; d < r.max_depth; ++d) {
-        launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
         q.stats = prof_stats(ctx, DPCS_STAGE_TRACE);
         pr = prof_begin(ctx, DPCS_STAGE_TRACE);
         launch_trace(l, q, cur, r, nullptr, n);

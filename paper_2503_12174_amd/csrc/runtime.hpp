@@ -98,7 +98,7 @@ void carve_queues(char* base, int64_t cap, int trace_blocks, Queues& q);
 // ext: also the pending buffers of the metallic / normal-map replay
 bool make_adj_queues(dpcs_context ctx, const char* name, int64_t cap, AdjQueues& aq, dpcs_status* st,
                      bool ext = false);
-void make_map_bins(dpcs_context ctx, const Launch& l, MapBins& mb, const char* name, int W, int H, int C, int RS,
+void make_map_bins(dpcs_context ctx, ZeroList& zl, MapBins& mb, const char* name, int W, int H, int C, int RS,
                    int64_t cap);
 
 // PRF'd projector irradiance and packed maps of one request in scratch (tag selects the buffers)

@@ -222,9 +222,11 @@ void dpcs_server_s::admit_locked(Launch& l) {
             r.dEp = (float*)take(16 * nEp);
             r.d_tex = (float*)take(20 * nT);
             r.d_acc = (float*)take(128);
-            launch_zero(l, r.dEp, 4 * (int64_t)nEp);
-            launch_zero(l, r.d_tex, 5 * (int64_t)nT);
-            launch_zero(l, r.d_acc, 32);
+            ZeroList zl(l);
+            zl.add(r.dEp, 4 * (int64_t)nEp);
+            zl.add(r.d_tex, 5 * (int64_t)nT);
+            zl.add(r.d_acc, 32);
+            zl.launch();
         }
         active.push_back(q);
     }
@@ -314,8 +316,7 @@ void dpcs_server_s::wave(Launch& l) {
                                             false, nullptr);
     int cur = 0;
     for (int d = 0; d < max_depth; ++d) {
-        launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
-        launch_trace(l, q, cur, any, nullptr, used);
+        launch_trace(l, q, cur, any, nullptr, used);   // (empties the queues shading appends to)
         launch_shade(l, q, cur, d, any, table, used);
         launch_shadow(l, q, 0, any, table, used, d, true);
         if (env) launch_shadow(l, q, 1, any, table, used, d, true);
@@ -337,10 +338,12 @@ void dpcs_server_s::wave(Launch& l) {
                 !loop_bins_view(ep_bins, ep_bins_cap, 3, 6, binq->r.Wp, binq->r.Hp, ab.eb)) {
                 binq = nullptr;
             } else {   // a fresh histogram for this map size
-                launch_zero(l, (float*)ab.tb.count, 1);
-                launch_zero(l, (float*)ab.tb.bins, 3 * (int64_t)MAP_MAX_BINS + 2);
-                launch_zero(l, (float*)ab.eb.count, 1);
-                launch_zero(l, (float*)ab.eb.bins, 3 * (int64_t)MAP_MAX_BINS + 2);
+                ZeroList zl(l);
+                zl.add((float*)ab.tb.count, 1);
+                zl.add((float*)ab.tb.bins, 3 * (int64_t)MAP_MAX_BINS + 2);
+                zl.add((float*)ab.eb.count, 1);
+                zl.add((float*)ab.eb.bins, 3 * (int64_t)MAP_MAX_BINS + 2);
+                zl.launch();
                 ++st_binned;
             }
         }

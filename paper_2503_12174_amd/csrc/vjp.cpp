@@ -48,9 +48,10 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     float* acc = (float*)scratch(ctx, "vjp.acc", sizeof(float) * 32, &st);
     if (!acc) return st;
     Launch l{ctx->stream, ctx->grid_cap};
-    launch_zero(l, dEp, 4 * (int64_t)nEp);
-    launch_zero(l, dtex, C * (int64_t)nT);
-    launch_zero(l, acc, 32);
+    ZeroList zl(l);   // the accumulators, cleared by one launch before the first wave
+    zl.add(dEp, 4 * (int64_t)nEp);
+    zl.add(dtex, C * (int64_t)nT);
+    zl.add(acc, 32);
     r.dEp = dEp;
     r.d_tex = dtex;
     r.d_acc = acc;
@@ -69,7 +70,7 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
     if (edge_density > 0.0) {
         pix_dE = (float4*)scratch(ctx, "vjp.pixel_cotangents", sizeof(float4) * npix, &st);
         if (!pix_dE) return st;
-        launch_zero(l, (float*)pix_dE, 4 * npix);
+        zl.add((float*)pix_dE, 4 * npix);
     }
     Queues q{};
     AdjQueues aq{};
@@ -92,10 +93,11 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
         // vertex -- and one E_p record per vertex
         const int64_t k = std::min(r.max_depth, BIN_DEPTHS);
         const int64_t per = (own_rec || path_records) ? k + 1 : 3 * k;
-        if (ext) make_map_bins(ctx, l, aq.tb, "vjp.tex9_bins", r.tw, r.th, 9, 12, ppw * r.spp * per);
-        else make_map_bins(ctx, l, aq.tb, "vjp.tex_bins", r.tw, r.th, 5, 8, ppw * r.spp * per);
-        make_map_bins(ctx, l, aq.eb, "vjp.ep_bins", r.Wp, r.Hp, 3, 6, ppw * r.spp * k);
+        if (ext) make_map_bins(ctx, zl, aq.tb, "vjp.tex9_bins", r.tw, r.th, 9, 12, ppw * r.spp * per);
+        else make_map_bins(ctx, zl, aq.tb, "vjp.tex_bins", r.tw, r.th, 5, 8, ppw * r.spp * per);
+        make_map_bins(ctx, zl, aq.eb, "vjp.ep_bins", r.Wp, r.Hp, 3, 6, ppw * r.spp * k);
     }
+    zl.launch();
     for (int64_t a = 0; a < npix; a += ppw) {
         const uint32_t b = (uint32_t)std::min(npix, a + ppw);
         if (own_rec) {
