@@ -636,11 +636,9 @@ __device__ __forceinline__ void store_record(float* __restrict__ p, const float*
 // goes to rowbase for the placement; also the largest |cotangent| of any record (for
 // the fixed-point accumulation)
 template <int C, int RS>
-__global__ void __launch_bounds__(BIN_TB) k_bin_hist(MapBins mb) {
-    __shared__ uint32_t h[MAP_MAX_BINS];
-    __shared__ uint32_t hmax;
+__device__ __forceinline__ void bin_hist(const MapBins& mb, uint32_t chunk, uint32_t* h, uint32_t& hmax) {
     const uint32_t n = map_records(mb);
-    const uint32_t b0 = blockIdx.x * BIN_CHUNK;
+    const uint32_t b0 = chunk * BIN_CHUNK;
     if (b0 >= n) return;   // uniform per workgroup
     for (int k = threadIdx.x; k < mb.nb; k += BIN_TB) h[k] = 0u;
     if (threadIdx.x == 0) hmax = 0u;
@@ -663,15 +661,23 @@ __global__ void __launch_bounds__(BIN_TB) k_bin_hist(MapBins mb) {
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
     if (__lane_id() == 0) atomicMax(&hmax, __float_as_uint(m));   // non-negative floats order as integers
     __syncthreads();
-    uint32_t* const rb = mb.rowbase + (size_t)blockIdx.x * mb.nb;
+    uint32_t* const rb = mb.rowbase + (size_t)chunk * mb.nb;
     for (int k = threadIdx.x; k < mb.nb; k += BIN_TB)
         if (h[k]) rb[k] = atomicAdd(&mb.bins[k], h[k]);
     if (threadIdx.x == 0 && hmax) atomicMax(&mb.bins[3 * mb.nb + 1], hmax);
 }
+// the flush kernels serve two maps at once (their chunks fill the chip together):
+// workgroups [0, ga) map a, the rest map b (none when only a is flushed)
+template <int CA, int RSA, int CB, int RSB>
+__global__ void __launch_bounds__(BIN_TB) k_bin_hist(MapBins a, MapBins b, uint32_t ga) {
+    __shared__ uint32_t h[MAP_MAX_BINS];
+    __shared__ uint32_t hmax;
+    if (blockIdx.x < ga) bin_hist<CA, RSA>(a, blockIdx.x, h, hmax);
+    else bin_hist<CB, RSB>(b, blockIdx.x - ga, h, hmax);
+}
 
 // tile offsets (exclusive scan of the counts, nb <= 4096); clears the counts
-__global__ void __launch_bounds__(1024) k_bin_scan(MapBins mb) {
-    __shared__ uint32_t part[1024];
+__device__ __forceinline__ void bin_scan(const MapBins& mb, uint32_t* part) {
     uint32_t* off = mb.bins + mb.nb;
     const int per = (mb.nb + 1023) / 1024;
     const int b = threadIdx.x * per, e = min(b + per, mb.nb);
@@ -694,6 +700,11 @@ __global__ void __launch_bounds__(1024) k_bin_scan(MapBins mb) {
     }
     if (threadIdx.x == 1023) off[mb.nb] = part[1023];
 }
+// workgroup 0: map a, workgroup 1: map b
+__global__ void __launch_bounds__(1024) k_bin_scan(MapBins a, MapBins b) {
+    __shared__ uint32_t part[1024];
+    bin_scan(blockIdx.x == 0 ? a : b, part);
+}
 
 // copy every record to its tile's range: the chunk's start inside each tile from the
 // histogram pass (rowbase), ranks inside the chunk from LDS atomics over the same records
@@ -701,14 +712,13 @@ __global__ void __launch_bounds__(1024) k_bin_scan(MapBins mb) {
 // read).  The order of a tile's records does not matter: the accumulation's integer sums
 // are exact.
 template <int RS>
-__global__ void __launch_bounds__(BIN_TB) k_bin_place(MapBins mb) {
-    __shared__ uint32_t cnt[MAP_MAX_BINS];
+__device__ __forceinline__ void bin_place(const MapBins& mb, uint32_t chunk, uint32_t* cnt) {
     const uint32_t n = map_records(mb);
-    const uint32_t b0 = blockIdx.x * BIN_CHUNK;
+    const uint32_t b0 = chunk * BIN_CHUNK;
     if (b0 >= n) return;   // uniform per workgroup
     const uint32_t e = min(n, b0 + BIN_CHUNK);
     const uint32_t* off = mb.bins + mb.nb;
-    const uint32_t* rb = mb.rowbase + (size_t)blockIdx.x * mb.nb;
+    const uint32_t* rb = mb.rowbase + (size_t)chunk * mb.nb;
     for (int k = threadIdx.x; k < mb.nb; k += BIN_TB) cnt[k] = off[k] + rb[k];
     __syncthreads();
     for (uint32_t base = b0; base < e; base += BIN_TB * BIN_U) {
@@ -729,22 +739,26 @@ __global__ void __launch_bounds__(BIN_TB) k_bin_place(MapBins mb) {
         }
     }
 }
+template <int RSA, int RSB>
+__global__ void __launch_bounds__(BIN_TB) k_bin_place(MapBins a, MapBins b, uint32_t ga) {
+    __shared__ uint32_t cnt[MAP_MAX_BINS];
+    if (blockIdx.x < ga) bin_place<RSA>(a, blockIdx.x, cnt);
+    else bin_place<RSB>(b, blockIdx.x - ga, cnt);
+}
 
 // Accumulation over fixed chunks of the tile-sorted records (balanced whatever the
 // tile sizes): a workgroup walks the tiles its chunk covers and, per tile, sums the
 // records in LDS over the tile plus one halo row/column and stores the (T + 1)^2 x C
 // block at pair index chunk + tile (unique: both grow along the sorted records).
 template <int C, int RS>
-__global__ void __launch_bounds__(ACC_TB) k_bin_accum(MapBins mb) {
+__device__ __forceinline__ void bin_accum(const MapBins& mb, uint32_t c, long long* t) {
     // Sums in 64-bit fixed point (integer LDS atomics are exact and much faster than
     // FP32 ones): values scaled by 2^E with |chunk sum| < 2^62 for every texel, i.e.
     // 2^-50 of the largest record value as resolution.  The chunk sums are stored as
     // integers, so the texel totals the gather forms do not depend on how the records
     // were split into chunks (which varies with the order atomics placed them in).
-    __shared__ long long t[(MAP_MAX_T + 1) * (MAP_MAX_T + 1) * C];
     const uint32_t* off = mb.bins + mb.nb;
     const uint32_t total = off[mb.nb];
-    const uint32_t c = blockIdx.x;
     const uint32_t i0 = c * ACC_CHUNK;
     if (c == 0 && threadIdx.x == 0) *mb.count = 0u;   // the counting passes are done
     if (i0 >= total) return;   // uniform per workgroup
@@ -807,13 +821,18 @@ __global__ void __launch_bounds__(ACC_TB) k_bin_accum(MapBins mb) {
         while (off[b + 1] == off[b]) ++b;   // skip empty tiles (a later tile holds record i1 - 1)
     }
 }
+template <int CA, int RSA, int CB, int RSB>
+__global__ void __launch_bounds__(ACC_TB) k_bin_accum(MapBins a, MapBins b, uint32_t ga) {
+    __shared__ long long t[(MAP_MAX_T + 1) * (MAP_MAX_T + 1) * (CA > CB ? CA : CB)];
+    if (blockIdx.x < ga) bin_accum<CA, RSA>(a, blockIdx.x, t);
+    else bin_accum<CB, RSB>(b, blockIdx.x - ga, t);
+}
 
 // one thread per texel: the blocks of every (chunk, tile) pair of its own tile plus
 // the halos of the tiles to the left, above and above-left, added into the map (each
 // texel written by one thread)
 template <int C>
-__global__ void k_bin_gather(MapBins mb, float* __restrict__ out, int stride) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void bin_gather(const MapBins& mb, float* __restrict__ out, int stride, int64_t t) {
     if (t == 0) mb.bins[3 * mb.nb + 1] = 0u;   // largest |value|: read by the accumulation only
     if (t >= (int64_t)mb.W * mb.H) return;
     const int y = (int)(t / mb.W), x = (int)(t - (int64_t)y * mb.W);
@@ -865,6 +884,12 @@ __global__ void k_bin_gather(MapBins mb, float* __restrict__ out, int stride) {
         const float v = nan ? __builtin_nanf("") : (float)(neg ? -m : m);
         if (v != 0.f) o[ch] += v;
     }
+}
+template <int CA, int CB>
+__global__ void __launch_bounds__(256) k_bin_gather(MapBins a, float* __restrict__ oa, int sa, MapBins b,
+                                                    float* __restrict__ ob, int sb, uint32_t ga) {
+    if (blockIdx.x < ga) bin_gather<CA>(a, oa, sa, (int64_t)blockIdx.x * 256 + threadIdx.x);
+    else bin_gather<CB>(b, ob, sb, (int64_t)(blockIdx.x - ga) * 256 + threadIdx.x);
 }
 
 // ---------------------------------------------------------------- replay from records
@@ -1453,26 +1478,29 @@ bool map_tiling(int W, int H, int& T, int& nbx, int& nby) {
     }
     return (int64_t)nbx * nby <= MAP_MAX_BINS;
 }
-template <int C, int RS>
-static void flush_one(const Launch& l, const MapBins& mb, float* out, int stride) {
-    const unsigned g = (unsigned)((mb.cap + BIN_CHUNK - 1) / BIN_CHUNK);
-    hipLaunchKernelGGL((k_bin_hist<C, RS>), dim3(g), dim3(BIN_TB), 0, l.st, mb);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, l.st, mb);
-    hipLaunchKernelGGL(k_bin_place<RS>, dim3(g), dim3(BIN_TB), 0, l.st, mb);
-    hipLaunchKernelGGL((k_bin_accum<C, RS>), dim3((unsigned)((mb.cap + ACC_CHUNK - 1) / ACC_CHUNK)), dim3(ACC_TB), 0,
-                       l.st, mb);
-    hipLaunchKernelGGL(k_bin_gather<C>, dim3(grid_of((int64_t)mb.W * mb.H, 256)), dim3(256), 0, l.st, mb, out,
-                       stride);
+// map a alone (b null) or maps a and b together; hist, scan, place, accumulate, gather
+template <int CA, int RSA, int CB, int RSB>
+static void flush_maps(const Launch& l, const MapBins& a, float* oa, int sa, const MapBins* b, float* ob, int sb) {
+    const MapBins& bb = b ? *b : a;
+    const uint32_t ha = (uint32_t)((a.cap + BIN_CHUNK - 1) / BIN_CHUNK), hb = b ? (uint32_t)((b->cap + BIN_CHUNK - 1) / BIN_CHUNK) : 0u;
+    const uint32_t aa = (uint32_t)((a.cap + ACC_CHUNK - 1) / ACC_CHUNK), ab = b ? (uint32_t)((b->cap + ACC_CHUNK - 1) / ACC_CHUNK) : 0u;
+    const uint32_t ta = grid_of((int64_t)a.W * a.H, 256), tb = b ? grid_of((int64_t)b->W * b->H, 256) : 0u;
+    hipLaunchKernelGGL((k_bin_hist<CA, RSA, CB, RSB>), dim3(ha + hb), dim3(BIN_TB), 0, l.st, a, bb, ha);
+    hipLaunchKernelGGL(k_bin_scan, dim3(b ? 2 : 1), dim3(1024), 0, l.st, a, bb);
+    hipLaunchKernelGGL((k_bin_place<RSA, RSB>), dim3(ha + hb), dim3(BIN_TB), 0, l.st, a, bb, ha);
+    hipLaunchKernelGGL((k_bin_accum<CA, RSA, CB, RSB>), dim3(aa + ab), dim3(ACC_TB), 0, l.st, a, bb, aa);
+    hipLaunchKernelGGL((k_bin_gather<CA, CB>), dim3(ta + tb), dim3(256), 0, l.st, a, oa, sa, bb, b ? ob : oa,
+                       b ? sb : sa, ta);
 }
 void launch_sum_partials(const Launch& l, const float* part, int nb, int stride, int nv, float* dst) {
     hipLaunchKernelGGL(k_sum_partials, dim3(nv), dim3(256), 0, l.st, part, nb, stride, nv, dst);
 }
 void launch_map_flush(const Launch& l, const AdjQueues& aq, const ReqDesc& r) {
-    if (aq.tb.rec && r.d_tex) {
-        if (r.dtex_c == 9) flush_one<9, TEX9_RS>(l, aq.tb, r.d_tex, 9);
-        else flush_one<5, TEX_RS>(l, aq.tb, r.d_tex, 5);
-    }
-    if (aq.eb.rec && r.dEp) flush_one<3, EP_RS>(l, aq.eb, r.dEp, 4);
+    const bool tex = aq.tb.rec && r.d_tex, ep = aq.eb.rec && r.dEp;
+    const MapBins* e = ep ? &aq.eb : nullptr;
+    if (tex && r.dtex_c == 9) flush_maps<9, TEX9_RS, 3, EP_RS>(l, aq.tb, r.d_tex, 9, e, r.dEp, 4);
+    else if (tex) flush_maps<5, TEX_RS, 3, EP_RS>(l, aq.tb, r.d_tex, 5, e, r.dEp, 4);
+    else if (ep) flush_maps<3, EP_RS, 3, EP_RS>(l, aq.eb, r.dEp, 4, nullptr, nullptr, 0);
 }
 void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* d_albedo, float* d_rough,
                        float* d_spec, float* d_scalars, float* acc, float* d_metal, float* d_nmap) {
