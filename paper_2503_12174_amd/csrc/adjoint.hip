@@ -893,6 +893,19 @@ __global__ void __launch_bounds__(256) k_bin_gather(MapBins a, float* __restrict
 }
 
 // ---------------------------------------------------------------- replay from records
+// The replay's queue sizes rotate over three slots, q.cnt[REPLAY_CNT + (depth mod 3)]:
+// a launch reads its own, appends to the next and empties the one after (read by the
+// launch before, untouched by this one; replay_count_clear), so no launch between depths
+// resets a count.  The caller starts depth 0 with its slot = queue size, the next = 0.
+__device__ __forceinline__ uint32_t* replay_count(const Queues& q, int depth) {
+    return q.cnt + REPLAY_CNT + depth % 3;
+}
+// Called by workgroup 0 after its last read of the counts: a store ahead of the size's
+// read turns that read from a scalar load into a vector load per wave, which made the
+// whole launch several times slower.
+__device__ __forceinline__ void replay_count_clear(const Queues& q, int depth) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(replay_count(q, depth + 2), 0u);
+}
 // One bounce of the replay when the forward kept its path records: the vertex's leaf and
 // the visibility of its shadow rays are read instead of traced.  Shading, the
 // next-event terms and the bounce are re-evaluated with the forward's Philox counters.
@@ -903,11 +916,14 @@ template <bool UNI>
 __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, int cur, int depth, ReqDesc uni,
                                                       const ReqDesc* __restrict__ table) {
     const int nxt = cur ^ 1;
-    const uint32_t n = q.cnt[cur];
+    const uint32_t n = *replay_count(q, depth);
     // one path per thread (the grid covers the queue): with no grid-stride loop no
     // descriptor field is held across iterations, which saves ~60 VGPRs
     const uint32_t base = blockIdx.x * BLOCK;
-    if (base >= n) return;   // uniform per workgroup
+    if (base >= n) {   // uniform per workgroup
+        replay_count_clear(q, depth);
+        return;
+    }
     {
         const uint32_t i = base + threadIdx.x;
         bool cont = false;
@@ -1106,9 +1122,10 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
             }
         }
         const bool pred[1] = {cont};
-        uint32_t* const ctr[1] = {&q.cnt[nxt]};
+        uint32_t* const ctr[1] = {replay_count(q, depth + 1)};
         uint32_t jn;
         block_append<1>(pred, ctr, &jn);
+        replay_count_clear(q, depth);
         if (cont) {
             nt_st(&q.po[nxt][jn], no);
             nt_st(&q.pd[nxt][jn], nd);
@@ -1135,9 +1152,12 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay(Queues q, AdjQueues aq, in
 // values (through the vertex's frame), so the records hold 9 channels.
 __global__ void __launch_bounds__(BLOCK) k_adj_replay_ext(Queues q, AdjQueues aq, int cur, int depth, ReqDesc r) {
     const int nxt = cur ^ 1;
-    const uint32_t n = q.cnt[cur];
+    const uint32_t n = *replay_count(q, depth);
     const uint32_t base = blockIdx.x * BLOCK;
-    if (base >= n) return;   // uniform per workgroup
+    if (base >= n) {   // uniform per workgroup
+        replay_count_clear(q, depth);
+        return;
+    }
     const uint32_t i = base + threadIdx.x;
     bool cont = false;
     PathO no{};
@@ -1315,9 +1335,10 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay_ext(Queues q, AdjQueues aq
         if (r.dEp) scatter_ep(r, e_on, e_pu, e_pv, eg);
     }
     const bool pred[1] = {cont};
-    uint32_t* const ctr[1] = {&q.cnt[nxt]};
+    uint32_t* const ctr[1] = {replay_count(q, depth + 1)};
     uint32_t jn;
     block_append<1>(pred, ctr, &jn);
+    replay_count_clear(q, depth);
     if (cont) {
         nt_st(&q.po[nxt][jn], no);
         nt_st(&q.pd[nxt][jn], nd);

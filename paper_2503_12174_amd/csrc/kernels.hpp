@@ -107,7 +107,8 @@ struct Queues {
     float4* sc[2];     // shadow contribution (w: batch sample index)
     float* st[2];      // shadow tmax
     float4* L;         // per batch sample radiance (rgb, -)
-    uint32_t* cnt;     // [0], [1] path queue sizes, [2], [3] shadow queue sizes
+    uint32_t* cnt;     // [0], [1] path queue sizes, [2], [3] shadow queue sizes, [4..6] the
+                       // replay's path queue sizes (by depth mod 3)
     int64_t cap;       // path capacity
     unsigned long long* stats;   // null, or [0] nodes visited, [1] triangles tested (profiling)
     int* spill;        // traversal stack overflow: SPILL ints per thread of a capped grid
@@ -198,6 +199,7 @@ struct AdjQueues {
     MapBins eb;        // E_p cotangent records (C = 3, 6 floats per record)
 };
 
+constexpr int REPLAY_CNT = 4;   // first of the replay's three queue-size slots in Queues::cnt
 struct Launch {
     hipStream_t st;
     int grid_cap;      // upper bound on workgroups of grid-stride kernels

@@ -97,7 +97,7 @@ void carve_queues(char* b, int64_t cap, int trace_blocks, Queues& q) {
     }
     q.hit = (int*)take(4 * c);
     q.L = (float4*)take(16 * c);
-    q.cnt = (uint32_t*)take(16);
+    q.cnt = (uint32_t*)take(4 * (REPLAY_CNT + 3));
     q.spill = (int*)take(4 * (size_t)trace_blocks * TRACE_TB * SPILL);
     q.trace_blocks = trace_blocks;
     q.cap = cap;
@@ -785,14 +785,14 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
     launch_adj_pixel(l, q, aq, r, a, b, sample_L, pix_dE);
     launch_cam_grad(l, q, aq, r, a, b);   // (no-op unless the camera-pose gradient is asked for)
     prof_end(ctx, pr, nullptr, b - a);
-    launch_set_count(l, q.cnt, 0, n, 1, 4);
     int cur = 0;
     if (r.rec) {   // the forward's path records stand in for tracing (camera rays regenerated in depth 0)
+        // (the replay's queue sizes rotate over their own slots: one reset for all depths)
+        launch_set_count(l, q.cnt, REPLAY_CNT, n, REPLAY_CNT + 1, REPLAY_CNT + 2);
         for (int d = 0; d < r.max_depth; ++d) {
-            launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
             pr = prof_begin(ctx, DPCS_STAGE_ADJ_SHADE);
             launch_adj_replay(l, q, aq, cur, d, r, nullptr, n);
-            prof_end(ctx, pr, q.cnt + cur, 0);
+            prof_end(ctx, pr, q.cnt + REPLAY_CNT + d % 3, 0);
             if ((aq.tb.rec || aq.eb.rec) && ((d + 1) % BIN_DEPTHS == 0 || d == r.max_depth - 1)) {
                 pr = prof_begin(ctx, DPCS_STAGE_OTHER);
                 launch_map_flush(l, aq, r);
@@ -802,8 +802,9 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
         }
         return;
     }
+    launch_set_count(l, q.cnt, 0, n, 1, 4);
     launch_adj_raygen(l, q, aq, r, 0, r.g_base, n);
-    for (int d = 0; d < r.max_depth; ++d) {
+    for (int d = 0; d < r.max_depth; ++d) {   // (the closest-hit launch empties the next queues)
         q.stats = prof_stats(ctx, DPCS_STAGE_TRACE);
         pr = prof_begin(ctx, DPCS_STAGE_TRACE);
         launch_trace(l, q, cur, r, nullptr, n);

@@ -349,12 +349,14 @@ void dpcs_server_s::wave(Launch& l) {
         }
         for (const Seg& s : segs)
             if (s.q->adjoint) launch_adj_pixel(l, q, aq, s.q->r, s.a, s.b, nullptr);
-        launch_set_count(l, q.cnt, 0, (uint32_t)n_adj, 1, 4);
+        // queue sizes: the replay's rotate over their own slots; re-tracing, the
+        // closest-hit launch empties the queues shading appends to
+        if (binq || replay) launch_set_count(l, q.cnt, REPLAY_CNT, (uint32_t)n_adj, REPLAY_CNT + 1, REPLAY_CNT + 2);
+        else launch_set_count(l, q.cnt, 0, (uint32_t)n_adj, 1, 4);
         for (const Seg& s : segs)
             if (s.q->adjoint) launch_adj_raygen(l, q, aq, s.q->r, s.q->slot, s.q->r.g_base, (s.b - s.a) * s.q->r.spp);
         cur = 0;
         for (int d = 0; d < max_depth; ++d) {
-            launch_set_count(l, q.cnt, cur ^ 1, 0, 2, 4);
             if (binq) {
                 launch_adj_replay(l, q, ab, cur, d, binq->r, nullptr, n_adj);
                 if ((d + 1) % BIN_DEPTHS == 0 || d == max_depth - 1) launch_map_flush(l, ab, binq->r);
