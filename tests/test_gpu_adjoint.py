@@ -6,7 +6,7 @@ from oracle import oracle as O
 from paper_2503_12174_amd import synth
 
 from . import scenes
-from .gpu_util import GRAD_KEYS, VJP_MODES, GpuRun, compare_grads, dev, run_vjp
+from .gpu_util import GRAD_KEYS, VJP_MODES, GpuRun, compare_grads, ctx, dev, run_vjp
 
 pytestmark = pytest.mark.gpu
 
@@ -143,6 +143,27 @@ def test_vjp_corner_200k_sampled_pixels():
     for mode in ("own", "retrace"):
         gpu = run_vjp(run, G, mode=mode)
         compare_grads(gpu, ref, keys=("Ip", "albedo", "roughness", "specular", "crf_gamma", "white_balance"))
+
+
+def test_vjp_headline_step_sampled_pixels():
+    """The benchmark's step at full size (50k triangles, camera and projector 256^2, 64 spp,
+    depth 4, device-built SAH tree): a forward keeping per-sample radiance and path records,
+    then the VJP replaying them (binned map flush), with a cotangent on 24 random clean
+    pixels and zero elsewhere; the oracle differentiates the same pixels."""
+    from paper_2503_12174_amd import dpcs
+    w = synth.corner_50k()
+    sc = O.Scene(w)
+    rng = np.random.default_rng(6)
+    px = rng.choice(256 * 256, 48, replace=False)
+    m = O.render(sc, pixels=px, want=("margin_clip",))["margin_clip"]
+    px = px[(m >= 1).all(axis=1)][:24]
+    assert len(px) >= 20
+    G = np.zeros((256 * 256, 3))
+    G[px] = rng.normal(size=(len(px), 3))
+    G = G.reshape(256, 256, 3)
+    ref = O.render_vjp(sc, G, pixels=px)
+    run = GpuRun(w, scene=dpcs.Scene(ctx(), w.mesh, bvh="sah"))
+    compare_grads(run_vjp(run, G, mode="records"), ref)
 
 
 def test_vjp_rejects_bad_arguments():
