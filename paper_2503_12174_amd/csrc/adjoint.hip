@@ -289,11 +289,10 @@ __global__ void __launch_bounds__(BLOCK) k_adj_pixel(Queues q, AdjQueues aq, Req
 // order (FP64), so the scalar gradients are the same on every run
 // one workgroup per value k < nv (grid nv): dst[k] += the sum of the nb partials of k, in
 // a fixed order (per thread a strided run, then a tree)
-__global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ part, int nb, int stride, int nv,
-                                                      float* __restrict__ dst) {
-    __shared__ double red[256];
-    const int k = blockIdx.x;
-    if (k >= nv) return;
+// value k of nb per-block partials (stride floats apart) added to dst[k] by thread 0, in
+// a fixed order (strided FP64 sums, then a tree); a 256-thread workgroup calls it whole
+__device__ __forceinline__ void sum_partial(const float* __restrict__ part, int nb, int stride, int k,
+                                            float* __restrict__ dst, double* red) {
     double s = 0.0;
     for (int b = threadIdx.x; b < nb; b += 256) s += part[(size_t)b * stride + k];
     red[threadIdx.x] = s;
@@ -303,6 +302,13 @@ __global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ 
         __syncthreads();
     }
     if (threadIdx.x == 0 && red[0] != 0.0) dst[k] += (float)red[0];
+    __syncthreads();   // (red is reused by the next call)
+}
+__global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ part, int nb, int stride, int nv,
+                                                      float* __restrict__ dst) {
+    __shared__ double red[256];
+    if ((int)blockIdx.x >= nv) return;
+    sum_partial(part, nb, stride, blockIdx.x, dst, red);
 }
 
 // replay camera rays at queue index = batch sample index (the depth-0 shading takes
@@ -1355,7 +1361,17 @@ __global__ void __launch_bounds__(BLOCK) k_adj_replay_ext(Queues q, AdjQueues aq
 
 // ---------------------------------------------------------------- finish
 // Eq. 1 backward per texel: z = g_p M y, y = I_p^gamma_p, E_p = max(0, z)
-__global__ void k_adj_prf(ReqDesc r, float* __restrict__ d_proj, float* __restrict__ acc) {
+__device__ __forceinline__ void adj_maps(const ReqDesc& r, int t, float* d_albedo, float* d_rough, float* d_spec,
+                                         float* d_metal, float* d_nmap);
+// workgroups [0, gp): the PRF backward per projector texel (per-block partials of the
+// 12 scalars); the rest: the map cotangents copied out per texel (adj_maps)
+__global__ void __launch_bounds__(BLOCK) k_adj_prf(ReqDesc r, float* __restrict__ d_proj, float* __restrict__ acc,
+                                                   int gp, float* d_albedo, float* d_rough, float* d_spec,
+                                                   float* d_metal, float* d_nmap) {
+    if ((int)blockIdx.x >= gp) {   // uniform per workgroup
+        adj_maps(r, (blockIdx.x - gp) * BLOCK + threadIdx.x, d_albedo, d_rough, d_spec, d_metal, d_nmap);
+        return;
+    }
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     float part[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // d gamma_p[3], d M[9]
     if (t < r.Wp * r.Hp) {
@@ -1397,9 +1413,8 @@ __global__ void k_adj_prf(ReqDesc r, float* __restrict__ d_proj, float* __restri
 }
 
 // scalar gradients and the de-interleaving of the map cotangents
-__global__ void k_adj_maps(ReqDesc r, float* d_albedo, float* d_rough, float* d_spec, float* d_metal,
-                           float* d_nmap) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void adj_maps(const ReqDesc& r, int t, float* d_albedo, float* d_rough, float* d_spec,
+                                         float* d_metal, float* d_nmap) {
     if (t >= r.tw * r.th) return;
     const float* s = r.d_tex + (size_t)r.dtex_c * t;
     if (r.dtex_c == 9) {
@@ -1426,7 +1441,12 @@ __global__ void k_adj_maps(ReqDesc r, float* d_albedo, float* d_rough, float* d_
     if (d_spec) d_spec[t] = r.brdf ? s[4] : 0.f;
 }
 
-__global__ void k_adj_scalars(ReqDesc r, const float* __restrict__ acc, float* d_scalars) {
+// one 256-thread workgroup: the PRF backward's partials (nb blocks) into acc[8..20), then
+// the scalar gradients
+__global__ void __launch_bounds__(256) k_adj_scalars(ReqDesc r, float* __restrict__ acc, float* d_scalars, int nb) {
+    __shared__ double red[256];
+    if (r.d_part)
+        for (int k = 0; k < 12; ++k) sum_partial(r.d_part, nb, 12, k, acc + 8, red);
     if (threadIdx.x != 0 || !d_scalars) return;
     for (int k = 0; k < 12; ++k) d_scalars[k] = acc[8 + k];           // gamma_p, M
     for (int c = 0; c < 3; ++c) {
@@ -1526,12 +1546,11 @@ void launch_map_flush(const Launch& l, const AdjQueues& aq, const ReqDesc& r) {
 void launch_adj_finish(const Launch& l, const ReqDesc& r, float* d_proj, float* d_albedo, float* d_rough,
                        float* d_spec, float* d_scalars, float* acc, float* d_metal, float* d_nmap) {
     const unsigned g = grid_of((int64_t)r.Wp * r.Hp, BLOCK);
-    hipLaunchKernelGGL(k_adj_prf, dim3(g), dim3(BLOCK), 0, l.st, r, d_proj, acc);
-    if (r.d_part) hipLaunchKernelGGL(k_sum_partials, dim3(12), dim3(256), 0, l.st, r.d_part, (int)g, 12, 12, acc + 8);
-    if (d_albedo || d_rough || d_spec || d_metal || d_nmap)
-        hipLaunchKernelGGL(k_adj_maps, dim3(grid_of((int64_t)r.tw * r.th, 256)), dim3(256), 0, l.st, r, d_albedo,
-                           d_rough, d_spec, d_metal, d_nmap);
-    hipLaunchKernelGGL(k_adj_scalars, dim3(1), dim3(64), 0, l.st, r, (const float*)acc, d_scalars);
+    const bool maps = d_albedo || d_rough || d_spec || d_metal || d_nmap;
+    const unsigned gm = maps ? grid_of((int64_t)r.tw * r.th, BLOCK) : 0u;
+    hipLaunchKernelGGL(k_adj_prf, dim3(g + gm), dim3(BLOCK), 0, l.st, r, d_proj, acc, (int)g, d_albedo, d_rough,
+                       d_spec, d_metal, d_nmap);
+    hipLaunchKernelGGL(k_adj_scalars, dim3(1), dim3(256), 0, l.st, r, acc, d_scalars, (int)g);
 }
 
 }  // namespace dpcs
