@@ -44,6 +44,22 @@ def test_vjp_matches_oracle_ggx(clip, env):
         print(f"{mode}: worst global relative gradient error {worst:.2e}")
 
 
+@pytest.mark.parametrize("depth", [1, 9])
+def test_vjp_direct_only_and_deep_paths(depth):
+    """Depth 1 (direct light only: no bounce, no pending cotangents) and depth 9, whose
+    replay flushes its binned map cotangents three times (after depths 4, 8 and 9) and
+    carries pending cotangents across each flush, with the environment light on."""
+    w = scenes.c3_ggx(spp=4, seed=41, max_depth=depth)
+    w.env = np.array([0.05, 0.04, 0.06])
+    sc = O.Scene(w)
+    G = _clean_cotangent(w, 7, sc)
+    ref = O.render_vjp(sc, G)
+    run = GpuRun(w)
+    for mode in VJP_MODES:
+        worst = compare_grads(run_vjp(run, G, mode=mode), ref)
+        print(f"depth {depth} {mode}: worst global relative gradient error {worst:.2e}")
+
+
 def test_vjp_non_square_devices_and_maps():
     """Camera, projector and maps of different, non-square sizes (the capture aspect
     ratios of the paper's setup, scaled down): a swapped width and height anywhere in
