@@ -60,6 +60,22 @@ def test_vjp_direct_only_and_deep_paths(depth):
         print(f"depth {depth} {mode}: worst global relative gradient error {worst:.2e}")
 
 
+def test_vjp_deep_paths_in_a_corner():
+    """Depth 8 in the folded corner (concave: paths keep bouncing between floor and wall,
+    so every depth holds records and two full flushes run), 512^2 GGX maps, env on."""
+    from paper_2503_12174_amd import dpcs
+    w = synth.corner_50k(spp=8, max_depth=8, res=48, n_quads=10, env=0.05)
+    sc = O.Scene(w)
+    hits = O.render(sc, want=("hits",))["hits"]
+    assert (hits[:, :, 5] >= 0).sum() >= 10   # records past the first flush
+    G = _clean_cotangent(w, 9, sc)
+    ref = O.render_vjp(sc, G)
+    run = GpuRun(w, scene=dpcs.Scene(ctx(), w.mesh, bvh="sah"))
+    for mode in VJP_MODES:
+        worst = compare_grads(run_vjp(run, G, mode=mode), ref)
+        print(f"corner depth 8 {mode}: worst global relative gradient error {worst:.2e}")
+
+
 def test_vjp_non_square_devices_and_maps():
     """Camera, projector and maps of different, non-square sizes (the capture aspect
     ratios of the paper's setup, scaled down): a swapped width and height anywhere in
