@@ -450,7 +450,7 @@ __global__ void __launch_bounds__(BLOCK) k_adj_shade(Queues q, AdjQueues aq, int
         }
         const bool to_rec = UNI && aq.tb.rec && pend_on;
         const bool pred[4] = {cont, shp, she, to_rec};
-        uint32_t* const ctr[4] = {&q.cnt[nxt], &q.cnt[2], &q.cnt[3], aq.tb.count};
+        uint32_t* const ctr[4] = {&q.cnt[nxt], &q.cnt[shadow_slot(cur, 0)], &q.cnt[shadow_slot(cur, 1)], aq.tb.count};
         uint32_t at[4];
         block_append<4>(pred, ctr, at);
         const uint32_t jn = at[0], jp = at[1], je = at[2];
@@ -505,7 +505,7 @@ __global__ void __launch_bounds__(TB) ADJ_SHADOW_OCCUPANCY k_adj_shadow(Queues q
     __shared__ int stack[(SHORT_STACK + 1) * TB];
     __shared__ float4 ltop[UNI ? 8 * TOP_NODES : 1];
     int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL;
-    const uint32_t n = q.cnt[2 + which];
+    const uint32_t n = q.cnt[shadow_slot(nxt ^ 1, which)];
     TopNodes top{nullptr, 0u};
     if constexpr (UNI)   // one tree for the whole launch: stage its top levels
         if (uni.nodes4) top = stage_top<TB>(ltop, uni.nodes4, uni.top_nodes);

@@ -107,8 +107,8 @@ struct Queues {
     float4* sc[2];     // shadow contribution (w: batch sample index)
     float* st[2];      // shadow tmax
     float4* L;         // per batch sample radiance (rgb, -)
-    uint32_t* cnt;     // [0], [1] path queue sizes, [2], [3] shadow queue sizes, [4..6] the
-                       // replay's path queue sizes (by depth mod 3)
+    uint32_t* cnt;     // [0], [1] path queue sizes, [4..6] the replay's path queue sizes (by
+                       // depth mod 3), [8..11] shadow queue sizes (shadow_slot)
     int64_t cap;       // path capacity
     unsigned long long* stats;   // null, or [0] nodes visited, [1] triangles tested (profiling)
     int* spill;        // traversal stack overflow: SPILL ints per thread of a capped grid
@@ -200,6 +200,13 @@ struct AdjQueues {
 };
 
 constexpr int REPLAY_CNT = 4;   // first of the replay's three queue-size slots in Queues::cnt
+// The shadow queues' sizes alternate by depth parity: shading at depth d appends to
+// q.cnt[shadow_slot(d & 1, which)] (every depth loop starts with cur = 0, so d & 1 = cur),
+// so the closest-hit launch of depth d + 1, which empties the slots shading at d + 1
+// appends to, leaves intact the sizes that depth d's shadow launch reads (the two may
+// run at the same time on two streams).
+constexpr int SHADOW_CNT = 8;
+__host__ __device__ constexpr int shadow_slot(int parity, int which) { return SHADOW_CNT + 2 * parity + which; }
 struct Launch {
     hipStream_t st;
     int grid_cap;      // upper bound on workgroups of grid-stride kernels

@@ -107,8 +107,8 @@ __global__ void __launch_bounds__(TB) TRAVERSAL_OCCUPANCY k_trace(Queues q, int 
     // only its own queue's count, and whatever read the others ran before it)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         q.cnt[cur ^ 1] = 0u;
-        q.cnt[2] = 0u;
-        q.cnt[3] = 0u;
+        q.cnt[shadow_slot(cur, 0)] = 0u;
+        q.cnt[shadow_slot(cur, 1)] = 0u;
     }
     TopNodes top{nullptr, 0u};
     if constexpr (UNI)   // one tree for the whole launch: stage its top levels
@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(BLOCK) k_shade(Queues q, int cur, int depth, R
         }
         const bool pred[3] = {cont, shp, she};
         const int key[3] = {octant(nd.x, nd.y, nd.z), 0, octant(ed.x, ed.y, ed.z)};
-        uint32_t* const ctr[3] = {&q.cnt[nxt], &q.cnt[2], &q.cnt[3]};
+        uint32_t* const ctr[3] = {&q.cnt[nxt], &q.cnt[shadow_slot(cur, 0)], &q.cnt[shadow_slot(cur, 1)]};
         uint32_t at[3];
         block_append_keyed<3, 8>(pred, key, ctr, at);
         const uint32_t jn = at[0], jp = at[1], je = at[2];
@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(TB) SHADOW_OCCUPANCY k_shadow(Queues q, int wh
     __shared__ int stack[(SHORT_STACK + 1) * TB];
     __shared__ float4 ltop[TREE ? 8 * TOP_NODES : 1];
     int* spill = q.spill + (size_t)blockIdx.x * TB * SPILL;
-    const uint32_t n = q.cnt[2 + which];
+    const uint32_t n = q.cnt[shadow_slot(depth & 1, which)];
     TopNodes top{nullptr, 0u};
     if constexpr (TREE)
         if (uni.nodes4) top = stage_top<TB>(ltop, uni.nodes4, uni.top_nodes);

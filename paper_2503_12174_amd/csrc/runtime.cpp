@@ -97,7 +97,7 @@ void carve_queues(char* b, int64_t cap, int trace_blocks, Queues& q) {
     }
     q.hit = (int*)take(4 * c);
     q.L = (float4*)take(16 * c);
-    q.cnt = (uint32_t*)take(4 * (REPLAY_CNT + 3));
+    q.cnt = (uint32_t*)take(4 * (SHADOW_CNT + 4));
     q.spill = (int*)take(4 * (size_t)trace_blocks * TRACE_TB * SPILL);
     q.trace_blocks = trace_blocks;
     q.cap = cap;
@@ -390,6 +390,12 @@ extern "C" void dpcs_context_destroy(dpcs_context ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto& kv : ctx->pool) (void)hipFree(kv.second.first);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->side) {
+        (void)hipStreamSynchronize(ctx->side);
+        (void)hipStreamDestroy(ctx->side);
+    }
+    if (ctx->ev_shade) (void)hipEventDestroy(ctx->ev_shade);
+    if (ctx->ev_shadow) (void)hipEventDestroy(ctx->ev_shadow);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->dstats) (void)hipFree(ctx->dstats);
     delete ctx;
@@ -739,7 +745,35 @@ bool prepare_request(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, 
     return true;
 }
 
-void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t b, bool finalize) {
+// the side stream and its events, made on first use (false: run on one stream)
+static bool side_stream(dpcs_context ctx) {
+    if (ctx->side) return true;
+    if (ctx->side_failed) return false;
+    hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (s) (void)hipStreamDestroy(s);
+        if (a) (void)hipEventDestroy(a);
+        ctx->side_failed = true;
+        return false;
+    }
+    ctx->side = s;
+    ctx->ev_shade = a;
+    ctx->ev_shadow = b;
+    return true;
+}
+
+int* side_spill(dpcs_context ctx, const Queues& q) {
+    dpcs_status st = DPCS_OK;
+    int* p = (int*)scratch(ctx, "fwd.spill2", 4 * (size_t)q.trace_blocks * TRACE_TB * SPILL, &st);
+    if (!p) ctx->err.clear();   // the forward then runs on one stream
+    return p;
+}
+
+void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t b, bool finalize, int* spill2) {
     Launch l{ctx->stream, ctx->grid_cap};
     const uint32_t n = (b - a) * (uint32_t)r.spp;
     r.g_base = a * (uint32_t)r.spp;
@@ -750,24 +784,41 @@ void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t 
     int pr = prof_begin(ctx, DPCS_STAGE_RAYGEN);
     prof_end(ctx, pr, nullptr, n);
     int cur = 0;
+    // A depth's shadow rays run on the side stream (with their own spill region) while the
+    // next depth's closest hit runs here, so each fills the other's tail; shading waits
+    // for the previous depth's shadow rays (both add to the samples' radiance), and so
+    // does the finalize.  Profiling keeps every launch on this stream.
+    const bool side = spill2 && !ctx->prof_mode && side_stream(ctx);
+    Queues qs = q;
+    qs.spill = spill2;
+    const Launch ls{ctx->side, ctx->grid_cap};
     for (int d = 0; d < r.max_depth; ++d) {
-        // (the closest-hit launch empties the next path queue and the shadow queues)
+        // (the closest-hit launch empties the next path queue and this depth's shadow queues)
         q.stats = prof_stats(ctx, DPCS_STAGE_TRACE);
         pr = prof_begin(ctx, DPCS_STAGE_TRACE);
         launch_trace(l, q, cur, r, nullptr, n, d == 0);
         prof_end(ctx, pr, q.cnt + cur, 0);
+        if (side && d > 0) (void)hipStreamWaitEvent(ctx->stream, ctx->ev_shadow, 0);
         pr = prof_begin(ctx, DPCS_STAGE_SHADE);
         launch_shade(l, q, cur, d, r, nullptr, n, d == 0);
         prof_end(ctx, pr, q.cnt + cur, 0);
         q.stats = prof_stats(ctx, DPCS_STAGE_SHADOW);
-        for (int w = 0; w < (r.env_on ? 2 : 1); ++w) {
-            pr = prof_begin(ctx, DPCS_STAGE_SHADOW);
-            launch_shadow(l, q, w, r, nullptr, n, d);
-            prof_end(ctx, pr, q.cnt + 2 + w, 0);
+        if (side) {
+            (void)hipEventRecord(ctx->ev_shade, ctx->stream);
+            (void)hipStreamWaitEvent(ctx->side, ctx->ev_shade, 0);
+            for (int w = 0; w < (r.env_on ? 2 : 1); ++w) launch_shadow(ls, qs, w, r, nullptr, n, d);
+            (void)hipEventRecord(ctx->ev_shadow, ctx->side);
+        } else {
+            for (int w = 0; w < (r.env_on ? 2 : 1); ++w) {
+                pr = prof_begin(ctx, DPCS_STAGE_SHADOW);
+                launch_shadow(l, q, w, r, nullptr, n, d);
+                prof_end(ctx, pr, q.cnt + shadow_slot(cur, w), 0);
+            }
         }
         q.stats = nullptr;
         cur ^= 1;
     }
+    if (side) (void)hipStreamWaitEvent(ctx->stream, ctx->ev_shadow, 0);
     if (finalize) {
         pr = prof_begin(ctx, DPCS_STAGE_FINALIZE);
         launch_finalize(l, q, r, nullptr, 0, a, b);
@@ -816,7 +867,7 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
         for (int w = 0; w < (r.env_on ? 2 : 1); ++w) {
             pr = prof_begin(ctx, DPCS_STAGE_ADJ_SHADOW);
             launch_adj_shadow(l, q, aq, w, cur ^ 1, r, nullptr, n);
-            prof_end(ctx, pr, q.cnt + 2 + w, 0);
+            prof_end(ctx, pr, q.cnt + shadow_slot(cur, w), 0);
         }
         q.stats = nullptr;
         if ((aq.tb.rec || aq.eb.rec) && ((d + 1) % BIN_DEPTHS == 0 || d == r.max_depth - 1)) {
@@ -901,7 +952,9 @@ static dpcs_status render_impl(dpcs_context ctx, dpcs_scene scene, const dpcs_re
         if (!make_queues(ctx, "fwd.queues", cap, q, &st)) return st;
     }
     const int64_t ppw = std::max<int64_t>(1, cap / r.spp);   // whole pixels per wave
-    for (int64_t a = 0; a < npix; a += ppw) forward_wave(ctx, q, r, (uint32_t)a, (uint32_t)std::min(npix, a + ppw), true);
+    int* spill2 = noalloc ? nullptr : side_spill(ctx, q);     // (the no-alloc path stays on one stream)
+    for (int64_t a = 0; a < npix; a += ppw)
+        forward_wave(ctx, q, r, (uint32_t)a, (uint32_t)std::min(npix, a + ppw), true, spill2);
     ctx->prof_mode = prof_mode;
     if (!hip_ok(ctx, hipGetLastError(), "kernel launch")) return DPCS_E_DEVICE;
     ctx->err.clear();

@@ -39,6 +39,11 @@ struct dpcs_context_s {
     unsigned long long* dstats = nullptr;  // device [DPCS_NUM_STAGES][2]
     void* noalloc = nullptr;               // this device's copy of the no-alloc scratch array
     int noalloc_err = 0;                   // hipError_t of its address lookup
+    // second stream (default priority) for a depth's shadow rays beside the next depth's
+    // closest hit, and the two events that order them (made on first use)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_shade = nullptr, ev_shadow = nullptr;
+    bool side_failed = false;
 };
 
 struct dpcs_scene_s {
@@ -105,7 +110,13 @@ void make_map_bins(dpcs_context ctx, ZeroList& zl, MapBins& mb, const char* name
 bool prepare_request(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, const char* tag, dpcs_status* st);
 // one launch wave of the forward path over pixels [a, b) (whole pixels); per-sample
 // radiance lands in q.L; finalize writes the request's outputs
-void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t b, bool finalize);
+// spill2: a second traversal spill region like q.spill (null: every launch on the
+// context's stream, one after the other)
+void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t b, bool finalize,
+                  int* spill2 = nullptr);
+// the second spill region of forward_wave for q (null when unavailable: then the
+// forward runs on one stream)
+int* side_spill(dpcs_context ctx, const Queues& q);
 // one launch wave of the path-replay adjoint over pixels [a, b) (q.L holds the samples
 // unless sample_L is given)
 void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, uint32_t a, uint32_t b,

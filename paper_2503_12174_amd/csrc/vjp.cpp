@@ -98,12 +98,13 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
         make_map_bins(ctx, zl, aq.eb, "vjp.ep_bins", r.Wp, r.Hp, 3, 6, ppw * r.spp * k);
     }
     zl.launch();
+    int* spill2 = own_rec ? side_spill(ctx, q) : nullptr;
     for (int64_t a = 0; a < npix; a += ppw) {
         const uint32_t b = (uint32_t)std::min(npix, a + ppw);
         if (own_rec) {
             r.rec = wave_rec;
             r.rec_g0 = (uint32_t)a * (uint32_t)r.spp;
-            forward_wave(ctx, q, r, (uint32_t)a, b, false);
+            forward_wave(ctx, q, r, (uint32_t)a, b, false, spill2);
         } else {
             r.rec = const_cast<uint32_t*>(path_records);   // read only in the adjoint
             r.rec_g0 = 0;
