@@ -827,7 +827,7 @@ void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t 
 }
 
 void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, uint32_t a, uint32_t b,
-                  const float* sample_L, float4* pix_dE) {
+                  const float* sample_L, float4* pix_dE, int* spill2) {
     Launch l{ctx->stream, ctx->grid_cap};
     const uint32_t n = (b - a) * (uint32_t)r.spp;
     r.g_base = a * (uint32_t)r.spp;
@@ -855,28 +855,45 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
     }
     launch_set_count(l, q.cnt, 0, n, 1, 4);
     launch_adj_raygen(l, q, aq, r, 0, r.g_base, n);
+    // as in the forward: a depth's shadow rays on the side stream beside the next depth's
+    // closest hit; the adjoint shading and the map flush (which read what they write:
+    // the next paths' remaining radiance, map records) wait for them
+    const bool side = spill2 && !ctx->prof_mode && side_stream(ctx);
+    Queues qs = q;
+    qs.spill = spill2;
+    const Launch ls{ctx->side, ctx->grid_cap};
     for (int d = 0; d < r.max_depth; ++d) {   // (the closest-hit launch empties the next queues)
         q.stats = prof_stats(ctx, DPCS_STAGE_TRACE);
         pr = prof_begin(ctx, DPCS_STAGE_TRACE);
         launch_trace(l, q, cur, r, nullptr, n);
         prof_end(ctx, pr, q.cnt + cur, 0);
+        if (side && d > 0) (void)hipStreamWaitEvent(ctx->stream, ctx->ev_shadow, 0);
         pr = prof_begin(ctx, DPCS_STAGE_ADJ_SHADE);
         launch_adj_shade(l, q, aq, cur, d, r, nullptr, n);
         prof_end(ctx, pr, q.cnt + cur, 0);
         q.stats = prof_stats(ctx, DPCS_STAGE_ADJ_SHADOW);
-        for (int w = 0; w < (r.env_on ? 2 : 1); ++w) {
-            pr = prof_begin(ctx, DPCS_STAGE_ADJ_SHADOW);
-            launch_adj_shadow(l, q, aq, w, cur ^ 1, r, nullptr, n);
-            prof_end(ctx, pr, q.cnt + shadow_slot(cur, w), 0);
+        if (side) {
+            (void)hipEventRecord(ctx->ev_shade, ctx->stream);
+            (void)hipStreamWaitEvent(ctx->side, ctx->ev_shade, 0);
+            for (int w = 0; w < (r.env_on ? 2 : 1); ++w) launch_adj_shadow(ls, qs, aq, w, cur ^ 1, r, nullptr, n);
+            (void)hipEventRecord(ctx->ev_shadow, ctx->side);
+        } else {
+            for (int w = 0; w < (r.env_on ? 2 : 1); ++w) {
+                pr = prof_begin(ctx, DPCS_STAGE_ADJ_SHADOW);
+                launch_adj_shadow(l, q, aq, w, cur ^ 1, r, nullptr, n);
+                prof_end(ctx, pr, q.cnt + shadow_slot(cur, w), 0);
+            }
         }
         q.stats = nullptr;
         if ((aq.tb.rec || aq.eb.rec) && ((d + 1) % BIN_DEPTHS == 0 || d == r.max_depth - 1)) {
+            if (side) (void)hipStreamWaitEvent(ctx->stream, ctx->ev_shadow, 0);
             pr = prof_begin(ctx, DPCS_STAGE_OTHER);
             launch_map_flush(l, aq, r);
             prof_end(ctx, pr, nullptr, 0);
         }
         cur ^= 1;
     }
+    if (side) (void)hipStreamWaitEvent(ctx->stream, ctx->ev_shadow, 0);
 }
 
 }  // namespace dpcs

@@ -120,7 +120,7 @@ int* side_spill(dpcs_context ctx, const Queues& q);
 // one launch wave of the path-replay adjoint over pixels [a, b) (q.L holds the samples
 // unless sample_L is given)
 void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, uint32_t a, uint32_t b,
-                  const float* sample_L, float4* pix_dE = nullptr);
+                  const float* sample_L, float4* pix_dE = nullptr, int* spill2 = nullptr);
 // the boundary part of the camera-pose gradient at the images of mesh edges, added into
 // dst[0..11] (R row-major, t); pix_dE: per-pixel cotangent of the clipped pixel means;
 // K the camera intrinsics; q's paths are reused (at most q.cap / 2 edge points per wave)

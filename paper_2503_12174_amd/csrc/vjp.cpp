@@ -98,7 +98,8 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
         make_map_bins(ctx, zl, aq.eb, "vjp.ep_bins", r.Wp, r.Hp, 3, 6, ppw * r.spp * k);
     }
     zl.launch();
-    int* spill2 = own_rec ? side_spill(ctx, q) : nullptr;
+    // the forward run here and the re-tracing replay put shadow rays on the side stream
+    int* spill2 = (own_rec || !path_records) ? side_spill(ctx, q) : nullptr;
     for (int64_t a = 0; a < npix; a += ppw) {
         const uint32_t b = (uint32_t)std::min(npix, a + ppw);
         if (own_rec) {
@@ -109,7 +110,7 @@ extern "C" dpcs_status dpcs_render_vjp(dpcs_context ctx, dpcs_scene scene, const
             r.rec = const_cast<uint32_t*>(path_records);   // read only in the adjoint
             r.rec_g0 = 0;
         }
-        adjoint_wave(ctx, q, aq, r, (uint32_t)a, b, sample_radiance, pix_dE);
+        adjoint_wave(ctx, q, aq, r, (uint32_t)a, b, sample_radiance, pix_dE, spill2);
     }
     if (pix_dE) {
         st = camera_edge_term(ctx, scene, r, q, edge_density, params->camera.K, pix_dE, acc + 20);
