@@ -154,6 +154,11 @@ size_t request_bytes(const ReqDesc& r, bool adjoint) {
 struct dpcs_server_s {
     dpcs_context ctx = nullptr;
     hipStream_t st = nullptr;
+    // a depth's shadow rays run on `side` (default priority, own spill region) beside the
+    // next depth's closest hit on `st`, ordered by the two events (null side: one stream)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_shade = nullptr, ev_shadow = nullptr;
+    int* spill2 = nullptr;
     size_t budget = 0, shared_bytes = 0, admitted_bytes = 0;
     int max_slots = 0;
     int64_t cap = 0;
@@ -315,13 +320,28 @@ void dpcs_server_s::wave(Launch& l) {
     for (const Seg& s : segs) launch_raygen(l, q, s.q->r, table, s.q->slot, s.q->r.g_base, (s.b - s.a) * s.q->r.spp,
                                             false, nullptr);
     int cur = 0;
+    // a depth's shadow rays on the side stream beside the next depth's closest hit;
+    // shading (both add to the samples' radiance) and the finalize wait for them
+    Queues qs = q;
+    qs.spill = spill2;
+    const Launch ls{side, ctx->grid_cap};
     for (int d = 0; d < max_depth; ++d) {
         launch_trace(l, q, cur, any, nullptr, used);   // (empties the queues shading appends to)
+        if (side && d > 0) (void)hipStreamWaitEvent(st, ev_shadow, 0);
         launch_shade(l, q, cur, d, any, table, used);
-        launch_shadow(l, q, 0, any, table, used, d, true);
-        if (env) launch_shadow(l, q, 1, any, table, used, d, true);
+        if (side) {
+            (void)hipEventRecord(ev_shade, st);
+            (void)hipStreamWaitEvent(side, ev_shade, 0);
+            launch_shadow(ls, qs, 0, any, table, used, d, true);
+            if (env) launch_shadow(ls, qs, 1, any, table, used, d, true);
+            (void)hipEventRecord(ev_shadow, side);
+        } else {
+            launch_shadow(l, q, 0, any, table, used, d, true);
+            if (env) launch_shadow(l, q, 1, any, table, used, d, true);
+        }
         cur ^= 1;
     }
+    if (side) (void)hipStreamWaitEvent(st, ev_shadow, 0);
     for (const Seg& s : segs) launch_finalize(l, q, s.q->r, table, s.q->slot, s.a, s.b);
     // adjoint replay of the compensation-step segments (a dense prefix of the wave)
     if (any_adj) {
@@ -362,14 +382,24 @@ void dpcs_server_s::wave(Launch& l) {
                 if ((d + 1) % BIN_DEPTHS == 0 || d == max_depth - 1) launch_map_flush(l, ab, binq->r);
             } else if (replay) {
                 launch_adj_replay(l, q, aq, cur, d, any, table, n_adj);
-            } else {
+            } else {   // (adjoint shadow rays beside the next closest hit, as in the forward)
                 launch_trace(l, q, cur, any, nullptr, n_adj);
+                if (side && d > 0) (void)hipStreamWaitEvent(st, ev_shadow, 0);
                 launch_adj_shade(l, q, aq, cur, d, any, table, n_adj);
-                launch_adj_shadow(l, q, aq, 0, cur ^ 1, any, table, n_adj);
-                if (env) launch_adj_shadow(l, q, aq, 1, cur ^ 1, any, table, n_adj);
+                if (side) {
+                    (void)hipEventRecord(ev_shade, st);
+                    (void)hipStreamWaitEvent(side, ev_shade, 0);
+                    launch_adj_shadow(ls, qs, aq, 0, cur ^ 1, any, table, n_adj);
+                    if (env) launch_adj_shadow(ls, qs, aq, 1, cur ^ 1, any, table, n_adj);
+                    (void)hipEventRecord(ev_shadow, side);
+                } else {
+                    launch_adj_shadow(l, q, aq, 0, cur ^ 1, any, table, n_adj);
+                    if (env) launch_adj_shadow(l, q, aq, 1, cur ^ 1, any, table, n_adj);
+                }
             }
             cur ^= 1;
         }
+        if (side && !binq && !replay) (void)hipStreamWaitEvent(st, ev_shadow, 0);
     }
     ++st_waves;
     st_samples += used + n_adj;
@@ -497,7 +527,7 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     // TRACE_TB paths of a wave
     const int tblocks = (int)std::min<int64_t>(trace_grid_cap(ctx->grid_cap, TRACE_ROUNDS), (s->cap + TRACE_TB - 1) / TRACE_TB);
     const size_t spill_bytes = 4 * (size_t)tblocks * TRACE_TB * SPILL;
-    const size_t qbytes = c * per_path + 64 * 256 + spill_bytes + 4 * 8 * c;
+    const size_t qbytes = c * per_path + 64 * 256 + 2 * spill_bytes + 4 * 8 * c;
     s->shared_bytes = qbytes + sizeof(ReqDesc) * (size_t)max_slots;
     if (s->shared_bytes >= s->budget) {
         delete s;
@@ -513,6 +543,16 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     if (binning) s->shared_bytes += bins_bytes;
     const size_t arena_bytes = s->budget - s->shared_bytes;
     bool ok = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) == hipSuccess;
+    if (ok && (hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess ||
+               hipEventCreateWithFlags(&s->ev_shade, hipEventDisableTiming) != hipSuccess ||
+               hipEventCreateWithFlags(&s->ev_shadow, hipEventDisableTiming) != hipSuccess)) {
+        (void)hipGetLastError();   // run every wave on one stream
+        if (s->side) (void)hipStreamDestroy(s->side);
+        if (s->ev_shade) (void)hipEventDestroy(s->ev_shade);
+        s->side = nullptr;
+        s->ev_shade = nullptr;
+        s->ev_shadow = nullptr;
+    }
     ok = ok && hipMalloc((void**)&s->table, sizeof(ReqDesc) * max_slots) == hipSuccess;
     ok = ok && hipMalloc(&s->qbuf, qbytes) == hipSuccess;
     ok = ok && hipMalloc((void**)&s->arena_base, arena_bytes) == hipSuccess;
@@ -526,6 +566,9 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
         if (s->table) (void)hipFree(s->table);
         if (s->qbuf) (void)hipFree(s->qbuf);
         if (s->st) (void)hipStreamDestroy(s->st);
+        if (s->side) (void)hipStreamDestroy(s->side);
+        if (s->ev_shade) (void)hipEventDestroy(s->ev_shade);
+        if (s->ev_shadow) (void)hipEventDestroy(s->ev_shadow);
         delete s;
         return fail(ctx, DPCS_E_OOM, "server allocation failed");
     }
@@ -562,8 +605,9 @@ extern "C" dpcs_status dpcs_server_create(dpcs_context ctx, size_t memory_budget
     s->aq.delta = (float4*)take(16 * c);
     s->aq.tb = MapBins{};   // several requests' compensation paths: direct scatter (a
     s->aq.eb = MapBins{};   // wave of one request binds the binning buffers instead)
-    s->q.cnt = (uint32_t*)take(16);
+    s->q.cnt = (uint32_t*)take(4 * (SHADOW_CNT + 4));
     s->q.spill = (int*)take(spill_bytes);
+    s->spill2 = (int*)take(spill_bytes);
     s->q.trace_blocks = tblocks;
     s->rec = (uint32_t*)take(4 * 8 * c);
     s->rec_cap = 8 * (int64_t)c;
@@ -688,6 +732,12 @@ extern "C" dpcs_status dpcs_server_destroy(dpcs_server s) {
     (void)hipFree(s->table);
     if (s->tex_bins) (void)hipFree(s->tex_bins);
     (void)hipStreamDestroy(s->st);
+    if (s->side) {
+        (void)hipStreamSynchronize(s->side);
+        (void)hipStreamDestroy(s->side);
+        (void)hipEventDestroy(s->ev_shade);
+        (void)hipEventDestroy(s->ev_shadow);
+    }
     const bool failed = !s->err.empty();
     delete s;
     return failed ? DPCS_E_DEVICE : DPCS_OK;
