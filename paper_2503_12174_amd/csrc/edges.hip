@@ -400,6 +400,13 @@ dpcs_status camera_edge_term(dpcs_context ctx, dpcs_scene sc, const ReqDesc& r, 
     const int64_t nbg_max = (m_max + EDGE_GRAD_TB - 1) / EDGE_GRAD_TB;
     a.part = (float*)scratch(ctx, "edge.partials", sizeof(float) * 12 * nbg_max, &st);
     if (!a.part) return st;
+    // as in the forward: a depth's shadow rays on the side stream beside the next depth's
+    // closest hit, shading and the gradient kernel waiting for them
+    int* spill2 = ctx->prof_mode ? nullptr : side_spill(ctx, qe);
+    const bool sidestream = spill2 && std::min<int64_t>(m_max, (int64_t)total) >= SIDE_MIN_PATHS && side_stream(ctx);
+    Queues qs = qe;
+    qs.spill = spill2;
+    const Launch ls{ctx->side, ctx->grid_cap};
     for (uint64_t k0 = 0; k0 < total; k0 += (uint64_t)m_max) {
         const uint32_t m = (uint32_t)std::min<uint64_t>((uint64_t)m_max, total - k0);
         a.k0 = k0;
@@ -424,10 +431,19 @@ dpcs_status camera_edge_term(dpcs_context ctx, dpcs_scene sc, const ReqDesc& r, 
             int cur = 0;
             for (int d = 0; d < re.max_depth; ++d) {
                 launch_trace(l, qe, cur, re, nullptr, m);   // (empties the queues shading appends to)
+                if (sidestream && d > 0) (void)hipStreamWaitEvent(l.st, ctx->ev_shadow, 0);
                 launch_shade(l, qe, cur, d, re, nullptr, m);
-                for (int w = 0; w < (re.env_on ? 2 : 1); ++w) launch_shadow(l, qe, w, re, nullptr, m, d);
+                if (sidestream) {
+                    (void)hipEventRecord(ctx->ev_shade, l.st);
+                    (void)hipStreamWaitEvent(ctx->side, ctx->ev_shade, 0);
+                    for (int w = 0; w < (re.env_on ? 2 : 1); ++w) launch_shadow(ls, qs, w, re, nullptr, m, d);
+                    (void)hipEventRecord(ctx->ev_shadow, ctx->side);
+                } else {
+                    for (int w = 0; w < (re.env_on ? 2 : 1); ++w) launch_shadow(l, qe, w, re, nullptr, m, d);
+                }
                 cur ^= 1;
             }
+            if (sidestream) (void)hipStreamWaitEvent(l.st, ctx->ev_shadow, 0);
         }
         const unsigned nbg = (m + EDGE_GRAD_TB - 1) / EDGE_GRAD_TB;
         hipLaunchKernelGGL(k_edge_grad, dim3(nbg), dim3(EDGE_GRAD_TB), 0, l.st, qe, r, a);

@@ -206,6 +206,10 @@ constexpr int REPLAY_CNT = 4;   // first of the replay's three queue-size slots 
 // appends to, leaves intact the sizes that depth d's shadow launch reads (the two may
 // run at the same time on two streams).
 constexpr int SHADOW_CNT = 8;
+// Launch waves of fewer paths keep their shadow rays on the main stream: their launches
+// take a few microseconds, less than the two cross-stream waits per depth cost.
+constexpr int64_t SIDE_MIN_PATHS = int64_t(1) << 17;
+constexpr int64_t LOOP_SIDE_MIN_PATHS = int64_t(1) << 21;   // the same for the request loop's waves
 __host__ __device__ constexpr int shadow_slot(int parity, int which) { return SHADOW_CNT + 2 * parity + which; }
 struct Launch {
     hipStream_t st;

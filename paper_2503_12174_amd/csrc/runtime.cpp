@@ -745,8 +745,7 @@ bool prepare_request(dpcs_context ctx, ReqDesc& r, const dpcs_render_params* p, 
     return true;
 }
 
-// the side stream and its events, made on first use (false: run on one stream)
-static bool side_stream(dpcs_context ctx) {
+bool side_stream(dpcs_context ctx) {
     if (ctx->side) return true;
     if (ctx->side_failed) return false;
     hipStream_t s = nullptr;
@@ -788,7 +787,7 @@ void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t 
     // next depth's closest hit runs here, so each fills the other's tail; shading waits
     // for the previous depth's shadow rays (both add to the samples' radiance), and so
     // does the finalize.  Profiling keeps every launch on this stream.
-    const bool side = spill2 && !ctx->prof_mode && side_stream(ctx);
+    const bool side = spill2 && !ctx->prof_mode && (int64_t)n >= SIDE_MIN_PATHS && side_stream(ctx);
     Queues qs = q;
     qs.spill = spill2;
     const Launch ls{ctx->side, ctx->grid_cap};
@@ -858,7 +857,7 @@ void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, 
     // as in the forward: a depth's shadow rays on the side stream beside the next depth's
     // closest hit; the adjoint shading and the map flush (which read what they write:
     // the next paths' remaining radiance, map records) wait for them
-    const bool side = spill2 && !ctx->prof_mode && side_stream(ctx);
+    const bool side = spill2 && !ctx->prof_mode && (int64_t)n >= SIDE_MIN_PATHS && side_stream(ctx);
     Queues qs = q;
     qs.spill = spill2;
     const Launch ls{ctx->side, ctx->grid_cap};

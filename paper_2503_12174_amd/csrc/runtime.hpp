@@ -117,6 +117,8 @@ void forward_wave(dpcs_context ctx, Queues& q, ReqDesc& r, uint32_t a, uint32_t 
 // the second spill region of forward_wave for q (null when unavailable: then the
 // forward runs on one stream)
 int* side_spill(dpcs_context ctx, const Queues& q);
+// the context's side stream and its two events, made on first use (false: run on one stream)
+bool side_stream(dpcs_context ctx);
 // one launch wave of the path-replay adjoint over pixels [a, b) (q.L holds the samples
 // unless sample_L is given)
 void adjoint_wave(dpcs_context ctx, Queues& q, const AdjQueues& aq, ReqDesc& r, uint32_t a, uint32_t b,

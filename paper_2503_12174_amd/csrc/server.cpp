@@ -325,11 +325,14 @@ void dpcs_server_s::wave(Launch& l) {
     Queues qs = q;
     qs.spill = spill2;
     const Launch ls{side, ctx->grid_cap};
+    // (only full-size waves: at 2^20 paths of a small scene, the scene-fit step's waves,
+    // the cross-stream waits cost more than the overlap gained: 2.50 -> 2.62 ms)
+    const bool side_fwd = side && used >= LOOP_SIDE_MIN_PATHS, side_adj = side && n_adj >= LOOP_SIDE_MIN_PATHS;
     for (int d = 0; d < max_depth; ++d) {
         launch_trace(l, q, cur, any, nullptr, used);   // (empties the queues shading appends to)
-        if (side && d > 0) (void)hipStreamWaitEvent(st, ev_shadow, 0);
+        if (side_fwd && d > 0) (void)hipStreamWaitEvent(st, ev_shadow, 0);
         launch_shade(l, q, cur, d, any, table, used);
-        if (side) {
+        if (side_fwd) {
             (void)hipEventRecord(ev_shade, st);
             (void)hipStreamWaitEvent(side, ev_shade, 0);
             launch_shadow(ls, qs, 0, any, table, used, d, true);
@@ -341,7 +344,7 @@ void dpcs_server_s::wave(Launch& l) {
         }
         cur ^= 1;
     }
-    if (side) (void)hipStreamWaitEvent(st, ev_shadow, 0);
+    if (side_fwd) (void)hipStreamWaitEvent(st, ev_shadow, 0);
     for (const Seg& s : segs) launch_finalize(l, q, s.q->r, table, s.q->slot, s.a, s.b);
     // adjoint replay of the compensation-step segments (a dense prefix of the wave)
     if (any_adj) {
@@ -384,9 +387,9 @@ void dpcs_server_s::wave(Launch& l) {
                 launch_adj_replay(l, q, aq, cur, d, any, table, n_adj);
             } else {   // (adjoint shadow rays beside the next closest hit, as in the forward)
                 launch_trace(l, q, cur, any, nullptr, n_adj);
-                if (side && d > 0) (void)hipStreamWaitEvent(st, ev_shadow, 0);
+                if (side_adj && d > 0) (void)hipStreamWaitEvent(st, ev_shadow, 0);
                 launch_adj_shade(l, q, aq, cur, d, any, table, n_adj);
-                if (side) {
+                if (side_adj) {
                     (void)hipEventRecord(ev_shade, st);
                     (void)hipStreamWaitEvent(side, ev_shade, 0);
                     launch_adj_shadow(ls, qs, aq, 0, cur ^ 1, any, table, n_adj);
@@ -399,7 +402,7 @@ void dpcs_server_s::wave(Launch& l) {
             }
             cur ^= 1;
         }
-        if (side && !binq && !replay) (void)hipStreamWaitEvent(st, ev_shadow, 0);
+        if (side_adj && !binq && !replay) (void)hipStreamWaitEvent(st, ev_shadow, 0);
     }
     ++st_waves;
     st_samples += used + n_adj;
