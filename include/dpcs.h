@@ -24,6 +24,10 @@
  *    dpcs_scene_create are HOST pointers and are copied.
  *  - Every render call is asynchronous on the context's HIP stream; nothing syncs
  *    the host except dpcs_scene_create, dpcs_context_synchronize and the server.
+ *    Inside a call, large waves run their shadow rays on a second stream the context
+ *    owns (default priority, made on first use), forked from the context's stream and
+ *    joined back into it by events within the same call: when the context's stream has
+ *    passed a call, all of its work is done.
  *  - Argument checks happen before any launch and return DPCS_E_INVALID with a
  *    message for dpcs_last_error().  Device faults are sticky: the next call on the
  *    context returns DPCS_E_DEVICE.
