@@ -198,6 +198,32 @@ def test_vjp_headline_step_sampled_pixels():
     compare_grads(run_vjp(run, G, mode="records"), ref)
 
 
+def test_overlapped_shadow_rays_give_the_serial_results():
+    """Full-size waves run a depth's shadow rays on a second stream beside the next depth's
+    closest hit; with profiling on every launch stays on one stream.  Forward (image,
+    per-sample radiance, path records) and VJP in all three replay modes: bit-identical."""
+    from paper_2503_12174_amd import dpcs
+    w = synth.corner_50k(spp=32)   # 256^2 x 32 spp: 2^21 paths per wave
+    w.env = np.array([0.03, 0.02, 0.04])   # both shadow queues
+    run = GpuRun(w, scene=dpcs.Scene(ctx(), w.mesh, bvh="sah"))
+    G = np.random.default_rng(3).normal(size=(256, 256, 3))
+    res = {}
+    try:
+        for mode in (0, 1):
+            ctx().set_profiling(mode)
+            out = run.render()
+            res[mode] = dict(img=out["Ic"], L=out["L"], hits=out["hits"],
+                             **{m: run_vjp(run, G, mode=m) for m in VJP_MODES})
+            ctx().profile()
+    finally:
+        ctx().set_profiling(0)
+    for k in ("img", "L", "hits"):
+        np.testing.assert_array_equal(res[0][k], res[1][k], err_msg=k)
+    for m in VJP_MODES:
+        for name, v in res[1][m].items():
+            np.testing.assert_array_equal(res[0][m][name], v, err_msg=f"{m} {name}")
+
+
 def test_vjp_rejects_bad_arguments():
     import torch
     from paper_2503_12174_amd import dpcs

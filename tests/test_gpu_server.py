@@ -89,6 +89,55 @@ def test_results_alone_equal_results_in_the_mix():
                 np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-5 * scale, err_msg=f"request {k} {name}")
 
 
+def test_full_waves_with_overlapped_shadow_rays():
+    """Waves of 2^21 paths put their shadow rays (forward, and the re-traced adjoint's) on
+    a second stream beside the next depth's closest hit: a large relight request (env on:
+    both shadow queues) and a depth-20 compensation step (its path records exceed the
+    loop's record buffer of 8 words per path: re-traced) through the loop equal the plain
+    entry points."""
+    import torch
+    from paper_2503_12174_amd import dpcs
+    scene = dpcs.Scene(ctx(), synth.folded_corner(30, 630, 730))
+    albedo, rough, spec = (dev(x, torch.float32) for x in synth.ggx_textures(7, 128))
+    reqs = []
+    for k, (spp, depth, comp) in enumerate([(64, 3, False), (32, 20, True)]):
+        w = synth.corner_50k(spp=spp, max_depth=depth, res=256, n_quads=8)
+        w.seed = 40 + k
+        w.env = np.full(3, 0.03)
+        p = dpcs.params_from(w, albedo, rough, spec)
+        ip = dev(synth.blob_image(256, 256, 910 + k), torch.float32)
+        out = torch.zeros((256, 256, 3), device="cuda")
+        grads = target = None
+        if comp:
+            target = dev(synth.blob_image(256, 256, 60 + k, lo=0.1, hi=0.9), torch.float32)
+            grads = dict(d_proj_image=torch.zeros_like(ip), d_albedo=torch.zeros_like(albedo),
+                         d_roughness=torch.zeros_like(rough), d_specular=torch.zeros_like(spec),
+                         d_scalars=torch.zeros(18, device="cuda"))
+        reqs.append((k, w, p, ip, out, target, grads))
+    torch.cuda.synchronize()
+    srv = dpcs.Server(ctx(), budget_bytes=16 << 30, max_slots=4)
+    for k, w, p, ip, out, target, grads in reqs:
+        assert srv.submit(k, scene, p, ip, out, target=target, grads=grads) == dpcs.OK
+    done = _wait(srv, len(reqs), timeout=120)
+    assert sorted(d[0] for d in done) == [0, 1] and all(d[1] == dpcs.OK for d in done)
+    assert srv.stats()["retraced_waves"] > 0
+    srv.close()
+    for k, w, p, ip, out, target, grads in reqs:
+        alone = torch.zeros_like(out)
+        L = torch.zeros((256, 256, w.spp, 3), device="cuda")
+        dpcs.dpcs_render(ctx(), scene, p, ip, alone, sample_radiance=L)
+        ctx().synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), alone.cpu().numpy(), err_msg=f"request {k}")
+        if grads is not None:
+            G = 2.0 * (alone - target) / (3 * 256 * 256)
+            g2 = {k2: torch.zeros_like(v) for k2, v in grads.items()}
+            dpcs.dpcs_render_vjp(ctx(), scene, p, ip, G.contiguous(), sample_radiance=L, **g2)
+            ctx().synchronize()
+            for name in grads:
+                a, b = grads[name].cpu().numpy(), g2[name].cpu().numpy()
+                np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-5 * (np.abs(b).max() + 1e-30), err_msg=name)
+
+
 def test_one_request_waves_bin_their_gradients():
     """Compensation steps submitted one at a time run alone in their waves: their map
     cotangents are binned and flushed (no atomics), and the gradients equal the plain
